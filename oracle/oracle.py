@@ -1,0 +1,158 @@
+"""Python access to the CPU oracle (``oracle/odgs_oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()`` and by the
+CPU-baseline leg of ``bench.py``.  The GPU product path never imports this module.
+
+All parameters are passed to the C code as float64 copies of the scene arrays (the float32
+inputs of the GPU path convert exactly), so finite differences can perturb them in double.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "odgs_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+NF = 40  # doubles per projection row, see oracle_project in the C source
+F_KEPT, F_CULL, F_DEPTH, F_DEPTH_BITS, F_U, F_V = 0, 1, 2, 3, 4, 5
+F_CONIC, F_OPAC, F_PMIN, F_RGB, F_RECT, F_COV2, F_J, F_COV3, F_MU, F_R, F_RGB_RAW = 6, 9, 10, 11, 14, 18, 21, 27, 33, 36, 37
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (plain C++17 + OpenMP, no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-Wall", "-o", tmp, _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32 = ctypes.c_int64, ctypes.c_int
+        scene_args = [P, P, P, P, P, i64, i32, P, P, i32, P]
+        L.oracle_num_threads.restype = i32
+        L.oracle_sh_basis.argtypes = [P, i64, i32, P]
+        L.oracle_project.argtypes = scene_args + [P]
+        L.oracle_project.restype = i32
+        L.oracle_keys.argtypes = scene_args + [P, P, i64]
+        L.oracle_keys.restype = i64
+        L.oracle_render.argtypes = scene_args + [i32, i32, P, i64, P, P, P, P, P]
+        L.oracle_render.restype = i32
+        L.oracle_backward.argtypes = scene_args + [i32, P, i64, P, P, P, P, P, P, P]
+        L.oracle_backward.restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def settings_array(settings: dict) -> np.ndarray:
+    bg = settings.get("bg", (0.0, 0.0, 0.0))
+    return np.array([settings["tile"], settings["near"], settings["far"], settings["dilation"],
+                     settings["pole_eps"], bg[0], bg[1], bg[2], 0.0], dtype=np.float64)
+
+
+class _Args:
+    def __init__(self, scene, cams, settings):
+        f = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        self.keep = [f(scene.means), f(scene.scales), f(scene.quats), f(scene.opacities), f(scene.sh),
+                     f(cams.cams), np.ascontiguousarray(cams.wh, dtype=np.int32), settings_array(settings)]
+        self.n = scene.means.shape[1]
+        self.deg = scene.sh_degree
+        self.V = cams.cams.shape[0]
+        self.wh = cams.wh
+
+    def tuple(self):
+        m, s, q, o, sh, c, wh, st = self.keep
+        return (_p(m), _p(s), _p(q), _p(o), _p(sh), self.n, self.deg, _p(c), _p(wh), self.V, _p(st))
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+def sh_basis(dirs: np.ndarray, K: int) -> np.ndarray:
+    d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros((d.shape[0], K))
+    lib().oracle_sh_basis(_p(d), d.shape[0], K, _p(out))
+    return out
+
+
+def project(scene, cams, settings) -> np.ndarray:
+    """Projection rows [V][N][NF] (see the field constants above)."""
+    a = _Args(scene, cams, settings)
+    out = np.zeros((a.V, a.n, NF))
+    lib().oracle_project(*a.tuple(), _p(out))
+    return out
+
+
+def keys(scene, cams, settings):
+    """Sorted (key uint64, gaussian index uint32) list over all views."""
+    a = _Args(scene, cams, settings)
+    P = lib().oracle_keys(*a.tuple(), None, None, 0)
+    k = np.zeros(max(P, 1), dtype=np.uint64)
+    v = np.zeros(max(P, 1), dtype=np.uint32)
+    P2 = lib().oracle_keys(*a.tuple(), _p(k), _p(v), P)
+    assert P2 == P
+    return k[:P], v[:P]
+
+
+def render(scene, cams, settings, mode: int = 32, band: bool = False, pix: np.ndarray | None = None):
+    """Brute-force (or band) render.  Returns dict of rgb, T, ncontrib, margin, sig.
+
+    Full image: rgb is [V][3][H][W] flattened and concatenated over views, the others [V][H][W].
+    With ``pix`` (int32 [n][3] rows of view, x, y): rgb [n][3], the others [n].
+    """
+    a = _Args(scene, cams, settings)
+    if pix is None:
+        npx = int(np.sum(a.wh[:, 0].astype(np.int64) * a.wh[:, 1]))
+        pp = None
+        rgb = np.zeros(3 * npx)
+    else:
+        pp = np.ascontiguousarray(pix, dtype=np.int32)
+        npx = pp.shape[0]
+        rgb = np.zeros((npx, 3))
+    T = np.zeros(npx)
+    nc = np.zeros(npx, dtype=np.int32)
+    margin = np.zeros(npx)
+    sig = np.zeros(npx, dtype=np.uint64)
+    lib().oracle_render(*a.tuple(), mode, int(band), _p(pp), npx if pp is not None else 0,
+                        _p(rgb), _p(T), _p(nc), _p(margin), _p(sig))
+    return dict(rgb=rgb, T=T, ncontrib=nc, margin=margin, sig=sig)
+
+
+def backward(scene, cams, settings, dL: np.ndarray, mode: int = 32, pix: np.ndarray | None = None,
+             want_g2d: bool = False):
+    """Gradient of sum(dL * rgb) w.r.t. every parameter (float64), and optionally the per-item
+    2D gradients [V][N][9] (u, v, conic a, b, c, opacity, r, g, b)."""
+    a = _Args(scene, cams, settings)
+    n, K = a.n, (a.deg + 1) ** 2
+    gm, gs, gq = np.zeros((3, n)), np.zeros((3, n)), np.zeros((4, n))
+    go, gsh = np.zeros(n), np.zeros((K * 3, n))
+    g2d = np.zeros((a.V, n, 9)) if want_g2d else None
+    d = np.ascontiguousarray(dL, dtype=np.float64)
+    pp = None if pix is None else np.ascontiguousarray(pix, dtype=np.int32)
+    lib().oracle_backward(*a.tuple(), mode, _p(pp), 0 if pp is None else pp.shape[0], _p(d),
+                          _p(gm), _p(gs), _p(gq), _p(go), _p(gsh), _p(g2d))
+    out = dict(means=gm, scales=gs, quats=gq, opacities=go, sh=gsh)
+    if want_g2d:
+        out["g2d"] = g2d
+    return out
