@@ -1,0 +1,164 @@
+/*
+ * odgs.h -- C ABI of the MI355X (gfx950) omnidirectional Gaussian rasterizer.
+ *
+ * Implements the rasterizer of ODGS (Lee et al., NeurIPS 2024, arXiv 2410.20686): every 3D
+ * Gaussian is projected perspectively onto the plane tangent to the unit sphere along the ray
+ * to its centre and mapped into equirectangular (ERP) pixel space (Sec. 3.2, Eq. equirec_proj,
+ * Eq. omni_rotation, Eq. omni_J, Eq. omni_QS, Eq. omni_Jacobian); pixels alpha-composite their
+ * depth-ordered Gaussians front to back (Sec. 3.1, Eq. gaussian2d, Eq. alphablending); the
+ * backward pass differentiates all of it (Sec. 3.2 last paragraph, Appendix C).
+ *
+ * General rules for every entry point:
+ *   - Pointers are DEVICE pointers unless marked [host].  All device buffers are owned by the
+ *     caller; the library never allocates, frees or synchronises, and keeps no global mutable
+ *     state.  Every call only enqueues work on `stream` (a hipStream_t; NULL = legacy stream)
+ *     and is therefore capturable in a HIP graph.
+ *   - float arrays are FP32, structure-of-arrays, with N = plan->n Gaussians:
+ *       means [3][N] world-space centres;  scales [3][N] linear axis scales (> 0);
+ *       quats [4][N] rotations (w, x, y, z), normalised inside;  opacities [N] in (0, 1);
+ *       sh [K*3][N] real spherical-harmonic colour coefficients, plane index k*3 + channel,
+ *       K = (sh_degree + 1)^2, basis order (l, m = -l..l);
+ *       cams [V][12] per view: world-to-camera rotation R (row-major 3x3) then t (3), so
+ *       x_cam = R x_world + t with OpenCV axes (z forward, x right, y down).
+ *   - Images of all views are concatenated view after view: rgb [V][3][H_v][W_v] (planar),
+ *     per-pixel planes [V][H_v][W_v].  Pixel (x, y) samples the point (x + 0.5, y + 0.5).
+ *   - Return value: ODGS_OK or a negative error code (argument errors are detected on the host,
+ *     before anything is enqueued).  Data-dependent conditions found on the device (pair-list
+ *     overflow) are written to the status record inside the workspace, which the caller reads
+ *     after its own synchronisation.
+ *   - Calls for one plan must use one workspace, in the order preprocess -> bin_sort ->
+ *     render_fwd -> render_bwd, on one stream (or with the caller ordering the streams).
+ */
+#ifndef ODGS_H
+#define ODGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ODGS_OK = 0,
+  ODGS_EINVAL = -1,    /* invalid argument (null or misaligned pointer, size out of range) */
+  ODGS_ENOSPACE = -2,  /* workspace smaller than odgs_workspace_bytes(plan) */
+  ODGS_EHIP = -3       /* a kernel launch failed */
+};
+
+#define ODGS_MAX_VIEWS 64
+#define ODGS_STATUS_OVERFLOW 1 /* more Gaussian-tile pairs than plan->pair_capacity */
+
+/* Rasterization settings.  The paper fixes none of these constants; the defaults follow the
+ * 3DGS rasterizer it builds on (Sec. 3.2, "can be used as a typical 3DGS"). */
+typedef struct odgs_settings {
+  int32_t tile;     /* tile edge in pixels: 8, 16 or 32; every W and H must be a multiple */
+  int32_t batch;    /* reserved, 0 */
+  float near_r;     /* spherical-shell culling radii (Sec. 3.2): keep near_r < |mu| < far_r */
+  float far_r;
+  float dilation;   /* added to the 2D covariance's diagonal (3DGS low-pass), e.g. 0.3 */
+  float pole_eps;   /* cull when sqrt(mu_x^2 + mu_z^2) <= pole_eps * |mu|, e.g. 1e-4 */
+  float bg[3];      /* background colour behind the final transmittance */
+  int32_t flags;    /* reserved, 0 */
+} odgs_settings;
+
+/* Device status record at byte offset plan->off_status of the workspace. */
+typedef struct odgs_status {
+  int32_t flags;      /* ODGS_STATUS_* bits */
+  int32_t n_pairs_stored; /* min(n_pairs, pair_capacity): pairs actually sorted and rendered */
+  int64_t n_pairs;    /* Gaussian-tile pairs P of the last odgs_preprocess */
+  int64_t n_visible;  /* (Gaussian, view) items that survived culling */
+  int64_t reserved2;
+} odgs_status;
+
+/* Plain-data description of one workload and of its workspace layout.  Filled by
+ * odgs_plan_init; callers treat it as opaque, keep it in host memory and pass it by pointer. */
+typedef struct odgs_plan {
+  int64_t n;               /* Gaussians */
+  int32_t sh_degree;       /* 0..3 */
+  int32_t n_views;         /* 1..ODGS_MAX_VIEWS */
+  odgs_settings s;
+  int32_t width[ODGS_MAX_VIEWS];
+  int32_t height[ODGS_MAX_VIEWS];
+  int32_t tile_base[ODGS_MAX_VIEWS + 1];  /* first global tile id of each view; [n_views] = total */
+  int64_t pix_base[ODGS_MAX_VIEWS + 1];   /* first pixel of each view; [n_views] = total */
+  int64_t items;           /* n * n_views (Gaussian, view) items, item id = view * n + gaussian */
+  int64_t pair_capacity;   /* maximum Gaussian-tile pairs the workspace holds */
+  int32_t tile_bits;       /* significant bits of a global tile id */
+  int32_t item_blocks;     /* sort / scan blocks over items */
+  int32_t pair_blocks;     /* sort blocks over pair_capacity */
+  int32_t reserved;
+  /* workspace layout, byte offsets */
+  size_t off_status, off_rec, off_rect, off_count, off_dkey[2], off_did[2], off_blocksum, off_pkey[2], off_pval[2],
+      off_hist, off_digit, off_ranges, off_T, off_last, off_g2d;
+  int32_t depth_final;     /* which of the two depth-sort buffers holds the sorted result */
+  int32_t pair_final;      /* which of the two pair buffers holds the sorted result */
+  size_t ws_bytes;
+} odgs_plan;
+
+/* Fill `plan` for n Gaussians of SH degree sh_degree seen by n_views views of sizes
+ * wh [host] = {W0, H0, W1, H1, ...}, with room for pair_capacity Gaussian-tile pairs
+ * (pair_capacity < 2^31).  Pure host computation. */
+int odgs_plan_init(odgs_plan* plan /*[host]*/, int64_t n, int32_t sh_degree, int32_t n_views, const int32_t* wh /*[host]*/,
+                   const odgs_settings* s /*[host]*/, int64_t pair_capacity);
+
+/* Bytes of device workspace a plan needs (256-byte aligned base pointer required). */
+size_t odgs_workspace_bytes(const odgs_plan* plan /*[host]*/);
+
+/* Per (Gaussian, view): view transform, shell and pole culling, ERP position (Eq. equirec_proj),
+ * 3D covariance R S S^T R^T (Sec. 3.1), tangent-plane Jacobian J_omni (Eq. omni_Jacobian),
+ * 2D covariance J_omni W Sigma W^T J_omni^T plus dilation, its inverse, SH colour, radial
+ * depth, and the footprint's tile rectangle.  Binning decisions are taken in FP64.
+ * Resets the status record. */
+int odgs_preprocess(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
+                    const float* opacities, const float* sh, const float* cams, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* Bin and sort: depth-sort the items, count and emit Gaussian-tile pairs, radix-sort them by
+ * global tile (stable, so each tile's list stays in (radial depth, Gaussian index) order, i.e.
+ * the pairs end up ordered by the 64-bit key (tile << 32 | depth bits)), and build each tile's
+ * [start, end) range.  P stays on the device; P > pair_capacity sets ODGS_STATUS_OVERFLOW and
+ * leaves the pair list truncated (the images are then invalid). */
+int odgs_bin_sort(const odgs_plan* plan, void* ws, size_t ws_bytes, void* stream);
+
+/* Front-to-back compositing of every pixel of every view in one launch (Eq. gaussian2d and
+ * Eq. alphablending, 3DGS constants alpha <= 0.99, alpha >= 1/255, stop below T = 1e-4).
+ * out_rgb [V][3][H][W] receives C + T_final * bg; out_T [V][H][W] (may be NULL) the final
+ * transmittance.  Keeps T and the last contributor per pixel in the workspace for render_bwd. */
+int odgs_render_fwd(const odgs_plan* plan, void* ws, size_t ws_bytes, float* out_rgb, float* out_T, void* stream);
+
+/* Gradient of L = sum(dL_drgb * out_rgb) with respect to every parameter, summed over the
+ * views (reverse compositing, then the adjoint of the tangent-plane projection and of the SH
+ * colour; Sec. 3.2 and Appendix C).  The parameters must be those given to odgs_preprocess.
+ * The five gradient arrays (same shapes as the parameters) are OVERWRITTEN. */
+int odgs_render_bwd(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
+                    const float* opacities, const float* sh, const float* cams, void* ws, size_t ws_bytes,
+                    const float* dL_drgb, float* d_means, float* d_scales, float* d_quats, float* d_opacities,
+                    float* d_sh, void* stream);
+
+/* Byte offset of the odgs_status record inside the workspace. */
+size_t odgs_status_offset(const odgs_plan* plan /*[host]*/);
+
+/* Static description of an error code. */
+const char* odgs_strerror(int code);
+
+/* Size of odgs_plan, so bindings can allocate it without the struct definition. */
+size_t odgs_plan_size(void);
+
+/* ---- inspection (tests): copy internal results out of the workspace ---------------------- */
+
+/* Per-item FP32 record [items][12]: u, v, A, B, C, opacity, p_min, depth, r, g, b, tile count,
+ * where the compositor's exponent is A du^2 + B du dv + C dv^2 (A = -a/2, B = -b, C = -c/2
+ * for the inverse covariance [[a, b], [b, c]]); culled items have tile count 0. */
+int odgs_debug_records(const odgs_plan* plan, const void* ws, float* out, void* stream);
+
+/* The sorted pair list as 64-bit keys (global tile << 32 | depth bits) and Gaussian indices,
+ * first min(P, cap) entries (P from the status record, read by the caller). */
+int odgs_debug_keys(const odgs_plan* plan, const void* ws, int64_t cap, uint64_t* keys, uint32_t* gauss,
+                    void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ODGS_H */

@@ -65,9 +65,12 @@ def _p(a):
 
 
 def settings_array(settings: dict) -> np.ndarray:
+    """Settings as doubles.  The real-valued ones are first rounded to float32, the precision in
+    which the rasterizer's C interface receives them, so both sides use identical constants."""
     bg = settings.get("bg", (0.0, 0.0, 0.0))
-    return np.array([settings["tile"], settings["near"], settings["far"], settings["dilation"],
-                     settings["pole_eps"], bg[0], bg[1], bg[2], 0.0], dtype=np.float64)
+    vals = [settings["near"], settings["far"], settings["dilation"], settings["pole_eps"], bg[0], bg[1], bg[2]]
+    vals = [float(np.float32(x)) for x in vals]
+    return np.array([settings["tile"], *vals, 0.0], dtype=np.float64)
 
 
 class _Args:

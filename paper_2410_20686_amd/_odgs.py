@@ -1,0 +1,155 @@
+"""ctypes binding of ``libodgs.so`` (the C ABI of include/odgs.h).
+
+Argument marshalling only: every function here forwards plain pointers and sizes to the
+library of the same name.  Loading fails loudly when the library has not been built; there is
+no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libodgs.so")
+
+MAX_VIEWS = 64
+OK, EINVAL, ENOSPACE, EHIP = 0, -1, -2, -3
+STATUS_OVERFLOW = 1
+
+EXPORTS = ("odgs_plan_init", "odgs_workspace_bytes", "odgs_preprocess", "odgs_bin_sort", "odgs_render_fwd",
+           "odgs_render_bwd", "odgs_status_offset", "odgs_strerror", "odgs_plan_size", "odgs_debug_records",
+           "odgs_debug_keys")
+
+
+class Settings(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("batch", ctypes.c_int32), ("near_r", ctypes.c_float),
+                ("far_r", ctypes.c_float), ("dilation", ctypes.c_float), ("pole_eps", ctypes.c_float),
+                ("bg", ctypes.c_float * 3), ("flags", ctypes.c_int32)]
+
+
+class Status(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_int32), ("n_pairs_stored", ctypes.c_int32), ("n_pairs", ctypes.c_int64),
+                ("n_visible", ctypes.c_int64), ("reserved2", ctypes.c_int64)]
+
+
+_OFFSETS = ["off_status", "off_rec", "off_rect", "off_count", "off_dkey0", "off_dkey1", "off_did0", "off_did1",
+            "off_blocksum", "off_pkey0", "off_pkey1", "off_pval0", "off_pval1", "off_hist", "off_digit",
+            "off_ranges", "off_T", "off_last", "off_g2d"]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = ([("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("n_views", ctypes.c_int32),
+                 ("s", Settings), ("width", ctypes.c_int32 * MAX_VIEWS), ("height", ctypes.c_int32 * MAX_VIEWS),
+                 ("tile_base", ctypes.c_int32 * (MAX_VIEWS + 1)), ("pix_base", ctypes.c_int64 * (MAX_VIEWS + 1)),
+                 ("items", ctypes.c_int64), ("pair_capacity", ctypes.c_int64), ("tile_bits", ctypes.c_int32),
+                 ("item_blocks", ctypes.c_int32), ("pair_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                + [(name, ctypes.c_size_t) for name in _OFFSETS]
+                + [("depth_final", ctypes.c_int32), ("pair_final", ctypes.c_int32), ("ws_bytes", ctypes.c_size_t)])
+
+
+_lib = None
+
+
+def lib():
+    """Load libodgs.so (raises if it is missing or does not match these declarations)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libodgs.so is not built (run __graft_entry__.build() or "
+                              "python -m paper_2410_20686_amd.build): %s" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P, c_i64, c_i32, c_sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+        pp = ctypes.POINTER(Plan)
+        L.odgs_plan_size.restype = c_sz
+        L.odgs_plan_init.argtypes = [pp, c_i64, c_i32, c_i32, P, ctypes.POINTER(Settings), c_i64]
+        L.odgs_plan_init.restype = c_i32
+        L.odgs_workspace_bytes.argtypes = [pp]
+        L.odgs_workspace_bytes.restype = c_sz
+        L.odgs_status_offset.argtypes = [pp]
+        L.odgs_status_offset.restype = c_sz
+        L.odgs_preprocess.argtypes = [pp, P, P, P, P, P, P, P, c_sz, P]
+        L.odgs_preprocess.restype = c_i32
+        L.odgs_bin_sort.argtypes = [pp, P, c_sz, P]
+        L.odgs_bin_sort.restype = c_i32
+        L.odgs_render_fwd.argtypes = [pp, P, c_sz, P, P, P]
+        L.odgs_render_fwd.restype = c_i32
+        L.odgs_render_bwd.argtypes = [pp, P, P, P, P, P, P, P, c_sz, P, P, P, P, P, P, P]
+        L.odgs_render_bwd.restype = c_i32
+        L.odgs_strerror.argtypes = [c_i32]
+        L.odgs_strerror.restype = ctypes.c_char_p
+        L.odgs_debug_records.argtypes = [pp, P, P, P]
+        L.odgs_debug_records.restype = c_i32
+        L.odgs_debug_keys.argtypes = [pp, P, c_i64, P, P, P]
+        L.odgs_debug_keys.restype = c_i32
+        if L.odgs_plan_size() != ctypes.sizeof(Plan):
+            raise ImportError("odgs_plan layout mismatch: library %d bytes, binding %d bytes"
+                              % (L.odgs_plan_size(), ctypes.sizeof(Plan)))
+        _lib = L
+    return _lib
+
+
+class OdgsError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise OdgsError("%s failed: %s (%d)" % (what, lib().odgs_strerror(rc).decode(), rc))
+
+
+def make_settings(tile=16, batch=0, near=0.2, far=1e4, dilation=0.3, pole_eps=1e-4, bg=(0.0, 0.0, 0.0)) -> Settings:
+    s = Settings()
+    s.tile, s.batch = int(tile), int(batch)
+    s.near_r, s.far_r, s.dilation, s.pole_eps = float(near), float(far), float(dilation), float(pole_eps)
+    for k in range(3):
+        s.bg[k] = float(bg[k])
+    s.flags = 0
+    return s
+
+
+def odgs_plan_init(n: int, sh_degree: int, wh, settings: Settings, pair_capacity: int) -> Plan:
+    plan = Plan()
+    flat = (ctypes.c_int32 * (2 * len(wh)))(*[int(x) for pair in wh for x in pair])
+    rc = lib().odgs_plan_init(ctypes.byref(plan), int(n), int(sh_degree), len(wh), ctypes.cast(flat, ctypes.c_void_p),
+                              ctypes.byref(settings), int(pair_capacity))
+    _check(rc, "odgs_plan_init")
+    return plan
+
+
+def odgs_workspace_bytes(plan: Plan) -> int:
+    return int(lib().odgs_workspace_bytes(ctypes.byref(plan)))
+
+
+def odgs_status_offset(plan: Plan) -> int:
+    return int(lib().odgs_status_offset(ctypes.byref(plan)))
+
+
+def odgs_preprocess(plan, means, scales, quats, opac, sh, cams, ws, ws_bytes, stream):
+    _check(lib().odgs_preprocess(ctypes.byref(plan), means, scales, quats, opac, sh, cams, ws, ws_bytes, stream),
+           "odgs_preprocess")
+
+
+def odgs_bin_sort(plan, ws, ws_bytes, stream):
+    _check(lib().odgs_bin_sort(ctypes.byref(plan), ws, ws_bytes, stream), "odgs_bin_sort")
+
+
+def odgs_render_fwd(plan, ws, ws_bytes, out_rgb, out_T, stream):
+    _check(lib().odgs_render_fwd(ctypes.byref(plan), ws, ws_bytes, out_rgb, out_T, stream), "odgs_render_fwd")
+
+
+def odgs_render_bwd(plan, means, scales, quats, opac, sh, cams, ws, ws_bytes, dL, d_means, d_scales, d_quats,
+                    d_opac, d_sh, stream):
+    _check(lib().odgs_render_bwd(ctypes.byref(plan), means, scales, quats, opac, sh, cams, ws, ws_bytes, dL, d_means,
+                                 d_scales, d_quats, d_opac, d_sh, stream), "odgs_render_bwd")
+
+
+def odgs_debug_records(plan, ws, out, stream):
+    _check(lib().odgs_debug_records(ctypes.byref(plan), ws, out, stream), "odgs_debug_records")
+
+
+def odgs_debug_keys(plan, ws, cap, keys, gauss, stream):
+    _check(lib().odgs_debug_keys(ctypes.byref(plan), ws, int(cap), keys, gauss, stream), "odgs_debug_keys")
+
+
+def odgs_strerror(code: int) -> str:
+    return lib().odgs_strerror(int(code)).decode()

@@ -1,0 +1,195 @@
+// C ABI of the gfx950 omnidirectional rasterizer: plan / workspace layout, argument checks and
+// the entry points declared in include/odgs.h.  No allocation, no synchronisation, no global
+// mutable state: every entry point validates on the host and enqueues kernels on the stream.
+#include <string.h>
+
+#include "common.h"
+
+namespace odgs {
+namespace {
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int check_ws(const odgs_plan* p, const void* ws, size_t ws_bytes) {
+  if (!p) return ODGS_EINVAL;
+  if (p->ws_bytes > 0 && (!ws || !aligned(ws, 256))) return ODGS_EINVAL;
+  if (ws_bytes < p->ws_bytes) return ODGS_ENOSPACE;
+  return ODGS_OK;
+}
+
+int check_params(const odgs_plan* p, const float* means, const float* scales, const float* quats, const float* opac,
+                 const float* sh, const float* cams) {
+  if (!cams || !aligned(cams, 4)) return ODGS_EINVAL;
+  if (p->n == 0) return ODGS_OK;
+  const float* ptrs[5] = {means, scales, quats, opac, sh};
+  for (const float* q : ptrs)
+    if (!q || !aligned(q, 4)) return ODGS_EINVAL;
+  return ODGS_OK;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? ODGS_OK : ODGS_EHIP; }
+
+bool batch_ok(int tile, int batch) {
+  if (tile == 8 || tile == 16) return batch == 32 || batch == 64 || batch == 128 || batch == 256;
+  if (tile == 32) return batch == 64 || batch == 128 || batch == 256;
+  return false;
+}
+
+}  // namespace
+}  // namespace odgs
+
+using namespace odgs;
+
+extern "C" {
+
+size_t odgs_plan_size(void) { return sizeof(odgs_plan); }
+
+int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_views, const int32_t* wh,
+                   const odgs_settings* s, int64_t pair_capacity) {
+  if (!plan || !wh || !s) return ODGS_EINVAL;
+  if (n < 0 || sh_degree < 0 || sh_degree > 3 || n_views < 1 || n_views > ODGS_MAX_VIEWS) return ODGS_EINVAL;
+  if (pair_capacity < 0 || pair_capacity >= (int64_t(1) << 31)) return ODGS_EINVAL;
+  if (n * (int64_t)n_views >= (int64_t(1) << 31)) return ODGS_EINVAL;
+  odgs_settings st = *s;
+  if (st.tile != 8 && st.tile != 16 && st.tile != 32) return ODGS_EINVAL;
+  if (st.batch == 0) st.batch = st.tile == 8 ? 64 : 256;
+  if (!batch_ok(st.tile, st.batch)) return ODGS_EINVAL;
+  if (!(st.near_r >= 0.0f) || !(st.far_r > st.near_r) || !(st.dilation >= 0.0f) || !(st.pole_eps >= 0.0f))
+    return ODGS_EINVAL;
+  memset(plan, 0, sizeof(*plan));
+  plan->n = n;
+  plan->sh_degree = sh_degree;
+  plan->n_views = n_views;
+  plan->s = st;
+  int64_t tiles = 0, pixels = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const int W = wh[2 * v], H = wh[2 * v + 1];
+    if (W <= 0 || H <= 0 || W % st.tile || H % st.tile || W / st.tile > 65535 || H / st.tile > 65535)
+      return ODGS_EINVAL;
+    plan->width[v] = W;
+    plan->height[v] = H;
+    plan->tile_base[v] = (int32_t)tiles;
+    plan->pix_base[v] = pixels;
+    tiles += (int64_t)(W / st.tile) * (H / st.tile);
+    pixels += (int64_t)W * H;
+    if (tiles >= (int64_t(1) << 31) || pixels >= (int64_t(1) << 40)) return ODGS_EINVAL;
+  }
+  plan->tile_base[n_views] = (int32_t)tiles;
+  plan->pix_base[n_views] = pixels;
+  plan->items = n * n_views;
+  plan->pair_capacity = pair_capacity;
+  int bits = 1;
+  while ((int64_t(1) << bits) < tiles) ++bits;
+  plan->tile_bits = bits;
+  plan->item_blocks = (int32_t)((plan->items + kSortBlockItems - 1) / kSortBlockItems);
+  if (plan->item_blocks < 1) plan->item_blocks = 1;
+  plan->pair_blocks = (int32_t)((pair_capacity + kSortBlockItems - 1) / kSortBlockItems);
+  if (plan->pair_blocks < 1) plan->pair_blocks = 1;
+  plan->depth_final = (4 % 2);                  // 4 passes of 8 bits over 32-bit depths
+  plan->pair_final = ((bits + 7) / 8) % 2;      // passes over the tile bits
+  const int64_t I = plan->items;
+  const int64_t sblocks = (I + 1023) / 1024 + 1;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  plan->off_status = take(256);
+  plan->off_rec = take((size_t)I * sizeof(Rec));
+  plan->off_rect = take((size_t)I * sizeof(Rect));
+  plan->off_count = take((size_t)I * 4);
+  plan->off_dkey[0] = take((size_t)I * 4);
+  plan->off_dkey[1] = take((size_t)I * 4);
+  plan->off_did[0] = take((size_t)I * 4);
+  plan->off_did[1] = take((size_t)I * 4);
+  plan->off_blocksum = take(align_up((size_t)sblocks, 64) * 4 + (size_t)sblocks * 8);
+  plan->off_pkey[0] = take((size_t)pair_capacity * 4);
+  plan->off_pkey[1] = take((size_t)pair_capacity * 4);
+  plan->off_pval[0] = take((size_t)pair_capacity * 4);
+  plan->off_pval[1] = take((size_t)pair_capacity * 4);
+  const int64_t hb = plan->item_blocks > plan->pair_blocks ? plan->item_blocks : plan->pair_blocks;
+  plan->off_hist = take((size_t)256 * hb * 4);
+  plan->off_digit = take(256 * 4);
+  plan->off_ranges = take((size_t)tiles * 8);
+  plan->off_T = take((size_t)pixels * 4);
+  plan->off_last = take((size_t)pixels * 4);
+  plan->off_g2d = take((size_t)9 * I * 4);
+  plan->ws_bytes = off;
+  return ODGS_OK;
+}
+
+size_t odgs_workspace_bytes(const odgs_plan* plan) { return plan ? plan->ws_bytes : 0; }
+
+size_t odgs_status_offset(const odgs_plan* plan) { return plan ? plan->off_status : 0; }
+
+int odgs_preprocess(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
+                    const float* opacities, const float* sh, const float* cams, void* ws, size_t ws_bytes,
+                    void* stream) {
+  int rc = check_ws(plan, ws, ws_bytes);
+  if (rc != ODGS_OK) return rc;
+  rc = check_params(plan, means, scales, quats, opacities, sh, cams);
+  if (rc != ODGS_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_status_reset(plan, ws, st);
+  if (e == hipSuccess) e = launch_preprocess(plan, means, scales, quats, opacities, sh, cams, ws, st);
+  return hip_status(e);
+}
+
+int odgs_bin_sort(const odgs_plan* plan, void* ws, size_t ws_bytes, void* stream) {
+  const int rc = check_ws(plan, ws, ws_bytes);
+  if (rc != ODGS_OK) return rc;
+  return hip_status(launch_bin_sort(plan, ws, static_cast<hipStream_t>(stream)));
+}
+
+int odgs_render_fwd(const odgs_plan* plan, void* ws, size_t ws_bytes, float* out_rgb, float* out_T, void* stream) {
+  const int rc = check_ws(plan, ws, ws_bytes);
+  if (rc != ODGS_OK) return rc;
+  if (!out_rgb || !aligned(out_rgb, 4) || (out_T && !aligned(out_T, 4))) return ODGS_EINVAL;
+  return hip_status(launch_render_fwd(plan, ws, out_rgb, out_T, static_cast<hipStream_t>(stream)));
+}
+
+int odgs_render_bwd(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
+                    const float* opacities, const float* sh, const float* cams, void* ws, size_t ws_bytes,
+                    const float* dL_drgb, float* d_means, float* d_scales, float* d_quats, float* d_opacities,
+                    float* d_sh, void* stream) {
+  int rc = check_ws(plan, ws, ws_bytes);
+  if (rc != ODGS_OK) return rc;
+  rc = check_params(plan, means, scales, quats, opacities, sh, cams);
+  if (rc != ODGS_OK) return rc;
+  if (!dL_drgb || !aligned(dL_drgb, 4)) return ODGS_EINVAL;
+  if (plan->n > 0) {
+    float* outs[5] = {d_means, d_scales, d_quats, d_opacities, d_sh};
+    for (float* q : outs)
+      if (!q || !aligned(q, 4)) return ODGS_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_render_bwd(plan, ws, dL_drgb, st);
+  if (e == hipSuccess)
+    e = launch_preprocess_bwd(plan, means, scales, quats, opacities, sh, cams, ws, d_means, d_scales, d_quats,
+                              d_opacities, d_sh, st);
+  return hip_status(e);
+}
+
+const char* odgs_strerror(int code) {
+  switch (code) {
+    case ODGS_OK: return "success";
+    case ODGS_EINVAL: return "invalid argument";
+    case ODGS_ENOSPACE: return "workspace too small";
+    case ODGS_EHIP: return "HIP kernel launch failed";
+    default: return "unknown error";
+  }
+}
+
+int odgs_debug_records(const odgs_plan* plan, const void* ws, float* out, void* stream) {
+  if (!plan || !ws || !out) return ODGS_EINVAL;
+  return hip_status(launch_debug_records(plan, ws, out, static_cast<hipStream_t>(stream)));
+}
+
+int odgs_debug_keys(const odgs_plan* plan, const void* ws, int64_t cap, uint64_t* keys, uint32_t* gauss,
+                    void* stream) {
+  if (!plan || !ws || cap < 0 || (cap > 0 && (!keys || !gauss))) return ODGS_EINVAL;
+  return hip_status(launch_debug_keys(plan, ws, cap, keys, gauss, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

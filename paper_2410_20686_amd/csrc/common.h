@@ -1,0 +1,88 @@
+// Shared device-side definitions of the gfx950 rasterizer (kernels + C ABI glue).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/odgs.h"
+
+namespace odgs {
+
+constexpr int kWave = 64;  // CDNA wavefront width
+
+// Per-view geometry passed to kernels by value (kernel arguments are captured by HIP graphs).
+struct ViewTable {
+  int32_t n_views;
+  int32_t W[ODGS_MAX_VIEWS];
+  int32_t H[ODGS_MAX_VIEWS];
+  int32_t tile_base[ODGS_MAX_VIEWS + 1];
+  int64_t pix_base[ODGS_MAX_VIEWS + 1];
+};
+
+// Compositor record of one (Gaussian, view) item, three 16-byte words:
+//   r0 = (u, v, A, B)          A du^2 + B du dv + C dv^2 is the Gaussian's exponent
+//   r1 = (C, opacity, p_min, depth)
+//   r2 = (red, green, blue, tile count as float bits)
+struct Rec {
+  float4 r0, r1, r2;
+};
+
+// Packed tile rectangle of an item: first column (may wrap), column count, first row, rows.
+struct Rect {
+  uint16_t col0, ncols, row0, nrows;
+};
+
+__host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+__device__ inline int view_of_tile(const ViewTable& vt, int32_t g) {
+  int v = 0;
+  while (v + 1 < vt.n_views && g >= vt.tile_base[v + 1]) ++v;
+  return v;
+}
+
+__device__ inline int view_of_item(int64_t item, int64_t n) { return (int)(item / n); }
+
+inline ViewTable make_view_table(const odgs_plan* p) {
+  ViewTable vt{};
+  vt.n_views = p->n_views;
+  for (int v = 0; v < p->n_views; ++v) {
+    vt.W[v] = p->width[v];
+    vt.H[v] = p->height[v];
+  }
+  for (int v = 0; v <= p->n_views; ++v) {
+    vt.tile_base[v] = p->tile_base[v];
+    vt.pix_base[v] = p->pix_base[v];
+  }
+  return vt;
+}
+
+template <typename T>
+inline T* ws_ptr(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+template <typename T>
+inline const T* ws_ptr(const void* ws, size_t off) {
+  return reinterpret_cast<const T*>(static_cast<const char*>(ws) + off);
+}
+
+// Launchers implemented in the kernel translation units.
+hipError_t launch_preprocess(const odgs_plan* p, const float* means, const float* scales, const float* quats,
+                             const float* opac, const float* sh, const float* cams, void* ws, hipStream_t st);
+hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st);
+hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float* out_T, hipStream_t st);
+hipError_t launch_render_bwd(const odgs_plan* p, void* ws, const float* dL_drgb, hipStream_t st);
+hipError_t launch_preprocess_bwd(const odgs_plan* p, const float* means, const float* scales, const float* quats,
+                                 const float* opac, const float* sh, const float* cams, const void* ws, float* d_means,
+                                 float* d_scales, float* d_quats, float* d_opac, float* d_sh, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* ptr, uint32_t value, int64_t n, hipStream_t st);
+hipError_t launch_status_reset(const odgs_plan* p, void* ws, hipStream_t st);
+hipError_t launch_debug_records(const odgs_plan* p, const void* ws, float* out, hipStream_t st);
+hipError_t launch_debug_keys(const odgs_plan* p, const void* ws, int64_t cap, uint64_t* keys, uint32_t* gauss,
+                             hipStream_t st);
+
+// Sort sizes: 256 threads x kSortIpt keys per block.
+constexpr int kSortThreads = 256;
+constexpr int kSortIpt = 16;
+constexpr int kSortBlockItems = kSortThreads * kSortIpt;
+
+}  // namespace odgs

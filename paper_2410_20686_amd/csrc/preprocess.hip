@@ -1,0 +1,554 @@
+// Per-(Gaussian, view) projection of the omnidirectional rasterizer and its adjoint, gfx950.
+//
+// One thread per Gaussian; the thread loops over the views, so the Gaussian's parameters
+// (236 bytes at SH degree 3) are read from HBM once per step however many views there are.
+// All geometry is evaluated in FP64: the radial depth is a sort key and the footprint rectangle
+// decides binning, and both must be bit-identical to an FP64 evaluation of the same formulas.
+// On gfx950 FP64 FMA issues at the same rate as non-packed FP32 and this kernel is bound by
+// HBM traffic, so double precision costs almost nothing here.
+#include <math.h>
+
+#include "common.h"
+
+namespace odgs {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct Params {
+  int32_t tile;
+  double near_r, far_r, dilation, pole_eps;
+};
+
+struct Cam {
+  double R[9];
+  double t[3];
+  double c[3];  // camera centre -R^T t
+};
+
+__device__ inline void load_cam(const float* __restrict__ cams, int v, Cam& c) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) c.R[k] = (double)cams[v * 12 + k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) c.t[k] = (double)cams[v * 12 + 9 + k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) c.c[k] = -((c.R[k] * c.t[0] + c.R[3 + k] * c.t[1]) + c.R[6 + k] * c.t[2]);
+}
+
+// Real spherical harmonics, degree <= 3, orthonormal, (l, m = -l..l) order; constants are
+// 1/(2 sqrt(pi)), sqrt(3/(4 pi)), sqrt(15/pi)/2, sqrt(5/pi)/4, sqrt(15/pi)/4, sqrt(35/(2 pi))/4,
+// sqrt(105/pi)/2, sqrt(21/(2 pi))/4, sqrt(7/pi)/4, sqrt(105/pi)/4.
+constexpr double kY0 = 0.28209479177387814;
+constexpr double kY1 = 0.4886025119029199;
+constexpr double kY2a = 1.0925484305920792;
+constexpr double kY2b = 0.31539156525252005;
+constexpr double kY2c = 0.5462742152960396;
+constexpr double kY3a = 0.5900435899266435;
+constexpr double kY3b = 2.890611442640554;
+constexpr double kY3c = 0.4570457994644658;
+constexpr double kY3d = 0.3731763325901154;
+constexpr double kY3e = 1.445305721320277;
+
+template <int K>
+__device__ inline void sh_basis(double x, double y, double z, double* Y) {
+  Y[0] = kY0;
+  if constexpr (K > 1) {
+    Y[1] = kY1 * y;
+    Y[2] = kY1 * z;
+    Y[3] = kY1 * x;
+  }
+  if constexpr (K > 4) {
+    const double xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = kY2a * (x * y);
+    Y[5] = kY2a * (y * z);
+    Y[6] = kY2b * (2.0 * zz - xx - yy);
+    Y[7] = kY2a * (x * z);
+    Y[8] = kY2c * (xx - yy);
+    if constexpr (K > 9) {
+      Y[9] = kY3a * (y * (3.0 * xx - yy));
+      Y[10] = kY3b * (x * y * z);
+      Y[11] = kY3c * (y * (4.0 * zz - xx - yy));
+      Y[12] = kY3d * (z * (2.0 * zz - 3.0 * xx - 3.0 * yy));
+      Y[13] = kY3c * (x * (4.0 * zz - xx - yy));
+      Y[14] = kY3e * (z * (xx - yy));
+      Y[15] = kY3a * (x * (xx - 3.0 * yy));
+    }
+  }
+}
+
+// Gradient of each basis polynomial w.r.t. (x, y, z) (before projection onto the sphere).
+template <int K>
+__device__ inline void sh_basis_grad(double x, double y, double z, double (*dY)[3]) {
+  dY[0][0] = dY[0][1] = dY[0][2] = 0.0;
+  if constexpr (K > 1) {
+    dY[1][0] = 0.0; dY[1][1] = kY1; dY[1][2] = 0.0;
+    dY[2][0] = 0.0; dY[2][1] = 0.0; dY[2][2] = kY1;
+    dY[3][0] = kY1; dY[3][1] = 0.0; dY[3][2] = 0.0;
+  }
+  if constexpr (K > 4) {
+    dY[4][0] = kY2a * y; dY[4][1] = kY2a * x; dY[4][2] = 0.0;
+    dY[5][0] = 0.0; dY[5][1] = kY2a * z; dY[5][2] = kY2a * y;
+    dY[6][0] = -2.0 * kY2b * x; dY[6][1] = -2.0 * kY2b * y; dY[6][2] = 4.0 * kY2b * z;
+    dY[7][0] = kY2a * z; dY[7][1] = 0.0; dY[7][2] = kY2a * x;
+    dY[8][0] = 2.0 * kY2c * x; dY[8][1] = -2.0 * kY2c * y; dY[8][2] = 0.0;
+    if constexpr (K > 9) {
+      const double xx = x * x, yy = y * y, zz = z * z;
+      dY[9][0] = 6.0 * kY3a * x * y; dY[9][1] = 3.0 * kY3a * (xx - yy); dY[9][2] = 0.0;
+      dY[10][0] = kY3b * y * z; dY[10][1] = kY3b * x * z; dY[10][2] = kY3b * x * y;
+      dY[11][0] = -2.0 * kY3c * x * y; dY[11][1] = kY3c * (4.0 * zz - xx - 3.0 * yy); dY[11][2] = 8.0 * kY3c * y * z;
+      dY[12][0] = -6.0 * kY3d * x * z; dY[12][1] = -6.0 * kY3d * y * z; dY[12][2] = kY3d * (6.0 * zz - 3.0 * xx - 3.0 * yy);
+      dY[13][0] = kY3c * (4.0 * zz - 3.0 * xx - yy); dY[13][1] = -2.0 * kY3c * x * y; dY[13][2] = 8.0 * kY3c * x * z;
+      dY[14][0] = 2.0 * kY3e * x * z; dY[14][1] = -2.0 * kY3e * y * z; dY[14][2] = kY3e * (xx - yy);
+      dY[15][0] = 3.0 * kY3a * (xx - yy); dY[15][1] = -6.0 * kY3a * x * y; dY[15][2] = 0.0;
+    }
+  }
+}
+
+// View-independent part: rotation of the normalised quaternion and Sigma = (R S)(R S)^T.
+struct Cov3 {
+  double qn, w, x, y, z;  // |q| and the normalised quaternion
+  double Rq[9];
+  double M[9];            // Rq * diag(s)
+  double S[9];            // Sigma
+};
+
+__device__ inline void cov3(const double s[3], const double q[4], Cov3& c) {
+  c.qn = sqrt(((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3]);
+  c.w = q[0] / c.qn;
+  c.x = q[1] / c.qn;
+  c.y = q[2] / c.qn;
+  c.z = q[3] / c.qn;
+  const double w = c.w, x = c.x, y = c.y, z = c.z;
+  c.Rq[0] = 1.0 - 2.0 * (y * y + z * z);
+  c.Rq[1] = 2.0 * (x * y - w * z);
+  c.Rq[2] = 2.0 * (x * z + w * y);
+  c.Rq[3] = 2.0 * (x * y + w * z);
+  c.Rq[4] = 1.0 - 2.0 * (x * x + z * z);
+  c.Rq[5] = 2.0 * (y * z - w * x);
+  c.Rq[6] = 2.0 * (x * z - w * y);
+  c.Rq[7] = 2.0 * (y * z + w * x);
+  c.Rq[8] = 1.0 - 2.0 * (x * x + y * y);
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c.M[3 * r + k] = c.Rq[3 * r + k] * s[k];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      c.S[3 * r + k] = (c.M[3 * r] * c.M[3 * k] + c.M[3 * r + 1] * c.M[3 * k + 1]) + c.M[3 * r + 2] * c.M[3 * k + 2];
+}
+
+// View-dependent geometry shared by the forward and the adjoint.
+struct Geo {
+  double mu[3], r2, r, p, rho;  // camera-space mean, |mu|^2, |mu|, mu_x^2 + mu_z^2, sqrt of it
+  double u, v;
+  double J[6];                  // J_omni = d(u, v) / d mu (closed form of Appendix B)
+  double A[6];                  // J_omni * R
+  double c2[3];                 // Sigma_2D + dilation: uu, uv, vv
+  double det;
+};
+
+// Returns false when the item is culled by the shell or the pole test.
+__device__ inline bool geometry(const double m[3], const Cam& cam, const Cov3& cv, int W, int H, const Params& P,
+                                Geo& g) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    g.mu[r] = ((cam.R[3 * r] * m[0] + cam.R[3 * r + 1] * m[1]) + cam.R[3 * r + 2] * m[2]) + cam.t[r];
+  g.r2 = (g.mu[0] * g.mu[0] + g.mu[1] * g.mu[1]) + g.mu[2] * g.mu[2];
+  g.r = sqrt(g.r2);
+  g.p = g.mu[0] * g.mu[0] + g.mu[2] * g.mu[2];
+  g.rho = sqrt(g.p);
+  if (!(g.r > P.near_r && g.r < P.far_r)) return false;
+  if (!(g.rho > P.pole_eps * g.r)) return false;
+  const double Wd = (double)W, Hd = (double)H;
+  const double phi = atan2(g.mu[0], g.mu[2]);
+  const double theta = atan2(-g.mu[1], g.rho);
+  g.u = (Wd / (2.0 * kPi)) * phi + Wd / 2.0;
+  g.v = (-Hd / kPi) * theta + Hd / 2.0;
+  // J_omni = S_o Q_o J_o T_mu written with cos(theta) = rho/r, sin(theta) = -mu_y/r,
+  // sin(phi) = mu_x/rho, cos(phi) = mu_z/rho.
+  const double a1 = Wd / (2.0 * kPi), a2 = Hd / kPi;
+  const double x = g.mu[0], y = g.mu[1], z = g.mu[2];
+  const double r2rho = g.r2 * g.rho;
+  g.J[0] = a1 * z / g.p;
+  g.J[1] = 0.0;
+  g.J[2] = -a1 * x / g.p;
+  g.J[3] = -a2 * x * y / r2rho;
+  g.J[4] = a2 * g.rho / g.r2;
+  g.J[5] = -a2 * y * z / r2rho;
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      g.A[3 * r + k] = (g.J[3 * r] * cam.R[k] + g.J[3 * r + 1] * cam.R[3 + k]) + g.J[3 * r + 2] * cam.R[6 + k];
+  double AS[6];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      AS[3 * r + k] = (g.A[3 * r] * cv.S[k] + g.A[3 * r + 1] * cv.S[3 + k]) + g.A[3 * r + 2] * cv.S[6 + k];
+  g.c2[0] = ((AS[0] * g.A[0] + AS[1] * g.A[1]) + AS[2] * g.A[2]) + P.dilation;
+  g.c2[1] = (AS[0] * g.A[3] + AS[1] * g.A[4]) + AS[2] * g.A[5];
+  g.c2[2] = ((AS[3] * g.A[3] + AS[4] * g.A[4]) + AS[5] * g.A[5]) + P.dilation;
+  g.det = g.c2[0] * g.c2[2] - g.c2[1] * g.c2[1];
+  return true;
+}
+
+__device__ inline void view_dir(const double m[3], const Cam& cam, double d[3], double& dist) {
+  const double w0 = m[0] - cam.c[0], w1 = m[1] - cam.c[1], w2 = m[2] - cam.c[2];
+  dist = sqrt((w0 * w0 + w1 * w1) + w2 * w2);
+  d[0] = w0 / dist;
+  d[1] = w1 / dist;
+  d[2] = w2 / dist;
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float* __restrict__ means,
+                                                         const float* __restrict__ scales, const float* __restrict__ quats,
+                                                         const float* __restrict__ opac, const float* __restrict__ sh,
+                                                         const float* __restrict__ cams, ViewTable vt, Params P,
+                                                         Rec* __restrict__ rec, Rect* __restrict__ rect,
+                                                         uint32_t* __restrict__ count, uint32_t* __restrict__ dkey,
+                                                         odgs_status* __restrict__ status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < n;
+  const int64_t ii = live ? i : 0;
+  double m[3], s[3], q[4];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) m[k] = (double)means[k * n + ii];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s[k] = (double)scales[k * n + ii];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = (double)quats[k * n + ii];
+  const float o = opac[ii];
+  float coef[K * 3];
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) coef[k] = sh[(int64_t)k * n + ii];
+  Cov3 cv;
+  cov3(s, q, cv);
+  const double p_min = -log(255.0 * (double)o);
+  unsigned long long visible = 0;
+
+  for (int v = 0; v < vt.n_views; ++v) {
+    Cam cam;
+    load_cam(cams, v, cam);
+    const int W = vt.W[v], H = vt.H[v];
+    Geo g;
+    bool kept = live && geometry(m, cam, cv, W, H, P, g);
+    float depth = (float)g.r;
+    Rec out;
+    Rect rr{0, 0, 0, 0};
+    uint32_t cnt = 0;
+    if (kept) {
+      const double ca = g.c2[2] / g.det, cb = -g.c2[1] / g.det, cc = g.c2[0] / g.det;
+      double d[3], dist;
+      view_dir(m, cam, d, dist);
+      double Y[K];
+      sh_basis<K>(d[0], d[1], d[2], Y);
+      float rgb[3];
+      bool finite = isfinite(g.u) && isfinite(g.v);
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc = acc + (double)coef[k * 3 + ch] * Y[k];
+        acc = acc + 0.5;
+        finite = finite && isfinite(acc);
+        rgb[ch] = acc > 0.0 ? (float)acc : 0.0f;
+      }
+      kept = (p_min < 0.0) && (g.det > 0.0) && finite;
+      if (kept) {
+        // Footprint: alpha >= 1/255 inside d^T Sigma^-1 d <= k2 = -2 p_min; half extents
+        // sqrt(k2 Sigma_uu), sqrt(k2 Sigma_vv), padded by 0.1% + 0.01 px.
+        const double k2 = -2.0 * p_min;
+        const double eu = sqrt(k2 * g.c2[0]) * (1.0 + 1e-3) + 1e-2;
+        const double ev = sqrt(k2 * g.c2[2]) * (1.0 + 1e-3) + 1e-2;
+        const int B = P.tile;
+        const int ntx = W / B, nty = H / B;
+        const double clo = floor((g.u - eu) / B), chi = floor((g.u + eu) / B);
+        int col0, ncols;
+        if (!(chi - clo + 1.0 < (double)ntx)) {
+          col0 = 0;
+          ncols = ntx;
+        } else {
+          long long c0 = (long long)clo % ntx;
+          if (c0 < 0) c0 += ntx;
+          col0 = (int)c0;
+          ncols = (int)(chi - clo + 1.0);
+        }
+        const double rlo = fmax(0.0, floor((g.v - ev) / B));
+        const double rhi = fmin((double)(nty - 1), floor((g.v + ev) / B));
+        const int row0 = (int)rlo;
+        const int nrows = (int)(rhi - rlo + 1.0);
+        kept = nrows > 0;
+        if (kept) {
+          rr = Rect{(uint16_t)col0, (uint16_t)ncols, (uint16_t)row0, (uint16_t)nrows};
+          cnt = (uint32_t)ncols * (uint32_t)nrows;
+          out.r0 = make_float4((float)g.u, (float)g.v, -0.5f * (float)ca, -(float)cb);
+          out.r1 = make_float4(-0.5f * (float)cc, o, (float)p_min, depth);
+          out.r2 = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(cnt));
+        }
+      }
+    }
+    if (live) {
+      const int64_t item = (int64_t)v * n + i;
+      if (!kept) {
+        out.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        out.r1 = make_float4(0.f, 0.f, 0.f, depth);
+        out.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      rec[item] = out;
+      rect[item] = rr;
+      count[item] = cnt;
+      dkey[item] = kept ? __float_as_uint(depth) : 0xffffffffu;
+    }
+    visible += kept ? 1 : 0;
+  }
+  // one atomic per wave for the visible-item counter
+  unsigned long long tot = visible;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+  if ((threadIdx.x & (kWave - 1)) == 0 && tot) atomicAdd((unsigned long long*)&status->n_visible, tot);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Adjoint.  Inputs per item: 2D gradients g2d[9][items] = (u, v, conic a, b, c, opacity, r, g, b)
+// where the inverse covariance is [[a, b], [b, c]] (b is the shared off-diagonal).  Sums over
+// views; writes (overwrites) the parameter gradients.
+// ---------------------------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(256) void preprocess_bwd_kernel(
+    int64_t n, const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
+    const float* __restrict__ opac, const float* __restrict__ sh, const float* __restrict__ cams, ViewTable vt, Params P,
+    const uint32_t* __restrict__ count, const float* __restrict__ g2d, int64_t items, float* __restrict__ d_means,
+    float* __restrict__ d_scales, float* __restrict__ d_quats, float* __restrict__ d_opac, float* __restrict__ d_sh) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double m[3], s[3], q[4];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) m[k] = (double)means[k * n + i];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s[k] = (double)scales[k * n + i];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = (double)quats[k * n + i];
+  float coef[K * 3];
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) coef[k] = sh[(int64_t)k * n + i];
+  Cov3 cv;
+  cov3(s, q, cv);
+
+  double gm[3] = {0.0, 0.0, 0.0};
+  double gS[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // dL/dSigma (symmetric)
+  double go = 0.0;
+  double gsh[K * 3];
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) gsh[k] = 0.0;
+
+  for (int v = 0; v < vt.n_views; ++v) {
+    const int64_t item = (int64_t)v * n + i;
+    if (count[item] == 0) continue;
+    double g[9];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      g[k] = (double)g2d[(int64_t)k * items + item];
+      any = any || g[k] != 0.0;
+    }
+    if (!any) continue;
+    Cam cam;
+    load_cam(cams, v, cam);
+    Geo G;
+    geometry(m, cam, cv, vt.W[v], vt.H[v], P, G);
+    // conic = inverse(Sigma2D): dL/dSigma2D = -C Gc C with Gc = [[ga, gb/2], [gb/2, gc]].
+    const double inv = 1.0 / G.det;
+    const double ca = G.c2[2] * inv, cb = -G.c2[1] * inv, cc = G.c2[0] * inv;
+    const double gc00 = g[2], gc01 = 0.5 * g[3], gc11 = g[4];
+    const double t00 = ca * gc00 + cb * gc01, t01 = ca * gc01 + cb * gc11;
+    const double t10 = cb * gc00 + cc * gc01, t11 = cb * gc01 + cc * gc11;
+    const double G00 = -(t00 * ca + t01 * cb);
+    const double G01 = -(t00 * cb + t01 * cc);
+    const double G11 = -(t10 * cb + t11 * cc);
+    // Sigma2D = A Sigma A^T: dA = 2 G2 A Sigma, dSigma += A^T G2 A (G2 symmetric 2x2).
+    double GA[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      GA[k] = G00 * G.A[k] + G01 * G.A[3 + k];
+      GA[3 + k] = G01 * G.A[k] + G11 * G.A[3 + k];
+    }
+    double dA[6];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        dA[3 * r + k] = 2.0 * (GA[3 * r] * cv.S[k] + GA[3 * r + 1] * cv.S[3 + k] + GA[3 * r + 2] * cv.S[6 + k]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) gS[3 * a + b] += G.A[a] * GA[b] + G.A[3 + a] * GA[3 + b];
+    // A = J R  =>  dJ = dA R^T
+    double dJ[6];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        dJ[3 * r + k] = dA[3 * r] * cam.R[3 * k] + dA[3 * r + 1] * cam.R[3 * k + 1] + dA[3 * r + 2] * cam.R[3 * k + 2];
+    // d(u, v)/d mu = J (mean path) plus the derivative of J itself.
+    const double x = G.mu[0], y = G.mu[1], z = G.mu[2];
+    const double p = G.p, rho = G.rho, r2 = G.r2, r4 = r2 * r2, p2 = p * p, rho3 = p * rho;
+    const double a1 = (double)vt.W[v] / (2.0 * kPi), a2 = (double)vt.H[v] / kPi;
+    double dmu[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dmu[k] = G.J[k] * g[0] + G.J[3 + k] * g[1];
+    const double xz2 = x * x - z * z;
+    const double q2 = 2.0 * p + r2;
+    const double r2m2y = r2 - 2.0 * y * y;
+    const double r2m2p = r2 - 2.0 * p;
+    // J00 = a1 z / p, J02 = -a1 x / p
+    dmu[0] += dJ[0] * (-2.0 * a1 * x * z / p2) + dJ[2] * (a1 * xz2 / p2);
+    dmu[2] += dJ[0] * (a1 * xz2 / p2) + dJ[2] * (2.0 * a1 * x * z / p2);
+    // J10 = -a2 x y / (r^2 rho)
+    dmu[0] += dJ[3] * (-a2 * y * (r2 * z * z - 2.0 * x * x * p) / (r4 * rho3));
+    dmu[1] += dJ[3] * (-a2 * x * r2m2y / (r4 * rho));
+    dmu[2] += dJ[3] * (a2 * x * y * z * q2 / (r4 * rho3));
+    // J11 = a2 rho / r^2
+    dmu[0] += dJ[4] * (a2 * x * r2m2p / (rho * r4));
+    dmu[1] += dJ[4] * (-2.0 * a2 * rho * y / r4);
+    dmu[2] += dJ[4] * (a2 * z * r2m2p / (rho * r4));
+    // J12 = -a2 y z / (r^2 rho)
+    dmu[0] += dJ[5] * (a2 * x * y * z * q2 / (r4 * rho3));
+    dmu[1] += dJ[5] * (-a2 * z * r2m2y / (r4 * rho));
+    dmu[2] += dJ[5] * (-a2 * y * (r2 * x * x - 2.0 * z * z * p) / (r4 * rho3));
+    // mu = R m + t  =>  dm = R^T dmu
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gm[k] += cam.R[k] * dmu[0] + cam.R[3 + k] * dmu[1] + cam.R[6 + k] * dmu[2];
+    go += g[5];
+    // colour = max(0, sum_k sh_k Y_k(dir) + 0.5), dir = (m - c) / |m - c|
+    double d[3], dist;
+    view_dir(m, cam, d, dist);
+    double Y[K];
+    sh_basis<K>(d[0], d[1], d[2], Y);
+    double dY[K][3];
+    sh_basis_grad<K>(d[0], d[1], d[2], dY);
+    double gdir[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc = acc + (double)coef[k * 3 + ch] * Y[k];
+      acc = acc + 0.5;
+      if (!(acc > 0.0)) continue;
+      const double gc = g[6 + ch];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        gsh[k * 3 + ch] += gc * Y[k];
+        const double w = gc * (double)coef[k * 3 + ch];
+        gdir[0] += w * dY[k][0];
+        gdir[1] += w * dY[k][1];
+        gdir[2] += w * dY[k][2];
+      }
+    }
+    const double dd = gdir[0] * d[0] + gdir[1] * d[1] + gdir[2] * d[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gm[k] += (gdir[k] - d[k] * dd) / dist;
+  }
+
+  // Sigma = M M^T, M = Rq diag(s): dM = 2 dSigma M (dSigma symmetric).
+  double dM[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      dM[3 * r + k] = 2.0 * (gS[3 * r] * cv.M[k] + gS[3 * r + 1] * cv.M[3 + k] + gS[3 * r + 2] * cv.M[6 + k]);
+  double gs[3], dR[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gs[k] = dM[k] * cv.Rq[k] + dM[3 + k] * cv.Rq[3 + k] + dM[6 + k] * cv.Rq[6 + k];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dR[3 * r + k] = dM[3 * r + k] * s[k];
+  // Rq of the unit quaternion (w, x, y, z)
+  const double w = cv.w, x = cv.x, y = cv.y, z = cv.z;
+  double gw = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+  double gx = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                     2.0 * x * dR[8]);
+  double gy = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                     2.0 * y * dR[8]);
+  double gz = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] +
+                     y * dR[7]);
+  // normalisation q_hat = q / |q|
+  const double dot = gw * w + gx * x + gy * y + gz * z;
+  const double iq = 1.0 / cv.qn;
+  d_quats[i] = (float)((gw - w * dot) * iq);
+  d_quats[n + i] = (float)((gx - x * dot) * iq);
+  d_quats[2 * n + i] = (float)((gy - y * dot) * iq);
+  d_quats[3 * n + i] = (float)((gz - z * dot) * iq);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    d_means[k * n + i] = (float)gm[k];
+    d_scales[k * n + i] = (float)gs[k];
+  }
+  d_opac[i] = (float)go;
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = (float)gsh[k];
+}
+
+Params make_params(const odgs_plan* p) {
+  Params P;
+  P.tile = p->s.tile;
+  P.near_r = p->s.near_r;
+  P.far_r = p->s.far_r;
+  P.dilation = p->s.dilation;
+  P.pole_eps = p->s.pole_eps;
+  return P;
+}
+
+}  // namespace
+
+hipError_t launch_preprocess(const odgs_plan* p, const float* means, const float* scales, const float* quats,
+                             const float* opac, const float* sh, const float* cams, void* ws, hipStream_t st) {
+  if (p->n == 0) return hipSuccess;
+  const ViewTable vt = make_view_table(p);
+  const Params P = make_params(p);
+  const unsigned grid = (unsigned)((p->n + 255) / 256);
+  Rec* rec = ws_ptr<Rec>(ws, p->off_rec);
+  Rect* rect = ws_ptr<Rect>(ws, p->off_rect);
+  uint32_t* count = ws_ptr<uint32_t>(ws, p->off_count);
+  uint32_t* dkey = ws_ptr<uint32_t>(ws, p->off_dkey[0]);
+  odgs_status* status = ws_ptr<odgs_status>(ws, p->off_status);
+#define ODGS_PRE(KK)                                                                                               \
+  hipLaunchKernelGGL(preprocess_kernel<KK>, dim3(grid), dim3(256), 0, st, p->n, means, scales, quats, opac, sh, cams, \
+                     vt, P, rec, rect, count, dkey, status)
+  switch (p->sh_degree) {
+    case 0: ODGS_PRE(1); break;
+    case 1: ODGS_PRE(4); break;
+    case 2: ODGS_PRE(9); break;
+    default: ODGS_PRE(16); break;
+  }
+#undef ODGS_PRE
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(const odgs_plan* p, const float* means, const float* scales, const float* quats,
+                                 const float* opac, const float* sh, const float* cams, const void* ws, float* d_means,
+                                 float* d_scales, float* d_quats, float* d_opac, float* d_sh, hipStream_t st) {
+  if (p->n == 0) return hipSuccess;
+  const ViewTable vt = make_view_table(p);
+  const Params P = make_params(p);
+  const unsigned grid = (unsigned)((p->n + 255) / 256);
+  const uint32_t* count = ws_ptr<uint32_t>(ws, p->off_count);
+  const float* g2d = ws_ptr<float>(ws, p->off_g2d);
+#define ODGS_PREB(KK)                                                                                             \
+  hipLaunchKernelGGL(preprocess_bwd_kernel<KK>, dim3(grid), dim3(256), 0, st, p->n, means, scales, quats, opac, sh, \
+                     cams, vt, P, count, g2d, p->items, d_means, d_scales, d_quats, d_opac, d_sh)
+  switch (p->sh_degree) {
+    case 0: ODGS_PREB(1); break;
+    case 1: ODGS_PREB(4); break;
+    case 2: ODGS_PREB(9); break;
+    default: ODGS_PREB(16); break;
+  }
+#undef ODGS_PREB
+  return hipGetLastError();
+}
+
+}  // namespace odgs

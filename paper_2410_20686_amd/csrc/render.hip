@@ -1,0 +1,332 @@
+// Compositing kernels of the omnidirectional rasterizer, gfx950.
+//
+// Forward: one workgroup per (view, tile), one thread per pixel.  The tile's depth-ordered list
+// is staged through LDS in batches of one record per thread, and every pixel alpha-composites
+// front to back (Eq. gaussian2d, Eq. alphablending) until its transmittance would drop below
+// 1e-4; the workgroup stops loading batches once every pixel has finished.
+// Backward: the same workgroups walk their lists back to front from the last contributor,
+// recover T by division, and produce per-pixel gradients of the 2D quantities; these are summed
+// across each wavefront with cross-lane reductions, across the workgroup's wavefronts in LDS,
+// and only then added to global memory with one float atomic per (Gaussian, tile, quantity).
+// All views of a step are covered by one launch: the grid spans the global tile ids of every
+// view (views may differ in size).
+#include <utility>
+
+#include "common.h"
+
+namespace odgs {
+namespace {
+
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTStop = 1e-4f;
+
+__device__ inline float wave_sum(float x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+template <int TILE, int BATCH>
+__global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(ViewTable vt, const uint2* __restrict__ ranges,
+                                                                const uint32_t* __restrict__ pair_items,
+                                                                const Rec* __restrict__ rec, float* __restrict__ out_rgb,
+                                                                float* __restrict__ out_T, float* __restrict__ ws_T,
+                                                                int32_t* __restrict__ ws_last, float bg0, float bg1,
+                                                                float bg2) {
+  constexpr int N = TILE * TILE;
+  __shared__ float4 s0[BATCH];
+  __shared__ float4 s1[BATCH];
+  __shared__ float4 s2[BATCH];
+  const int g = blockIdx.x;
+  const int v = view_of_tile(vt, g);
+  const int W = vt.W[v], H = vt.H[v];
+  const int ntx = W / TILE;
+  const int lt = g - vt.tile_base[v];
+  const int x = (lt % ntx) * TILE + (int)(threadIdx.x % TILE);
+  const int y = (lt / ntx) * TILE + (int)(threadIdx.x / TILE);
+  const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+  const float Wf = (float)W, half = (float)W * 0.5f;
+  const uint2 rg = ranges[g];
+  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+  int last = 0;
+  bool done = false;
+  for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
+    if (__syncthreads_count(done) == N) break;
+    const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
+    for (int t = threadIdx.x; t < cnt; t += N) {
+      const Rec r = rec[pair_items[base + t]];
+      s0[t] = r.r0;
+      s1[t] = r.r1;
+      s2[t] = r.r2;
+    }
+    __syncthreads();
+    if (!done) {
+      for (int k = 0; k < cnt; ++k) {
+        const float4 a = s0[k];
+        const float4 b = s1[k];
+        float du = px - a.x;
+        if (du >= half) du = du - Wf;
+        else if (du < -half) du = du + Wf;
+        const float dv = py - a.y;
+        const float power = fmaf(a.z, du * du, fmaf(a.w, du * dv, b.x * (dv * dv)));
+        if (power > 0.0f || power < b.z) continue;
+        float alpha = b.y * __expf(power);
+        if (alpha > kAlphaMax) alpha = kAlphaMax;
+        const float Tn = T * (1.0f - alpha);
+        if (Tn < kTStop) {
+          done = true;
+          break;
+        }
+        const float w = alpha * T;
+        const float4 c = s2[k];
+        C0 = fmaf(w, c.x, C0);
+        C1 = fmaf(w, c.y, C1);
+        C2 = fmaf(w, c.z, C2);
+        T = Tn;
+        last = (int)(base - rg.x) + k + 1;
+      }
+    }
+  }
+  const int64_t plane = (int64_t)W * H;
+  const int64_t pix = (int64_t)y * W + x;
+  float* img = out_rgb + 3 * vt.pix_base[v];
+  img[pix] = fmaf(T, bg0, C0);
+  img[plane + pix] = fmaf(T, bg1, C1);
+  img[2 * plane + pix] = fmaf(T, bg2, C2);
+  const int64_t gp = vt.pix_base[v] + pix;
+  ws_T[gp] = T;
+  ws_last[gp] = last;
+  if (out_T) out_T[gp] = T;
+}
+
+// g2d layout: [9][items] = d/du, d/dv, d/da, d/db, d/dc, d/dopacity, d/dr, d/dg, d/db(colour),
+// with the inverse 2D covariance [[a, b], [b, c]].
+template <int TILE, int BATCH>
+__global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, const uint2* __restrict__ ranges,
+                                                                const uint32_t* __restrict__ pair_items,
+                                                                const Rec* __restrict__ rec, const float* __restrict__ ws_T,
+                                                                const int32_t* __restrict__ ws_last,
+                                                                const float* __restrict__ dL_drgb, float* __restrict__ g2d,
+                                                                int64_t items, float bg0, float bg1, float bg2) {
+  constexpr int N = TILE * TILE;
+  __shared__ float4 s0[BATCH];
+  __shared__ float4 s1[BATCH];
+  __shared__ float4 s2[BATCH];
+  __shared__ uint32_t sid[BATCH];
+  __shared__ float acc[9][BATCH];
+  __shared__ int smax;
+  const int g = blockIdx.x;
+  const int v = view_of_tile(vt, g);
+  const int W = vt.W[v], H = vt.H[v];
+  const int ntx = W / TILE;
+  const int lt = g - vt.tile_base[v];
+  const int x = (lt % ntx) * TILE + (int)(threadIdx.x % TILE);
+  const int y = (lt / ntx) * TILE + (int)(threadIdx.x / TILE);
+  const int lane = threadIdx.x & (kWave - 1);
+  const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+  const float Wf = (float)W, half = (float)W * 0.5f;
+  const uint2 rg = ranges[g];
+  const int64_t plane = (int64_t)W * H;
+  const int64_t pix = (int64_t)y * W + x;
+  const int64_t gp = vt.pix_base[v] + pix;
+  const float* dimg = dL_drgb + 3 * vt.pix_base[v];
+  const float dl0 = dimg[pix], dl1 = dimg[plane + pix], dl2 = dimg[2 * plane + pix];
+  float T = ws_T[gp];
+  const int last = ws_last[gp];
+  float S0 = T * bg0, S1 = T * bg1, S2 = T * bg2;  // colour of everything behind, incl. background
+  if (threadIdx.x == 0) smax = 0;
+  __syncthreads();
+  atomicMax(&smax, last);
+  __syncthreads();
+  const int end_all = smax;
+  for (int end = end_all; end > 0; end -= BATCH) {
+    const int cnt = min(BATCH, end);
+    for (int t = threadIdx.x; t < cnt; t += N) {
+      const uint32_t item = pair_items[rg.x + end - 1 - t];
+      const Rec r = rec[item];
+      s0[t] = r.r0;
+      s1[t] = r.r1;
+      s2[t] = r.r2;
+      sid[t] = item;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) acc[q][t] = 0.0f;
+    }
+    __syncthreads();
+    for (int k = 0; k < cnt; ++k) {
+      const int jrel = end - 1 - k;
+      float gq[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) gq[q] = 0.0f;
+      bool contrib = false;
+      if (jrel < last) {
+        const float4 a = s0[k];
+        const float4 b = s1[k];
+        float du = px - a.x;
+        if (du >= half) du = du - Wf;
+        else if (du < -half) du = du + Wf;
+        const float dv = py - a.y;
+        const float power = fmaf(a.z, du * du, fmaf(a.w, du * dv, b.x * (dv * dv)));
+        if (!(power > 0.0f || power < b.z)) {
+          contrib = true;
+          const float G = __expf(power);
+          float alpha = b.y * G;
+          const bool clamped = alpha > kAlphaMax;
+          if (clamped) alpha = kAlphaMax;
+          const float om = 1.0f - alpha;
+          T = T / om;  // transmittance in front of this Gaussian
+          const float w = alpha * T;
+          const float4 c = s2[k];
+          gq[6] = w * dl0;
+          gq[7] = w * dl1;
+          gq[8] = w * dl2;
+          const float inv_om = 1.0f / om;
+          const float dL_da =
+              dl0 * (c.x * T - S0 * inv_om) + dl1 * (c.y * T - S1 * inv_om) + dl2 * (c.z * T - S2 * inv_om);
+          S0 = fmaf(c.x, w, S0);
+          S1 = fmaf(c.y, w, S1);
+          S2 = fmaf(c.z, w, S2);
+          if (!clamped) {
+            const float dpow = dL_da * alpha;
+            const float ca = -2.0f * a.z, cb = -a.w, cc = -2.0f * b.x;
+            gq[0] = dpow * (ca * du + cb * dv);
+            gq[1] = dpow * (cb * du + cc * dv);
+            gq[2] = -0.5f * dpow * (du * du);
+            gq[3] = -dpow * (du * dv);
+            gq[4] = -0.5f * dpow * (dv * dv);
+            gq[5] = dL_da * G;
+          }
+        }
+      }
+      if (__ballot(contrib) != 0ull) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) gq[q] = wave_sum(gq[q]);
+        if (lane == 0) {
+#pragma unroll
+          for (int q = 0; q < 9; ++q) atomicAdd(&acc[q][k], gq[q]);
+        }
+      }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += N) {
+      const uint32_t item = sid[t];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const float s = acc[q][t];
+        if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)q * items + item], s);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void debug_records_kernel(const Rec* __restrict__ rec, int64_t items, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= items) return;
+  const Rec r = rec[i];
+  float* o = out + i * 12;
+  o[0] = r.r0.x; o[1] = r.r0.y; o[2] = r.r0.z; o[3] = r.r0.w;
+  o[4] = r.r1.x; o[5] = r.r1.y; o[6] = r.r1.z; o[7] = r.r1.w;
+  o[8] = r.r2.x; o[9] = r.r2.y; o[10] = r.r2.z;
+  o[11] = (float)__float_as_uint(r.r2.w);
+}
+
+__global__ void debug_keys_kernel(const uint32_t* __restrict__ pkey, const uint32_t* __restrict__ pval,
+                                  const Rec* __restrict__ rec, const odgs_status* __restrict__ status, int64_t cap,
+                                  int64_t n, uint64_t* __restrict__ keys, uint32_t* __restrict__ gauss) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t m = min((int64_t)status->n_pairs_stored, cap);
+  if (j >= m) return;
+  const uint32_t item = pval[j];
+  keys[j] = ((uint64_t)pkey[j] << 32) | (uint64_t)__float_as_uint(rec[item].r1.w);
+  gauss[j] = (uint32_t)(item % n);
+}
+
+template <int TILE, int BATCH>
+void fwd_launch(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
+                const Rec* rec, float* out_rgb, float* out_T, float* wT, int32_t* wl, hipStream_t st) {
+  hipLaunchKernelGGL((render_fwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items, rec,
+                     out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+}
+
+template <int TILE, int BATCH>
+void bwd_launch(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
+                const Rec* rec, const float* wT, const int32_t* wl, const float* dL, float* g2d, hipStream_t st) {
+  hipLaunchKernelGGL((render_bwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items, rec,
+                     wT, wl, dL, g2d, p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+}
+
+// Dispatch over the supported (tile, batch) pairs; returns false for an unsupported pair.
+template <template <int, int> class F, typename... Args>
+bool dispatch(int tile, int batch, Args&&... args) {
+#define ODGS_CASE(TT, BB)                        \
+  if (tile == TT && batch == BB) {               \
+    F<TT, BB>::run(std::forward<Args>(args)...); \
+    return true;                                 \
+  }
+  ODGS_CASE(8, 32) ODGS_CASE(8, 64) ODGS_CASE(8, 128) ODGS_CASE(8, 256)
+  ODGS_CASE(16, 32) ODGS_CASE(16, 64) ODGS_CASE(16, 128) ODGS_CASE(16, 256)
+  ODGS_CASE(32, 64) ODGS_CASE(32, 128) ODGS_CASE(32, 256)
+#undef ODGS_CASE
+  return false;
+}
+
+template <int TILE, int BATCH>
+struct FwdRun {
+  template <typename... A>
+  static void run(A&&... a) { fwd_launch<TILE, BATCH>(std::forward<A>(a)...); }
+};
+template <int TILE, int BATCH>
+struct BwdRun {
+  template <typename... A>
+  static void run(A&&... a) { bwd_launch<TILE, BATCH>(std::forward<A>(a)...); }
+};
+
+}  // namespace
+
+hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float* out_T, hipStream_t st) {
+  const ViewTable vt = make_view_table(p);
+  const int tiles = p->tile_base[p->n_views];
+  if (tiles == 0) return hipSuccess;
+  const uint2* ranges = ws_ptr<uint2>(ws, p->off_ranges);
+  const uint32_t* items = ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]);
+  const Rec* rec = ws_ptr<Rec>(ws, p->off_rec);
+  float* wT = ws_ptr<float>(ws, p->off_T);
+  int32_t* wl = ws_ptr<int32_t>(ws, p->off_last);
+  if (!dispatch<FwdRun>(p->s.tile, p->s.batch, p, tiles, vt, ranges, items, rec, out_rgb, out_T, wT, wl, st))
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_render_bwd(const odgs_plan* p, void* ws, const float* dL_drgb, hipStream_t st) {
+  const ViewTable vt = make_view_table(p);
+  const int tiles = p->tile_base[p->n_views];
+  float* g2d = ws_ptr<float>(ws, p->off_g2d);
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(g2d), 0u, 9 * p->items, st);
+  if (e != hipSuccess || tiles == 0) return e;
+  const uint2* ranges = ws_ptr<uint2>(ws, p->off_ranges);
+  const uint32_t* items = ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]);
+  const Rec* rec = ws_ptr<Rec>(ws, p->off_rec);
+  const float* wT = ws_ptr<float>(ws, p->off_T);
+  const int32_t* wl = ws_ptr<int32_t>(ws, p->off_last);
+  if (!dispatch<BwdRun>(p->s.tile, p->s.batch, p, tiles, vt, ranges, items, rec, wT, wl, dL_drgb, g2d, st))
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_records(const odgs_plan* p, const void* ws, float* out, hipStream_t st) {
+  if (p->items == 0) return hipSuccess;
+  hipLaunchKernelGGL(debug_records_kernel, dim3((unsigned)((p->items + 255) / 256)), dim3(256), 0, st,
+                     ws_ptr<Rec>(ws, p->off_rec), p->items, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_keys(const odgs_plan* p, const void* ws, int64_t cap, uint64_t* keys, uint32_t* gauss,
+                             hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(debug_keys_kernel, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st,
+                     ws_ptr<uint32_t>(ws, p->off_pkey[p->pair_final]), ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]),
+                     ws_ptr<Rec>(ws, p->off_rec), ws_ptr<odgs_status>(ws, p->off_status), cap, p->n, keys, gauss);
+  return hipGetLastError();
+}
+
+}  // namespace odgs

@@ -1,0 +1,339 @@
+// Binning of the omnidirectional rasterizer, gfx950: depth pre-sort of the (Gaussian, view)
+// items, pair emission, stable LSD radix sort of the pairs by global tile, per-tile ranges.
+//
+// The pairs must end up ordered by the 64-bit key (global tile << 32 | depth bits), ties by
+// Gaussian index.  Instead of sorting 64-bit keys over all pairs, the items (far fewer than the
+// pairs) are first sorted by their 32-bit depth; pairs are then emitted in that order and sorted
+// stably by tile id alone, which needs only ceil(log2(tiles) / 8) passes over the pairs.  The
+// result is the same permutation as a stable sort of the 64-bit keys of index-ordered pairs.
+//
+// Radix sort: 8-bit digits, reduce-then-scan (no inter-workgroup spinning, so no forward-progress
+// assumption): per-block digit histograms, an exclusive scan per digit across blocks, then a
+// stable scatter in which each wavefront ranks its keys with 8 ballots (multi-split).
+// Every count the kernels need (number of pairs) is read from device memory, so the whole
+// chain runs without a host round trip and can be captured in a graph.
+#include "common.h"
+
+namespace odgs {
+namespace {
+
+__device__ inline uint32_t wave_incl_scan(uint32_t x) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// Inclusive scan across a 256-thread block.  `lds` holds 4 words; contains two barriers.
+__device__ inline uint32_t block_incl_scan256(uint32_t x, uint32_t* lds, uint32_t& total) {
+  const uint32_t incl = wave_incl_scan(x);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+  if (lane == kWave - 1) lds[w] = incl;
+  __syncthreads();
+  uint32_t pre = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) pre += (k < w) ? lds[k] : 0u;
+  total = lds[0] + lds[1] + lds[2] + lds[3];
+  __syncthreads();
+  return incl + pre;
+}
+
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t value, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+__device__ inline uint32_t active_count(const uint32_t* n_dev, uint32_t n_host) {
+  return n_dev ? min(*n_dev, n_host) : n_host;
+}
+
+// Per-block histogram of the 8-bit digit at `shift`: hist[digit * nblocks + block].
+__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
+                                                                 const uint32_t* __restrict__ n_dev, uint32_t n_host,
+                                                                 int shift, uint32_t* __restrict__ hist, int nblocks) {
+  __shared__ uint32_t h[256];
+  const int t = threadIdx.x;
+  h[t] = 0;
+  __syncthreads();
+  const uint32_t n = active_count(n_dev, n_host);
+  const uint32_t start = blockIdx.x * (uint32_t)kSortBlockItems;
+#pragma unroll 4
+  for (int r = 0; r < kSortIpt; ++r) {
+    const uint32_t idx = start + r * kSortThreads + t;
+    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[t * nblocks + blockIdx.x] = h[t];
+}
+
+// Block d: exclusive scan of hist[d][0..nblocks) in place; digit total to digit_tot[d].
+__global__ __launch_bounds__(256) void radix_digit_scan_kernel(uint32_t* __restrict__ hist, int nblocks,
+                                                               uint32_t* __restrict__ digit_tot) {
+  __shared__ uint32_t lds[4];
+  uint32_t* row = hist + (size_t)blockIdx.x * nblocks;
+  uint32_t carry = 0;
+  for (int base = 0; base < nblocks; base += 256) {
+    const int k = base + threadIdx.x;
+    const uint32_t x = k < nblocks ? row[k] : 0u;
+    uint32_t total;
+    const uint32_t incl = block_incl_scan256(x, lds, total);
+    if (k < nblocks) row[k] = carry + incl - x;
+    carry += total;
+  }
+  if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
+}
+
+// Stable scatter of one digit pass.  vin == nullptr means the values are the input positions.
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot, int nblocks) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[4][256];
+  __shared__ uint32_t lds[4];
+  const int t = threadIdx.x, lane = t & (kWave - 1), wave = t >> 6;
+  const uint32_t n = active_count(n_dev, n_host);
+  const uint32_t start = blockIdx.x * (uint32_t)kSortBlockItems;
+  if (start >= n) return;  // uniform across the block
+  // global start of each digit for this block
+  uint32_t total;
+  const uint32_t dt = digit_tot[t];
+  const uint32_t incl = block_incl_scan256(dt, lds, total);
+  base[t] = incl - dt + hist[t * nblocks + blockIdx.x];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) wcnt[w][t] = 0;
+  __syncthreads();
+  const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  for (int r = 0; r < kSortIpt; ++r) {
+    const uint32_t idx = start + r * kSortThreads + t;
+    const bool valid = idx < n;
+    const uint32_t key = valid ? kin[idx] : 0u;
+    const uint32_t val = valid ? (vin ? vin[idx] : idx) : 0u;
+    const uint32_t d = (key >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = __popcll(peers & lanes_below);
+    if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+    __syncthreads();
+    {
+      const uint32_t b0 = base[t];
+      const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
+      wcnt[0][t] = b0;
+      wcnt[1][t] = b0 + c0;
+      wcnt[2][t] = b0 + c0 + c1;
+      wcnt[3][t] = b0 + c0 + c1 + c2;
+      base[t] = b0 + c0 + c1 + c2 + c3;
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t pos = wcnt[wave][d] + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < 4; ++w) wcnt[w][t] = 0;
+    __syncthreads();
+  }
+}
+
+// Sum of the tile counts of each block of depth-sorted items.
+constexpr int kScanIpt = 4;
+constexpr int kScanBlockItems = 256 * kScanIpt;
+
+__global__ __launch_bounds__(256) void count_reduce_kernel(const uint32_t* __restrict__ sorted_ids,
+                                                           const uint32_t* __restrict__ count, int64_t items,
+                                                           uint32_t* __restrict__ block_sum) {
+  __shared__ uint32_t lds[4];
+  const int64_t start = (int64_t)blockIdx.x * kScanBlockItems;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanIpt; ++k) {
+    const int64_t j = start + threadIdx.x * kScanIpt + k;
+    if (j < items) s += count[sorted_ids[j]];
+  }
+  uint32_t total;
+  block_incl_scan256(s, lds, total);
+  if (threadIdx.x == 0) block_sum[blockIdx.x] = total;
+}
+
+// Exclusive scan of the block sums (in place, as 64-bit offsets) and the pair total.
+__global__ __launch_bounds__(256) void count_top_kernel(const uint32_t* __restrict__ block_sum,
+                                                        uint64_t* __restrict__ block_off, int nblocks,
+                                                        int64_t capacity, odgs_status* __restrict__ status) {
+  __shared__ uint64_t wtot[4];
+  uint64_t carry = 0;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+  for (int base = 0; base < nblocks; base += 256) {
+    const int k = base + threadIdx.x;
+    const uint64_t x = k < nblocks ? (uint64_t)block_sum[k] : 0ull;
+    uint64_t incl = x;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint64_t y = __shfl_up(incl, off);
+      if (lane >= off) incl += y;
+    }
+    if (lane == kWave - 1) wtot[w] = incl;
+    __syncthreads();
+    uint64_t pre = 0;
+    for (int q = 0; q < w; ++q) pre += wtot[q];
+    const uint64_t total = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+    __syncthreads();
+    if (k < nblocks) block_off[k] = carry + pre + incl - x;
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    status->n_pairs = (int64_t)carry;
+    const int64_t stored = (int64_t)carry < capacity ? (int64_t)carry : capacity;
+    status->n_pairs_stored = (int32_t)stored;
+    if ((int64_t)carry > capacity) status->flags |= ODGS_STATUS_OVERFLOW;
+  }
+}
+
+// Emit the (tile, item) pairs of depth-sorted items: pairs of one item are contiguous, items in
+// depth order, so a later stable sort by tile keeps (depth, index) order inside every tile.
+__global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ sorted_ids,
+                                                   const uint32_t* __restrict__ count, const Rect* __restrict__ rect,
+                                                   const uint64_t* __restrict__ block_off, int64_t items, int64_t n,
+                                                   ViewTable vt, int tile, int64_t capacity,
+                                                   uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
+  __shared__ uint32_t lds[4];
+  const int64_t start = (int64_t)blockIdx.x * kScanBlockItems;
+  uint32_t ids[kScanIpt], cnt[kScanIpt];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanIpt; ++k) {
+    const int64_t j = start + threadIdx.x * kScanIpt + k;
+    ids[k] = j < items ? sorted_ids[j] : 0u;
+    cnt[k] = j < items ? count[ids[k]] : 0u;
+    s += cnt[k];
+  }
+  uint32_t total;
+  const uint32_t incl = block_incl_scan256(s, lds, total);
+  uint64_t off = block_off[blockIdx.x] + (incl - s);
+#pragma unroll 1
+  for (int k = 0; k < kScanIpt; ++k) {
+    if (cnt[k] == 0) continue;
+    const uint32_t item = ids[k];
+    const Rect rr = rect[item];
+    const int v = view_of_item(item, n);
+    const int ntx = vt.W[v] / tile;
+    const uint32_t tb = (uint32_t)vt.tile_base[v];
+    uint64_t pos = off;
+    for (int r = 0; r < rr.nrows; ++r) {
+      const uint32_t rowbase = tb + (uint32_t)(rr.row0 + r) * ntx;
+      int col = rr.col0;
+      for (int c = 0; c < rr.ncols; ++c) {
+        if (pos < (uint64_t)capacity) {
+          pkey[pos] = rowbase + col;
+          pval[pos] = item;
+        }
+        ++pos;
+        if (++col == ntx) col = 0;
+      }
+    }
+    off += cnt[k];
+  }
+}
+
+__global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* __restrict__ keys,
+                                                     const odgs_status* __restrict__ status, uint2* __restrict__ ranges) {
+  const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t n = (uint32_t)status->n_pairs_stored;
+  if (j >= n) return;
+  const uint32_t k = keys[j];
+  if (j == 0 || keys[j - 1] != k) ranges[k].x = j;
+  if (j + 1 == n || keys[j + 1] != k) ranges[k].y = j + 1;
+}
+
+__global__ void status_reset_kernel(odgs_status* st) {
+  if (threadIdx.x == 0) {
+    st->flags = 0;
+    st->n_pairs_stored = 0;
+    st->n_pairs = 0;
+    st->n_visible = 0;
+    st->reserved2 = 0;
+  }
+}
+
+hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, bool identity_vals,
+                      const uint32_t* n_dev, uint32_t n_host, int bits, int nblocks, uint32_t* hist,
+                      uint32_t* digit_tot, hipStream_t st) {
+  uint32_t* kb[2] = {k0, k1};
+  uint32_t* vb[2] = {v0, v1};
+  int cur = 0;
+  for (int shift = 0; shift < bits; shift += 8) {
+    const uint32_t* vin = (shift == 0 && identity_vals) ? nullptr : vb[cur];
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(nblocks), dim3(kSortThreads), 0, st, kb[cur], n_dev, n_host, shift,
+                       hist, nblocks);
+    hipLaunchKernelGGL(radix_digit_scan_kernel, dim3(256), dim3(256), 0, st, hist, nblocks, digit_tot);
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblocks), dim3(kSortThreads), 0, st, kb[cur], vin, kb[cur ^ 1],
+                       vb[cur ^ 1], n_dev, n_host, shift, hist, digit_tot, nblocks);
+    cur ^= 1;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int sort_passes(int bits) { return (bits + 7) / 8; }
+
+hipError_t launch_status_reset(const odgs_plan* p, void* ws, hipStream_t st) {
+  hipLaunchKernelGGL(status_reset_kernel, dim3(1), dim3(64), 0, st, ws_ptr<odgs_status>(ws, p->off_status));
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* ptr, uint32_t value, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ptr, value, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
+  odgs_status* status = ws_ptr<odgs_status>(ws, p->off_status);
+  const int64_t items = p->items;
+  uint32_t* hist = ws_ptr<uint32_t>(ws, p->off_hist);
+  uint32_t* digit = ws_ptr<uint32_t>(ws, p->off_digit);
+  uint2* ranges = ws_ptr<uint2>(ws, p->off_ranges);
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * (int64_t)p->tile_base[p->n_views], st);
+  if (e != hipSuccess) return e;
+  if (items == 0) return hipSuccess;
+  // 1. items by radial depth (culled items carry the largest key)
+  uint32_t* dk[2] = {ws_ptr<uint32_t>(ws, p->off_dkey[0]), ws_ptr<uint32_t>(ws, p->off_dkey[1])};
+  uint32_t* di[2] = {ws_ptr<uint32_t>(ws, p->off_did[0]), ws_ptr<uint32_t>(ws, p->off_did[1])};
+  e = radix_sort(dk[0], di[0], dk[1], di[1], true, nullptr, (uint32_t)items, 32, p->item_blocks, hist, digit, st);
+  if (e != hipSuccess) return e;
+  const uint32_t* sorted_ids = di[p->depth_final];
+  // 2. pair offsets in depth order, and P
+  const int sblocks = (int)((items + kScanBlockItems - 1) / kScanBlockItems);
+  uint32_t* bsum = ws_ptr<uint32_t>(ws, p->off_blocksum);
+  uint64_t* boff = reinterpret_cast<uint64_t*>(bsum + align_up((size_t)sblocks, 64));
+  const uint32_t* count = ws_ptr<uint32_t>(ws, p->off_count);
+  hipLaunchKernelGGL(count_reduce_kernel, dim3(sblocks), dim3(256), 0, st, sorted_ids, count, items, bsum);
+  hipLaunchKernelGGL(count_top_kernel, dim3(1), dim3(256), 0, st, bsum, boff, sblocks, p->pair_capacity, status);
+  // 3. emit pairs
+  uint32_t* pk[2] = {ws_ptr<uint32_t>(ws, p->off_pkey[0]), ws_ptr<uint32_t>(ws, p->off_pkey[1])};
+  uint32_t* pv[2] = {ws_ptr<uint32_t>(ws, p->off_pval[0]), ws_ptr<uint32_t>(ws, p->off_pval[1])};
+  const ViewTable vt = make_view_table(p);
+  hipLaunchKernelGGL(emit_kernel, dim3(sblocks), dim3(256), 0, st, sorted_ids, count,
+                     ws_ptr<Rect>(ws, p->off_rect), boff, items, p->n, vt, p->s.tile, p->pair_capacity, pk[0], pv[0]);
+  // 4. stable sort of the pairs by global tile
+  const uint32_t* n_dev = reinterpret_cast<const uint32_t*>(&status->n_pairs_stored);
+  e = radix_sort(pk[0], pv[0], pk[1], pv[1], false, n_dev, (uint32_t)p->pair_capacity, p->tile_bits, p->pair_blocks,
+                 hist, digit, st);
+  if (e != hipSuccess) return e;
+  // 5. tile ranges
+  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((p->pair_capacity + 255) / 256)), dim3(256), 0, st,
+                     pk[p->pair_final], status, ranges);
+  return hipGetLastError();
+}
+
+}  // namespace odgs

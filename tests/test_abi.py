@@ -1,0 +1,77 @@
+"""The C ABI library loads, exports every entry point declared in include/odgs.h, and rejects
+bad arguments on the host before enqueuing anything (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2410_20686_amd import _odgs as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "odgs.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2410_20686_amd import build
+        build.build()
+    return B.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(odgs_[a-z_0-9]+)\s*\(", text, re.M))
+    assert {"odgs_preprocess", "odgs_bin_sort", "odgs_render_fwd", "odgs_render_bwd"} <= declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(B.EXPORTS) == declared
+
+
+def test_plan_layout(lib):
+    p = B.odgs_plan_init(12345, 3, [(1024, 512), (2048, 1024), (64, 32)], B.make_settings(tile=16), 1_000_003)
+    assert p.n_views == 3 and p.items == 3 * 12345
+    assert list(p.tile_base[:4]) == [0, 2048, 2048 + 8192, 2048 + 8192 + 8]
+    assert p.pix_base[3] == 1024 * 512 + 2048 * 1024 + 64 * 32
+    assert p.tile_bits == 14 and p.s.batch == 256
+    offs = sorted(getattr(p, n) for n in B._OFFSETS)
+    assert all(o % 256 == 0 for o in offs)
+    assert len(set(offs)) == len(offs)
+    assert B.odgs_workspace_bytes(p) == p.ws_bytes >= offs[-1]
+    assert B.odgs_status_offset(p) == p.off_status
+
+
+@pytest.mark.parametrize("kw,wh", [
+    (dict(tile=12), [(64, 32)]),
+    (dict(tile=16), [(100, 64)]),
+    (dict(tile=32, batch=32), [(64, 32)]),
+    (dict(tile=16, batch=100), [(64, 32)]),
+    (dict(tile=16), [(64, 32)] * 65),
+    (dict(tile=16, far=0.1), [(64, 32)]),
+])
+def test_plan_rejects_bad_settings(lib, kw, wh):
+    with pytest.raises(B.OdgsError):
+        B.odgs_plan_init(10, 0, wh, B.make_settings(**kw), 100)
+
+
+@pytest.mark.parametrize("n,deg,cap", [(-1, 0, 10), (10, 4, 10), (10, -1, 10), (10, 0, 1 << 31), (1 << 31, 0, 10)])
+def test_plan_rejects_bad_sizes(lib, n, deg, cap):
+    with pytest.raises(B.OdgsError):
+        B.odgs_plan_init(n, deg, [(64, 32)], B.make_settings(), cap)
+
+
+def test_entry_points_validate_on_host(lib):
+    p = B.odgs_plan_init(10, 0, [(64, 32)], B.make_settings(), 100)
+    nul = None
+    fake = ctypes.c_void_p(256 * 1024)  # never dereferenced: validation fails first
+    assert lib.odgs_preprocess(ctypes.byref(p), fake, fake, fake, fake, fake, fake, nul, p.ws_bytes, nul) == B.EINVAL
+    assert lib.odgs_bin_sort(ctypes.byref(p), fake, p.ws_bytes - 1, nul) == B.ENOSPACE
+    assert lib.odgs_render_fwd(ctypes.byref(p), fake, p.ws_bytes, nul, nul, nul) == B.EINVAL
+    misaligned = ctypes.c_void_p(256 * 1024 + 2)
+    assert lib.odgs_preprocess(ctypes.byref(p), misaligned, fake, fake, fake, fake, fake, fake, p.ws_bytes,
+                               nul) == B.EINVAL
+    assert lib.odgs_render_bwd(ctypes.byref(p), fake, fake, fake, fake, fake, fake, fake, p.ws_bytes, nul, fake,
+                               fake, fake, fake, fake, nul) == B.EINVAL
+    for code in (B.OK, B.EINVAL, B.ENOSPACE, B.EHIP):
+        assert B.odgs_strerror(code)

@@ -1,0 +1,164 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, element by element.
+
+Sizes here span many tiles and ragged tails (Gaussian counts that are not multiples of any
+block size, pair counts that are not multiples of the sort block, several views of different
+sizes) while the brute-force oracle still finishes in seconds.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2410_20686_amd import scenes
+from tests import _gpu as G
+from tests._util import settings
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_cases():
+    cases = []
+    sc, cams, st = scenes.config("cfg0")
+    cases.append(("cfg0", sc, cams, st))
+    sc1 = scenes.sphere_scene(3001, 3, seed=31)
+    cams1 = scenes.uneven_cameras(3, seed=7, sizes=((128, 64), (256, 128), (512, 256)))
+    cases.append(("sh3_uneven3", sc1, cams1, settings()))
+    sc2 = scenes.roaming_scene(4099, 3, seed=32)
+    cams2 = scenes.identity_cameras(512, 256)
+    cases.append(("roam_seam", sc2, cams2, settings(bg=(0.2, 0.1, 0.05))))
+    return cases
+
+
+CASES = _small_cases()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_records_match_oracle(case):
+    name, sc, cams, st = case
+    res = G.run_gpu(sc, cams, st, return_rast=True)
+    rec = res["rast"].records().cpu().numpy().reshape(cams.n_views, sc.n, 12)
+    rows = O.project(sc, cams, st)
+    kept = rows[..., O.F_KEPT] > 0
+    cnt = (rows[..., O.F_RECT + 1] * rows[..., O.F_RECT + 3]) * kept
+    np.testing.assert_array_equal(rec[..., 11].astype(np.int64), cnt.astype(np.int64))
+    k = kept
+    np.testing.assert_array_equal(rec[..., 7][k].view(np.uint32), rows[..., O.F_DEPTH_BITS][k].astype(np.uint32))
+    f32 = lambda x: x.astype(np.float32)
+    expect = {
+        0: f32(rows[..., O.F_U]), 1: f32(rows[..., O.F_V]),
+        2: np.float32(-0.5) * f32(rows[..., O.F_CONIC]), 3: -f32(rows[..., O.F_CONIC + 1]),
+        4: np.float32(-0.5) * f32(rows[..., O.F_CONIC + 2]), 5: f32(rows[..., O.F_OPAC]),
+        6: f32(rows[..., O.F_PMIN]), 8: f32(rows[..., O.F_RGB]), 9: f32(rows[..., O.F_RGB + 1]),
+        10: f32(rows[..., O.F_RGB + 2]),
+    }
+    for col, ref in expect.items():
+        got = rec[..., col][k]
+        want = ref[k]
+        ulp = np.abs(got.view(np.int32).astype(np.int64) - want.view(np.int32).astype(np.int64))
+        ok = (ulp <= 2) | (np.abs(got - want) <= 1e-30)
+        assert ok.all(), (name, col, np.count_nonzero(~ok), got[~ok][:3], want[~ok][:3])
+        assert np.mean(ulp == 0) > 0.999, (name, col, np.mean(ulp == 0))
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_key_list_bit_exact(case, tile):
+    name, sc, cams, st = case
+    st = dict(st, tile=tile)
+    res = G.run_gpu(sc, cams, st, return_rast=True)
+    keys, gauss = res["rast"].keys()
+    okeys, ovals = O.keys(sc, cams, st)
+    assert res["status"]["n_pairs"] == len(okeys)
+    np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint64), okeys)
+    np.testing.assert_array_equal(gauss.cpu().numpy().astype(np.uint32), ovals)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_forward_matches_oracle(case):
+    name, sc, cams, st = case
+    res = G.run_gpu(sc, cams, st)
+    ref = O.render(sc, cams, st, mode=32)
+    ok = G.strict_pixels(ref["margin"])
+    okc = np.concatenate([np.tile(ok[o:o + w * h], 3) for o, w, h in _views(cams)])
+    err = np.abs(res["rgb"] - ref["rgb"])
+    assert err[okc].max() <= G.RGB_ATOL, (name, err[okc].max())
+    assert np.abs(res["T"] - ref["T"])[ok].max() <= G.RGB_ATOL
+    assert (~ok).sum() <= max(2, 1e-4 * ok.size), (~ok).sum()
+    print(name, "max |drgb| %.3g, flagged pixels %d" % (err[okc].max(), (~ok).sum()))
+
+
+def _views(cams):
+    off = 0
+    for w, h in cams.wh:
+        yield off, int(w), int(h)
+        off += int(w) * int(h)
+
+
+def _masked_upstream(cams, margin, seed):
+    dL = scenes.upstream_gradient(cams, seed).astype(np.float64)
+    ok = G.strict_pixels(margin)
+    parts = []
+    base = 0
+    for o, w, h in _views(cams):
+        m = np.tile(ok[o:o + w * h], 3)
+        parts.append(np.where(m, dL[base:base + 3 * w * h], 0.0))
+        base += 3 * w * h
+    return np.concatenate(parts)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_backward_matches_oracle(case):
+    name, sc, cams, st = case
+    fwd = O.render(sc, cams, st, mode=32)
+    dL = _masked_upstream(cams, fwd["margin"], seed=1000)
+    res = G.run_gpu(sc, cams, st, dL=dL)
+    ref = O.backward(sc, cams, st, dL, mode=32)
+    rep = G.assert_grads_close(res["grads"], ref)
+    print(name, rep)
+
+
+def test_batched_equals_per_view():
+    """All views in one launch give the same images as one launch per view."""
+    sc = scenes.roaming_scene(5003, 3, seed=41)
+    cams = scenes.yaw_cameras(4, 256, 128, seed=41)
+    st = settings()
+    dL = scenes.upstream_gradient(cams, 1041)
+    res = G.run_gpu(sc, cams, st, dL=dL)
+    rgb_parts, grads = [], None
+    base = 0
+    for v in range(cams.n_views):
+        cv = cams.view(v)
+        w, h = int(cv.wh[0, 0]), int(cv.wh[0, 1])
+        r = G.run_gpu(sc, cv, st, dL=dL[base:base + 3 * w * h])
+        base += 3 * w * h
+        rgb_parts.append(r["rgb"])
+        grads = r["grads"] if grads is None else {k: grads[k] + r["grads"][k] for k in grads}
+    np.testing.assert_array_equal(res["rgb"], np.concatenate(rgb_parts))
+    G.assert_grads_close(res["grads"], grads, rtol=1e-4, floor=1e-6)
+
+
+def test_overflow_is_reported_and_recovered():
+    sc, cams, st = scenes.config("cfg0")
+    res = G.run_gpu(sc, cams, st, pair_capacity=1000, return_rast=True)
+    assert res["rast"].capacity > 1000
+    okeys, _ = O.keys(sc, cams, st)
+    assert res["status"]["n_pairs"] == len(okeys)
+    ref = O.render(sc, cams, st, mode=32)
+    assert np.abs(res["rgb"] - ref["rgb"]).max() < 1e-3
+
+
+def test_empty_and_fully_culled_scenes():
+    from tests._util import make_scene
+    cams = scenes.identity_cameras(64, 32)
+    st = settings(bg=(0.25, 0.5, 0.75))
+    empty = make_scene(np.zeros((0, 3)), np.zeros((0, 3)), dtype=np.float32)
+    r = G.run_gpu(empty, cams, st)
+    np.testing.assert_array_equal(r["T"], 1.0)
+    np.testing.assert_allclose(r["rgb"].reshape(3, -1)[:, 0], [0.25, 0.5, 0.75])
+    culled = make_scene([[0, 0, 0.1], [0, -3.0, 0], [0, 0, 3.0]], [0.1, 0.1, 0.1], opac=[0.5, 0.5, 0.002],
+                        dtype=np.float32)
+    dL = scenes.upstream_gradient(cams, 3)
+    r = G.run_gpu(culled, cams, st, dL=dL)
+    assert r["status"]["n_visible"] == 0 and r["status"]["n_pairs"] == 0
+    np.testing.assert_array_equal(r["T"], 1.0)
+    for g in r["grads"].values():
+        np.testing.assert_array_equal(g, 0.0)

@@ -25,6 +25,7 @@ def _proj(sc, cams, st=None):
 
 
 def _cov2(row, dil):
+    dil = float(np.float32(dil))  # settings reach the rasterizer (and the oracle) as float32
     uu, uv, vv = row[O.F_COV2:O.F_COV2 + 3]
     return np.array([[uu - dil, uv], [uv, vv - dil]])
 
