@@ -1,0 +1,219 @@
+#!/usr/bin/env python
+"""Benchmark of the gfx950 omnidirectional Gaussian rasterizer.
+
+Metric: forward+backward megapixels per second at 2048x1024 with 500k Gaussians, all views of
+one step batched into one launch per stage (one HIP graph per step), next to the same work done
+as one pipeline per view.
+
+Workload "M": 500,000 Gaussians of the roaming distribution (70% in 50 blobs, 30% uniform in the
+shell r in [2, 20], SH degree 3), 8 views of 2048x1024 ERP with camera centres uniform in a 1 m
+cube and random yaw; upstream image gradient N(0, 1).  A step = preprocess, bin + sort, forward
+compositing, reverse compositing and projection adjoint over all 8 views, gradients summed over
+views.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd megapixels/s at 2048×1024, 500k Gaussians; batched vs per-view"
+HBM_PEAK_GBS = 8000.0
+# FP32 vector issue rate without packed instructions: 256 CUs x 64 lanes x 2.4 GHz (lane-ops/s)
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+# Algorithmic FP32 lane-operations per unit of compositing work (itemised in the design doc):
+#   a test = one (pixel, list entry) evaluation of the Gaussian's exponent and footprint test;
+#   an accept = one (pixel, Gaussian) contribution.
+OPS_FWD_TEST, OPS_FWD_ACCEPT = 14, 14
+OPS_BWD_TEST, OPS_BWD_ACCEPT = 15, 50
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--n", type=int, default=500_000)
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pixels-per-view", type=int, default=1024)
+    return ap.parse_args()
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def time_graph(fn, steps, warmup):
+    """Capture fn() into one HIP graph and time `steps` replays (after `warmup` replays)."""
+    import torch
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()  # eager warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, g
+
+
+def time_stages(step, steps):
+    """Eager steps with HIP events around every entry point (all on torch's current stream, the
+    stream the kernels are launched on).  Returns mean ms per stage."""
+    import torch
+    names = ("bin", "fwd", "composite_bwd", "project_bwd")
+    fns = (step.bin, step.fwd, step.composite_bwd, step.project_bwd)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    for k in range(steps):
+        ev[k][0].record()
+        for j, f in enumerate(fns):
+            f()
+            ev[k][j + 1].record()
+    torch.cuda.synchronize()
+    return {n: sum(ev[k][j].elapsed_time(ev[k][j + 1]) for k in range(steps)) / steps for j, n in enumerate(names)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2410_20686_amd import scenes
+    from paper_2410_20686_amd import _odgs as B
+    from paper_2410_20686_amd.rasterizer import Rasterizer, TrainStep
+
+    t0 = time.time()
+    sc, cams, st = scenes.config("M", n=args.n)
+    st = dict(st, tile=args.tile, batch=args.batch)
+    wh = [tuple(int(x) for x in r) for r in cams.wh]
+    V = len(wh)
+    mp_per_step = sum(w * h for w, h in wh) / 1e6
+    dL_np = scenes.upstream_gradient(cams, 1005)
+    log("scene ready %.1fs" % (time.time() - t0))
+
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    tensors = [dev(a) for a in (sc.means, sc.scales, sc.quats, sc.opacities, sc.sh, cams.cams)]
+    dL = dev(dL_np)
+
+    # size the pair list from one binning pass, then keep it fixed (no host sync inside steps)
+    rast = Rasterizer(sc.n, sc.sh_degree, wh, st)
+    status0 = rast.bin_checked(*tensors)
+    rast._alloc(int(status0["n_pairs"] * 1.05) + 4096)
+    step = TrainStep(rast, tensors[:5], tensors[5], dL)
+    ms_batched, _graph = time_graph(step.run, args.steps, args.warmup)
+    status = rast.status()
+    if status["flags"] & B.STATUS_OVERFLOW:
+        raise RuntimeError("pair list overflowed during timing")
+    log("batched %.3f ms/step, P=%d" % (ms_batched, status["n_pairs"]))
+
+    stages = time_stages(step, max(3, min(args.steps, 10)))
+    cnt = rast.pixel_counts().to(torch.int64).sum(dim=0).cpu().numpy()
+    evals_fwd, last_total, contrib_total = int(cnt[2]), int(cnt[0]), int(cnt[1])
+    log("stages ms", stages)
+
+    per_view = None
+    if not args.no_per_view:
+        pv_steps = []
+        for v in range(V):
+            cv = cams.view(v)
+            rv = Rasterizer(sc.n, sc.sh_degree, [wh[v]], st)
+            tv = tensors[:5] + [dev(cv.cams)]
+            off = 3 * sum(w * h for w, h in wh[:v])
+            dv = dL[off:off + 3 * wh[v][0] * wh[v][1]]
+            s0 = rv.bin_checked(*tv)
+            rv._alloc(int(s0["n_pairs"] * 1.05) + 4096)
+            pv_steps.append(TrainStep(rv, tv[:5], tv[5], dv))
+        acc = tuple(torch.empty_like(x) for x in tensors[:5])
+
+        def run_per_view():
+            for k, s in enumerate(pv_steps):
+                s.run()
+                for a, g in zip(acc, s.grads):
+                    if k == 0:
+                        a.copy_(g)
+                    else:
+                        a.add_(g)
+
+        ms_pv, _g2 = time_graph(run_per_view, args.steps, args.warmup)
+        per_view = dict(ms_per_step=ms_pv, value=mp_per_step / (ms_pv / 1e3), speedup_batched=ms_pv / ms_batched)
+        log("per-view %.3f ms/step" % ms_pv)
+        del pv_steps
+
+    # roofline of the dominant kernel (reverse compositing: one kernel per odgs_composite_bwd call)
+    dom = max(stages, key=stages.get)
+    alg_ops = {
+        "fwd": OPS_FWD_TEST * evals_fwd + OPS_FWD_ACCEPT * contrib_total,
+        "composite_bwd": OPS_BWD_TEST * last_total + OPS_BWD_ACCEPT * contrib_total,
+    }
+    roof = None
+    if dom in alg_ops:
+        achieved = alg_ops[dom] / (stages[dom] / 1e3) / 1e12
+        roof = dict(bound="alu", kernel=dom, achieved=round(achieved, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Top/s",
+                    frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=None,
+                    work=dict(tests=last_total if dom == "composite_bwd" else evals_fwd, accepts=contrib_total))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        _, pix = scenes.sparse_upstream_gradient(cams, 2005, args.cpu_pixels_per_view)
+        gpix = np.random.default_rng(3005).standard_normal((len(pix), 3))
+        tc = time.time()
+        O.render(sc, cams, st, mode=32, pix=pix)
+        O.backward(sc, cams, st, gpix, mode=32, pix=pix)
+        dt = time.time() - tc
+        cpu = dict(value=round(len(pix) / 1e6 / dt, 6), unit="MP/s", cores=O.num_threads(), kind="oracle",
+                   sample="%d random pixels (%d per view) of workload M, brute-force forward + backward in FP32 "
+                          "decision mode, each call including its own per-Gaussian projection of all views; %.1f s"
+                          % (len(pix), args.cpu_pixels_per_view, dt))
+        log("cpu baseline", cpu)
+
+    value = mp_per_step / (ms_batched / 1e3)
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "MP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_batched, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "M: 500k Gaussians (roaming: 70%% in 50 blobs, 30%% shell r 2-20, SH degree 3), "
+                               "%d views 2048x1024, fwd+bwd, all views batched in one HIP graph per step" % V,
+                   "gaussians": sc.n, "views": V, "width": wh[0][0], "height": wh[0][1], "sh_degree": 3,
+                   "tile": st["tile"], "batch": rast.plan.s.batch, "pairs": status["n_pairs"]},
+        "per_view": per_view,
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

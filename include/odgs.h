@@ -90,7 +90,8 @@ typedef struct odgs_plan {
   int32_t reserved;
   /* workspace layout, byte offsets */
   size_t off_status, off_rec, off_rect, off_count, off_dkey[2], off_did[2], off_blocksum, off_pkey[2], off_pval[2],
-      off_hist, off_digit, off_ranges, off_T, off_last, off_g2d;
+      off_hist, off_digit, off_ranges, off_T, off_last, off_ncontrib, off_neval,
+      off_g2d;
   int32_t depth_final;     /* which of the two depth-sort buffers holds the sorted result */
   int32_t pair_final;      /* which of the two pair buffers holds the sorted result */
   size_t ws_bytes;
@@ -124,17 +125,33 @@ int odgs_bin_sort(const odgs_plan* plan, void* ws, size_t ws_bytes, void* stream
 /* Front-to-back compositing of every pixel of every view in one launch (Eq. gaussian2d and
  * Eq. alphablending, 3DGS constants alpha <= 0.99, alpha >= 1/255, stop below T = 1e-4).
  * out_rgb [V][3][H][W] receives C + T_final * bg; out_T [V][H][W] (may be NULL) the final
- * transmittance.  Keeps T and the last contributor per pixel in the workspace for render_bwd. */
+ * transmittance.  Keeps, per pixel, T, the list position after the last contributor and the
+ * number of contributors and the entries evaluated in the workspace (the first two for the
+ * backward). */
 int odgs_render_fwd(const odgs_plan* plan, void* ws, size_t ws_bytes, float* out_rgb, float* out_T, void* stream);
 
 /* Gradient of L = sum(dL_drgb * out_rgb) with respect to every parameter, summed over the
  * views (reverse compositing, then the adjoint of the tangent-plane projection and of the SH
  * colour; Sec. 3.2 and Appendix C).  The parameters must be those given to odgs_preprocess.
- * The five gradient arrays (same shapes as the parameters) are OVERWRITTEN. */
+ * The five gradient arrays (same shapes as the parameters) are OVERWRITTEN.
+ * Equivalent to odgs_composite_bwd followed by odgs_project_bwd. */
 int odgs_render_bwd(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
                     const float* opacities, const float* sh, const float* cams, void* ws, size_t ws_bytes,
                     const float* dL_drgb, float* d_means, float* d_scales, float* d_quats, float* d_opacities,
                     float* d_sh, void* stream);
+
+/* First backward stage: reverse compositing of every pixel of every view (Eq. alphablending
+ * differentiated), accumulating per-(Gaussian, view) gradients of the ERP position, the inverse
+ * 2D covariance, the opacity and the colour into the workspace (which odgs_bin_sort and
+ * odgs_project_bwd leave cleared).  dL_drgb has the layout of out_rgb. */
+int odgs_composite_bwd(const odgs_plan* plan, void* ws, size_t ws_bytes, const float* dL_drgb, void* stream);
+
+/* Second backward stage: adjoint of the per-(Gaussian, view) projection (Eq. omni_Jacobian and
+ * its derivative, Sigma = R S S^T R^T with the quaternion normalisation, SH colour), summed over
+ * views into the five gradient arrays (OVERWRITTEN); clears the workspace's 2D gradients. */
+int odgs_project_bwd(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
+                     const float* opacities, const float* sh, const float* cams, void* ws, size_t ws_bytes,
+                     float* d_means, float* d_scales, float* d_quats, float* d_opacities, float* d_sh, void* stream);
 
 /* Byte offset of the odgs_status record inside the workspace. */
 size_t odgs_status_offset(const odgs_plan* plan /*[host]*/);
@@ -151,6 +168,11 @@ size_t odgs_plan_size(void);
  * where the compositor's exponent is A du^2 + B du dv + C dv^2 (A = -a/2, B = -b, C = -c/2
  * for the inverse covariance [[a, b], [b, c]]); culled items have tile count 0. */
 int odgs_debug_records(const odgs_plan* plan, const void* ws, float* out, void* stream);
+
+/* Per-pixel int32 [pixels][3] of the last odgs_render_fwd: list position after the last
+ * contributor, number of contributors, and list entries evaluated (up to and including the one
+ * that ended the pixel by early termination, else the whole list). */
+int odgs_debug_pixel_counts(const odgs_plan* plan, const void* ws, int32_t* out, void* stream);
 
 /* The sorted pair list as 64-bit keys (global tile << 32 | depth bits) and Gaussian indices,
  * first min(P, cap) entries (P from the status record, read by the caller). */

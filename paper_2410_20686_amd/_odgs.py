@@ -17,8 +17,8 @@ OK, EINVAL, ENOSPACE, EHIP = 0, -1, -2, -3
 STATUS_OVERFLOW = 1
 
 EXPORTS = ("odgs_plan_init", "odgs_workspace_bytes", "odgs_preprocess", "odgs_bin_sort", "odgs_render_fwd",
-           "odgs_render_bwd", "odgs_status_offset", "odgs_strerror", "odgs_plan_size", "odgs_debug_records",
-           "odgs_debug_keys")
+           "odgs_render_bwd", "odgs_composite_bwd", "odgs_project_bwd", "odgs_status_offset", "odgs_strerror",
+           "odgs_plan_size", "odgs_debug_records", "odgs_debug_keys", "odgs_debug_pixel_counts")
 
 
 class Settings(ctypes.Structure):
@@ -34,7 +34,7 @@ class Status(ctypes.Structure):
 
 _OFFSETS = ["off_status", "off_rec", "off_rect", "off_count", "off_dkey0", "off_dkey1", "off_did0", "off_did1",
             "off_blocksum", "off_pkey0", "off_pkey1", "off_pval0", "off_pval1", "off_hist", "off_digit",
-            "off_ranges", "off_T", "off_last", "off_g2d"]
+            "off_ranges", "off_T", "off_last", "off_ncontrib", "off_neval", "off_g2d"]
 
 
 class Plan(ctypes.Structure):
@@ -75,6 +75,12 @@ def lib():
         L.odgs_render_fwd.restype = c_i32
         L.odgs_render_bwd.argtypes = [pp, P, P, P, P, P, P, P, c_sz, P, P, P, P, P, P, P]
         L.odgs_render_bwd.restype = c_i32
+        L.odgs_composite_bwd.argtypes = [pp, P, c_sz, P, P]
+        L.odgs_composite_bwd.restype = c_i32
+        L.odgs_project_bwd.argtypes = [pp, P, P, P, P, P, P, P, c_sz, P, P, P, P, P, P]
+        L.odgs_project_bwd.restype = c_i32
+        L.odgs_debug_pixel_counts.argtypes = [pp, P, P, P]
+        L.odgs_debug_pixel_counts.restype = c_i32
         L.odgs_strerror.argtypes = [c_i32]
         L.odgs_strerror.restype = ctypes.c_char_p
         L.odgs_debug_records.argtypes = [pp, P, P, P]
@@ -141,6 +147,20 @@ def odgs_render_bwd(plan, means, scales, quats, opac, sh, cams, ws, ws_bytes, dL
                     d_opac, d_sh, stream):
     _check(lib().odgs_render_bwd(ctypes.byref(plan), means, scales, quats, opac, sh, cams, ws, ws_bytes, dL, d_means,
                                  d_scales, d_quats, d_opac, d_sh, stream), "odgs_render_bwd")
+
+
+def odgs_composite_bwd(plan, ws, ws_bytes, dL, stream):
+    _check(lib().odgs_composite_bwd(ctypes.byref(plan), ws, ws_bytes, dL, stream), "odgs_composite_bwd")
+
+
+def odgs_project_bwd(plan, means, scales, quats, opac, sh, cams, ws, ws_bytes, d_means, d_scales, d_quats, d_opac,
+                     d_sh, stream):
+    _check(lib().odgs_project_bwd(ctypes.byref(plan), means, scales, quats, opac, sh, cams, ws, ws_bytes, d_means,
+                                  d_scales, d_quats, d_opac, d_sh, stream), "odgs_project_bwd")
+
+
+def odgs_debug_pixel_counts(plan, ws, out, stream):
+    _check(lib().odgs_debug_pixel_counts(ctypes.byref(plan), ws, out, stream), "odgs_debug_pixel_counts")
 
 
 def odgs_debug_records(plan, ws, out, stream):

@@ -114,6 +114,8 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   plan->off_ranges = take((size_t)tiles * 8);
   plan->off_T = take((size_t)pixels * 4);
   plan->off_last = take((size_t)pixels * 4);
+  plan->off_ncontrib = take((size_t)pixels * 4);
+  plan->off_neval = take((size_t)pixels * 4);
   plan->off_g2d = take((size_t)9 * I * 4);
   plan->ws_bytes = off;
   return ODGS_OK;
@@ -149,6 +151,29 @@ int odgs_render_fwd(const odgs_plan* plan, void* ws, size_t ws_bytes, float* out
   return hip_status(launch_render_fwd(plan, ws, out_rgb, out_T, static_cast<hipStream_t>(stream)));
 }
 
+int odgs_composite_bwd(const odgs_plan* plan, void* ws, size_t ws_bytes, const float* dL_drgb, void* stream) {
+  const int rc = check_ws(plan, ws, ws_bytes);
+  if (rc != ODGS_OK) return rc;
+  if (!dL_drgb || !aligned(dL_drgb, 4)) return ODGS_EINVAL;
+  return hip_status(launch_render_bwd(plan, ws, dL_drgb, static_cast<hipStream_t>(stream)));
+}
+
+int odgs_project_bwd(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
+                     const float* opacities, const float* sh, const float* cams, void* ws, size_t ws_bytes,
+                     float* d_means, float* d_scales, float* d_quats, float* d_opacities, float* d_sh, void* stream) {
+  int rc = check_ws(plan, ws, ws_bytes);
+  if (rc != ODGS_OK) return rc;
+  rc = check_params(plan, means, scales, quats, opacities, sh, cams);
+  if (rc != ODGS_OK) return rc;
+  if (plan->n > 0) {
+    float* outs[5] = {d_means, d_scales, d_quats, d_opacities, d_sh};
+    for (float* q : outs)
+      if (!q || !aligned(q, 4)) return ODGS_EINVAL;
+  }
+  return hip_status(launch_preprocess_bwd(plan, means, scales, quats, opacities, sh, cams, ws, d_means, d_scales,
+                                          d_quats, d_opacities, d_sh, static_cast<hipStream_t>(stream)));
+}
+
 int odgs_render_bwd(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
                     const float* opacities, const float* sh, const float* cams, void* ws, size_t ws_bytes,
                     const float* dL_drgb, float* d_means, float* d_scales, float* d_quats, float* d_opacities,
@@ -158,17 +183,10 @@ int odgs_render_bwd(const odgs_plan* plan, const float* means, const float* scal
   rc = check_params(plan, means, scales, quats, opacities, sh, cams);
   if (rc != ODGS_OK) return rc;
   if (!dL_drgb || !aligned(dL_drgb, 4)) return ODGS_EINVAL;
-  if (plan->n > 0) {
-    float* outs[5] = {d_means, d_scales, d_quats, d_opacities, d_sh};
-    for (float* q : outs)
-      if (!q || !aligned(q, 4)) return ODGS_EINVAL;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_render_bwd(plan, ws, dL_drgb, st);
-  if (e == hipSuccess)
-    e = launch_preprocess_bwd(plan, means, scales, quats, opacities, sh, cams, ws, d_means, d_scales, d_quats,
-                              d_opacities, d_sh, st);
-  return hip_status(e);
+  rc = odgs_composite_bwd(plan, ws, ws_bytes, dL_drgb, stream);
+  if (rc != ODGS_OK) return rc;
+  return odgs_project_bwd(plan, means, scales, quats, opacities, sh, cams, ws, ws_bytes, d_means, d_scales, d_quats,
+                          d_opacities, d_sh, stream);
 }
 
 const char* odgs_strerror(int code) {
@@ -184,6 +202,11 @@ const char* odgs_strerror(int code) {
 int odgs_debug_records(const odgs_plan* plan, const void* ws, float* out, void* stream) {
   if (!plan || !ws || !out) return ODGS_EINVAL;
   return hip_status(launch_debug_records(plan, ws, out, static_cast<hipStream_t>(stream)));
+}
+
+int odgs_debug_pixel_counts(const odgs_plan* plan, const void* ws, int32_t* out, void* stream) {
+  if (!plan || !ws || !out) return ODGS_EINVAL;
+  return hip_status(launch_debug_pixel_counts(plan, ws, out, static_cast<hipStream_t>(stream)));
 }
 
 int odgs_debug_keys(const odgs_plan* plan, const void* ws, int64_t cap, uint64_t* keys, uint32_t* gauss,

@@ -72,11 +72,12 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st);
 hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float* out_T, hipStream_t st);
 hipError_t launch_render_bwd(const odgs_plan* p, void* ws, const float* dL_drgb, hipStream_t st);
 hipError_t launch_preprocess_bwd(const odgs_plan* p, const float* means, const float* scales, const float* quats,
-                                 const float* opac, const float* sh, const float* cams, const void* ws, float* d_means,
+                                 const float* opac, const float* sh, const float* cams, void* ws, float* d_means,
                                  float* d_scales, float* d_quats, float* d_opac, float* d_sh, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* ptr, uint32_t value, int64_t n, hipStream_t st);
 hipError_t launch_status_reset(const odgs_plan* p, void* ws, hipStream_t st);
 hipError_t launch_debug_records(const odgs_plan* p, const void* ws, float* out, hipStream_t st);
+hipError_t launch_debug_pixel_counts(const odgs_plan* p, const void* ws, int32_t* out, hipStream_t st);
 hipError_t launch_debug_keys(const odgs_plan* p, const void* ws, int64_t cap, uint64_t* keys, uint32_t* gauss,
                              hipStream_t st);
 

@@ -321,7 +321,7 @@ template <int K>
 __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     int64_t n, const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
     const float* __restrict__ opac, const float* __restrict__ sh, const float* __restrict__ cams, ViewTable vt, Params P,
-    const uint32_t* __restrict__ count, const float* __restrict__ g2d, int64_t items, float* __restrict__ d_means,
+    const uint32_t* __restrict__ count, float* __restrict__ g2d, int64_t items, float* __restrict__ d_means,
     float* __restrict__ d_scales, float* __restrict__ d_quats, float* __restrict__ d_opac, float* __restrict__ d_sh) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -356,6 +356,9 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
       any = any || g[k] != 0.0;
     }
     if (!any) continue;
+    // consumed: leave the accumulators cleared for the next reverse compositing pass
+#pragma unroll
+    for (int k = 0; k < 9; ++k) g2d[(int64_t)k * items + item] = 0.0f;
     Cam cam;
     load_cam(cams, v, cam);
     Geo G;
@@ -530,14 +533,14 @@ hipError_t launch_preprocess(const odgs_plan* p, const float* means, const float
 }
 
 hipError_t launch_preprocess_bwd(const odgs_plan* p, const float* means, const float* scales, const float* quats,
-                                 const float* opac, const float* sh, const float* cams, const void* ws, float* d_means,
+                                 const float* opac, const float* sh, const float* cams, void* ws, float* d_means,
                                  float* d_scales, float* d_quats, float* d_opac, float* d_sh, hipStream_t st) {
   if (p->n == 0) return hipSuccess;
   const ViewTable vt = make_view_table(p);
   const Params P = make_params(p);
   const unsigned grid = (unsigned)((p->n + 255) / 256);
   const uint32_t* count = ws_ptr<uint32_t>(ws, p->off_count);
-  const float* g2d = ws_ptr<float>(ws, p->off_g2d);
+  float* g2d = ws_ptr<float>(ws, p->off_g2d);
 #define ODGS_PREB(KK)                                                                                             \
   hipLaunchKernelGGL(preprocess_bwd_kernel<KK>, dim3(grid), dim3(256), 0, st, p->n, means, scales, quats, opac, sh, \
                      cams, vt, P, count, g2d, p->items, d_means, d_scales, d_quats, d_opac, d_sh)

@@ -31,7 +31,9 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(ViewTable vt, co
                                                                 const uint32_t* __restrict__ pair_items,
                                                                 const Rec* __restrict__ rec, float* __restrict__ out_rgb,
                                                                 float* __restrict__ out_T, float* __restrict__ ws_T,
-                                                                int32_t* __restrict__ ws_last, float bg0, float bg1,
+                                                                int32_t* __restrict__ ws_last,
+                                                                int32_t* __restrict__ ws_ncontrib,
+                                                                int32_t* __restrict__ ws_neval, float bg0, float bg1,
                                                                 float bg2) {
   constexpr int N = TILE * TILE;
   __shared__ float4 s0[BATCH];
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(ViewTable vt, co
   const float Wf = (float)W, half = (float)W * 0.5f;
   const uint2 rg = ranges[g];
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-  int last = 0;
+  int last = 0, ncontrib = 0, stop = 0;
   bool done = false;
   for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
     if (__syncthreads_count(done) == N) break;
@@ -75,6 +77,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(ViewTable vt, co
         const float Tn = T * (1.0f - alpha);
         if (Tn < kTStop) {
           done = true;
+          stop = (int)(base - rg.x) + k + 1;
           break;
         }
         const float w = alpha * T;
@@ -84,6 +87,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(ViewTable vt, co
         C2 = fmaf(w, c.z, C2);
         T = Tn;
         last = (int)(base - rg.x) + k + 1;
+        ++ncontrib;
       }
     }
   }
@@ -96,6 +100,8 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(ViewTable vt, co
   const int64_t gp = vt.pix_base[v] + pix;
   ws_T[gp] = T;
   ws_last[gp] = last;
+  ws_ncontrib[gp] = ncontrib;
+  ws_neval[gp] = done ? stop : (int)(rg.y - rg.x);
   if (out_T) out_T[gp] = T;
 }
 
@@ -243,9 +249,10 @@ __global__ void debug_keys_kernel(const uint32_t* __restrict__ pkey, const uint3
 
 template <int TILE, int BATCH>
 void fwd_launch(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
-                const Rec* rec, float* out_rgb, float* out_T, float* wT, int32_t* wl, hipStream_t st) {
+                const Rec* rec, float* out_rgb, float* out_T, float* wT, int32_t* wl, int32_t* wn, int32_t* we,
+                hipStream_t st) {
   hipLaunchKernelGGL((render_fwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items, rec,
-                     out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+                     out_rgb, out_T, wT, wl, wn, we, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
 }
 
 template <int TILE, int BATCH>
@@ -292,7 +299,9 @@ hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float
   const Rec* rec = ws_ptr<Rec>(ws, p->off_rec);
   float* wT = ws_ptr<float>(ws, p->off_T);
   int32_t* wl = ws_ptr<int32_t>(ws, p->off_last);
-  if (!dispatch<FwdRun>(p->s.tile, p->s.batch, p, tiles, vt, ranges, items, rec, out_rgb, out_T, wT, wl, st))
+  int32_t* wn = ws_ptr<int32_t>(ws, p->off_ncontrib);
+  int32_t* we = ws_ptr<int32_t>(ws, p->off_neval);
+  if (!dispatch<FwdRun>(p->s.tile, p->s.batch, p, tiles, vt, ranges, items, rec, out_rgb, out_T, wT, wl, wn, we, st))
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -301,8 +310,7 @@ hipError_t launch_render_bwd(const odgs_plan* p, void* ws, const float* dL_drgb,
   const ViewTable vt = make_view_table(p);
   const int tiles = p->tile_base[p->n_views];
   float* g2d = ws_ptr<float>(ws, p->off_g2d);
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(g2d), 0u, 9 * p->items, st);
-  if (e != hipSuccess || tiles == 0) return e;
+  if (tiles == 0) return hipSuccess;
   const uint2* ranges = ws_ptr<uint2>(ws, p->off_ranges);
   const uint32_t* items = ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]);
   const Rec* rec = ws_ptr<Rec>(ws, p->off_rec);
@@ -317,6 +325,23 @@ hipError_t launch_debug_records(const odgs_plan* p, const void* ws, float* out, 
   if (p->items == 0) return hipSuccess;
   hipLaunchKernelGGL(debug_records_kernel, dim3((unsigned)((p->items + 255) / 256)), dim3(256), 0, st,
                      ws_ptr<Rec>(ws, p->off_rec), p->items, out);
+  return hipGetLastError();
+}
+
+__global__ void debug_pixel_counts_kernel(const int32_t* __restrict__ last, const int32_t* __restrict__ nc,
+                                          const int32_t* __restrict__ ne, int64_t pixels, int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pixels) return;
+  out[3 * i] = last[i];
+  out[3 * i + 1] = nc[i];
+  out[3 * i + 2] = ne[i];
+}
+
+hipError_t launch_debug_pixel_counts(const odgs_plan* p, const void* ws, int32_t* out, hipStream_t st) {
+  const int64_t pixels = p->pix_base[p->n_views];
+  hipLaunchKernelGGL(debug_pixel_counts_kernel, dim3((unsigned)((pixels + 255) / 256)), dim3(256), 0, st,
+                     ws_ptr<int32_t>(ws, p->off_last), ws_ptr<int32_t>(ws, p->off_ncontrib),
+                     ws_ptr<int32_t>(ws, p->off_neval), pixels, out);
   return hipGetLastError();
 }
 

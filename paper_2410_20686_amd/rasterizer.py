@@ -126,6 +126,70 @@ class Rasterizer:
         return keys[:m], gauss[:m]
 
 
+    def composite_bwd(self, dL_drgb):
+        B.odgs_composite_bwd(self.plan, _ptr(self.ws), self.ws_bytes, _ptr(dL_drgb), _stream())
+
+    def project_bwd(self, means, scales, quats, opac, sh, cams, grads):
+        B.odgs_project_bwd(self.plan, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opac), _ptr(sh), _ptr(cams),
+                           _ptr(self.ws), self.ws_bytes, *[_ptr(g) for g in grads], _stream())
+
+    def pixel_counts(self) -> torch.Tensor:
+        """[pixels, 3] int32: list position after the last contributor, contributors, entries
+        evaluated, of the last forward."""
+        out = torch.empty((self.pixels, 3), dtype=torch.int32, device=self.device)
+        B.odgs_debug_pixel_counts(self.plan, _ptr(self.ws), _ptr(out), _stream())
+        return out
+
+
+class TrainStep:
+    """One forward + backward step over every view with preallocated outputs, so that it can be
+    captured once into a HIP graph and replayed.  Parameters, camera poses and the upstream
+    gradient are read from the given device tensors at every replay (update them in place)."""
+
+    def __init__(self, rast: Rasterizer, params, cams: torch.Tensor, dL_drgb: torch.Tensor):
+        self.rast = rast
+        self.params = tuple(params)
+        self.cams = cams
+        self.dL = dL_drgb
+        self.rgb = torch.empty(3 * rast.pixels, dtype=torch.float32, device=rast.device)
+        self.grads = tuple(torch.empty_like(x) for x in self.params)
+        self.graph = None
+
+    def bin(self):
+        self.rast.bin(*self.params, self.cams)
+
+    def fwd(self):
+        self.rast.render_fwd(self.rgb, None, want_T=False)
+
+    def composite_bwd(self):
+        self.rast.composite_bwd(self.dL)
+
+    def project_bwd(self):
+        self.rast.project_bwd(*self.params, self.cams, self.grads)
+
+    def run(self):
+        self.bin()
+        self.fwd()
+        self.composite_bwd()
+        self.project_bwd()
+
+    def capture(self):
+        """Record run() into a HIP graph (after one eager run on the capture stream)."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.run()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.run()
+        return self.graph
+
+    def replay(self):
+        self.graph.replay()
+
+
 class _RenderFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, scales, quats, opac, sh, cams, rast):
