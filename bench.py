@@ -139,7 +139,7 @@ def main():
 
     stages = time_stages(step, max(3, min(args.steps, 10)))
     cnt = rast.pixel_counts().to(torch.int64).sum(dim=0).cpu().numpy()
-    evals_fwd, last_total, contrib_total = int(cnt[2]), int(cnt[0]), int(cnt[1])
+    contrib_total, evals_fwd, evals_bwd = int(cnt[1]), int(cnt[2]), int(cnt[3])
     log("stages ms", stages)
 
     per_view = None
@@ -174,14 +174,14 @@ def main():
     dom = max(stages, key=stages.get)
     alg_ops = {
         "fwd": OPS_FWD_TEST * evals_fwd + OPS_FWD_ACCEPT * contrib_total,
-        "composite_bwd": OPS_BWD_TEST * last_total + OPS_BWD_ACCEPT * contrib_total,
+        "composite_bwd": OPS_BWD_TEST * evals_bwd + OPS_BWD_ACCEPT * contrib_total,
     }
     roof = None
     if dom in alg_ops:
         achieved = alg_ops[dom] / (stages[dom] / 1e3) / 1e12
         roof = dict(bound="alu", kernel=dom, achieved=round(achieved, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Top/s",
                     frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=None,
-                    work=dict(tests=last_total if dom == "composite_bwd" else evals_fwd, accepts=contrib_total))
+                    work=dict(tests=evals_bwd if dom == "composite_bwd" else evals_fwd, accepts=contrib_total))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -89,9 +89,9 @@ typedef struct odgs_plan {
   int32_t pair_blocks;     /* sort blocks over pair_capacity */
   int32_t reserved;
   /* workspace layout, byte offsets */
-  size_t off_status, off_rec, off_rect, off_count, off_dkey[2], off_did[2], off_blocksum, off_pkey[2], off_pval[2],
+  size_t off_status, off_rec, off_rect, off_count, off_depth, off_dkey[2], off_did[2], off_blocksum, off_pkey[2], off_pval[2],
       off_hist, off_digit, off_ranges, off_T, off_last, off_ncontrib, off_neval,
-      off_g2d;
+      off_lasteval, off_g2d;
   int32_t depth_final;     /* which of the two depth-sort buffers holds the sorted result */
   int32_t pair_final;      /* which of the two pair buffers holds the sorted result */
   size_t ws_bytes;
@@ -125,9 +125,8 @@ int odgs_bin_sort(const odgs_plan* plan, void* ws, size_t ws_bytes, void* stream
 /* Front-to-back compositing of every pixel of every view in one launch (Eq. gaussian2d and
  * Eq. alphablending, 3DGS constants alpha <= 0.99, alpha >= 1/255, stop below T = 1e-4).
  * out_rgb [V][3][H][W] receives C + T_final * bg; out_T [V][H][W] (may be NULL) the final
- * transmittance.  Keeps, per pixel, T, the list position after the last contributor and the
- * number of contributors and the entries evaluated in the workspace (the first two for the
- * backward). */
+ * transmittance.  Keeps per-pixel T, the list position after the last contributor (both read by
+ * the backward) and the work counters of odgs_debug_pixel_counts in the workspace. */
 int odgs_render_fwd(const odgs_plan* plan, void* ws, size_t ws_bytes, float* out_rgb, float* out_T, void* stream);
 
 /* Gradient of L = sum(dL_drgb * out_rgb) with respect to every parameter, summed over the
@@ -169,9 +168,11 @@ size_t odgs_plan_size(void);
  * for the inverse covariance [[a, b], [b, c]]); culled items have tile count 0. */
 int odgs_debug_records(const odgs_plan* plan, const void* ws, float* out, void* stream);
 
-/* Per-pixel int32 [pixels][3] of the last odgs_render_fwd: list position after the last
- * contributor, number of contributors, and list entries evaluated (up to and including the one
- * that ended the pixel by early termination, else the whole list). */
+/* Per-pixel int32 [pixels][4] of the last odgs_render_fwd: list position after the last
+ * contributor; number of contributors; list entries evaluated (up to and including the one that
+ * ended the pixel by early termination, else the whole list); and entries evaluated up to the
+ * last contributor.  The last two count only entries whose padded footprint rectangle reaches
+ * the pixel's 8x8 quadrant (the others are skipped for the whole wavefront). */
 int odgs_debug_pixel_counts(const odgs_plan* plan, const void* ws, int32_t* out, void* stream);
 
 /* The sorted pair list as 64-bit keys (global tile << 32 | depth bits) and Gaussian indices,

@@ -99,6 +99,7 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   plan->off_rec = take((size_t)I * sizeof(Rec));
   plan->off_rect = take((size_t)I * sizeof(Rect));
   plan->off_count = take((size_t)I * 4);
+  plan->off_depth = take((size_t)I * 4);
   plan->off_dkey[0] = take((size_t)I * 4);
   plan->off_dkey[1] = take((size_t)I * 4);
   plan->off_did[0] = take((size_t)I * 4);
@@ -116,6 +117,7 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   plan->off_last = take((size_t)pixels * 4);
   plan->off_ncontrib = take((size_t)pixels * 4);
   plan->off_neval = take((size_t)pixels * 4);
+  plan->off_lasteval = take((size_t)pixels * 4);
   plan->off_g2d = take((size_t)9 * I * 4);
   plan->ws_bytes = off;
   return ODGS_OK;

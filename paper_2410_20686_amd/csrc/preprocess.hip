@@ -195,6 +195,13 @@ __device__ inline bool geometry(const double m[3], const Cam& cam, const Cov3& c
   return true;
 }
 
+// float(x) rounded towards +infinity, so a padded extent never shrinks when stored as float.
+__device__ inline float round_up_f32(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = nextafterf(f, INFINITY);
+  return f;
+}
+
 __device__ inline void view_dir(const double m[3], const Cam& cam, double d[3], double& dist) {
   const double w0 = m[0] - cam.c[0], w1 = m[1] - cam.c[1], w2 = m[2] - cam.c[2];
   dist = sqrt((w0 * w0 + w1 * w1) + w2 * w2);
@@ -210,7 +217,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
                                                          const float* __restrict__ cams, ViewTable vt, Params P,
                                                          Rec* __restrict__ rec, Rect* __restrict__ rect,
                                                          uint32_t* __restrict__ count, uint32_t* __restrict__ dkey,
-                                                         odgs_status* __restrict__ status) {
+                                                         float* __restrict__ depth_out, odgs_status* __restrict__ status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < n;
   const int64_t ii = live ? i : 0;
@@ -286,8 +293,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
           rr = Rect{(uint16_t)col0, (uint16_t)ncols, (uint16_t)row0, (uint16_t)nrows};
           cnt = (uint32_t)ncols * (uint32_t)nrows;
           out.r0 = make_float4((float)g.u, (float)g.v, -0.5f * (float)ca, -(float)cb);
-          out.r1 = make_float4(-0.5f * (float)cc, o, (float)p_min, depth);
-          out.r2 = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(cnt));
+          out.r1 = make_float4(-0.5f * (float)cc, o, (float)p_min, round_up_f32(eu));
+          out.r2 = make_float4(rgb[0], rgb[1], rgb[2], round_up_f32(ev));
         }
       }
     }
@@ -295,10 +302,11 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
       const int64_t item = (int64_t)v * n + i;
       if (!kept) {
         out.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        out.r1 = make_float4(0.f, 0.f, 0.f, depth);
+        out.r1 = make_float4(0.f, 0.f, 0.f, 0.f);
         out.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
       }
       rec[item] = out;
+      depth_out[item] = depth;
       rect[item] = rr;
       count[item] = cnt;
       dkey[item] = kept ? __float_as_uint(depth) : 0xffffffffu;
@@ -518,10 +526,11 @@ hipError_t launch_preprocess(const odgs_plan* p, const float* means, const float
   Rect* rect = ws_ptr<Rect>(ws, p->off_rect);
   uint32_t* count = ws_ptr<uint32_t>(ws, p->off_count);
   uint32_t* dkey = ws_ptr<uint32_t>(ws, p->off_dkey[0]);
+  float* depth = ws_ptr<float>(ws, p->off_depth);
   odgs_status* status = ws_ptr<odgs_status>(ws, p->off_status);
 #define ODGS_PRE(KK)                                                                                               \
   hipLaunchKernelGGL(preprocess_kernel<KK>, dim3(grid), dim3(256), 0, st, p->n, means, scales, quats, opac, sh, cams, \
-                     vt, P, rec, rect, count, dkey, status)
+                     vt, P, rec, rect, count, dkey, depth, status)
   switch (p->sh_degree) {
     case 0: ODGS_PRE(1); break;
     case 1: ODGS_PRE(4); break;

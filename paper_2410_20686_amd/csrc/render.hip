@@ -1,15 +1,19 @@
 // Compositing kernels of the omnidirectional rasterizer, gfx950.
 //
-// Forward: one workgroup per (view, tile), one thread per pixel.  The tile's depth-ordered list
-// is staged through LDS in batches of one record per thread, and every pixel alpha-composites
-// front to back (Eq. gaussian2d, Eq. alphablending) until its transmittance would drop below
-// 1e-4; the workgroup stops loading batches once every pixel has finished.
-// Backward: the same workgroups walk their lists back to front from the last contributor,
-// recover T by division, and produce per-pixel gradients of the 2D quantities; these are summed
-// across each wavefront with cross-lane reductions, across the workgroup's wavefronts in LDS,
-// and only then added to global memory with one float atomic per (Gaussian, tile, quantity).
-// All views of a step are covered by one launch: the grid spans the global tile ids of every
-// view (views may differ in size).
+// One workgroup per (view, tile); one thread per pixel; every 64-wide wavefront owns an 8x8
+// pixel quadrant of the tile.  The tile's depth-ordered list is staged through LDS in batches;
+// while staging, each record gets a bit mask of the quadrants its padded footprint rectangle
+// overlaps, so a wavefront skips, with a uniform branch, every Gaussian that cannot reach any of
+// its 64 pixels.  (The mask is conservative: a skipped Gaussian has alpha < 1/255 at every pixel
+// of the quadrant, so results are identical to testing every pixel.)
+//
+// Forward: front-to-back compositing (Eq. gaussian2d, Eq. alphablending) until a pixel's
+// transmittance would drop below 1e-4; the workgroup stops loading batches once every pixel is
+// done.  Backward: back to front from the last contributor, transmittance recovered by
+// multiplying with 1/(1 - alpha); per-pixel gradients of the 2D quantities are summed over the
+// wavefront with DPP row operations, over the workgroup's wavefronts with LDS float atomics,
+// and reach global memory with one float atomic per (Gaussian, tile, quantity).
+// One launch covers all views of a step: the grid spans the global tile ids of every view.
 #include <utility>
 
 #include "common.h"
@@ -20,37 +24,81 @@ namespace {
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTStop = 1e-4f;
 
-__device__ inline float wave_sum(float x) {
+template <int CTRL, int ROW_MASK>
+__device__ inline float dpp_shift_add(float v) {
+  const int s = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
+  return v + __int_as_float(s);
+}
+
+// Wavefront sum by DPP; the total lands in lane 63.
+__device__ inline float wave_sum_to_lane63(float v) {
+  v = dpp_shift_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]: pairs
+  v = dpp_shift_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]: quads
+  v = dpp_shift_add<0x141, 0xF>(v);  // row_half_mirror: 8 lanes
+  v = dpp_shift_add<0x140, 0xF>(v);  // row_mirror: 16-lane rows
+  v = dpp_shift_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_shift_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+__device__ inline float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
+
+// Pixel of a thread inside a TILE x TILE tile: wavefront w owns quadrant w (row-major over the
+// TILE/8 x TILE/8 quadrants), lane l the pixel (l % 8, l / 8) inside it.
+template <int TILE>
+__device__ inline void local_pixel(int t, int& lx, int& ly) {
+  constexpr int QPR = TILE / 8;
+  const int w = t >> 6, l = t & 63;
+  lx = (w % QPR) * 8 + (l & 7);
+  ly = (w / QPR) * 8 + (l >> 3);
+}
+
+// Quadrants of a tile whose pixel centres can lie inside the rectangle u +- eu, v +- ev
+// (u wraps around the seam).
+template <int TILE>
+__device__ inline uint32_t quadrant_mask(float u, float v, float eu, float ev, int tx0, int ty0, float Wf,
+                                         float half) {
+  constexpr int QPR = TILE / 8;
+  uint32_t mask = 0;
+  const bool all_cols = eu + 3.5f >= half;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-  return x;
+  for (int q = 0; q < QPR * QPR; ++q) {
+    const float qcx = (float)(tx0 + (q % QPR) * 8 + 4);
+    const float qcy = (float)(ty0 + (q / QPR) * 8 + 4);
+    float du = qcx - u;
+    if (du >= half) du -= Wf;
+    else if (du < -half) du += Wf;
+    const bool hit = fabsf(v - qcy) <= ev + 3.5f && (all_cols || fabsf(du) <= eu + 3.5f);
+    mask |= hit ? (1u << q) : 0u;
+  }
+  return mask;
 }
 
 template <int TILE, int BATCH>
-__global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(ViewTable vt, const uint2* __restrict__ ranges,
-                                                                const uint32_t* __restrict__ pair_items,
-                                                                const Rec* __restrict__ rec, float* __restrict__ out_rgb,
-                                                                float* __restrict__ out_T, float* __restrict__ ws_T,
-                                                                int32_t* __restrict__ ws_last,
-                                                                int32_t* __restrict__ ws_ncontrib,
-                                                                int32_t* __restrict__ ws_neval, float bg0, float bg1,
-                                                                float bg2) {
+__global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
+    ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
+    float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
+    int32_t* __restrict__ ws_ncontrib, int32_t* __restrict__ ws_neval, int32_t* __restrict__ ws_lasteval, float bg0,
+    float bg1, float bg2) {
   constexpr int N = TILE * TILE;
   __shared__ float4 s0[BATCH];
-  __shared__ float4 s1[BATCH];
+  __shared__ float4 s1[BATCH];  // (C, opacity, p_min, quadrant mask bits)
   __shared__ float4 s2[BATCH];
   const int g = blockIdx.x;
   const int v = view_of_tile(vt, g);
   const int W = vt.W[v], H = vt.H[v];
   const int ntx = W / TILE;
   const int lt = g - vt.tile_base[v];
-  const int x = (lt % ntx) * TILE + (int)(threadIdx.x % TILE);
-  const int y = (lt / ntx) * TILE + (int)(threadIdx.x / TILE);
+  const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+  int lx, ly;
+  local_pixel<TILE>(threadIdx.x, lx, ly);
+  const int x = tx0 + lx, y = ty0 + ly;
+  const uint32_t qbit = 1u << (threadIdx.x >> 6);
   const float px = (float)x + 0.5f, py = (float)y + 0.5f;
   const float Wf = (float)W, half = (float)W * 0.5f;
   const uint2 rg = ranges[g];
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-  int last = 0, ncontrib = 0, stop = 0;
+  int last = 0, ncontrib = 0, nev = 0, lastev = 0;
   bool done = false;
   for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
     if (__syncthreads_count(done) == N) break;
@@ -58,14 +106,17 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(ViewTable vt, co
     for (int t = threadIdx.x; t < cnt; t += N) {
       const Rec r = rec[pair_items[base + t]];
       s0[t] = r.r0;
-      s1[t] = r.r1;
+      const uint32_t m = quadrant_mask<TILE>(r.r0.x, r.r0.y, r.r1.w, r.r2.w, tx0, ty0, Wf, half);
+      s1[t] = make_float4(r.r1.x, r.r1.y, r.r1.z, __uint_as_float(m));
       s2[t] = r.r2;
     }
     __syncthreads();
     if (!done) {
       for (int k = 0; k < cnt; ++k) {
-        const float4 a = s0[k];
         const float4 b = s1[k];
+        if (!(__float_as_uint(b.w) & qbit)) continue;  // uniform across the wavefront
+        const float4 a = s0[k];
+        ++nev;
         float du = px - a.x;
         if (du >= half) du = du - Wf;
         else if (du < -half) du = du + Wf;
@@ -77,7 +128,6 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(ViewTable vt, co
         const float Tn = T * (1.0f - alpha);
         if (Tn < kTStop) {
           done = true;
-          stop = (int)(base - rg.x) + k + 1;
           break;
         }
         const float w = alpha * T;
@@ -87,6 +137,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(ViewTable vt, co
         C2 = fmaf(w, c.z, C2);
         T = Tn;
         last = (int)(base - rg.x) + k + 1;
+        lastev = nev;
         ++ncontrib;
       }
     }
@@ -101,7 +152,8 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(ViewTable vt, co
   ws_T[gp] = T;
   ws_last[gp] = last;
   ws_ncontrib[gp] = ncontrib;
-  ws_neval[gp] = done ? stop : (int)(rg.y - rg.x);
+  ws_neval[gp] = nev;
+  ws_lasteval[gp] = lastev;
   if (out_T) out_T[gp] = T;
 }
 
@@ -126,9 +178,12 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   const int W = vt.W[v], H = vt.H[v];
   const int ntx = W / TILE;
   const int lt = g - vt.tile_base[v];
-  const int x = (lt % ntx) * TILE + (int)(threadIdx.x % TILE);
-  const int y = (lt / ntx) * TILE + (int)(threadIdx.x / TILE);
+  const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+  int lx, ly;
+  local_pixel<TILE>(threadIdx.x, lx, ly);
+  const int x = tx0 + lx, y = ty0 + ly;
   const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t qbit = 1u << (threadIdx.x >> 6);
   const float px = (float)x + 0.5f, py = (float)y + 0.5f;
   const float Wf = (float)W, half = (float)W * 0.5f;
   const uint2 rg = ranges[g];
@@ -140,9 +195,13 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   float T = ws_T[gp];
   const int last = ws_last[gp];
   float S0 = T * bg0, S1 = T * bg1, S2 = T * bg2;  // colour of everything behind, incl. background
+  // largest `last` of the wavefront (uniform) and of the workgroup
+  int wmax = last;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
   if (threadIdx.x == 0) smax = 0;
   __syncthreads();
-  atomicMax(&smax, last);
+  if (lane == 0) atomicMax(&smax, wmax);
   __syncthreads();
   const int end_all = smax;
   for (int end = end_all; end > 0; end -= BATCH) {
@@ -151,14 +210,19 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       const uint32_t item = pair_items[rg.x + end - 1 - t];
       const Rec r = rec[item];
       s0[t] = r.r0;
-      s1[t] = r.r1;
+      const uint32_t m = quadrant_mask<TILE>(r.r0.x, r.r0.y, r.r1.w, r.r2.w, tx0, ty0, Wf, half);
+      s1[t] = make_float4(r.r1.x, r.r1.y, r.r1.z, __uint_as_float(m));
       s2[t] = r.r2;
       sid[t] = item;
 #pragma unroll
       for (int q = 0; q < 9; ++q) acc[q][t] = 0.0f;
     }
     __syncthreads();
-    for (int k = 0; k < cnt; ++k) {
+    // entries at list positions >= wmax cannot touch this wavefront
+    const int k0 = max(0, end - wmax);
+    for (int k = k0; k < cnt; ++k) {
+      const float4 b = s1[k];
+      if (!(__float_as_uint(b.w) & qbit)) continue;  // uniform across the wavefront
       const int jrel = end - 1 - k;
       float gq[9];
 #pragma unroll
@@ -166,7 +230,6 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       bool contrib = false;
       if (jrel < last) {
         const float4 a = s0[k];
-        const float4 b = s1[k];
         float du = px - a.x;
         if (du >= half) du = du - Wf;
         else if (du < -half) du = du + Wf;
@@ -178,24 +241,23 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
           float alpha = b.y * G;
           const bool clamped = alpha > kAlphaMax;
           if (clamped) alpha = kAlphaMax;
-          const float om = 1.0f - alpha;
-          T = T / om;  // transmittance in front of this Gaussian
+          const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
+          T = T * inv_om;  // transmittance in front of this Gaussian
           const float w = alpha * T;
           const float4 c = s2[k];
           gq[6] = w * dl0;
           gq[7] = w * dl1;
           gq[8] = w * dl2;
-          const float inv_om = 1.0f / om;
-          const float dL_da =
-              dl0 * (c.x * T - S0 * inv_om) + dl1 * (c.y * T - S1 * inv_om) + dl2 * (c.z * T - S2 * inv_om);
+          const float dL_da = dl0 * fmaf(c.x, T, -S0 * inv_om) + dl1 * fmaf(c.y, T, -S1 * inv_om) +
+                              dl2 * fmaf(c.z, T, -S2 * inv_om);
           S0 = fmaf(c.x, w, S0);
           S1 = fmaf(c.y, w, S1);
           S2 = fmaf(c.z, w, S2);
           if (!clamped) {
             const float dpow = dL_da * alpha;
             const float ca = -2.0f * a.z, cb = -a.w, cc = -2.0f * b.x;
-            gq[0] = dpow * (ca * du + cb * dv);
-            gq[1] = dpow * (cb * du + cc * dv);
+            gq[0] = dpow * fmaf(ca, du, cb * dv);
+            gq[1] = dpow * fmaf(cb, du, cc * dv);
             gq[2] = -0.5f * dpow * (du * du);
             gq[3] = -dpow * (du * dv);
             gq[4] = -0.5f * dpow * (dv * dv);
@@ -205,7 +267,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       }
       if (__ballot(contrib) != 0ull) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) gq[q] = wave_sum(gq[q]);
+        for (int q = 0; q < 9; ++q) gq[q] = lane63(wave_sum_to_lane63(gq[q]));
         if (lane == 0) {
 #pragma unroll
           for (int q = 0; q < 9; ++q) atomicAdd(&acc[q][k], gq[q]);
@@ -225,42 +287,58 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   }
 }
 
-__global__ void debug_records_kernel(const Rec* __restrict__ rec, int64_t items, float* __restrict__ out) {
+__global__ void debug_records_kernel(const Rec* __restrict__ rec, const float* __restrict__ depth,
+                                     const uint32_t* __restrict__ count, int64_t items, float* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= items) return;
   const Rec r = rec[i];
   float* o = out + i * 12;
   o[0] = r.r0.x; o[1] = r.r0.y; o[2] = r.r0.z; o[3] = r.r0.w;
-  o[4] = r.r1.x; o[5] = r.r1.y; o[6] = r.r1.z; o[7] = r.r1.w;
+  o[4] = r.r1.x; o[5] = r.r1.y; o[6] = r.r1.z; o[7] = depth[i];
   o[8] = r.r2.x; o[9] = r.r2.y; o[10] = r.r2.z;
-  o[11] = (float)__float_as_uint(r.r2.w);
+  o[11] = (float)count[i];
 }
 
 __global__ void debug_keys_kernel(const uint32_t* __restrict__ pkey, const uint32_t* __restrict__ pval,
-                                  const Rec* __restrict__ rec, const odgs_status* __restrict__ status, int64_t cap,
+                                  const float* __restrict__ depth, const odgs_status* __restrict__ status, int64_t cap,
                                   int64_t n, uint64_t* __restrict__ keys, uint32_t* __restrict__ gauss) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t m = min((int64_t)status->n_pairs_stored, cap);
   if (j >= m) return;
   const uint32_t item = pval[j];
-  keys[j] = ((uint64_t)pkey[j] << 32) | (uint64_t)__float_as_uint(rec[item].r1.w);
+  keys[j] = ((uint64_t)pkey[j] << 32) | (uint64_t)__float_as_uint(depth[item]);
   gauss[j] = (uint32_t)(item % n);
 }
 
-template <int TILE, int BATCH>
-void fwd_launch(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
-                const Rec* rec, float* out_rgb, float* out_T, float* wT, int32_t* wl, int32_t* wn, int32_t* we,
-                hipStream_t st) {
-  hipLaunchKernelGGL((render_fwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items, rec,
-                     out_rgb, out_T, wT, wl, wn, we, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+__global__ void debug_pixel_counts_kernel(const int32_t* __restrict__ last, const int32_t* __restrict__ nc,
+                                          const int32_t* __restrict__ ne, const int32_t* __restrict__ le,
+                                          int64_t pixels, int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pixels) return;
+  out[4 * i] = last[i];
+  out[4 * i + 1] = nc[i];
+  out[4 * i + 2] = ne[i];
+  out[4 * i + 3] = le[i];
 }
 
 template <int TILE, int BATCH>
-void bwd_launch(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
-                const Rec* rec, const float* wT, const int32_t* wl, const float* dL, float* g2d, hipStream_t st) {
-  hipLaunchKernelGGL((render_bwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items, rec,
-                     wT, wl, dL, g2d, p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
-}
+struct FwdRun {
+  static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
+                  const Rec* rec, float* out_rgb, float* out_T, float* wT, int32_t* wl, int32_t* wn, int32_t* we,
+                  int32_t* wle, hipStream_t st) {
+    hipLaunchKernelGGL((render_fwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items,
+                       rec, out_rgb, out_T, wT, wl, wn, we, wle, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+  }
+};
+
+template <int TILE, int BATCH>
+struct BwdRun {
+  static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
+                  const Rec* rec, const float* wT, const int32_t* wl, const float* dL, float* g2d, hipStream_t st) {
+    hipLaunchKernelGGL((render_bwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items,
+                       rec, wT, wl, dL, g2d, p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+  }
+};
 
 // Dispatch over the supported (tile, batch) pairs; returns false for an unsupported pair.
 template <template <int, int> class F, typename... Args>
@@ -277,17 +355,6 @@ bool dispatch(int tile, int batch, Args&&... args) {
   return false;
 }
 
-template <int TILE, int BATCH>
-struct FwdRun {
-  template <typename... A>
-  static void run(A&&... a) { fwd_launch<TILE, BATCH>(std::forward<A>(a)...); }
-};
-template <int TILE, int BATCH>
-struct BwdRun {
-  template <typename... A>
-  static void run(A&&... a) { bwd_launch<TILE, BATCH>(std::forward<A>(a)...); }
-};
-
 }  // namespace
 
 hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float* out_T, hipStream_t st) {
@@ -301,7 +368,9 @@ hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float
   int32_t* wl = ws_ptr<int32_t>(ws, p->off_last);
   int32_t* wn = ws_ptr<int32_t>(ws, p->off_ncontrib);
   int32_t* we = ws_ptr<int32_t>(ws, p->off_neval);
-  if (!dispatch<FwdRun>(p->s.tile, p->s.batch, p, tiles, vt, ranges, items, rec, out_rgb, out_T, wT, wl, wn, we, st))
+  int32_t* wle = ws_ptr<int32_t>(ws, p->off_lasteval);
+  if (!dispatch<FwdRun>(p->s.tile, p->s.batch, p, tiles, vt, ranges, items, rec, out_rgb, out_T, wT, wl, wn, we, wle,
+                        st))
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -309,8 +378,8 @@ hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float
 hipError_t launch_render_bwd(const odgs_plan* p, void* ws, const float* dL_drgb, hipStream_t st) {
   const ViewTable vt = make_view_table(p);
   const int tiles = p->tile_base[p->n_views];
-  float* g2d = ws_ptr<float>(ws, p->off_g2d);
   if (tiles == 0) return hipSuccess;
+  float* g2d = ws_ptr<float>(ws, p->off_g2d);
   const uint2* ranges = ws_ptr<uint2>(ws, p->off_ranges);
   const uint32_t* items = ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]);
   const Rec* rec = ws_ptr<Rec>(ws, p->off_rec);
@@ -324,24 +393,17 @@ hipError_t launch_render_bwd(const odgs_plan* p, void* ws, const float* dL_drgb,
 hipError_t launch_debug_records(const odgs_plan* p, const void* ws, float* out, hipStream_t st) {
   if (p->items == 0) return hipSuccess;
   hipLaunchKernelGGL(debug_records_kernel, dim3((unsigned)((p->items + 255) / 256)), dim3(256), 0, st,
-                     ws_ptr<Rec>(ws, p->off_rec), p->items, out);
+                     ws_ptr<Rec>(ws, p->off_rec), ws_ptr<float>(ws, p->off_depth), ws_ptr<uint32_t>(ws, p->off_count),
+                     p->items, out);
   return hipGetLastError();
-}
-
-__global__ void debug_pixel_counts_kernel(const int32_t* __restrict__ last, const int32_t* __restrict__ nc,
-                                          const int32_t* __restrict__ ne, int64_t pixels, int32_t* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= pixels) return;
-  out[3 * i] = last[i];
-  out[3 * i + 1] = nc[i];
-  out[3 * i + 2] = ne[i];
 }
 
 hipError_t launch_debug_pixel_counts(const odgs_plan* p, const void* ws, int32_t* out, hipStream_t st) {
   const int64_t pixels = p->pix_base[p->n_views];
+  if (pixels == 0) return hipSuccess;
   hipLaunchKernelGGL(debug_pixel_counts_kernel, dim3((unsigned)((pixels + 255) / 256)), dim3(256), 0, st,
                      ws_ptr<int32_t>(ws, p->off_last), ws_ptr<int32_t>(ws, p->off_ncontrib),
-                     ws_ptr<int32_t>(ws, p->off_neval), pixels, out);
+                     ws_ptr<int32_t>(ws, p->off_neval), ws_ptr<int32_t>(ws, p->off_lasteval), pixels, out);
   return hipGetLastError();
 }
 
@@ -350,7 +412,7 @@ hipError_t launch_debug_keys(const odgs_plan* p, const void* ws, int64_t cap, ui
   if (cap <= 0) return hipSuccess;
   hipLaunchKernelGGL(debug_keys_kernel, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st,
                      ws_ptr<uint32_t>(ws, p->off_pkey[p->pair_final]), ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]),
-                     ws_ptr<Rec>(ws, p->off_rec), ws_ptr<odgs_status>(ws, p->off_status), cap, p->n, keys, gauss);
+                     ws_ptr<float>(ws, p->off_depth), ws_ptr<odgs_status>(ws, p->off_status), cap, p->n, keys, gauss);
   return hipGetLastError();
 }
 

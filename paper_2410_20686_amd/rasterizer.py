@@ -134,9 +134,10 @@ class Rasterizer:
                            _ptr(self.ws), self.ws_bytes, *[_ptr(g) for g in grads], _stream())
 
     def pixel_counts(self) -> torch.Tensor:
-        """[pixels, 3] int32: list position after the last contributor, contributors, entries
-        evaluated, of the last forward."""
-        out = torch.empty((self.pixels, 3), dtype=torch.int32, device=self.device)
+        """[pixels, 4] int32 of the last forward: list position after the last contributor,
+        contributors, entries evaluated, and entries evaluated up to the last contributor (the
+        last two count only entries whose footprint reaches the pixel's 8x8 quadrant)."""
+        out = torch.empty((self.pixels, 4), dtype=torch.int32, device=self.device)
         B.odgs_debug_pixel_counts(self.plan, _ptr(self.ws), _ptr(out), _stream())
         return out
 
