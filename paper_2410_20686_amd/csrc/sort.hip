@@ -198,49 +198,98 @@ __global__ __launch_bounds__(256) void count_top_kernel(const uint32_t* __restri
   }
 }
 
-// Emit the (tile, item) pairs of depth-sorted items: pairs of one item are contiguous, items in
-// depth order, so a later stable sort by tile keeps (depth, index) order inside every tile.
-__global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ sorted_ids,
-                                                   const uint32_t* __restrict__ count, const Rect* __restrict__ rect,
-                                                   const uint64_t* __restrict__ block_off, int64_t items, int64_t n,
-                                                   ViewTable vt, int tile, int64_t capacity,
-                                                   uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
+// First pair position of every depth-sorted item (clamped to the capacity: items starting past
+// it emit nothing).  Pairs of one item are contiguous and items follow depth order, so a later
+// stable sort by tile keeps (depth, index) order inside every tile.
+__global__ __launch_bounds__(256) void item_offsets_kernel(const uint32_t* __restrict__ sorted_ids,
+                                                           const uint32_t* __restrict__ count,
+                                                           const uint64_t* __restrict__ block_off, int64_t items,
+                                                           int64_t capacity, uint32_t* __restrict__ ioff) {
   __shared__ uint32_t lds[4];
   const int64_t start = (int64_t)blockIdx.x * kScanBlockItems;
-  uint32_t ids[kScanIpt], cnt[kScanIpt];
+  uint32_t cnt[kScanIpt];
   uint32_t s = 0;
 #pragma unroll
   for (int k = 0; k < kScanIpt; ++k) {
     const int64_t j = start + threadIdx.x * kScanIpt + k;
-    ids[k] = j < items ? sorted_ids[j] : 0u;
-    cnt[k] = j < items ? count[ids[k]] : 0u;
+    cnt[k] = j < items ? count[sorted_ids[j]] : 0u;
     s += cnt[k];
   }
   uint32_t total;
   const uint32_t incl = block_incl_scan256(s, lds, total);
   uint64_t off = block_off[blockIdx.x] + (incl - s);
-#pragma unroll 1
+#pragma unroll
   for (int k = 0; k < kScanIpt; ++k) {
-    if (cnt[k] == 0) continue;
-    const uint32_t item = ids[k];
-    const Rect rr = rect[item];
-    const int v = view_of_item(item, n);
-    const int ntx = vt.W[v] / tile;
-    const uint32_t tb = (uint32_t)vt.tile_base[v];
-    uint64_t pos = off;
-    for (int r = 0; r < rr.nrows; ++r) {
-      const uint32_t rowbase = tb + (uint32_t)(rr.row0 + r) * ntx;
-      int col = rr.col0;
-      for (int c = 0; c < rr.ncols; ++c) {
-        if (pos < (uint64_t)capacity) {
-          pkey[pos] = rowbase + col;
-          pval[pos] = item;
-        }
-        ++pos;
-        if (++col == ntx) col = 0;
-      }
-    }
+    const int64_t j = start + threadIdx.x * kScanIpt + k;
+    if (j < items) ioff[j] = (uint32_t)(off < (uint64_t)capacity ? off : (uint64_t)capacity);
     off += cnt[k];
+  }
+}
+
+// Pair-parallel emission: block b writes pairs [b * kEmitPairs, (b + 1) * kEmitPairs), one thread
+// per pair, so stores are coalesced whatever the items' sizes.  The block locates its items with
+// one binary search over the item offsets, stages them in LDS, and each thread finds its item by
+// a binary search in LDS.
+constexpr int kEmitPairs = 1024;
+
+__device__ inline int64_t upper_bound_u32(const uint32_t* a, int64_t n, uint32_t x) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] <= x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restrict__ sorted_ids,
+                                                         const uint32_t* __restrict__ ioff,
+                                                         const Rect* __restrict__ rect,
+                                                         const odgs_status* __restrict__ status, int64_t items,
+                                                         int64_t n, ViewTable vt, int tile, uint32_t* __restrict__ pkey,
+                                                         uint32_t* __restrict__ pval) {
+  __shared__ uint32_t s_off[kEmitPairs + 1];
+  __shared__ uint32_t s_item[kEmitPairs + 1];
+  __shared__ Rect s_rect[kEmitPairs + 1];
+  __shared__ uint32_t s_tb[kEmitPairs + 1];
+  __shared__ uint16_t s_ntx[kEmitPairs + 1];
+  __shared__ int64_t s_range[2];
+  const uint32_t np = (uint32_t)status->n_pairs_stored;
+  const uint32_t p0 = blockIdx.x * (uint32_t)kEmitPairs;
+  if (p0 >= np) return;  // uniform
+  const uint32_t p1 = min(p0 + (uint32_t)kEmitPairs, np);
+  if (threadIdx.x == 0) {
+    s_range[0] = upper_bound_u32(ioff, items, p0) - 1;      // item holding pair p0
+    s_range[1] = upper_bound_u32(ioff, items, p1 - 1) - 1;  // item holding pair p1 - 1
+  }
+  __syncthreads();
+  const int64_t i0 = s_range[0];
+  const int m = (int)(s_range[1] - i0 + 1);  // <= kEmitPairs: every listed item owns >= 1 pair here
+  for (int t = threadIdx.x; t < m; t += 256) {
+    const uint32_t item = sorted_ids[i0 + t];
+    const int v = view_of_item(item, n);
+    s_off[t] = ioff[i0 + t];
+    s_item[t] = item;
+    s_rect[t] = rect[item];
+    s_tb[t] = (uint32_t)vt.tile_base[v];
+    s_ntx[t] = (uint16_t)(vt.W[v] / tile);
+  }
+  __syncthreads();
+  for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256) {
+    int lo = 0, hi = m;  // largest idx with s_off[idx] <= p
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_off[mid] <= p) lo = mid;
+      else hi = mid;
+    }
+    const Rect rr = s_rect[lo];
+    const uint32_t local = p - s_off[lo];
+    const uint32_t r = local / rr.ncols;
+    uint32_t col = rr.col0 + (local - r * rr.ncols);
+    const uint32_t ntx = s_ntx[lo];
+    if (col >= ntx) col -= ntx;
+    pkey[p] = s_tb[lo] + (uint32_t)(rr.row0 + r) * ntx + col;
+    pval[p] = s_item[lo];
   }
 }
 
@@ -322,12 +371,16 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
   const uint32_t* count = ws_ptr<uint32_t>(ws, p->off_count);
   hipLaunchKernelGGL(count_reduce_kernel, dim3(sblocks), dim3(256), 0, st, sorted_ids, count, items, bsum);
   hipLaunchKernelGGL(count_top_kernel, dim3(1), dim3(256), 0, st, bsum, boff, sblocks, p->pair_capacity, status);
-  // 3. emit pairs
+  // 3. emit pairs: per-item offsets (into the free ping-pong buffer), then pair-parallel writes
   uint32_t* pk[2] = {ws_ptr<uint32_t>(ws, p->off_pkey[0]), ws_ptr<uint32_t>(ws, p->off_pkey[1])};
   uint32_t* pv[2] = {ws_ptr<uint32_t>(ws, p->off_pval[0]), ws_ptr<uint32_t>(ws, p->off_pval[1])};
   const ViewTable vt = make_view_table(p);
-  hipLaunchKernelGGL(emit_kernel, dim3(sblocks), dim3(256), 0, st, sorted_ids, count,
-                     ws_ptr<Rect>(ws, p->off_rect), boff, items, p->n, vt, p->s.tile, p->pair_capacity, pk[0], pv[0]);
+  uint32_t* ioff = dk[p->depth_final ^ 1];
+  hipLaunchKernelGGL(item_offsets_kernel, dim3(sblocks), dim3(256), 0, st, sorted_ids, count, boff, items,
+                     p->pair_capacity, ioff);
+  hipLaunchKernelGGL(emit_pairs_kernel, dim3((unsigned)((p->pair_capacity + kEmitPairs - 1) / kEmitPairs)), dim3(256),
+                     0, st, sorted_ids, ioff, ws_ptr<Rect>(ws, p->off_rect), status, items, p->n, vt, p->s.tile, pk[0],
+                     pv[0]);
   // 4. stable sort of the pairs by global tile
   const uint32_t* n_dev = reinterpret_cast<const uint32_t*>(&status->n_pairs_stored);
   e = radix_sort(pk[0], pv[0], pk[1], pv[1], false, n_dev, (uint32_t)p->pair_capacity, p->tile_bits, p->pair_blocks,

@@ -30,12 +30,13 @@ def _snapshot(step):
 
 
 def _compare(a, b):
+    """Images bit-identical; gradients equal up to the order of float atomic additions, which
+    differs from run to run (relative 1e-4 plus 1e-5 of the tensor's largest magnitude)."""
     import torch
     assert torch.equal(a[0], b[0])
-    for ga, gb in zip(a[1], b[1]):
-        ga, gb = ga.double().cpu().numpy(), gb.double().cpu().numpy()
-        lim = 1e-5 * np.abs(gb) + 1e-7 * np.abs(gb).max()
-        assert np.all(np.abs(ga - gb) <= lim)
+    names = ("means", "scales", "quats", "opacities", "sh")
+    G.assert_grads_close({k: g.cpu().numpy() for k, g in zip(names, a[1])},
+                         {k: g.cpu().numpy() for k, g in zip(names, b[1])}, rtol=1e-4, floor=1e-5)
 
 
 def test_graph_replays_match_eager():
