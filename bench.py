@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--n", type=int, default=500_000)
+    ap.add_argument("--autotune", action="store_true", help="pick (tile, batch) with the autotuner first")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of this many MiB (a known-size reference "
+                         "dispatch for hardware byte counters)")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels-per-view", type=int, default=1024)
@@ -122,9 +126,23 @@ def main():
     dL_np = scenes.upstream_gradient(cams, 1005)
     log("scene ready %.1fs" % (time.time() - t0))
 
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
     tensors = [dev(a) for a in (sc.means, sc.scales, sc.quats, sc.opacities, sc.sh, cams.cams)]
     dL = dev(dL_np)
+
+    tuned = None
+    if args.autotune:
+        from paper_2410_20686_amd import autotune
+        tuned = autotune.tune(tensors[:5], tensors[5], dL, sc.sh_degree, wh, st, cache=None, log=log)
+        st = dict(st, tile=tuned["tile"], batch=tuned["batch"])
+        log("autotuned:", tuned["tile"], tuned["batch"])
 
     # size the pair list from one binning pass, then keep it fixed (no host sync inside steps)
     rast = Rasterizer(sc.n, sc.sh_degree, wh, st)
@@ -206,7 +224,8 @@ def main():
         "config": {"workload": "M: 500k Gaussians (roaming: 70%% in 50 blobs, 30%% shell r 2-20, SH degree 3), "
                                "%d views 2048x1024, fwd+bwd, all views batched in one HIP graph per step" % V,
                    "gaussians": sc.n, "views": V, "width": wh[0][0], "height": wh[0][1], "sh_degree": 3,
-                   "tile": st["tile"], "batch": rast.plan.s.batch, "pairs": status["n_pairs"]},
+                   "tile": st["tile"], "batch": rast.plan.s.batch, "pairs": status["n_pairs"],
+                   "autotuned": tuned is not None},
         "per_view": per_view,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roof,

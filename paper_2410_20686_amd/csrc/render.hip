@@ -74,16 +74,82 @@ __device__ inline uint32_t quadrant_mask(float u, float v, float eu, float ev, i
   return mask;
 }
 
+// Horizontal offset wrapped into [-W/2, W/2) without branches.
+__device__ inline float wrap_du(float du, float Wf, float half) {
+  du = du >= half ? du - Wf : du;
+  return du < -half ? du + Wf : du;
+}
+
+// Stage `cnt` records of a tile list into LDS (entry e <- list position first + dir * e) and
+// build, for every quadrant, the order-preserving list of entries whose footprint reaches it.
+// Counts per quadrant are returned in nq[] (identical in every thread).
+template <int TILE, int BATCH>
+struct Stage {
+  static constexpr int N = TILE * TILE;
+  static constexpr int NQ = (TILE / 8) * (TILE / 8);
+  static constexpr int NW = N / kWave;
+  float4 s0[BATCH];
+  float4 s1[BATCH];
+  float4 s2[BATCH];
+  uint32_t sid[BATCH];
+  uint8_t list[NQ][BATCH];
+  uint32_t wcnt[NW][NQ];
+};
+
+template <int TILE, int BATCH>
+__device__ inline void stage_batch(Stage<TILE, BATCH>& S, const uint32_t* __restrict__ pair_items,
+                                   const Rec* __restrict__ rec, uint32_t first, int dir, int cnt, int tx0, int ty0,
+                                   float Wf, float half, int (&nq)[Stage<TILE, BATCH>::NQ]) {
+  using St = Stage<TILE, BATCH>;
+  const int t = threadIdx.x, ln = t & (kWave - 1), wv = t >> 6;
+  const uint64_t below = ln == 0 ? 0ull : (~0ull >> (kWave - ln));
+#pragma unroll
+  for (int q = 0; q < St::NQ; ++q) nq[q] = 0;
+  for (int r0 = 0; r0 < cnt; r0 += St::N) {
+    const int e = r0 + t;
+    uint32_t m = 0;
+    if (e < cnt) {
+      const uint32_t item = pair_items[first + dir * e];
+      const Rec r = rec[item];
+      S.s0[e] = r.r0;
+      S.s1[e] = r.r1;
+      S.s2[e] = r.r2;
+      S.sid[e] = item;
+      m = quadrant_mask<TILE>(r.r0.x, r.r0.y, r.r1.w, r.r2.w, tx0, ty0, Wf, half);
+    }
+    uint32_t within[St::NQ];
+#pragma unroll
+    for (int q = 0; q < St::NQ; ++q) {
+      const uint64_t bq = __ballot((m >> q) & 1u);
+      within[q] = __popcll(bq & below);
+      if (ln == 0) S.wcnt[wv][q] = __popcll(bq);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < St::NQ; ++q) {
+      int base = nq[q], tot = 0;
+#pragma unroll
+      for (int w = 0; w < St::NW; ++w) {
+        const int c = (int)S.wcnt[w][q];
+        base += w < wv ? c : 0;
+        tot += c;
+      }
+      if ((m >> q) & 1u) S.list[q][base + within[q]] = (uint8_t)e;
+      nq[q] += tot;
+    }
+    __syncthreads();
+  }
+}
+
 template <int TILE, int BATCH>
 __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
     float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
     int32_t* __restrict__ ws_ncontrib, int32_t* __restrict__ ws_neval, int32_t* __restrict__ ws_lasteval, float bg0,
     float bg1, float bg2) {
-  constexpr int N = TILE * TILE;
-  __shared__ float4 s0[BATCH];
-  __shared__ float4 s1[BATCH];  // (C, opacity, p_min, quadrant mask bits)
-  __shared__ float4 s2[BATCH];
+  using St = Stage<TILE, BATCH>;
+  constexpr int N = St::N;
+  __shared__ St S;
   const int g = blockIdx.x;
   const int v = view_of_tile(vt, g);
   const int W = vt.W[v], H = vt.H[v];
@@ -93,7 +159,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
   int lx, ly;
   local_pixel<TILE>(threadIdx.x, lx, ly);
   const int x = tx0 + lx, y = ty0 + ly;
-  const uint32_t qbit = 1u << (threadIdx.x >> 6);
+  const int wq = threadIdx.x >> 6;  // this wavefront's quadrant
   const float px = (float)x + 0.5f, py = (float)y + 0.5f;
   const float Wf = (float)W, half = (float)W * 0.5f;
   const uint2 rg = ranges[g];
@@ -103,43 +169,35 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
   for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
     if (__syncthreads_count(done) == N) break;
     const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
-    for (int t = threadIdx.x; t < cnt; t += N) {
-      const Rec r = rec[pair_items[base + t]];
-      s0[t] = r.r0;
-      const uint32_t m = quadrant_mask<TILE>(r.r0.x, r.r0.y, r.r1.w, r.r2.w, tx0, ty0, Wf, half);
-      s1[t] = make_float4(r.r1.x, r.r1.y, r.r1.z, __uint_as_float(m));
-      s2[t] = r.r2;
-    }
-    __syncthreads();
-    if (!done) {
-      for (int k = 0; k < cnt; ++k) {
-        const float4 b = s1[k];
-        if (!(__float_as_uint(b.w) & qbit)) continue;  // uniform across the wavefront
-        const float4 a = s0[k];
-        ++nev;
-        float du = px - a.x;
-        if (du >= half) du = du - Wf;
-        else if (du < -half) du = du + Wf;
-        const float dv = py - a.y;
-        const float power = fmaf(a.z, du * du, fmaf(a.w, du * dv, b.x * (dv * dv)));
-        if (power > 0.0f || power < b.z) continue;
-        float alpha = b.y * __expf(power);
-        if (alpha > kAlphaMax) alpha = kAlphaMax;
-        const float Tn = T * (1.0f - alpha);
-        if (Tn < kTStop) {
-          done = true;
-          break;
-        }
-        const float w = alpha * T;
-        const float4 c = s2[k];
-        C0 = fmaf(w, c.x, C0);
-        C1 = fmaf(w, c.y, C1);
-        C2 = fmaf(w, c.z, C2);
-        T = Tn;
-        last = (int)(base - rg.x) + k + 1;
-        lastev = nev;
-        ++ncontrib;
-      }
+    int nq[St::NQ];
+    stage_batch<TILE, BATCH>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq);
+    const int n = nq[wq];
+    for (int i = 0; i < n; ++i) {
+      if (__ballot(!done) == 0ull) break;  // uniform: every pixel of the wavefront has finished
+      const int k = S.list[wq][i];
+      const float4 a = S.s0[k];
+      const float4 b = S.s1[k];
+      const float du = wrap_du(px - a.x, Wf, half);
+      const float dv = py - a.y;
+      const float power = fmaf(a.z, du * du, fmaf(a.w, du * dv, b.x * (dv * dv)));
+      nev += done ? 0 : 1;
+      const bool ok = !done && !(power > 0.0f || power < b.z);
+      if (__ballot(ok) == 0ull) continue;  // uniform
+      float alpha = b.y * __expf(power);
+      alpha = alpha > kAlphaMax ? kAlphaMax : alpha;
+      const float Tn = T * (1.0f - alpha);
+      const bool stop = ok && Tn < kTStop;
+      const bool acc = ok && !(Tn < kTStop);
+      done = done || stop;
+      const float4 c = S.s2[k];
+      const float w = acc ? alpha * T : 0.0f;
+      C0 = fmaf(w, c.x, C0);
+      C1 = fmaf(w, c.y, C1);
+      C2 = fmaf(w, c.z, C2);
+      T = acc ? Tn : T;
+      last = acc ? (int)(base - rg.x) + k + 1 : last;
+      lastev = acc ? nev : lastev;
+      ncontrib += acc ? 1 : 0;
     }
   }
   const int64_t plane = (int64_t)W * H;
@@ -166,11 +224,9 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
                                                                 const int32_t* __restrict__ ws_last,
                                                                 const float* __restrict__ dL_drgb, float* __restrict__ g2d,
                                                                 int64_t items, float bg0, float bg1, float bg2) {
-  constexpr int N = TILE * TILE;
-  __shared__ float4 s0[BATCH];
-  __shared__ float4 s1[BATCH];
-  __shared__ float4 s2[BATCH];
-  __shared__ uint32_t sid[BATCH];
+  using St = Stage<TILE, BATCH>;
+  constexpr int N = St::N;
+  __shared__ St S;
   __shared__ float acc[9][BATCH];
   __shared__ int smax;
   const int g = blockIdx.x;
@@ -183,7 +239,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   local_pixel<TILE>(threadIdx.x, lx, ly);
   const int x = tx0 + lx, y = ty0 + ly;
   const int lane = threadIdx.x & (kWave - 1);
-  const uint32_t qbit = 1u << (threadIdx.x >> 6);
+  const int wq = threadIdx.x >> 6;
   const float px = (float)x + 0.5f, py = (float)y + 0.5f;
   const float Wf = (float)W, half = (float)W * 0.5f;
   const uint2 rg = ranges[g];
@@ -207,76 +263,60 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   for (int end = end_all; end > 0; end -= BATCH) {
     const int cnt = min(BATCH, end);
     for (int t = threadIdx.x; t < cnt; t += N) {
-      const uint32_t item = pair_items[rg.x + end - 1 - t];
-      const Rec r = rec[item];
-      s0[t] = r.r0;
-      const uint32_t m = quadrant_mask<TILE>(r.r0.x, r.r0.y, r.r1.w, r.r2.w, tx0, ty0, Wf, half);
-      s1[t] = make_float4(r.r1.x, r.r1.y, r.r1.z, __uint_as_float(m));
-      s2[t] = r.r2;
-      sid[t] = item;
 #pragma unroll
       for (int q = 0; q < 9; ++q) acc[q][t] = 0.0f;
     }
-    __syncthreads();
-    // entries at list positions >= wmax cannot touch this wavefront
-    const int k0 = max(0, end - wmax);
-    for (int k = k0; k < cnt; ++k) {
-      const float4 b = s1[k];
-      if (!(__float_as_uint(b.w) & qbit)) continue;  // uniform across the wavefront
+    int nq[St::NQ];
+    // entry e is list position end - 1 - e (back to front)
+    stage_batch<TILE, BATCH>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq);
+    const int n = nq[wq];
+    for (int i = 0; i < n; ++i) {
+      const int k = S.list[wq][i];
       const int jrel = end - 1 - k;
+      if (jrel >= wmax) continue;  // uniform: behind every contributor of this wavefront
+      const float4 a = S.s0[k];
+      const float4 b = S.s1[k];
+      const float du = wrap_du(px - a.x, Wf, half);
+      const float dv = py - a.y;
+      const float power = fmaf(a.z, du * du, fmaf(a.w, du * dv, b.x * (dv * dv)));
+      const bool ok = jrel < last && !(power > 0.0f || power < b.z);
+      if (__ballot(ok) == 0ull) continue;  // uniform
+      const float G = __expf(power);
+      float alpha = b.y * G;
+      const bool clamped = alpha > kAlphaMax;
+      alpha = clamped ? kAlphaMax : alpha;
+      const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
+      T = ok ? T * inv_om : T;  // transmittance in front of this Gaussian
+      const float w = alpha * T;
+      const float4 c = S.s2[k];
+      const float dL_da =
+          dl0 * fmaf(c.x, T, -S0 * inv_om) + dl1 * fmaf(c.y, T, -S1 * inv_om) + dl2 * fmaf(c.z, T, -S2 * inv_om);
+      const float wk = ok ? w : 0.0f;
+      S0 = fmaf(c.x, wk, S0);
+      S1 = fmaf(c.y, wk, S1);
+      S2 = fmaf(c.z, wk, S2);
+      const float dpow = (ok && !clamped) ? dL_da * alpha : 0.0f;
+      const float ca = -2.0f * a.z, cb = -a.w, cc = -2.0f * b.x;
       float gq[9];
+      gq[0] = dpow * fmaf(ca, du, cb * dv);
+      gq[1] = dpow * fmaf(cb, du, cc * dv);
+      gq[2] = -0.5f * dpow * (du * du);
+      gq[3] = -dpow * (du * dv);
+      gq[4] = -0.5f * dpow * (dv * dv);
+      gq[5] = (ok && !clamped) ? dL_da * G : 0.0f;
+      gq[6] = wk * dl0;
+      gq[7] = wk * dl1;
+      gq[8] = wk * dl2;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) gq[q] = 0.0f;
-      bool contrib = false;
-      if (jrel < last) {
-        const float4 a = s0[k];
-        float du = px - a.x;
-        if (du >= half) du = du - Wf;
-        else if (du < -half) du = du + Wf;
-        const float dv = py - a.y;
-        const float power = fmaf(a.z, du * du, fmaf(a.w, du * dv, b.x * (dv * dv)));
-        if (!(power > 0.0f || power < b.z)) {
-          contrib = true;
-          const float G = __expf(power);
-          float alpha = b.y * G;
-          const bool clamped = alpha > kAlphaMax;
-          if (clamped) alpha = kAlphaMax;
-          const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
-          T = T * inv_om;  // transmittance in front of this Gaussian
-          const float w = alpha * T;
-          const float4 c = s2[k];
-          gq[6] = w * dl0;
-          gq[7] = w * dl1;
-          gq[8] = w * dl2;
-          const float dL_da = dl0 * fmaf(c.x, T, -S0 * inv_om) + dl1 * fmaf(c.y, T, -S1 * inv_om) +
-                              dl2 * fmaf(c.z, T, -S2 * inv_om);
-          S0 = fmaf(c.x, w, S0);
-          S1 = fmaf(c.y, w, S1);
-          S2 = fmaf(c.z, w, S2);
-          if (!clamped) {
-            const float dpow = dL_da * alpha;
-            const float ca = -2.0f * a.z, cb = -a.w, cc = -2.0f * b.x;
-            gq[0] = dpow * fmaf(ca, du, cb * dv);
-            gq[1] = dpow * fmaf(cb, du, cc * dv);
-            gq[2] = -0.5f * dpow * (du * du);
-            gq[3] = -dpow * (du * dv);
-            gq[4] = -0.5f * dpow * (dv * dv);
-            gq[5] = dL_da * G;
-          }
-        }
-      }
-      if (__ballot(contrib) != 0ull) {
+      for (int q = 0; q < 9; ++q) gq[q] = lane63(wave_sum_to_lane63(gq[q]));
+      if (lane == 0) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) gq[q] = lane63(wave_sum_to_lane63(gq[q]));
-        if (lane == 0) {
-#pragma unroll
-          for (int q = 0; q < 9; ++q) atomicAdd(&acc[q][k], gq[q]);
-        }
+        for (int q = 0; q < 9; ++q) atomicAdd(&acc[q][k], gq[q]);
       }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < cnt; t += N) {
-      const uint32_t item = sid[t];
+      const uint32_t item = S.sid[t];
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
         const float s = acc[q][t];
