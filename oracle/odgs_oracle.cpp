@@ -405,9 +405,15 @@ uint32_t float_bits(float f) {
 // ----------------------------------------------------------------------------------------------
 // Records used by the compositor, in the compositing precision R.
 // ----------------------------------------------------------------------------------------------
+// The exponent of Eq. gaussian2d, power = -1/2 d^T Sigma^-1 d, is evaluated as a sum of two
+// squares, power = -((l0 du + l1 dv)^2 + (l2 dv)^2), where (l0, l1; 0, l2) is the Cholesky factor
+// of Sigma^-1 / 2.  Written this way the float evaluation has no cancellation even for very
+// elongated footprints (the expanded quadratic form loses ~1e-3 relative accuracy there).  The
+// factor is computed from Sigma_2D in double without cancellation:
+//   l0 = sqrt(S_vv / (2 det)),  l1 = -S_uv / (2 det l0),  l2 = 1 / sqrt(2 S_vv).
 template <typename R>
 struct Rec {
-  R u, v, A, Bc, C, o, pmin, rgb[3];
+  R u, v, l0, l1, l2, o, pmin, rgb[3];
 };
 
 template <typename R>
@@ -415,11 +421,12 @@ Rec<R> make_rec(const Proj<double>& p, const Info& info) {
   Rec<R> r;
   r.u = (R)p.u;
   r.v = (R)p.v;
-  // power = -1/2 (a du^2 + 2 b du dv + c dv^2) = A du^2 + Bc du dv + C dv^2 (scalings by 1/2 and
-  // sign flips are exact after rounding a, b, c).
-  r.A = (R)(-0.5) * (R)p.conic[0];
-  r.Bc = -(R)p.conic[1];
-  r.C = (R)(-0.5) * (R)p.conic[2];
+  const double suu = info.cov2[0], suv = info.cov2[1], svv = info.cov2[2];
+  const double det = suu * svv - suv * suv;
+  const double l0 = std::sqrt(svv / (2.0 * det));
+  r.l0 = (R)l0;
+  r.l1 = (R)(-suv / (2.0 * det * l0));
+  r.l2 = (R)(1.0 / std::sqrt(2.0 * svv));
   r.o = (R)p.opacity;
   r.pmin = (R)info.p_min;
   for (int k = 0; k < 3; ++k) r.rgb[k] = (R)p.rgb[k];
@@ -474,7 +481,9 @@ PixResult composite(const int32_t* order, int64_t count, const Rec<R>* recs, int
     if (du >= half) du = du - Wf;
     else if (du < -half) du = du + Wf;
     const R dv = py - g.v;
-    const R power = std::fma(g.A, du * du, std::fma(g.Bc, du * dv, g.C * (dv * dv)));
+    const R t1 = std::fma(g.l0, du, g.l1 * dv);
+    const R t2 = g.l2 * dv;
+    const R power = -std::fma(t1, t1, t2 * t2);
     if (power > (R)0 || power < g.pmin) continue;
     R alpha = g.o * exp_r(power);
     int clamped = 0;
@@ -640,7 +649,8 @@ PixResult render_pixel(const Prepared& P, const std::vector<Rec<R>>& recs, const
 //   dC_c/d rgb_jc = a_j T_j
 //   dC_c/d a_j   = rgb_jc T_j - (sum_{k>j} rgb_kc a_k T_k + T_final bg_c) / (1 - a_j)
 // then through a = min(0.99, o G), G = exp(power),
-//   power = -1/2 (a du^2 + 2 b du dv + c dv^2),  du = x + 0.5 - u (wrapped), dv = y + 0.5 - v.
+//   power = -1/2 (a du^2 + 2 b du dv + c dv^2),  du = x + 0.5 - u (wrapped), dv = y + 0.5 - v,
+// with d power / d(a, b, c) = -(du^2/2, du dv, dv^2/2) and d power / d(u, v) = Sigma^-1 d.
 // g2d layout per item: [u, v, conic a, conic b, conic c, opacity, r, g, b].
 void pixel_backward(const std::vector<Contrib>& cl, const std::vector<Rec<double>>& rec64, const double* gpix,
                     const double* bg, double* g2d_view) {
@@ -650,7 +660,8 @@ void pixel_backward(const std::vector<Contrib>& cl, const std::vector<Rec<double
   for (size_t j = 0; j < n; ++j) {
     const Rec<double>& g = rec64[cl[j].idx];
     const double du = cl[j].du, dv = cl[j].dv;
-    const double power = g.A * du * du + g.Bc * du * dv + g.C * dv * dv;
+    const double t1 = g.l0 * du + g.l1 * dv, t2 = g.l2 * dv;
+    const double power = -(t1 * t1 + t2 * t2);
     G[j] = std::exp(power);
     alpha[j] = cl[j].clamped ? 0.99 : g.o * G[j];
     T[j + 1] = T[j] * (1.0 - alpha[j]);
@@ -670,10 +681,11 @@ void pixel_backward(const std::vector<Contrib>& cl, const std::vector<Rec<double
     }
     if (cl[jj].clamped) continue;
     const double du = cl[jj].du, dv = cl[jj].dv;
-    const double a = -2.0 * g.A, b = -g.Bc, c = -2.0 * g.C;  // conic entries
+    const double t1 = g.l0 * du + g.l1 * dv, t2 = g.l2 * dv;
     const double dL_dpow = dL_da * alpha[jj];
-    const double gu = dL_dpow * (a * du + b * dv);   // d power / d u = a du + b dv
-    const double gv = dL_dpow * (b * du + c * dv);
+    // d power / d u = (Sigma^-1 d)_u = 2 l0 t1,  d power / d v = 2 (l1 t1 + l2 t2)
+    const double gu = dL_dpow * (2.0 * g.l0 * t1);
+    const double gv = dL_dpow * (2.0 * (g.l1 * t1 + g.l2 * t2));
     const double ga = dL_dpow * (-0.5 * du * du);
     const double gb = dL_dpow * (-du * dv);
     const double gc = dL_dpow * (-0.5 * dv * dv);
@@ -847,8 +859,8 @@ int oracle_backward(const double* means, const double* scales, const double* qua
       r32 = make_recs<float>(P, v);
       rvals.resize(r32.size());
       for (size_t i = 0; i < r32.size(); ++i) {
-        rvals[i].u = r32[i].u; rvals[i].v = r32[i].v; rvals[i].A = r32[i].A; rvals[i].Bc = r32[i].Bc;
-        rvals[i].C = r32[i].C; rvals[i].o = r32[i].o; rvals[i].pmin = r32[i].pmin;
+        rvals[i].u = r32[i].u; rvals[i].v = r32[i].v; rvals[i].l0 = r32[i].l0; rvals[i].l1 = r32[i].l1;
+        rvals[i].l2 = r32[i].l2; rvals[i].o = r32[i].o; rvals[i].pmin = r32[i].pmin;
         for (int c = 0; c < 3; ++c) rvals[i].rgb[c] = r32[i].rgb[c];
       }
     } else {

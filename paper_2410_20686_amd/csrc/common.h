@@ -20,9 +20,9 @@ struct ViewTable {
 };
 
 // Compositor record of one (Gaussian, view) item, three 16-byte words:
-//   r0 = (u, v, A, B)          A du^2 + B du dv + C dv^2 is the Gaussian's exponent
-//   r1 = (C, opacity, p_min, depth)
-//   r2 = (red, green, blue, tile count as float bits)
+//   r0 = (u, v, l0, l1)        exponent -((l0 du + l1 dv)^2 + (l2 dv)^2), du = px - u, dv = py - v
+//   r1 = (l2, opacity, p_min, eu)
+//   r2 = (red, green, blue, ev)  eu, ev: padded half extents of the alpha >= 1/255 footprint
 struct Rec {
   float4 r0, r1, r2;
 };

@@ -248,7 +248,11 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
     Rect rr{0, 0, 0, 0};
     uint32_t cnt = 0;
     if (kept) {
-      const double ca = g.c2[2] / g.det, cb = -g.c2[1] / g.det, cc = g.c2[0] / g.det;
+      // Cholesky factor (l0, l1; 0, l2) of Sigma^-1 / 2, so that the compositor evaluates the
+      // exponent -d^T Sigma^-1 d / 2 as -((l0 du + l1 dv)^2 + (l2 dv)^2) without cancellation.
+      const double l0 = sqrt(g.c2[2] / (2.0 * g.det));
+      const double l1 = -g.c2[1] / (2.0 * g.det * l0);
+      const double l2 = 1.0 / sqrt(2.0 * g.c2[2]);
       double d[3], dist;
       view_dir(m, cam, d, dist);
       double Y[K];
@@ -292,8 +296,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
         if (kept) {
           rr = Rect{(uint16_t)col0, (uint16_t)ncols, (uint16_t)row0, (uint16_t)nrows};
           cnt = (uint32_t)ncols * (uint32_t)nrows;
-          out.r0 = make_float4((float)g.u, (float)g.v, -0.5f * (float)ca, -(float)cb);
-          out.r1 = make_float4(-0.5f * (float)cc, o, (float)p_min, round_up_f32(eu));
+          out.r0 = make_float4((float)g.u, (float)g.v, (float)l0, (float)l1);
+          out.r1 = make_float4((float)l2, o, (float)p_min, round_up_f32(eu));
           out.r2 = make_float4(rgb[0], rgb[1], rgb[2], round_up_f32(ev));
         }
       }
@@ -321,9 +325,9 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
 }
 
 // ---------------------------------------------------------------------------------------------
-// Adjoint.  Inputs per item: 2D gradients g2d[9][items] = (u, v, conic a, b, c, opacity, r, g, b)
-// where the inverse covariance is [[a, b], [b, c]] (b is the shared off-diagonal).  Sums over
-// views; writes (overwrites) the parameter gradients.
+// Adjoint.  Inputs per item: 2D gradients g2d[9][items] = (u, v, S_uu, S_uv, S_vv, opacity, r, g,
+// b) with Sigma_2D = [[S_uu, S_uv], [S_uv, S_vv]] (S_uv the shared off-diagonal, dilation
+// included).  Sums over views; writes (overwrites) the parameter gradients.
 // ---------------------------------------------------------------------------------------------
 template <int K>
 __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
@@ -371,15 +375,8 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     load_cam(cams, v, cam);
     Geo G;
     geometry(m, cam, cv, vt.W[v], vt.H[v], P, G);
-    // conic = inverse(Sigma2D): dL/dSigma2D = -C Gc C with Gc = [[ga, gb/2], [gb/2, gc]].
-    const double inv = 1.0 / G.det;
-    const double ca = G.c2[2] * inv, cb = -G.c2[1] * inv, cc = G.c2[0] * inv;
-    const double gc00 = g[2], gc01 = 0.5 * g[3], gc11 = g[4];
-    const double t00 = ca * gc00 + cb * gc01, t01 = ca * gc01 + cb * gc11;
-    const double t10 = cb * gc00 + cc * gc01, t11 = cb * gc01 + cc * gc11;
-    const double G00 = -(t00 * ca + t01 * cb);
-    const double G01 = -(t00 * cb + t01 * cc);
-    const double G11 = -(t10 * cb + t11 * cc);
+    // dL/dSigma_2D as a symmetric matrix (the shared off-diagonal derivative split in halves)
+    const double G00 = g[2], G01 = 0.5 * g[3], G11 = g[4];
     // Sigma2D = A Sigma A^T: dA = 2 G2 A Sigma, dSigma += A^T G2 A (G2 symmetric 2x2).
     double GA[6];
 #pragma unroll

@@ -10,9 +10,10 @@
 // Forward: front-to-back compositing (Eq. gaussian2d, Eq. alphablending) until a pixel's
 // transmittance would drop below 1e-4; the workgroup stops loading batches once every pixel is
 // done.  Backward: back to front from the last contributor, transmittance recovered by
-// multiplying with 1/(1 - alpha); per-pixel gradients of the 2D quantities are summed over the
-// wavefront with DPP row operations, over the workgroup's wavefronts with LDS float atomics,
-// and reach global memory with one float atomic per (Gaussian, tile, quantity).
+// multiplying with 1/(1 - alpha); the nine per-pixel gradients of the 2D quantities are summed
+// over each 16-lane row by a DPP butterfly that leaves one value per lane, over rows and
+// wavefronts with LDS float atomics, and reach global memory with one float atomic per
+// (Gaussian, tile, quantity).
 // One launch covers all views of a step: the grid spans the global tile ids of every view.
 #include <utility>
 
@@ -43,6 +44,36 @@ __device__ inline float wave_sum_to_lane63(float v) {
 
 __device__ inline float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
 
+template <int CTRL>
+__device__ inline float dpp_read(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Exchange step of a multi-value butterfly: the lane keeps `lo` or `hi` (by `bit`) and adds the
+// partner's copy of the same slot; the partner (reached with DPP control CTRL) has the opposite
+// `bit` and holds the same slot meanings.
+template <int CTRL>
+__device__ inline float bfly(float lo, float hi, bool bit) {
+  return (bit ? hi : lo) + dpp_read<CTRL>(bit ? lo : hi);
+}
+
+// Sums nine per-lane values over each 16-lane row in four DPP exchange steps (pairs (i, 15-i),
+// (i, 7-i), (i, 3-i), (i, i^1) inside the row; each step halves the slots a lane holds).  Lane i
+// ends with the row sum of value kRowSlot[i % 16] (none where the table says 15).
+constexpr uint64_t kRowSlot = 0xFFF8F765FF43F210ull;  // nibble i = value index held by row lane i
+
+__device__ inline float row_reduce9(const float (&g)[9], bool b3, bool b2, bool b1, bool b0) {
+  float a[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) a[j] = bfly<0x140>(g[j], j < 4 ? g[5 + j] : 0.0f, b3);  // row_mirror
+  float c[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) c[j] = bfly<0x141>(a[j], j < 2 ? a[3 + j] : 0.0f, b2);  // row_half_mirror
+  const float d0 = bfly<0x1B>(c[0], c[2], b1);                                         // quad_perm [3,2,1,0]
+  const float d1 = bfly<0x1B>(c[1], 0.0f, b1);
+  return bfly<0xB1>(d0, d1, b0);                                                        // quad_perm [1,0,3,2]
+}
+
 // Pixel of a thread inside a TILE x TILE tile: wavefront w owns quadrant w (row-major over the
 // TILE/8 x TILE/8 quadrants), lane l the pixel (l % 8, l / 8) inside it.
 template <int TILE>
@@ -53,14 +84,44 @@ __device__ inline void local_pixel(int t, int& lx, int& ly) {
   ly = (w / QPR) * 8 + (l >> 3);
 }
 
-// Quadrants of a tile whose pixel centres can lie inside the rectangle u +- eu, v +- ev
-// (u wraps around the seam).
+// Minimum over the rectangle [x0, x1] x [y0, y1] of f(x, y) = a x^2 + 2 b x y + c y^2 (positive
+// definite), with nba = -b/a and nbc = -b/c precomputed.  Float; callers add a margin that covers
+// its rounding.
+__device__ inline float rect_min_quadratic(float a, float b, float c, float nba, float nbc, float x0, float x1,
+                                           float y0, float y1) {
+  if (x0 <= 0.0f && 0.0f <= x1 && y0 <= 0.0f && 0.0f <= y1) return 0.0f;
+  float m = 3.0e38f;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const float x = e ? x1 : x0;  // vertical edge: best y = -b x / c, clamped
+    const float y = fminf(fmaxf(nbc * x, y0), y1);
+    m = fminf(m, fmaf(a * x, x, y * fmaf(2.0f * b, x, c * y)));
+    const float yy = e ? y1 : y0;  // horizontal edge
+    const float xx = fminf(fmaxf(nba * yy, x0), x1);
+    m = fminf(m, fmaf(a * xx, xx, yy * fmaf(2.0f * b, xx, c * yy)));
+  }
+  return m;
+}
+
+// Quadrants (8x8 pixel blocks) of a tile that can hold a pixel where the Gaussian reaches
+// alpha >= 1/255.  First the padded rectangle u +- eu, v +- ev; then, for quadrants that pass,
+// the minimum of the exponent's quadratic form over the quadrant's pixel-centre rectangle.  The
+// margin exceeds, tenfold or more, both the compositor's float evaluation error of the exponent
+// (rounding of products and of du, dv) and the rounding of this test, so no contributing pixel
+// is ever skipped.  Quadrants whose horizontal span reaches the +-W/2 wrap point keep the
+// rectangle test only.
 template <int TILE>
-__device__ inline uint32_t quadrant_mask(float u, float v, float eu, float ev, int tx0, int ty0, float Wf,
-                                         float half) {
+__device__ inline uint32_t quadrant_mask(const Rec& r, int tx0, int ty0, float Wf, float half) {
   constexpr int QPR = TILE / 8;
-  uint32_t mask = 0;
+  const float u = r.r0.x, v = r.r0.y, eu = r.r1.w, ev = r.r2.w;
+  // inverse covariance [[a, b], [b, c]] = 2 L^T L of the stored factor
+  const float l0 = r.r0.z, l1 = r.r0.w, l2 = r.r1.x;
+  const float a = 2.0f * l0 * l0, b = 2.0f * l0 * l1, c = 2.0f * fmaf(l1, l1, l2 * l2);
+  const float nba = -b * __builtin_amdgcn_rcpf(a), nbc = -b * __builtin_amdgcn_rcpf(c);
+  const float aa = fabsf(a), ab = fabsf(b), ac = fabsf(c);
+  const float k2 = -2.0f * r.r1.z;
   const bool all_cols = eu + 3.5f >= half;
+  uint32_t mask = 0;
 #pragma unroll
   for (int q = 0; q < QPR * QPR; ++q) {
     const float qcx = (float)(tx0 + (q % QPR) * 8 + 4);
@@ -68,7 +129,15 @@ __device__ inline uint32_t quadrant_mask(float u, float v, float eu, float ev, i
     float du = qcx - u;
     if (du >= half) du -= Wf;
     else if (du < -half) du += Wf;
-    const bool hit = fabsf(v - qcy) <= ev + 3.5f && (all_cols || fabsf(du) <= eu + 3.5f);
+    const float dy = qcy - v;
+    bool hit = fabsf(dy) <= ev + 3.5f && (all_cols || fabsf(du) <= eu + 3.5f);
+    if (hit && fabsf(du) + 4.0f < half) {
+      const float X = fabsf(du) + 3.5f, Y = fabsf(dy) + 3.5f;
+      const float tmax = fmaf(aa * X, X, Y * fmaf(2.0f * ab, X, ac * Y));
+      const float gmax = 2.0f * fmaf(aa + ab, X, (ab + ac) * Y);
+      const float margin = fmaf(1e-5f, tmax, fmaf(1e-2f, gmax, fmaf(1e-4f, k2, 1e-6f)));
+      hit = rect_min_quadratic(a, b, c, nba, nbc, du - 3.5f, du + 3.5f, dy - 3.5f, dy + 3.5f) <= k2 + margin;
+    }
     mask |= hit ? (1u << q) : 0u;
   }
   return mask;
@@ -115,7 +184,7 @@ __device__ inline void stage_batch(Stage<TILE, BATCH>& S, const uint32_t* __rest
       S.s1[e] = r.r1;
       S.s2[e] = r.r2;
       S.sid[e] = item;
-      m = quadrant_mask<TILE>(r.r0.x, r.r0.y, r.r1.w, r.r2.w, tx0, ty0, Wf, half);
+      m = quadrant_mask<TILE>(r, tx0, ty0, Wf, half);
     }
     uint32_t within[St::NQ];
 #pragma unroll
@@ -179,7 +248,8 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
       const float4 b = S.s1[k];
       const float du = wrap_du(px - a.x, Wf, half);
       const float dv = py - a.y;
-      const float power = fmaf(a.z, du * du, fmaf(a.w, du * dv, b.x * (dv * dv)));
+      const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
+      const float power = -fmaf(t1, t1, t2 * t2);
       nev += done ? 0 : 1;
       const bool ok = !done && !(power > 0.0f || power < b.z);
       if (__ballot(ok) == 0ull) continue;  // uniform
@@ -215,8 +285,10 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
   if (out_T) out_T[gp] = T;
 }
 
-// g2d layout: [9][items] = d/du, d/dv, d/da, d/db, d/dc, d/dopacity, d/dr, d/dg, d/db(colour),
-// with the inverse 2D covariance [[a, b], [b, c]].
+// g2d layout: [9][items] = d/du, d/dv, d/dS_uu, d/dS_uv, d/dS_vv, d/dopacity, d/dr, d/dg,
+// d/db(colour), where Sigma_2D = [[S_uu, S_uv], [S_uv, S_vv]] (S_uv the shared off-diagonal).
+// Accumulating w.r.t. Sigma_2D rather than its inverse keeps the sums well scaled for very
+// anisotropic footprints (no later multiplication by the inverse covariance twice).
 template <int TILE, int BATCH>
 __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, const uint2* __restrict__ ranges,
                                                                 const uint32_t* __restrict__ pair_items,
@@ -240,6 +312,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   const int x = tx0 + lx, y = ty0 + ly;
   const int lane = threadIdx.x & (kWave - 1);
   const int wq = threadIdx.x >> 6;
+  const int slot = (int)((kRowSlot >> (4 * (lane & 15))) & 0xF);
   const float px = (float)x + 0.5f, py = (float)y + 0.5f;
   const float Wf = (float)W, half = (float)W * 0.5f;
   const uint2 rg = ranges[g];
@@ -278,7 +351,8 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       const float4 b = S.s1[k];
       const float du = wrap_du(px - a.x, Wf, half);
       const float dv = py - a.y;
-      const float power = fmaf(a.z, du * du, fmaf(a.w, du * dv, b.x * (dv * dv)));
+      const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
+      const float power = -fmaf(t1, t1, t2 * t2);
       const bool ok = jrel < last && !(power > 0.0f || power < b.z);
       if (__ballot(ok) == 0ull) continue;  // uniform
       const float G = __expf(power);
@@ -296,23 +370,20 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       S1 = fmaf(c.y, wk, S1);
       S2 = fmaf(c.z, wk, S2);
       const float dpow = (ok && !clamped) ? dL_da * alpha : 0.0f;
-      const float ca = -2.0f * a.z, cb = -a.w, cc = -2.0f * b.x;
       float gq[9];
-      gq[0] = dpow * fmaf(ca, du, cb * dv);
-      gq[1] = dpow * fmaf(cb, du, cc * dv);
-      gq[2] = -0.5f * dpow * (du * du);
-      gq[3] = -dpow * (du * dv);
-      gq[4] = -0.5f * dpow * (dv * dv);
+      // with w = Sigma^-1 d = 2 L^T (t1, t2): d power / d(u, v) = w, d power / d Sigma_2D = w w^T / 2
+      const float wx = 2.0f * a.z * t1, wy = 2.0f * fmaf(a.w, t1, b.x * t2);
+      gq[0] = dpow * wx;
+      gq[1] = dpow * wy;
+      gq[2] = 0.5f * gq[0] * wx;
+      gq[3] = gq[0] * wy;
+      gq[4] = 0.5f * gq[1] * wy;
       gq[5] = (ok && !clamped) ? dL_da * G : 0.0f;
       gq[6] = wk * dl0;
       gq[7] = wk * dl1;
       gq[8] = wk * dl2;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) gq[q] = lane63(wave_sum_to_lane63(gq[q]));
-      if (lane == 0) {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) atomicAdd(&acc[q][k], gq[q]);
-      }
+      const float rs = row_reduce9(gq, lane & 8, lane & 4, lane & 2, lane & 1);
+      if (slot < 9) atomicAdd(&acc[slot][k], rs);  // 9 lanes per row, 4 rows: one LDS atomic
     }
     __syncthreads();
     for (int t = threadIdx.x; t < cnt; t += N) {

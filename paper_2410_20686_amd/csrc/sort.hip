@@ -87,32 +87,43 @@ __global__ __launch_bounds__(256) void radix_digit_scan_kernel(uint32_t* __restr
 }
 
 // Stable scatter of one digit pass.  vin == nullptr means the values are the input positions.
+// Phase 1 ranks the block's keys within their digit (rounds of 256 keys in input order; inside a
+// round, wavefront multi-split by 8 ballots, then an exclusive prefix over the wavefronts).
+// Phase 2 places the keys digit-sorted in LDS; phase 3 writes them out in that order, so
+// consecutive threads store consecutive addresses of each digit's output run.
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot, int nblocks) {
-  __shared__ uint32_t base[256];
+  __shared__ uint32_t s_key[kSortBlockItems];
+  __shared__ uint32_t s_val[kSortBlockItems];
+  __shared__ uint32_t cnt[256];      // running per-digit count inside the block
+  __shared__ uint32_t lstart[256];   // local (block) start of each digit
+  __shared__ uint32_t gstart[256];   // global start of each digit for this block
   __shared__ uint32_t wcnt[4][256];
   __shared__ uint32_t lds[4];
   const int t = threadIdx.x, lane = t & (kWave - 1), wave = t >> 6;
   const uint32_t n = active_count(n_dev, n_host);
   const uint32_t start = blockIdx.x * (uint32_t)kSortBlockItems;
   if (start >= n) return;  // uniform across the block
-  // global start of each digit for this block
+  const uint32_t nb = min((uint32_t)kSortBlockItems, n - start);
   uint32_t total;
   const uint32_t dt = digit_tot[t];
   const uint32_t incl = block_incl_scan256(dt, lds, total);
-  base[t] = incl - dt + hist[t * nblocks + blockIdx.x];
+  gstart[t] = incl - dt + hist[t * nblocks + blockIdx.x];
+  cnt[t] = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) wcnt[w][t] = 0;
   __syncthreads();
   const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  uint32_t key[kSortIpt], val[kSortIpt], rank[kSortIpt];
+#pragma unroll
   for (int r = 0; r < kSortIpt; ++r) {
-    const uint32_t idx = start + r * kSortThreads + t;
-    const bool valid = idx < n;
-    const uint32_t key = valid ? kin[idx] : 0u;
-    const uint32_t val = valid ? (vin ? vin[idx] : idx) : 0u;
-    const uint32_t d = (key >> shift) & 255u;
+    const uint32_t li = r * kSortThreads + t;
+    const bool valid = li < nb;
+    key[r] = valid ? kin[start + li] : 0u;
+    val[r] = valid ? (vin ? vin[start + li] : start + li) : 0u;
+    const uint32_t d = (key[r] >> shift) & 255u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -120,28 +131,52 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
       const uint64_t bb = __ballot(bit);
       peers &= bit ? bb : ~bb;
     }
-    const uint32_t rank = __popcll(peers & lanes_below);
-    if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+    const uint32_t wr = __popcll(peers & lanes_below);
+    if (valid && wr == 0) wcnt[wave][d] = __popcll(peers);
     __syncthreads();
     {
-      const uint32_t b0 = base[t];
+      const uint32_t b0 = cnt[t];
       const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
       wcnt[0][t] = b0;
       wcnt[1][t] = b0 + c0;
       wcnt[2][t] = b0 + c0 + c1;
       wcnt[3][t] = b0 + c0 + c1 + c2;
-      base[t] = b0 + c0 + c1 + c2 + c3;
+      cnt[t] = b0 + c0 + c1 + c2 + c3;
     }
     __syncthreads();
-    if (valid) {
-      const uint32_t pos = wcnt[wave][d] + rank;
-      kout[pos] = key;
-      vout[pos] = val;
-    }
+    rank[r] = valid ? wcnt[wave][d] + wr : 0u;
     __syncthreads();
 #pragma unroll
     for (int w = 0; w < 4; ++w) wcnt[w][t] = 0;
     __syncthreads();
+  }
+  // local digit starts
+  const uint32_t c = cnt[t];
+  const uint32_t ci = block_incl_scan256(c, lds, total);
+  lstart[t] = ci - c;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortIpt; ++r) {
+    const uint32_t li = r * kSortThreads + t;
+    if (li < nb) {
+      const uint32_t p = lstart[(key[r] >> shift) & 255u] + rank[r];
+      s_key[p] = key[r];
+      s_val[p] = val[r];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortIpt; ++r) {
+    const uint32_t i = r * kSortThreads + t;
+    if (i < nb) {
+      const uint32_t k = s_key[i];
+      const uint32_t d = (k >> shift) & 255u;
+      const uint32_t pos = gstart[d] + (i - lstart[d]);
+      if (pos < n) {  // always true for a consistent histogram; keeps a corrupted one in bounds
+        kout[pos] = k;
+        vout[pos] = s_val[i];
+      }
+    }
   }
 }
 

@@ -25,7 +25,25 @@ def _small_cases():
     sc2 = scenes.roaming_scene(4099, 3, seed=32)
     cams2 = scenes.identity_cameras(512, 256)
     cases.append(("roam_seam", sc2, cams2, settings(bg=(0.2, 0.1, 0.05))))
+    cases.append(("needles", _needle_scene(), scenes.identity_cameras(512, 256), settings(dilation=0.1)))
     return cases
+
+
+def _needle_scene(n=3003, seed=33):
+    """Strongly anisotropic Gaussians (one long axis), many near the poles and on the seam:
+    the hardest case for footprint rectangles and per-quadrant culling margins."""
+    from tests._util import make_scene
+    rng = np.random.default_rng(seed)
+    el = np.concatenate([rng.uniform(-1.45, 1.45, n // 2), rng.choice([-1, 1], n - n // 2) * rng.uniform(1.2, 1.5, n - n // 2)])
+    az = rng.uniform(-np.pi, np.pi, n)
+    az[: n // 10] = np.pi + rng.uniform(-0.05, 0.05, n // 10)
+    r = rng.uniform(1.5, 6.0, n)
+    means = np.stack([r * np.cos(el) * np.sin(az), -r * np.sin(el), r * np.cos(el) * np.cos(az)], axis=1)
+    scales = np.stack([rng.uniform(1e-3, 5e-3, n), rng.uniform(1e-3, 5e-3, n), rng.uniform(0.05, 0.8, n)], axis=1)
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    sh = rng.uniform(-1.5, 1.5, (3, n))
+    return make_scene(means, scales, quats=q, opac=rng.uniform(0.05, 0.99, n), sh=sh, dtype=np.float32)
 
 
 CASES = _small_cases()
@@ -43,10 +61,17 @@ def test_records_match_oracle(case):
     k = kept
     np.testing.assert_array_equal(rec[..., 7][k].view(np.uint32), rows[..., O.F_DEPTH_BITS][k].astype(np.uint32))
     f32 = lambda x: x.astype(np.float32)
+    # exponent factor from the oracle's FP64 Sigma_2D (the record stores l0, l1, l2 with
+    # -d^T Sigma^-1 d / 2 = -((l0 du + l1 dv)^2 + (l2 dv)^2))
+    suu, suv, svv = (rows[..., O.F_COV2 + j] for j in range(3))
+    with np.errstate(all="ignore"):
+        det = suu * svv - suv * suv
+        l0 = np.sqrt(svv / (2.0 * det))
+        l1 = -suv / (2.0 * det * l0)
+        l2 = 1.0 / np.sqrt(2.0 * svv)
     expect = {
         0: f32(rows[..., O.F_U]), 1: f32(rows[..., O.F_V]),
-        2: np.float32(-0.5) * f32(rows[..., O.F_CONIC]), 3: -f32(rows[..., O.F_CONIC + 1]),
-        4: np.float32(-0.5) * f32(rows[..., O.F_CONIC + 2]), 5: f32(rows[..., O.F_OPAC]),
+        2: f32(l0), 3: f32(l1), 4: f32(l2), 5: f32(rows[..., O.F_OPAC]),
         6: f32(rows[..., O.F_PMIN]), 8: f32(rows[..., O.F_RGB]), 9: f32(rows[..., O.F_RGB + 1]),
         10: f32(rows[..., O.F_RGB + 2]),
     }
@@ -112,7 +137,12 @@ def test_backward_matches_oracle(case):
     dL = _masked_upstream(cams, fwd["margin"], seed=1000)
     res = G.run_gpu(sc, cams, st, dL=dL)
     ref = O.backward(sc, cams, st, dL, mode=32)
-    rep = G.assert_grads_close(res["grads"], ref)
+    # Needles (axis ratios up to ~500:1): the long-axis scale gradient and the rotation gradient
+    # contract the 3D covariance gradient along the long axis, a cancellation of terms ~1e5
+    # times larger, so float rounding of the per-pixel 2D gradients (~1e-7) shows up there at
+    # ~1e-3; those are bounded by 1e-4 of the same Gaussian's largest component.
+    extra = {"scales": 1e-4, "quats": 1e-4} if name == "needles" else None
+    rep = G.assert_grads_close(res["grads"], ref, per_gaussian_floor=extra)
     print(name, rep)
 
 
