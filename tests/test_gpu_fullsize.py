@@ -1,0 +1,84 @@
+"""Parity at the workloads' full sizes, in the launch configuration the benchmark times (all
+views batched, tile 16, batch 256): bit-exact key lists, colours at sampled pixels against the
+brute-force oracle, and every parameter gradient under an upstream gradient that is non-zero
+only on the sampled pixels (so the oracle evaluates those pixels only, while the GPU runs the
+whole image)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2410_20686_amd import scenes
+from tests import _gpu as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _view_offsets(cams):
+    off = [0]
+    for w, h in cams.wh:
+        off.append(off[-1] + int(w) * int(h))
+    return off
+
+
+def _sampled(res, cams, pix):
+    off = _view_offsets(cams)
+    rgb = np.zeros((len(pix), 3))
+    T = np.zeros(len(pix))
+    for k, (v, x, y) in enumerate(pix):
+        w, h = int(cams.wh[v, 0]), int(cams.wh[v, 1])
+        p = int(y) * w + int(x)
+        for c in range(3):
+            rgb[k, c] = res["rgb"][3 * off[v] + c * w * h + p]
+        T[k] = res["T"][off[v] + p]
+    return rgb, T
+
+
+def _check(sc, cams, st, n_pix, seed, key_views=None):
+    dL, pix = scenes.sparse_upstream_gradient(cams, seed, n_pix)
+    ref = O.render(sc, cams, st, mode=32, pix=pix)
+    ok = G.strict_pixels(ref["margin"])
+    # upstream gradient only on strictly comparable sampled pixels
+    off = _view_offsets(cams)
+    gpix = np.zeros((len(pix), 3))
+    for k, (v, x, y) in enumerate(pix):
+        w, h = int(cams.wh[v, 0]), int(cams.wh[v, 1])
+        p = int(y) * w + int(x)
+        for c in range(3):
+            i = 3 * off[v] + c * w * h + p
+            if not ok[k]:
+                dL[i] = 0.0
+            gpix[k, c] = dL[i]
+    res = G.run_gpu(sc, cams, st, dL=dL, return_rast=key_views is not None)
+    rgb, T = _sampled(res, cams, pix)
+    assert np.abs(rgb - ref["rgb"])[ok].max() <= G.RGB_ATOL
+    assert np.abs(T - ref["T"])[ok].max() <= G.RGB_ATOL
+    assert (~ok).sum() <= max(2, 0.01 * len(pix))
+    gref = O.backward(sc, cams, st, gpix, mode=32, pix=pix)
+    G.assert_grads_close(res["grads"], gref)
+    if key_views is not None:
+        sub = scenes.Cameras(np.ascontiguousarray(cams.cams[:key_views]), np.ascontiguousarray(cams.wh[:key_views]))
+        okeys, ovals = O.keys(sc, sub, st)
+        keys, gauss = res["rast"].keys()
+        keys = keys.cpu().numpy().view(np.uint64)
+        gauss = gauss.cpu().numpy().astype(np.uint32)
+        plan = res["rast"].plan
+        sel = (keys >> np.uint64(32)) < np.uint64(plan.tile_base[key_views])
+        np.testing.assert_array_equal(keys[sel], okeys)
+        np.testing.assert_array_equal(gauss[sel], ovals)
+        if key_views == cams.n_views:
+            assert res["status"]["n_pairs"] == len(okeys)
+
+
+def test_cfg2_roaming_500k_4096x2048():
+    sc, cams, st = scenes.config("cfg2")
+    _check(sc, cams, st, n_pix=768, seed=1002, key_views=1)
+
+
+def test_M_500k_8x2048x1024_batched():
+    sc, cams, st = scenes.config("M")
+    _check(sc, cams, st, n_pix=96, seed=1005, key_views=2)
+
+
+def test_cfg3_1M_8x2048x1024_batched():
+    sc, cams, st = scenes.config("cfg3")
+    _check(sc, cams, st, n_pix=64, seed=1003)
