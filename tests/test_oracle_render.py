@@ -245,3 +245,45 @@ def test_fp32_and_fp64_modes_agree():
     ok = (a["margin"] > 1e-3) & (b["margin"] > 1e-3)
     okc = np.tile(ok, 3)
     assert np.abs(a["rgb"] - b["rgb"])[okc].max() < 1e-5
+
+
+def test_backward_fd_uneven_16_views():
+    """cfg4 shape (16 views of three sizes, Haar-random rotations, roaming scene): the analytic
+    FP64 gradient equals FP64 central differences over 64 random parameters."""
+    sc = scenes.roaming_scene(400, 3, seed=4, r_range=(2.0, 6.0)).as_f64()
+    cams = scenes.uneven_cameras(16, seed=4, sizes=((64, 32), (128, 64), (256, 128)))
+    st = settings(bg=(0.05, 0.1, 0.15))
+    dL = scenes.upstream_gradient(cams, 1004).astype(np.float64)
+    g = O.backward(sc, cams, st, dL, mode=64)
+    rng = np.random.default_rng(44)
+    groups = [("means", 3), ("scales", 3), ("quats", 4), ("opacities", 1), ("sh", 48)]
+    visible = np.nonzero(np.abs(g["opacities"]) > 0)[0]
+    checked = tries = 0
+    while checked < 64:
+        tries += 1
+        assert tries < 400
+        name, rows = groups[int(rng.integers(0, len(groups)))]
+        i = int(rng.choice(visible))
+        c = int(rng.integers(0, rows))
+        base = getattr(sc, name)
+        x0 = base[i] if name == "opacities" else base[c, i]
+        h = 1e-6 * max(1.0, abs(x0))
+
+        def loss(delta):
+            s = sc.copy()
+            arr = getattr(s, name)
+            if name == "opacities":
+                arr[i] += delta
+            else:
+                arr[c, i] += delta
+            r = O.render(s, cams, st, mode=64)
+            return float(np.dot(r["rgb"], dL)), r["sig"]
+
+        lp, sp = loss(h)
+        lm, sm = loss(-h)
+        if not np.array_equal(sp, sm):
+            continue
+        fd = (lp - lm) / (2 * h)
+        an = g[name][i] if name == "opacities" else g[name][c, i]
+        assert abs(fd - an) <= 1e-5 * abs(an) + 1e-7 * np.abs(g[name]).max(), (name, i, c, fd, an)
+        checked += 1
