@@ -50,7 +50,7 @@ enum {
 #define ODGS_STATUS_OVERFLOW 1 /* more Gaussian-tile pairs than plan->pair_capacity */
 
 /* Rasterization settings.  The paper fixes none of these constants; the defaults follow the
- * 3DGS rasterizer it builds on (Sec. 3.2, "can be used as a typical 3DGS"). */
+ * 3DGS rasterizer the method builds on (Sec. 3.2). */
 typedef struct odgs_settings {
   int32_t tile;     /* tile edge in pixels: 8, 16 or 32; every W and H must be a multiple */
   int32_t batch;    /* reserved, 0 */
@@ -103,6 +103,32 @@ typedef struct odgs_plan {
 int odgs_plan_init(odgs_plan* plan /*[host]*/, int64_t n, int32_t sh_degree, int32_t n_views, const int32_t* wh /*[host]*/,
                    const odgs_settings* s /*[host]*/, int64_t pair_capacity);
 
+/* Densification statistics (Sec. 3.3), optionally accumulated by the reverse projection stage
+ * for every (Gaussian, view) that is visible (kept by the culling tests and covering at least
+ * one tile).  All three arrays have n entries and are ADDED to, so they can gather several
+ * steps; the caller clears them (e.g. after odgs_densify).
+ *   grad_sum += |(dL/du * W/2, dL/dv * H/2)|: the length of the gradient of the loss with
+ *               respect to the Gaussian's 2D mean in normalised image units;
+ *   tau_sum  += tau_min + (1 - cos theta) (tau_max - tau_min), theta the elevation of the mean
+ *               seen from that view (the paper's elevation-dependent threshold; the paper uses
+ *               tau_min = 2e-5, tau_max = 1e-4);
+ *   count    += 1. */
+typedef struct odgs_densify_acc {
+  float* grad_sum;
+  float* tau_sum;
+  int32_t* count;
+  float tau_min, tau_max;
+} odgs_densify_acc;
+
+/* Parameters of one clone / split / prune step (the 3DGS rules the method keeps, with the
+ * threshold of Sec. 3.3 and percent_dense = 1e-3 of the paper's implementation details). */
+typedef struct odgs_densify_params {
+  float extent;          /* scene extent: the clone / split boundary is percent_dense * extent */
+  float percent_dense;   /* e.g. 1e-3 */
+  float min_opacity;     /* prune below this opacity, e.g. 0.005 */
+  float max_scale_frac;  /* > 0: also prune a largest scale above max_scale_frac * extent; 0: off */
+} odgs_densify_params;
+
 /* Bytes of device workspace a plan needs (256-byte aligned base pointer required). */
 size_t odgs_workspace_bytes(const odgs_plan* plan /*[host]*/);
 
@@ -133,24 +159,48 @@ int odgs_render_fwd(const odgs_plan* plan, void* ws, size_t ws_bytes, float* out
  * views (reverse compositing, then the adjoint of the tangent-plane projection and of the SH
  * colour; Sec. 3.2 and Appendix C).  The parameters must be those given to odgs_preprocess.
  * The five gradient arrays (same shapes as the parameters) are OVERWRITTEN.
- * Equivalent to odgs_composite_bwd followed by odgs_project_bwd. */
+ * Equivalent to odgs_composite_bwd followed by odgs_project_bwd (acc as there). */
 int odgs_render_bwd(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
                     const float* opacities, const float* sh, const float* cams, void* ws, size_t ws_bytes,
                     const float* dL_drgb, float* d_means, float* d_scales, float* d_quats, float* d_opacities,
-                    float* d_sh, void* stream);
+                    float* d_sh, const odgs_densify_acc* acc, void* stream);
 
 /* First backward stage: reverse compositing of every pixel of every view (Eq. alphablending
- * differentiated), accumulating per-(Gaussian, view) gradients of the ERP position, the inverse
- * 2D covariance, the opacity and the colour into the workspace (which odgs_bin_sort and
- * odgs_project_bwd leave cleared).  dL_drgb has the layout of out_rgb. */
+ * differentiated), accumulating per-(Gaussian, view) gradients of the ERP position, the 2D
+ * covariance Sigma_2D (dilation included), the opacity and the colour into the workspace (which
+ * odgs_bin_sort and odgs_project_bwd leave cleared).  dL_drgb has the layout of out_rgb. */
 int odgs_composite_bwd(const odgs_plan* plan, void* ws, size_t ws_bytes, const float* dL_drgb, void* stream);
 
 /* Second backward stage: adjoint of the per-(Gaussian, view) projection (Eq. omni_Jacobian and
  * its derivative, Sigma = R S S^T R^T with the quaternion normalisation, SH colour), summed over
- * views into the five gradient arrays (OVERWRITTEN); clears the workspace's 2D gradients. */
+ * views into the five gradient arrays (OVERWRITTEN); clears the workspace's 2D gradients.
+ * acc [host] (may be NULL): densification statistics to accumulate, see odgs_densify_acc. */
 int odgs_project_bwd(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
                      const float* opacities, const float* sh, const float* cams, void* ws, size_t ws_bytes,
-                     float* d_means, float* d_scales, float* d_quats, float* d_opacities, float* d_sh, void* stream);
+                     float* d_means, float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
+                     const odgs_densify_acc* acc, void* stream);
+
+/* Device workspace bytes odgs_densify needs for n Gaussians (256-byte aligned base). */
+size_t odgs_densify_workspace_bytes(int64_t n);
+
+/* One densification step (Sec. 3.3): Gaussian i is selected when count[i] > 0 and
+ * grad_sum[i] >= tau_sum[i] (its mean gradient reaches its mean threshold; FP32 compare).
+ * Selected Gaussians whose largest scale is <= percent_dense * extent are cloned; the others are
+ * split into two children at m + R(q) (s * xi_c) with scales s / 1.6 and all other parameters
+ * copied, xi_c = noise[c][3][n] (c = 0, 1: standard normal draws supplied by the caller), and
+ * the parent is removed.  Every resulting Gaussian with opacity < min_opacity (or, if
+ * max_scale_frac > 0, largest scale > max_scale_frac * extent) is pruned.
+ * Inputs are the parameter arrays (layouts as above, n Gaussians) and the statistics of
+ * odgs_densify_acc.  Outputs have the same layouts with column stride `capacity` (>= 2 n, the
+ * largest possible result): out_means [3][capacity], ..., out_sh [K*3][capacity]; out_src
+ * [capacity] the parent index of each output; out_counts [4] (int64, device) the numbers of
+ * surviving originals, clones, first children and second children, which appear in that order,
+ * each group in parent order.  Entries past the total are left untouched. */
+int odgs_densify(int64_t n, int32_t sh_degree, const float* means, const float* scales, const float* quats,
+                 const float* opacities, const float* sh, const float* grad_sum, const float* tau_sum,
+                 const int32_t* count, const float* noise, const odgs_densify_params* dp /*[host]*/,
+                 int64_t capacity, float* out_means, float* out_scales, float* out_quats, float* out_opacities,
+                 float* out_sh, int32_t* out_src, int64_t* out_counts, void* ws, size_t ws_bytes, void* stream);
 
 /* Byte offset of the odgs_status record inside the workspace. */
 size_t odgs_status_offset(const odgs_plan* plan /*[host]*/);
@@ -163,9 +213,10 @@ size_t odgs_plan_size(void);
 
 /* ---- inspection (tests): copy internal results out of the workspace ---------------------- */
 
-/* Per-item FP32 record [items][12]: u, v, A, B, C, opacity, p_min, depth, r, g, b, tile count,
- * where the compositor's exponent is A du^2 + B du dv + C dv^2 (A = -a/2, B = -b, C = -c/2
- * for the inverse covariance [[a, b], [b, c]]); culled items have tile count 0. */
+/* Per-item FP32 record [items][12]: u, v, l0, l1, l2, opacity, p_min, depth, r, g, b, tile count,
+ * where the compositor's exponent -d^T Sigma_2D^-1 d / 2 is evaluated as
+ * -((l0 du + l1 dv)^2 + (l2 dv)^2) (a Cholesky factor of Sigma_2D^-1 / 2); culled items have
+ * tile count 0. */
 int odgs_debug_records(const odgs_plan* plan, const void* ws, float* out, void* stream);
 
 /* Per-pixel int32 [pixels][4] of the last odgs_render_fwd: list position after the last

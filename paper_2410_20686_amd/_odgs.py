@@ -18,6 +18,7 @@ STATUS_OVERFLOW = 1
 
 EXPORTS = ("odgs_plan_init", "odgs_workspace_bytes", "odgs_preprocess", "odgs_bin_sort", "odgs_render_fwd",
            "odgs_render_bwd", "odgs_composite_bwd", "odgs_project_bwd", "odgs_status_offset", "odgs_strerror",
+           "odgs_densify", "odgs_densify_workspace_bytes",
            "odgs_plan_size", "odgs_debug_records", "odgs_debug_keys", "odgs_debug_pixel_counts")
 
 
@@ -25,6 +26,16 @@ class Settings(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("batch", ctypes.c_int32), ("near_r", ctypes.c_float),
                 ("far_r", ctypes.c_float), ("dilation", ctypes.c_float), ("pole_eps", ctypes.c_float),
                 ("bg", ctypes.c_float * 3), ("flags", ctypes.c_int32)]
+
+
+class DensifyAcc(ctypes.Structure):
+    _fields_ = [("grad_sum", ctypes.c_void_p), ("tau_sum", ctypes.c_void_p), ("count", ctypes.c_void_p),
+                ("tau_min", ctypes.c_float), ("tau_max", ctypes.c_float)]
+
+
+class DensifyParams(ctypes.Structure):
+    _fields_ = [("extent", ctypes.c_float), ("percent_dense", ctypes.c_float), ("min_opacity", ctypes.c_float),
+                ("max_scale_frac", ctypes.c_float)]
 
 
 class Status(ctypes.Structure):
@@ -73,12 +84,16 @@ def lib():
         L.odgs_bin_sort.restype = c_i32
         L.odgs_render_fwd.argtypes = [pp, P, c_sz, P, P, P]
         L.odgs_render_fwd.restype = c_i32
-        L.odgs_render_bwd.argtypes = [pp, P, P, P, P, P, P, P, c_sz, P, P, P, P, P, P, P]
+        L.odgs_render_bwd.argtypes = [pp, P, P, P, P, P, P, P, c_sz, P, P, P, P, P, P, P, P]
         L.odgs_render_bwd.restype = c_i32
         L.odgs_composite_bwd.argtypes = [pp, P, c_sz, P, P]
         L.odgs_composite_bwd.restype = c_i32
-        L.odgs_project_bwd.argtypes = [pp, P, P, P, P, P, P, P, c_sz, P, P, P, P, P, P]
+        L.odgs_project_bwd.argtypes = [pp, P, P, P, P, P, P, P, c_sz, P, P, P, P, P, P, P]
         L.odgs_project_bwd.restype = c_i32
+        L.odgs_densify_workspace_bytes.argtypes = [c_i64]
+        L.odgs_densify_workspace_bytes.restype = c_sz
+        L.odgs_densify.argtypes = [c_i64, c_i32] + [P] * 9 + [ctypes.POINTER(DensifyParams), c_i64] + [P] * 8 + [c_sz, P]
+        L.odgs_densify.restype = c_i32
         L.odgs_debug_pixel_counts.argtypes = [pp, P, P, P]
         L.odgs_debug_pixel_counts.restype = c_i32
         L.odgs_strerror.argtypes = [c_i32]
@@ -143,10 +158,15 @@ def odgs_render_fwd(plan, ws, ws_bytes, out_rgb, out_T, stream):
     _check(lib().odgs_render_fwd(ctypes.byref(plan), ws, ws_bytes, out_rgb, out_T, stream), "odgs_render_fwd")
 
 
+def _acc_ref(acc):
+    return None if acc is None else ctypes.byref(acc)
+
+
 def odgs_render_bwd(plan, means, scales, quats, opac, sh, cams, ws, ws_bytes, dL, d_means, d_scales, d_quats,
-                    d_opac, d_sh, stream):
+                    d_opac, d_sh, acc, stream):
+    """acc: DensifyAcc or None."""
     _check(lib().odgs_render_bwd(ctypes.byref(plan), means, scales, quats, opac, sh, cams, ws, ws_bytes, dL, d_means,
-                                 d_scales, d_quats, d_opac, d_sh, stream), "odgs_render_bwd")
+                                 d_scales, d_quats, d_opac, d_sh, _acc_ref(acc), stream), "odgs_render_bwd")
 
 
 def odgs_composite_bwd(plan, ws, ws_bytes, dL, stream):
@@ -154,9 +174,21 @@ def odgs_composite_bwd(plan, ws, ws_bytes, dL, stream):
 
 
 def odgs_project_bwd(plan, means, scales, quats, opac, sh, cams, ws, ws_bytes, d_means, d_scales, d_quats, d_opac,
-                     d_sh, stream):
+                     d_sh, acc, stream):
+    """acc: DensifyAcc or None."""
     _check(lib().odgs_project_bwd(ctypes.byref(plan), means, scales, quats, opac, sh, cams, ws, ws_bytes, d_means,
-                                  d_scales, d_quats, d_opac, d_sh, stream), "odgs_project_bwd")
+                                  d_scales, d_quats, d_opac, d_sh, _acc_ref(acc), stream), "odgs_project_bwd")
+
+
+def odgs_densify_workspace_bytes(n: int) -> int:
+    return int(lib().odgs_densify_workspace_bytes(int(n)))
+
+
+def odgs_densify(n, sh_degree, means, scales, quats, opac, sh, grad_sum, tau_sum, count, noise, params: DensifyParams,
+                 capacity, out_means, out_scales, out_quats, out_opac, out_sh, out_src, out_counts, ws, ws_bytes, stream):
+    _check(lib().odgs_densify(int(n), int(sh_degree), means, scales, quats, opac, sh, grad_sum, tau_sum, count, noise,
+                              ctypes.byref(params), int(capacity), out_means, out_scales, out_quats, out_opac, out_sh,
+                              out_src, out_counts, ws, ws_bytes, stream), "odgs_densify")
 
 
 def odgs_debug_pixel_counts(plan, ws, out, stream):

@@ -162,7 +162,8 @@ int odgs_composite_bwd(const odgs_plan* plan, void* ws, size_t ws_bytes, const f
 
 int odgs_project_bwd(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
                      const float* opacities, const float* sh, const float* cams, void* ws, size_t ws_bytes,
-                     float* d_means, float* d_scales, float* d_quats, float* d_opacities, float* d_sh, void* stream) {
+                     float* d_means, float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
+                     const odgs_densify_acc* acc, void* stream) {
   int rc = check_ws(plan, ws, ws_bytes);
   if (rc != ODGS_OK) return rc;
   rc = check_params(plan, means, scales, quats, opacities, sh, cams);
@@ -171,15 +172,47 @@ int odgs_project_bwd(const odgs_plan* plan, const float* means, const float* sca
     float* outs[5] = {d_means, d_scales, d_quats, d_opacities, d_sh};
     for (float* q : outs)
       if (!q || !aligned(q, 4)) return ODGS_EINVAL;
+    if (acc) {
+      if (!acc->grad_sum || !acc->tau_sum || !acc->count) return ODGS_EINVAL;
+      if (!aligned(acc->grad_sum, 4) || !aligned(acc->tau_sum, 4) || !aligned(acc->count, 4)) return ODGS_EINVAL;
+      if (!std::isfinite(acc->tau_min) || !std::isfinite(acc->tau_max)) return ODGS_EINVAL;
+    }
   }
   return hip_status(launch_preprocess_bwd(plan, means, scales, quats, opacities, sh, cams, ws, d_means, d_scales,
-                                          d_quats, d_opacities, d_sh, static_cast<hipStream_t>(stream)));
+                                          d_quats, d_opacities, d_sh, acc, static_cast<hipStream_t>(stream)));
+}
+
+size_t odgs_densify_workspace_bytes(int64_t n) { return n < 0 ? 0 : densify_workspace_bytes(n); }
+
+int odgs_densify(int64_t n, int32_t sh_degree, const float* means, const float* scales, const float* quats,
+                 const float* opacities, const float* sh, const float* grad_sum, const float* tau_sum,
+                 const int32_t* count, const float* noise, const odgs_densify_params* dp, int64_t capacity,
+                 float* out_means, float* out_scales, float* out_quats, float* out_opacities, float* out_sh,
+                 int32_t* out_src, int64_t* out_counts, void* ws, size_t ws_bytes, void* stream) {
+  if (n < 0 || n >= ((int64_t)1 << 30) || sh_degree < 0 || sh_degree > 3 || !dp) return ODGS_EINVAL;
+  if (!out_counts || !aligned(out_counts, 8) || !ws || !aligned(ws, 256)) return ODGS_EINVAL;
+  if (capacity < 2 * n) return ODGS_EINVAL;
+  if (!std::isfinite(dp->extent) || !std::isfinite(dp->percent_dense) || !std::isfinite(dp->min_opacity) ||
+      !std::isfinite(dp->max_scale_frac) || dp->max_scale_frac < 0.0f)
+    return ODGS_EINVAL;
+  if (ws_bytes < densify_workspace_bytes(n)) return ODGS_ENOSPACE;
+  if (n > 0) {
+    const void* in[10] = {means, scales, quats, opacities, sh, grad_sum, tau_sum, count, noise, nullptr};
+    for (int k = 0; k < 9; ++k)
+      if (!in[k] || !aligned(in[k], 4)) return ODGS_EINVAL;
+    const void* out[6] = {out_means, out_scales, out_quats, out_opacities, out_sh, out_src};
+    for (const void* q : out)
+      if (!q || !aligned(q, 4)) return ODGS_EINVAL;
+  }
+  return hip_status(launch_densify(n, sh_degree, means, scales, quats, opacities, sh, grad_sum, tau_sum, count, noise,
+                                   *dp, capacity, out_means, out_scales, out_quats, out_opacities, out_sh, out_src,
+                                   out_counts, ws, static_cast<hipStream_t>(stream)));
 }
 
 int odgs_render_bwd(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
                     const float* opacities, const float* sh, const float* cams, void* ws, size_t ws_bytes,
                     const float* dL_drgb, float* d_means, float* d_scales, float* d_quats, float* d_opacities,
-                    float* d_sh, void* stream) {
+                    float* d_sh, const odgs_densify_acc* acc, void* stream) {
   int rc = check_ws(plan, ws, ws_bytes);
   if (rc != ODGS_OK) return rc;
   rc = check_params(plan, means, scales, quats, opacities, sh, cams);
@@ -188,7 +221,7 @@ int odgs_render_bwd(const odgs_plan* plan, const float* means, const float* scal
   rc = odgs_composite_bwd(plan, ws, ws_bytes, dL_drgb, stream);
   if (rc != ODGS_OK) return rc;
   return odgs_project_bwd(plan, means, scales, quats, opacities, sh, cams, ws, ws_bytes, d_means, d_scales, d_quats,
-                          d_opacities, d_sh, stream);
+                          d_opacities, d_sh, acc, stream);
 }
 
 const char* odgs_strerror(int code) {

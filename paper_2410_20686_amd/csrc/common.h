@@ -73,7 +73,14 @@ hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float
 hipError_t launch_render_bwd(const odgs_plan* p, void* ws, const float* dL_drgb, hipStream_t st);
 hipError_t launch_preprocess_bwd(const odgs_plan* p, const float* means, const float* scales, const float* quats,
                                  const float* opac, const float* sh, const float* cams, void* ws, float* d_means,
-                                 float* d_scales, float* d_quats, float* d_opac, float* d_sh, hipStream_t st);
+                                 float* d_scales, float* d_quats, float* d_opac, float* d_sh,
+                                 const odgs_densify_acc* acc, hipStream_t st);
+hipError_t launch_densify(int64_t n, int32_t sh_degree, const float* means, const float* scales, const float* quats,
+                          const float* opac, const float* sh, const float* grad_sum, const float* tau_sum,
+                          const int32_t* count, const float* noise, const odgs_densify_params& dp, int64_t capacity,
+                          float* out_means, float* out_scales, float* out_quats, float* out_opac, float* out_sh,
+                          int32_t* out_src, int64_t* out_counts, void* ws, hipStream_t st);
+size_t densify_workspace_bytes(int64_t n);
 hipError_t launch_fill_u32(uint32_t* ptr, uint32_t value, int64_t n, hipStream_t st);
 hipError_t launch_status_reset(const odgs_plan* p, void* ws, hipStream_t st);
 hipError_t launch_debug_records(const odgs_plan* p, const void* ws, float* out, hipStream_t st);

@@ -329,12 +329,21 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
 // b) with Sigma_2D = [[S_uu, S_uv], [S_uv, S_vv]] (S_uv the shared off-diagonal, dilation
 // included).  Sums over views; writes (overwrites) the parameter gradients.
 // ---------------------------------------------------------------------------------------------
-template <int K>
+// Densification statistics (Sec. 3.3) gathered while the 2D gradients are consumed.
+struct DensAcc {
+  float* grad_sum;
+  float* tau_sum;
+  int32_t* count;
+  double tau_min, tau_max;
+};
+
+template <int K, bool STATS>
 __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     int64_t n, const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
     const float* __restrict__ opac, const float* __restrict__ sh, const float* __restrict__ cams, ViewTable vt, Params P,
     const uint32_t* __restrict__ count, float* __restrict__ g2d, int64_t items, float* __restrict__ d_means,
-    float* __restrict__ d_scales, float* __restrict__ d_quats, float* __restrict__ d_opac, float* __restrict__ d_sh) {
+    float* __restrict__ d_scales, float* __restrict__ d_quats, float* __restrict__ d_opac, float* __restrict__ d_sh,
+    DensAcc dacc) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double m[3], s[3], q[4];
@@ -356,6 +365,8 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
   double gsh[K * 3];
 #pragma unroll
   for (int k = 0; k < K * 3; ++k) gsh[k] = 0.0;
+  double st_grad = 0.0, st_tau = 0.0;
+  int st_count = 0;
 
   for (int v = 0; v < vt.n_views; ++v) {
     const int64_t item = (int64_t)v * n + i;
@@ -366,6 +377,21 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     for (int k = 0; k < 9; ++k) {
       g[k] = (double)g2d[(int64_t)k * items + item];
       any = any || g[k] != 0.0;
+    }
+    if (STATS) {
+      // visible in this view: |dL/d(u, v)| in normalised image units, and the threshold at the
+      // elevation theta of the mean seen from this camera (cos theta = rho / r)
+      Cam c;
+      load_cam(cams, v, c);
+      double mu[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) mu[r] = ((c.R[3 * r] * m[0] + c.R[3 * r + 1] * m[1]) + c.R[3 * r + 2] * m[2]) + c.t[r];
+      const double rr = sqrt((mu[0] * mu[0] + mu[1] * mu[1]) + mu[2] * mu[2]);
+      const double ct = sqrt(mu[0] * mu[0] + mu[2] * mu[2]) / rr;
+      st_tau += dacc.tau_min + (1.0 - ct) * (dacc.tau_max - dacc.tau_min);
+      const double gu = g[0] * (0.5 * (double)vt.W[v]), gv = g[1] * (0.5 * (double)vt.H[v]);
+      st_grad += sqrt(gu * gu + gv * gv);
+      ++st_count;
     }
     if (!any) continue;
     // consumed: leave the accumulators cleared for the next reverse compositing pass
@@ -497,6 +523,11 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     d_scales[k * n + i] = (float)gs[k];
   }
   d_opac[i] = (float)go;
+  if (STATS && st_count > 0) {
+    dacc.grad_sum[i] = (float)((double)dacc.grad_sum[i] + st_grad);
+    dacc.tau_sum[i] = (float)((double)dacc.tau_sum[i] + st_tau);
+    dacc.count[i] += st_count;
+  }
 #pragma unroll
   for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = (float)gsh[k];
 }
@@ -540,16 +571,25 @@ hipError_t launch_preprocess(const odgs_plan* p, const float* means, const float
 
 hipError_t launch_preprocess_bwd(const odgs_plan* p, const float* means, const float* scales, const float* quats,
                                  const float* opac, const float* sh, const float* cams, void* ws, float* d_means,
-                                 float* d_scales, float* d_quats, float* d_opac, float* d_sh, hipStream_t st) {
+                                 float* d_scales, float* d_quats, float* d_opac, float* d_sh,
+                                 const odgs_densify_acc* acc, hipStream_t st) {
   if (p->n == 0) return hipSuccess;
+  DensAcc da{nullptr, nullptr, nullptr, 0.0, 0.0};
+  if (acc) da = DensAcc{acc->grad_sum, acc->tau_sum, acc->count, (double)acc->tau_min, (double)acc->tau_max};
   const ViewTable vt = make_view_table(p);
   const Params P = make_params(p);
   const unsigned grid = (unsigned)((p->n + 255) / 256);
   const uint32_t* count = ws_ptr<uint32_t>(ws, p->off_count);
   float* g2d = ws_ptr<float>(ws, p->off_g2d);
-#define ODGS_PREB(KK)                                                                                             \
-  hipLaunchKernelGGL(preprocess_bwd_kernel<KK>, dim3(grid), dim3(256), 0, st, p->n, means, scales, quats, opac, sh, \
-                     cams, vt, P, count, g2d, p->items, d_means, d_scales, d_quats, d_opac, d_sh)
+#define ODGS_PREB(KK)                                                                                        \
+  if (acc)                                                                                                   \
+    hipLaunchKernelGGL((preprocess_bwd_kernel<KK, true>), dim3(grid), dim3(256), 0, st, p->n, means, scales,   \
+                       quats, opac, sh, cams, vt, P, count, g2d, p->items, d_means, d_scales, d_quats, d_opac, \
+                       d_sh, da);                                                                            \
+  else                                                                                                       \
+    hipLaunchKernelGGL((preprocess_bwd_kernel<KK, false>), dim3(grid), dim3(256), 0, st, p->n, means, scales,  \
+                       quats, opac, sh, cams, vt, P, count, g2d, p->items, d_means, d_scales, d_quats, d_opac, \
+                       d_sh, da)
   switch (p->sh_degree) {
     case 0: ODGS_PREB(1); break;
     case 1: ODGS_PREB(4); break;

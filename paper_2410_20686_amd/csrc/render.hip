@@ -323,7 +323,9 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   const float dl0 = dimg[pix], dl1 = dimg[plane + pix], dl2 = dimg[2 * plane + pix];
   float T = ws_T[gp];
   const int last = ws_last[gp];
-  float S0 = T * bg0, S1 = T * bg1, S2 = T * bg2;  // colour of everything behind, incl. background
+  // D = dL/dC . (colour composited behind the current Gaussian, background included); only this
+  // dot product enters dL/dalpha, so one scalar replaces the three suffix colours.
+  float D = T * fmaf(dl0, bg0, fmaf(dl1, bg1, dl2 * bg2));
   // largest `last` of the wavefront (uniform) and of the workgroup
   int wmax = last;
 #pragma unroll
@@ -363,12 +365,10 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       T = ok ? T * inv_om : T;  // transmittance in front of this Gaussian
       const float w = alpha * T;
       const float4 c = S.s2[k];
-      const float dL_da =
-          dl0 * fmaf(c.x, T, -S0 * inv_om) + dl1 * fmaf(c.y, T, -S1 * inv_om) + dl2 * fmaf(c.z, T, -S2 * inv_om);
+      const float dlc = fmaf(dl0, c.x, fmaf(dl1, c.y, dl2 * c.z));
+      const float dL_da = fmaf(dlc, T, -D * inv_om);
       const float wk = ok ? w : 0.0f;
-      S0 = fmaf(c.x, wk, S0);
-      S1 = fmaf(c.y, wk, S1);
-      S2 = fmaf(c.z, wk, S2);
+      D = fmaf(dlc, wk, D);
       const float dpow = (ok && !clamped) ? dL_da * alpha : 0.0f;
       float gq[9];
       // with w = Sigma^-1 d = 2 L^T (t1, t2): d power / d(u, v) = w, d power / d Sigma_2D = w w^T / 2

@@ -101,14 +101,17 @@ class Rasterizer:
         self.generation += 1
         return out_rgb, out_T
 
-    def render_bwd(self, means, scales, quats, opac, sh, cams, dL_drgb, grads=None):
+    def render_bwd(self, means, scales, quats, opac, sh, cams, dL_drgb, grads=None, stats=None):
+        """Parameter gradients (overwritten into ``grads`` if given); ``stats`` (a
+        densify.DensifyStats) also accumulates the densification statistics."""
         self._check_inputs(means, scales, quats, opac, sh, cams)
         if dL_drgb.shape != (3 * self.pixels,) or dL_drgb.dtype != torch.float32 or not dL_drgb.is_contiguous():
             raise ValueError("dL_drgb must be contiguous float32 [%d]" % (3 * self.pixels))
         if grads is None:
             grads = tuple(torch.empty_like(t) for t in (means, scales, quats, opac, sh))
         B.odgs_render_bwd(self.plan, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opac), _ptr(sh), _ptr(cams),
-                          _ptr(self.ws), self.ws_bytes, _ptr(dL_drgb), *[_ptr(g) for g in grads], _stream())
+                          _ptr(self.ws), self.ws_bytes, _ptr(dL_drgb), *[_ptr(g) for g in grads],
+                          None if stats is None else stats.acc(self.n), _stream())
         return grads
 
     # ---- inspection ---------------------------------------------------------------------------
@@ -129,9 +132,10 @@ class Rasterizer:
     def composite_bwd(self, dL_drgb):
         B.odgs_composite_bwd(self.plan, _ptr(self.ws), self.ws_bytes, _ptr(dL_drgb), _stream())
 
-    def project_bwd(self, means, scales, quats, opac, sh, cams, grads):
+    def project_bwd(self, means, scales, quats, opac, sh, cams, grads, stats=None):
         B.odgs_project_bwd(self.plan, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opac), _ptr(sh), _ptr(cams),
-                           _ptr(self.ws), self.ws_bytes, *[_ptr(g) for g in grads], _stream())
+                           _ptr(self.ws), self.ws_bytes, *[_ptr(g) for g in grads],
+                           None if stats is None else stats.acc(self.n), _stream())
 
     def pixel_counts(self) -> torch.Tensor:
         """[pixels, 4] int32 of the last forward: list position after the last contributor,
@@ -147,8 +151,9 @@ class TrainStep:
     captured once into a HIP graph and replayed.  Parameters, camera poses and the upstream
     gradient are read from the given device tensors at every replay (update them in place)."""
 
-    def __init__(self, rast: Rasterizer, params, cams: torch.Tensor, dL_drgb: torch.Tensor):
+    def __init__(self, rast: Rasterizer, params, cams: torch.Tensor, dL_drgb: torch.Tensor, stats=None):
         self.rast = rast
+        self.stats = stats
         self.params = tuple(params)
         self.cams = cams
         self.dL = dL_drgb
@@ -166,7 +171,7 @@ class TrainStep:
         self.rast.composite_bwd(self.dL)
 
     def project_bwd(self):
-        self.rast.project_bwd(*self.params, self.cams, self.grads)
+        self.rast.project_bwd(*self.params, self.cams, self.grads, self.stats)
 
     def run(self):
         self.bin()

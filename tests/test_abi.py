@@ -72,6 +72,33 @@ def test_entry_points_validate_on_host(lib):
     assert lib.odgs_preprocess(ctypes.byref(p), misaligned, fake, fake, fake, fake, fake, fake, p.ws_bytes,
                                nul) == B.EINVAL
     assert lib.odgs_render_bwd(ctypes.byref(p), fake, fake, fake, fake, fake, fake, fake, p.ws_bytes, nul, fake,
-                               fake, fake, fake, fake, nul) == B.EINVAL
+                               fake, fake, fake, fake, nul, nul) == B.EINVAL
+    # statistics requested with a null accumulator array
+    acc = B.DensifyAcc(None, 256 * 1024, 256 * 1024, 2e-5, 1e-4)
+    assert lib.odgs_project_bwd(ctypes.byref(p), fake, fake, fake, fake, fake, fake, fake, p.ws_bytes, fake, fake,
+                                fake, fake, fake, ctypes.byref(acc), nul) == B.EINVAL
     for code in (B.OK, B.EINVAL, B.ENOSPACE, B.EHIP):
         assert B.odgs_strerror(code)
+
+
+def test_densify_validates_on_host(lib):
+    fake = ctypes.c_void_p(256 * 1024)
+    nul = None
+    n = 100
+    ws = B.odgs_densify_workspace_bytes(n)
+    assert ws >= 3 * 4 and ws % 256 == 0
+    dp = B.DensifyParams(10.0, 1e-3, 0.005, 0.0)
+    ins = [fake] * 9
+    outs = [fake] * 8
+
+    def call(n=n, deg=3, cap=2 * n, dp=dp, ws_bytes=ws, ins=ins, outs=outs):
+        return lib.odgs_densify(n, deg, *ins, ctypes.byref(dp), cap, *outs, ws_bytes, nul)
+
+    assert call(cap=2 * n - 1) == B.EINVAL          # capacity below the largest result
+    assert call(deg=4) == B.EINVAL
+    assert call(n=-1) == B.EINVAL
+    assert call(ws_bytes=ws - 1) == B.ENOSPACE
+    assert call(ins=[fake] * 8 + [nul]) == B.EINVAL  # noise missing
+    assert call(outs=[fake] * 6 + [ctypes.c_void_p(256 * 1024 + 4), fake]) == B.EINVAL  # misaligned counts
+    assert call(dp=B.DensifyParams(float("nan"), 1e-3, 0.005, 0.0)) == B.EINVAL
+    assert call(dp=B.DensifyParams(10.0, 1e-3, 0.005, -1.0)) == B.EINVAL

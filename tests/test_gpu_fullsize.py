@@ -82,3 +82,25 @@ def test_M_500k_8x2048x1024_batched():
 def test_cfg3_1M_8x2048x1024_batched():
     sc, cams, st = scenes.config("cfg3")
     _check(sc, cams, st, n_pix=64, seed=1003)
+
+
+def test_cfg1_100k_2048x1024():
+    sc, cams, st = scenes.config("cfg1")
+    _check(sc, cams, st, n_pix=512, seed=1001, key_views=1)
+
+
+def test_cfg4_16_uneven_views_autotuned():
+    """16 views of three resolutions with Haar-random rotations: tile edge and batch chosen by the
+    autotuner on this device, then parity in that configuration."""
+    import torch
+    from paper_2410_20686_amd import autotune
+    sc, cams, st = scenes.config("cfg4")
+    wh = [tuple(int(x) for x in r) for r in cams.wh]
+    t = G.to_gpu(sc, cams)
+    dL = torch.from_numpy(scenes.upstream_gradient(cams, 1004)).cuda()
+    best = autotune.tune(t[:5], t[5], dL, sc.sh_degree, wh, st, reps=3, cache=None, log=print)
+    assert (best["tile"], best["batch"]) in autotune.CANDIDATES
+    assert len(best["table"]) == len(autotune.CANDIDATES)
+    del t, dL
+    torch.cuda.empty_cache()
+    _check(sc, cams, dict(st, tile=best["tile"], batch=best["batch"]), n_pix=48, seed=1004, key_views=1)
