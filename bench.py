@@ -47,9 +47,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=0, help="forward LDS batch (0: library default)")
+    ap.add_argument("--batch-bwd", type=int, default=0, help="reverse LDS batch (0: library default)")
     ap.add_argument("--n", type=int, default=500_000)
-    ap.add_argument("--autotune", action="store_true", help="pick (tile, batch) with the autotuner first")
+    ap.add_argument("--autotune", action="store_true", help="pick the tile and batch sizes with the autotuner first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a known-size reference "
                          "dispatch for hardware byte counters)")
@@ -119,7 +120,7 @@ def main():
 
     t0 = time.time()
     sc, cams, st = scenes.config("M", n=args.n)
-    st = dict(st, tile=args.tile, batch=args.batch)
+    st = dict(st, tile=args.tile, batch=args.batch, batch_bwd=args.batch_bwd)
     wh = [tuple(int(x) for x in r) for r in cams.wh]
     V = len(wh)
     mp_per_step = sum(w * h for w, h in wh) / 1e6
@@ -141,8 +142,8 @@ def main():
     if args.autotune:
         from paper_2410_20686_amd import autotune
         tuned = autotune.tune(tensors[:5], tensors[5], dL, sc.sh_degree, wh, st, cache=None, log=log)
-        st = dict(st, tile=tuned["tile"], batch=tuned["batch"])
-        log("autotuned:", tuned["tile"], tuned["batch"])
+        st = dict(st, tile=tuned["tile"], batch=tuned["batch"], batch_bwd=tuned["batch_bwd"])
+        log("autotuned:", tuned["tile"], tuned["batch"], tuned["batch_bwd"])
 
     # size the pair list from one binning pass, then keep it fixed (no host sync inside steps)
     rast = Rasterizer(sc.n, sc.sh_degree, wh, st)
@@ -224,7 +225,8 @@ def main():
         "config": {"workload": "M: 500k Gaussians (roaming: 70%% in 50 blobs, 30%% shell r 2-20, SH degree 3), "
                                "%d views 2048x1024, fwd+bwd, all views batched in one HIP graph per step" % V,
                    "gaussians": sc.n, "views": V, "width": wh[0][0], "height": wh[0][1], "sh_degree": 3,
-                   "tile": st["tile"], "batch": rast.plan.s.batch, "pairs": status["n_pairs"],
+                   "tile": st["tile"], "batch": rast.plan.s.batch, "batch_bwd": rast.plan.s.batch_bwd,
+                   "pairs": status["n_pairs"],
                    "autotuned": tuned is not None},
         "per_view": per_view,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},

@@ -23,7 +23,7 @@ EXPORTS = ("odgs_plan_init", "odgs_workspace_bytes", "odgs_preprocess", "odgs_bi
 
 
 class Settings(ctypes.Structure):
-    _fields_ = [("tile", ctypes.c_int32), ("batch", ctypes.c_int32), ("near_r", ctypes.c_float),
+    _fields_ = [("tile", ctypes.c_int32), ("batch", ctypes.c_int32), ("batch_bwd", ctypes.c_int32), ("near_r", ctypes.c_float),
                 ("far_r", ctypes.c_float), ("dilation", ctypes.c_float), ("pole_eps", ctypes.c_float),
                 ("bg", ctypes.c_float * 3), ("flags", ctypes.c_int32)]
 
@@ -118,9 +118,10 @@ def _check(rc: int, what: str):
         raise OdgsError("%s failed: %s (%d)" % (what, lib().odgs_strerror(rc).decode(), rc))
 
 
-def make_settings(tile=16, batch=0, near=0.2, far=1e4, dilation=0.3, pole_eps=1e-4, bg=(0.0, 0.0, 0.0)) -> Settings:
+def make_settings(tile=16, batch=0, batch_bwd=0, near=0.2, far=1e4, dilation=0.3, pole_eps=1e-4,
+                  bg=(0.0, 0.0, 0.0)) -> Settings:
     s = Settings()
-    s.tile, s.batch = int(tile), int(batch)
+    s.tile, s.batch, s.batch_bwd = int(tile), int(batch), int(batch_bwd)
     s.near_r, s.far_r, s.dilation, s.pole_eps = float(near), float(far), float(dilation), float(pole_eps)
     for k in range(3):
         s.bg[k] = float(bg[k])

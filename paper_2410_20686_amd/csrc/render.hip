@@ -62,6 +62,15 @@ __device__ inline float bfly(float lo, float hi, bool bit) {
 // ends with the row sum of value kRowSlot[i % 16] (none where the table says 15).
 constexpr uint64_t kRowSlot = 0xFFF8F765FF43F210ull;  // nibble i = value index held by row lane i
 
+// Sum of a value over the four 16-lane rows of the wavefront, returned in every row: the gfx950
+// row-swap permutes (lanes 32-63 <-> 0-31, then odd <-> even rows) need no LDS traffic.
+__device__ inline float sum_rows(float x) {
+  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  const float y = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(y), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 __device__ inline float row_reduce9(const float (&g)[9], bool b3, bool b2, bool b1, bool b0) {
   float a[5];
 #pragma unroll
@@ -298,8 +307,12 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
                                                                 int64_t items, float bg0, float bg1, float bg2) {
   using St = Stage<TILE, BATCH>;
   constexpr int N = St::N;
+  // Up to four wavefronts per tile: each wavefront owns a slot per (value, entry) and the slots
+  // are summed at the flush, so no LDS atomics; more wavefronts share one slot set atomically.
+  constexpr bool kSlots = St::NW <= 4;
+  constexpr int NS = kSlots ? St::NW : 1;
   __shared__ St S;
-  __shared__ float acc[9][BATCH];
+  __shared__ float acc[NS][9][BATCH];
   __shared__ int smax;
   const int g = blockIdx.x;
   const int v = view_of_tile(vt, g);
@@ -323,9 +336,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   const float dl0 = dimg[pix], dl1 = dimg[plane + pix], dl2 = dimg[2 * plane + pix];
   float T = ws_T[gp];
   const int last = ws_last[gp];
-  // D = dL/dC . (colour composited behind the current Gaussian, background included); only this
-  // dot product enters dL/dalpha, so one scalar replaces the three suffix colours.
-  float D = T * fmaf(dl0, bg0, fmaf(dl1, bg1, dl2 * bg2));
+  float S0 = T * bg0, S1 = T * bg1, S2 = T * bg2;  // colour of everything behind, incl. background
   // largest `last` of the wavefront (uniform) and of the workgroup
   int wmax = last;
 #pragma unroll
@@ -339,7 +350,9 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
     const int cnt = min(BATCH, end);
     for (int t = threadIdx.x; t < cnt; t += N) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) acc[q][t] = 0.0f;
+      for (int w = 0; w < NS; ++w)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc[w][q][t] = 0.0f;
     }
     int nq[St::NQ];
     // entry e is list position end - 1 - e (back to front)
@@ -365,10 +378,12 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       T = ok ? T * inv_om : T;  // transmittance in front of this Gaussian
       const float w = alpha * T;
       const float4 c = S.s2[k];
-      const float dlc = fmaf(dl0, c.x, fmaf(dl1, c.y, dl2 * c.z));
-      const float dL_da = fmaf(dlc, T, -D * inv_om);
+      const float dL_da =
+          dl0 * fmaf(c.x, T, -S0 * inv_om) + dl1 * fmaf(c.y, T, -S1 * inv_om) + dl2 * fmaf(c.z, T, -S2 * inv_om);
       const float wk = ok ? w : 0.0f;
-      D = fmaf(dlc, wk, D);
+      S0 = fmaf(c.x, wk, S0);
+      S1 = fmaf(c.y, wk, S1);
+      S2 = fmaf(c.z, wk, S2);
       const float dpow = (ok && !clamped) ? dL_da * alpha : 0.0f;
       float gq[9];
       // with w = Sigma^-1 d = 2 L^T (t1, t2): d power / d(u, v) = w, d power / d Sigma_2D = w w^T / 2
@@ -383,14 +398,21 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       gq[7] = wk * dl1;
       gq[8] = wk * dl2;
       const float rs = row_reduce9(gq, lane & 8, lane & 4, lane & 2, lane & 1);
-      if (slot < 9) atomicAdd(&acc[slot][k], rs);  // 9 lanes per row, 4 rows: one LDS atomic
+      if constexpr (kSlots) {
+        const float ws = sum_rows(rs);
+        if (lane < 16 && slot < 9) acc[wq][slot][k] = ws;
+      } else {
+        if (slot < 9) atomicAdd(&acc[0][slot][k], rs);  // 9 lanes per row, 4 rows: one LDS atomic
+      }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < cnt; t += N) {
       const uint32_t item = S.sid[t];
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
-        const float s = acc[q][t];
+        float s = acc[0][q][t];
+#pragma unroll
+        for (int w = 1; w < NS; ++w) s += acc[w][q][t];
         if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)q * items + item], s);
       }
     }
@@ -496,7 +518,7 @@ hipError_t launch_render_bwd(const odgs_plan* p, void* ws, const float* dL_drgb,
   const Rec* rec = ws_ptr<Rec>(ws, p->off_rec);
   const float* wT = ws_ptr<float>(ws, p->off_T);
   const int32_t* wl = ws_ptr<int32_t>(ws, p->off_last);
-  if (!dispatch<BwdRun>(p->s.tile, p->s.batch, p, tiles, vt, ranges, items, rec, wT, wl, dL_drgb, g2d, st))
+  if (!dispatch<BwdRun>(p->s.tile, p->s.batch_bwd, p, tiles, vt, ranges, items, rec, wT, wl, dL_drgb, g2d, st))
     return hipErrorInvalidValue;
   return hipGetLastError();
 }

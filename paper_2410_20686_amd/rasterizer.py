@@ -16,7 +16,7 @@ import torch
 
 from . import _odgs as B
 
-DEFAULT_SETTINGS = dict(tile=16, batch=0, near=0.2, far=1.0e4, dilation=0.3, pole_eps=1.0e-4, bg=(0.0, 0.0, 0.0))
+DEFAULT_SETTINGS = dict(tile=16, batch=0, batch_bwd=0, near=0.2, far=1.0e4, dilation=0.3, pole_eps=1.0e-4, bg=(0.0, 0.0, 0.0))
 
 
 def _ptr(t: torch.Tensor | None):
@@ -55,6 +55,15 @@ class Rasterizer:
             raise RuntimeError("workspace is not 256-byte aligned")
         self.pixels = int(self.plan.pix_base[len(self.wh)])
         self.status_offset = B.odgs_status_offset(self.plan)
+
+    def set_batches(self, batch: int, batch_bwd: int):
+        """Change the compositors' LDS batch sizes; the workspace (whose layout does not depend
+        on them) and its contents stay valid."""
+        self.settings.update(batch=int(batch), batch_bwd=int(batch_bwd))
+        plan = B.odgs_plan_init(self.n, self.sh_degree, self.wh, B.make_settings(**self.settings), self.capacity)
+        if B.odgs_workspace_bytes(plan) != self.ws_bytes:
+            raise RuntimeError("workspace layout changed with the batch sizes")
+        self.plan = plan
 
     # ---------------------------------------------------------------------------------------
     def status(self) -> dict:

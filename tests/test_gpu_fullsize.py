@@ -99,8 +99,10 @@ def test_cfg4_16_uneven_views_autotuned():
     t = G.to_gpu(sc, cams)
     dL = torch.from_numpy(scenes.upstream_gradient(cams, 1004)).cuda()
     best = autotune.tune(t[:5], t[5], dL, sc.sh_degree, wh, st, reps=3, cache=None, log=print)
-    assert (best["tile"], best["batch"]) in autotune.CANDIDATES
-    assert len(best["table"]) == len(autotune.CANDIDATES)
+    assert best["tile"] in autotune.TILES
+    assert best["batch"] in autotune.BATCHES[best["tile"]] and best["batch_bwd"] in autotune.BATCHES[best["tile"]]
+    assert len(best["table"]) == len(autotune.TILES)
     del t, dL
     torch.cuda.empty_cache()
-    _check(sc, cams, dict(st, tile=best["tile"], batch=best["batch"]), n_pix=48, seed=1004, key_views=1)
+    _check(sc, cams, dict(st, tile=best["tile"], batch=best["batch"], batch_bwd=best["batch_bwd"]), n_pix=48,
+           seed=1004, key_views=1)
