@@ -37,6 +37,32 @@ OPS_FWD_TEST, OPS_FWD_ACCEPT = 14, 14
 OPS_BWD_TEST, OPS_BWD_ACCEPT = 15, 50
 
 
+PROFILE = os.path.join(ROOT, "profiles", "render_kernels_M_500k_8x2048x1024.txt")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_2410_20686_amd/csrc/render.hip", "paper_2410_20686_amd/csrc/common.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of the reverse compositor from the committed rocprofv3 counter summary
+    (calibrated FETCH_SIZE + WRITE_SIZE), or None when the summary is missing, covers another
+    kernel instance, or was taken from different kernel source."""
+    try:
+        with open(PROFILE) as f:
+            kv = dict(line.split(": ", 1) for line in f.read().splitlines() if ": " in line and not line.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("kernel", "").strip() != kernel or kv.get("source_sha256_16", "").strip() != kernel_source_hash():
+        return None
+    return int(float(kv["traffic_bytes_per_launch"]))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -56,7 +82,7 @@ def parse():
                          "dispatch for hardware byte counters)")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels-per-view", type=int, default=1024)
+    ap.add_argument("--cpu-pixels-per-view", type=int, default=768)
     return ap.parse_args()
 
 
@@ -198,8 +224,10 @@ def main():
     roof = None
     if dom in alg_ops:
         achieved = alg_ops[dom] / (stages[dom] / 1e3) / 1e12
+        kname = "odgs::render_bwd_kernel<%d, %d>" % (st["tile"], rast.plan.s.batch_bwd) if dom == "composite_bwd" \
+            else "odgs::render_fwd_kernel<%d, %d>" % (st["tile"], rast.plan.s.batch)
         roof = dict(bound="alu", kernel=dom, achieved=round(achieved, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Top/s",
-                    frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=None,
+                    frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=measured_traffic(kname),
                     work=dict(tests=evals_bwd if dom == "composite_bwd" else evals_fwd, accepts=contrib_total))
 
     cpu = None
