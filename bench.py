@@ -183,7 +183,11 @@ def main():
     log("batched %.3f ms/step, P=%d" % (ms_batched, status["n_pairs"]))
 
     stages = time_stages(step, max(3, min(args.steps, 10)))
+    # work counters for the algorithmic op count: one extra forward in the counting variant
+    rast.set_batches(rast.plan.s.batch, rast.plan.s.batch_bwd, count_work=True)
+    step.fwd()
     cnt = rast.pixel_counts().to(torch.int64).sum(dim=0).cpu().numpy()
+    rast.set_batches(rast.plan.s.batch, rast.plan.s.batch_bwd, count_work=False)
     contrib_total, evals_fwd, evals_bwd = int(cnt[1]), int(cnt[2]), int(cnt[3])
     log("stages ms", stages)
 

@@ -48,6 +48,8 @@ enum {
 
 #define ODGS_MAX_VIEWS 64
 #define ODGS_STATUS_OVERFLOW 1 /* more Gaussian-tile pairs than plan->pair_capacity */
+#define ODGS_FLAG_COUNT_WORK 1 /* settings flag: odgs_render_fwd also records the per-pixel work
+                                  counters of odgs_debug_pixel_counts (slower; for measurement) */
 
 /* Rasterization settings.  The paper fixes none of these constants; the defaults follow the
  * 3DGS rasterizer the method builds on (Sec. 3.2). */
@@ -61,7 +63,7 @@ typedef struct odgs_settings {
   float dilation;   /* added to the 2D covariance's diagonal (3DGS low-pass), e.g. 0.3 */
   float pole_eps;   /* cull when sqrt(mu_x^2 + mu_z^2) <= pole_eps * |mu|, e.g. 1e-4 */
   float bg[3];      /* background colour behind the final transmittance */
-  int32_t flags;    /* reserved, 0 */
+  int32_t flags;    /* ODGS_FLAG_* bits, 0 for none */
 } odgs_settings;
 
 /* Device status record at byte offset plan->off_status of the workspace. */
@@ -224,7 +226,8 @@ int odgs_debug_records(const odgs_plan* plan, const void* ws, float* out, void* 
 /* Per-pixel int32 [pixels][4] of the last odgs_render_fwd: list position after the last
  * contributor; number of contributors; list entries evaluated (up to and including the one that
  * ended the pixel by early termination, else the whole list); and entries evaluated up to the
- * last contributor.  The last two count only entries whose padded footprint rectangle reaches
+ * last contributor.  The last three are only recorded by a forward whose plan has
+ * ODGS_FLAG_COUNT_WORK set (otherwise they hold whatever an earlier counting forward left).  The last two count only entries whose padded footprint rectangle reaches
  * the pixel's 8x8 quadrant (the others are skipped for the whole wavefront). */
 int odgs_debug_pixel_counts(const odgs_plan* plan, const void* ws, int32_t* out, void* stream);
 

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libodgs.so")
 MAX_VIEWS = 64
 OK, EINVAL, ENOSPACE, EHIP = 0, -1, -2, -3
 STATUS_OVERFLOW = 1
+FLAG_COUNT_WORK = 1
 
 EXPORTS = ("odgs_plan_init", "odgs_workspace_bytes", "odgs_preprocess", "odgs_bin_sort", "odgs_render_fwd",
            "odgs_render_bwd", "odgs_composite_bwd", "odgs_project_bwd", "odgs_status_offset", "odgs_strerror",
@@ -119,13 +120,13 @@ def _check(rc: int, what: str):
 
 
 def make_settings(tile=16, batch=0, batch_bwd=0, near=0.2, far=1e4, dilation=0.3, pole_eps=1e-4,
-                  bg=(0.0, 0.0, 0.0)) -> Settings:
+                  bg=(0.0, 0.0, 0.0), count_work=False) -> Settings:
     s = Settings()
     s.tile, s.batch, s.batch_bwd = int(tile), int(batch), int(batch_bwd)
     s.near_r, s.far_r, s.dilation, s.pole_eps = float(near), float(far), float(dilation), float(pole_eps)
     for k in range(3):
         s.bg[k] = float(bg[k])
-    s.flags = 0
+    s.flags = FLAG_COUNT_WORK if count_work else 0
     return s
 
 

@@ -159,26 +159,44 @@ __device__ inline float wrap_du(float du, float Wf, float half) {
 }
 
 // Stage `cnt` records of a tile list into LDS (entry e <- list position first + dir * e) and
-// build, for every quadrant, the order-preserving list of entries whose footprint reaches it.
-// Counts per quadrant are returned in nq[] (identical in every thread).
-template <int TILE, int BATCH>
+// build, for every wavefront, the order-preserving list of entries whose footprint reaches its
+// pixels.  With PX pixels per lane a wavefront owns PX horizontally adjacent quadrants (8x8
+// pixel blocks), so there are NQ / PX lists.  Counts per list are returned in nq[] (identical
+// in every thread).
+template <int TILE, int BATCH, int PX = 1>
 struct Stage {
-  static constexpr int N = TILE * TILE;
-  static constexpr int NQ = (TILE / 8) * (TILE / 8);
+  static constexpr int N = TILE * TILE / PX;  // threads
+  static constexpr int NQ = (TILE / 8) * (TILE / 8) / PX;  // lists = wavefronts
   static constexpr int NW = N / kWave;
+  static_assert(NQ == NW, "one list per wavefront");
   float4 s0[BATCH];
   float4 s1[BATCH];
   float4 s2[BATCH];
   uint32_t sid[BATCH];
   uint8_t list[NQ][BATCH];
-  uint32_t wcnt[NW][NQ];
+  uint32_t wcnt[NW][NQ];  // per-wavefront counts, then (in place) exclusive prefix over wavefronts
+  uint32_t tot[NQ];
 };
 
-template <int TILE, int BATCH>
-__device__ inline void stage_batch(Stage<TILE, BATCH>& S, const uint32_t* __restrict__ pair_items,
+// Quadrant mask -> mask of the wavefronts' quadrant groups (PX adjacent quadrants each).
+template <int PX>
+__device__ inline uint32_t group_mask(uint32_t m) {
+  if constexpr (PX == 1) {
+    return m;
+  } else {
+    static_assert(PX == 2, "one or two pixels per lane");
+    uint32_t g = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) g |= ((m >> (2 * r)) & 3u) ? (1u << r) : 0u;
+    return g;
+  }
+}
+
+template <int TILE, int BATCH, int PX = 1>
+__device__ inline void stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __restrict__ pair_items,
                                    const Rec* __restrict__ rec, uint32_t first, int dir, int cnt, int tx0, int ty0,
-                                   float Wf, float half, int (&nq)[Stage<TILE, BATCH>::NQ]) {
-  using St = Stage<TILE, BATCH>;
+                                   float Wf, float half, int (&nq)[Stage<TILE, BATCH, PX>::NQ]) {
+  using St = Stage<TILE, BATCH, PX>;
   const int t = threadIdx.x, ln = t & (kWave - 1), wv = t >> 6;
   const uint64_t below = ln == 0 ? 0ull : (~0ull >> (kWave - ln));
 #pragma unroll
@@ -193,33 +211,44 @@ __device__ inline void stage_batch(Stage<TILE, BATCH>& S, const uint32_t* __rest
       S.s1[e] = r.r1;
       S.s2[e] = r.r2;
       S.sid[e] = item;
-      m = quadrant_mask<TILE>(r, tx0, ty0, Wf, half);
+      m = group_mask<PX>(quadrant_mask<TILE>(r, tx0, ty0, Wf, half));
     }
     uint32_t within[St::NQ];
 #pragma unroll
     for (int q = 0; q < St::NQ; ++q) {
-      const uint64_t bq = __ballot((m >> q) & 1u);
+      const uint64_t bq = __builtin_amdgcn_ballot_w64((m >> q) & 1u);
       within[q] = __popcll(bq & below);
       if (ln == 0) S.wcnt[wv][q] = __popcll(bq);
     }
     __syncthreads();
+    if constexpr (St::NW > 1) {
+      // thread q turns list q's per-wavefront counts into exclusive prefixes
+      if (t < St::NQ) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < St::NW; ++w) {
+          const uint32_t c = S.wcnt[w][t];
+          S.wcnt[w][t] = run;
+          run += c;
+        }
+        S.tot[t] = run;
+      }
+      __syncthreads();
+    }
 #pragma unroll
     for (int q = 0; q < St::NQ; ++q) {
-      int base = nq[q], tot = 0;
-#pragma unroll
-      for (int w = 0; w < St::NW; ++w) {
-        const int c = (int)S.wcnt[w][q];
-        base += w < wv ? c : 0;
-        tot += c;
-      }
-      if ((m >> q) & 1u) S.list[q][base + within[q]] = (uint8_t)e;
+      const int pre = St::NW > 1 ? (int)S.wcnt[wv][q] : 0;
+      const int tot = St::NW > 1 ? (int)S.tot[q] : (int)S.wcnt[0][q];
+      if ((m >> q) & 1u) S.list[q][nq[q] + pre + (int)within[q]] = (uint8_t)e;
       nq[q] += tot;
     }
     __syncthreads();
   }
 }
 
-template <int TILE, int BATCH>
+// COUNT: also record the per-pixel work counters read by odgs_debug_pixel_counts (a separate
+// instantiation, so the production forward carries no counting instructions).
+template <int TILE, int BATCH, bool COUNT>
 __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
     float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
@@ -237,7 +266,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
   int lx, ly;
   local_pixel<TILE>(threadIdx.x, lx, ly);
   const int x = tx0 + lx, y = ty0 + ly;
-  const int wq = threadIdx.x >> 6;  // this wavefront's quadrant
+  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // this wavefront's quadrant (uniform)
   const float px = (float)x + 0.5f, py = (float)y + 0.5f;
   const float Wf = (float)W, half = (float)W * 0.5f;
   const uint2 rg = ranges[g];
@@ -249,9 +278,9 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
     const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
     int nq[St::NQ];
     stage_batch<TILE, BATCH>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq);
-    const int n = nq[wq];
+    const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
-      if (__ballot(!done) == 0ull) break;  // uniform: every pixel of the wavefront has finished
+      if (__builtin_amdgcn_ballot_w64(!done) == 0ull) break;  // uniform: every pixel has finished
       const int k = S.list[wq][i];
       const float4 a = S.s0[k];
       const float4 b = S.s1[k];
@@ -259,9 +288,9 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
       const float dv = py - a.y;
       const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
       const float power = -fmaf(t1, t1, t2 * t2);
-      nev += done ? 0 : 1;
+      if (COUNT) nev += done ? 0 : 1;
       const bool ok = !done && !(power > 0.0f || power < b.z);
-      if (__ballot(ok) == 0ull) continue;  // uniform
+      if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
       float alpha = b.y * __expf(power);
       alpha = alpha > kAlphaMax ? kAlphaMax : alpha;
       const float Tn = T * (1.0f - alpha);
@@ -275,8 +304,10 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
       C2 = fmaf(w, c.z, C2);
       T = acc ? Tn : T;
       last = acc ? (int)(base - rg.x) + k + 1 : last;
-      lastev = acc ? nev : lastev;
-      ncontrib += acc ? 1 : 0;
+      if (COUNT) {
+        lastev = acc ? nev : lastev;
+        ncontrib += acc ? 1 : 0;
+      }
     }
   }
   const int64_t plane = (int64_t)W * H;
@@ -288,9 +319,11 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
   const int64_t gp = vt.pix_base[v] + pix;
   ws_T[gp] = T;
   ws_last[gp] = last;
-  ws_ncontrib[gp] = ncontrib;
-  ws_neval[gp] = nev;
-  ws_lasteval[gp] = lastev;
+  if (COUNT) {
+    ws_ncontrib[gp] = ncontrib;
+    ws_neval[gp] = nev;
+    ws_lasteval[gp] = lastev;
+  }
   if (out_T) out_T[gp] = T;
 }
 
@@ -324,7 +357,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   local_pixel<TILE>(threadIdx.x, lx, ly);
   const int x = tx0 + lx, y = ty0 + ly;
   const int lane = threadIdx.x & (kWave - 1);
-  const int wq = threadIdx.x >> 6;
+  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int slot = (int)((kRowSlot >> (4 * (lane & 15))) & 0xF);
   const float px = (float)x + 0.5f, py = (float)y + 0.5f;
   const float Wf = (float)W, half = (float)W * 0.5f;
@@ -341,6 +374,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   int wmax = last;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
+  wmax = __builtin_amdgcn_readfirstlane(wmax);
   if (threadIdx.x == 0) smax = 0;
   __syncthreads();
   if (lane == 0) atomicMax(&smax, wmax);
@@ -357,9 +391,9 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
     int nq[St::NQ];
     // entry e is list position end - 1 - e (back to front)
     stage_batch<TILE, BATCH>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq);
-    const int n = nq[wq];
+    const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
-      const int k = S.list[wq][i];
+      const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);  // uniform entry index
       const int jrel = end - 1 - k;
       if (jrel >= wmax) continue;  // uniform: behind every contributor of this wavefront
       const float4 a = S.s0[k];
@@ -369,7 +403,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
       const float power = -fmaf(t1, t1, t2 * t2);
       const bool ok = jrel < last && !(power > 0.0f || power < b.z);
-      if (__ballot(ok) == 0ull) continue;  // uniform
+      if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
       const float G = __expf(power);
       float alpha = b.y * G;
       const bool clamped = alpha > kAlphaMax;
@@ -403,6 +437,154 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
         if (lane < 16 && slot < 9) acc[wq][slot][k] = ws;
       } else {
         if (slot < 9) atomicAdd(&acc[0][slot][k], rs);  // 9 lanes per row, 4 rows: one LDS atomic
+      }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += N) {
+      const uint32_t item = S.sid[t];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        float s = acc[0][q][t];
+#pragma unroll
+        for (int w = 1; w < NS; ++w) s += acc[w][q][t];
+        if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)q * items + item], s);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Reverse compositing state of one pixel (back to front from its last contributor).
+struct BwdPixel {
+  float T, S0, S1, S2, dl0, dl1, dl2;
+  int last;
+};
+
+// One pixel's contribution of a Gaussian to the nine 2D gradients (added to gq when ADD, else
+// written), and the pixel's recursion step.  `ok`: the Gaussian contributed to this pixel.
+template <bool ADD>
+__device__ inline void bwd_pixel_step(BwdPixel& P, bool ok, float power, float t1, float t2, const float4& a,
+                                      const float4& b, const float4& c, float (&gq)[9]) {
+  const float G = __expf(power);
+  float alpha = b.y * G;
+  const bool clamped = alpha > kAlphaMax;
+  alpha = clamped ? kAlphaMax : alpha;
+  const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
+  P.T = ok ? P.T * inv_om : P.T;  // transmittance in front of this Gaussian
+  const float w = alpha * P.T;
+  const float dL_da = P.dl0 * fmaf(c.x, P.T, -P.S0 * inv_om) + P.dl1 * fmaf(c.y, P.T, -P.S1 * inv_om) +
+                      P.dl2 * fmaf(c.z, P.T, -P.S2 * inv_om);
+  const float wk = ok ? w : 0.0f;
+  P.S0 = fmaf(c.x, wk, P.S0);
+  P.S1 = fmaf(c.y, wk, P.S1);
+  P.S2 = fmaf(c.z, wk, P.S2);
+  const bool live = ok && !clamped;
+  const float dpow = live ? dL_da * alpha : 0.0f;
+  // with w = Sigma^-1 d = 2 L^T (t1, t2): d power / d(u, v) = w, d power / d Sigma_2D = w w^T / 2
+  const float wx = 2.0f * a.z * t1, wy = 2.0f * fmaf(a.w, t1, b.x * t2);
+  const float g0 = dpow * wx, g1 = dpow * wy;
+  const float h[9] = {g0, g1, 0.5f * g0 * wx, g0 * wy, 0.5f * g1 * wy, live ? dL_da * G : 0.0f,
+                      wk * P.dl0, wk * P.dl1, wk * P.dl2};
+#pragma unroll
+  for (int q = 0; q < 9; ++q) gq[q] = ADD ? gq[q] + h[q] : h[q];
+}
+
+// Reverse compositing with two pixels per lane (32x32 tiles): wavefront w owns quadrants
+// 2w and 2w + 1 (side by side), lane l the pixel (l % 8, l / 8) of each.  Both pixels' gradient
+// contributions are added in registers, so each (entry, wavefront) needs one cross-lane
+// reduction for 128 pixels, and the per-entry LDS reads and loop control are shared.
+template <int TILE, int BATCH>
+__global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
+    ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
+    const float* __restrict__ ws_T, const int32_t* __restrict__ ws_last, const float* __restrict__ dL_drgb,
+    float* __restrict__ g2d, int64_t items, float bg0, float bg1, float bg2) {
+  using St = Stage<TILE, BATCH, 2>;
+  constexpr int N = St::N;
+  constexpr int QPR = TILE / 8;
+  constexpr bool kSlots = St::NW <= 4;
+  constexpr int NS = kSlots ? St::NW : 1;
+  __shared__ St S;
+  __shared__ float acc[NS][9][BATCH];
+  __shared__ int smax;
+  const int g = blockIdx.x;
+  const int v = view_of_tile(vt, g);
+  const int W = vt.W[v], H = vt.H[v];
+  const int ntx = W / TILE;
+  const int lt = g - vt.tile_base[v];
+  const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int qa = 2 * wq;  // quadrant of pixel A; pixel B is 8 pixels to the right
+  const int x = tx0 + (qa % QPR) * 8 + (lane & 7), y = ty0 + (qa / QPR) * 8 + (lane >> 3);
+  const int slot = (int)((kRowSlot >> (4 * (lane & 15))) & 0xF);
+  const float pxa = (float)x + 0.5f, pxb = (float)(x + 8) + 0.5f, py = (float)y + 0.5f;
+  const float Wf = (float)W, half = (float)W * 0.5f;
+  const uint2 rg = ranges[g];
+  const int64_t plane = (int64_t)W * H;
+  const int64_t pix = (int64_t)y * W + x;
+  const int64_t gp = vt.pix_base[v] + pix;
+  const float* dimg = dL_drgb + 3 * vt.pix_base[v];
+  BwdPixel A, B;
+  A.dl0 = dimg[pix], A.dl1 = dimg[plane + pix], A.dl2 = dimg[2 * plane + pix];
+  B.dl0 = dimg[pix + 8], B.dl1 = dimg[plane + pix + 8], B.dl2 = dimg[2 * plane + pix + 8];
+  A.T = ws_T[gp];
+  B.T = ws_T[gp + 8];
+  A.last = ws_last[gp];
+  B.last = ws_last[gp + 8];
+  A.S0 = A.T * bg0, A.S1 = A.T * bg1, A.S2 = A.T * bg2;  // colour behind, incl. background
+  B.S0 = B.T * bg0, B.S1 = B.T * bg1, B.S2 = B.T * bg2;
+  // largest `last` of the wavefront (uniform) and of the workgroup
+  int wmax = max(A.last, B.last);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
+  wmax = __builtin_amdgcn_readfirstlane(wmax);
+  if (threadIdx.x == 0) smax = 0;
+  __syncthreads();
+  if (lane == 0) atomicMax(&smax, wmax);
+  __syncthreads();
+  const int end_all = smax;
+  for (int end = end_all; end > 0; end -= BATCH) {
+    const int cnt = min(BATCH, end);
+    for (int t = threadIdx.x; t < cnt; t += N) {
+#pragma unroll
+      for (int w = 0; w < NS; ++w)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc[w][q][t] = 0.0f;
+    }
+    int nq[St::NQ];
+    // entry e is list position end - 1 - e (back to front)
+    stage_batch<TILE, BATCH, 2>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq);
+    const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
+    for (int i = 0; i < n; ++i) {
+      const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);  // uniform entry index
+      const int jrel = end - 1 - k;
+      if (jrel >= wmax) continue;  // uniform: behind every contributor of this wavefront
+      const float4 a = S.s0[k];
+      const float4 b = S.s1[k];
+      const float dv = py - a.y;
+      const float l1dv = a.w * dv, t2 = b.x * dv, t22 = t2 * t2;
+      const float dua = wrap_du(pxa - a.x, Wf, half), dub = wrap_du(pxb - a.x, Wf, half);
+      const float t1a = fmaf(a.z, dua, l1dv), t1b = fmaf(a.z, dub, l1dv);
+      const float pa = -fmaf(t1a, t1a, t22), pb = -fmaf(t1b, t1b, t22);
+      const bool oka = jrel < A.last && !(pa > 0.0f || pa < b.z);
+      const bool okb = jrel < B.last && !(pb > 0.0f || pb < b.z);
+      if (__builtin_amdgcn_ballot_w64(oka || okb) == 0ull) continue;  // uniform
+      const float4 c = S.s2[k];
+      float gq[9];
+      const bool anya = __builtin_amdgcn_ballot_w64(oka) != 0ull;  // uniform
+      const bool anyb = __builtin_amdgcn_ballot_w64(okb) != 0ull;
+      if (anya) {
+        bwd_pixel_step<false>(A, oka, pa, t1a, t2, a, b, c, gq);
+        if (anyb) bwd_pixel_step<true>(B, okb, pb, t1b, t2, a, b, c, gq);
+      } else {
+        bwd_pixel_step<false>(B, okb, pb, t1b, t2, a, b, c, gq);
+      }
+      const float rs = row_reduce9(gq, lane & 8, lane & 4, lane & 2, lane & 1);
+      if constexpr (kSlots) {
+        const float ws = sum_rows(rs);
+        if (lane < 16 && slot < 9) acc[wq][slot][k] = ws;
+      } else {
+        if (slot < 9) atomicAdd(&acc[0][slot][k], rs);
       }
     }
     __syncthreads();
@@ -459,8 +641,12 @@ struct FwdRun {
   static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
                   const Rec* rec, float* out_rgb, float* out_T, float* wT, int32_t* wl, int32_t* wn, int32_t* we,
                   int32_t* wle, hipStream_t st) {
-    hipLaunchKernelGGL((render_fwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items,
-                       rec, out_rgb, out_T, wT, wl, wn, we, wle, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+    if (p->s.flags & ODGS_FLAG_COUNT_WORK)
+      hipLaunchKernelGGL((render_fwd_kernel<TILE, BATCH, true>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges,
+                         items, rec, out_rgb, out_T, wT, wl, wn, we, wle, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+    else
+      hipLaunchKernelGGL((render_fwd_kernel<TILE, BATCH, false>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges,
+                         items, rec, out_rgb, out_T, wT, wl, wn, we, wle, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
   }
 };
 
@@ -468,8 +654,14 @@ template <int TILE, int BATCH>
 struct BwdRun {
   static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
                   const Rec* rec, const float* wT, const int32_t* wl, const float* dL, float* g2d, hipStream_t st) {
-    hipLaunchKernelGGL((render_bwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items,
-                       rec, wT, wl, dL, g2d, p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+    // two pixels per lane pay off for 32x32 tiles (half the wavefronts staging and scanning the
+    // lists); at 16x16 the union of two quadrants' lists costs as much as the shared reduction saves
+    if constexpr (TILE >= 32)
+      hipLaunchKernelGGL((render_bwd2_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE / 2), 0, st, vt, ranges,
+                         items, rec, wT, wl, dL, g2d, p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+    else
+      hipLaunchKernelGGL((render_bwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items,
+                         rec, wT, wl, dL, g2d, p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
   }
 };
 

@@ -16,7 +16,7 @@ import torch
 
 from . import _odgs as B
 
-DEFAULT_SETTINGS = dict(tile=16, batch=0, batch_bwd=0, near=0.2, far=1.0e4, dilation=0.3, pole_eps=1.0e-4, bg=(0.0, 0.0, 0.0))
+DEFAULT_SETTINGS = dict(tile=16, batch=0, batch_bwd=0, count_work=False, near=0.2, far=1.0e4, dilation=0.3, pole_eps=1.0e-4, bg=(0.0, 0.0, 0.0))
 
 
 def _ptr(t: torch.Tensor | None):
@@ -56,10 +56,12 @@ class Rasterizer:
         self.pixels = int(self.plan.pix_base[len(self.wh)])
         self.status_offset = B.odgs_status_offset(self.plan)
 
-    def set_batches(self, batch: int, batch_bwd: int):
-        """Change the compositors' LDS batch sizes; the workspace (whose layout does not depend
-        on them) and its contents stay valid."""
+    def set_batches(self, batch: int, batch_bwd: int, count_work: bool | None = None):
+        """Change the compositors' LDS batch sizes (and whether the forward records its work
+        counters); the workspace, whose layout depends on neither, and its contents stay valid."""
         self.settings.update(batch=int(batch), batch_bwd=int(batch_bwd))
+        if count_work is not None:
+            self.settings["count_work"] = bool(count_work)
         plan = B.odgs_plan_init(self.n, self.sh_degree, self.wh, B.make_settings(**self.settings), self.capacity)
         if B.odgs_workspace_bytes(plan) != self.ws_bytes:
             raise RuntimeError("workspace layout changed with the batch sizes")
@@ -149,7 +151,8 @@ class Rasterizer:
     def pixel_counts(self) -> torch.Tensor:
         """[pixels, 4] int32 of the last forward: list position after the last contributor,
         contributors, entries evaluated, and entries evaluated up to the last contributor (the
-        last two count only entries whose footprint reaches the pixel's 8x8 quadrant)."""
+        last two count only entries whose footprint reaches the pixel's 8x8 quadrant; the last
+        three need a forward with the count_work setting)."""
         out = torch.empty((self.pixels, 4), dtype=torch.int32, device=self.device)
         B.odgs_debug_pixel_counts(self.plan, _ptr(self.ws), _ptr(out), _stream())
         return out

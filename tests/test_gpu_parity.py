@@ -192,3 +192,20 @@ def test_empty_and_fully_culled_scenes():
     np.testing.assert_array_equal(r["T"], 1.0)
     for g in r["grads"].values():
         np.testing.assert_array_equal(g, 0.0)
+
+
+@pytest.mark.parametrize("case", CASES[:3], ids=[c[0] for c in CASES[:3]])
+def test_work_counters(case):
+    """The counting forward variant gives the same image, the oracle's contributor counts, and
+    consistent counters; the production variant leaves image and list positions unchanged."""
+    name, sc, cams, st = case
+    res = G.run_gpu(sc, cams, dict(st, count_work=True), return_rast=True)
+    rast = res["rast"]
+    cnt = rast.pixel_counts().cpu().numpy()
+    ref = O.render(sc, cams, st, mode=32)
+    ok = G.strict_pixels(ref["margin"])
+    np.testing.assert_array_equal(cnt[ok, 1], ref["ncontrib"][ok])
+    assert (cnt[:, 3] <= cnt[:, 2]).all() and (cnt[:, 1] <= cnt[:, 3]).all() and (cnt[:, 3] <= cnt[:, 0]).all()
+    plain = G.run_gpu(sc, cams, st, return_rast=True)
+    np.testing.assert_array_equal(plain["rgb"], res["rgb"])
+    np.testing.assert_array_equal(plain["rast"].pixel_counts().cpu().numpy()[:, 0], cnt[:, 0])
