@@ -186,8 +186,18 @@ def main():
     # work counters for the algorithmic op count: one extra forward in the counting variant
     rast.set_batches(rast.plan.s.batch, rast.plan.s.batch_bwd, count_work=True)
     step.fwd()
-    cnt = rast.pixel_counts().to(torch.int64).sum(dim=0).cpu().numpy()
+    pc = rast.pixel_counts().to(torch.int64)
+    cnt = pc.sum(dim=0).cpu().numpy()
     rast.set_batches(rast.plan.s.batch, rast.plan.s.batch_bwd, count_work=False)
+    # wavefront iterations: every 8x8 quadrant is one wavefront, which steps through its list
+    # until its slowest pixel is done
+    wave_iters = [0, 0]
+    off = 0
+    for (w, h) in wh:
+        q = pc[off:off + w * h].reshape(h // 8, 8, w // 8, 8, 4).amax(dim=(1, 3))
+        wave_iters[0] += int(q[..., 2].sum())
+        wave_iters[1] += int(q[..., 3].sum())
+        off += w * h
     contrib_total, evals_fwd, evals_bwd = int(cnt[1]), int(cnt[2]), int(cnt[3])
     log("stages ms", stages)
 
@@ -232,7 +242,8 @@ def main():
             else "odgs::render_fwd_kernel<%d, %d>" % (st["tile"], rast.plan.s.batch)
         roof = dict(bound="alu", kernel=dom, achieved=round(achieved, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Top/s",
                     frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=measured_traffic(kname),
-                    work=dict(tests=evals_bwd if dom == "composite_bwd" else evals_fwd, accepts=contrib_total))
+                    work=dict(tests=evals_bwd if dom == "composite_bwd" else evals_fwd, accepts=contrib_total,
+                              wave_iters=wave_iters[1] if dom == "composite_bwd" else wave_iters[0]))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -93,7 +93,8 @@ typedef struct odgs_plan {
   int32_t pair_blocks;     /* sort blocks over pair_capacity */
   int32_t reserved;
   /* workspace layout, byte offsets */
-  size_t off_status, off_rec, off_rect, off_count, off_depth, off_dkey[2], off_did[2], off_blocksum, off_pkey[2], off_pval[2],
+  size_t off_status, off_rec, off_rect, off_count, off_depth, off_dkey[2], off_did[2], off_srect, off_blocksum, off_pkey[2],
+      off_pval[2],
       off_hist, off_digit, off_ranges, off_T, off_last, off_ncontrib, off_neval,
       off_lasteval, off_g2d;
   int32_t depth_final;     /* which of the two depth-sort buffers holds the sorted result */

@@ -44,7 +44,7 @@ class Status(ctypes.Structure):
                 ("n_visible", ctypes.c_int64), ("reserved2", ctypes.c_int64)]
 
 
-_OFFSETS = ["off_status", "off_rec", "off_rect", "off_count", "off_depth", "off_dkey0", "off_dkey1", "off_did0", "off_did1",
+_OFFSETS = ["off_status", "off_rec", "off_rect", "off_count", "off_depth", "off_dkey0", "off_dkey1", "off_did0", "off_did1", "off_srect",
             "off_blocksum", "off_pkey0", "off_pkey1", "off_pval0", "off_pval1", "off_hist", "off_digit",
             "off_ranges", "off_T", "off_last", "off_ncontrib", "off_neval", "off_lasteval", "off_g2d"]
 

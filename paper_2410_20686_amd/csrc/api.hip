@@ -106,6 +106,7 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   plan->off_dkey[1] = take((size_t)I * 4);
   plan->off_did[0] = take((size_t)I * 4);
   plan->off_did[1] = take((size_t)I * 4);
+  plan->off_srect = take((size_t)I * sizeof(Rect));
   plan->off_blocksum = take(align_up((size_t)sblocks, 64) * 4 + (size_t)sblocks * 8);
   plan->off_pkey[0] = take((size_t)pair_capacity * 4);
   plan->off_pkey[1] = take((size_t)pair_capacity * 4);

@@ -184,16 +184,22 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 constexpr int kScanIpt = 4;
 constexpr int kScanBlockItems = 256 * kScanIpt;
 
+// Gathers the items' tile rectangles into depth order (the one random access of binning; the
+// offset and emission passes then read them sequentially) and reduces the tile counts per block.
 __global__ __launch_bounds__(256) void count_reduce_kernel(const uint32_t* __restrict__ sorted_ids,
-                                                           const uint32_t* __restrict__ count, int64_t items,
-                                                           uint32_t* __restrict__ block_sum) {
+                                                           const Rect* __restrict__ rect, int64_t items,
+                                                           Rect* __restrict__ srect, uint32_t* __restrict__ block_sum) {
   __shared__ uint32_t lds[4];
   const int64_t start = (int64_t)blockIdx.x * kScanBlockItems;
   uint32_t s = 0;
 #pragma unroll
   for (int k = 0; k < kScanIpt; ++k) {
-    const int64_t j = start + threadIdx.x * kScanIpt + k;
-    if (j < items) s += count[sorted_ids[j]];
+    const int64_t j = start + k * 256 + threadIdx.x;  // coalesced
+    if (j < items) {
+      const Rect r = rect[sorted_ids[j]];
+      srect[j] = r;
+      s += (uint32_t)r.ncols * (uint32_t)r.nrows;
+    }
   }
   uint32_t total;
   block_incl_scan256(s, lds, total);
@@ -236,8 +242,7 @@ __global__ __launch_bounds__(256) void count_top_kernel(const uint32_t* __restri
 // First pair position of every depth-sorted item (clamped to the capacity: items starting past
 // it emit nothing).  Pairs of one item are contiguous and items follow depth order, so a later
 // stable sort by tile keeps (depth, index) order inside every tile.
-__global__ __launch_bounds__(256) void item_offsets_kernel(const uint32_t* __restrict__ sorted_ids,
-                                                           const uint32_t* __restrict__ count,
+__global__ __launch_bounds__(256) void item_offsets_kernel(const Rect* __restrict__ srect,
                                                            const uint64_t* __restrict__ block_off, int64_t items,
                                                            int64_t capacity, uint32_t* __restrict__ ioff) {
   __shared__ uint32_t lds[4];
@@ -247,7 +252,12 @@ __global__ __launch_bounds__(256) void item_offsets_kernel(const uint32_t* __res
 #pragma unroll
   for (int k = 0; k < kScanIpt; ++k) {
     const int64_t j = start + threadIdx.x * kScanIpt + k;
-    cnt[k] = j < items ? count[sorted_ids[j]] : 0u;
+    if (j < items) {
+      const Rect r = srect[j];
+      cnt[k] = (uint32_t)r.ncols * (uint32_t)r.nrows;
+    } else {
+      cnt[k] = 0u;
+    }
     s += cnt[k];
   }
   uint32_t total;
@@ -279,7 +289,7 @@ __device__ inline int64_t upper_bound_u32(const uint32_t* a, int64_t n, uint32_t
 
 __global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restrict__ sorted_ids,
                                                          const uint32_t* __restrict__ ioff,
-                                                         const Rect* __restrict__ rect,
+                                                         const Rect* __restrict__ srect,
                                                          const odgs_status* __restrict__ status, int64_t items,
                                                          int64_t n, ViewTable vt, int tile, uint32_t* __restrict__ pkey,
                                                          uint32_t* __restrict__ pval) {
@@ -305,7 +315,7 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restr
     const int v = view_of_item(item, n);
     s_off[t] = ioff[i0 + t];
     s_item[t] = item;
-    s_rect[t] = rect[item];
+    s_rect[t] = srect[i0 + t];
     s_tb[t] = (uint32_t)vt.tile_base[v];
     s_ntx[t] = (uint16_t)(vt.W[v] / tile);
   }
@@ -403,18 +413,19 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
   const int sblocks = (int)((items + kScanBlockItems - 1) / kScanBlockItems);
   uint32_t* bsum = ws_ptr<uint32_t>(ws, p->off_blocksum);
   uint64_t* boff = reinterpret_cast<uint64_t*>(bsum + align_up((size_t)sblocks, 64));
-  const uint32_t* count = ws_ptr<uint32_t>(ws, p->off_count);
-  hipLaunchKernelGGL(count_reduce_kernel, dim3(sblocks), dim3(256), 0, st, sorted_ids, count, items, bsum);
+  Rect* srect = ws_ptr<Rect>(ws, p->off_srect);
+  hipLaunchKernelGGL(count_reduce_kernel, dim3(sblocks), dim3(256), 0, st, sorted_ids, ws_ptr<Rect>(ws, p->off_rect),
+                     items, srect, bsum);
   hipLaunchKernelGGL(count_top_kernel, dim3(1), dim3(256), 0, st, bsum, boff, sblocks, p->pair_capacity, status);
   // 3. emit pairs: per-item offsets (into the free ping-pong buffer), then pair-parallel writes
   uint32_t* pk[2] = {ws_ptr<uint32_t>(ws, p->off_pkey[0]), ws_ptr<uint32_t>(ws, p->off_pkey[1])};
   uint32_t* pv[2] = {ws_ptr<uint32_t>(ws, p->off_pval[0]), ws_ptr<uint32_t>(ws, p->off_pval[1])};
   const ViewTable vt = make_view_table(p);
   uint32_t* ioff = dk[p->depth_final ^ 1];
-  hipLaunchKernelGGL(item_offsets_kernel, dim3(sblocks), dim3(256), 0, st, sorted_ids, count, boff, items,
-                     p->pair_capacity, ioff);
+  hipLaunchKernelGGL(item_offsets_kernel, dim3(sblocks), dim3(256), 0, st, srect, boff, items, p->pair_capacity,
+                     ioff);
   hipLaunchKernelGGL(emit_pairs_kernel, dim3((unsigned)((p->pair_capacity + kEmitPairs - 1) / kEmitPairs)), dim3(256),
-                     0, st, sorted_ids, ioff, ws_ptr<Rect>(ws, p->off_rect), status, items, p->n, vt, p->s.tile, pk[0],
+                     0, st, sorted_ids, ioff, srect, status, items, p->n, vt, p->s.tile, pk[0],
                      pv[0]);
   // 4. stable sort of the pairs by global tile
   const uint32_t* n_dev = reinterpret_cast<const uint32_t*>(&status->n_pairs_stored);
