@@ -53,7 +53,7 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   odgs_settings st = *s;
   if (st.tile != 8 && st.tile != 16 && st.tile != 32) return ODGS_EINVAL;
   if (st.batch == 0) st.batch = st.tile == 8 ? 64 : 256;
-  if (st.batch_bwd == 0) st.batch_bwd = st.tile == 16 ? 128 : 64;
+  if (st.batch_bwd == 0) st.batch_bwd = st.tile == 8 ? 32 : (st.tile == 16 ? 64 : 256);
   if (!batch_ok(st.tile, st.batch) || !batch_ok(st.tile, st.batch_bwd)) return ODGS_EINVAL;
   if (st.flags & ~ODGS_FLAG_COUNT_WORK) return ODGS_EINVAL;
   if (!(st.near_r >= 0.0f) || !(st.far_r > st.near_r) || !(st.dilation >= 0.0f) || !(st.pole_eps >= 0.0f))

@@ -325,7 +325,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
 }
 
 // ---------------------------------------------------------------------------------------------
-// Adjoint.  Inputs per item: 2D gradients g2d[9][items] = (u, v, S_uu, S_uv, S_vv, opacity, r, g,
+// Adjoint.  Inputs per item: 2D gradients g2d[items][9] = (u, v, S_uu, S_uv, S_vv, opacity, r, g,
 // b) with Sigma_2D = [[S_uu, S_uv], [S_uv, S_vv]] (S_uv the shared off-diagonal, dilation
 // included).  Sums over views; writes (overwrites) the parameter gradients.
 // ---------------------------------------------------------------------------------------------
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     bool any = false;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      g[k] = (double)g2d[(int64_t)k * items + item];
+      g[k] = (double)g2d[item * 9 + k];
       any = any || g[k] != 0.0;
     }
     if (STATS) {
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     if (!any) continue;
     // consumed: leave the accumulators cleared for the next reverse compositing pass
 #pragma unroll
-    for (int k = 0; k < 9; ++k) g2d[(int64_t)k * items + item] = 0.0f;
+    for (int k = 0; k < 9; ++k) g2d[item * 9 + k] = 0.0f;
     Cam cam;
     load_cam(cams, v, cam);
     Geo G;

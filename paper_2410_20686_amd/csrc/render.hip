@@ -71,6 +71,47 @@ __device__ inline float sum_rows(float x) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
+// Sum of a value over the eight lanes of an aligned 8-lane group (every lane gets the sum).
+__device__ inline float group8_sum(float x) {
+  x += dpp_read<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_read<0x4E>(x);   // quad_perm [2,3,0,1]
+  return x + dpp_read<0x141>(x);  // row_half_mirror: the other quad of the 8-lane group
+}
+
+// Wavefront sum of one value, in every lane.
+__device__ inline float wave_sum(float x) {
+  x = group8_sum(x);
+  x += dpp_read<0x140>(x);  // row_mirror: the other half of the 16-lane row
+  return sum_rows(x);
+}
+
+// Nine per-lane values summed over the wavefront with most of the data movement in LDS.
+// Values 0..7 go value-major into the wavefront's scratch red[8][kRedStride]; lane 8j+m later
+// reads entries 8m..8m+7 of value j, adds them, and an 8-lane DPP sum completes the total
+// (held by lane 8j).  The reads are issued one accepted entry later, so their latency overlaps
+// that entry's arithmetic; value 8 is summed with DPP directly.  LDS executes one wavefront's
+// operations in order, so only compiler reordering across the wave barriers must be prevented.
+constexpr int kRedStride = 68;  // padded rows (16-byte aligned)
+
+__device__ inline void red_write(float (&red)[8][kRedStride], const float (&g)[9], int lane) {
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) red[q][lane] = g[q];
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline void red_read(const float (&red)[8][kRedStride], int lane, float4& r0, float4& r1) {
+  __builtin_amdgcn_wave_barrier();
+  const int j = lane >> 3, m = lane & 7;
+  r0 = *reinterpret_cast<const float4*>(&red[j][8 * m]);
+  r1 = *reinterpret_cast<const float4*>(&red[j][8 * m + 4]);
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline float red_finish(const float4& r0, const float4& r1) {
+  return group8_sum(((r0.x + r0.y) + (r0.z + r0.w)) + ((r1.x + r1.y) + (r1.z + r1.w)));
+}
+
 __device__ inline float row_reduce9(const float (&g)[9], bool b3, bool b2, bool b1, bool b0) {
   float a[5];
 #pragma unroll
@@ -327,7 +368,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
   if (out_T) out_T[gp] = T;
 }
 
-// g2d layout: [9][items] = d/du, d/dv, d/dS_uu, d/dS_uv, d/dS_vv, d/dopacity, d/dr, d/dg,
+// g2d layout: [items][9] = d/du, d/dv, d/dS_uu, d/dS_uv, d/dS_vv, d/dopacity, d/dr, d/dg,
 // d/db(colour), where Sigma_2D = [[S_uu, S_uv], [S_uv, S_vv]] (S_uv the shared off-diagonal).
 // Accumulating w.r.t. Sigma_2D rather than its inverse keeps the sums well scaled for very
 // anisotropic footprints (no later multiplication by the inverse covariance twice).
@@ -345,7 +386,8 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   constexpr bool kSlots = St::NW <= 4;
   constexpr int NS = kSlots ? St::NW : 1;
   __shared__ St S;
-  __shared__ float acc[NS][9][BATCH];
+  __shared__ float acc[NS][9][BATCH + 1];  // padded rows: the nine slot writes hit nine banks
+  __shared__ float red[kSlots ? St::NW : 1][8][kRedStride];  // per-wavefront reduction scratch
   __shared__ int smax;
   const int g = blockIdx.x;
   const int v = view_of_tile(vt, g);
@@ -392,18 +434,28 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
     // entry e is list position end - 1 - e (back to front)
     stage_batch<TILE, BATCH>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
+    bool pend = false;  // an accepted entry whose values 0..7 still wait in red (uniform)
+    int pk = 0;
+    // software pipeline: the next entry's list index and records are read while this one is
+    // processed, taking two LDS round trips off each iteration's dependency chain
+    int kn = n > 0 ? S.list[wq][0] : 0;  // entries 0..n-1 of the list are valid
+    float4 an = S.s0[kn], bn = S.s1[kn];
     for (int i = 0; i < n; ++i) {
-      const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);  // uniform entry index
+      const int k = __builtin_amdgcn_readfirstlane(kn);  // uniform entry index
+      const float4 a = an, b = bn;
+      kn = S.list[wq][min(i + 1, n - 1)];
+      an = S.s0[kn];
+      bn = S.s1[kn];
       const int jrel = end - 1 - k;
       if (jrel >= wmax) continue;  // uniform: behind every contributor of this wavefront
-      const float4 a = S.s0[k];
-      const float4 b = S.s1[k];
       const float du = wrap_du(px - a.x, Wf, half);
       const float dv = py - a.y;
       const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
       const float power = -fmaf(t1, t1, t2 * t2);
       const bool ok = jrel < last && !(power > 0.0f || power < b.z);
       if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
+      float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+      if (kSlots && pend) red_read(red[wq], lane, r0, r1);  // previous accepted entry's values
       const float G = __expf(power);
       float alpha = b.y * G;
       const bool clamped = alpha > kAlphaMax;
@@ -431,24 +483,36 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       gq[6] = wk * dl0;
       gq[7] = wk * dl1;
       gq[8] = wk * dl2;
-      const float rs = row_reduce9(gq, lane & 8, lane & 4, lane & 2, lane & 1);
       if constexpr (kSlots) {
-        const float ws = sum_rows(rs);
-        if (lane < 16 && slot < 9) acc[wq][slot][k] = ws;
+        if (pend) {
+          const float sj = red_finish(r0, r1);
+          if ((lane & 7) == 0) acc[wq][lane >> 3][pk] = sj;
+        }
+        red_write(red[wq], gq, lane);
+        const float s8 = wave_sum(gq[8]);
+        if (lane == 1) acc[wq][8][k] = s8;
+        pend = true;
+        pk = k;
       } else {
+        const float rs = row_reduce9(gq, lane & 8, lane & 4, lane & 2, lane & 1);
         if (slot < 9) atomicAdd(&acc[0][slot][k], rs);  // 9 lanes per row, 4 rows: one LDS atomic
       }
     }
+    if (kSlots && pend) {
+      float4 r0, r1;
+      red_read(red[wq], lane, r0, r1);
+      const float sj = red_finish(r0, r1);
+      if ((lane & 7) == 0) acc[wq][lane >> 3][pk] = sj;
+    }
     __syncthreads();
-    for (int t = threadIdx.x; t < cnt; t += N) {
-      const uint32_t item = S.sid[t];
+    // nine consecutive lanes carry one entry's nine values, so one atomic instruction covers
+    // about seven items' contiguous 36-byte gradient records instead of 64 scattered lines
+    for (int x = threadIdx.x; x < 9 * cnt; x += N) {
+      const int t = x / 9, q = x - 9 * t;
+      float s = acc[0][q][t];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        float s = acc[0][q][t];
-#pragma unroll
-        for (int w = 1; w < NS; ++w) s += acc[w][q][t];
-        if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)q * items + item], s);
-      }
+      for (int w = 1; w < NS; ++w) s += acc[w][q][t];
+      if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s);
     }
     __syncthreads();
   }
@@ -504,7 +568,7 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
   constexpr bool kSlots = St::NW <= 4;
   constexpr int NS = kSlots ? St::NW : 1;
   __shared__ St S;
-  __shared__ float acc[NS][9][BATCH];
+  __shared__ float acc[NS][9][BATCH + 1];  // padded rows: the nine slot writes hit nine banks
   __shared__ int smax;
   const int g = blockIdx.x;
   const int v = view_of_tile(vt, g);
@@ -588,15 +652,14 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
       }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < cnt; t += N) {
-      const uint32_t item = S.sid[t];
+    // nine consecutive lanes carry one entry's nine values, so one atomic instruction covers
+    // about seven items' contiguous 36-byte gradient records instead of 64 scattered lines
+    for (int x = threadIdx.x; x < 9 * cnt; x += N) {
+      const int t = x / 9, q = x - 9 * t;
+      float s = acc[0][q][t];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        float s = acc[0][q][t];
-#pragma unroll
-        for (int w = 1; w < NS; ++w) s += acc[w][q][t];
-        if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)q * items + item], s);
-      }
+      for (int w = 1; w < NS; ++w) s += acc[w][q][t];
+      if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s);
     }
     __syncthreads();
   }
