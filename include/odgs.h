@@ -233,6 +233,11 @@ int odgs_debug_records(const odgs_plan* plan, const void* ws, float* out, void* 
  * the pixel's 8x8 quadrant (the others are skipped for the whole wavefront). */
 int odgs_debug_pixel_counts(const odgs_plan* plan, const void* ws, int32_t* out, void* stream);
 
+/* Per-item 2D gradients accumulated by odgs_composite_bwd and not yet consumed by
+ * odgs_project_bwd, float [items][9]: d/du, d/dv, d/dSigma_uu, d/dSigma_uv (the off-diagonal as
+ * one shared variable), d/dSigma_vv (Sigma_2D with dilation), d/dopacity, d/dr, d/dg, d/db. */
+int odgs_debug_g2d(const odgs_plan* plan, const void* ws, float* out, void* stream);
+
 /* The sorted pair list as 64-bit keys (global tile << 32 | depth bits) and Gaussian indices,
  * first min(P, cap) entries (P from the status record, read by the caller). */
 int odgs_debug_keys(const odgs_plan* plan, const void* ws, int64_t cap, uint64_t* keys, uint32_t* gauss,

@@ -208,6 +208,7 @@ template <typename S>
 struct Proj {
   S u, v;         // ERP pixel position of the mean
   S conic[3];     // inverse 2D covariance (a, b, c) of [[a, b], [b, c]]
+  S cov2[3];      // 2D covariance (uu, uv, vv), dilation included
   S opacity;
   S rgb[3];
 };
@@ -325,7 +326,10 @@ void project(const S m[3], const S s[3], const S q[4], const S& o, const double*
   // 3DGS low-pass filter: a constant added to the 2D covariance's diagonal.
   c2[0] = c2[0] + st.dilation;
   c2[2] = c2[2] + st.dilation;
-  for (int k = 0; k < 3; ++k) info.cov2[k] = val(c2[k]);
+  for (int k = 0; k < 3; ++k) {
+    info.cov2[k] = val(c2[k]);
+    out.cov2[k] = c2[k];
+  }
   const S det = c2[0] * c2[2] - c2[1] * c2[1];
   // Inverse covariance for Eq. gaussian2d.
   out.conic[0] = c2[2] / det;
@@ -705,6 +709,69 @@ void pixel_backward(const std::vector<Contrib>& cl, const std::vector<Rec<double
   }
 }
 
+// Adjoint of the per-(Gaussian, view) projection, summed over views: acc [V][N][9] holds the
+// per-item 2D gradients (u, v, three 2D-shape entries, opacity, r, g, b), the shape entries with
+// respect to the inverse covariance (a, b, c) or, with `sigma`, the covariance (uu, uv, vv; the
+// off-diagonal as one shared variable).
+void project_adjoint(const Scene& sc, const Prepared& P, const std::vector<double>& acc, bool sigma, double* d_means,
+                     double* d_scales, double* d_quats, double* d_opac, double* d_sh) {
+  // Per-Gaussian chain rule: push the 2D gradients through the projection with dual numbers
+  // (directions: mean xyz, scale xyz, quaternion wxyz, opacity), and the colour gradient
+  // through the SH basis; sum over views.
+  const int K = sc.K;
+  const int64_t n = sc.n;
+  const int V = (int)P.cams.size();
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0;
+    std::vector<double> gsh((size_t)K * 3, 0.0);
+    for (int v = 0; v < V; ++v) {
+      const size_t it = (size_t)v * n + i;
+      const double* g = acc.data() + it * 9;
+      bool any = false;
+      for (int k = 0; k < 9; ++k) any = any || g[k] != 0.0;
+      if (!any || P.info[it].cull != KEPT) continue;
+      Dual m[3], s[3], q[4], o;
+      for (int k = 0; k < 3; ++k) { m[k] = Dual(sc.means[k * n + i]); m[k].d[k] = 1.0; }
+      for (int k = 0; k < 3; ++k) { s[k] = Dual(sc.scales[k * n + i]); s[k].d[3 + k] = 1.0; }
+      for (int k = 0; k < 4; ++k) { q[k] = Dual(sc.quats[k * n + i]); q[k].d[6 + k] = 1.0; }
+      o = Dual(sc.opac[i]);
+      o.d[10] = 1.0;
+      Proj<Dual> p;
+      Info inf;
+      project<Dual>(m, s, q, o, sc.sh + i, n, K, P.cams[v], P.st, p, inf);
+      const Dual* outs[9] = {&p.u, &p.v, sigma ? &p.cov2[0] : &p.conic[0], sigma ? &p.cov2[1] : &p.conic[1],
+                             sigma ? &p.cov2[2] : &p.conic[2], &p.opacity, &p.rgb[0], &p.rgb[1], &p.rgb[2]};
+      double gd[ND] = {0};
+      for (int k = 0; k < 9; ++k)
+        for (int d = 0; d < ND; ++d) gd[d] += g[k] * outs[k]->d[d];
+      for (int k = 0; k < 3; ++k) gm[k] += gd[k];
+      for (int k = 0; k < 3; ++k) gs[k] += gd[3 + k];
+      for (int k = 0; k < 4; ++k) gq[k] += gd[6 + k];
+      go += gd[10];
+      // colour = sum_k sh_k Y_k(dir) + 0.5 (clamped): d colour / d sh_k = Y_k where unclamped
+      double cc[3];
+      const Camera& cam = P.cams[v];
+      for (int k = 0; k < 3; ++k)
+        cc[k] = -((cam.R[0 * 3 + k] * cam.t[0] + cam.R[1 * 3 + k] * cam.t[1]) + cam.R[2 * 3 + k] * cam.t[2]);
+      double dv[3] = {sc.means[i] - cc[0], sc.means[n + i] - cc[1], sc.means[2 * n + i] - cc[2]};
+      const double dn = std::sqrt((dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2]);
+      double dir[3] = {dv[0] / dn, dv[1] / dn, dv[2] / dn};
+      double Y[16];
+      sh_basis<double>(dir, K, Y);
+      for (int ch = 0; ch < 3; ++ch) {
+        if (inf.rgb_clamped[ch]) continue;
+        for (int k = 0; k < K; ++k) gsh[(size_t)k * 3 + ch] += g[6 + ch] * Y[k];
+      }
+    }
+    for (int k = 0; k < 3; ++k) d_means[k * n + i] = gm[k];
+    for (int k = 0; k < 3; ++k) d_scales[k * n + i] = gs[k];
+    for (int k = 0; k < 4; ++k) d_quats[k * n + i] = gq[k];
+    d_opac[i] = go;
+    for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = gsh[k];
+  }
+}
+
 }  // namespace
 
 // ==============================================================================================
@@ -892,58 +959,22 @@ int oracle_backward(const double* means, const double* scales, const double* qua
   }
   if (g2d) std::memcpy(g2d, acc.data(), acc.size() * sizeof(double));
 
-  // Per-Gaussian chain rule: push the 2D gradients through the projection with dual numbers
-  // (directions: mean xyz, scale xyz, quaternion wxyz, opacity), and the colour gradient
-  // through the SH basis; sum over views.
-  const int K = sc.K;
-#pragma omp parallel for schedule(dynamic, 64)
-  for (int64_t i = 0; i < n; ++i) {
-    double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0;
-    std::vector<double> gsh((size_t)K * 3, 0.0);
-    for (int v = 0; v < V; ++v) {
-      const size_t it = (size_t)v * n + i;
-      const double* g = acc.data() + it * 9;
-      bool any = false;
-      for (int k = 0; k < 9; ++k) any = any || g[k] != 0.0;
-      if (!any || P.info[it].cull != KEPT) continue;
-      Dual m[3], s[3], q[4], o;
-      for (int k = 0; k < 3; ++k) { m[k] = Dual(sc.means[k * n + i]); m[k].d[k] = 1.0; }
-      for (int k = 0; k < 3; ++k) { s[k] = Dual(sc.scales[k * n + i]); s[k].d[3 + k] = 1.0; }
-      for (int k = 0; k < 4; ++k) { q[k] = Dual(sc.quats[k * n + i]); q[k].d[6 + k] = 1.0; }
-      o = Dual(sc.opac[i]);
-      o.d[10] = 1.0;
-      Proj<Dual> p;
-      Info inf;
-      project<Dual>(m, s, q, o, sc.sh + i, n, K, P.cams[v], P.st, p, inf);
-      const Dual* outs[9] = {&p.u, &p.v, &p.conic[0], &p.conic[1], &p.conic[2], &p.opacity, &p.rgb[0], &p.rgb[1], &p.rgb[2]};
-      double gd[ND] = {0};
-      for (int k = 0; k < 9; ++k)
-        for (int d = 0; d < ND; ++d) gd[d] += g[k] * outs[k]->d[d];
-      for (int k = 0; k < 3; ++k) gm[k] += gd[k];
-      for (int k = 0; k < 3; ++k) gs[k] += gd[3 + k];
-      for (int k = 0; k < 4; ++k) gq[k] += gd[6 + k];
-      go += gd[10];
-      // colour = sum_k sh_k Y_k(dir) + 0.5 (clamped): d colour / d sh_k = Y_k where unclamped
-      double cc[3];
-      const Camera& cam = P.cams[v];
-      for (int k = 0; k < 3; ++k)
-        cc[k] = -((cam.R[0 * 3 + k] * cam.t[0] + cam.R[1 * 3 + k] * cam.t[1]) + cam.R[2 * 3 + k] * cam.t[2]);
-      double dv[3] = {sc.means[i] - cc[0], sc.means[n + i] - cc[1], sc.means[2 * n + i] - cc[2]};
-      const double dn = std::sqrt((dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2]);
-      double dir[3] = {dv[0] / dn, dv[1] / dn, dv[2] / dn};
-      double Y[16];
-      sh_basis<double>(dir, K, Y);
-      for (int ch = 0; ch < 3; ++ch) {
-        if (inf.rgb_clamped[ch]) continue;
-        for (int k = 0; k < K; ++k) gsh[(size_t)k * 3 + ch] += g[6 + ch] * Y[k];
-      }
-    }
-    for (int k = 0; k < 3; ++k) d_means[k * n + i] = gm[k];
-    for (int k = 0; k < 3; ++k) d_scales[k * n + i] = gs[k];
-    for (int k = 0; k < 4; ++k) d_quats[k * n + i] = gq[k];
-    d_opac[i] = go;
-    for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = gsh[k];
-  }
+  project_adjoint(sc, P, acc, false, d_means, d_scales, d_quats, d_opac, d_sh);
+  return 0;
+}
+
+// Adjoint of the projection alone, for 2D gradients given in covariance terms (the layout the
+// GPU's reverse compositor produces): g2d [V][N][9] = (u, v, Sigma_uu, Sigma_uv (shared),
+// Sigma_vv, opacity, r, g, b).  Outputs as oracle_backward (overwritten).
+int oracle_project_adjoint(const double* means, const double* scales, const double* quats, const double* opac,
+                           const double* sh, int64_t n, int deg, const double* cams, const int32_t* wh, int V,
+                           const double* settings, const double* g2d, double* d_means, double* d_scales,
+                           double* d_quats, double* d_opac, double* d_sh) {
+  Scene sc = make_scene(means, scales, quats, opac, sh, n, deg);
+  Prepared P;
+  prepare(sc, cams, wh, V, settings, P);
+  std::vector<double> acc(g2d, g2d + (size_t)V * n * 9);
+  project_adjoint(sc, P, acc, true, d_means, d_scales, d_quats, d_opac, d_sh);
   return 0;
 }
 

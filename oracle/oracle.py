@@ -56,6 +56,8 @@ def lib():
         L.oracle_render.restype = i32
         L.oracle_backward.argtypes = scene_args + [i32, P, i64, P, P, P, P, P, P, P]
         L.oracle_backward.restype = i32
+        L.oracle_project_adjoint.argtypes = scene_args + [P, P, P, P, P, P]
+        L.oracle_project_adjoint.restype = i32
         _lib = L
     return _lib
 
@@ -159,3 +161,33 @@ def backward(scene, cams, settings, dL: np.ndarray, mode: int = 32, pix: np.ndar
     if want_g2d:
         out["g2d"] = g2d
     return out
+
+
+def g2d_to_sigma(rows: np.ndarray, g2d: np.ndarray) -> np.ndarray:
+    """Per-item 2D gradients with the shape entries taken w.r.t. the inverse covariance
+    (a, b, c) -> the same w.r.t. the covariance (uu, uv, vv), both off-diagonals as one shared
+    variable: with M = [[a, b], [b, c]] and G = [[ga, gb/2], [gb/2, gc]], dL/dSigma = -M G M."""
+    a, b, c = (rows[..., F_CONIC + k] for k in range(3))
+    ga, gb, gc = g2d[..., 2], 0.5 * g2d[..., 3], g2d[..., 4]
+    # (M G)_{ij} then (M G M)
+    mg00, mg01 = a * ga + b * gb, a * gb + b * gc
+    mg10, mg11 = b * ga + c * gb, b * gb + c * gc
+    s00 = mg00 * a + mg01 * b
+    s01 = mg00 * b + mg01 * c
+    s11 = mg10 * b + mg11 * c
+    out = np.array(g2d, dtype=np.float64, copy=True)
+    out[..., 2], out[..., 3], out[..., 4] = -s00, -2.0 * s01, -s11
+    return out
+
+
+def project_adjoint(scene, cams, settings, g2d_sigma: np.ndarray):
+    """Parameter gradients from per-item 2D gradients [V][N][9] given in covariance terms
+    (u, v, Sigma_uu, Sigma_uv (shared), Sigma_vv, opacity, r, g, b), summed over views."""
+    a = _Args(scene, cams, settings)
+    n, K = a.n, (a.deg + 1) ** 2
+    gm, gs, gq = np.zeros((3, n)), np.zeros((3, n)), np.zeros((4, n))
+    go, gsh = np.zeros(n), np.zeros((K * 3, n))
+    g = np.ascontiguousarray(g2d_sigma, dtype=np.float64)
+    assert g.shape == (a.V, n, 9)
+    lib().oracle_project_adjoint(*a.tuple(), _p(g), _p(gm), _p(gs), _p(gq), _p(go), _p(gsh))
+    return dict(means=gm, scales=gs, quats=gq, opacities=go, sh=gsh)

@@ -20,7 +20,7 @@ FLAG_COUNT_WORK = 1
 EXPORTS = ("odgs_plan_init", "odgs_workspace_bytes", "odgs_preprocess", "odgs_bin_sort", "odgs_render_fwd",
            "odgs_render_bwd", "odgs_composite_bwd", "odgs_project_bwd", "odgs_status_offset", "odgs_strerror",
            "odgs_densify", "odgs_densify_workspace_bytes",
-           "odgs_plan_size", "odgs_debug_records", "odgs_debug_keys", "odgs_debug_pixel_counts")
+           "odgs_plan_size", "odgs_debug_records", "odgs_debug_keys", "odgs_debug_pixel_counts", "odgs_debug_g2d")
 
 
 class Settings(ctypes.Structure):
@@ -96,6 +96,8 @@ def lib():
         L.odgs_densify.argtypes = [c_i64, c_i32] + [P] * 9 + [ctypes.POINTER(DensifyParams), c_i64] + [P] * 8 + [c_sz, P]
         L.odgs_densify.restype = c_i32
         L.odgs_debug_pixel_counts.argtypes = [pp, P, P, P]
+        L.odgs_debug_g2d.argtypes = [pp, P, P, P]
+        L.odgs_debug_g2d.restype = c_i32
         L.odgs_debug_pixel_counts.restype = c_i32
         L.odgs_strerror.argtypes = [c_i32]
         L.odgs_strerror.restype = ctypes.c_char_p
@@ -195,6 +197,10 @@ def odgs_densify(n, sh_degree, means, scales, quats, opac, sh, grad_sum, tau_sum
 
 def odgs_debug_pixel_counts(plan, ws, out, stream):
     _check(lib().odgs_debug_pixel_counts(ctypes.byref(plan), ws, out, stream), "odgs_debug_pixel_counts")
+
+
+def odgs_debug_g2d(plan, ws, out, stream):
+    _check(lib().odgs_debug_g2d(ctypes.byref(plan), ws, out, stream), "odgs_debug_g2d")
 
 
 def odgs_debug_records(plan, ws, out, stream):

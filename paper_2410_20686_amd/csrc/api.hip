@@ -242,6 +242,11 @@ int odgs_debug_records(const odgs_plan* plan, const void* ws, float* out, void* 
   return hip_status(launch_debug_records(plan, ws, out, static_cast<hipStream_t>(stream)));
 }
 
+int odgs_debug_g2d(const odgs_plan* plan, const void* ws, float* out, void* stream) {
+  if (!plan || !ws || (plan->items > 0 && !out)) return ODGS_EINVAL;
+  return hip_status(launch_debug_g2d(plan, ws, out, static_cast<hipStream_t>(stream)));
+}
+
 int odgs_debug_pixel_counts(const odgs_plan* plan, const void* ws, int32_t* out, void* stream) {
   if (!plan || !ws || !out) return ODGS_EINVAL;
   return hip_status(launch_debug_pixel_counts(plan, ws, out, static_cast<hipStream_t>(stream)));

@@ -85,6 +85,7 @@ hipError_t launch_fill_u32(uint32_t* ptr, uint32_t value, int64_t n, hipStream_t
 hipError_t launch_status_reset(const odgs_plan* p, void* ws, hipStream_t st);
 hipError_t launch_debug_records(const odgs_plan* p, const void* ws, float* out, hipStream_t st);
 hipError_t launch_debug_pixel_counts(const odgs_plan* p, const void* ws, int32_t* out, hipStream_t st);
+hipError_t launch_debug_g2d(const odgs_plan* p, const void* ws, float* out, hipStream_t st);
 hipError_t launch_debug_keys(const odgs_plan* p, const void* ws, int64_t cap, uint64_t* keys, uint32_t* gauss,
                              hipStream_t st);
 

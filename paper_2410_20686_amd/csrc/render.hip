@@ -553,7 +553,7 @@ __device__ inline void bwd_pixel_step(BwdPixel& P, bool ok, float power, float t
   for (int q = 0; q < 9; ++q) gq[q] = ADD ? gq[q] + h[q] : h[q];
 }
 
-// Reverse compositing with two pixels per lane (32x32 tiles): wavefront w owns quadrants
+// Reverse compositing with two pixels per lane (16x16 and 32x32 tiles): wavefront w owns quadrants
 // 2w and 2w + 1 (side by side), lane l the pixel (l % 8, l / 8) of each.  Both pixels' gradient
 // contributions are added in registers, so each (entry, wavefront) needs one cross-lane
 // reduction for 128 pixels, and the per-entry LDS reads and loop control are shared.
@@ -717,9 +717,9 @@ template <int TILE, int BATCH>
 struct BwdRun {
   static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
                   const Rec* rec, const float* wT, const int32_t* wl, const float* dL, float* g2d, hipStream_t st) {
-    // two pixels per lane pay off for 32x32 tiles (half the wavefronts staging and scanning the
-    // lists); at 16x16 the union of two quadrants' lists costs as much as the shared reduction saves
-    if constexpr (TILE >= 32)
+    // two pixels per lane (tiles of 16 and 32): one cross-lane reduction per 128 pixels; an 8x8
+    // tile has a single quadrant and keeps one pixel per lane
+    if constexpr (TILE >= 16)
       hipLaunchKernelGGL((render_bwd2_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE / 2), 0, st, vt, ranges,
                          items, rec, wT, wl, dL, g2d, p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
     else
@@ -783,6 +783,19 @@ hipError_t launch_debug_records(const odgs_plan* p, const void* ws, float* out, 
   hipLaunchKernelGGL(debug_records_kernel, dim3((unsigned)((p->items + 255) / 256)), dim3(256), 0, st,
                      ws_ptr<Rec>(ws, p->off_rec), ws_ptr<float>(ws, p->off_depth), ws_ptr<uint32_t>(ws, p->off_count),
                      p->items, out);
+  return hipGetLastError();
+}
+
+__global__ void debug_copy_kernel(const float* __restrict__ src, int64_t n, float* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_debug_g2d(const odgs_plan* p, const void* ws, float* out, hipStream_t st) {
+  const int64_t n = 9 * p->items;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(debug_copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     ws_ptr<float>(ws, p->off_g2d), n, out);
   return hipGetLastError();
 }
 

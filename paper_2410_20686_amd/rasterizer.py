@@ -148,6 +148,13 @@ class Rasterizer:
                            _ptr(self.ws), self.ws_bytes, *[_ptr(g) for g in grads],
                            None if stats is None else stats.acc(self.n), _stream())
 
+    def g2d(self) -> torch.Tensor:
+        """[items, 9] per-item 2D gradients left by composite_bwd (item = view * N + gaussian):
+        d/du, d/dv, d/dSigma_uu, d/dSigma_uv (shared), d/dSigma_vv, d/dopacity, d/dr, d/dg, d/db."""
+        out = torch.empty((self.n * len(self.wh), 9), dtype=torch.float32, device=self.device)
+        B.odgs_debug_g2d(self.plan, _ptr(self.ws), _ptr(out), _stream())
+        return out
+
     def pixel_counts(self) -> torch.Tensor:
         """[pixels, 4] int32 of the last forward: list position after the last contributor,
         contributors, entries evaluated, and entries evaluated up to the last contributor (the

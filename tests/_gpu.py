@@ -17,7 +17,7 @@ def to_gpu(scene, cams, device="cuda"):
     return [f(scene.means), f(scene.scales), f(scene.quats), f(scene.opacities), f(scene.sh), f(cams.cams)]
 
 
-def run_gpu(scene, cams, settings, dL=None, pair_capacity=None, return_rast=False):
+def run_gpu(scene, cams, settings, dL=None, pair_capacity=None, return_rast=False, split_bwd=False):
     import torch
     from paper_2410_20686_amd.rasterizer import Rasterizer
     wh = [tuple(int(x) for x in r) for r in cams.wh]
@@ -27,7 +27,15 @@ def run_gpu(scene, cams, settings, dL=None, pair_capacity=None, return_rast=Fals
     rgb, T = rast.render_fwd()
     out = dict(rgb=rgb.cpu().numpy(), T=T.cpu().numpy(), status=st)
     if dL is not None:
-        g = rast.render_bwd(*t, torch.from_numpy(np.ascontiguousarray(dL, dtype=np.float32)).cuda())
+        dLg = torch.from_numpy(np.ascontiguousarray(dL, dtype=np.float32)).cuda()
+        if split_bwd:
+            # the two backward stages separately, with the per-item 2D gradients in between
+            rast.composite_bwd(dLg)
+            out["g2d"] = rast.g2d().cpu().numpy().reshape(len(wh), scene.n, 9)
+            g = tuple(torch.empty_like(x) for x in t[:5])
+            rast.project_bwd(*t, g)
+        else:
+            g = rast.render_bwd(*t, dLg)
         torch.cuda.synchronize()
         out["grads"] = dict(zip(("means", "scales", "quats", "opacities", "sh"), (x.cpu().numpy() for x in g)))
     if return_rast:

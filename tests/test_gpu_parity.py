@@ -132,17 +132,27 @@ def _masked_upstream(cams, margin, seed):
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_backward_matches_oracle(case):
+    """Both backward stages against the oracle: the reverse compositor's per-item 2D gradients
+    (float sums over pixels) at the gradient tolerance; the projection adjoint applied to those
+    very 2D gradients exactly (both sides in double); and the end-to-end parameter gradients."""
     name, sc, cams, st = case
     fwd = O.render(sc, cams, st, mode=32)
     dL = _masked_upstream(cams, fwd["margin"], seed=1000)
-    res = G.run_gpu(sc, cams, st, dL=dL)
-    ref = O.backward(sc, cams, st, dL, mode=32)
-    # Needles (axis ratios up to ~500:1): the long-axis scale gradient and the rotation gradient
-    # contract the 3D covariance gradient along the long axis, a cancellation of terms ~1e5
-    # times larger, so float rounding of the per-pixel 2D gradients (~1e-7) shows up there at
-    # ~1e-3; those are bounded by 1e-4 of the same Gaussian's largest component.
-    extra = {"scales": 1e-4, "quats": 1e-4} if name == "needles" else None
-    rep = G.assert_grads_close(res["grads"], ref, per_gaussian_floor=extra)
+    res = G.run_gpu(sc, cams, st, dL=dL, split_bwd=True)
+    ref = O.backward(sc, cams, st, dL, mode=32, want_g2d=True)
+    rows = O.project(sc, cams, st)
+    ref2d = O.g2d_to_sigma(rows, ref["g2d"])
+    labels = ("u", "v", "S_uu", "S_uv", "S_vv", "opacity", "r", "g", "b")
+    G.assert_grads_close({k: res["g2d"][..., j] for j, k in enumerate(labels)},
+                         {k: ref2d[..., j] for j, k in enumerate(labels)}, names=labels)
+    adj = O.project_adjoint(sc, cams, st, res["g2d"].astype(np.float64))
+    G.assert_grads_close(res["grads"], adj, rtol=1e-5, floor=1e-7)
+    # Needles (axis ratios up to 800:1): their scale and rotation gradients contract the 3D
+    # covariance gradient along the long axis, cancelling terms up to ~1e5 times larger, so the
+    # float rounding of the 2D gradients checked above (~1e-7 relative) is amplified beyond 1e-3
+    # there; for those two the stage checks above are the parity statement.
+    names = ("means", "opacities", "sh") if name == "needles" else ("means", "scales", "quats", "opacities", "sh")
+    rep = G.assert_grads_close(res["grads"], ref, names=names)
     print(name, rep)
 
 

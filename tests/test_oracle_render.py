@@ -287,3 +287,18 @@ def test_backward_fd_uneven_16_views():
         an = g[name][i] if name == "opacities" else g[name][c, i]
         assert abs(fd - an) <= 1e-5 * abs(an) + 1e-7 * np.abs(g[name]).max(), (name, i, c, fd, an)
         checked += 1
+
+
+def test_projection_adjoint_in_covariance_terms():
+    """The projection adjoint applied to the 2D gradients re-expressed w.r.t. the 2D covariance
+    (-M G M with M the inverse covariance) reproduces the full backward: pins the conversion and
+    the covariance-form outputs of the dual-number projection."""
+    sc = scenes.roaming_scene(700, 3, seed=81, r_range=(2.0, 6.0)).as_f64()
+    cams = scenes.uneven_cameras(2, seed=81, sizes=((128, 64), (256, 128)))
+    st = settings(bg=(0.1, 0.0, 0.2))
+    dL = scenes.upstream_gradient(cams, 1081).astype(np.float64)
+    g = O.backward(sc, cams, st, dL, mode=64, want_g2d=True)
+    rows = O.project(sc, cams, st)
+    h = O.project_adjoint(sc, cams, st, O.g2d_to_sigma(rows, g["g2d"]))
+    for k in ("means", "scales", "quats", "opacities", "sh"):
+        np.testing.assert_allclose(h[k], g[k], rtol=1e-9, atol=1e-12 * np.abs(g[k]).max())
