@@ -238,8 +238,11 @@ def main():
     roof = None
     if dom in alg_ops:
         achieved = alg_ops[dom] / (stages[dom] / 1e3) / 1e12
-        kname = "odgs::render_bwd_kernel<%d, %d>" % (st["tile"], rast.plan.s.batch_bwd) if dom == "composite_bwd" \
-            else "odgs::render_fwd_kernel<%d, %d>" % (st["tile"], rast.plan.s.batch)
+        if dom == "composite_bwd":  # two pixels per lane from 16x16 tiles up
+            kname = "odgs::render_bwd%s_kernel<%d, %d>" % ("2" if st["tile"] >= 16 else "", st["tile"],
+                                                          rast.plan.s.batch_bwd)
+        else:
+            kname = "odgs::render_fwd_kernel<%d, %d, false>" % (st["tile"], rast.plan.s.batch)
         roof = dict(bound="alu", kernel=dom, achieved=round(achieved, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Top/s",
                     frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=measured_traffic(kname),
                     work=dict(tests=evals_bwd if dom == "composite_bwd" else evals_fwd, accepts=contrib_total,
