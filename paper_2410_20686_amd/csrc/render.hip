@@ -368,6 +368,102 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
   if (out_T) out_T[gp] = T;
 }
 
+// Forward compositing state of one pixel.
+struct FwdPixel {
+  float T, C0, C1, C2;
+  int last;
+  bool done;
+};
+
+// One Gaussian's front-to-back step for one pixel (Eq. alphablending with the 3DGS constants).
+__device__ inline void fwd_pixel_step(FwdPixel& P, bool ok, float power, const float4& b, const float4& c, int pos) {
+  float alpha = b.y * __expf(power);
+  alpha = alpha > kAlphaMax ? kAlphaMax : alpha;
+  const float Tn = P.T * (1.0f - alpha);
+  const bool stop = ok && Tn < kTStop;
+  const bool acc = ok && !(Tn < kTStop);
+  P.done = P.done || stop;
+  const float w = acc ? alpha * P.T : 0.0f;
+  P.C0 = fmaf(w, c.x, P.C0);
+  P.C1 = fmaf(w, c.y, P.C1);
+  P.C2 = fmaf(w, c.z, P.C2);
+  P.T = acc ? Tn : P.T;
+  P.last = acc ? pos : P.last;
+}
+
+// Forward compositing with two pixels per lane (32x32 tiles), the layout of the two-pixel
+// reverse compositor: wavefront w owns quadrants 2w and 2w + 1, lane l pixel (l % 8, l / 8) of
+// each.  Two independent pixel chains per lane share each entry's list index and record reads.
+template <int TILE, int BATCH>
+__global__ __launch_bounds__(TILE* TILE / 2) void render_fwd2_kernel(
+    ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
+    float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
+    float bg0, float bg1, float bg2) {
+  using St = Stage<TILE, BATCH, 2>;
+  constexpr int N = St::N;
+  constexpr int QPR = TILE / 8;
+  __shared__ St S;
+  const int g = blockIdx.x;
+  const int v = view_of_tile(vt, g);
+  const int W = vt.W[v], H = vt.H[v];
+  const int ntx = W / TILE;
+  const int lt = g - vt.tile_base[v];
+  const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int qa = 2 * wq;
+  const int x = tx0 + (qa % QPR) * 8 + (lane & 7), y = ty0 + (qa / QPR) * 8 + (lane >> 3);
+  const float pxa = (float)x + 0.5f, pxb = (float)(x + 8) + 0.5f, py = (float)y + 0.5f;
+  const float Wf = (float)W, half = (float)W * 0.5f;
+  const uint2 rg = ranges[g];
+  FwdPixel A{1.0f, 0.0f, 0.0f, 0.0f, 0, false}, B{1.0f, 0.0f, 0.0f, 0.0f, 0, false};
+  for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
+    if (__syncthreads_count(A.done && B.done) == N) break;
+    const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
+    int nq[St::NQ];
+    stage_batch<TILE, BATCH, 2>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq);
+    const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
+    for (int i = 0; i < n; ++i) {
+      if (__builtin_amdgcn_ballot_w64(!(A.done && B.done)) == 0ull) break;  // uniform
+      const int k = S.list[wq][i];
+      const float4 a = S.s0[k];
+      const float4 b = S.s1[k];
+      const float dv = py - a.y;
+      const float l1dv = a.w * dv, t2 = b.x * dv, t22 = t2 * t2;
+      const float dua = wrap_du(pxa - a.x, Wf, half), dub = wrap_du(pxb - a.x, Wf, half);
+      const float t1a = fmaf(a.z, dua, l1dv), t1b = fmaf(a.z, dub, l1dv);
+      const float pa = -fmaf(t1a, t1a, t22), pb = -fmaf(t1b, t1b, t22);
+      const bool oka = !A.done && !(pa > 0.0f || pa < b.z);
+      const bool okb = !B.done && !(pb > 0.0f || pb < b.z);
+      const bool anya = __builtin_amdgcn_ballot_w64(oka) != 0ull;  // uniform
+      const bool anyb = __builtin_amdgcn_ballot_w64(okb) != 0ull;
+      if (!anya && !anyb) continue;
+      const float4 c = S.s2[k];
+      const int pos = (int)(base - rg.x) + k + 1;
+      if (anya) fwd_pixel_step(A, oka, pa, b, c, pos);
+      if (anyb) fwd_pixel_step(B, okb, pb, b, c, pos);
+    }
+  }
+  const int64_t plane = (int64_t)W * H;
+  const int64_t pix = (int64_t)y * W + x;
+  float* img = out_rgb + 3 * vt.pix_base[v];
+  img[pix] = fmaf(A.T, bg0, A.C0);
+  img[plane + pix] = fmaf(A.T, bg1, A.C1);
+  img[2 * plane + pix] = fmaf(A.T, bg2, A.C2);
+  img[pix + 8] = fmaf(B.T, bg0, B.C0);
+  img[plane + pix + 8] = fmaf(B.T, bg1, B.C1);
+  img[2 * plane + pix + 8] = fmaf(B.T, bg2, B.C2);
+  const int64_t gp = vt.pix_base[v] + pix;
+  ws_T[gp] = A.T;
+  ws_T[gp + 8] = B.T;
+  ws_last[gp] = A.last;
+  ws_last[gp + 8] = B.last;
+  if (out_T) {
+    out_T[gp] = A.T;
+    out_T[gp + 8] = B.T;
+  }
+}
+
 // g2d layout: [items][9] = d/du, d/dv, d/dS_uu, d/dS_uv, d/dS_vv, d/dopacity, d/dr, d/dg,
 // d/db(colour), where Sigma_2D = [[S_uu, S_uv], [S_uv, S_vv]] (S_uv the shared off-diagonal).
 // Accumulating w.r.t. Sigma_2D rather than its inverse keeps the sums well scaled for very
@@ -704,9 +800,13 @@ struct FwdRun {
   static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
                   const Rec* rec, float* out_rgb, float* out_T, float* wT, int32_t* wl, int32_t* wn, int32_t* we,
                   int32_t* wle, hipStream_t st) {
+    // the counting variant keeps one pixel per lane, so its counters are per 8x8 quadrant
     if (p->s.flags & ODGS_FLAG_COUNT_WORK)
       hipLaunchKernelGGL((render_fwd_kernel<TILE, BATCH, true>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges,
                          items, rec, out_rgb, out_T, wT, wl, wn, we, wle, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+    else if constexpr (TILE >= 32)  // at 16x16 the union of two quadrants' lists costs more than it saves
+      hipLaunchKernelGGL((render_fwd2_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE / 2), 0, st, vt, ranges,
+                         items, rec, out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
     else
       hipLaunchKernelGGL((render_fwd_kernel<TILE, BATCH, false>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges,
                          items, rec, out_rgb, out_T, wT, wl, wn, we, wle, p->s.bg[0], p->s.bg[1], p->s.bg[2]);

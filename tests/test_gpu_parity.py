@@ -219,3 +219,24 @@ def test_work_counters(case):
     plain = G.run_gpu(sc, cams, st, return_rast=True)
     np.testing.assert_array_equal(plain["rgb"], res["rgb"])
     np.testing.assert_array_equal(plain["rast"].pixel_counts().cpu().numpy()[:, 0], cnt[:, 0])
+
+
+@pytest.mark.parametrize("tile,batch", [(8, 32), (8, 256), (32, 64), (32, 256)])
+def test_other_tiles_forward_and_backward(tile, batch):
+    """The other compositor instances: one pixel per lane at 8x8 tiles, two pixels per lane with
+    shared LDS slots at 32x32 tiles, at the smallest and largest LDS batches."""
+    name, sc, cams, st = CASES[1]
+    st = dict(st, tile=tile, batch=batch, batch_bwd=batch)
+    fwd = O.render(sc, cams, st, mode=32)
+    dL = _masked_upstream(cams, fwd["margin"], seed=1007)
+    res = G.run_gpu(sc, cams, st, dL=dL, split_bwd=True)
+    ok = G.strict_pixels(fwd["margin"])
+    assert np.abs(res["T"] - fwd["T"])[ok].max() <= G.RGB_ATOL
+    okc = np.concatenate([np.tile(ok[o:o + w * h], 3) for o, w, h in _views(cams)])
+    assert np.abs(res["rgb"] - fwd["rgb"])[okc].max() <= G.RGB_ATOL
+    ref = O.backward(sc, cams, st, dL, mode=32, want_g2d=True)
+    ref2d = O.g2d_to_sigma(O.project(sc, cams, st), ref["g2d"])
+    labels = ("u", "v", "S_uu", "S_uv", "S_vv", "opacity", "r", "g", "b")
+    G.assert_grads_close({k: res["g2d"][..., j] for j, k in enumerate(labels)},
+                         {k: ref2d[..., j] for j, k in enumerate(labels)}, names=labels)
+    G.assert_grads_close(res["grads"], ref)
