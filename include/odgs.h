@@ -208,6 +208,47 @@ int odgs_densify(int64_t n, int32_t sh_degree, const float* means, const float* 
                  int64_t capacity, float* out_means, float* out_scales, float* out_quats, float* out_opacities,
                  float* out_sh, int32_t* out_src, int64_t* out_counts, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- training step around the rasterizer (the 3DGS recipe the paper keeps) ---------------- */
+
+/* Device pointers to the five parameter arrays (layouts as above). */
+typedef struct odgs_param_ptrs {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opacities;
+  float* sh;
+} odgs_param_ptrs;
+
+typedef struct odgs_adam_hyper {
+  float beta1, beta2, eps;  /* 3DGS: 0.9, 0.999, 1e-15 */
+} odgs_adam_hyper;
+
+/* Device workspace bytes odgs_l1_loss needs for `count` image values (256-byte aligned base). */
+size_t odgs_l1_loss_workspace_bytes(int64_t count);
+
+/* Image loss L = mean |rgb - target| over `count` values (any layout, both arrays alike):
+ * writes dL/drgb = sign(rgb - target) / count (0 where equal) into dL (may feed
+ * odgs_render_bwd) and L into loss[0] (device float), summed in double in a fixed order. */
+int odgs_l1_loss(const float* rgb, const float* target, int64_t count, float* dL, float* loss, void* ws,
+                 size_t ws_bytes, void* stream);
+
+/* One Adam step (Kingma & Ba; PyTorch's placement of eps) over parameters kept before their
+ * activations: raw scales are log-scales (scale = exp(raw)), raw opacities logits (opacity =
+ * sigmoid(raw)); means, quaternions and SH coefficients are their own raw values.
+ *   grad: gradients w.r.t. the ACTIVATED parameters (as odgs_render_bwd writes them); chained
+ *         through the activations with the activated values in `act`;
+ *   m, v: first and second moments (same layouts), updated;
+ *   raw:  updated in place; act: overwritten with the new activated values (for identity groups
+ *         act may alias raw);
+ *   lr:   device float[6], learning rates of means, raw scales, quaternions, raw opacities, SH DC
+ *         planes (k = 0) and the other SH planes;
+ *   step: device int32 step counter t (read as t, the update uses t + 1, then incremented), so a
+ *         captured HIP graph can be replayed step after step. */
+int odgs_adam_step(int64_t n, int32_t sh_degree, const odgs_param_ptrs* raw /*[host]*/,
+                   const odgs_param_ptrs* act /*[host]*/, const odgs_param_ptrs* grad /*[host]*/,
+                   const odgs_param_ptrs* m /*[host]*/, const odgs_param_ptrs* v /*[host]*/, const float* lr,
+                   int32_t* step, const odgs_adam_hyper* hp /*[host]*/, void* stream);
+
 /* Byte offset of the odgs_status record inside the workspace. */
 size_t odgs_status_offset(const odgs_plan* plan /*[host]*/);
 

@@ -19,7 +19,8 @@ FLAG_COUNT_WORK = 1
 
 EXPORTS = ("odgs_plan_init", "odgs_workspace_bytes", "odgs_preprocess", "odgs_bin_sort", "odgs_render_fwd",
            "odgs_render_bwd", "odgs_composite_bwd", "odgs_project_bwd", "odgs_status_offset", "odgs_strerror",
-           "odgs_densify", "odgs_densify_workspace_bytes",
+           "odgs_densify", "odgs_densify_workspace_bytes", "odgs_l1_loss", "odgs_l1_loss_workspace_bytes",
+           "odgs_adam_step",
            "odgs_plan_size", "odgs_debug_records", "odgs_debug_keys", "odgs_debug_pixel_counts", "odgs_debug_g2d")
 
 
@@ -32,6 +33,15 @@ class Settings(ctypes.Structure):
 class DensifyAcc(ctypes.Structure):
     _fields_ = [("grad_sum", ctypes.c_void_p), ("tau_sum", ctypes.c_void_p), ("count", ctypes.c_void_p),
                 ("tau_min", ctypes.c_float), ("tau_max", ctypes.c_float)]
+
+
+class ParamPtrs(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("opacities", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+
+
+class AdamHyper(ctypes.Structure):
+    _fields_ = [("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 
 class DensifyParams(ctypes.Structure):
@@ -95,6 +105,13 @@ def lib():
         L.odgs_densify_workspace_bytes.restype = c_sz
         L.odgs_densify.argtypes = [c_i64, c_i32] + [P] * 9 + [ctypes.POINTER(DensifyParams), c_i64] + [P] * 8 + [c_sz, P]
         L.odgs_densify.restype = c_i32
+        L.odgs_l1_loss_workspace_bytes.argtypes = [c_i64]
+        L.odgs_l1_loss_workspace_bytes.restype = c_sz
+        L.odgs_l1_loss.argtypes = [P, P, c_i64, P, P, P, c_sz, P]
+        L.odgs_l1_loss.restype = c_i32
+        pptr = ctypes.POINTER(ParamPtrs)
+        L.odgs_adam_step.argtypes = [c_i64, c_i32, pptr, pptr, pptr, pptr, pptr, P, P, ctypes.POINTER(AdamHyper), P]
+        L.odgs_adam_step.restype = c_i32
         L.odgs_debug_pixel_counts.argtypes = [pp, P, P, P]
         L.odgs_debug_g2d.argtypes = [pp, P, P, P]
         L.odgs_debug_g2d.restype = c_i32
@@ -182,6 +199,21 @@ def odgs_project_bwd(plan, means, scales, quats, opac, sh, cams, ws, ws_bytes, d
     """acc: DensifyAcc or None."""
     _check(lib().odgs_project_bwd(ctypes.byref(plan), means, scales, quats, opac, sh, cams, ws, ws_bytes, d_means,
                                   d_scales, d_quats, d_opac, d_sh, _acc_ref(acc), stream), "odgs_project_bwd")
+
+
+def odgs_l1_loss_workspace_bytes(count: int) -> int:
+    return int(lib().odgs_l1_loss_workspace_bytes(int(count)))
+
+
+def odgs_l1_loss(rgb, target, count, dL, loss, ws, ws_bytes, stream):
+    _check(lib().odgs_l1_loss(rgb, target, int(count), dL, loss, ws, ws_bytes, stream), "odgs_l1_loss")
+
+
+def odgs_adam_step(n, sh_degree, raw: ParamPtrs, act: ParamPtrs, grad: ParamPtrs, m: ParamPtrs, v: ParamPtrs, lr, step,
+                   hyper: AdamHyper, stream):
+    _check(lib().odgs_adam_step(int(n), int(sh_degree), ctypes.byref(raw), ctypes.byref(act), ctypes.byref(grad),
+                                ctypes.byref(m), ctypes.byref(v), lr, step, ctypes.byref(hyper), stream),
+           "odgs_adam_step")
 
 
 def odgs_densify_workspace_bytes(n: int) -> int:

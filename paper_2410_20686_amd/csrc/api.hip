@@ -185,6 +185,41 @@ int odgs_project_bwd(const odgs_plan* plan, const float* means, const float* sca
                                           d_quats, d_opacities, d_sh, acc, static_cast<hipStream_t>(stream)));
 }
 
+size_t odgs_l1_loss_workspace_bytes(int64_t count) { return count < 0 ? 0 : l1_workspace_bytes(count); }
+
+int odgs_l1_loss(const float* rgb, const float* target, int64_t count, float* dL, float* loss, void* ws,
+                 size_t ws_bytes, void* stream) {
+  if (count < 0 || !loss || !aligned(loss, 4) || !ws || !aligned(ws, 256)) return ODGS_EINVAL;
+  if (count > 0 && (!rgb || !target || !dL || !aligned(rgb, 4) || !aligned(target, 4) || !aligned(dL, 4)))
+    return ODGS_EINVAL;
+  if (ws_bytes < l1_workspace_bytes(count)) return ODGS_ENOSPACE;
+  return hip_status(launch_l1(rgb, target, count, dL, loss, ws, static_cast<hipStream_t>(stream)));
+}
+
+namespace {
+bool params_ok(const odgs_param_ptrs* p) {
+  if (!p) return false;
+  const float* a[5] = {p->means, p->scales, p->quats, p->opacities, p->sh};
+  for (const float* q : a)
+    if (!q || !aligned(q, 4)) return false;
+  return true;
+}
+}  // namespace
+
+int odgs_adam_step(int64_t n, int32_t sh_degree, const odgs_param_ptrs* raw, const odgs_param_ptrs* act,
+                   const odgs_param_ptrs* grad, const odgs_param_ptrs* m, const odgs_param_ptrs* v, const float* lr,
+                   int32_t* step, const odgs_adam_hyper* hp, void* stream) {
+  if (n < 0 || sh_degree < 0 || sh_degree > 3 || !hp || !lr || !step || !aligned(lr, 4) || !aligned(step, 4))
+    return ODGS_EINVAL;
+  if (!(hp->beta1 >= 0.0f && hp->beta1 < 1.0f && hp->beta2 >= 0.0f && hp->beta2 < 1.0f && hp->eps >= 0.0f))
+    return ODGS_EINVAL;
+  if (!raw || !act || !grad || !m || !v) return ODGS_EINVAL;
+  if (n > 0 && !(params_ok(raw) && params_ok(act) && params_ok(grad) && params_ok(m) && params_ok(v)))
+    return ODGS_EINVAL;
+  return hip_status(launch_adam_step(n, sh_degree, *raw, *act, *grad, *m, *v, lr, step, *hp,
+                                     static_cast<hipStream_t>(stream)));
+}
+
 size_t odgs_densify_workspace_bytes(int64_t n) { return n < 0 ? 0 : densify_workspace_bytes(n); }
 
 int odgs_densify(int64_t n, int32_t sh_degree, const float* means, const float* scales, const float* quats,

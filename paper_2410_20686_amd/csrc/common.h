@@ -81,6 +81,12 @@ hipError_t launch_densify(int64_t n, int32_t sh_degree, const float* means, cons
                           float* out_means, float* out_scales, float* out_quats, float* out_opac, float* out_sh,
                           int32_t* out_src, int64_t* out_counts, void* ws, hipStream_t st);
 size_t densify_workspace_bytes(int64_t n);
+size_t l1_workspace_bytes(int64_t count);
+hipError_t launch_l1(const float* rgb, const float* tgt, int64_t count, float* dL, float* loss, void* ws,
+                     hipStream_t st);
+hipError_t launch_adam_step(int64_t n, int32_t sh_degree, const odgs_param_ptrs& raw, const odgs_param_ptrs& act,
+                            const odgs_param_ptrs& grad, const odgs_param_ptrs& m, const odgs_param_ptrs& v,
+                            const float* lr, int32_t* step, const odgs_adam_hyper& hp, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* ptr, uint32_t value, int64_t n, hipStream_t st);
 hipError_t launch_status_reset(const odgs_plan* p, void* ws, hipStream_t st);
 hipError_t launch_debug_records(const odgs_plan* p, const void* ws, float* out, hipStream_t st);
