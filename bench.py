@@ -81,6 +81,7 @@ def parse():
                     help="first run one device-to-device copy of this many MiB (a known-size reference "
                          "dispatch for hardware byte counters)")
     ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-train", action="store_true", help="skip timing the loss + Adam training iteration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels-per-view", type=int, default=768)
     return ap.parse_args()
@@ -201,6 +202,23 @@ def main():
     contrib_total, evals_fwd, evals_bwd = int(cnt[1]), int(cnt[2]), int(cnt[3])
     log("stages ms", stages)
 
+    # a whole training iteration (L1 loss against a fixed target + backward + Adam update) as
+    # context for the metric; targets are the step's own first image dimmed by 10%
+    train = None
+    if not args.no_train:
+        from paper_2410_20686_amd.optim import GaussianParams, LossTrainStep
+        target = (step.rgb * 0.9).contiguous()
+        o = tensors[3].clamp(1e-4, 1 - 1e-4)
+        gp = GaussianParams(tensors[0], torch.log(tensors[1]), tensors[2], torch.log(o / (1 - o)), tensors[4],
+                            sh_degree=sc.sh_degree)
+        tstep = LossTrainStep(rast, gp, tensors[5], target)
+        ms_train, _g3 = time_graph(tstep.run, args.steps, args.warmup)
+        train = dict(ms_per_step=round(ms_train, 4), loss_last=round(float(tstep.loss.cpu()), 6))
+        if rast.status()["flags"] & B.STATUS_OVERFLOW:
+            train = dict(note="pair list overflowed while the parameters moved; not timed")
+        log("train iteration %.3f ms" % ms_train)
+        del tstep, gp
+
     per_view = None
     if not args.no_per_view:
         pv_steps = []
@@ -275,6 +293,7 @@ def main():
                    "pairs": status["n_pairs"],
                    "autotuned": tuned is not None},
         "per_view": per_view,
+        "train_iteration": train,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
