@@ -115,6 +115,8 @@ struct Camera {
   double R[9];  // world -> camera rotation, row-major (the paper's W, Sec. 3.1)
   double t[3];
   int W, H;
+  bool pinhole = false;  // perspective camera of Sec. 3.1 (else equirectangular, Sec. 3.2)
+  double fx = 0, fy = 0, cx = 0, cy = 0;  // its intrinsics K
 };
 
 struct Settings {
@@ -131,6 +133,21 @@ struct Scene {
   int64_t n;
   int K;  // number of SH basis functions, (degree+1)^2
 };
+
+// Settings array: [tile, near, far, dilation, pole_eps, bg0, bg1, bg2, P] followed by P records
+// (view, fx, fy, cx, cy) marking pinhole views.
+void read_pinholes(const double* s, std::vector<Camera>& cams) {
+  const int P = (int)s[8];
+  for (int k = 0; k < P; ++k) {
+    const double* r = s + 9 + 5 * k;
+    Camera& c = cams[(int)r[0]];
+    c.pinhole = true;
+    c.fx = r[1];
+    c.fy = r[2];
+    c.cx = r[3];
+    c.cy = r[4];
+  }
+}
 
 Settings read_settings(const double* s) {
   Settings st;
@@ -202,7 +219,7 @@ void sh_basis(const S d[3], int K, S* Y) {
 // double-valued intermediates go to Info.
 // ----------------------------------------------------------------------------------------------
 enum Cull { KEPT = 0, CULL_SHELL = 1, CULL_POLE = 2, CULL_OPACITY = 3, CULL_DET = 4, CULL_EMPTY = 5,
-            CULL_NONFINITE = 6 };
+            CULL_NONFINITE = 6, CULL_FRUSTUM = 7 };
 
 template <typename S>
 struct Proj {
@@ -245,21 +262,36 @@ void project(const S m[3], const S s[3], const S q[4], const S& o, const double*
   for (int k = 0; k < 3; ++k) info.mu[k] = val(mu[k]);
   info.r = val(rr);
   info.rho = val(rho);
-  info.depth = (float)val(rr);
+  info.depth = (float)val(cam.pinhole ? mu[2] : rr);
 
-  // Culling in a spherical shell (Sec. 3.2, last paragraph) instead of a view frustum.
-  if (!(val(rr) > st.near_r && val(rr) < st.far_r)) { info.cull = CULL_SHELL; return; }
-  // At the poles the azimuth is undefined and sec(theta) diverges (Eq. omni_QS); such
-  // Gaussians are dropped.
-  if (!(val(rho) > st.pole_eps * val(rr))) { info.cull = CULL_POLE; return; }
-
-  // Spherical coordinates (Sec. 3.2): azimuth from +z, elevation from the z-x plane, with y
-  // pointing down.  atan2 gives the stated ranges [-pi, pi] and [-pi/2, pi/2].
-  const S phi = atan2(mu[0], mu[2]);
-  const S theta = atan2(-mu[1], rho);
-  // Eq. equirec_proj.
-  out.u = (Wd / (2.0 * pi)) * phi + Wd / 2.0;
-  out.v = (-Hd / pi) * theta + Hd / 2.0;
+  S phi = S(0.0), theta = S(0.0);
+  if (cam.pinhole) {
+    // Perspective camera (Sec. 3.1): depth range on the camera's z, and a guard band of 1.3
+    // times the field of view around the image for the projected mean.
+    const double z = val(mu[2]);
+    if (!(z > st.near_r && z < st.far_r)) { info.cull = CULL_SHELL; return; }
+    if (!(std::fabs(val(mu[0]) / z) <= 1.3 * (Wd / (2.0 * cam.fx)) &&
+          std::fabs(val(mu[1]) / z) <= 1.3 * (Hd / (2.0 * cam.fy)))) {
+      info.cull = CULL_FRUSTUM;
+      return;
+    }
+    // pi(mu) = K_{1:2} (mu_x / mu_z, mu_y / mu_z, 1)
+    out.u = cam.fx * (mu[0] / mu[2]) + cam.cx;
+    out.v = cam.fy * (mu[1] / mu[2]) + cam.cy;
+  } else {
+    // Culling in a spherical shell (Sec. 3.2, last paragraph) instead of a view frustum.
+    if (!(val(rr) > st.near_r && val(rr) < st.far_r)) { info.cull = CULL_SHELL; return; }
+    // At the poles the azimuth is undefined and sec(theta) diverges (Eq. omni_QS); such
+    // Gaussians are dropped.
+    if (!(val(rho) > st.pole_eps * val(rr))) { info.cull = CULL_POLE; return; }
+    // Spherical coordinates (Sec. 3.2): azimuth from +z, elevation from the z-x plane, with y
+    // pointing down.  atan2 gives the stated ranges [-pi, pi] and [-pi/2, pi/2].
+    phi = atan2(mu[0], mu[2]);
+    theta = atan2(-mu[1], rho);
+    // Eq. equirec_proj.
+    out.u = (Wd / (2.0 * pi)) * phi + Wd / 2.0;
+    out.v = (-Hd / pi) * theta + Hd / 2.0;
+  }
 
   // 3D covariance Sigma = R S S^T R^T (Sec. 3.1) from the normalised quaternion (w, x, y, z).
   const S qn = sqrt(((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3]);
@@ -284,6 +316,16 @@ void project(const S m[3], const S s[3], const S q[4], const S& o, const double*
   info.cov3[0] = val(Sig[0]); info.cov3[1] = val(Sig[1]); info.cov3[2] = val(Sig[2]);
   info.cov3[3] = val(Sig[4]); info.cov3[4] = val(Sig[5]); info.cov3[5] = val(Sig[8]);
 
+  S J[6];
+  if (cam.pinhole) {
+    // Eq. jacob_pers.
+    J[0] = cam.fx / mu[2];
+    J[1] = S(0.0);
+    J[2] = -cam.fx * mu[0] / (mu[2] * mu[2]);
+    J[3] = S(0.0);
+    J[4] = cam.fy / mu[2];
+    J[5] = -cam.fy * mu[1] / (mu[2] * mu[2]);
+  } else {
   // Tangent-plane projection.  Eq. omni_rotation: T_mu = T_theta * T_phi turns the camera's z
   // axis towards mu.  Eq. omni_J: unit-focal perspective Jacobian at mu_o = (0, 0, |mu|).
   // Eq. omni_QS: horizontal ERP stretch sec(theta), then pixel scale (W/2pi, H/pi).
@@ -304,10 +346,10 @@ void project(const S m[3], const S s[3], const S q[4], const S& o, const double*
   S SQJ[6];
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 3; ++c) SQJ[3 * r + c] = SQ[2 * r + 0] * Jo[0 * 3 + c] + SQ[2 * r + 1] * Jo[1 * 3 + c];
-  S J[6];
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 3; ++c)
       J[3 * r + c] = (SQJ[3 * r + 0] * Tmu[0 * 3 + c] + SQJ[3 * r + 1] * Tmu[1 * 3 + c]) + SQJ[3 * r + 2] * Tmu[2 * 3 + c];
+  }
   for (int k = 0; k < 6; ++k) info.J[k] = val(J[k]);
 
   // Sigma_2D,o = J_omni W Sigma W^T J_omni^T (below Eq. omni_Jacobian).
@@ -374,7 +416,13 @@ void project(const S m[3], const S s[3], const S q[4], const S& o, const double*
   const int ntx = cam.W / B, nty = cam.H / B;
   const double uu = val(out.u), vv = val(out.v);
   const double clo = std::floor((uu - eu) / B), chi = std::floor((uu + eu) / B);
-  if (!(chi - clo + 1.0 < (double)ntx)) {
+  if (cam.pinhole) {
+    // no seam: columns clamp at the image edges like the rows
+    const double c0 = std::max(0.0, clo), c1 = std::min((double)(ntx - 1), chi);
+    info.col0 = (int)std::max(0.0, std::min(c0, (double)ntx));
+    info.ncols = (int)(c1 - c0 + 1.0);
+    if (info.ncols <= 0) { info.cull = CULL_EMPTY; return; }
+  } else if (!(chi - clo + 1.0 < (double)ntx)) {
     info.col0 = 0;
     info.ncols = ntx;
   } else {
@@ -467,10 +515,10 @@ inline uint64_t mix(uint64_t h, uint64_t x) {
 //   - 3DGS constants: alpha <= 0.99, skip alpha < 1/255 (as power < p_min), stop before the
 //     Gaussian that would take the transmittance below 1e-4.
 template <typename R>
-PixResult composite(const int32_t* order, int64_t count, const Rec<R>* recs, int x, int y, int W,
+PixResult composite(const int32_t* order, int64_t count, const Rec<R>* recs, int x, int y, int W, bool wrap,
                     const double* bg, std::vector<Contrib>* contrib) {
   const R px = (R)x + (R)0.5, py = (R)y + (R)0.5;
-  const R Wf = (R)W, half = (R)W * (R)0.5;
+  const R Wf = (R)W, half = wrap ? (R)W * (R)0.5 : (R)INFINITY;
   const R t_stop = (R)1e-4;
   R T = (R)1.0;
   R C[3] = {(R)0, (R)0, (R)0};
@@ -522,6 +570,7 @@ struct Prepared {
 
 void prepare(const Scene& sc, const double* cams, const int32_t* wh, int V, const double* settings, Prepared& P) {
   P.cams = read_cameras(cams, wh, V);
+  read_pinholes(settings, P.cams);
   P.st = read_settings(settings);
   P.n = sc.n;
   P.V = V;
@@ -642,10 +691,10 @@ PixResult render_pixel(const Prepared& P, const std::vector<Rec<R>>& recs, const
     const int B = P.st.tile;
     const int64_t tile = cand->tile_base[v] + (int64_t)(y / B) * (cam.W / B) + x / B;
     const std::vector<int32_t>& lst = cand->band[tile];
-    return composite<R>(lst.data(), (int64_t)lst.size(), recs.data(), x, y, cam.W, P.st.bg, contrib);
+    return composite<R>(lst.data(), (int64_t)lst.size(), recs.data(), x, y, cam.W, !cam.pinhole, P.st.bg, contrib);
   }
   const std::vector<int32_t>& ord = P.order[v];
-  return composite<R>(ord.data(), (int64_t)ord.size(), recs.data(), x, y, cam.W, P.st.bg, contrib);
+  return composite<R>(ord.data(), (int64_t)ord.size(), recs.data(), x, y, cam.W, !cam.pinhole, P.st.bg, contrib);
 }
 
 // Reverse recursion over one pixel's contributors (Eq. alphablending differentiated):
@@ -819,7 +868,7 @@ int oracle_project(const double* means, const double* scales, const double* quat
       o[2] = f.depth;
       o[3] = float_bits(f.depth);
       o[33] = f.mu[0]; o[34] = f.mu[1]; o[35] = f.mu[2]; o[36] = f.r;
-      if (f.cull == CULL_SHELL || f.cull == CULL_POLE) continue;
+      if (f.cull == CULL_SHELL || f.cull == CULL_POLE || f.cull == CULL_FRUSTUM) continue;
       o[4] = p.u; o[5] = p.v;
       for (int k = 0; k < 3; ++k) o[6 + k] = p.conic[k];
       o[9] = p.opacity;

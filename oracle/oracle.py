@@ -72,7 +72,12 @@ def settings_array(settings: dict) -> np.ndarray:
     bg = settings.get("bg", (0.0, 0.0, 0.0))
     vals = [settings["near"], settings["far"], settings["dilation"], settings["pole_eps"], bg[0], bg[1], bg[2]]
     vals = [float(np.float32(x)) for x in vals]
-    return np.array([settings["tile"], *vals, 0.0], dtype=np.float64)
+    # pinhole views: {view: (fx, fy, cx, cy)}, appended as (view, fx, fy, cx, cy) records
+    pin = settings.get("pinhole") or {}
+    tail = [float(len(pin))]
+    for v in sorted(pin):
+        tail += [float(v)] + [float(np.float32(x)) for x in pin[v]]
+    return np.array([settings["tile"], *vals, *tail], dtype=np.float64)
 
 
 class _Args:

@@ -177,6 +177,25 @@ def yaw_matrix(angle: float) -> np.ndarray:
     return np.array([[c, 0.0, -s], [0.0, 1.0, 0.0], [s, 0.0, c]])
 
 
+def cube_rotations():
+    """World-to-camera rotations of the six cube faces (camera axes x right, y down, z forward as
+    rows): looking along +z, -z, +x, -x, +y, -y."""
+    faces = []
+    for z, y in (((0, 0, 1), (0, 1, 0)), ((0, 0, -1), (0, 1, 0)), ((1, 0, 0), (0, 1, 0)),
+                 ((-1, 0, 0), (0, 1, 0)), ((0, 1, 0), (0, 0, -1)), ((0, -1, 0), (0, 0, 1))):
+        z, y = np.array(z, float), np.array(y, float)
+        faces.append(np.stack([np.cross(y, z), y, z]))
+    return faces
+
+
+def cubemap_cameras(face: int, centre=(0.0, 0.0, 0.0)) -> Cameras:
+    """Six square pinhole views (90 degree field of view, face x face pixels) around one centre;
+    use with settings pinhole={v: (face / 2, face / 2, face / 2, face / 2)}."""
+    c = np.asarray(centre, dtype=np.float64)
+    Rs = cube_rotations()
+    return _pack_cams(Rs, [c] * 6, [[face, face]] * 6)
+
+
 def yaw_cameras(n_views: int, width: int, height: int, seed: int) -> Cameras:
     """cfg3/M cameras: centres uniform in [-0.5, 0.5]^3, yaw uniform in [0, 2pi)."""
     rng = np.random.default_rng(seed)
