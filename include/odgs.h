@@ -87,6 +87,7 @@ typedef struct odgs_plan {
   int32_t height[ODGS_MAX_VIEWS];
   int32_t tile_base[ODGS_MAX_VIEWS + 1];  /* first global tile id of each view; [n_views] = total */
   int64_t pix_base[ODGS_MAX_VIEWS + 1];   /* first pixel of each view; [n_views] = total */
+  float pinhole[ODGS_MAX_VIEWS][4];       /* fx, fy, cx, cy of a perspective view; fx == 0: ERP view */
   int64_t items;           /* n * n_views (Gaussian, view) items, item id = view * n + gaussian */
   int64_t pair_capacity;   /* maximum Gaussian-tile pairs the workspace holds */
   int32_t tile_bits;       /* significant bits of a global tile id */
@@ -134,6 +135,15 @@ typedef struct odgs_densify_params {
   float min_opacity;     /* prune below this opacity, e.g. 0.005 */
   float max_scale_frac;  /* > 0: also prune a largest scale above max_scale_frac * extent; 0: off */
 } odgs_densify_params;
+
+/* Make view `view` of an initialised plan a perspective (pinhole) camera, the 3DGS model of
+ * Sec. 3.1: pixel position pi(mu) = (fx mu_x / mu_z + cx, fy mu_y / mu_z + cy) (pixel (x, y)
+ * samples (x + 0.5, y + 0.5) as in ERP views), Jacobian Eq. jacob_pers, sort depth mu_z, culling
+ * to near_r < mu_z < far_r with the projected mean inside 1.3 times the field of view
+ * (|mu_x / mu_z| <= 1.3 W / (2 fx), likewise y), tile columns clamped at the image edges (no
+ * seam).  Such views share every other step with the ERP views of the same plan (e.g. the six
+ * faces of a cubemap next to panoramas).  Pure host computation; fx, fy > 0. */
+int odgs_plan_set_pinhole(odgs_plan* plan /*[host]*/, int32_t view, float fx, float fy, float cx, float cy);
 
 /* Bytes of device workspace a plan needs (256-byte aligned base pointer required). */
 size_t odgs_workspace_bytes(const odgs_plan* plan /*[host]*/);

@@ -17,7 +17,7 @@ OK, EINVAL, ENOSPACE, EHIP = 0, -1, -2, -3
 STATUS_OVERFLOW = 1
 FLAG_COUNT_WORK = 1
 
-EXPORTS = ("odgs_plan_init", "odgs_workspace_bytes", "odgs_preprocess", "odgs_bin_sort", "odgs_render_fwd",
+EXPORTS = ("odgs_plan_init", "odgs_plan_set_pinhole", "odgs_workspace_bytes", "odgs_preprocess", "odgs_bin_sort", "odgs_render_fwd",
            "odgs_render_bwd", "odgs_composite_bwd", "odgs_project_bwd", "odgs_status_offset", "odgs_strerror",
            "odgs_densify", "odgs_densify_workspace_bytes", "odgs_l1_loss", "odgs_l1_loss_workspace_bytes",
            "odgs_adam_step",
@@ -63,6 +63,7 @@ class Plan(ctypes.Structure):
     _fields_ = ([("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("n_views", ctypes.c_int32),
                  ("s", Settings), ("width", ctypes.c_int32 * MAX_VIEWS), ("height", ctypes.c_int32 * MAX_VIEWS),
                  ("tile_base", ctypes.c_int32 * (MAX_VIEWS + 1)), ("pix_base", ctypes.c_int64 * (MAX_VIEWS + 1)),
+                 ("pinhole", (ctypes.c_float * 4) * MAX_VIEWS),
                  ("items", ctypes.c_int64), ("pair_capacity", ctypes.c_int64), ("tile_bits", ctypes.c_int32),
                  ("item_blocks", ctypes.c_int32), ("pair_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
                 + [(name, ctypes.c_size_t) for name in _OFFSETS]
@@ -85,6 +86,9 @@ def lib():
         L.odgs_plan_size.restype = c_sz
         L.odgs_plan_init.argtypes = [pp, c_i64, c_i32, c_i32, P, ctypes.POINTER(Settings), c_i64]
         L.odgs_plan_init.restype = c_i32
+        c_f = ctypes.c_float
+        L.odgs_plan_set_pinhole.argtypes = [pp, c_i32, c_f, c_f, c_f, c_f]
+        L.odgs_plan_set_pinhole.restype = c_i32
         L.odgs_workspace_bytes.argtypes = [pp]
         L.odgs_workspace_bytes.restype = c_sz
         L.odgs_status_offset.argtypes = [pp]
@@ -156,6 +160,11 @@ def odgs_plan_init(n: int, sh_degree: int, wh, settings: Settings, pair_capacity
                               ctypes.byref(settings), int(pair_capacity))
     _check(rc, "odgs_plan_init")
     return plan
+
+
+def odgs_plan_set_pinhole(plan: Plan, view: int, fx: float, fy: float, cx: float, cy: float):
+    _check(lib().odgs_plan_set_pinhole(ctypes.byref(plan), int(view), float(fx), float(fy), float(cx), float(cy)),
+           "odgs_plan_set_pinhole")
 
 
 def odgs_workspace_bytes(plan: Plan) -> int:

@@ -44,6 +44,18 @@ extern "C" {
 
 size_t odgs_plan_size(void) { return sizeof(odgs_plan); }
 
+int odgs_plan_set_pinhole(odgs_plan* plan, int32_t view, float fx, float fy, float cx, float cy) {
+  if (!plan || view < 0 || view >= plan->n_views) return ODGS_EINVAL;
+  if (!(fx > 0.0f) || !(fy > 0.0f) || !std::isfinite(fx) || !std::isfinite(fy) || !std::isfinite(cx) ||
+      !std::isfinite(cy))
+    return ODGS_EINVAL;
+  plan->pinhole[view][0] = fx;
+  plan->pinhole[view][1] = fy;
+  plan->pinhole[view][2] = cx;
+  plan->pinhole[view][3] = cy;
+  return ODGS_OK;
+}
+
 int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_views, const int32_t* wh,
                    const odgs_settings* s, int64_t pair_capacity) {
   if (!plan || !wh || !s) return ODGS_EINVAL;

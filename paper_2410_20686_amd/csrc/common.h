@@ -17,7 +17,14 @@ struct ViewTable {
   int32_t H[ODGS_MAX_VIEWS];
   int32_t tile_base[ODGS_MAX_VIEWS + 1];
   int64_t pix_base[ODGS_MAX_VIEWS + 1];
+  float pin[ODGS_MAX_VIEWS][4];  // fx, fy, cx, cy of pinhole views; fx == 0: equirectangular
 };
+
+// Half width at which horizontal offsets wrap round the +-pi seam: W/2 for ERP views, none
+// (infinite) for pinhole views.
+__device__ inline float wrap_half(const ViewTable& vt, int v) {
+  return vt.pin[v][0] > 0.0f ? INFINITY : (float)vt.W[v] * 0.5f;
+}
 
 // Compositor record of one (Gaussian, view) item, three 16-byte words:
 //   r0 = (u, v, l0, l1)        exponent -((l0 du + l1 dv)^2 + (l2 dv)^2), du = px - u, dv = py - v
@@ -48,6 +55,7 @@ inline ViewTable make_view_table(const odgs_plan* p) {
   for (int v = 0; v < p->n_views; ++v) {
     vt.W[v] = p->width[v];
     vt.H[v] = p->height[v];
+    for (int k = 0; k < 4; ++k) vt.pin[v][k] = p->pinhole[v][k];
   }
   for (int v = 0; v <= p->n_views; ++v) {
     vt.tile_base[v] = p->tile_base[v];

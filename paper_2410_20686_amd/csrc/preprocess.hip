@@ -142,6 +142,7 @@ __device__ inline void cov3(const double s[3], const double q[4], Cov3& c) {
 // View-dependent geometry shared by the forward and the adjoint.
 struct Geo {
   double mu[3], r2, r, p, rho;  // camera-space mean, |mu|^2, |mu|, mu_x^2 + mu_z^2, sqrt of it
+  double depth;                 // sort depth: |mu| (ERP), mu_z (pinhole)
   double u, v;
   double J[6];                  // J_omni = d(u, v) / d mu (closed form of Appendix B)
   double A[6];                  // J_omni * R
@@ -149,9 +150,15 @@ struct Geo {
   double det;
 };
 
-// Returns false when the item is culled by the shell or the pole test.
+// Pinhole intrinsics of a view (fx == 0: equirectangular view).
+struct Pin {
+  double fx, fy, cx, cy;
+};
+
+// Returns false when the item is culled (shell and pole tests for ERP views; depth range and
+// the 1.3x field-of-view guard band for pinhole views).
 __device__ inline bool geometry(const double m[3], const Cam& cam, const Cov3& cv, int W, int H, const Params& P,
-                                Geo& g) {
+                                const Pin& pin, Geo& g) {
 #pragma unroll
   for (int r = 0; r < 3; ++r)
     g.mu[r] = ((cam.R[3 * r] * m[0] + cam.R[3 * r + 1] * m[1]) + cam.R[3 * r + 2] * m[2]) + cam.t[r];
@@ -159,9 +166,25 @@ __device__ inline bool geometry(const double m[3], const Cam& cam, const Cov3& c
   g.r = sqrt(g.r2);
   g.p = g.mu[0] * g.mu[0] + g.mu[2] * g.mu[2];
   g.rho = sqrt(g.p);
+  const double Wd = (double)W, Hd = (double)H;
+  if (pin.fx > 0.0) {
+    // Perspective camera (Sec. 3.1): pi(mu) = K (mu_x / mu_z, mu_y / mu_z), J of Eq. jacob_pers.
+    const double x = g.mu[0], y = g.mu[1], z = g.mu[2];
+    g.depth = z;
+    if (!(z > P.near_r && z < P.far_r)) return false;
+    if (!(fabs(x / z) <= 1.3 * (Wd / (2.0 * pin.fx)) && fabs(y / z) <= 1.3 * (Hd / (2.0 * pin.fy)))) return false;
+    g.u = pin.fx * (x / z) + pin.cx;
+    g.v = pin.fy * (y / z) + pin.cy;
+    g.J[0] = pin.fx / z;
+    g.J[1] = 0.0;
+    g.J[2] = -pin.fx * x / (z * z);
+    g.J[3] = 0.0;
+    g.J[4] = pin.fy / z;
+    g.J[5] = -pin.fy * y / (z * z);
+  } else {
+  g.depth = g.r;
   if (!(g.r > P.near_r && g.r < P.far_r)) return false;
   if (!(g.rho > P.pole_eps * g.r)) return false;
-  const double Wd = (double)W, Hd = (double)H;
   const double phi = atan2(g.mu[0], g.mu[2]);
   const double theta = atan2(-g.mu[1], g.rho);
   g.u = (Wd / (2.0 * kPi)) * phi + Wd / 2.0;
@@ -177,6 +200,7 @@ __device__ inline bool geometry(const double m[3], const Cam& cam, const Cov3& c
   g.J[3] = -a2 * x * y / r2rho;
   g.J[4] = a2 * g.rho / g.r2;
   g.J[5] = -a2 * y * z / r2rho;
+  }
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -242,8 +266,9 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
     load_cam(cams, v, cam);
     const int W = vt.W[v], H = vt.H[v];
     Geo g;
-    bool kept = live && geometry(m, cam, cv, W, H, P, g);
-    float depth = (float)g.r;
+    const Pin pin{(double)vt.pin[v][0], (double)vt.pin[v][1], (double)vt.pin[v][2], (double)vt.pin[v][3]};
+    bool kept = live && geometry(m, cam, cv, W, H, P, pin, g);
+    float depth = (float)g.depth;
     Rec out;
     Rect rr{0, 0, 0, 0};
     uint32_t cnt = 0;
@@ -279,7 +304,12 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
         const int ntx = W / B, nty = H / B;
         const double clo = floor((g.u - eu) / B), chi = floor((g.u + eu) / B);
         int col0, ncols;
-        if (!(chi - clo + 1.0 < (double)ntx)) {
+        if (pin.fx > 0.0) {
+          // no seam: columns clamp at the image edges like the rows
+          const double c0 = fmax(0.0, clo), c1 = fmin((double)(ntx - 1), chi);
+          col0 = (int)fmax(0.0, fmin(c0, (double)ntx));
+          ncols = (int)(c1 - c0 + 1.0);
+        } else if (!(chi - clo + 1.0 < (double)ntx)) {
           col0 = 0;
           ncols = ntx;
         } else {
@@ -292,7 +322,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
         const double rhi = fmin((double)(nty - 1), floor((g.v + ev) / B));
         const int row0 = (int)rlo;
         const int nrows = (int)(rhi - rlo + 1.0);
-        kept = nrows > 0;
+        kept = nrows > 0 && ncols > 0;
         if (kept) {
           rr = Rect{(uint16_t)col0, (uint16_t)ncols, (uint16_t)row0, (uint16_t)nrows};
           cnt = (uint32_t)ncols * (uint32_t)nrows;
@@ -400,7 +430,8 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     Cam cam;
     load_cam(cams, v, cam);
     Geo G;
-    geometry(m, cam, cv, vt.W[v], vt.H[v], P, G);
+    const Pin pin{(double)vt.pin[v][0], (double)vt.pin[v][1], (double)vt.pin[v][2], (double)vt.pin[v][3]};
+    geometry(m, cam, cv, vt.W[v], vt.H[v], P, pin, G);
     // dL/dSigma_2D as a symmetric matrix (the shared off-diagonal derivative split in halves)
     const double G00 = g[2], G01 = 0.5 * g[3], G11 = g[4];
     // Sigma2D = A Sigma A^T: dA = 2 G2 A Sigma, dSigma += A^T G2 A (G2 symmetric 2x2).
@@ -434,6 +465,14 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     double dmu[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) dmu[k] = G.J[k] * g[0] + G.J[3 + k] * g[1];
+    if (pin.fx > 0.0) {
+      // Eq. jacob_pers: J00 = fx / z, J02 = -fx x / z^2, J11 = fy / z, J12 = -fy y / z^2
+      const double iz2 = 1.0 / (z * z), iz3 = iz2 / z;
+      dmu[0] += dJ[2] * (-pin.fx * iz2);
+      dmu[1] += dJ[5] * (-pin.fy * iz2);
+      dmu[2] += dJ[0] * (-pin.fx * iz2) + dJ[2] * (2.0 * pin.fx * x * iz3) + dJ[4] * (-pin.fy * iz2) +
+                dJ[5] * (2.0 * pin.fy * y * iz3);
+    } else {
     const double xz2 = x * x - z * z;
     const double q2 = 2.0 * p + r2;
     const double r2m2y = r2 - 2.0 * y * y;
@@ -453,6 +492,7 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     dmu[0] += dJ[5] * (a2 * x * y * z * q2 / (r4 * rho3));
     dmu[1] += dJ[5] * (-a2 * z * r2m2y / (r4 * rho));
     dmu[2] += dJ[5] * (-a2 * y * (r2 * x * x - 2.0 * z * z * p) / (r4 * rho3));
+    }
     // mu = R m + t  =>  dm = R^T dmu
 #pragma unroll
     for (int k = 0; k < 3; ++k) gm[k] += cam.R[k] * dmu[0] + cam.R[3 + k] * dmu[1] + cam.R[6 + k] * dmu[2];

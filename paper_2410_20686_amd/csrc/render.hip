@@ -309,7 +309,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
   const int x = tx0 + lx, y = ty0 + ly;
   const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // this wavefront's quadrant (uniform)
   const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-  const float Wf = (float)W, half = (float)W * 0.5f;
+  const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
   const uint2 rg = ranges[g];
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   int last = 0, ncontrib = 0, nev = 0, lastev = 0;
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_fwd2_kernel(
   const int qa = 2 * wq;
   const int x = tx0 + (qa % QPR) * 8 + (lane & 7), y = ty0 + (qa / QPR) * 8 + (lane >> 3);
   const float pxa = (float)x + 0.5f, pxb = (float)(x + 8) + 0.5f, py = (float)y + 0.5f;
-  const float Wf = (float)W, half = (float)W * 0.5f;
+  const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
   const uint2 rg = ranges[g];
   FwdPixel A{1.0f, 0.0f, 0.0f, 0.0f, 0, false}, B{1.0f, 0.0f, 0.0f, 0.0f, 0, false};
   for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
@@ -498,7 +498,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int slot = (int)((kRowSlot >> (4 * (lane & 15))) & 0xF);
   const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-  const float Wf = (float)W, half = (float)W * 0.5f;
+  const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
   const uint2 rg = ranges[g];
   const int64_t plane = (int64_t)W * H;
   const int64_t pix = (int64_t)y * W + x;
@@ -678,7 +678,7 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
   const int x = tx0 + (qa % QPR) * 8 + (lane & 7), y = ty0 + (qa / QPR) * 8 + (lane >> 3);
   const int slot = (int)((kRowSlot >> (4 * (lane & 15))) & 0xF);
   const float pxa = (float)x + 0.5f, pxb = (float)(x + 8) + 0.5f, py = (float)y + 0.5f;
-  const float Wf = (float)W, half = (float)W * 0.5f;
+  const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
   const uint2 rg = ranges[g];
   const int64_t plane = (int64_t)W * H;
   const int64_t pix = (int64_t)y * W + x;

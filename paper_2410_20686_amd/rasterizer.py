@@ -16,7 +16,7 @@ import torch
 
 from . import _odgs as B
 
-DEFAULT_SETTINGS = dict(tile=16, batch=0, batch_bwd=0, count_work=False, near=0.2, far=1.0e4, dilation=0.3, pole_eps=1.0e-4, bg=(0.0, 0.0, 0.0))
+DEFAULT_SETTINGS = dict(tile=16, batch=0, batch_bwd=0, count_work=False, pinhole=None, near=0.2, far=1.0e4, dilation=0.3, pole_eps=1.0e-4, bg=(0.0, 0.0, 0.0))
 
 
 def _ptr(t: torch.Tensor | None):
@@ -46,9 +46,18 @@ class Rasterizer:
         self.generation = 0
         self._alloc(int(pair_capacity))
 
+    def _make_plan(self, capacity: int) -> B.Plan:
+        """Plan for the current settings; settings["pinhole"] = {view: (fx, fy, cx, cy)} marks
+        perspective views (the others are equirectangular)."""
+        st = {k: v for k, v in self.settings.items() if k != "pinhole"}
+        plan = B.odgs_plan_init(self.n, self.sh_degree, self.wh, B.make_settings(**st), capacity)
+        for view, (fx, fy, cx, cy) in sorted((self.settings.get("pinhole") or {}).items()):
+            B.odgs_plan_set_pinhole(plan, view, fx, fy, cx, cy)
+        return plan
+
     def _alloc(self, capacity: int):
         self.capacity = min(capacity, (1 << 31) - 1)
-        self.plan = B.odgs_plan_init(self.n, self.sh_degree, self.wh, B.make_settings(**self.settings), self.capacity)
+        self.plan = self._make_plan(self.capacity)
         self.ws_bytes = B.odgs_workspace_bytes(self.plan)
         self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
         if self.ws.data_ptr() % 256:
@@ -62,7 +71,7 @@ class Rasterizer:
         self.settings.update(batch=int(batch), batch_bwd=int(batch_bwd))
         if count_work is not None:
             self.settings["count_work"] = bool(count_work)
-        plan = B.odgs_plan_init(self.n, self.sh_degree, self.wh, B.make_settings(**self.settings), self.capacity)
+        plan = self._make_plan(self.capacity)
         if B.odgs_workspace_bytes(plan) != self.ws_bytes:
             raise RuntimeError("workspace layout changed with the batch sizes")
         self.plan = plan
