@@ -167,9 +167,13 @@ int odgs_bin_sort(const odgs_plan* plan, void* ws, size_t ws_bytes, void* stream
 /* Front-to-back compositing of every pixel of every view in one launch (Eq. gaussian2d and
  * Eq. alphablending, 3DGS constants alpha <= 0.99, alpha >= 1/255, stop below T = 1e-4).
  * out_rgb [V][3][H][W] receives C + T_final * bg; out_T [V][H][W] (may be NULL) the final
- * transmittance.  Keeps per-pixel T, the list position after the last contributor (both read by
- * the backward) and the work counters of odgs_debug_pixel_counts in the workspace. */
-int odgs_render_fwd(const odgs_plan* plan, void* ws, size_t ws_bytes, float* out_rgb, float* out_T, void* stream);
+ * transmittance (accumulated alpha = 1 - T); out_depth [V][H][W] (may be NULL) the
+ * alpha-weighted depth sum_j alpha_j T_j d_j with d_j the sort depth (radial distance in ERP
+ * views, camera z in pinhole views; divide by 1 - T for the expected depth of the covered part).
+ * Keeps per-pixel T, the list position after the last contributor (both read by the backward)
+ * and the work counters of odgs_debug_pixel_counts in the workspace. */
+int odgs_render_fwd(const odgs_plan* plan, void* ws, size_t ws_bytes, float* out_rgb, float* out_T, float* out_depth,
+                    void* stream);
 
 /* Gradient of L = sum(dL_drgb * out_rgb) with respect to every parameter, summed over the
  * views (reverse compositing, then the adjoint of the tangent-plane projection and of the SH

@@ -466,6 +466,7 @@ uint32_t float_bits(float f) {
 template <typename R>
 struct Rec {
   R u, v, l0, l1, l2, o, pmin, rgb[3];
+  R depth;  // the sort depth (float), for the expected-depth output
 };
 
 template <typename R>
@@ -482,6 +483,7 @@ Rec<R> make_rec(const Proj<double>& p, const Info& info) {
   r.o = (R)p.opacity;
   r.pmin = (R)info.p_min;
   for (int k = 0; k < 3; ++k) r.rgb[k] = (R)p.rgb[k];
+  r.depth = (R)info.depth;
   return r;
 }
 
@@ -497,6 +499,7 @@ struct Contrib {
 struct PixResult {
   double rgb[3];
   double T;
+  double depth;  // sum over contributors of alpha T depth (the alpha-weighted depth)
   int32_t n_contrib;
   double margin;   // min over tested steps of |T'/T_stop - 1| (termination decision margin)
   uint64_t sig;    // hash of the decision sequence (contributors, clamps, termination)
@@ -522,6 +525,7 @@ PixResult composite(const int32_t* order, int64_t count, const Rec<R>* recs, int
   const R t_stop = (R)1e-4;
   R T = (R)1.0;
   R C[3] = {(R)0, (R)0, (R)0};
+  R D = (R)0;
   PixResult res;
   res.n_contrib = 0;
   res.margin = 1e30;
@@ -545,6 +549,7 @@ PixResult composite(const int32_t* order, int64_t count, const Rec<R>* recs, int
     if (Tn < t_stop) { res.sig = mix(res.sig, 0xffffffffULL); break; }
     const R w = alpha * T;
     for (int c = 0; c < 3; ++c) C[c] = C[c] + w * g.rgb[c];
+    D = D + w * g.depth;
     T = Tn;
     res.n_contrib++;
     res.sig = mix(res.sig, ((uint64_t)(uint32_t)idx << 1) | (uint64_t)clamped);
@@ -552,6 +557,7 @@ PixResult composite(const int32_t* order, int64_t count, const Rec<R>* recs, int
   }
   for (int c = 0; c < 3; ++c) res.rgb[c] = (double)C[c] + (double)T * bg[c];
   res.T = (double)T;
+  res.depth = (double)D;
   return res;
 }
 
@@ -907,7 +913,7 @@ int64_t oracle_keys(const double* means, const double* scales, const double* qua
 int oracle_render(const double* means, const double* scales, const double* quats, const double* opac,
                   const double* sh, int64_t n, int deg, const double* cams, const int32_t* wh, int V,
                   const double* settings, int mode, int band, const int32_t* pix, int64_t npix, double* rgb,
-                  double* T, int32_t* ncontrib, double* margin, uint64_t* sig) {
+                  double* T, int32_t* ncontrib, double* margin, uint64_t* sig, double* depth) {
   Scene sc = make_scene(means, scales, quats, opac, sh, n, deg);
   Prepared P;
   prepare(sc, cams, wh, V, settings, P);
@@ -938,6 +944,7 @@ int oracle_render(const double* means, const double* scales, const double* quats
           ncontrib[p] = r.n_contrib;
           margin[p] = r.margin;
           sig[p] = r.sig;
+          if (depth) depth[p] = r.depth;
         }
     }
   } else {
@@ -949,6 +956,7 @@ int oracle_render(const double* means, const double* scales, const double* quats
       ncontrib[k] = r.n_contrib;
       margin[k] = r.margin;
       sig[k] = r.sig;
+      if (depth) depth[k] = r.depth;
     }
   }
   return 0;

@@ -52,7 +52,7 @@ def lib():
         L.oracle_project.restype = i32
         L.oracle_keys.argtypes = scene_args + [P, P, i64]
         L.oracle_keys.restype = i64
-        L.oracle_render.argtypes = scene_args + [i32, i32, P, i64, P, P, P, P, P]
+        L.oracle_render.argtypes = scene_args + [i32, i32, P, i64, P, P, P, P, P, P]
         L.oracle_render.restype = i32
         L.oracle_backward.argtypes = scene_args + [i32, P, i64, P, P, P, P, P, P, P]
         L.oracle_backward.restype = i32
@@ -126,7 +126,8 @@ def keys(scene, cams, settings):
 
 
 def render(scene, cams, settings, mode: int = 32, band: bool = False, pix: np.ndarray | None = None):
-    """Brute-force (or band) render.  Returns dict of rgb, T, ncontrib, margin, sig.
+    """Brute-force (or band) render.  Returns dict of rgb, T, ncontrib, margin, sig, depth (the
+    alpha-weighted sort depth, sum of alpha_j T_j d_j over the contributors).
 
     Full image: rgb is [V][3][H][W] flattened and concatenated over views, the others [V][H][W].
     With ``pix`` (int32 [n][3] rows of view, x, y): rgb [n][3], the others [n].
@@ -144,9 +145,10 @@ def render(scene, cams, settings, mode: int = 32, band: bool = False, pix: np.nd
     nc = np.zeros(npx, dtype=np.int32)
     margin = np.zeros(npx)
     sig = np.zeros(npx, dtype=np.uint64)
+    depth = np.zeros(npx)
     lib().oracle_render(*a.tuple(), mode, int(band), _p(pp), npx if pp is not None else 0,
-                        _p(rgb), _p(T), _p(nc), _p(margin), _p(sig))
-    return dict(rgb=rgb, T=T, ncontrib=nc, margin=margin, sig=sig)
+                        _p(rgb), _p(T), _p(nc), _p(margin), _p(sig), _p(depth))
+    return dict(rgb=rgb, T=T, ncontrib=nc, margin=margin, sig=sig, depth=depth)
 
 
 def backward(scene, cams, settings, dL: np.ndarray, mode: int = 32, pix: np.ndarray | None = None,

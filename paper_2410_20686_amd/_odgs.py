@@ -97,7 +97,7 @@ def lib():
         L.odgs_preprocess.restype = c_i32
         L.odgs_bin_sort.argtypes = [pp, P, c_sz, P]
         L.odgs_bin_sort.restype = c_i32
-        L.odgs_render_fwd.argtypes = [pp, P, c_sz, P, P, P]
+        L.odgs_render_fwd.argtypes = [pp, P, c_sz, P, P, P, P]
         L.odgs_render_fwd.restype = c_i32
         L.odgs_render_bwd.argtypes = [pp, P, P, P, P, P, P, P, c_sz, P, P, P, P, P, P, P, P]
         L.odgs_render_bwd.restype = c_i32
@@ -184,8 +184,8 @@ def odgs_bin_sort(plan, ws, ws_bytes, stream):
     _check(lib().odgs_bin_sort(ctypes.byref(plan), ws, ws_bytes, stream), "odgs_bin_sort")
 
 
-def odgs_render_fwd(plan, ws, ws_bytes, out_rgb, out_T, stream):
-    _check(lib().odgs_render_fwd(ctypes.byref(plan), ws, ws_bytes, out_rgb, out_T, stream), "odgs_render_fwd")
+def odgs_render_fwd(plan, ws, ws_bytes, out_rgb, out_T, out_depth, stream):
+    _check(lib().odgs_render_fwd(ctypes.byref(plan), ws, ws_bytes, out_rgb, out_T, out_depth, stream), "odgs_render_fwd")
 
 
 def _acc_ref(acc):

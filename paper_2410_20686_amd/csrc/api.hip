@@ -161,11 +161,13 @@ int odgs_bin_sort(const odgs_plan* plan, void* ws, size_t ws_bytes, void* stream
   return hip_status(launch_bin_sort(plan, ws, static_cast<hipStream_t>(stream)));
 }
 
-int odgs_render_fwd(const odgs_plan* plan, void* ws, size_t ws_bytes, float* out_rgb, float* out_T, void* stream) {
+int odgs_render_fwd(const odgs_plan* plan, void* ws, size_t ws_bytes, float* out_rgb, float* out_T, float* out_depth,
+                    void* stream) {
   const int rc = check_ws(plan, ws, ws_bytes);
   if (rc != ODGS_OK) return rc;
-  if (!out_rgb || !aligned(out_rgb, 4) || (out_T && !aligned(out_T, 4))) return ODGS_EINVAL;
-  return hip_status(launch_render_fwd(plan, ws, out_rgb, out_T, static_cast<hipStream_t>(stream)));
+  if (!out_rgb || !aligned(out_rgb, 4) || (out_T && !aligned(out_T, 4)) || (out_depth && !aligned(out_depth, 4)))
+    return ODGS_EINVAL;
+  return hip_status(launch_render_fwd(plan, ws, out_rgb, out_T, out_depth, static_cast<hipStream_t>(stream)));
 }
 
 int odgs_composite_bwd(const odgs_plan* plan, void* ws, size_t ws_bytes, const float* dL_drgb, void* stream) {

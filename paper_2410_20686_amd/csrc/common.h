@@ -77,7 +77,8 @@ inline const T* ws_ptr(const void* ws, size_t off) {
 hipError_t launch_preprocess(const odgs_plan* p, const float* means, const float* scales, const float* quats,
                              const float* opac, const float* sh, const float* cams, void* ws, hipStream_t st);
 hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st);
-hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float* out_T, hipStream_t st);
+hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float* out_T, float* out_depth,
+                             hipStream_t st);
 hipError_t launch_render_bwd(const odgs_plan* p, void* ws, const float* dL_drgb, hipStream_t st);
 hipError_t launch_preprocess_bwd(const odgs_plan* p, const float* means, const float* scales, const float* quats,
                                  const float* opac, const float* sh, const float* cams, void* ws, float* d_means,

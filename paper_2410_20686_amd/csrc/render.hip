@@ -214,6 +214,7 @@ struct Stage {
   float4 s1[BATCH];
   float4 s2[BATCH];
   uint32_t sid[BATCH];
+  float dep[BATCH];  // sort depths (staged only for the expected-depth output)
   uint8_t list[NQ][BATCH];
   uint32_t wcnt[NW][NQ];  // per-wavefront counts, then (in place) exclusive prefix over wavefronts
   uint32_t tot[NQ];
@@ -236,7 +237,8 @@ __device__ inline uint32_t group_mask(uint32_t m) {
 template <int TILE, int BATCH, int PX = 1>
 __device__ inline void stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __restrict__ pair_items,
                                    const Rec* __restrict__ rec, uint32_t first, int dir, int cnt, int tx0, int ty0,
-                                   float Wf, float half, int (&nq)[Stage<TILE, BATCH, PX>::NQ]) {
+                                   float Wf, float half, int (&nq)[Stage<TILE, BATCH, PX>::NQ],
+                                   const float* __restrict__ depth = nullptr) {
   using St = Stage<TILE, BATCH, PX>;
   const int t = threadIdx.x, ln = t & (kWave - 1), wv = t >> 6;
   const uint64_t below = ln == 0 ? 0ull : (~0ull >> (kWave - ln));
@@ -252,6 +254,7 @@ __device__ inline void stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __
       S.s1[e] = r.r1;
       S.s2[e] = r.r2;
       S.sid[e] = item;
+      if (depth) S.dep[e] = depth[item];
       m = group_mask<PX>(quadrant_mask<TILE>(r, tx0, ty0, Wf, half));
     }
     uint32_t within[St::NQ];
@@ -289,12 +292,13 @@ __device__ inline void stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __
 
 // COUNT: also record the per-pixel work counters read by odgs_debug_pixel_counts (a separate
 // instantiation, so the production forward carries no counting instructions).
-template <int TILE, int BATCH, bool COUNT>
+// DEPTH: also write the alpha-weighted sort depth sum_j alpha_j T_j d_j of every pixel.
+template <int TILE, int BATCH, bool COUNT, bool DEPTH>
 __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
     float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
     int32_t* __restrict__ ws_ncontrib, int32_t* __restrict__ ws_neval, int32_t* __restrict__ ws_lasteval, float bg0,
-    float bg1, float bg2) {
+    float bg1, float bg2, const float* __restrict__ depth, float* __restrict__ out_depth) {
   using St = Stage<TILE, BATCH>;
   constexpr int N = St::N;
   __shared__ St S;
@@ -311,14 +315,14 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
   const float px = (float)x + 0.5f, py = (float)y + 0.5f;
   const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
   const uint2 rg = ranges[g];
-  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f;
   int last = 0, ncontrib = 0, nev = 0, lastev = 0;
   bool done = false;
   for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
     if (__syncthreads_count(done) == N) break;
     const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
     int nq[St::NQ];
-    stage_batch<TILE, BATCH>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq);
+    stage_batch<TILE, BATCH>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq, DEPTH ? depth : nullptr);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
       if (__builtin_amdgcn_ballot_w64(!done) == 0ull) break;  // uniform: every pixel has finished
@@ -343,6 +347,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
       C0 = fmaf(w, c.x, C0);
       C1 = fmaf(w, c.y, C1);
       C2 = fmaf(w, c.z, C2);
+      if (DEPTH) D = D + w * S.dep[k];
       T = acc ? Tn : T;
       last = acc ? (int)(base - rg.x) + k + 1 : last;
       if (COUNT) {
@@ -365,6 +370,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
     ws_neval[gp] = nev;
     ws_lasteval[gp] = lastev;
   }
+  if (DEPTH) out_depth[gp] = D;
   if (out_T) out_T[gp] = T;
 }
 
@@ -799,17 +805,25 @@ template <int TILE, int BATCH>
 struct FwdRun {
   static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
                   const Rec* rec, float* out_rgb, float* out_T, float* wT, int32_t* wl, int32_t* wn, int32_t* we,
-                  int32_t* wle, hipStream_t st) {
-    // the counting variant keeps one pixel per lane, so its counters are per 8x8 quadrant
-    if (p->s.flags & ODGS_FLAG_COUNT_WORK)
-      hipLaunchKernelGGL((render_fwd_kernel<TILE, BATCH, true>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges,
-                         items, rec, out_rgb, out_T, wT, wl, wn, we, wle, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+                  int32_t* wle, const float* depth, float* out_depth, hipStream_t st) {
+    const bool count = (p->s.flags & ODGS_FLAG_COUNT_WORK) != 0;
+#define ODGS_FWD1(C, D)                                                                                        \
+  hipLaunchKernelGGL((render_fwd_kernel<TILE, BATCH, C, D>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, \
+                     items, rec, out_rgb, out_T, wT, wl, wn, we, wle, p->s.bg[0], p->s.bg[1], p->s.bg[2], depth,  \
+                     out_depth)
+    // the counting and depth variants keep one pixel per lane (counters per 8x8 quadrant)
+    if (count && out_depth)
+      ODGS_FWD1(true, true);
+    else if (count)
+      ODGS_FWD1(true, false);
+    else if (out_depth)
+      ODGS_FWD1(false, true);
     else if constexpr (TILE >= 32)  // at 16x16 the union of two quadrants' lists costs more than it saves
       hipLaunchKernelGGL((render_fwd2_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE / 2), 0, st, vt, ranges,
                          items, rec, out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
     else
-      hipLaunchKernelGGL((render_fwd_kernel<TILE, BATCH, false>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges,
-                         items, rec, out_rgb, out_T, wT, wl, wn, we, wle, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+      ODGS_FWD1(false, false);
+#undef ODGS_FWD1
   }
 };
 
@@ -845,7 +859,8 @@ bool dispatch(int tile, int batch, Args&&... args) {
 
 }  // namespace
 
-hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float* out_T, hipStream_t st) {
+hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float* out_T, float* out_depth,
+                             hipStream_t st) {
   const ViewTable vt = make_view_table(p);
   const int tiles = p->tile_base[p->n_views];
   if (tiles == 0) return hipSuccess;
@@ -857,8 +872,9 @@ hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float
   int32_t* wn = ws_ptr<int32_t>(ws, p->off_ncontrib);
   int32_t* we = ws_ptr<int32_t>(ws, p->off_neval);
   int32_t* wle = ws_ptr<int32_t>(ws, p->off_lasteval);
+  const float* depth = ws_ptr<float>(ws, p->off_depth);
   if (!dispatch<FwdRun>(p->s.tile, p->s.batch, p, tiles, vt, ranges, items, rec, out_rgb, out_T, wT, wl, wn, we, wle,
-                        st))
+                        depth, out_depth, st))
     return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -112,12 +112,16 @@ class Rasterizer:
                 raise RuntimeError("pair list still overflows after growing to %d" % self.capacity)
         return st
 
-    def render_fwd(self, out_rgb: torch.Tensor | None = None, out_T: torch.Tensor | None = None, want_T=True):
+    def render_fwd(self, out_rgb: torch.Tensor | None = None, out_T: torch.Tensor | None = None, want_T=True,
+                   out_depth: torch.Tensor | None = None):
+        """Images (and final transmittance, whose complement is the accumulated alpha).  Pass
+        out_depth (float32 [pixels]) to also get the alpha-weighted depth sum_j alpha_j T_j d_j."""
         if out_rgb is None:
             out_rgb = torch.empty(3 * self.pixels, dtype=torch.float32, device=self.device)
         if out_T is None and want_T:
             out_T = torch.empty(self.pixels, dtype=torch.float32, device=self.device)
-        B.odgs_render_fwd(self.plan, _ptr(self.ws), self.ws_bytes, _ptr(out_rgb), _ptr(out_T), _stream())
+        B.odgs_render_fwd(self.plan, _ptr(self.ws), self.ws_bytes, _ptr(out_rgb), _ptr(out_T), _ptr(out_depth),
+                          _stream())
         self.generation += 1
         return out_rgb, out_T
 

@@ -67,7 +67,7 @@ def test_entry_points_validate_on_host(lib):
     fake = ctypes.c_void_p(256 * 1024)  # never dereferenced: validation fails first
     assert lib.odgs_preprocess(ctypes.byref(p), fake, fake, fake, fake, fake, fake, nul, p.ws_bytes, nul) == B.EINVAL
     assert lib.odgs_bin_sort(ctypes.byref(p), fake, p.ws_bytes - 1, nul) == B.ENOSPACE
-    assert lib.odgs_render_fwd(ctypes.byref(p), fake, p.ws_bytes, nul, nul, nul) == B.EINVAL
+    assert lib.odgs_render_fwd(ctypes.byref(p), fake, p.ws_bytes, nul, nul, nul, nul) == B.EINVAL
     misaligned = ctypes.c_void_p(256 * 1024 + 2)
     assert lib.odgs_preprocess(ctypes.byref(p), misaligned, fake, fake, fake, fake, fake, fake, p.ws_bytes,
                                nul) == B.EINVAL

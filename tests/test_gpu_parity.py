@@ -240,3 +240,27 @@ def test_other_tiles_forward_and_backward(tile, batch):
     G.assert_grads_close({k: res["g2d"][..., j] for j, k in enumerate(labels)},
                          {k: ref2d[..., j] for j, k in enumerate(labels)}, names=labels)
     G.assert_grads_close(res["grads"], ref)
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_alpha_weighted_depth_output(tile):
+    """The forward's depth output against the oracle's sum_j alpha_j T_j d_j (ERP and pinhole
+    views in one batch), and an image identical to the plain forward."""
+    import torch
+    from paper_2410_20686_amd.rasterizer import Rasterizer
+    sc = scenes.roaming_scene(3001, 3, seed=71, r_range=(2.0, 9.0))
+    erp = scenes.yaw_cameras(2, 256, 128, seed=71)
+    faces = scenes.cubemap_cameras(64)
+    cams = scenes.Cameras(np.concatenate([erp.cams, faces.cams[:2]]), np.concatenate([erp.wh, faces.wh[:2]]))
+    st = settings(tile=tile, pinhole={2: (32.0, 32.0, 32.0, 32.0), 3: (32.0, 32.0, 32.0, 32.0)})
+    ref = O.render(sc, cams, st, mode=32)
+    res = G.run_gpu(sc, cams, st, return_rast=True)
+    rast = res["rast"]
+    depth = torch.empty(rast.pixels, dtype=torch.float32, device="cuda")
+    rgb2, _ = rast.render_fwd(out_depth=depth)
+    d = depth.cpu().numpy()
+    ok = G.strict_pixels(ref["margin"])
+    err = np.abs(d - ref["depth"])[ok]
+    assert (err <= 1e-4 * np.maximum(1.0, ref["depth"][ok]) + 1e-5).all(), err.max()
+    np.testing.assert_array_equal(rgb2.cpu().numpy(), res["rgb"])
+    assert (d[ok] > 0).mean() > 0.5

@@ -38,6 +38,21 @@ def test_stacked_identical_gaussians(k):
     assert r["ncontrib"][0] == n
     np.testing.assert_allclose(r["T"][0], (1 - a) ** n, rtol=1e-12)
     np.testing.assert_allclose(r["rgb"][0], rgb * (1 - (1 - a) ** n), rtol=1e-12)
+    # alpha-weighted depth: every contributor sits at radial depth 5
+    np.testing.assert_allclose(r["depth"][0], 5.0 * (1 - (1 - a) ** n), rtol=1e-12)
+
+
+def test_alpha_weighted_depth_of_two_layers():
+    """Two Gaussians on one ray at radial depths 3 and 6: D = a1 3 + a2 (1 - a1) 6."""
+    sc = make_scene([[0.0, 0.0, 6.0], [0.0, 0.0, 3.0]], [[0.4, 0.4, 0.4], [0.2, 0.2, 0.2]], opac=[0.7, 0.5])
+    cams = scenes.identity_cameras(256, 128)
+    rows = O.project(sc, cams, settings())[0]
+    x, y = 127, 63
+    a_far = _alpha_at(rows[0], 0.7, x + 0.5, y + 0.5)
+    a_near = _alpha_at(rows[1], 0.5, x + 0.5, y + 0.5)
+    r = O.render(sc, cams, settings(), mode=64, pix=np.array([[0, x, y]], dtype=np.int32))
+    np.testing.assert_allclose(r["depth"][0], a_near * 3.0 + a_far * (1 - a_near) * 6.0, rtol=1e-12)
+    np.testing.assert_allclose(r["T"][0], (1 - a_near) * (1 - a_far), rtol=1e-12)
 
 
 def test_front_to_back_order_by_radial_depth():
