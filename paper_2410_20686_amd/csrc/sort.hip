@@ -87,20 +87,24 @@ __global__ __launch_bounds__(256) void radix_digit_scan_kernel(uint32_t* __restr
 }
 
 // Stable scatter of one digit pass.  vin == nullptr means the values are the input positions.
-// Phase 1 ranks the block's keys within their digit (rounds of 256 keys in input order; inside a
-// round, wavefront multi-split by 8 ballots, then an exclusive prefix over the wavefronts).
-// Phase 2 places the keys digit-sorted in LDS; phase 3 writes them out in that order, so
-// consecutive threads store consecutive addresses of each digit's output run.
+// Phase 1: each wavefront ranks its own contiguous quarter of the block's keys (rounds of 64 in
+// input order; per round a multi-split by 8 ballots gives the rank among same-digit peers, added
+// to the wavefront's running per-digit count in LDS) with no block barriers; one exclusive prefix
+// over the wavefronts per digit then makes the ranks block-wide and stable.  Phase 2 places the
+// keys digit-sorted in LDS; phase 3 writes them out in that order, so consecutive threads store
+// consecutive addresses of each digit's output run.
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot, int nblocks) {
+  constexpr int NW = kSortThreads / kWave;
+  constexpr int PER_WAVE = kSortBlockItems / NW;
+  constexpr int ROUNDS = PER_WAVE / kWave;
   __shared__ uint32_t s_key[kSortBlockItems];
   __shared__ uint32_t s_val[kSortBlockItems];
-  __shared__ uint32_t cnt[256];      // running per-digit count inside the block
-  __shared__ uint32_t lstart[256];   // local (block) start of each digit
-  __shared__ uint32_t gstart[256];   // global start of each digit for this block
-  __shared__ uint32_t wcnt[4][256];
+  __shared__ uint32_t wh[NW][256];    // per-wavefront running digit counts, then their prefixes
+  __shared__ uint32_t lstart[256];    // local (block) start of each digit
+  __shared__ uint32_t gstart[256];    // global start of each digit for this block
   __shared__ uint32_t lds[4];
   const int t = threadIdx.x, lane = t & (kWave - 1), wave = t >> 6;
   const uint32_t n = active_count(n_dev, n_host);
@@ -111,55 +115,59 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
   const uint32_t dt = digit_tot[t];
   const uint32_t incl = block_incl_scan256(dt, lds, total);
   gstart[t] = incl - dt + hist[t * nblocks + blockIdx.x];
-  cnt[t] = 0;
 #pragma unroll
-  for (int w = 0; w < 4; ++w) wcnt[w][t] = 0;
+  for (int w = 0; w < NW; ++w) wh[w][t] = 0;
   __syncthreads();
   const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-  uint32_t key[kSortIpt], val[kSortIpt], rank[kSortIpt];
+  uint32_t key[ROUNDS], val[ROUNDS], rank[ROUNDS];
 #pragma unroll
-  for (int r = 0; r < kSortIpt; ++r) {
-    const uint32_t li = r * kSortThreads + t;
+  for (int r = 0; r < ROUNDS; ++r) {
+    const uint32_t li = (uint32_t)(wave * PER_WAVE + r * kWave + lane);
     const bool valid = li < nb;
     key[r] = valid ? kin[start + li] : 0u;
     val[r] = valid ? (vin ? vin[start + li] : start + li) : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const uint32_t li = (uint32_t)(wave * PER_WAVE + r * kWave + lane);
+    const bool valid = li < nb;
     const uint32_t d = (key[r] >> shift) & 255u;
-    uint64_t peers = __ballot(valid);
+    uint64_t peers = __builtin_amdgcn_ballot_w64(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
       const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
+      const uint64_t bb = __builtin_amdgcn_ballot_w64(bit);
       peers &= bit ? bb : ~bb;
     }
     const uint32_t wr = __popcll(peers & lanes_below);
-    if (valid && wr == 0) wcnt[wave][d] = __popcll(peers);
-    __syncthreads();
-    {
-      const uint32_t b0 = cnt[t];
-      const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
-      wcnt[0][t] = b0;
-      wcnt[1][t] = b0 + c0;
-      wcnt[2][t] = b0 + c0 + c1;
-      wcnt[3][t] = b0 + c0 + c1 + c2;
-      cnt[t] = b0 + c0 + c1 + c2 + c3;
-    }
-    __syncthreads();
-    rank[r] = valid ? wcnt[wave][d] + wr : 0u;
-    __syncthreads();
-#pragma unroll
-    for (int w = 0; w < 4; ++w) wcnt[w][t] = 0;
-    __syncthreads();
+    // every lane of a peer group reads the group's running count, then its first lane advances it
+    // (one wavefront's LDS operations execute in order)
+    const uint32_t base = wh[wave][d];
+    __builtin_amdgcn_wave_barrier();
+    rank[r] = base + wr;
+    if (valid && wr == 0) wh[wave][d] = base + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
   }
-  // local digit starts
-  const uint32_t c = cnt[t];
-  const uint32_t ci = block_incl_scan256(c, lds, total);
-  lstart[t] = ci - c;
+  __syncthreads();
+  // per digit: exclusive prefix over the wavefronts, block totals, local digit starts
+  {
+    uint32_t run = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const uint32_t c = wh[w][t];
+      wh[w][t] = run;
+      run += c;
+    }
+    const uint32_t ci = block_incl_scan256(run, lds, total);
+    lstart[t] = ci - run;
+  }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kSortIpt; ++r) {
-    const uint32_t li = r * kSortThreads + t;
+  for (int r = 0; r < ROUNDS; ++r) {
+    const uint32_t li = (uint32_t)(wave * PER_WAVE + r * kWave + lane);
     if (li < nb) {
-      const uint32_t p = lstart[(key[r] >> shift) & 255u] + rank[r];
+      const uint32_t d = (key[r] >> shift) & 255u;
+      const uint32_t p = lstart[d] + wh[wave][d] + rank[r];
       s_key[p] = key[r];
       s_val[p] = val[r];
     }
