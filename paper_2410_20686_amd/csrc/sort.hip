@@ -346,14 +346,38 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restr
   }
 }
 
+// Tile ranges from the sorted keys: each thread scans eight consecutive keys (two 16-byte loads
+// when the run is whole) and marks where a tile's run starts and ends.
+constexpr int kRangeKeys = 8;
+
 __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* __restrict__ keys,
                                                      const odgs_status* __restrict__ status, uint2* __restrict__ ranges) {
-  const uint32_t j = blockIdx.x * 256 + threadIdx.x;
   const uint32_t n = (uint32_t)status->n_pairs_stored;
-  if (j >= n) return;
-  const uint32_t k = keys[j];
-  if (j == 0 || keys[j - 1] != k) ranges[k].x = j;
-  if (j + 1 == n || keys[j + 1] != k) ranges[k].y = j + 1;
+  const uint32_t j0 = (blockIdx.x * 256 + threadIdx.x) * (uint32_t)kRangeKeys;
+  if (j0 >= n) return;
+  uint32_t k[kRangeKeys];
+  if (j0 + kRangeKeys <= n) {
+    const uint4 a = *reinterpret_cast<const uint4*>(keys + j0);
+    const uint4 b = *reinterpret_cast<const uint4*>(keys + j0 + 4);
+    k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w;
+    k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < kRangeKeys; ++i) k[i] = j0 + i < n ? keys[j0 + i] : 0u;
+  }
+  uint32_t prev = j0 > 0 ? keys[j0 - 1] : ~k[0];
+  const uint32_t after = j0 + kRangeKeys < n ? keys[j0 + kRangeKeys] : 0u;
+#pragma unroll
+  for (int i = 0; i < kRangeKeys; ++i) {
+    const uint32_t j = j0 + i;
+    if (j < n) {
+      if (prev != k[i]) ranges[k[i]].x = j;
+      const bool last = j + 1 == n;
+      const uint32_t next = i + 1 < kRangeKeys ? k[i + 1] : after;
+      if (last || next != k[i]) ranges[k[i]].y = j + 1;
+    }
+    prev = k[i];
+  }
 }
 
 __global__ void status_reset_kernel(odgs_status* st) {
@@ -441,8 +465,8 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
                  hist, digit, st);
   if (e != hipSuccess) return e;
   // 5. tile ranges
-  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((p->pair_capacity + 255) / 256)), dim3(256), 0, st,
-                     pk[p->pair_final], status, ranges);
+  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((p->pair_capacity + 256 * kRangeKeys - 1) / (256 * kRangeKeys))),
+                     dim3(256), 0, st, pk[p->pair_final], status, ranges);
   return hipGetLastError();
 }
 
