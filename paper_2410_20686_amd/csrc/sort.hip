@@ -50,23 +50,38 @@ __device__ inline uint32_t active_count(const uint32_t* n_dev, uint32_t n_host) 
   return n_dev ? min(*n_dev, n_host) : n_host;
 }
 
-// Per-block histogram of the 8-bit digit at `shift`: hist[digit * nblocks + block].
+// Per-block histogram of the 8-bit digit at `shift`: hist[digit * nblocks + block].  Each
+// wavefront counts into its own LDS histogram (a quarter of the same-address atomics), reading
+// four consecutive keys per 16-byte load.
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
                                                                  const uint32_t* __restrict__ n_dev, uint32_t n_host,
                                                                  int shift, uint32_t* __restrict__ hist, int nblocks) {
-  __shared__ uint32_t h[256];
-  const int t = threadIdx.x;
-  h[t] = 0;
+  constexpr int NW = kSortThreads / kWave;
+  __shared__ uint32_t h[NW][256];
+  const int t = threadIdx.x, wave = t >> 6;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) h[w][t] = 0;
   __syncthreads();
   const uint32_t n = active_count(n_dev, n_host);
   const uint32_t start = blockIdx.x * (uint32_t)kSortBlockItems;
-#pragma unroll 4
-  for (int r = 0; r < kSortIpt; ++r) {
-    const uint32_t idx = start + r * kSortThreads + t;
-    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+#pragma unroll
+  for (int r = 0; r < kSortIpt / 4; ++r) {
+    const uint32_t idx = start + 4u * (uint32_t)(r * kSortThreads + t);
+    if (idx + 4 <= n) {
+      const uint4 k4 = *reinterpret_cast<const uint4*>(keys + idx);
+      atomicAdd(&h[wave][(k4.x >> shift) & 255u], 1u);
+      atomicAdd(&h[wave][(k4.y >> shift) & 255u], 1u);
+      atomicAdd(&h[wave][(k4.z >> shift) & 255u], 1u);
+      atomicAdd(&h[wave][(k4.w >> shift) & 255u], 1u);
+    } else {
+      for (uint32_t i = idx; i < n && i < idx + 4; ++i) atomicAdd(&h[wave][(keys[i] >> shift) & 255u], 1u);
+    }
   }
   __syncthreads();
-  hist[t * nblocks + blockIdx.x] = h[t];
+  uint32_t c = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) c += h[w][t];
+  hist[t * nblocks + blockIdx.x] = c;
 }
 
 // Block d: exclusive scan of hist[d][0..nblocks) in place; digit total to digit_tot[d].
