@@ -120,6 +120,7 @@ struct Camera {
 };
 
 struct Settings {
+  bool spherical = false;  // exact per-ray footprint in equirectangular views (see project())
   int tile;          // tile edge in pixels (binning only)
   double near_r;     // spherical-shell culling radii (Sec. 3.2: shell instead of frustum)
   double far_r;
@@ -135,7 +136,7 @@ struct Scene {
 };
 
 // Settings array: [tile, near, far, dilation, pole_eps, bg0, bg1, bg2, P] followed by P records
-// (view, fx, fy, cx, cy) marking pinhole views.
+// (view, fx, fy, cx, cy) marking pinhole views, then the footprint model (0 affine, 1 spherical).
 void read_pinholes(const double* s, std::vector<Camera>& cams) {
   const int P = (int)s[8];
   for (int k = 0; k < P; ++k) {
@@ -159,6 +160,7 @@ Settings read_settings(const double* s) {
   st.bg[0] = s[5];
   st.bg[1] = s[6];
   st.bg[2] = s[7];
+  st.spherical = s[9 + 5 * (int)s[8]] != 0.0;
   return st;
 }
 
@@ -228,6 +230,10 @@ struct Proj {
   S cov2[3];      // 2D covariance (uu, uv, vv), dilation included
   S opacity;
   S rgb[3];
+  // spherical footprint (equirectangular views with Settings::spherical):
+  S mu_hat[3];    // unit direction of the camera-space mean
+  S A[6];         // inverse of the normalised covariance (xx xy xz yy yz zz)
+  S Q[6], w[3], k2;  // the same quadratic forms in the kernel's parameterisation (see make_sph_rec)
 };
 
 struct Info {
@@ -241,12 +247,17 @@ struct Info {
   double rgb_raw[3];   // colour before the clamp at zero
   int rgb_clamped[3];
   int col0, ncols, row0, nrows;  // tile rectangle (columns wrap around the seam)
+  bool spherical;      // evaluated with the spherical footprint
+  double scov[6];      // normalised camera-space covariance Sigma~ (xx xy xz yy yz zz)
+  double beta;         // half-angle of the cone of rays that can reach alpha >= 1/255
 };
 
 template <typename S>
 void project(const S m[3], const S s[3], const S q[4], const S& o, const double* shg, int64_t sh_stride,
              int K, const Camera& cam, const Settings& st, Proj<S>& out, Info& info) {
   info.cull = KEPT;
+  info.spherical = false;
+  info.beta = 0.0;
   const double pi = M_PI;
   const double Wd = cam.W, Hd = cam.H;
 
@@ -315,6 +326,52 @@ void project(const S m[3], const S s[3], const S q[4], const S& o, const double*
                                                  M[3 * r + 2] * M[3 * c + 2];
   info.cov3[0] = val(Sig[0]); info.cov3[1] = val(Sig[1]); info.cov3[2] = val(Sig[2]);
   info.cov3[3] = val(Sig[4]); info.cov3[4] = val(Sig[5]); info.cov3[5] = val(Sig[8]);
+
+  // Spherical footprint (the paper's stated limitation of the local affine approximation, Sec. 5,
+  // addressed exactly): instead of a 2D Gaussian on the image, each pixel ray t d (t > 0) is
+  // given the largest value the 3D Gaussian takes along it, exp(-m/2) with
+  //   m(d) = min_t (t d - mu)^T Sigma_cam^-1 (t d - mu).
+  // m is unchanged when mu and Sigma_cam are scaled by 1/r and 1/r^2, so the quadratic form is
+  // kept at unit distance: mu^ = mu / r, Sigma~ = Sigma_cam / r^2 + delta I.  The 3DGS low-pass
+  // term becomes an isotropic angular variance delta = dilation (pi / H)^2 (dilation in squared
+  // pixels at the vertical pixel pitch).
+  info.spherical = st.spherical && !cam.pinhole;
+  S detA = S(1.0);
+  if (info.spherical) {
+    S RS[9], Sc[9];  // W Sigma, then W Sigma W^T
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        RS[3 * r + c] = (cam.R[3 * r + 0] * Sig[0 * 3 + c] + cam.R[3 * r + 1] * Sig[1 * 3 + c]) + cam.R[3 * r + 2] * Sig[2 * 3 + c];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        Sc[3 * r + c] = (RS[3 * r + 0] * cam.R[3 * c + 0] + RS[3 * r + 1] * cam.R[3 * c + 1]) + RS[3 * r + 2] * cam.R[3 * c + 2];
+    const double dang = st.dilation * (pi / Hd) * (pi / Hd);
+    const S ir2 = 1.0 / r2;
+    const S C[6] = {Sc[0] * ir2 + dang, Sc[1] * ir2, Sc[2] * ir2, Sc[4] * ir2 + dang, Sc[5] * ir2, Sc[8] * ir2 + dang};
+    for (int k = 0; k < 6; ++k) info.scov[k] = val(C[k]);
+    // inverse by cofactors: [[a, b, c], [b, d, e], [c, e, f]]
+    const S &a = C[0], &b = C[1], &c = C[2], &d = C[3], &e = C[4], &f = C[5];
+    const S c00 = d * f - e * e, c01 = c * e - b * f, c02 = b * e - c * d;
+    const S c11 = a * f - c * c, c12 = b * c - a * e, c22 = a * d - b * b;
+    const S det3 = (a * c00 + b * c01) + c * c02;
+    out.A[0] = c00 / det3; out.A[1] = c01 / det3; out.A[2] = c02 / det3;
+    out.A[3] = c11 / det3; out.A[4] = c12 / det3; out.A[5] = c22 / det3;
+    detA = det3;
+    for (int k = 0; k < 3; ++k) out.mu_hat[k] = mu[k] / rr;
+    // The kernel's parameterisation of the same function: with cA = mu^T A mu and y = A mu,
+    //   h(d) = w . d,  w = y / cA;   q(d) = d^T Q d,  Q = (A - y y^T / cA) / 2;   k2 = 2 / cA,
+    // m = 2 q / (h^2 + k2 q) for h > 0 (h > 0 <=> the minimising t is positive).
+    const S* A6 = out.A;
+    const S y0 = (A6[0] * out.mu_hat[0] + A6[1] * out.mu_hat[1]) + A6[2] * out.mu_hat[2];
+    const S y1 = (A6[1] * out.mu_hat[0] + A6[3] * out.mu_hat[1]) + A6[4] * out.mu_hat[2];
+    const S y2 = (A6[2] * out.mu_hat[0] + A6[4] * out.mu_hat[1]) + A6[5] * out.mu_hat[2];
+    const S cA = (y0 * out.mu_hat[0] + y1 * out.mu_hat[1]) + y2 * out.mu_hat[2];
+    out.w[0] = y0 / cA; out.w[1] = y1 / cA; out.w[2] = y2 / cA;
+    out.Q[0] = 0.5 * (A6[0] - y0 * y0 / cA); out.Q[1] = 0.5 * (A6[1] - y0 * y1 / cA);
+    out.Q[2] = 0.5 * (A6[2] - y0 * y2 / cA); out.Q[3] = 0.5 * (A6[3] - y1 * y1 / cA);
+    out.Q[4] = 0.5 * (A6[4] - y1 * y2 / cA); out.Q[5] = 0.5 * (A6[5] - y2 * y2 / cA);
+    out.k2 = 2.0 / cA;
+  }
 
   S J[6];
   if (cam.pinhole) {
@@ -403,8 +460,54 @@ void project(const S m[3], const S s[3], const S q[4], const S& o, const double*
   // p_min = -ln(255 o); Gaussians with o <= 1/255 never contribute.
   info.p_min = -std::log(255.0 * val(o));
   if (!(info.p_min < 0.0)) { info.cull = CULL_OPACITY; return; }
-  if (!(val(det) > 0.0)) { info.cull = CULL_DET; return; }
+  if (!(val(info.spherical ? detA : det) > 0.0)) { info.cull = CULL_DET; return; }
   if (!finite) { info.cull = CULL_NONFINITE; return; }
+
+  const int B = st.tile;
+  const int ntx = cam.W / B, nty = cam.H / B;
+  if (info.spherical) {
+    // Rays with m <= k^2 and a positive minimiser meet the ellipsoid m <= k^2 around mu^, which
+    // lies inside the ball of radius k sqrt(lambda_max(Sigma~)); the rays through that ball form
+    // a cone of half-angle beta = asin(k sqrt(lambda_max)) about mu^ (all directions when the
+    // ball holds the camera).  lambda_max(Sigma~) = max_i s_i^2 / r^2 + delta exactly.  The
+    // cone's latitude range is theta_c +- beta; its longitude half-width asin(sin beta / cos
+    // theta_c) unless it reaches a pole (then every column).  Padding as for the ellipse.
+    double smax2 = 0.0;
+    for (int k = 0; k < 3; ++k) smax2 = std::max(smax2, val(s[k]) * val(s[k]));
+    const double lam = smax2 / (info.r * info.r) + st.dilation * (pi / Hd) * (pi / Hd);
+    const double sb = std::sqrt(-2.0 * info.p_min * lam) * (1.0 + 1e-3);
+    const double thc = val(theta);
+    if (!(sb < 1.0)) {
+      info.beta = pi;
+      info.col0 = 0; info.ncols = ntx; info.row0 = 0; info.nrows = nty;
+      return;
+    }
+    const double beta = std::asin(sb);
+    info.beta = beta;
+    const double vlo = Hd / 2.0 - (Hd / pi) * (thc + beta) - 1e-2, vhi = Hd / 2.0 - (Hd / pi) * (thc - beta) + 1e-2;
+    const double rlo = std::max(0.0, std::floor(vlo / B)), rhi = std::min((double)(nty - 1), std::floor(vhi / B));
+    info.row0 = (int)rlo;
+    info.nrows = (int)(rhi - rlo + 1.0);
+    if (info.nrows <= 0) { info.cull = CULL_EMPTY; return; }
+    if (!(std::fabs(thc) + beta < pi / 2.0)) {
+      info.col0 = 0;
+      info.ncols = ntx;
+      return;
+    }
+    const double eu = (Wd / (2.0 * pi)) * std::asin(std::sin(beta) / std::cos(thc)) + 1e-2;
+    const double uu = val(out.u);
+    const double clo = std::floor((uu - eu) / B), chi = std::floor((uu + eu) / B);
+    if (!(chi - clo + 1.0 < (double)ntx)) {
+      info.col0 = 0;
+      info.ncols = ntx;
+    } else {
+      long long c0 = (long long)clo % ntx;
+      if (c0 < 0) c0 += ntx;
+      info.col0 = (int)c0;
+      info.ncols = (int)(chi - clo + 1.0);
+    }
+    return;
+  }
 
   // Footprint rectangle: the ellipse d^T Sigma^-1 d <= k^2 with k^2 = -2 p_min bounds every
   // pixel where alpha >= 1/255; its half-extents are sqrt(k^2 Sigma_uu), sqrt(k^2 Sigma_vv),
@@ -412,8 +515,6 @@ void project(const S m[3], const S s[3], const S q[4], const S& o, const double*
   const double k2 = -2.0 * info.p_min;
   const double eu = std::sqrt(k2 * info.cov2[0]) * (1.0 + 1e-3) + 1e-2;
   const double ev = std::sqrt(k2 * info.cov2[2]) * (1.0 + 1e-3) + 1e-2;
-  const int B = st.tile;
-  const int ntx = cam.W / B, nty = cam.H / B;
   const double uu = val(out.u), vv = val(out.v);
   const double clo = std::floor((uu - eu) / B), chi = std::floor((uu + eu) / B);
   if (cam.pinhole) {
@@ -562,6 +663,163 @@ PixResult composite(const int32_t* order, int64_t count, const Rec<R>* recs, int
 }
 
 // ----------------------------------------------------------------------------------------------
+// Spherical footprint: per-pixel rays and the two record forms.
+// ----------------------------------------------------------------------------------------------
+// Unit direction of the ray through the centre (x + 0.5, y + 0.5) of an equirectangular pixel:
+// Eq. equirec_proj inverted, then the spherical coordinates of Sec. 3.2 (azimuth from +z,
+// elevation from the z-x plane, y down).  The angles are formed with this exact sequence of
+// double operations (no contraction).
+void pixel_dir(int x, int y, int W, int H, double d[3]) {
+  const double phi = (((double)x + 0.5) - 0.5 * (double)W) * ((2.0 * M_PI) / (double)W);
+  const double th = (0.5 * (double)H - ((double)y + 0.5)) * (M_PI / (double)H);
+  const double cth = std::cos(th);
+  d[0] = cth * std::sin(phi);
+  d[1] = -std::sin(th);
+  d[2] = cth * std::cos(phi);
+}
+
+// Mode 64: the definition itself.  For the line t d, with a = d^T A d, b = d^T A mu^ and
+// c = mu^T A mu^, the minimum over t of the quadratic is c - b^2 / a at t = b / a; rays whose
+// minimiser is not in front of the camera (b <= 0) get nothing.
+struct SphRec64 {
+  double mu[3], A[6], o, pmin, rgb[3], depth;
+};
+
+inline double sym3(const double* A, const double* x, const double* y) {
+  return x[0] * (A[0] * y[0] + A[1] * y[1] + A[2] * y[2]) + x[1] * (A[1] * y[0] + A[3] * y[1] + A[4] * y[2]) +
+         x[2] * (A[2] * y[0] + A[4] * y[1] + A[5] * y[2]);
+}
+
+inline bool sph_power(const SphRec64& g, const double d[3], double& power) {
+  const double a = sym3(g.A, d, d), b = sym3(g.A, d, g.mu), c = sym3(g.A, g.mu, g.mu);
+  if (!(b > 0.0)) return false;
+  power = -0.5 * (c - b * b / a);
+  return !(power < g.pmin);
+}
+
+// Mode 32: the float form both sides decide in.  In the tangent frame of mu^ (e1 east, e2 =
+// mu^ x e1) let P, c and s33 be the blocks of Sigma~ (tangent 2x2, tangent-radial, radial).  The
+// same minimum is m = 2 qh / (h^2 + k2 qh) with
+//   qh = (u1 . d)^2 + (u2 . d)^2,  u1 = l0 e1 + l1 e2,  u2 = l2 e2   ((l0, l1; 0, l2): the
+//        factor of P^-1 / 2 used for the affine exponent),
+//   h  = w . d,  w = mu^ - (P^-1 c)_1 e1 - (P^-1 c)_2 e2,   k2 = 2 (s33 - c^T P^-1 c),
+// a sum of squares with no cancellation at the scale of the footprint.  Accepted iff h > 0 and
+// p_min D + qh <= 0 (D = h^2 + k2 qh, one fused multiply-add); the exponent is -qh / D.
+struct SphRec32 {
+  float u1[3], u2[3], w[3], k2, o, pmin, rgb[3], depth;
+};
+
+struct SphForm {
+  double u1[3], u2[3], w[3], k2;
+};
+
+SphForm sph_form(const Proj<double>& p, const Info& info) {
+  const double* m = p.mu_hat;
+  const double rh = std::sqrt(m[0] * m[0] + m[2] * m[2]);
+  const double e1[3] = {m[2] / rh, 0.0, -m[0] / rh};
+  const double e2[3] = {m[1] * e1[2] - m[2] * e1[1], m[2] * e1[0] - m[0] * e1[2], m[0] * e1[1] - m[1] * e1[0]};
+  const double* C = info.scov;
+  const double P11 = sym3(C, e1, e1), P12 = sym3(C, e1, e2), P22 = sym3(C, e2, e2);
+  const double c1 = sym3(C, e1, m), c2 = sym3(C, e2, m), s33 = sym3(C, m, m);
+  const double det = P11 * P22 - P12 * P12;
+  const double l0 = std::sqrt(P22 / (2.0 * det)), l1 = -P12 / (2.0 * det * l0), l2 = 1.0 / std::sqrt(2.0 * P22);
+  const double a1 = -(P22 * c1 - P12 * c2) / det, a2 = -(P11 * c2 - P12 * c1) / det;  // -P^-1 c
+  SphForm f;
+  for (int k = 0; k < 3; ++k) {
+    f.u1[k] = l0 * e1[k] + l1 * e2[k];
+    f.u2[k] = l2 * e2[k];
+    f.w[k] = m[k] + a1 * e1[k] + a2 * e2[k];
+  }
+  f.k2 = 2.0 * (s33 + (a1 * c1 + a2 * c2));
+  return f;
+}
+
+// The form evaluated in double (m, not the exponent; no acceptance test).
+double sph_form_m(const SphForm& f, const double d[3]) {
+  const double t1 = f.u1[0] * d[0] + f.u1[1] * d[1] + f.u1[2] * d[2];
+  const double t2 = f.u2[0] * d[0] + f.u2[1] * d[1] + f.u2[2] * d[2];
+  const double h = f.w[0] * d[0] + f.w[1] * d[1] + f.w[2] * d[2];
+  const double qh = t1 * t1 + t2 * t2;
+  return 2.0 * qh / (h * h + f.k2 * qh);
+}
+
+SphRec32 make_sph_rec32(const Proj<double>& p, const Info& info) {
+  const SphForm f = sph_form(p, info);
+  SphRec32 r;
+  for (int k = 0; k < 3; ++k) {
+    r.u1[k] = (float)f.u1[k];
+    r.u2[k] = (float)f.u2[k];
+    r.w[k] = (float)f.w[k];
+  }
+  r.k2 = (float)f.k2;
+  r.o = (float)p.opacity;
+  r.pmin = (float)info.p_min;
+  for (int k = 0; k < 3; ++k) r.rgb[k] = (float)p.rgb[k];
+  r.depth = info.depth;
+  return r;
+}
+
+SphRec64 make_sph_rec64(const Proj<double>& p, const Info& info) {
+  SphRec64 r;
+  for (int k = 0; k < 3; ++k) r.mu[k] = p.mu_hat[k];
+  for (int k = 0; k < 6; ++k) r.A[k] = p.A[k];
+  r.o = p.opacity;
+  r.pmin = info.p_min;
+  for (int k = 0; k < 3; ++k) r.rgb[k] = p.rgb[k];
+  r.depth = info.depth;
+  return r;
+}
+
+inline bool sph_power(const SphRec32& g, const float d[3], float& power) {
+  const float t1 = std::fma(g.u1[2], d[2], std::fma(g.u1[1], d[1], g.u1[0] * d[0]));
+  const float t2 = std::fma(g.u2[2], d[2], std::fma(g.u2[1], d[1], g.u2[0] * d[0]));
+  const float h = std::fma(g.w[2], d[2], std::fma(g.w[1], d[1], g.w[0] * d[0]));
+  const float qh = std::fma(t1, t1, t2 * t2);
+  const float D = std::fma(g.k2, qh, h * h);
+  if (!(h > 0.0f) || std::fma(g.pmin, D, qh) > 0.0f) return false;
+  power = -(qh / D);
+  return true;
+}
+
+// Front-to-back compositing of one pixel with the spherical footprint (the same 3DGS constants
+// and termination as composite()).
+template <typename R, typename SR>
+PixResult composite_sph(const int32_t* order, int64_t count, const SR* recs, const R d[3], const double* bg,
+                        std::vector<Contrib>* contrib) {
+  const R t_stop = (R)1e-4;
+  R T = (R)1.0;
+  R C[3] = {(R)0, (R)0, (R)0};
+  R Dp = (R)0;
+  PixResult res;
+  res.n_contrib = 0;
+  res.margin = 1e30;
+  res.sig = 0;
+  for (int64_t k = 0; k < count; ++k) {
+    const int32_t idx = order[k];
+    const SR& g = recs[idx];
+    R power;
+    if (!sph_power(g, d, power)) continue;
+    R alpha = g.o * exp_r(power);
+    int clamped = 0;
+    if (alpha > (R)0.99) { alpha = (R)0.99; clamped = 1; }
+    const R Tn = T * ((R)1 - alpha);
+    res.margin = std::min(res.margin, std::fabs((double)Tn / 1e-4 - 1.0));
+    if (Tn < t_stop) { res.sig = mix(res.sig, 0xffffffffULL); break; }
+    const R w = alpha * T;
+    for (int c = 0; c < 3; ++c) C[c] = C[c] + w * g.rgb[c];
+    Dp = Dp + w * (R)g.depth;
+    T = Tn;
+    res.n_contrib++;
+    res.sig = mix(res.sig, ((uint64_t)(uint32_t)idx << 1) | (uint64_t)clamped);
+    if (contrib) contrib->push_back(Contrib{idx, clamped, 0.0, 0.0});
+  }
+  for (int c = 0; c < 3; ++c) res.rgb[c] = (double)C[c] + (double)T * bg[c];
+  res.T = (double)T;
+  res.depth = (double)Dp;
+  return res;
+}
+
+// ----------------------------------------------------------------------------------------------
 // Whole-scene preparation shared by the entry points.
 // ----------------------------------------------------------------------------------------------
 struct Prepared {
@@ -703,6 +961,35 @@ PixResult render_pixel(const Prepared& P, const std::vector<Rec<R>>& recs, const
   return composite<R>(ord.data(), (int64_t)ord.size(), recs.data(), x, y, cam.W, !cam.pinhole, P.st.bg, contrib);
 }
 
+inline bool sph_view(const Prepared& P, int v) { return P.st.spherical && !P.cams[v].pinhole; }
+
+template <typename SR>
+std::vector<SR> make_sph_recs(const Prepared& P, int v, SR (*make)(const Proj<double>&, const Info&)) {
+  std::vector<SR> recs((size_t)P.n);
+  for (int64_t i = 0; i < P.n; ++i) {
+    const size_t it = (size_t)v * P.n + i;
+    if (P.info[it].cull == KEPT) recs[i] = make(P.proj[it], P.info[it]);
+  }
+  return recs;
+}
+
+template <typename R, typename SR>
+PixResult render_pixel_sph(const Prepared& P, const std::vector<SR>& recs, const Candidates* cand, int v, int x, int y,
+                           std::vector<Contrib>* contrib) {
+  const Camera& cam = P.cams[v];
+  double dd[3];
+  pixel_dir(x, y, cam.W, cam.H, dd);
+  const R d[3] = {(R)dd[0], (R)dd[1], (R)dd[2]};
+  if (cand) {
+    const int B = P.st.tile;
+    const int64_t tile = cand->tile_base[v] + (int64_t)(y / B) * (cam.W / B) + x / B;
+    const std::vector<int32_t>& lst = cand->band[tile];
+    return composite_sph<R, SR>(lst.data(), (int64_t)lst.size(), recs.data(), d, P.st.bg, contrib);
+  }
+  const std::vector<int32_t>& ord = P.order[v];
+  return composite_sph<R, SR>(ord.data(), (int64_t)ord.size(), recs.data(), d, P.st.bg, contrib);
+}
+
 // Reverse recursion over one pixel's contributors (Eq. alphablending differentiated):
 //   C_c = sum_j rgb_jc a_j T_j + T_final bg_c,  T_j = prod_{k<j} (1 - a_k)
 //   dC_c/d rgb_jc = a_j T_j
@@ -712,7 +999,7 @@ PixResult render_pixel(const Prepared& P, const std::vector<Rec<R>>& recs, const
 // with d power / d(a, b, c) = -(du^2/2, du dv, dv^2/2) and d power / d(u, v) = Sigma^-1 d.
 // g2d layout per item: [u, v, conic a, conic b, conic c, opacity, r, g, b].
 void pixel_backward(const std::vector<Contrib>& cl, const std::vector<Rec<double>>& rec64, const double* gpix,
-                    const double* bg, double* g2d_view) {
+                    const double* bg, double* g2d_view, int stride) {
   const size_t n = cl.size();
   std::vector<double> alpha(n), T(n + 1), G(n);
   T[0] = 1.0;
@@ -729,7 +1016,7 @@ void pixel_backward(const std::vector<Contrib>& cl, const std::vector<Rec<double
   for (int c = 0; c < 3; ++c) S[c] = T[n] * bg[c];
   for (size_t jj = n; jj-- > 0;) {
     const Rec<double>& g = rec64[cl[jj].idx];
-    double* out = g2d_view + (size_t)cl[jj].idx * 9;
+    double* out = g2d_view + (size_t)cl[jj].idx * stride;
     double dL_da = 0.0;
     for (int c = 0; c < 3; ++c) {
       const double grgb = gpix[c] * alpha[jj] * T[jj];
@@ -764,12 +1051,102 @@ void pixel_backward(const std::vector<Contrib>& cl, const std::vector<Rec<double
   }
 }
 
-// Adjoint of the per-(Gaussian, view) projection, summed over views: acc [V][N][9] holds the
-// per-item 2D gradients (u, v, three 2D-shape entries, opacity, r, g, b), the shape entries with
-// respect to the inverse covariance (a, b, c) or, with `sigma`, the covariance (uu, uv, vv; the
-// off-diagonal as one shared variable).
-void project_adjoint(const Scene& sc, const Prepared& P, const std::vector<double>& acc, bool sigma, double* d_means,
-                     double* d_scales, double* d_quats, double* d_opac, double* d_sh) {
+// Reverse recursion for the spherical footprint (same alpha / T recursion as pixel_backward).
+// Per contributor the exponent is power = -m / 2 with m the minimum over t of the quadratic along
+// the ray; by the envelope theorem its derivatives are those of the quadratic at the fixed
+// minimiser t* = b / a: with v = t* d - mu^, dm/dA = v v^T and dm/dmu^ = -2 A v.
+//   g_def [stride]: mu^ (3), A (6, off-diagonals as one shared variable), opacity, r, g, b.
+//   g_ker [14] (optional): the same gradient in the kernel's variables of the exponent
+//     -qh / D, qh = d^T Q d, h = w . d, D = h^2 + k2 qh:  Q (6, shared), w (3), k2, opacity, rgb.
+void pixel_backward_sph(const std::vector<Contrib>& cl, const std::vector<SphRec64>& rec, const Proj<double>* proj,
+                        const double d[3], const double* gpix, const double* bg, double* g_def, int stride,
+                        double* g_ker) {
+  const size_t n = cl.size();
+  std::vector<double> alpha(n), T(n + 1), G(n), pw(n);
+  T[0] = 1.0;
+  for (size_t j = 0; j < n; ++j) {
+    const SphRec64& g = rec[cl[j].idx];
+    double p = 0.0;
+    sph_power(g, d, p);
+    pw[j] = p;
+    G[j] = std::exp(p);
+    alpha[j] = cl[j].clamped ? 0.99 : g.o * G[j];
+    T[j + 1] = T[j] * (1.0 - alpha[j]);
+  }
+  double S[3];
+  for (int c = 0; c < 3; ++c) S[c] = T[n] * bg[c];
+  for (size_t jj = n; jj-- > 0;) {
+    const SphRec64& g = rec[cl[jj].idx];
+    double out[13] = {0};
+    double ker[14] = {0};
+    double dL_da = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      out[10 + c] = gpix[c] * alpha[jj] * T[jj];
+      dL_da += gpix[c] * (g.rgb[c] * T[jj] - S[c] / (1.0 - alpha[jj]));
+      S[c] += g.rgb[c] * alpha[jj] * T[jj];
+    }
+    if (!cl[jj].clamped) {
+      const double dL_dpow = dL_da * alpha[jj];
+      const double a = sym3(g.A, d, d), b = sym3(g.A, d, g.mu);
+      const double t = b / a;
+      const double v[3] = {t * d[0] - g.mu[0], t * d[1] - g.mu[1], t * d[2] - g.mu[2]};
+      const double Av[3] = {g.A[0] * v[0] + g.A[1] * v[1] + g.A[2] * v[2], g.A[1] * v[0] + g.A[3] * v[1] + g.A[4] * v[2],
+                            g.A[2] * v[0] + g.A[4] * v[1] + g.A[5] * v[2]};
+      // dL/dm = -dL_dpow / 2
+      for (int k = 0; k < 3; ++k) out[k] = dL_dpow * Av[k];
+      out[3] = -0.5 * dL_dpow * v[0] * v[0];
+      out[4] = -dL_dpow * v[0] * v[1];
+      out[5] = -dL_dpow * v[0] * v[2];
+      out[6] = -0.5 * dL_dpow * v[1] * v[1];
+      out[7] = -dL_dpow * v[1] * v[2];
+      out[8] = -0.5 * dL_dpow * v[2] * v[2];
+      out[9] = dL_da * G[jj];
+      if (g_ker) {
+        const Proj<double>& pr = proj[cl[jj].idx];
+        const double qh = pr.Q[0] * d[0] * d[0] + 2.0 * pr.Q[1] * d[0] * d[1] + 2.0 * pr.Q[2] * d[0] * d[2] +
+                          pr.Q[3] * d[1] * d[1] + 2.0 * pr.Q[4] * d[1] * d[2] + pr.Q[5] * d[2] * d[2];
+        const double h = pr.w[0] * d[0] + pr.w[1] * d[1] + pr.w[2] * d[2];
+        const double D = h * h + pr.k2 * qh;
+        const double p = -qh / D;
+        const double gq = dL_dpow * -(h / D) * (h / D);  // dp/dqh = -(h / D)^2
+        const double gh = dL_dpow * (-2.0 * p * h / D);   // dp/dh = 2 qh h / D^2
+        ker[0] = gq * d[0] * d[0];
+        ker[1] = 2.0 * gq * d[0] * d[1];
+        ker[2] = 2.0 * gq * d[0] * d[2];
+        ker[3] = gq * d[1] * d[1];
+        ker[4] = 2.0 * gq * d[1] * d[2];
+        ker[5] = gq * d[2] * d[2];
+        for (int k = 0; k < 3; ++k) ker[6 + k] = gh * d[k];
+        ker[9] = dL_dpow * p * p;  // dp/dk2 = qh^2 / D^2
+        ker[10] = out[9];
+      }
+    }
+    for (int c = 0; c < 3; ++c) ker[11 + c] = out[10 + c];
+    double* o1 = g_def + (size_t)cl[jj].idx * stride;
+    for (int k = 0; k < 13; ++k) {
+      if (out[k] == 0.0) continue;
+#pragma omp atomic
+      o1[k] += out[k];
+    }
+    if (g_ker) {
+      double* o2 = g_ker + (size_t)cl[jj].idx * 14;
+      for (int k = 0; k < 14; ++k) {
+        if (ker[k] == 0.0) continue;
+#pragma omp atomic
+        o2[k] += ker[k];
+      }
+    }
+  }
+}
+
+// Adjoint of the per-(Gaussian, view) projection, summed over views.  acc [V][N][stride] holds
+// per-item gradients of the compositor's inputs.  Affine items: (u, v, three 2D-shape entries,
+// opacity, r, g, b), the shape entries with respect to the inverse covariance (a, b, c) or, with
+// `sigma`, the covariance (uu, uv, vv; the off-diagonal as one shared variable).  Spherical
+// items: (mu^, A, opacity, rgb) as pixel_backward_sph's g_def or, with `sigma`, its kernel
+// layout (Q, w, k2, opacity, rgb).
+void project_adjoint(const Scene& sc, const Prepared& P, const std::vector<double>& acc, int stride, bool sigma,
+                     double* d_means, double* d_scales, double* d_quats, double* d_opac, double* d_sh) {
   // Per-Gaussian chain rule: push the 2D gradients through the projection with dual numbers
   // (directions: mean xyz, scale xyz, quaternion wxyz, opacity), and the colour gradient
   // through the SH basis; sum over views.
@@ -782,9 +1159,11 @@ void project_adjoint(const Scene& sc, const Prepared& P, const std::vector<doubl
     std::vector<double> gsh((size_t)K * 3, 0.0);
     for (int v = 0; v < V; ++v) {
       const size_t it = (size_t)v * n + i;
-      const double* g = acc.data() + it * 9;
+      const double* g = acc.data() + it * stride;
+      const bool sph = P.info[it].spherical;
+      const int nv = sph ? (sigma ? 14 : 13) : 9;
       bool any = false;
-      for (int k = 0; k < 9; ++k) any = any || g[k] != 0.0;
+      for (int k = 0; k < nv; ++k) any = any || g[k] != 0.0;
       if (!any || P.info[it].cull != KEPT) continue;
       Dual m[3], s[3], q[4], o;
       for (int k = 0; k < 3; ++k) { m[k] = Dual(sc.means[k * n + i]); m[k].d[k] = 1.0; }
@@ -795,10 +1174,25 @@ void project_adjoint(const Scene& sc, const Prepared& P, const std::vector<doubl
       Proj<Dual> p;
       Info inf;
       project<Dual>(m, s, q, o, sc.sh + i, n, K, P.cams[v], P.st, p, inf);
-      const Dual* outs[9] = {&p.u, &p.v, sigma ? &p.cov2[0] : &p.conic[0], sigma ? &p.cov2[1] : &p.conic[1],
+      const Dual* outs[14];
+      if (!sph) {
+        const Dual* o9[9] = {&p.u, &p.v, sigma ? &p.cov2[0] : &p.conic[0], sigma ? &p.cov2[1] : &p.conic[1],
                              sigma ? &p.cov2[2] : &p.conic[2], &p.opacity, &p.rgb[0], &p.rgb[1], &p.rgb[2]};
+        std::copy(o9, o9 + 9, outs);
+      } else if (!sigma) {
+        for (int k = 0; k < 3; ++k) outs[k] = &p.mu_hat[k];
+        for (int k = 0; k < 6; ++k) outs[3 + k] = &p.A[k];
+      } else {
+        for (int k = 0; k < 6; ++k) outs[k] = &p.Q[k];
+        for (int k = 0; k < 3; ++k) outs[6 + k] = &p.w[k];
+        outs[9] = &p.k2;
+      }
+      if (sph) {
+        outs[nv - 4] = &p.opacity;
+        for (int k = 0; k < 3; ++k) outs[nv - 3 + k] = &p.rgb[k];
+      }
       double gd[ND] = {0};
-      for (int k = 0; k < 9; ++k)
+      for (int k = 0; k < nv; ++k)
         for (int d = 0; d < ND; ++d) gd[d] += g[k] * outs[k]->d[d];
       for (int k = 0; k < 3; ++k) gm[k] += gd[k];
       for (int k = 0; k < 3; ++k) gs[k] += gd[3 + k];
@@ -816,7 +1210,7 @@ void project_adjoint(const Scene& sc, const Prepared& P, const std::vector<doubl
       sh_basis<double>(dir, K, Y);
       for (int ch = 0; ch < 3; ++ch) {
         if (inf.rgb_clamped[ch]) continue;
-        for (int k = 0; k < K; ++k) gsh[(size_t)k * 3 + ch] += g[6 + ch] * Y[k];
+        for (int k = 0; k < K; ++k) gsh[(size_t)k * 3 + ch] += g[nv - 3 + ch] * Y[k];
       }
     }
     for (int k = 0; k < 3; ++k) d_means[k * n + i] = gm[k];
@@ -852,10 +1246,44 @@ void oracle_sh_basis(const double* dirs, int64_t n, int K, double* Y) {
   }
 }
 
-// Per-(view, Gaussian) projection rows of ORACLE_NF doubles, layout [V][N][40]:
+// Spherical footprint at single (view, x, y, gaussian) queries q [nq][4], for the pins: out [nq][6]
+// = (m by the definition c - b^2/a, b = d^T A mu^, m by the tangent-frame form in double, the
+// float exponent (0 where rejected), float acceptance, kept).  Every listed view must be
+// equirectangular and the settings must select the spherical footprint.
+int oracle_sph_eval(const double* means, const double* scales, const double* quats, const double* opac,
+                    const double* sh, int64_t n, int deg, const double* cams, const int32_t* wh, int V,
+                    const double* settings, const int32_t* q, int64_t nq, double* out) {
+  Scene sc = make_scene(means, scales, quats, opac, sh, n, deg);
+  Prepared P;
+  prepare(sc, cams, wh, V, settings, P);
+  for (int64_t k = 0; k < nq; ++k) {
+    const int v = q[4 * k], x = q[4 * k + 1], y = q[4 * k + 2], i = q[4 * k + 3];
+    double* o = out + 6 * k;
+    std::fill(o, o + 6, 0.0);
+    const size_t it = (size_t)v * n + i;
+    if (!sph_view(P, v) || P.info[it].cull != KEPT) continue;
+    o[5] = 1.0;
+    double d[3];
+    pixel_dir(x, y, P.cams[v].W, P.cams[v].H, d);
+    const SphRec64 r = make_sph_rec64(P.proj[it], P.info[it]);
+    const double a = sym3(r.A, d, d), b = sym3(r.A, d, r.mu), c = sym3(r.A, r.mu, r.mu);
+    o[0] = c - b * b / a;
+    o[1] = b;
+    o[2] = sph_form_m(sph_form(P.proj[it], P.info[it]), d);
+    const SphRec32 r32 = make_sph_rec32(P.proj[it], P.info[it]);
+    const float d32[3] = {(float)d[0], (float)d[1], (float)d[2]};
+    float pw = 0.0f;
+    const bool ok = sph_power(r32, d32, pw);
+    o[3] = ok ? pw : 0.0;
+    o[4] = ok;
+  }
+  return 0;
+}
+
+// Per-(view, Gaussian) projection rows of ORACLE_NF doubles, layout [V][N][41]:
 //  0 kept  1 cull  2 depth  3 depth bits  4 u  5 v  6..8 conic a,b,c  9 opacity  10 p_min
 //  11..13 rgb  14..17 col0 ncols row0 nrows  18..20 cov2 uu uv vv  21..26 J_omni  27..32 cov3
-//  33..35 mu  36 r  37..39 rgb before clamp
+//  33..35 mu  36 r  37..39 rgb before clamp  40 cone half-angle (spherical footprint)
 int oracle_project(const double* means, const double* scales, const double* quats, const double* opac,
                    const double* sh, int64_t n, int deg, const double* cams, const int32_t* wh, int V,
                    const double* settings, double* out) {
@@ -867,8 +1295,8 @@ int oracle_project(const double* means, const double* scales, const double* quat
       const size_t it = (size_t)v * n + i;
       const Proj<double>& p = P.proj[it];
       const Info& f = P.info[it];
-      double* o = out + it * 40;
-      std::fill(o, o + 40, 0.0);
+      double* o = out + it * 41;
+      std::fill(o, o + 41, 0.0);
       o[0] = f.cull == KEPT;
       o[1] = f.cull;
       o[2] = f.depth;
@@ -885,6 +1313,7 @@ int oracle_project(const double* means, const double* scales, const double* quat
       for (int k = 0; k < 6; ++k) o[21 + k] = f.J[k];
       for (int k = 0; k < 6; ++k) o[27 + k] = f.cov3[k];
       for (int k = 0; k < 3; ++k) o[37 + k] = f.rgb_raw[k];
+      o[40] = f.beta;
     }
   return 0;
 }
@@ -922,11 +1351,22 @@ int oracle_render(const double* means, const double* scales, const double* quats
   const Candidates* cp = band ? &cand : nullptr;
   std::vector<std::vector<Rec<float>>> r32(V);
   std::vector<std::vector<Rec<double>>> r64(V);
+  std::vector<std::vector<SphRec32>> s32(V);
+  std::vector<std::vector<SphRec64>> s64(V);
   for (int v = 0; v < V; ++v) {
-    if (mode == 32) r32[v] = make_recs<float>(P, v);
-    else r64[v] = make_recs<double>(P, v);
+    if (sph_view(P, v)) {
+      if (mode == 32) s32[v] = make_sph_recs<SphRec32>(P, v, make_sph_rec32);
+      else s64[v] = make_sph_recs<SphRec64>(P, v, make_sph_rec64);
+    } else if (mode == 32) {
+      r32[v] = make_recs<float>(P, v);
+    } else {
+      r64[v] = make_recs<double>(P, v);
+    }
   }
   auto one = [&](int v, int x, int y) {
+    if (sph_view(P, v))
+      return mode == 32 ? render_pixel_sph<float, SphRec32>(P, s32[v], cp, v, x, y, nullptr)
+                        : render_pixel_sph<double, SphRec64>(P, s64[v], cp, v, x, y, nullptr);
     return mode == 32 ? render_pixel<float>(P, r32[v], cp, v, x, y, nullptr)
                       : render_pixel<double>(P, r64[v], cp, v, x, y, nullptr);
   };
@@ -966,16 +1406,54 @@ int oracle_render(const double* means, const double* scales, const double* quats
 // mode-64 forward; all gradient arithmetic is double.  dL: with pix == NULL the full
 // [V][3][H][W] image gradient, else [npix][3] for the listed pixels only (others are zero).
 // Outputs (overwritten): d_means [3][N], d_scales [3][N], d_quats [4][N], d_opac [N],
-// d_sh [K*3][N]; g2d (optional, NULL to skip) [V][N][9] per-item 2D gradients.
+// d_sh [K*3][N]; g2d (optional, NULL to skip) [V][N][G] per-item gradients of the compositor's
+// inputs, G = 9 (affine) or 13 (spherical footprint: mu^, A, opacity, rgb); g2d_kernel
+// (optional, spherical footprint only) [V][N][14] the same in the kernel's variables.
 int oracle_backward(const double* means, const double* scales, const double* quats, const double* opac,
                     const double* sh, int64_t n, int deg, const double* cams, const int32_t* wh, int V,
                     const double* settings, int mode, const int32_t* pix, int64_t npix, const double* dL,
-                    double* d_means, double* d_scales, double* d_quats, double* d_opac, double* d_sh, double* g2d) {
+                    double* d_means, double* d_scales, double* d_quats, double* d_opac, double* d_sh, double* g2d,
+                    double* g2d_kernel) {
   Scene sc = make_scene(means, scales, quats, opac, sh, n, deg);
   Prepared P;
   prepare(sc, cams, wh, V, settings, P);
-  std::vector<double> acc((size_t)V * n * 9, 0.0);
+  const int stride = P.st.spherical ? 13 : 9;
+  std::vector<double> acc((size_t)V * n * stride, 0.0);
+  std::vector<double> acck(P.st.spherical && g2d_kernel ? (size_t)V * n * 14 : 0, 0.0);
   for (int v = 0; v < V; ++v) {
+    if (sph_view(P, v)) {
+      std::vector<SphRec32> s32;
+      std::vector<SphRec64> s64 = make_sph_recs<SphRec64>(P, v, make_sph_rec64);
+      if (mode == 32) s32 = make_sph_recs<SphRec32>(P, v, make_sph_rec32);
+      double* gv = acc.data() + (size_t)v * n * stride;
+      double* gk = acck.empty() ? nullptr : acck.data() + (size_t)v * n * 14;
+      const Proj<double>* pr = P.proj.data() + (size_t)v * n;
+      const int W = P.cams[v].W, H = P.cams[v].H;
+      auto run = [&](int x, int y, const double* gpix) {
+        if (gpix[0] == 0.0 && gpix[1] == 0.0 && gpix[2] == 0.0) return;
+        std::vector<Contrib> cl;
+        if (mode == 32) render_pixel_sph<float, SphRec32>(P, s32, nullptr, v, x, y, &cl);
+        else render_pixel_sph<double, SphRec64>(P, s64, nullptr, v, x, y, &cl);
+        double d[3];
+        pixel_dir(x, y, W, H, d);
+        pixel_backward_sph(cl, s64, pr, d, gpix, P.st.bg, gv, stride, gk);
+      };
+      if (pix == nullptr) {
+        const int64_t off = pix_offset(P, v);
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int y = 0; y < H; ++y)
+          for (int x = 0; x < W; ++x) {
+            double g[3];
+            for (int c = 0; c < 3; ++c) g[c] = dL[3 * off + (int64_t)c * W * H + (int64_t)y * W + x];
+            run(x, y, g);
+          }
+      } else {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t k = 0; k < npix; ++k)
+          if (pix[3 * k] == v) run(pix[3 * k + 1], pix[3 * k + 2], dL + 3 * k);
+      }
+      continue;
+    }
     std::vector<Rec<float>> r32;
     std::vector<Rec<double>> r64 = make_recs<double>(P, v);
     std::vector<Rec<double>> rvals;  // values used in the gradient arithmetic
@@ -990,14 +1468,14 @@ int oracle_backward(const double* means, const double* scales, const double* qua
     } else {
       rvals = r64;
     }
-    double* gv = acc.data() + (size_t)v * n * 9;
+    double* gv = acc.data() + (size_t)v * n * stride;
     const int W = P.cams[v].W, H = P.cams[v].H;
     auto run = [&](int x, int y, const double* gpix) {
       if (gpix[0] == 0.0 && gpix[1] == 0.0 && gpix[2] == 0.0) return;
       std::vector<Contrib> cl;
       if (mode == 32) render_pixel<float>(P, r32, nullptr, v, x, y, &cl);
       else render_pixel<double>(P, r64, nullptr, v, x, y, &cl);
-      pixel_backward(cl, rvals, gpix, P.st.bg, gv);
+      pixel_backward(cl, rvals, gpix, P.st.bg, gv, stride);
     };
     if (pix == nullptr) {
       const int64_t off = pix_offset(P, v);
@@ -1015,14 +1493,16 @@ int oracle_backward(const double* means, const double* scales, const double* qua
     }
   }
   if (g2d) std::memcpy(g2d, acc.data(), acc.size() * sizeof(double));
+  if (g2d_kernel && !acck.empty()) std::memcpy(g2d_kernel, acck.data(), acck.size() * sizeof(double));
 
-  project_adjoint(sc, P, acc, false, d_means, d_scales, d_quats, d_opac, d_sh);
+  project_adjoint(sc, P, acc, stride, false, d_means, d_scales, d_quats, d_opac, d_sh);
   return 0;
 }
 
-// Adjoint of the projection alone, for 2D gradients given in covariance terms (the layout the
-// GPU's reverse compositor produces): g2d [V][N][9] = (u, v, Sigma_uu, Sigma_uv (shared),
-// Sigma_vv, opacity, r, g, b).  Outputs as oracle_backward (overwritten).
+// Adjoint of the projection alone, for per-item gradients in the layout the GPU's reverse
+// compositor produces: g2d [V][N][9] = (u, v, Sigma_uu, Sigma_uv (shared), Sigma_vv, opacity,
+// r, g, b), or with the spherical footprint [V][N][14] = (Q (6, shared off-diagonals), w (3),
+// k2, opacity, r, g, b).  Outputs as oracle_backward (overwritten).
 int oracle_project_adjoint(const double* means, const double* scales, const double* quats, const double* opac,
                            const double* sh, int64_t n, int deg, const double* cams, const int32_t* wh, int V,
                            const double* settings, const double* g2d, double* d_means, double* d_scales,
@@ -1030,8 +1510,9 @@ int oracle_project_adjoint(const double* means, const double* scales, const doub
   Scene sc = make_scene(means, scales, quats, opac, sh, n, deg);
   Prepared P;
   prepare(sc, cams, wh, V, settings, P);
-  std::vector<double> acc(g2d, g2d + (size_t)V * n * 9);
-  project_adjoint(sc, P, acc, true, d_means, d_scales, d_quats, d_opac, d_sh);
+  const int stride = P.st.spherical ? 14 : 9;
+  std::vector<double> acc(g2d, g2d + (size_t)V * n * stride);
+  project_adjoint(sc, P, acc, stride, true, d_means, d_scales, d_quats, d_opac, d_sh);
   return 0;
 }
 

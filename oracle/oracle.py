@@ -18,9 +18,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "odgs_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-NF = 40  # doubles per projection row, see oracle_project in the C source
+NF = 41  # doubles per projection row, see oracle_project in the C source
 F_KEPT, F_CULL, F_DEPTH, F_DEPTH_BITS, F_U, F_V = 0, 1, 2, 3, 4, 5
 F_CONIC, F_OPAC, F_PMIN, F_RGB, F_RECT, F_COV2, F_J, F_COV3, F_MU, F_R, F_RGB_RAW = 6, 9, 10, 11, 14, 18, 21, 27, 33, 36, 37
+F_BETA = 40
 
 
 def build(force: bool = True) -> str:
@@ -54,10 +55,12 @@ def lib():
         L.oracle_keys.restype = i64
         L.oracle_render.argtypes = scene_args + [i32, i32, P, i64, P, P, P, P, P, P]
         L.oracle_render.restype = i32
-        L.oracle_backward.argtypes = scene_args + [i32, P, i64, P, P, P, P, P, P, P]
+        L.oracle_backward.argtypes = scene_args + [i32, P, i64, P, P, P, P, P, P, P, P]
         L.oracle_backward.restype = i32
         L.oracle_project_adjoint.argtypes = scene_args + [P, P, P, P, P, P]
         L.oracle_project_adjoint.restype = i32
+        L.oracle_sph_eval.argtypes = scene_args + [P, i64, P]
+        L.oracle_sph_eval.restype = i32
         _lib = L
     return _lib
 
@@ -77,6 +80,12 @@ def settings_array(settings: dict) -> np.ndarray:
     tail = [float(len(pin))]
     for v in sorted(pin):
         tail += [float(v)] + [float(np.float32(x)) for x in pin[v]]
+    # footprint model: "affine" (the paper's local affine approximation) or "spherical" (exact
+    # per-ray maximum of the 3D Gaussian in equirectangular views)
+    fp = settings.get("footprint", "affine")
+    if fp not in ("affine", "spherical"):
+        raise ValueError("footprint must be 'affine' or 'spherical'")
+    tail.append(1.0 if fp == "spherical" else 0.0)
     return np.array([settings["tile"], *vals, *tail], dtype=np.float64)
 
 
@@ -151,22 +160,43 @@ def render(scene, cams, settings, mode: int = 32, band: bool = False, pix: np.nd
     return dict(rgb=rgb, T=T, ncontrib=nc, margin=margin, sig=sig, depth=depth)
 
 
+def spherical(settings) -> bool:
+    return settings.get("footprint", "affine") == "spherical"
+
+
 def backward(scene, cams, settings, dL: np.ndarray, mode: int = 32, pix: np.ndarray | None = None,
              want_g2d: bool = False):
     """Gradient of sum(dL * rgb) w.r.t. every parameter (float64), and optionally the per-item
-    2D gradients [V][N][9] (u, v, conic a, b, c, opacity, r, g, b)."""
+    gradients of the compositor's inputs: affine footprint g2d [V][N][9] (u, v, conic a, b, c,
+    opacity, r, g, b); spherical footprint g2d [V][N][13] (mu^, A, opacity, rgb) and g2d_kernel
+    [V][N][14] (Q, w, k2, opacity, rgb; the reverse compositor's layout)."""
     a = _Args(scene, cams, settings)
     n, K = a.n, (a.deg + 1) ** 2
     gm, gs, gq = np.zeros((3, n)), np.zeros((3, n)), np.zeros((4, n))
     go, gsh = np.zeros(n), np.zeros((K * 3, n))
-    g2d = np.zeros((a.V, n, 9)) if want_g2d else None
+    sph = spherical(settings)
+    g2d = np.zeros((a.V, n, 13 if sph else 9)) if want_g2d else None
+    g2dk = np.zeros((a.V, n, 14)) if (want_g2d and sph) else None
     d = np.ascontiguousarray(dL, dtype=np.float64)
     pp = None if pix is None else np.ascontiguousarray(pix, dtype=np.int32)
     lib().oracle_backward(*a.tuple(), mode, _p(pp), 0 if pp is None else pp.shape[0], _p(d),
-                          _p(gm), _p(gs), _p(gq), _p(go), _p(gsh), _p(g2d))
+                          _p(gm), _p(gs), _p(gq), _p(go), _p(gsh), _p(g2d), _p(g2dk))
     out = dict(means=gm, scales=gs, quats=gq, opacities=go, sh=gsh)
     if want_g2d:
         out["g2d"] = g2d
+        if sph:
+            out["g2d_kernel"] = g2dk
+    return out
+
+
+def sph_eval(scene, cams, settings, queries: np.ndarray) -> np.ndarray:
+    """Spherical footprint at (view, x, y, gaussian) rows: [n][6] = (m by the definition,
+    b = d^T A mu^, m by the tangent-frame form in double, float exponent (0 if rejected), float
+    acceptance, kept)."""
+    a = _Args(scene, cams, settings)
+    q = np.ascontiguousarray(queries, dtype=np.int32).reshape(-1, 4)
+    out = np.zeros((q.shape[0], 6))
+    lib().oracle_sph_eval(*a.tuple(), _p(q), q.shape[0], _p(out))
     return out
 
 
@@ -188,13 +218,14 @@ def g2d_to_sigma(rows: np.ndarray, g2d: np.ndarray) -> np.ndarray:
 
 
 def project_adjoint(scene, cams, settings, g2d_sigma: np.ndarray):
-    """Parameter gradients from per-item 2D gradients [V][N][9] given in covariance terms
-    (u, v, Sigma_uu, Sigma_uv (shared), Sigma_vv, opacity, r, g, b), summed over views."""
+    """Parameter gradients from per-item gradients in the reverse compositor's layout, summed
+    over views: affine [V][N][9] in covariance terms (u, v, Sigma_uu, Sigma_uv (shared),
+    Sigma_vv, opacity, r, g, b); spherical footprint [V][N][14] (Q, w, k2, opacity, rgb)."""
     a = _Args(scene, cams, settings)
     n, K = a.n, (a.deg + 1) ** 2
     gm, gs, gq = np.zeros((3, n)), np.zeros((3, n)), np.zeros((4, n))
     go, gsh = np.zeros(n), np.zeros((K * 3, n))
     g = np.ascontiguousarray(g2d_sigma, dtype=np.float64)
-    assert g.shape == (a.V, n, 9)
+    assert g.shape == (a.V, n, 14 if spherical(settings) else 9)
     lib().oracle_project_adjoint(*a.tuple(), _p(g), _p(gm), _p(gs), _p(gq), _p(go), _p(gsh))
     return dict(means=gm, scales=gs, quats=gq, opacities=go, sh=gsh)
