@@ -50,6 +50,22 @@ enum {
 #define ODGS_STATUS_OVERFLOW 1 /* more Gaussian-tile pairs than plan->pair_capacity */
 #define ODGS_FLAG_COUNT_WORK 1 /* settings flag: odgs_render_fwd also records the per-pixel work
                                   counters of odgs_debug_pixel_counts (slower; for measurement) */
+#define ODGS_FLAG_SPHERICAL 2  /* settings flag: spherical footprint instead of the local affine
+                                  approximation, see below (not with pinhole views, not with
+                                  ODGS_FLAG_COUNT_WORK, no densification statistics) */
+
+/* Spherical footprint (ODGS_FLAG_SPHERICAL).  The paper names its local affine approximation
+ * of the projected Gaussian as its limitation (Sec. 5).  With this flag every pixel ray t d
+ * (t > 0, d the unit direction through the pixel centre, Eq. equirec_proj inverted) receives the
+ * largest value the 3D Gaussian takes along the ray, exp(-m / 2) with
+ *   m(d) = min_t (t d - mu^)^T Sigma~^-1 (t d - mu^),  mu^ = mu / |mu|,
+ *   Sigma~ = W Sigma W^T / |mu|^2 + dilation (pi / H)^2 I,
+ * so the footprint follows the curved image of the Gaussian exactly (the low-pass term becomes an
+ * isotropic angular variance of `dilation` squared pixels at the vertical pixel pitch).  Sorting,
+ * culling, compositing and the 3DGS constants are unchanged.  The tile rectangle bounds the cone
+ * of rays through the ball of radius k sqrt(lambda_max(Sigma~)) around mu^ (k^2 = -2 p_min).
+ * The kernels decide in float with the form described at SphRec in the sources (exponent
+ * -qh / D, accepted iff h > 0 and p_min D + qh <= 0). */
 
 /* Rasterization settings.  The paper fixes none of these constants; the defaults follow the
  * 3DGS rasterizer the method builds on (Sec. 3.2). */
@@ -93,12 +109,12 @@ typedef struct odgs_plan {
   int32_t tile_bits;       /* significant bits of a global tile id */
   int32_t item_blocks;     /* sort / scan blocks over items */
   int32_t pair_blocks;     /* sort blocks over pair_capacity */
-  int32_t reserved;
+  int32_t g2d_stride;      /* per-item gradient values of the reverse compositor: 9, or 13 (spherical) */
   /* workspace layout, byte offsets */
   size_t off_status, off_rec, off_rect, off_count, off_depth, off_dkey[2], off_did[2], off_srect, off_blocksum, off_pkey[2],
       off_pval[2],
       off_hist, off_digit, off_ranges, off_T, off_last, off_ncontrib, off_neval,
-      off_lasteval, off_g2d;
+      off_lasteval, off_g2d, off_srec, off_cone, off_dirs;
   int32_t depth_final;     /* which of the two depth-sort buffers holds the sorted result */
   int32_t pair_final;      /* which of the two pair buffers holds the sorted result */
   size_t ws_bytes;
@@ -290,7 +306,9 @@ int odgs_debug_pixel_counts(const odgs_plan* plan, const void* ws, int32_t* out,
 
 /* Per-item 2D gradients accumulated by odgs_composite_bwd and not yet consumed by
  * odgs_project_bwd, float [items][9]: d/du, d/dv, d/dSigma_uu, d/dSigma_uv (the off-diagonal as
- * one shared variable), d/dSigma_vv (Sigma_2D with dilation), d/dopacity, d/dr, d/dg, d/db. */
+ * one shared variable), d/dSigma_vv (Sigma_2D with dilation), d/dopacity, d/dr, d/dg, d/db.
+ * Spherical footprint: float [items][13]: d/dmu^ (3), d/dSigma~ (xx, xy, xz, yy, yz, zz; the
+ * off-diagonals as one shared variable), d/dopacity, d/dr, d/dg, d/db. */
 int odgs_debug_g2d(const odgs_plan* plan, const void* ws, float* out, void* stream);
 
 /* The sorted pair list as 64-bit keys (global tile << 32 | depth bits) and Gaussian indices,

@@ -232,8 +232,8 @@ struct Proj {
   S rgb[3];
   // spherical footprint (equirectangular views with Settings::spherical):
   S mu_hat[3];    // unit direction of the camera-space mean
-  S A[6];         // inverse of the normalised covariance (xx xy xz yy yz zz)
-  S Q[6], w[3], k2;  // the same quadratic forms in the kernel's parameterisation (see make_sph_rec)
+  S C[6];         // normalised covariance Sigma~ (xx xy xz yy yz zz)
+  S A[6];         // its inverse
 };
 
 struct Info {
@@ -348,7 +348,10 @@ void project(const S m[3], const S s[3], const S q[4], const S& o, const double*
     const double dang = st.dilation * (pi / Hd) * (pi / Hd);
     const S ir2 = 1.0 / r2;
     const S C[6] = {Sc[0] * ir2 + dang, Sc[1] * ir2, Sc[2] * ir2, Sc[4] * ir2 + dang, Sc[5] * ir2, Sc[8] * ir2 + dang};
-    for (int k = 0; k < 6; ++k) info.scov[k] = val(C[k]);
+    for (int k = 0; k < 6; ++k) {
+      info.scov[k] = val(C[k]);
+      out.C[k] = C[k];
+    }
     // inverse by cofactors: [[a, b, c], [b, d, e], [c, e, f]]
     const S &a = C[0], &b = C[1], &c = C[2], &d = C[3], &e = C[4], &f = C[5];
     const S c00 = d * f - e * e, c01 = c * e - b * f, c02 = b * e - c * d;
@@ -358,19 +361,6 @@ void project(const S m[3], const S s[3], const S q[4], const S& o, const double*
     out.A[3] = c11 / det3; out.A[4] = c12 / det3; out.A[5] = c22 / det3;
     detA = det3;
     for (int k = 0; k < 3; ++k) out.mu_hat[k] = mu[k] / rr;
-    // The kernel's parameterisation of the same function: with cA = mu^T A mu and y = A mu,
-    //   h(d) = w . d,  w = y / cA;   q(d) = d^T Q d,  Q = (A - y y^T / cA) / 2;   k2 = 2 / cA,
-    // m = 2 q / (h^2 + k2 q) for h > 0 (h > 0 <=> the minimising t is positive).
-    const S* A6 = out.A;
-    const S y0 = (A6[0] * out.mu_hat[0] + A6[1] * out.mu_hat[1]) + A6[2] * out.mu_hat[2];
-    const S y1 = (A6[1] * out.mu_hat[0] + A6[3] * out.mu_hat[1]) + A6[4] * out.mu_hat[2];
-    const S y2 = (A6[2] * out.mu_hat[0] + A6[4] * out.mu_hat[1]) + A6[5] * out.mu_hat[2];
-    const S cA = (y0 * out.mu_hat[0] + y1 * out.mu_hat[1]) + y2 * out.mu_hat[2];
-    out.w[0] = y0 / cA; out.w[1] = y1 / cA; out.w[2] = y2 / cA;
-    out.Q[0] = 0.5 * (A6[0] - y0 * y0 / cA); out.Q[1] = 0.5 * (A6[1] - y0 * y1 / cA);
-    out.Q[2] = 0.5 * (A6[2] - y0 * y2 / cA); out.Q[3] = 0.5 * (A6[3] - y1 * y1 / cA);
-    out.Q[4] = 0.5 * (A6[4] - y1 * y2 / cA); out.Q[5] = 0.5 * (A6[5] - y2 * y2 / cA);
-    out.k2 = 2.0 / cA;
   }
 
   S J[6];
@@ -1056,11 +1046,10 @@ void pixel_backward(const std::vector<Contrib>& cl, const std::vector<Rec<double
 // the ray; by the envelope theorem its derivatives are those of the quadratic at the fixed
 // minimiser t* = b / a: with v = t* d - mu^, dm/dA = v v^T and dm/dmu^ = -2 A v.
 //   g_def [stride]: mu^ (3), A (6, off-diagonals as one shared variable), opacity, r, g, b.
-//   g_ker [14] (optional): the same gradient in the kernel's variables of the exponent
-//     -qh / D, qh = d^T Q d, h = w . d, D = h^2 + k2 qh:  Q (6, shared), w (3), k2, opacity, rgb.
-void pixel_backward_sph(const std::vector<Contrib>& cl, const std::vector<SphRec64>& rec, const Proj<double>* proj,
-                        const double d[3], const double* gpix, const double* bg, double* g_def, int stride,
-                        double* g_ker) {
+//   g_ker [13] (optional): the kernel's layout, mu^ (3), Sigma~ (6, shared), opacity, rgb, from
+//     dm/dSigma~ = -A (dm/dA) A = -z z^T with z = A v.
+void pixel_backward_sph(const std::vector<Contrib>& cl, const std::vector<SphRec64>& rec, const double d[3],
+                        const double* gpix, const double* bg, double* g_def, int stride, double* g_ker) {
   const size_t n = cl.size();
   std::vector<double> alpha(n), T(n + 1), G(n), pw(n);
   T[0] = 1.0;
@@ -1078,7 +1067,7 @@ void pixel_backward_sph(const std::vector<Contrib>& cl, const std::vector<SphRec
   for (size_t jj = n; jj-- > 0;) {
     const SphRec64& g = rec[cl[jj].idx];
     double out[13] = {0};
-    double ker[14] = {0};
+    double ker[13] = {0};
     double dL_da = 0.0;
     for (int c = 0; c < 3; ++c) {
       out[10 + c] = gpix[c] * alpha[jj] * T[jj];
@@ -1101,27 +1090,17 @@ void pixel_backward_sph(const std::vector<Contrib>& cl, const std::vector<SphRec
       out[7] = -dL_dpow * v[1] * v[2];
       out[8] = -0.5 * dL_dpow * v[2] * v[2];
       out[9] = dL_da * G[jj];
-      if (g_ker) {
-        const Proj<double>& pr = proj[cl[jj].idx];
-        const double qh = pr.Q[0] * d[0] * d[0] + 2.0 * pr.Q[1] * d[0] * d[1] + 2.0 * pr.Q[2] * d[0] * d[2] +
-                          pr.Q[3] * d[1] * d[1] + 2.0 * pr.Q[4] * d[1] * d[2] + pr.Q[5] * d[2] * d[2];
-        const double h = pr.w[0] * d[0] + pr.w[1] * d[1] + pr.w[2] * d[2];
-        const double D = h * h + pr.k2 * qh;
-        const double p = -qh / D;
-        const double gq = dL_dpow * -(h / D) * (h / D);  // dp/dqh = -(h / D)^2
-        const double gh = dL_dpow * (-2.0 * p * h / D);   // dp/dh = 2 qh h / D^2
-        ker[0] = gq * d[0] * d[0];
-        ker[1] = 2.0 * gq * d[0] * d[1];
-        ker[2] = 2.0 * gq * d[0] * d[2];
-        ker[3] = gq * d[1] * d[1];
-        ker[4] = 2.0 * gq * d[1] * d[2];
-        ker[5] = gq * d[2] * d[2];
-        for (int k = 0; k < 3; ++k) ker[6 + k] = gh * d[k];
-        ker[9] = dL_dpow * p * p;  // dp/dk2 = qh^2 / D^2
-        ker[10] = out[9];
-      }
+      // power = -m / 2:  dpower/dmu^ = A v = z,  dpower/dSigma~ = z z^T / 2
+      for (int k = 0; k < 3; ++k) ker[k] = out[k];
+      ker[3] = 0.5 * dL_dpow * Av[0] * Av[0];
+      ker[4] = dL_dpow * Av[0] * Av[1];
+      ker[5] = dL_dpow * Av[0] * Av[2];
+      ker[6] = 0.5 * dL_dpow * Av[1] * Av[1];
+      ker[7] = dL_dpow * Av[1] * Av[2];
+      ker[8] = 0.5 * dL_dpow * Av[2] * Av[2];
+      ker[9] = out[9];
     }
-    for (int c = 0; c < 3; ++c) ker[11 + c] = out[10 + c];
+    for (int c = 0; c < 3; ++c) ker[10 + c] = out[10 + c];
     double* o1 = g_def + (size_t)cl[jj].idx * stride;
     for (int k = 0; k < 13; ++k) {
       if (out[k] == 0.0) continue;
@@ -1129,8 +1108,8 @@ void pixel_backward_sph(const std::vector<Contrib>& cl, const std::vector<SphRec
       o1[k] += out[k];
     }
     if (g_ker) {
-      double* o2 = g_ker + (size_t)cl[jj].idx * 14;
-      for (int k = 0; k < 14; ++k) {
+      double* o2 = g_ker + (size_t)cl[jj].idx * 13;
+      for (int k = 0; k < 13; ++k) {
         if (ker[k] == 0.0) continue;
 #pragma omp atomic
         o2[k] += ker[k];
@@ -1144,7 +1123,7 @@ void pixel_backward_sph(const std::vector<Contrib>& cl, const std::vector<SphRec
 // opacity, r, g, b), the shape entries with respect to the inverse covariance (a, b, c) or, with
 // `sigma`, the covariance (uu, uv, vv; the off-diagonal as one shared variable).  Spherical
 // items: (mu^, A, opacity, rgb) as pixel_backward_sph's g_def or, with `sigma`, its kernel
-// layout (Q, w, k2, opacity, rgb).
+// layout (mu^, Sigma~, opacity, rgb).
 void project_adjoint(const Scene& sc, const Prepared& P, const std::vector<double>& acc, int stride, bool sigma,
                      double* d_means, double* d_scales, double* d_quats, double* d_opac, double* d_sh) {
   // Per-Gaussian chain rule: push the 2D gradients through the projection with dual numbers
@@ -1161,7 +1140,7 @@ void project_adjoint(const Scene& sc, const Prepared& P, const std::vector<doubl
       const size_t it = (size_t)v * n + i;
       const double* g = acc.data() + it * stride;
       const bool sph = P.info[it].spherical;
-      const int nv = sph ? (sigma ? 14 : 13) : 9;
+      const int nv = sph ? 13 : 9;
       bool any = false;
       for (int k = 0; k < nv; ++k) any = any || g[k] != 0.0;
       if (!any || P.info[it].cull != KEPT) continue;
@@ -1179,13 +1158,9 @@ void project_adjoint(const Scene& sc, const Prepared& P, const std::vector<doubl
         const Dual* o9[9] = {&p.u, &p.v, sigma ? &p.cov2[0] : &p.conic[0], sigma ? &p.cov2[1] : &p.conic[1],
                              sigma ? &p.cov2[2] : &p.conic[2], &p.opacity, &p.rgb[0], &p.rgb[1], &p.rgb[2]};
         std::copy(o9, o9 + 9, outs);
-      } else if (!sigma) {
-        for (int k = 0; k < 3; ++k) outs[k] = &p.mu_hat[k];
-        for (int k = 0; k < 6; ++k) outs[3 + k] = &p.A[k];
       } else {
-        for (int k = 0; k < 6; ++k) outs[k] = &p.Q[k];
-        for (int k = 0; k < 3; ++k) outs[6 + k] = &p.w[k];
-        outs[9] = &p.k2;
+        for (int k = 0; k < 3; ++k) outs[k] = &p.mu_hat[k];
+        for (int k = 0; k < 6; ++k) outs[3 + k] = sigma ? &p.C[k] : &p.A[k];
       }
       if (sph) {
         outs[nv - 4] = &p.opacity;
@@ -1408,7 +1383,8 @@ int oracle_render(const double* means, const double* scales, const double* quats
 // Outputs (overwritten): d_means [3][N], d_scales [3][N], d_quats [4][N], d_opac [N],
 // d_sh [K*3][N]; g2d (optional, NULL to skip) [V][N][G] per-item gradients of the compositor's
 // inputs, G = 9 (affine) or 13 (spherical footprint: mu^, A, opacity, rgb); g2d_kernel
-// (optional, spherical footprint only) [V][N][14] the same in the kernel's variables.
+// (optional, spherical footprint only) [V][N][13] the same in the kernel's variables (mu^,
+// Sigma~, opacity, rgb).
 int oracle_backward(const double* means, const double* scales, const double* quats, const double* opac,
                     const double* sh, int64_t n, int deg, const double* cams, const int32_t* wh, int V,
                     const double* settings, int mode, const int32_t* pix, int64_t npix, const double* dL,
@@ -1419,15 +1395,14 @@ int oracle_backward(const double* means, const double* scales, const double* qua
   prepare(sc, cams, wh, V, settings, P);
   const int stride = P.st.spherical ? 13 : 9;
   std::vector<double> acc((size_t)V * n * stride, 0.0);
-  std::vector<double> acck(P.st.spherical && g2d_kernel ? (size_t)V * n * 14 : 0, 0.0);
+  std::vector<double> acck(P.st.spherical && g2d_kernel ? (size_t)V * n * 13 : 0, 0.0);
   for (int v = 0; v < V; ++v) {
     if (sph_view(P, v)) {
       std::vector<SphRec32> s32;
       std::vector<SphRec64> s64 = make_sph_recs<SphRec64>(P, v, make_sph_rec64);
       if (mode == 32) s32 = make_sph_recs<SphRec32>(P, v, make_sph_rec32);
       double* gv = acc.data() + (size_t)v * n * stride;
-      double* gk = acck.empty() ? nullptr : acck.data() + (size_t)v * n * 14;
-      const Proj<double>* pr = P.proj.data() + (size_t)v * n;
+      double* gk = acck.empty() ? nullptr : acck.data() + (size_t)v * n * 13;
       const int W = P.cams[v].W, H = P.cams[v].H;
       auto run = [&](int x, int y, const double* gpix) {
         if (gpix[0] == 0.0 && gpix[1] == 0.0 && gpix[2] == 0.0) return;
@@ -1436,7 +1411,7 @@ int oracle_backward(const double* means, const double* scales, const double* qua
         else render_pixel_sph<double, SphRec64>(P, s64, nullptr, v, x, y, &cl);
         double d[3];
         pixel_dir(x, y, W, H, d);
-        pixel_backward_sph(cl, s64, pr, d, gpix, P.st.bg, gv, stride, gk);
+        pixel_backward_sph(cl, s64, d, gpix, P.st.bg, gv, stride, gk);
       };
       if (pix == nullptr) {
         const int64_t off = pix_offset(P, v);
@@ -1501,8 +1476,8 @@ int oracle_backward(const double* means, const double* scales, const double* qua
 
 // Adjoint of the projection alone, for per-item gradients in the layout the GPU's reverse
 // compositor produces: g2d [V][N][9] = (u, v, Sigma_uu, Sigma_uv (shared), Sigma_vv, opacity,
-// r, g, b), or with the spherical footprint [V][N][14] = (Q (6, shared off-diagonals), w (3),
-// k2, opacity, r, g, b).  Outputs as oracle_backward (overwritten).
+// r, g, b), or with the spherical footprint [V][N][13] = (mu^ (3), Sigma~ (6, shared
+// off-diagonals), opacity, r, g, b).  Outputs as oracle_backward (overwritten).
 int oracle_project_adjoint(const double* means, const double* scales, const double* quats, const double* opac,
                            const double* sh, int64_t n, int deg, const double* cams, const int32_t* wh, int V,
                            const double* settings, const double* g2d, double* d_means, double* d_scales,
@@ -1510,7 +1485,7 @@ int oracle_project_adjoint(const double* means, const double* scales, const doub
   Scene sc = make_scene(means, scales, quats, opac, sh, n, deg);
   Prepared P;
   prepare(sc, cams, wh, V, settings, P);
-  const int stride = P.st.spherical ? 14 : 9;
+  const int stride = P.st.spherical ? 13 : 9;
   std::vector<double> acc(g2d, g2d + (size_t)V * n * stride);
   project_adjoint(sc, P, acc, stride, true, d_means, d_scales, d_quats, d_opac, d_sh);
   return 0;

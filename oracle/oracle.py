@@ -169,14 +169,14 @@ def backward(scene, cams, settings, dL: np.ndarray, mode: int = 32, pix: np.ndar
     """Gradient of sum(dL * rgb) w.r.t. every parameter (float64), and optionally the per-item
     gradients of the compositor's inputs: affine footprint g2d [V][N][9] (u, v, conic a, b, c,
     opacity, r, g, b); spherical footprint g2d [V][N][13] (mu^, A, opacity, rgb) and g2d_kernel
-    [V][N][14] (Q, w, k2, opacity, rgb; the reverse compositor's layout)."""
+    [V][N][13] (mu^, Sigma~, opacity, rgb; the reverse compositor's layout)."""
     a = _Args(scene, cams, settings)
     n, K = a.n, (a.deg + 1) ** 2
     gm, gs, gq = np.zeros((3, n)), np.zeros((3, n)), np.zeros((4, n))
     go, gsh = np.zeros(n), np.zeros((K * 3, n))
     sph = spherical(settings)
     g2d = np.zeros((a.V, n, 13 if sph else 9)) if want_g2d else None
-    g2dk = np.zeros((a.V, n, 14)) if (want_g2d and sph) else None
+    g2dk = np.zeros((a.V, n, 13)) if (want_g2d and sph) else None
     d = np.ascontiguousarray(dL, dtype=np.float64)
     pp = None if pix is None else np.ascontiguousarray(pix, dtype=np.int32)
     lib().oracle_backward(*a.tuple(), mode, _p(pp), 0 if pp is None else pp.shape[0], _p(d),
@@ -220,12 +220,13 @@ def g2d_to_sigma(rows: np.ndarray, g2d: np.ndarray) -> np.ndarray:
 def project_adjoint(scene, cams, settings, g2d_sigma: np.ndarray):
     """Parameter gradients from per-item gradients in the reverse compositor's layout, summed
     over views: affine [V][N][9] in covariance terms (u, v, Sigma_uu, Sigma_uv (shared),
-    Sigma_vv, opacity, r, g, b); spherical footprint [V][N][14] (Q, w, k2, opacity, rgb)."""
+    Sigma_vv, opacity, r, g, b); spherical footprint [V][N][13] (mu^, Sigma~ (shared off-diagonals),
+    opacity, rgb)."""
     a = _Args(scene, cams, settings)
     n, K = a.n, (a.deg + 1) ** 2
     gm, gs, gq = np.zeros((3, n)), np.zeros((3, n)), np.zeros((4, n))
     go, gsh = np.zeros(n), np.zeros((K * 3, n))
     g = np.ascontiguousarray(g2d_sigma, dtype=np.float64)
-    assert g.shape == (a.V, n, 14 if spherical(settings) else 9)
+    assert g.shape == (a.V, n, 13 if spherical(settings) else 9)
     lib().oracle_project_adjoint(*a.tuple(), _p(g), _p(gm), _p(gs), _p(gq), _p(go), _p(gsh))
     return dict(means=gm, scales=gs, quats=gq, opacities=go, sh=gsh)

@@ -16,6 +16,7 @@ MAX_VIEWS = 64
 OK, EINVAL, ENOSPACE, EHIP = 0, -1, -2, -3
 STATUS_OVERFLOW = 1
 FLAG_COUNT_WORK = 1
+FLAG_SPHERICAL = 2
 
 EXPORTS = ("odgs_plan_init", "odgs_plan_set_pinhole", "odgs_workspace_bytes", "odgs_preprocess", "odgs_bin_sort", "odgs_render_fwd",
            "odgs_render_bwd", "odgs_composite_bwd", "odgs_project_bwd", "odgs_status_offset", "odgs_strerror",
@@ -56,7 +57,8 @@ class Status(ctypes.Structure):
 
 _OFFSETS = ["off_status", "off_rec", "off_rect", "off_count", "off_depth", "off_dkey0", "off_dkey1", "off_did0", "off_did1", "off_srect",
             "off_blocksum", "off_pkey0", "off_pkey1", "off_pval0", "off_pval1", "off_hist", "off_digit",
-            "off_ranges", "off_T", "off_last", "off_ncontrib", "off_neval", "off_lasteval", "off_g2d"]
+            "off_ranges", "off_T", "off_last", "off_ncontrib", "off_neval", "off_lasteval", "off_g2d", "off_srec",
+            "off_cone", "off_dirs"]
 
 
 class Plan(ctypes.Structure):
@@ -65,7 +67,7 @@ class Plan(ctypes.Structure):
                  ("tile_base", ctypes.c_int32 * (MAX_VIEWS + 1)), ("pix_base", ctypes.c_int64 * (MAX_VIEWS + 1)),
                  ("pinhole", (ctypes.c_float * 4) * MAX_VIEWS),
                  ("items", ctypes.c_int64), ("pair_capacity", ctypes.c_int64), ("tile_bits", ctypes.c_int32),
-                 ("item_blocks", ctypes.c_int32), ("pair_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                 ("item_blocks", ctypes.c_int32), ("pair_blocks", ctypes.c_int32), ("g2d_stride", ctypes.c_int32)]
                 + [(name, ctypes.c_size_t) for name in _OFFSETS]
                 + [("depth_final", ctypes.c_int32), ("pair_final", ctypes.c_int32), ("ws_bytes", ctypes.c_size_t)])
 
@@ -143,13 +145,17 @@ def _check(rc: int, what: str):
 
 
 def make_settings(tile=16, batch=0, batch_bwd=0, near=0.2, far=1e4, dilation=0.3, pole_eps=1e-4,
-                  bg=(0.0, 0.0, 0.0), count_work=False) -> Settings:
+                  bg=(0.0, 0.0, 0.0), count_work=False, footprint="affine") -> Settings:
+    """footprint: "affine" (the paper's local affine approximation) or "spherical"
+    (ODGS_FLAG_SPHERICAL: the exact per-ray maximum of each 3D Gaussian)."""
+    if footprint not in ("affine", "spherical"):
+        raise ValueError("footprint must be 'affine' or 'spherical'")
     s = Settings()
     s.tile, s.batch, s.batch_bwd = int(tile), int(batch), int(batch_bwd)
     s.near_r, s.far_r, s.dilation, s.pole_eps = float(near), float(far), float(dilation), float(pole_eps)
     for k in range(3):
         s.bg[k] = float(bg[k])
-    s.flags = FLAG_COUNT_WORK if count_work else 0
+    s.flags = (FLAG_COUNT_WORK if count_work else 0) | (FLAG_SPHERICAL if footprint == "spherical" else 0)
     return s
 
 

@@ -46,6 +46,7 @@ size_t odgs_plan_size(void) { return sizeof(odgs_plan); }
 
 int odgs_plan_set_pinhole(odgs_plan* plan, int32_t view, float fx, float fy, float cx, float cy) {
   if (!plan || view < 0 || view >= plan->n_views) return ODGS_EINVAL;
+  if (plan_spherical(plan)) return ODGS_EINVAL;  // the spherical footprint is defined for ERP views
   if (!(fx > 0.0f) || !(fy > 0.0f) || !std::isfinite(fx) || !std::isfinite(fy) || !std::isfinite(cx) ||
       !std::isfinite(cy))
     return ODGS_EINVAL;
@@ -67,7 +68,8 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   if (st.batch == 0) st.batch = st.tile == 8 ? 64 : 256;
   if (st.batch_bwd == 0) st.batch_bwd = st.tile == 8 ? 32 : (st.tile == 16 ? 64 : 256);
   if (!batch_ok(st.tile, st.batch) || !batch_ok(st.tile, st.batch_bwd)) return ODGS_EINVAL;
-  if (st.flags & ~ODGS_FLAG_COUNT_WORK) return ODGS_EINVAL;
+  if (st.flags & ~(ODGS_FLAG_COUNT_WORK | ODGS_FLAG_SPHERICAL)) return ODGS_EINVAL;
+  if ((st.flags & ODGS_FLAG_COUNT_WORK) && (st.flags & ODGS_FLAG_SPHERICAL)) return ODGS_EINVAL;
   if (!(st.near_r >= 0.0f) || !(st.far_r > st.near_r) || !(st.dilation >= 0.0f) || !(st.pole_eps >= 0.0f))
     return ODGS_EINVAL;
   memset(plan, 0, sizeof(*plan));
@@ -133,7 +135,14 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   plan->off_ncontrib = take((size_t)pixels * 4);
   plan->off_neval = take((size_t)pixels * 4);
   plan->off_lasteval = take((size_t)pixels * 4);
-  plan->off_g2d = take((size_t)9 * I * 4);
+  const bool sph = (st.flags & ODGS_FLAG_SPHERICAL) != 0;
+  plan->g2d_stride = sph ? 13 : 9;
+  plan->off_g2d = take((size_t)plan->g2d_stride * I * 4);
+  int64_t dirs = 0;
+  for (int v = 0; v < n_views; ++v) dirs += plan->width[v] + plan->height[v];
+  plan->off_srec = take(sph ? (size_t)I * sizeof(SphRec) : 0);
+  plan->off_cone = take(sph ? (size_t)I * 16 : 0);
+  plan->off_dirs = take(sph ? (size_t)dirs * 16 : 0);
   plan->ws_bytes = off;
   return ODGS_OK;
 }
@@ -167,14 +176,18 @@ int odgs_render_fwd(const odgs_plan* plan, void* ws, size_t ws_bytes, float* out
   if (rc != ODGS_OK) return rc;
   if (!out_rgb || !aligned(out_rgb, 4) || (out_T && !aligned(out_T, 4)) || (out_depth && !aligned(out_depth, 4)))
     return ODGS_EINVAL;
-  return hip_status(launch_render_fwd(plan, ws, out_rgb, out_T, out_depth, static_cast<hipStream_t>(stream)));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (plan_spherical(plan)) return hip_status(launch_render_sph_fwd(plan, ws, out_rgb, out_T, out_depth, st));
+  return hip_status(launch_render_fwd(plan, ws, out_rgb, out_T, out_depth, st));
 }
 
 int odgs_composite_bwd(const odgs_plan* plan, void* ws, size_t ws_bytes, const float* dL_drgb, void* stream) {
   const int rc = check_ws(plan, ws, ws_bytes);
   if (rc != ODGS_OK) return rc;
   if (!dL_drgb || !aligned(dL_drgb, 4)) return ODGS_EINVAL;
-  return hip_status(launch_render_bwd(plan, ws, dL_drgb, static_cast<hipStream_t>(stream)));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (plan_spherical(plan)) return hip_status(launch_render_sph_bwd(plan, ws, dL_drgb, st));
+  return hip_status(launch_render_bwd(plan, ws, dL_drgb, st));
 }
 
 int odgs_project_bwd(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
@@ -190,6 +203,7 @@ int odgs_project_bwd(const odgs_plan* plan, const float* means, const float* sca
     for (float* q : outs)
       if (!q || !aligned(q, 4)) return ODGS_EINVAL;
     if (acc) {
+      if (plan_spherical(plan)) return ODGS_EINVAL;  // statistics are defined on the 2D mean
       if (!acc->grad_sum || !acc->tau_sum || !acc->count) return ODGS_EINVAL;
       if (!aligned(acc->grad_sum, 4) || !aligned(acc->tau_sum, 4) || !aligned(acc->count, 4)) return ODGS_EINVAL;
       if (!std::isfinite(acc->tau_min) || !std::isfinite(acc->tau_max)) return ODGS_EINVAL;
@@ -270,6 +284,7 @@ int odgs_render_bwd(const odgs_plan* plan, const float* means, const float* scal
   rc = check_params(plan, means, scales, quats, opacities, sh, cams);
   if (rc != ODGS_OK) return rc;
   if (!dL_drgb || !aligned(dL_drgb, 4)) return ODGS_EINVAL;
+  if (acc && plan_spherical(plan)) return ODGS_EINVAL;
   rc = odgs_composite_bwd(plan, ws, ws_bytes, dL_drgb, stream);
   if (rc != ODGS_OK) return rc;
   return odgs_project_bwd(plan, means, scales, quats, opacities, sh, cams, ws, ws_bytes, d_means, d_scales, d_quats,

@@ -10,6 +10,8 @@ namespace odgs {
 
 constexpr int kWave = 64;  // CDNA wavefront width
 
+inline bool plan_spherical(const odgs_plan* p) { return (p->s.flags & ODGS_FLAG_SPHERICAL) != 0; }
+
 // Per-view geometry passed to kernels by value (kernel arguments are captured by HIP graphs).
 struct ViewTable {
   int32_t n_views;
@@ -18,6 +20,7 @@ struct ViewTable {
   int32_t tile_base[ODGS_MAX_VIEWS + 1];
   int64_t pix_base[ODGS_MAX_VIEWS + 1];
   float pin[ODGS_MAX_VIEWS][4];  // fx, fy, cx, cy of pinhole views; fx == 0: equirectangular
+  int32_t dir_base[ODGS_MAX_VIEWS + 1];  // first entry of each view's ray table (W columns, then H rows)
 };
 
 // Half width at which horizontal offsets wrap round the +-pi seam: W/2 for ERP views, none
@@ -32,6 +35,14 @@ __device__ inline float wrap_half(const ViewTable& vt, int v) {
 //   r2 = (red, green, blue, ev)  eu, ev: padded half extents of the alpha >= 1/255 footprint
 struct Rec {
   float4 r0, r1, r2;
+};
+
+// Compositor record of the spherical footprint, four 16-byte words:
+//   s0 = (u1x, u1y, u1z, u2x), s1 = (u2y, u2z, wx, wy), s2 = (wz, k2, opacity, p_min), s3 = (r, g, b, 0)
+// For a pixel ray d: t1 = u1 . d, t2 = u2 . d, h = w . d, qh = t1^2 + t2^2, D = h^2 + k2 qh; the
+// Gaussian reaches the pixel iff h > 0 and p_min D + qh <= 0, with exponent -qh / D.
+struct SphRec {
+  float4 s0, s1, s2, s3;
 };
 
 // Packed tile rectangle of an item: first column (may wrap), column count, first row, rows.
@@ -61,6 +72,8 @@ inline ViewTable make_view_table(const odgs_plan* p) {
     vt.tile_base[v] = p->tile_base[v];
     vt.pix_base[v] = p->pix_base[v];
   }
+  vt.dir_base[0] = 0;
+  for (int v = 0; v < p->n_views; ++v) vt.dir_base[v + 1] = vt.dir_base[v] + p->width[v] + p->height[v];
   return vt;
 }
 
@@ -80,6 +93,9 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st);
 hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float* out_T, float* out_depth,
                              hipStream_t st);
 hipError_t launch_render_bwd(const odgs_plan* p, void* ws, const float* dL_drgb, hipStream_t st);
+hipError_t launch_render_sph_fwd(const odgs_plan* p, void* ws, float* out_rgb, float* out_T, float* out_depth,
+                                 hipStream_t st);
+hipError_t launch_render_sph_bwd(const odgs_plan* p, void* ws, const float* dL_drgb, hipStream_t st);
 hipError_t launch_preprocess_bwd(const odgs_plan* p, const float* means, const float* scales, const float* quats,
                                  const float* opac, const float* sh, const float* cams, void* ws, float* d_means,
                                  float* d_scales, float* d_quats, float* d_opac, float* d_sh,

@@ -234,6 +234,119 @@ __device__ inline void view_dir(const double m[3], const Cam& cam, double d[3], 
   d[2] = w2 / dist;
 }
 
+__device__ inline double sym3(const double* C, const double* x, const double* y) {
+  return x[0] * (C[0] * y[0] + C[1] * y[1] + C[2] * y[2]) + x[1] * (C[1] * y[0] + C[3] * y[1] + C[4] * y[2]) +
+         x[2] * (C[2] * y[0] + C[4] * y[1] + C[5] * y[2]);
+}
+
+// Normalised camera-space covariance of the spherical footprint, Sigma~ = W Sigma W^T / |mu|^2
+// + dilation (pi / H)^2 I, as (xx, xy, xz, yy, yz, zz); also returns W Sigma W^T.
+__device__ inline void sph_cov(const Geo& g, const Cam& cam, const Cov3& cv, int H, const Params& P, double C[6],
+                               double Sc[6]) {
+  double RS[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      RS[3 * r + k] = (cam.R[3 * r] * cv.S[k] + cam.R[3 * r + 1] * cv.S[3 + k]) + cam.R[3 * r + 2] * cv.S[6 + k];
+  const int idx[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+  const double dang = P.dilation * (kPi / (double)H) * (kPi / (double)H);
+  const double ir2 = 1.0 / g.r2;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int r = idx[e][0], k = idx[e][1];
+    Sc[e] = (RS[3 * r] * cam.R[3 * k] + RS[3 * r + 1] * cam.R[3 * k + 1]) + RS[3 * r + 2] * cam.R[3 * k + 2];
+    C[e] = Sc[e] * ir2 + (r == k ? dang : 0.0);
+  }
+}
+
+// Spherical footprint of one kept ERP item: the float record (tangent frame e1 east, e2 = mu^ x e1;
+// P, c, s33 the tangent, tangent-radial and radial blocks of Sigma~; (l0, l1; 0, l2) the factor
+// of P^-1 / 2; u1 = l0 e1 + l1 e2, u2 = l2 e2, w = mu^ - (P^-1 c)_1 e1 - (P^-1 c)_2 e2,
+// k2 = 2 (s33 - c^T P^-1 c)), the cone (mu^, half-angle beta) and its tile rectangle: latitudes
+// theta_c +- beta, longitudes +- asin(sin beta / cos theta_c) unless the cone reaches a pole,
+// everything when the ball of radius k sqrt(lambda_max) holds the camera.  Returns false when
+// culled (Sigma~ not positive definite, empty rectangle).
+__device__ inline bool sph_item(const Geo& g, const Cam& cam, const Cov3& cv, const double s[3], int W, int H,
+                                const Params& P, double p_min, float o, const float rgb[3], SphRec& out, float4& cn,
+                                Rect& rr) {
+  double C[6], Sc[6];
+  sph_cov(g, cam, cv, H, P, C, Sc);
+  const double c00 = C[3] * C[5] - C[4] * C[4], c01 = C[2] * C[4] - C[1] * C[5], c02 = C[1] * C[4] - C[2] * C[3];
+  const double det3 = (C[0] * c00 + C[1] * c01) + C[2] * c02;
+  if (!(det3 > 0.0)) return false;
+  const double m[3] = {g.mu[0] / g.r, g.mu[1] / g.r, g.mu[2] / g.r};
+  const double rh = sqrt(m[0] * m[0] + m[2] * m[2]);
+  const double e1[3] = {m[2] / rh, 0.0, -m[0] / rh};
+  const double e2[3] = {m[1] * e1[2] - m[2] * e1[1], m[2] * e1[0] - m[0] * e1[2], m[0] * e1[1] - m[1] * e1[0]};
+  const double P11 = sym3(C, e1, e1), P12 = sym3(C, e1, e2), P22 = sym3(C, e2, e2);
+  const double c1 = sym3(C, e1, m), c2 = sym3(C, e2, m), s33 = sym3(C, m, m);
+  const double det = P11 * P22 - P12 * P12;
+  const double l0 = sqrt(P22 / (2.0 * det)), l1 = -P12 / (2.0 * det * l0), l2 = 1.0 / sqrt(2.0 * P22);
+  const double a1 = -(P22 * c1 - P12 * c2) / det, a2 = -(P11 * c2 - P12 * c1) / det;
+  double u1[3], u2[3], w[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    u1[k] = l0 * e1[k] + l1 * e2[k];
+    u2[k] = l2 * e2[k];
+    w[k] = m[k] + a1 * e1[k] + a2 * e2[k];
+  }
+  const double k2 = 2.0 * (s33 + (a1 * c1 + a2 * c2));
+  out.s0 = make_float4((float)u1[0], (float)u1[1], (float)u1[2], (float)u2[0]);
+  out.s1 = make_float4((float)u2[1], (float)u2[2], (float)w[0], (float)w[1]);
+  out.s2 = make_float4((float)w[2], (float)k2, o, (float)p_min);
+  out.s3 = make_float4(rgb[0], rgb[1], rgb[2], 0.0f);
+  // cone of the rays that can reach alpha >= 1/255
+  const double smax2 = fmax(fmax(s[0] * s[0], s[1] * s[1]), s[2] * s[2]);
+  const double lam = smax2 / (g.r * g.r) + P.dilation * (kPi / (double)H) * (kPi / (double)H);
+  const double sb = sqrt(-2.0 * p_min * lam) * (1.0 + 1e-3);
+  const int B = P.tile;
+  const int ntx = W / B, nty = H / B;
+  if (!(sb < 1.0)) {
+    cn = make_float4((float)m[0], (float)m[1], (float)m[2], (float)kPi);
+    rr = Rect{0, (uint16_t)ntx, 0, (uint16_t)nty};
+    return true;
+  }
+  const double beta = asin(sb);
+  cn = make_float4((float)m[0], (float)m[1], (float)m[2], round_up_f32(beta));
+  const double thc = atan2(-g.mu[1], g.rho);
+  const double Hd = (double)H, Wd = (double)W;
+  const double vlo = Hd / 2.0 - (Hd / kPi) * (thc + beta) - 1e-2, vhi = Hd / 2.0 - (Hd / kPi) * (thc - beta) + 1e-2;
+  const double rlo = fmax(0.0, floor(vlo / B)), rhi = fmin((double)(nty - 1), floor(vhi / B));
+  const int nrows = (int)(rhi - rlo + 1.0);
+  if (nrows <= 0) return false;
+  int col0 = 0, ncols = ntx;
+  if (fabs(thc) + beta < kPi / 2.0) {
+    const double eu = (Wd / (2.0 * kPi)) * asin(sin(beta) / cos(thc)) + 1e-2;
+    const double clo = floor((g.u - eu) / B), chi = floor((g.u + eu) / B);
+    if (chi - clo + 1.0 < (double)ntx) {
+      long long c0 = (long long)clo % ntx;
+      if (c0 < 0) c0 += ntx;
+      col0 = (int)c0;
+      ncols = (int)(chi - clo + 1.0);
+    }
+  }
+  rr = Rect{(uint16_t)col0, (uint16_t)ncols, (uint16_t)rlo, (uint16_t)nrows};
+  return true;
+}
+
+// Ray table of the spherical footprint: per view, (sin phi, cos phi) of the W pixel-centre
+// azimuths, then (sin theta, cos theta) of the H pixel-centre elevations (Eq. equirec_proj
+// inverted), each angle formed by this exact sequence of double operations.
+__global__ void dir_table_kernel(ViewTable vt, double2* __restrict__ tab) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= vt.dir_base[vt.n_views]) return;
+  int v = 0;
+  while (i >= vt.dir_base[v + 1]) ++v;
+  const int j = i - vt.dir_base[v];
+  const double W = (double)vt.W[v], H = (double)vt.H[v];
+  double a;
+  if (j < vt.W[v]) a = (((double)j + 0.5) - 0.5 * W) * ((2.0 * kPi) / W);
+  else a = (0.5 * H - ((double)(j - vt.W[v]) + 0.5)) * (kPi / H);
+  tab[i] = make_double2(sin(a), cos(a));
+}
+
 template <int K>
 __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float* __restrict__ means,
                                                          const float* __restrict__ scales, const float* __restrict__ quats,
@@ -241,7 +354,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
                                                          const float* __restrict__ cams, ViewTable vt, Params P,
                                                          Rec* __restrict__ rec, Rect* __restrict__ rect,
                                                          uint32_t* __restrict__ count, uint32_t* __restrict__ dkey,
-                                                         float* __restrict__ depth_out, odgs_status* __restrict__ status) {
+                                                         float* __restrict__ depth_out, odgs_status* __restrict__ status,
+                                                         SphRec* __restrict__ srec, float4* __restrict__ cone) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < n;
   const int64_t ii = live ? i : 0;
@@ -293,8 +407,24 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
         finite = finite && isfinite(acc);
         rgb[ch] = acc > 0.0 ? (float)acc : 0.0f;
       }
-      kept = (p_min < 0.0) && (g.det > 0.0) && finite;
-      if (kept) {
+      if (srec) {
+        // spherical footprint (ERP views only)
+        SphRec sr;
+        float4 cn;
+        kept = (p_min < 0.0) && finite && sph_item(g, cam, cv, s, W, H, P, p_min, o, rgb, sr, cn, rr);
+        if (kept) {
+          cnt = (uint32_t)rr.ncols * (uint32_t)rr.nrows;
+          const int64_t item = (int64_t)v * n + i;
+          srec[item] = sr;
+          cone[item] = cn;
+          out.r0 = make_float4((float)g.u, (float)g.v, (float)l0, (float)l1);
+          out.r1 = make_float4((float)l2, o, (float)p_min, 0.0f);
+          out.r2 = make_float4(rgb[0], rgb[1], rgb[2], 0.0f);
+        } else {
+          rr = Rect{0, 0, 0, 0};
+        }
+      }
+      else if ((kept = (p_min < 0.0) && (g.det > 0.0) && finite)) {
         // Footprint: alpha >= 1/255 inside d^T Sigma^-1 d <= k2 = -2 p_min; half extents
         // sqrt(k2 Sigma_uu), sqrt(k2 Sigma_vv), padded by 0.1% + 0.01 px.
         const double k2 = -2.0 * p_min;
@@ -366,6 +496,52 @@ struct DensAcc {
   int32_t* count;
   double tau_min, tau_max;
 };
+
+// Last step of both adjoints: dL/dSigma -> scales and (normalised) quaternion, then the writes.
+template <int K>
+__device__ inline void write_param_grads(int64_t n, int64_t i, const double s[3], const Cov3& cv, const double gm[3],
+                                         const double gS[9], double go, const double* gsh, float* __restrict__ d_means,
+                                         float* __restrict__ d_scales, float* __restrict__ d_quats,
+                                         float* __restrict__ d_opac, float* __restrict__ d_sh) {
+  // Sigma = M M^T, M = Rq diag(s): dM = 2 dSigma M (dSigma symmetric).
+  double dM[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      dM[3 * r + k] = 2.0 * (gS[3 * r] * cv.M[k] + gS[3 * r + 1] * cv.M[3 + k] + gS[3 * r + 2] * cv.M[6 + k]);
+  double gs[3], dR[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gs[k] = dM[k] * cv.Rq[k] + dM[3 + k] * cv.Rq[3 + k] + dM[6 + k] * cv.Rq[6 + k];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dR[3 * r + k] = dM[3 * r + k] * s[k];
+  // Rq of the unit quaternion (w, x, y, z)
+  const double w = cv.w, x = cv.x, y = cv.y, z = cv.z;
+  double gw = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+  double gx = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                     2.0 * x * dR[8]);
+  double gy = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                     2.0 * y * dR[8]);
+  double gz = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] +
+                     y * dR[7]);
+  // normalisation q_hat = q / |q|
+  const double dot = gw * w + gx * x + gy * y + gz * z;
+  const double iq = 1.0 / cv.qn;
+  d_quats[i] = (float)((gw - w * dot) * iq);
+  d_quats[n + i] = (float)((gx - x * dot) * iq);
+  d_quats[2 * n + i] = (float)((gy - y * dot) * iq);
+  d_quats[3 * n + i] = (float)((gz - z * dot) * iq);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    d_means[k * n + i] = (float)gm[k];
+    d_scales[k * n + i] = (float)gs[k];
+  }
+  d_opac[i] = (float)go;
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = (float)gsh[k];
+}
 
 template <int K, bool STATS>
 __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
@@ -527,49 +703,127 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     for (int k = 0; k < 3; ++k) gm[k] += (gdir[k] - d[k] * dd) / dist;
   }
 
-  // Sigma = M M^T, M = Rq diag(s): dM = 2 dSigma M (dSigma symmetric).
-  double dM[9];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-      dM[3 * r + k] = 2.0 * (gS[3 * r] * cv.M[k] + gS[3 * r + 1] * cv.M[3 + k] + gS[3 * r + 2] * cv.M[6 + k]);
-  double gs[3], dR[9];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) gs[k] = dM[k] * cv.Rq[k] + dM[3 + k] * cv.Rq[3 + k] + dM[6 + k] * cv.Rq[6 + k];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) dR[3 * r + k] = dM[3 * r + k] * s[k];
-  // Rq of the unit quaternion (w, x, y, z)
-  const double w = cv.w, x = cv.x, y = cv.y, z = cv.z;
-  double gw = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-  double gx = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
-                     2.0 * x * dR[8]);
-  double gy = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
-                     2.0 * y * dR[8]);
-  double gz = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] +
-                     y * dR[7]);
-  // normalisation q_hat = q / |q|
-  const double dot = gw * w + gx * x + gy * y + gz * z;
-  const double iq = 1.0 / cv.qn;
-  d_quats[i] = (float)((gw - w * dot) * iq);
-  d_quats[n + i] = (float)((gx - x * dot) * iq);
-  d_quats[2 * n + i] = (float)((gy - y * dot) * iq);
-  d_quats[3 * n + i] = (float)((gz - z * dot) * iq);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    d_means[k * n + i] = (float)gm[k];
-    d_scales[k * n + i] = (float)gs[k];
-  }
-  d_opac[i] = (float)go;
+  write_param_grads<K>(n, i, s, cv, gm, gS, go, gsh, d_means, d_scales, d_quats, d_opac, d_sh);
   if (STATS && st_count > 0) {
     dacc.grad_sum[i] = (float)((double)dacc.grad_sum[i] + st_grad);
     dacc.tau_sum[i] = (float)((double)dacc.tau_sum[i] + st_tau);
     dacc.count[i] += st_count;
   }
+}
+
+// Adjoint of the spherical footprint.  Inputs per item g2d[items][13]: the gradient w.r.t. the
+// unit direction mu^ (3) and the normalised covariance Sigma~ (xx, xy, xz, yy, yz, zz, the
+// off-diagonals as one shared variable), opacity, r, g, b.  With Sigma~ = W Sigma W^T / r^2 +
+// delta I, mu^ = mu / r and r = |mu|:  dL/d(W Sigma W^T) = dL/dSigma~ / r^2,
+// dL/dr = -2 <dL/dSigma~, W Sigma W^T> / r^3,  dL/dmu = (I - mu^ mu^^T) dL/dmu^ / r + mu^ dL/dr;
+// colour as in the affine adjoint.  Sums over views, overwrites the parameter gradients, clears
+// the consumed g2d entries.
+template <int K>
+__global__ __launch_bounds__(256) void preprocess_sph_bwd_kernel(
+    int64_t n, const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
+    const float* __restrict__ opac, const float* __restrict__ sh, const float* __restrict__ cams, ViewTable vt, Params P,
+    const uint32_t* __restrict__ count, float* __restrict__ g2d, float* __restrict__ d_means,
+    float* __restrict__ d_scales, float* __restrict__ d_quats, float* __restrict__ d_opac, float* __restrict__ d_sh) {
+  constexpr int NV = 13;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double m[3], s[3], q[4];
 #pragma unroll
-  for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = (float)gsh[k];
+  for (int k = 0; k < 3; ++k) m[k] = (double)means[k * n + i];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s[k] = (double)scales[k * n + i];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = (double)quats[k * n + i];
+  float coef[K * 3];
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) coef[k] = sh[(int64_t)k * n + i];
+  Cov3 cv;
+  cov3(s, q, cv);
+  double gm[3] = {0.0, 0.0, 0.0};
+  double gS[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // dL/dSigma (symmetric)
+  double go = 0.0;
+  double gsh[K * 3];
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) gsh[k] = 0.0;
+  for (int v = 0; v < vt.n_views; ++v) {
+    const int64_t item = (int64_t)v * n + i;
+    if (count[item] == 0) continue;
+    double g[NV];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      g[k] = (double)g2d[item * NV + k];
+      any = any || g[k] != 0.0;
+    }
+    if (!any) continue;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) g2d[item * NV + k] = 0.0f;
+    Cam cam;
+    load_cam(cams, v, cam);
+    Geo G;
+    const Pin pin{0.0, 0.0, 0.0, 0.0};
+    geometry(m, cam, cv, vt.W[v], vt.H[v], P, pin, G);
+    double C[6], Sc[6];
+    sph_cov(G, cam, cv, vt.H[v], P, C, Sc);
+    const double r = G.r, ir2 = 1.0 / G.r2;
+    const double mh[3] = {G.mu[0] / r, G.mu[1] / r, G.mu[2] / r};
+    // full symmetric dL/dSigma~ from the shared-off-diagonal values
+    const double gC[9] = {g[3], 0.5 * g[4], 0.5 * g[5], 0.5 * g[4], g[6], 0.5 * g[7], 0.5 * g[5], 0.5 * g[7], g[8]};
+    const double Sfull[9] = {Sc[0], Sc[1], Sc[2], Sc[1], Sc[3], Sc[4], Sc[2], Sc[4], Sc[5]};
+    double inner = 0.0;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) inner += gC[e] * Sfull[e];
+    const double gr = -2.0 * inner * ir2 / r;
+    // W Sigma W^T:  dL/dSigma += W^T (dL/dSigma~ / r^2) W
+    double RtG[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        RtG[3 * a + b] = (cam.R[a] * gC[b] + cam.R[3 + a] * gC[3 + b] + cam.R[6 + a] * gC[6 + b]) * ir2;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        gS[3 * a + b] += RtG[3 * a] * cam.R[b] + RtG[3 * a + 1] * cam.R[3 + b] + RtG[3 * a + 2] * cam.R[6 + b];
+    // mu^ = mu / r, r = |mu|
+    const double dot = g[0] * mh[0] + g[1] * mh[1] + g[2] * mh[2];
+    double dmu[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dmu[a] = (g[a] - mh[a] * dot) / r + mh[a] * gr;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gm[k] += cam.R[k] * dmu[0] + cam.R[3 + k] * dmu[1] + cam.R[6 + k] * dmu[2];
+    go += g[9];
+    // colour = max(0, sum_k sh_k Y_k(dir) + 0.5), dir = (m - c) / |m - c|
+    double d[3], dist;
+    view_dir(m, cam, d, dist);
+    double Y[K];
+    sh_basis<K>(d[0], d[1], d[2], Y);
+    double dY[K][3];
+    sh_basis_grad<K>(d[0], d[1], d[2], dY);
+    double gdir[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc = acc + (double)coef[k * 3 + ch] * Y[k];
+      acc = acc + 0.5;
+      if (!(acc > 0.0)) continue;
+      const double gcol = g[10 + ch];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        gsh[k * 3 + ch] += gcol * Y[k];
+        const double wk = gcol * (double)coef[k * 3 + ch];
+        gdir[0] += wk * dY[k][0];
+        gdir[1] += wk * dY[k][1];
+        gdir[2] += wk * dY[k][2];
+      }
+    }
+    const double dd = gdir[0] * d[0] + gdir[1] * d[1] + gdir[2] * d[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gm[k] += (gdir[k] - d[k] * dd) / dist;
+  }
+  write_param_grads<K>(n, i, s, cv, gm, gS, go, gsh, d_means, d_scales, d_quats, d_opac, d_sh);
 }
 
 Params make_params(const odgs_plan* p) {
@@ -596,9 +850,18 @@ hipError_t launch_preprocess(const odgs_plan* p, const float* means, const float
   uint32_t* dkey = ws_ptr<uint32_t>(ws, p->off_dkey[0]);
   float* depth = ws_ptr<float>(ws, p->off_depth);
   odgs_status* status = ws_ptr<odgs_status>(ws, p->off_status);
+  SphRec* srec = nullptr;
+  float4* cone = nullptr;
+  if (plan_spherical(p)) {
+    srec = ws_ptr<SphRec>(ws, p->off_srec);
+    cone = ws_ptr<float4>(ws, p->off_cone);
+    const int entries = vt.dir_base[vt.n_views];
+    hipLaunchKernelGGL(dir_table_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, st, vt,
+                       ws_ptr<double2>(ws, p->off_dirs));
+  }
 #define ODGS_PRE(KK)                                                                                               \
   hipLaunchKernelGGL(preprocess_kernel<KK>, dim3(grid), dim3(256), 0, st, p->n, means, scales, quats, opac, sh, cams, \
-                     vt, P, rec, rect, count, dkey, depth, status)
+                     vt, P, rec, rect, count, dkey, depth, status, srec, cone)
   switch (p->sh_degree) {
     case 0: ODGS_PRE(1); break;
     case 1: ODGS_PRE(4); break;
@@ -622,7 +885,10 @@ hipError_t launch_preprocess_bwd(const odgs_plan* p, const float* means, const f
   const uint32_t* count = ws_ptr<uint32_t>(ws, p->off_count);
   float* g2d = ws_ptr<float>(ws, p->off_g2d);
 #define ODGS_PREB(KK)                                                                                        \
-  if (acc)                                                                                                   \
+  if (plan_spherical(p))                                                                                     \
+    hipLaunchKernelGGL((preprocess_sph_bwd_kernel<KK>), dim3(grid), dim3(256), 0, st, p->n, means, scales,     \
+                       quats, opac, sh, cams, vt, P, count, g2d, d_means, d_scales, d_quats, d_opac, d_sh);    \
+  else if (acc)                                                                                              \
     hipLaunchKernelGGL((preprocess_bwd_kernel<KK, true>), dim3(grid), dim3(256), 0, st, p->n, means, scales,   \
                        quats, opac, sh, cams, vt, P, count, g2d, p->items, d_means, d_scales, d_quats, d_opac, \
                        d_sh, da);                                                                            \

@@ -18,6 +18,7 @@
 #include <utility>
 
 #include "common.h"
+#include "wave.h"
 
 namespace odgs {
 namespace {
@@ -44,32 +45,12 @@ __device__ inline float wave_sum_to_lane63(float v) {
 
 __device__ inline float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
 
-template <int CTRL>
-__device__ inline float dpp_read(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-
-// Exchange step of a multi-value butterfly: the lane keeps `lo` or `hi` (by `bit`) and adds the
-// partner's copy of the same slot; the partner (reached with DPP control CTRL) has the opposite
-// `bit` and holds the same slot meanings.
-template <int CTRL>
-__device__ inline float bfly(float lo, float hi, bool bit) {
-  return (bit ? hi : lo) + dpp_read<CTRL>(bit ? lo : hi);
-}
 
 // Sums nine per-lane values over each 16-lane row in four DPP exchange steps (pairs (i, 15-i),
 // (i, 7-i), (i, 3-i), (i, i^1) inside the row; each step halves the slots a lane holds).  Lane i
 // ends with the row sum of value kRowSlot[i % 16] (none where the table says 15).
 constexpr uint64_t kRowSlot = 0xFFF8F765FF43F210ull;  // nibble i = value index held by row lane i
 
-// Sum of a value over the four 16-lane rows of the wavefront, returned in every row: the gfx950
-// row-swap permutes (lanes 32-63 <-> 0-31, then odd <-> even rows) need no LDS traffic.
-__device__ inline float sum_rows(float x) {
-  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-  const float y = __uint_as_float(h[0]) + __uint_as_float(h[1]);
-  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(y), __float_as_uint(y), false, false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
 
 // Sum of a value over the eight lanes of an aligned 8-lane group (every lane gets the sum).
 __device__ inline float group8_sum(float x) {
@@ -124,15 +105,6 @@ __device__ inline float row_reduce9(const float (&g)[9], bool b3, bool b2, bool 
   return bfly<0xB1>(d0, d1, b0);                                                        // quad_perm [1,0,3,2]
 }
 
-// Pixel of a thread inside a TILE x TILE tile: wavefront w owns quadrant w (row-major over the
-// TILE/8 x TILE/8 quadrants), lane l the pixel (l % 8, l / 8) inside it.
-template <int TILE>
-__device__ inline void local_pixel(int t, int& lx, int& ly) {
-  constexpr int QPR = TILE / 8;
-  const int w = t >> 6, l = t & 63;
-  lx = (w % QPR) * 8 + (l & 7);
-  ly = (w / QPR) * 8 + (l >> 3);
-}
 
 // Minimum over the rectangle [x0, x1] x [y0, y1] of f(x, y) = a x^2 + 2 b x y + c y^2 (positive
 // definite), with nba = -b/a and nbc = -b/c precomputed.  Float; callers add a margin that covers
@@ -908,7 +880,7 @@ __global__ void debug_copy_kernel(const float* __restrict__ src, int64_t n, floa
 }
 
 hipError_t launch_debug_g2d(const odgs_plan* p, const void* ws, float* out, hipStream_t st) {
-  const int64_t n = 9 * p->items;
+  const int64_t n = (int64_t)p->g2d_stride * p->items;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(debug_copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                      ws_ptr<float>(ws, p->off_g2d), n, out);

@@ -1,0 +1,442 @@
+// Compositing kernels of the spherical footprint (ODGS_FLAG_SPHERICAL), gfx950.
+//
+// Same structure as the affine compositors: one workgroup per (view, tile), one thread per
+// pixel, every 64-wide wavefront owns an 8x8 quadrant, the tile's depth-ordered list is staged
+// through LDS in batches.  What changes is the evaluation: each pixel carries the unit direction
+// d of its ray (from the per-view ray table, rounded once to float), and a Gaussian's exponent is
+// -qh / D with t1 = u1 . d, t2 = u2 . d, h = w . d, qh = t1^2 + t2^2, D = h^2 + k2 qh (the maximum
+// of the 3D Gaussian along the ray, see SphRec); it reaches the pixel iff h > 0 and
+// p_min D + qh <= 0.  While staging, a record's quadrant mask comes from its cone (mu^, beta): a
+// quadrant is skipped when the angle between its centre ray and mu^ exceeds beta plus the
+// quadrant's angular radius.
+//
+// Backward: per accepted (Gaussian, wavefront) the 13 gradient values (mu^ (3), Sigma~ (6),
+// opacity, rgb) are summed over each 16-lane row by a 16-slot DPP butterfly and over rows by the
+// row-swap permutes, kept per wavefront in LDS, and flushed with one float atomic per (Gaussian,
+// tile, value) to contiguous 52-byte records.
+#include "common.h"
+#include "wave.h"
+
+#include <utility>
+
+namespace odgs {
+namespace {
+
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTStop = 1e-4f;
+constexpr int kNV = 13;  // gradient values per item
+
+template <int TILE, int BATCH>
+struct SphStage {
+  static constexpr int N = TILE * TILE;
+  static constexpr int NQ = (TILE / 8) * (TILE / 8);
+  static constexpr int NW = N / kWave;
+  float4 s0[BATCH];
+  float4 s1[BATCH];
+  float4 s2[BATCH];
+  float4 s3[BATCH];
+  uint32_t sid[BATCH];
+  float dep[BATCH];
+  uint8_t list[NQ][BATCH];
+  uint32_t wcnt[NW][NQ];
+  uint32_t tot[NQ];
+  float3 qdir[NQ];  // centre ray of each quadrant
+};
+
+// Unit ray direction of pixel (x, y) of view v: (cos theta sin phi, -sin theta, cos theta cos phi),
+// each component a double product rounded once to float.
+__device__ inline float3 pixel_ray(const double2* __restrict__ dirs, const ViewTable& vt, int v, int x, int y) {
+  const double2 c = dirs[vt.dir_base[v] + x];             // (sin phi, cos phi)
+  const double2 r = dirs[vt.dir_base[v] + vt.W[v] + y];   // (sin theta, cos theta)
+  return make_float3((float)(r.y * c.x), (float)(-r.x), (float)(r.y * c.y));
+}
+
+// Angular radius about a quadrant's centre ray (pixel (4, 4) of the 8x8 block) that holds every
+// pixel ray of the quadrant: at most 4 pixel pitches in each direction, i.e. 4 pi / H in
+// elevation plus 4 (2 pi / W) cos(theta) <= 8 pi / W along the parallel (the path along the
+// meridian then the parallel is no shorter than the great circle).
+__device__ inline float quadrant_radius(int W, int H) {
+  return (4.0f * 3.14159265f / (float)H + 8.0f * 3.14159265f / (float)W) * 1.001f + 1e-6f;
+}
+
+template <int TILE, int BATCH>
+__device__ inline void sph_stage_init(SphStage<TILE, BATCH>& S, const double2* __restrict__ dirs, const ViewTable& vt,
+                                      int v, int tx0, int ty0) {
+  constexpr int QPR = TILE / 8;
+  if (threadIdx.x < SphStage<TILE, BATCH>::NQ) {
+    const int q = threadIdx.x;
+    S.qdir[q] = pixel_ray(dirs, vt, v, tx0 + (q % QPR) * 8 + 4, ty0 + (q / QPR) * 8 + 4);
+  }
+  __syncthreads();
+}
+
+// Stage `cnt` records (entry e <- list position first + dir * e) and build every wavefront's
+// order-preserving list of the entries whose cone reaches its quadrant.
+template <int TILE, int BATCH>
+__device__ inline void sph_stage_batch(SphStage<TILE, BATCH>& S, const uint32_t* __restrict__ pair_items,
+                                       const SphRec* __restrict__ rec, const float4* __restrict__ cone, uint32_t first,
+                                       int dir, int cnt, float qrad, int (&nq)[SphStage<TILE, BATCH>::NQ],
+                                       const float* __restrict__ depth) {
+  using St = SphStage<TILE, BATCH>;
+  const int t = threadIdx.x, ln = t & (kWave - 1), wv = t >> 6;
+  const uint64_t below = ln == 0 ? 0ull : (~0ull >> (kWave - ln));
+#pragma unroll
+  for (int q = 0; q < St::NQ; ++q) nq[q] = 0;
+  for (int r0 = 0; r0 < cnt; r0 += St::N) {
+    const int e = r0 + t;
+    uint32_t m = 0;
+    if (e < cnt) {
+      const uint32_t item = pair_items[first + dir * e];
+      const SphRec r = rec[item];
+      S.s0[e] = r.s0;
+      S.s1[e] = r.s1;
+      S.s2[e] = r.s2;
+      S.s3[e] = r.s3;
+      S.sid[e] = item;
+      if (depth) S.dep[e] = depth[item];
+      const float4 c = cone[item];
+      // hit iff angle(quadrant centre, mu^) <= beta + qrad; the 1e-5 slack covers the float
+      // rounding of the dot product and of the cosine
+      const float lim = c.w + qrad >= 3.14159f ? -2.0f : cosf(c.w + qrad) - 1e-5f;
+#pragma unroll
+      for (int q = 0; q < St::NQ; ++q) {
+        const float3 d = S.qdir[q];
+        const float dot = fmaf(d.z, c.z, fmaf(d.y, c.y, d.x * c.x));
+        m |= dot >= lim ? (1u << q) : 0u;
+      }
+    }
+    uint32_t within[St::NQ];
+#pragma unroll
+    for (int q = 0; q < St::NQ; ++q) {
+      const uint64_t bq = __builtin_amdgcn_ballot_w64((m >> q) & 1u);
+      within[q] = __popcll(bq & below);
+      if (ln == 0) S.wcnt[wv][q] = __popcll(bq);
+    }
+    __syncthreads();
+    if constexpr (St::NW > 1) {
+      if (t < St::NQ) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < St::NW; ++w) {
+          const uint32_t c = S.wcnt[w][t];
+          S.wcnt[w][t] = run;
+          run += c;
+        }
+        S.tot[t] = run;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < St::NQ; ++q) {
+      const int pre = St::NW > 1 ? (int)S.wcnt[wv][q] : 0;
+      const int tot = St::NW > 1 ? (int)S.tot[q] : (int)S.wcnt[0][q];
+      if ((m >> q) & 1u) S.list[q][nq[q] + pre + (int)within[q]] = (uint8_t)e;
+      nq[q] += tot;
+    }
+    __syncthreads();
+  }
+}
+
+// Float evaluation of one record for ray d: returns the acceptance; power = -qh / D (correctly
+// rounded division); also hands out t1, t2, h, D and qh for the backward.
+__device__ inline bool sph_eval(const float4& a, const float4& b, const float4& c, const float3& d, float& power,
+                                float& t1, float& t2, float& h, float& D, float& qh) {
+  t1 = fmaf(a.z, d.z, fmaf(a.y, d.y, a.x * d.x));
+  t2 = fmaf(b.y, d.z, fmaf(b.x, d.y, a.w * d.x));
+  h = fmaf(c.x, d.z, fmaf(b.w, d.y, b.z * d.x));
+  qh = fmaf(t1, t1, t2 * t2);
+  D = fmaf(c.y, qh, h * h);
+  power = -__fdiv_rn(qh, D);
+  return h > 0.0f && !(fmaf(c.w, D, qh) > 0.0f);
+}
+
+template <int TILE, int BATCH, bool DEPTH>
+__global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
+    ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items,
+    const SphRec* __restrict__ rec, const float4* __restrict__ cone, const double2* __restrict__ dirs,
+    float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
+    float bg0, float bg1, float bg2, const float* __restrict__ depth, float* __restrict__ out_depth) {
+  using St = SphStage<TILE, BATCH>;
+  constexpr int N = St::N;
+  __shared__ St S;
+  const int g = blockIdx.x;
+  const int v = view_of_tile(vt, g);
+  const int W = vt.W[v], H = vt.H[v];
+  const int ntx = W / TILE;
+  const int lt = g - vt.tile_base[v];
+  const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+  int lx, ly;
+  local_pixel<TILE>(threadIdx.x, lx, ly);
+  const int x = tx0 + lx, y = ty0 + ly;
+  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const float3 d = pixel_ray(dirs, vt, v, x, y);
+  const float qrad = quadrant_radius(W, H);
+  sph_stage_init<TILE, BATCH>(S, dirs, vt, v, tx0, ty0);
+  const uint2 rg = ranges[g];
+  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, Dsum = 0.0f;
+  int last = 0;
+  bool done = false;
+  for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
+    if (__syncthreads_count(done) == N) break;
+    const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
+    int nq[St::NQ];
+    sph_stage_batch<TILE, BATCH>(S, pair_items, rec, cone, base, 1, cnt, qrad, nq, DEPTH ? depth : nullptr);
+    const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
+    for (int i = 0; i < n; ++i) {
+      if (__builtin_amdgcn_ballot_w64(!done) == 0ull) break;  // uniform: every pixel has finished
+      const int k = S.list[wq][i];
+      const float4 c = S.s2[k];
+      float power, t1, t2, h, D, qh;
+      const bool hit = sph_eval(S.s0[k], S.s1[k], c, d, power, t1, t2, h, D, qh);
+      const bool ok = !done && hit;
+      if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
+      float alpha = c.z * __expf(power);
+      alpha = alpha > kAlphaMax ? kAlphaMax : alpha;
+      const float Tn = T * (1.0f - alpha);
+      const bool stop = ok && Tn < kTStop;
+      const bool acc = ok && !(Tn < kTStop);
+      done = done || stop;
+      const float4 col = S.s3[k];
+      const float w = acc ? alpha * T : 0.0f;
+      C0 = fmaf(w, col.x, C0);
+      C1 = fmaf(w, col.y, C1);
+      C2 = fmaf(w, col.z, C2);
+      if (DEPTH) Dsum = Dsum + w * S.dep[k];
+      T = acc ? Tn : T;
+      last = acc ? (int)(base - rg.x) + k + 1 : last;
+    }
+  }
+  const int64_t plane = (int64_t)W * H;
+  const int64_t pix = (int64_t)y * W + x;
+  float* img = out_rgb + 3 * vt.pix_base[v];
+  img[pix] = fmaf(T, bg0, C0);
+  img[plane + pix] = fmaf(T, bg1, C1);
+  img[2 * plane + pix] = fmaf(T, bg2, C2);
+  const int64_t gp = vt.pix_base[v] + pix;
+  ws_T[gp] = T;
+  ws_last[gp] = last;
+  if (DEPTH) out_depth[gp] = Dsum;
+  if (out_T) out_T[gp] = T;
+}
+
+// Sums sixteen per-lane values over each 16-lane row in four DPP exchange steps (partners
+// 15 - i, 7 - i, 3 - i, i ^ 1 inside the row); lane i ends with the row sum of value i % 16.
+__device__ inline float row_reduce16(const float (&g)[16], int lane) {
+  const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+  float a[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] = bfly<0x140>(g[j], g[8 + j], b3);  // row_mirror
+  float c[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) c[j] = bfly<0x141>(a[j], a[4 + j], b2);  // row_half_mirror
+  const float e0 = bfly<0x1B>(c[0], c[2], b1);                         // quad_perm [3,2,1,0]
+  const float e1 = bfly<0x1B>(c[1], c[3], b1);
+  return bfly<0xB1>(e0, e1, b0);                                       // quad_perm [1,0,3,2]
+}
+
+// g2d layout [items][13]: d/dmu^ (3), d/dSigma~ (xx, xy, xz, yy, yz, zz; off-diagonals as one
+// shared variable), d/dopacity, d/d(r, g, b).  With A = Sigma~^-1 and the ray's closest approach
+// t* d (t* = h / D) the exponent p = -m / 2 has dp/dmu^ = z and dp/dSigma~ = z z^T / 2, where
+// z = A (t* d - mu^) = (2 / D) (h (t1 u1 + t2 u2) - qh w) (A = 2 (u1 u1^T + u2 u2^T) + (2 / k2) w w^T,
+// u1, u2 tangent, w . mu^ = 1): no inverse and no cancellation at the footprint's scale.  Like
+// the affine path this accumulates w.r.t. the covariance, which keeps the sums well scaled.
+template <int TILE, int BATCH>
+__global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
+    ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items,
+    const SphRec* __restrict__ rec, const float4* __restrict__ cone, const double2* __restrict__ dirs,
+    const float* __restrict__ ws_T, const int32_t* __restrict__ ws_last, const float* __restrict__ dL_drgb,
+    float* __restrict__ g2d, float bg0, float bg1, float bg2) {
+  using St = SphStage<TILE, BATCH>;
+  constexpr int N = St::N;
+  constexpr bool kSlots = St::NW <= 4;  // a slot set per wavefront, else one shared set (LDS atomics)
+  constexpr int NS = kSlots ? St::NW : 1;
+  __shared__ St S;
+  __shared__ float acc[NS][kNV][BATCH + 1];
+  __shared__ int smax;
+  const int g = blockIdx.x;
+  const int v = view_of_tile(vt, g);
+  const int W = vt.W[v], H = vt.H[v];
+  const int ntx = W / TILE;
+  const int lt = g - vt.tile_base[v];
+  const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+  int lx, ly;
+  local_pixel<TILE>(threadIdx.x, lx, ly);
+  const int x = tx0 + lx, y = ty0 + ly;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const float3 d = pixel_ray(dirs, vt, v, x, y);
+  const float qrad = quadrant_radius(W, H);
+  sph_stage_init<TILE, BATCH>(S, dirs, vt, v, tx0, ty0);
+  const uint2 rg = ranges[g];
+  const int64_t plane = (int64_t)W * H;
+  const int64_t pix = (int64_t)y * W + x;
+  const int64_t gp = vt.pix_base[v] + pix;
+  const float* dimg = dL_drgb + 3 * vt.pix_base[v];
+  const float dl0 = dimg[pix], dl1 = dimg[plane + pix], dl2 = dimg[2 * plane + pix];
+  float T = ws_T[gp];
+  const int last = ws_last[gp];
+  float S0 = T * bg0, S1 = T * bg1, S2 = T * bg2;
+  int wmax = last;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
+  wmax = __builtin_amdgcn_readfirstlane(wmax);
+  if (threadIdx.x == 0) smax = 0;
+  __syncthreads();
+  if (lane == 0) atomicMax(&smax, wmax);
+  __syncthreads();
+  const int end_all = smax;
+  for (int end = end_all; end > 0; end -= BATCH) {
+    const int cnt = min(BATCH, end);
+    for (int t = threadIdx.x; t < cnt; t += N) {
+#pragma unroll
+      for (int w = 0; w < NS; ++w)
+#pragma unroll
+        for (int q = 0; q < kNV; ++q) acc[w][q][t] = 0.0f;
+    }
+    int nq[St::NQ];
+    // entry e is list position end - 1 - e (back to front)
+    sph_stage_batch<TILE, BATCH>(S, pair_items, rec, cone, rg.x + end - 1, -1, cnt, qrad, nq, nullptr);
+    const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
+    for (int i = 0; i < n; ++i) {
+      const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);
+      const int jrel = end - 1 - k;
+      if (jrel >= wmax) continue;  // uniform: behind every contributor of this wavefront
+      const float4 a = S.s0[k], b = S.s1[k], c = S.s2[k];
+      float power, t1, t2, h, D, qh;
+      // evaluated on every lane (no short circuit): the gradient terms below are formed on all
+      // lanes and zeroed by selects, which needs finite operands
+      const bool hit = sph_eval(a, b, c, d, power, t1, t2, h, D, qh);
+      const bool ok = jrel < last && hit;
+      if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
+      const float G = __expf(power);
+      float alpha = c.z * G;
+      const bool clamped = alpha > kAlphaMax;
+      alpha = clamped ? kAlphaMax : alpha;
+      const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
+      T = ok ? T * inv_om : T;  // transmittance in front of this Gaussian
+      const float w = alpha * T;
+      const float4 col = S.s3[k];
+      const float dL_da = dl0 * fmaf(col.x, T, -S0 * inv_om) + dl1 * fmaf(col.y, T, -S1 * inv_om) +
+                          dl2 * fmaf(col.z, T, -S2 * inv_om);
+      const float wk = ok ? w : 0.0f;
+      S0 = fmaf(col.x, wk, S0);
+      S1 = fmaf(col.y, wk, S1);
+      S2 = fmaf(col.z, wk, S2);
+      const bool live = ok && !clamped;
+      const float dpow = live ? dL_da * alpha : 0.0f;
+      // z = (2 / D) (h (t1 u1 + t2 u2) - qh w), zero on lanes that do not contribute
+      const float s2 = live ? 2.0f * __builtin_amdgcn_rcpf(D) : 0.0f;
+      const float ht1 = h * t1, ht2 = h * t2;
+      const float zx = s2 * fmaf(ht1, a.x, fmaf(ht2, a.w, -qh * b.z));
+      const float zy = s2 * fmaf(ht1, a.y, fmaf(ht2, b.x, -qh * b.w));
+      const float zz = s2 * fmaf(ht1, a.z, fmaf(ht2, b.y, -qh * c.x));
+      const float gx = dpow * zx, gy = dpow * zy, gz = dpow * zz;
+      float gv[16];
+      gv[0] = gx;
+      gv[1] = gy;
+      gv[2] = gz;
+      gv[3] = 0.5f * gx * zx;  // dpow z z^T / 2, the shared off-diagonals counted twice
+      gv[4] = gx * zy;
+      gv[5] = gx * zz;
+      gv[6] = 0.5f * gy * zy;
+      gv[7] = gy * zz;
+      gv[8] = 0.5f * gz * zz;
+      gv[9] = live ? dL_da * G : 0.0f;
+      gv[10] = wk * dl0;
+      gv[11] = wk * dl1;
+      gv[12] = wk * dl2;
+      gv[13] = 0.0f;
+      gv[14] = 0.0f;
+      gv[15] = 0.0f;
+      const float rs = row_reduce16(gv, lane);
+      const int slot = lane & 15;
+      if constexpr (kSlots) {
+        const float ws = sum_rows(rs);
+        if (lane < kNV) acc[wq][lane][k] = ws;
+      } else {
+        if (slot < kNV) atomicAdd(&acc[0][slot][k], rs);
+      }
+    }
+    __syncthreads();
+    // thirteen consecutive lanes carry one entry's values: contiguous 52-byte records
+    for (int xx = threadIdx.x; xx < kNV * cnt; xx += N) {
+      const int t = xx / kNV, q = xx - kNV * t;
+      float s = acc[0][q][t];
+#pragma unroll
+      for (int w = 1; w < NS; ++w) s += acc[w][q][t];
+      if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * kNV + q], s);
+    }
+    __syncthreads();
+  }
+}
+
+template <int TILE, int BATCH>
+struct SphFwdRun {
+  static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
+                  const SphRec* rec, const float4* cone, const double2* dirs, float* out_rgb, float* out_T, float* wT,
+                  int32_t* wl, const float* depth, float* out_depth, hipStream_t st) {
+    if (out_depth)
+      hipLaunchKernelGGL((render_sph_fwd_kernel<TILE, BATCH, true>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges,
+                         items, rec, cone, dirs, out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], depth,
+                         out_depth);
+    else
+      hipLaunchKernelGGL((render_sph_fwd_kernel<TILE, BATCH, false>), dim3(tiles), dim3(TILE * TILE), 0, st, vt,
+                         ranges, items, rec, cone, dirs, out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2],
+                         depth, out_depth);
+  }
+};
+
+template <int TILE, int BATCH>
+struct SphBwdRun {
+  static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
+                  const SphRec* rec, const float4* cone, const double2* dirs, const float* wT, const int32_t* wl,
+                  const float* dL, float* g2d, hipStream_t st) {
+    hipLaunchKernelGGL((render_sph_bwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items,
+                       rec, cone, dirs, wT, wl, dL, g2d, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+  }
+};
+
+template <template <int, int> class F, typename... Args>
+bool sph_dispatch(int tile, int batch, Args&&... args) {
+#define ODGS_CASE(TT, BB)                        \
+  if (tile == TT && batch == BB) {               \
+    F<TT, BB>::run(std::forward<Args>(args)...); \
+    return true;                                 \
+  }
+  ODGS_CASE(8, 32) ODGS_CASE(8, 64) ODGS_CASE(8, 128) ODGS_CASE(8, 256)
+  ODGS_CASE(16, 32) ODGS_CASE(16, 64) ODGS_CASE(16, 128) ODGS_CASE(16, 256)
+  ODGS_CASE(32, 64) ODGS_CASE(32, 128) ODGS_CASE(32, 256)
+#undef ODGS_CASE
+  return false;
+}
+
+}  // namespace
+
+hipError_t launch_render_sph_fwd(const odgs_plan* p, void* ws, float* out_rgb, float* out_T, float* out_depth,
+                                 hipStream_t st) {
+  const ViewTable vt = make_view_table(p);
+  const int tiles = p->tile_base[p->n_views];
+  if (tiles == 0) return hipSuccess;
+  if (!sph_dispatch<SphFwdRun>(p->s.tile, p->s.batch, p, tiles, vt, ws_ptr<uint2>(ws, p->off_ranges),
+                               ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]), ws_ptr<SphRec>(ws, p->off_srec),
+                               ws_ptr<float4>(ws, p->off_cone), ws_ptr<double2>(ws, p->off_dirs), out_rgb, out_T,
+                               ws_ptr<float>(ws, p->off_T), ws_ptr<int32_t>(ws, p->off_last),
+                               ws_ptr<float>(ws, p->off_depth), out_depth, st))
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_render_sph_bwd(const odgs_plan* p, void* ws, const float* dL_drgb, hipStream_t st) {
+  const ViewTable vt = make_view_table(p);
+  const int tiles = p->tile_base[p->n_views];
+  if (tiles == 0) return hipSuccess;
+  if (!sph_dispatch<SphBwdRun>(p->s.tile, p->s.batch_bwd, p, tiles, vt, ws_ptr<uint2>(ws, p->off_ranges),
+                               ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]), ws_ptr<SphRec>(ws, p->off_srec),
+                               ws_ptr<float4>(ws, p->off_cone), ws_ptr<double2>(ws, p->off_dirs),
+                               ws_ptr<float>(ws, p->off_T), ws_ptr<int32_t>(ws, p->off_last), dL_drgb,
+                               ws_ptr<float>(ws, p->off_g2d), st))
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace odgs

@@ -447,7 +447,7 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * (int64_t)p->tile_base[p->n_views], st);
   if (e != hipSuccess) return e;
   // the backward's 2D gradient accumulators start cleared
-  e = launch_fill_u32(ws_ptr<uint32_t>(ws, p->off_g2d), 0u, 9 * p->items, st);
+  e = launch_fill_u32(ws_ptr<uint32_t>(ws, p->off_g2d), 0u, (int64_t)p->g2d_stride * p->items, st);
   if (e != hipSuccess) return e;
   if (items == 0) return hipSuccess;
   // 1. items by radial depth (culled items carry the largest key)

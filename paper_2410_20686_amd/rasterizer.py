@@ -16,7 +16,8 @@ import torch
 
 from . import _odgs as B
 
-DEFAULT_SETTINGS = dict(tile=16, batch=0, batch_bwd=0, count_work=False, pinhole=None, near=0.2, far=1.0e4, dilation=0.3, pole_eps=1.0e-4, bg=(0.0, 0.0, 0.0))
+DEFAULT_SETTINGS = dict(tile=16, batch=0, batch_bwd=0, count_work=False, pinhole=None, footprint="affine", near=0.2,
+                        far=1.0e4, dilation=0.3, pole_eps=1.0e-4, bg=(0.0, 0.0, 0.0))
 
 
 def _ptr(t: torch.Tensor | None):
@@ -162,9 +163,11 @@ class Rasterizer:
                            None if stats is None else stats.acc(self.n), _stream())
 
     def g2d(self) -> torch.Tensor:
-        """[items, 9] per-item 2D gradients left by composite_bwd (item = view * N + gaussian):
-        d/du, d/dv, d/dSigma_uu, d/dSigma_uv (shared), d/dSigma_vv, d/dopacity, d/dr, d/dg, d/db."""
-        out = torch.empty((self.n * len(self.wh), 9), dtype=torch.float32, device=self.device)
+        """[items, G] per-item gradients left by composite_bwd (item = view * N + gaussian).  Affine
+        footprint, G = 9: d/du, d/dv, d/dSigma_uu, d/dSigma_uv (shared), d/dSigma_vv, d/dopacity,
+        d/dr, d/dg, d/db.  Spherical footprint, G = 13: d/dmu^ (3), d/dSigma~ (xx, xy, xz, yy, yz,
+        zz; shared off-diagonals), d/dopacity, d/d(r, g, b)."""
+        out = torch.empty((self.n * len(self.wh), int(self.plan.g2d_stride)), dtype=torch.float32, device=self.device)
         B.odgs_debug_g2d(self.plan, _ptr(self.ws), _ptr(out), _stream())
         return out
 

@@ -35,11 +35,40 @@ def test_plan_layout(lib):
     assert list(p.tile_base[:4]) == [0, 2048, 2048 + 8192, 2048 + 8192 + 8]
     assert p.pix_base[3] == 1024 * 512 + 2048 * 1024 + 64 * 32
     assert p.tile_bits == 14 and p.s.batch == 256 and p.s.batch_bwd == 64
-    offs = sorted(getattr(p, n) for n in B._OFFSETS)
+    sph_only = ("off_srec", "off_cone", "off_dirs")  # empty regions (at the end) without the spherical flag
+    offs = sorted(getattr(p, n) for n in B._OFFSETS if n not in sph_only)
     assert all(o % 256 == 0 for o in offs)
     assert len(set(offs)) == len(offs)
     assert B.odgs_workspace_bytes(p) == p.ws_bytes >= offs[-1]
+    assert all(getattr(p, n) == p.ws_bytes for n in sph_only)
     assert B.odgs_status_offset(p) == p.off_status
+    assert p.g2d_stride == 9
+
+
+def test_spherical_plan_layout(lib):
+    wh = [(1024, 512), (64, 32)]
+    p = B.odgs_plan_init(12345, 3, wh, B.make_settings(tile=16, footprint="spherical"), 1_000_003)
+    q = B.odgs_plan_init(12345, 3, wh, B.make_settings(tile=16), 1_000_003)
+    assert p.g2d_stride == 13 and p.s.flags == B.FLAG_SPHERICAL
+    offs = sorted(getattr(p, n) for n in B._OFFSETS)
+    assert len(set(offs)) == len(offs) and all(o % 256 == 0 for o in offs)
+    items = 2 * 12345
+    assert p.off_cone - p.off_srec >= 64 * items and p.off_dirs - p.off_cone >= 16 * items
+    assert p.ws_bytes - p.off_dirs >= 16 * (1024 + 512 + 64 + 32)
+    assert p.ws_bytes > q.ws_bytes + (4 * 4 + 64 + 16) * items
+    # the spherical footprint is defined for equirectangular views and has no work counters
+    with pytest.raises(B.OdgsError):
+        B.odgs_plan_set_pinhole(p, 0, 100.0, 100.0, 32.0, 16.0)
+    with pytest.raises(B.OdgsError):
+        B.odgs_plan_init(10, 0, [(64, 32)], B.make_settings(footprint="spherical", count_work=True), 100)
+    # no densification statistics with it (rejected before anything is enqueued)
+    nul, fake = None, ctypes.c_void_p(256 * 1024)
+    acc = B.DensifyAcc(256 * 1024, 256 * 1024, 256 * 1024, 2e-5, 1e-4)
+    p = B.odgs_plan_init(10, 0, [(64, 32)], B.make_settings(footprint="spherical"), 100)
+    assert lib.odgs_project_bwd(ctypes.byref(p), fake, fake, fake, fake, fake, fake, fake, p.ws_bytes, fake, fake,
+                                fake, fake, fake, ctypes.byref(acc), nul) == B.EINVAL
+    assert lib.odgs_render_bwd(ctypes.byref(p), fake, fake, fake, fake, fake, fake, fake, p.ws_bytes, fake, fake,
+                               fake, fake, fake, fake, ctypes.byref(acc), nul) == B.EINVAL
 
 
 @pytest.mark.parametrize("kw,wh", [

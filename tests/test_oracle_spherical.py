@@ -277,8 +277,8 @@ def test_gradient_by_finite_differences():
 
 
 def test_kernel_layout_adjoint_reproduces_the_backward():
-    """Gradients taken w.r.t. the kernel's variables (Q, w, k2) and pushed through the projection
-    equal those taken w.r.t. (mu^, A): two derivations of the same chain rule."""
+    """Gradients taken w.r.t. the kernel's variables (mu^, Sigma~) and pushed through the
+    projection equal those taken w.r.t. (mu^, A = Sigma~^-1): two derivations of the chain rule."""
     sc = scenes.roaming_scene(600, 3, seed=40, r_range=(1.5, 6.0)).as_f64()
     cams = scenes.uneven_cameras(2, seed=40, sizes=((128, 64), (256, 128)))
     st = settings(bg=(0.1, 0.0, 0.2), **SPH)
