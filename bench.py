@@ -43,7 +43,8 @@ PROFILE = os.path.join(ROOT, "profiles", "render_kernels_M_500k_8x2048x1024.txt"
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("paper_2410_20686_amd/csrc/render.hip", "paper_2410_20686_amd/csrc/common.h"):
+    for f in ("paper_2410_20686_amd/csrc/render.hip", "paper_2410_20686_amd/csrc/common.h",
+              "paper_2410_20686_amd/csrc/wave.h"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -82,6 +83,8 @@ def parse():
                          "dispatch for hardware byte counters)")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-train", action="store_true", help="skip timing the loss + Adam training iteration")
+    ap.add_argument("--no-spherical", action="store_true",
+                    help="skip timing the same step with the spherical (exact per-ray) footprint")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels-per-view", type=int, default=768)
     return ap.parse_args()
@@ -219,6 +222,24 @@ def main():
         log("train iteration %.3f ms" % ms_train)
         del tstep, gp
 
+    # the same step with the spherical footprint (exact per-ray evaluation instead of the local
+    # affine approximation): its own pair list (cone rectangles) and compositors
+    sph = None
+    if not args.no_spherical:
+        st_s = dict(st, footprint="spherical")
+        rs = Rasterizer(sc.n, sc.sh_degree, wh, st_s)
+        s0 = rs.bin_checked(*tensors)
+        rs._alloc(int(s0["n_pairs"] * 1.05) + 4096)
+        sstep = TrainStep(rs, tensors[:5], tensors[5], dL)
+        ms_sph, _g4 = time_graph(sstep.run, args.steps, args.warmup)
+        if rs.status()["flags"] & B.STATUS_OVERFLOW:
+            raise RuntimeError("pair list overflowed during timing (spherical footprint)")
+        sst = time_stages(sstep, max(3, min(args.steps, 10)))
+        sph = dict(ms_per_step=round(ms_sph, 4), value=round(mp_per_step / (ms_sph / 1e3), 2), unit="MP/s",
+                   pairs=int(rs.status()["n_pairs"]), stages_ms={k: round(v, 4) for k, v in sst.items()})
+        log("spherical footprint %.3f ms/step, P=%d, stages %s" % (ms_sph, sph["pairs"], sst))
+        del sstep, rs
+
     per_view = None
     if not args.no_per_view:
         pv_steps = []
@@ -294,6 +315,7 @@ def main():
                    "autotuned": tuned is not None},
         "per_view": per_view,
         "train_iteration": train,
+        "spherical_footprint": sph,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roof,
         "cpu_baseline": cpu,

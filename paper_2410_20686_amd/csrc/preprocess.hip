@@ -347,7 +347,9 @@ __global__ void dir_table_kernel(ViewTable vt, double2* __restrict__ tab) {
   tab[i] = make_double2(sin(a), cos(a));
 }
 
-template <int K>
+// SPH: spherical-footprint records (srec, cone) instead of the affine rectangle (a separate
+// instantiation, so the affine kernel carries none of it).
+template <int K, bool SPH>
 __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float* __restrict__ means,
                                                          const float* __restrict__ scales, const float* __restrict__ quats,
                                                          const float* __restrict__ opac, const float* __restrict__ sh,
@@ -407,7 +409,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
         finite = finite && isfinite(acc);
         rgb[ch] = acc > 0.0 ? (float)acc : 0.0f;
       }
-      if (srec) {
+      if constexpr (SPH) {
         // spherical footprint (ERP views only)
         SphRec sr;
         float4 cn;
@@ -423,8 +425,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
         } else {
           rr = Rect{0, 0, 0, 0};
         }
-      }
-      else if ((kept = (p_min < 0.0) && (g.det > 0.0) && finite)) {
+      } else if ((kept = (p_min < 0.0) && (g.det > 0.0) && finite)) {
         // Footprint: alpha >= 1/255 inside d^T Sigma^-1 d <= k2 = -2 p_min; half extents
         // sqrt(k2 Sigma_uu), sqrt(k2 Sigma_vv), padded by 0.1% + 0.01 px.
         const double k2 = -2.0 * p_min;
@@ -859,9 +860,13 @@ hipError_t launch_preprocess(const odgs_plan* p, const float* means, const float
     hipLaunchKernelGGL(dir_table_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, st, vt,
                        ws_ptr<double2>(ws, p->off_dirs));
   }
-#define ODGS_PRE(KK)                                                                                               \
-  hipLaunchKernelGGL(preprocess_kernel<KK>, dim3(grid), dim3(256), 0, st, p->n, means, scales, quats, opac, sh, cams, \
-                     vt, P, rec, rect, count, dkey, depth, status, srec, cone)
+#define ODGS_PRE(KK)                                                                                              \
+  if (srec)                                                                                                       \
+    hipLaunchKernelGGL((preprocess_kernel<KK, true>), dim3(grid), dim3(256), 0, st, p->n, means, scales, quats,     \
+                       opac, sh, cams, vt, P, rec, rect, count, dkey, depth, status, srec, cone);                 \
+  else                                                                                                            \
+    hipLaunchKernelGGL((preprocess_kernel<KK, false>), dim3(grid), dim3(256), 0, st, p->n, means, scales, quats,    \
+                       opac, sh, cams, vt, P, rec, rect, count, dkey, depth, status, srec, cone)
   switch (p->sh_degree) {
     case 0: ODGS_PRE(1); break;
     case 1: ODGS_PRE(4); break;
