@@ -141,7 +141,7 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   int64_t dirs = 0;
   for (int v = 0; v < n_views; ++v) dirs += plan->width[v] + plan->height[v];
   plan->off_srec = take(sph ? (size_t)I * sizeof(SphRec) : 0);
-  plan->off_cone = take(sph ? (size_t)I * 16 : 0);
+  plan->off_cone = take(sph ? (size_t)I * sizeof(SphCull) : 0);
   plan->off_dirs = take(sph ? (size_t)dirs * 16 : 0);
   plan->ws_bytes = off;
   return ODGS_OK;

@@ -45,6 +45,15 @@ struct SphRec {
   float4 s0, s1, s2, s3;
 };
 
+// Culling data of a spherical-footprint item, read only while staging:
+//   c0 = (mu^, beta)  the cone that holds every ray reaching alpha >= 1/255 (beta = pi: all rays);
+//   c1 = (e1x, e1z, e2x, e2y), c2 = (e2z, p0x, p0y, M11), c3 = (M12, M22, rho, sqrt(lambda_max(M))):
+//   in the gnomonic coordinates p = (d . e1, d . e2) / (d . mu^) of the tangent plane those rays
+//   satisfy (p - p0)^T M (p - p0) <= rho^2 (rho < 0: no such ellipse, cone only).
+struct SphCull {
+  float4 c0, c1, c2, c3;
+};
+
 // Packed tile rectangle of an item: first column (may wrap), column count, first row, rows.
 struct Rect {
   uint16_t col0, ncols, row0, nrows;

@@ -268,7 +268,7 @@ __device__ inline void sph_cov(const Geo& g, const Cam& cam, const Cov3& cv, int
 // everything when the ball of radius k sqrt(lambda_max) holds the camera.  Returns false when
 // culled (Sigma~ not positive definite, empty rectangle).
 __device__ inline bool sph_item(const Geo& g, const Cam& cam, const Cov3& cv, const double s[3], int W, int H,
-                                const Params& P, double p_min, float o, const float rgb[3], SphRec& out, float4& cn,
+                                const Params& P, double p_min, float o, const float rgb[3], SphRec& out, SphCull& cn,
                                 Rect& rr) {
   double C[6], Sc[6];
   sph_cov(g, cam, cv, H, P, C, Sc);
@@ -296,6 +296,30 @@ __device__ inline bool sph_item(const Geo& g, const Cam& cam, const Cov3& cv, co
   out.s1 = make_float4((float)u2[1], (float)u2[2], (float)w[0], (float)w[1]);
   out.s2 = make_float4((float)w[2], (float)k2, o, (float)p_min);
   out.s3 = make_float4(rgb[0], rgb[1], rgb[2], 0.0f);
+  // Gnomonic ellipse of the rays that can reach alpha >= 1/255: with g = (d . e1, d . e2),
+  // s = d . mu^, p = g / s, m <= k^2 reads (1 - k^2 kappa) p^T P^-1 p <= k^2 (1 + a . p)^2
+  // (a = -P^-1 c, kappa = s33 - c^T P^-1 c), an ellipse when k^2 s33 < 1 (the ellipsoid stays in
+  // front of the camera along mu^): M = (1 - k^2 kappa) P^-1 - k^2 a a^T, p0 = k^2 M^-1 a,
+  // rho^2 = k^2 + k^4 a^T M^-1 a.
+  {
+    const double kk = -2.0 * p_min;
+    const double kap = s33 + (a1 * c1 + a2 * c2);
+    const double f = 1.0 - kk * kap;
+    const double M11 = f * (P22 / det) - kk * a1 * a1, M12 = f * (-P12 / det) - kk * a1 * a2;
+    const double M22 = f * (P11 / det) - kk * a2 * a2;
+    const double detM = M11 * M22 - M12 * M12;
+    float p0x = 0.0f, p0y = 0.0f, rho = -1.0f, sl = 0.0f;
+    if (kk * s33 < 0.999 && detM > 0.0 && M11 > 0.0) {
+      const double q0 = (M22 * a1 - M12 * a2) / detM, q1 = (M11 * a2 - M12 * a1) / detM;  // M^-1 a
+      p0x = (float)(kk * q0);
+      p0y = (float)(kk * q1);
+      rho = round_up_f32(sqrt(kk + kk * kk * (a1 * q0 + a2 * q1)) * (1.0 + 1e-3));
+      sl = round_up_f32(sqrt(0.5 * (M11 + M22 + sqrt((M11 - M22) * (M11 - M22) + 4.0 * M12 * M12))));
+    }
+    cn.c1 = make_float4((float)e1[0], (float)e1[2], (float)e2[0], (float)e2[1]);
+    cn.c2 = make_float4((float)e2[2], p0x, p0y, (float)M11);
+    cn.c3 = make_float4((float)M12, (float)M22, rho, sl);
+  }
   // cone of the rays that can reach alpha >= 1/255
   const double smax2 = fmax(fmax(s[0] * s[0], s[1] * s[1]), s[2] * s[2]);
   const double lam = smax2 / (g.r * g.r) + P.dilation * (kPi / (double)H) * (kPi / (double)H);
@@ -303,12 +327,12 @@ __device__ inline bool sph_item(const Geo& g, const Cam& cam, const Cov3& cv, co
   const int B = P.tile;
   const int ntx = W / B, nty = H / B;
   if (!(sb < 1.0)) {
-    cn = make_float4((float)m[0], (float)m[1], (float)m[2], (float)kPi);
+    cn.c0 = make_float4((float)m[0], (float)m[1], (float)m[2], (float)kPi);
     rr = Rect{0, (uint16_t)ntx, 0, (uint16_t)nty};
     return true;
   }
   const double beta = asin(sb);
-  cn = make_float4((float)m[0], (float)m[1], (float)m[2], round_up_f32(beta));
+  cn.c0 = make_float4((float)m[0], (float)m[1], (float)m[2], round_up_f32(beta));
   const double thc = atan2(-g.mu[1], g.rho);
   const double Hd = (double)H, Wd = (double)W;
   const double vlo = Hd / 2.0 - (Hd / kPi) * (thc + beta) - 1e-2, vhi = Hd / 2.0 - (Hd / kPi) * (thc - beta) + 1e-2;
@@ -357,7 +381,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
                                                          Rec* __restrict__ rec, Rect* __restrict__ rect,
                                                          uint32_t* __restrict__ count, uint32_t* __restrict__ dkey,
                                                          float* __restrict__ depth_out, odgs_status* __restrict__ status,
-                                                         SphRec* __restrict__ srec, float4* __restrict__ cone) {
+                                                         SphRec* __restrict__ srec, SphCull* __restrict__ cone) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < n;
   const int64_t ii = live ? i : 0;
@@ -412,7 +436,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
       if constexpr (SPH) {
         // spherical footprint (ERP views only)
         SphRec sr;
-        float4 cn;
+        SphCull cn;
         kept = (p_min < 0.0) && finite && sph_item(g, cam, cv, s, W, H, P, p_min, o, rgb, sr, cn, rr);
         if (kept) {
           cnt = (uint32_t)rr.ncols * (uint32_t)rr.nrows;
@@ -852,10 +876,10 @@ hipError_t launch_preprocess(const odgs_plan* p, const float* means, const float
   float* depth = ws_ptr<float>(ws, p->off_depth);
   odgs_status* status = ws_ptr<odgs_status>(ws, p->off_status);
   SphRec* srec = nullptr;
-  float4* cone = nullptr;
+  SphCull* cone = nullptr;
   if (plan_spherical(p)) {
     srec = ws_ptr<SphRec>(ws, p->off_srec);
-    cone = ws_ptr<float4>(ws, p->off_cone);
+    cone = ws_ptr<SphCull>(ws, p->off_cone);
     const int entries = vt.dir_base[vt.n_views];
     hipLaunchKernelGGL(dir_table_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, st, vt,
                        ws_ptr<double2>(ws, p->off_dirs));

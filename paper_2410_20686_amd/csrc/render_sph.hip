@@ -6,9 +6,10 @@
 // d of its ray (from the per-view ray table, rounded once to float), and a Gaussian's exponent is
 // -qh / D with t1 = u1 . d, t2 = u2 . d, h = w . d, qh = t1^2 + t2^2, D = h^2 + k2 qh (the maximum
 // of the 3D Gaussian along the ray, see SphRec); it reaches the pixel iff h > 0 and
-// p_min D + qh <= 0.  While staging, a record's quadrant mask comes from its cone (mu^, beta): a
-// quadrant is skipped when the angle between its centre ray and mu^ exceeds beta plus the
-// quadrant's angular radius.
+// p_min D + qh <= 0.  While staging, a record's quadrant mask comes from its culling data
+// (SphCull): a quadrant is skipped when the angle between its centre ray and mu^ exceeds the cone
+// half-angle beta plus the quadrant's angular radius, or when the disk that holds the gnomonic
+// images of the quadrant's rays misses the item's gnomonic ellipse.
 //
 // Backward: per accepted (Gaussian, wavefront) the 13 gradient values (mu^ (3), Sigma~ (6),
 // opacity, rgb) are summed over each 16-lane row by a 16-slot DPP butterfly and over rows by the
@@ -74,9 +75,9 @@ __device__ inline void sph_stage_init(SphStage<TILE, BATCH>& S, const double2* _
 // order-preserving list of the entries whose cone reaches its quadrant.
 template <int TILE, int BATCH>
 __device__ inline void sph_stage_batch(SphStage<TILE, BATCH>& S, const uint32_t* __restrict__ pair_items,
-                                       const SphRec* __restrict__ rec, const float4* __restrict__ cone, uint32_t first,
-                                       int dir, int cnt, float qrad, int (&nq)[SphStage<TILE, BATCH>::NQ],
-                                       const float* __restrict__ depth) {
+                                       const SphRec* __restrict__ rec, const SphCull* __restrict__ cull,
+                                       uint32_t first, int dir, int cnt, float qrad,
+                                       int (&nq)[SphStage<TILE, BATCH>::NQ], const float* __restrict__ depth) {
   using St = SphStage<TILE, BATCH>;
   const int t = threadIdx.x, ln = t & (kWave - 1), wv = t >> 6;
   const uint64_t below = ln == 0 ? 0ull : (~0ull >> (kWave - ln));
@@ -94,15 +95,32 @@ __device__ inline void sph_stage_batch(SphStage<TILE, BATCH>& S, const uint32_t*
       S.s3[e] = r.s3;
       S.sid[e] = item;
       if (depth) S.dep[e] = depth[item];
-      const float4 c = cone[item];
-      // hit iff angle(quadrant centre, mu^) <= beta + qrad; the 1e-5 slack covers the float
+      const SphCull cu = cull[item];
+      const float4 c = cu.c0;
+      // cone: hit iff angle(quadrant centre, mu^) <= beta + qrad; the 1e-5 slack covers the float
       // rounding of the dot product and of the cosine
       const float lim = c.w + qrad >= 3.14159f ? -2.0f : cosf(c.w + qrad) - 1e-5f;
+      const float cq = cosf(qrad), sq = sinf(qrad);
 #pragma unroll
       for (int q = 0; q < St::NQ; ++q) {
         const float3 d = S.qdir[q];
-        const float dot = fmaf(d.z, c.z, fmaf(d.y, c.y, d.x * c.x));
-        m |= dot >= lim ? (1u << q) : 0u;
+        const float sd = fmaf(d.z, c.z, fmaf(d.y, c.y, d.x * c.x));  // cos of the centre's angle to mu^
+        bool hit = sd >= lim;
+        // ellipse: every ray of the quadrant is within qrad of the centre ray, hence at most
+        // gamma_max = gamma_c + qrad from mu^, and the gnomonic map stretches distances by at most
+        // sec^2(gamma_max) there: the images lie within r_q = qrad sec^2(gamma_max) of the
+        // centre's image p_c.  The quadrant is kept iff that disk can meet the ellipse:
+        // (p_c - p0)^T M (p_c - p0) <= (rho + sqrt(lambda_max) r_q)^2 (1e-3 relative slack).
+        const float cmax = fmaf(sd, cq, -sqrtf(fmaxf(0.0f, fmaf(-sd, sd, 1.0f))) * sq);  // cos(gamma_max)
+        if (hit && cu.c3.z > 0.0f && cmax > 0.05f) {
+          const float inv = 1.0f / sd;
+          const float px = fmaf(d.z, cu.c1.y, d.x * cu.c1.x) * inv - cu.c2.y;
+          const float py = fmaf(d.z, cu.c2.x, fmaf(d.y, cu.c1.w, d.x * cu.c1.z)) * inv - cu.c2.z;
+          const float qv = fmaf(cu.c2.w * px, px, py * fmaf(2.0f * cu.c3.x, px, cu.c3.y * py));
+          const float rr = fmaf(cu.c3.w, qrad / (cmax * cmax), cu.c3.z);
+          hit = qv <= rr * rr * 1.001f + 1e-6f;
+        }
+        m |= hit ? (1u << q) : 0u;
       }
     }
     uint32_t within[St::NQ];
@@ -153,7 +171,7 @@ __device__ inline bool sph_eval(const float4& a, const float4& b, const float4& 
 template <int TILE, int BATCH, bool DEPTH>
 __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items,
-    const SphRec* __restrict__ rec, const float4* __restrict__ cone, const double2* __restrict__ dirs,
+    const SphRec* __restrict__ rec, const SphCull* __restrict__ cull, const double2* __restrict__ dirs,
     float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
     float bg0, float bg1, float bg2, const float* __restrict__ depth, float* __restrict__ out_depth) {
   using St = SphStage<TILE, BATCH>;
@@ -180,7 +198,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
     if (__syncthreads_count(done) == N) break;
     const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
     int nq[St::NQ];
-    sph_stage_batch<TILE, BATCH>(S, pair_items, rec, cone, base, 1, cnt, qrad, nq, DEPTH ? depth : nullptr);
+    sph_stage_batch<TILE, BATCH>(S, pair_items, rec, cull, base, 1, cnt, qrad, nq, DEPTH ? depth : nullptr);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
       if (__builtin_amdgcn_ballot_w64(!done) == 0ull) break;  // uniform: every pixel has finished
@@ -243,7 +261,7 @@ __device__ inline float row_reduce16(const float (&g)[16], int lane) {
 template <int TILE, int BATCH>
 __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items,
-    const SphRec* __restrict__ rec, const float4* __restrict__ cone, const double2* __restrict__ dirs,
+    const SphRec* __restrict__ rec, const SphCull* __restrict__ cull, const double2* __restrict__ dirs,
     const float* __restrict__ ws_T, const int32_t* __restrict__ ws_last, const float* __restrict__ dL_drgb,
     float* __restrict__ g2d, float bg0, float bg1, float bg2) {
   using St = SphStage<TILE, BATCH>;
@@ -295,7 +313,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
     }
     int nq[St::NQ];
     // entry e is list position end - 1 - e (back to front)
-    sph_stage_batch<TILE, BATCH>(S, pair_items, rec, cone, rg.x + end - 1, -1, cnt, qrad, nq, nullptr);
+    sph_stage_batch<TILE, BATCH>(S, pair_items, rec, cull, rg.x + end - 1, -1, cnt, qrad, nq, nullptr);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
       const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);
@@ -373,7 +391,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
 template <int TILE, int BATCH>
 struct SphFwdRun {
   static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
-                  const SphRec* rec, const float4* cone, const double2* dirs, float* out_rgb, float* out_T, float* wT,
+                  const SphRec* rec, const SphCull* cone, const double2* dirs, float* out_rgb, float* out_T, float* wT,
                   int32_t* wl, const float* depth, float* out_depth, hipStream_t st) {
     if (out_depth)
       hipLaunchKernelGGL((render_sph_fwd_kernel<TILE, BATCH, true>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges,
@@ -389,7 +407,7 @@ struct SphFwdRun {
 template <int TILE, int BATCH>
 struct SphBwdRun {
   static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
-                  const SphRec* rec, const float4* cone, const double2* dirs, const float* wT, const int32_t* wl,
+                  const SphRec* rec, const SphCull* cone, const double2* dirs, const float* wT, const int32_t* wl,
                   const float* dL, float* g2d, hipStream_t st) {
     hipLaunchKernelGGL((render_sph_bwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items,
                        rec, cone, dirs, wT, wl, dL, g2d, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
@@ -419,7 +437,7 @@ hipError_t launch_render_sph_fwd(const odgs_plan* p, void* ws, float* out_rgb, f
   if (tiles == 0) return hipSuccess;
   if (!sph_dispatch<SphFwdRun>(p->s.tile, p->s.batch, p, tiles, vt, ws_ptr<uint2>(ws, p->off_ranges),
                                ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]), ws_ptr<SphRec>(ws, p->off_srec),
-                               ws_ptr<float4>(ws, p->off_cone), ws_ptr<double2>(ws, p->off_dirs), out_rgb, out_T,
+                               ws_ptr<SphCull>(ws, p->off_cone), ws_ptr<double2>(ws, p->off_dirs), out_rgb, out_T,
                                ws_ptr<float>(ws, p->off_T), ws_ptr<int32_t>(ws, p->off_last),
                                ws_ptr<float>(ws, p->off_depth), out_depth, st))
     return hipErrorInvalidValue;
@@ -432,7 +450,7 @@ hipError_t launch_render_sph_bwd(const odgs_plan* p, void* ws, const float* dL_d
   if (tiles == 0) return hipSuccess;
   if (!sph_dispatch<SphBwdRun>(p->s.tile, p->s.batch_bwd, p, tiles, vt, ws_ptr<uint2>(ws, p->off_ranges),
                                ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]), ws_ptr<SphRec>(ws, p->off_srec),
-                               ws_ptr<float4>(ws, p->off_cone), ws_ptr<double2>(ws, p->off_dirs),
+                               ws_ptr<SphCull>(ws, p->off_cone), ws_ptr<double2>(ws, p->off_dirs),
                                ws_ptr<float>(ws, p->off_T), ws_ptr<int32_t>(ws, p->off_last), dL_drgb,
                                ws_ptr<float>(ws, p->off_g2d), st))
     return hipErrorInvalidValue;

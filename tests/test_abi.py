@@ -53,9 +53,9 @@ def test_spherical_plan_layout(lib):
     offs = sorted(getattr(p, n) for n in B._OFFSETS)
     assert len(set(offs)) == len(offs) and all(o % 256 == 0 for o in offs)
     items = 2 * 12345
-    assert p.off_cone - p.off_srec >= 64 * items and p.off_dirs - p.off_cone >= 16 * items
+    assert p.off_cone - p.off_srec >= 64 * items and p.off_dirs - p.off_cone >= 64 * items
     assert p.ws_bytes - p.off_dirs >= 16 * (1024 + 512 + 64 + 32)
-    assert p.ws_bytes > q.ws_bytes + (4 * 4 + 64 + 16) * items
+    assert p.ws_bytes > q.ws_bytes + (4 * 4 + 64 + 64) * items
     # the spherical footprint is defined for equirectangular views and has no work counters
     with pytest.raises(B.OdgsError):
         B.odgs_plan_set_pinhole(p, 0, 100.0, 100.0, 32.0, 16.0)
