@@ -223,7 +223,11 @@ __device__ inline void stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __
       const uint32_t item = pair_items[first + dir * e];
       const Rec r = rec[item];
       S.s0[e] = r.r0;
-      S.s1[e] = r.r1;
+      // the fourth word (the half extent, needed only for the mask below) carries whether every
+      // pixel centre of the tile lies within W/2 - 1 of u: the seam wrap is then the identity,
+      // which the reverse compositor skips with a uniform branch
+      const float reach = fabsf((float)tx0 + 0.5f * (float)TILE - r.r0.x) + 0.5f * (float)TILE + 1.0f;
+      S.s1[e] = make_float4(r.r1.x, r.r1.y, r.r1.z, reach < half ? 1.0f : 0.0f);
       S.s2[e] = r.r2;
       S.sid[e] = item;
       if (depth) S.dep[e] = depth[item];
@@ -701,7 +705,11 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
       const float4 b = S.s1[k];
       const float dv = py - a.y;
       const float l1dv = a.w * dv, t2 = b.x * dv, t22 = t2 * t2;
-      const float dua = wrap_du(pxa - a.x, Wf, half), dub = wrap_du(pxb - a.x, Wf, half);
+      float dua = pxa - a.x, dub = pxb - a.x;
+      if (__builtin_amdgcn_readfirstlane(__float_as_int(b.w)) == 0) {  // uniform: the seam is within reach
+        dua = wrap_du(dua, Wf, half);
+        dub = wrap_du(dub, Wf, half);
+      }
       const float t1a = fmaf(a.z, dua, l1dv), t1b = fmaf(a.z, dub, l1dv);
       const float pa = -fmaf(t1a, t1a, t22), pb = -fmaf(t1b, t1b, t22);
       const bool oka = jrel < A.last && !(pa > 0.0f || pa < b.z);
