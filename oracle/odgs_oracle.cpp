@@ -252,6 +252,104 @@ struct Info {
   double beta;         // half-angle of the cone of rays that can reach alpha >= 1/255
 };
 
+// Angular extent of the rays that can reach alpha >= 1/255 under the spherical footprint,
+// through the tangent plane of mu^ (frame e1 east, e2 = mu^ x e1) in gnomonic coordinates
+// p = (d . e1, d . e2) / (d . mu^).  There m <= k^2 reads (1 - k^2 kappa) p^T P^-1 p <=
+// k^2 (1 + a . p)^2 with P, c, s33 the tangent, tangent-radial and radial blocks of Sigma~,
+// a = -P^-1 c and kappa = s33 - c^T P^-1 c: the ellipse (p - p0)^T M (p - p0) <= rho^2,
+// M = (1 - k^2 kappa) P^-1 - k^2 a a^T, p0 = k^2 M^-1 a, rho^2 = k^2 + k^4 a^T M^-1 a, whenever
+// k^2 s33 < 1.  Its bounding box (half-widths rho sqrt((M^-1)_ii), padded by 1e-3) is a
+// spherical quadrilateral whose edges are great-circle arcs: along such an arc the longitude is
+// monotonic, so the longitude range is that of the four corners; the latitude extremes are at
+// the corners or at an arc's highest (lowest) point when that lies on the arc; a pole inside the
+// box takes every longitude.  Returns false when the ellipse form does not apply.
+struct SphBox {
+  double sin_lo, sin_hi;    // range of sin(latitude) = -d_y
+  double dphi_lo, dphi_hi;  // longitude range relative to the mean's azimuth
+  bool north, south;        // a pole inside the box
+};
+
+bool sph_box(const double m[3], const double C[6], double p_min, double phic, SphBox& bx) {
+  auto sym = [&](const double* x, const double* y) {
+    return x[0] * (C[0] * y[0] + C[1] * y[1] + C[2] * y[2]) + x[1] * (C[1] * y[0] + C[3] * y[1] + C[4] * y[2]) +
+           x[2] * (C[2] * y[0] + C[4] * y[1] + C[5] * y[2]);
+  };
+  const double rh = std::sqrt(m[0] * m[0] + m[2] * m[2]);
+  const double e1[3] = {m[2] / rh, 0.0, -m[0] / rh};
+  const double e2[3] = {m[1] * e1[2] - m[2] * e1[1], m[2] * e1[0] - m[0] * e1[2], m[0] * e1[1] - m[1] * e1[0]};
+  const double P11 = sym(e1, e1), P12 = sym(e1, e2), P22 = sym(e2, e2);
+  const double c1 = sym(e1, m), c2 = sym(e2, m), s33 = sym(m, m);
+  const double det = P11 * P22 - P12 * P12;
+  const double a1 = -(P22 * c1 - P12 * c2) / det, a2 = -(P11 * c2 - P12 * c1) / det;
+  const double kk = -2.0 * p_min;
+  const double f = 1.0 - kk * (s33 + (a1 * c1 + a2 * c2));
+  const double M11 = f * (P22 / det) - kk * a1 * a1, M12 = f * (-P12 / det) - kk * a1 * a2;
+  const double M22 = f * (P11 / det) - kk * a2 * a2;
+  const double detM = M11 * M22 - M12 * M12;
+  if (!(kk * s33 < 0.999 && detM > 0.0 && M11 > 0.0)) return false;
+  const double q0 = (M22 * a1 - M12 * a2) / detM, q1 = (M11 * a2 - M12 * a1) / detM;
+  const double p0[2] = {kk * q0, kk * q1};
+  const double rho2 = kk + kk * kk * (a1 * q0 + a2 * q1);
+  const double hx = std::sqrt(rho2 * M22 / detM) * (1.0 + 1e-3), hy = std::sqrt(rho2 * M11 / detM) * (1.0 + 1e-3);
+  // poles: gnomonic image inside the box
+  bx.north = bx.south = false;
+  for (int sgn = -1; sgn <= 1; sgn += 2) {  // north = (0, -1, 0), south = (0, 1, 0)
+    const double sdot = sgn * m[1];
+    if (!(sdot > 0.0)) continue;
+    const double px = sgn * e1[1] / sdot, py = sgn * e2[1] / sdot;
+    if (std::fabs(px - p0[0]) <= hx && std::fabs(py - p0[1]) <= hy) (sgn < 0 ? bx.north : bx.south) = true;
+  }
+  double D[4][3];
+  const double sx[4] = {-1.0, 1.0, 1.0, -1.0}, sy[4] = {-1.0, -1.0, 1.0, 1.0};
+  bx.sin_lo = 2.0;
+  bx.sin_hi = -2.0;
+  bx.dphi_lo = 10.0;
+  bx.dphi_hi = -10.0;
+  for (int k = 0; k < 4; ++k) {
+    const double px = p0[0] + sx[k] * hx, py = p0[1] + sy[k] * hy;
+    double nrm2 = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      D[k][j] = m[j] + px * e1[j] + py * e2[j];
+      nrm2 += D[k][j] * D[k][j];
+    }
+    const double nrm = std::sqrt(nrm2);
+    for (int j = 0; j < 3; ++j) D[k][j] /= nrm;
+    bx.sin_lo = std::min(bx.sin_lo, -D[k][1]);
+    bx.sin_hi = std::max(bx.sin_hi, -D[k][1]);
+    double dp = std::atan2(D[k][0], D[k][2]) - phic;
+    if (dp > M_PI) dp -= 2.0 * M_PI;
+    if (dp < -M_PI) dp += 2.0 * M_PI;
+    bx.dphi_lo = std::min(bx.dphi_lo, dp);
+    bx.dphi_hi = std::max(bx.dphi_hi, dp);
+  }
+  // highest / lowest point of each edge's great circle, when it lies on the edge
+  for (int k = 0; k < 4; ++k) {
+    const double* A = D[k];
+    const double* Bv = D[(k + 1) % 4];
+    const double n[3] = {A[1] * Bv[2] - A[2] * Bv[1], A[2] * Bv[0] - A[0] * Bv[2], A[0] * Bv[1] - A[1] * Bv[0]};
+    const double nn = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+    if (!(nn > 0.0)) continue;
+    for (int sgn = -1; sgn <= 1; sgn += 2) {  // towards north (0, -1, 0), then south (0, 1, 0)
+      // projection of the pole direction onto the circle's plane
+      double v[3] = {-(sgn * n[1]) * n[0] / nn, sgn - (sgn * n[1]) * n[1] / nn, -(sgn * n[1]) * n[2] / nn};
+      const double vn = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      if (!(vn > 0.0)) continue;
+      for (int j = 0; j < 3; ++j) v[j] /= vn;
+      const double t1 = (A[1] * v[2] - A[2] * v[1]) * n[0] + (A[2] * v[0] - A[0] * v[2]) * n[1] +
+                        (A[0] * v[1] - A[1] * v[0]) * n[2];
+      const double t2 = (v[1] * Bv[2] - v[2] * Bv[1]) * n[0] + (v[2] * Bv[0] - v[0] * Bv[2]) * n[1] +
+                        (v[0] * Bv[1] - v[1] * Bv[0]) * n[2];
+      if (t1 >= 0.0 && t2 >= 0.0) {
+        bx.sin_lo = std::min(bx.sin_lo, -v[1]);
+        bx.sin_hi = std::max(bx.sin_hi, -v[1]);
+      }
+    }
+  }
+  if (bx.north) bx.sin_hi = 1.0;
+  if (bx.south) bx.sin_lo = -1.0;
+  return true;
+}
+
 template <typename S>
 void project(const S m[3], const S s[3], const S q[4], const S& o, const double* shg, int64_t sh_stride,
              int K, const Camera& cam, const Settings& st, Proj<S>& out, Info& info) {
@@ -474,6 +572,30 @@ void project(const S m[3], const S s[3], const S q[4], const S& o, const double*
     }
     const double beta = std::asin(sb);
     info.beta = beta;
+    const double mh[3] = {info.mu[0] / info.r, info.mu[1] / info.r, info.mu[2] / info.r};
+    SphBox bx;
+    if (sph_box(mh, info.scov, info.p_min, val(phi), bx)) {
+      // the box of the gnomonic ellipse (tighter than the cone for anisotropic footprints)
+      const double vlo = Hd / 2.0 - (Hd / pi) * std::asin(std::min(1.0, bx.sin_hi)) - 1e-2;
+      const double vhi = Hd / 2.0 - (Hd / pi) * std::asin(std::max(-1.0, bx.sin_lo)) + 1e-2;
+      const double rlo = std::max(0.0, std::floor(vlo / B)), rhi = std::min((double)(nty - 1), std::floor(vhi / B));
+      info.row0 = (int)rlo;
+      info.nrows = (int)(rhi - rlo + 1.0);
+      if (info.nrows <= 0) { info.cull = CULL_EMPTY; return; }
+      const double uu = val(out.u);
+      const double clo = std::floor((uu + (Wd / (2.0 * pi)) * bx.dphi_lo - 1e-2) / B);
+      const double chi = std::floor((uu + (Wd / (2.0 * pi)) * bx.dphi_hi + 1e-2) / B);
+      if (bx.north || bx.south || !(chi - clo + 1.0 < (double)ntx)) {
+        info.col0 = 0;
+        info.ncols = ntx;
+      } else {
+        long long c0 = (long long)clo % ntx;
+        if (c0 < 0) c0 += ntx;
+        info.col0 = (int)c0;
+        info.ncols = (int)(chi - clo + 1.0);
+      }
+      return;
+    }
     const double vlo = Hd / 2.0 - (Hd / pi) * (thc + beta) - 1e-2, vhi = Hd / 2.0 - (Hd / pi) * (thc - beta) + 1e-2;
     const double rlo = std::max(0.0, std::floor(vlo / B)), rhi = std::min((double)(nty - 1), std::floor(vhi / B));
     info.row0 = (int)rlo;

@@ -260,6 +260,84 @@ __device__ inline void sph_cov(const Geo& g, const Cam& cam, const Cov3& cv, int
   }
 }
 
+// Latitude / longitude range of the bounding box of the item's gnomonic ellipse (see sph_item):
+// the box is a spherical quadrilateral of great-circle arcs, so the longitude range is that of
+// its corners (longitude is monotonic along a great circle that misses the poles) and the
+// latitude extremes are at the corners or at an edge's highest or lowest point when that lies
+// on the edge; a pole whose gnomonic image is inside the box takes every longitude.
+struct LatLonBox {
+  double sin_lo, sin_hi, dphi_lo, dphi_hi;
+  bool north, south;
+};
+
+__device__ inline void gnomonic_box(const double m[3], const double e1[3], const double e2[3], double p0x, double p0y,
+                                    double hx, double hy, double phic, LatLonBox& bx) {
+  bx.north = bx.south = false;
+  // north pole (0, -1, 0), south pole (0, 1, 0)
+  if (-m[1] > 0.0) {
+    const double px = -e1[1] / -m[1], py = -e2[1] / -m[1];
+    bx.north = fabs(px - p0x) <= hx && fabs(py - p0y) <= hy;
+  }
+  if (m[1] > 0.0) {
+    const double px = e1[1] / m[1], py = e2[1] / m[1];
+    bx.south = fabs(px - p0x) <= hx && fabs(py - p0y) <= hy;
+  }
+  double D[4][3];
+  const double sx[4] = {-1.0, 1.0, 1.0, -1.0}, sy[4] = {-1.0, -1.0, 1.0, 1.0};
+  bx.sin_lo = 2.0;
+  bx.sin_hi = -2.0;
+  bx.dphi_lo = 10.0;
+  bx.dphi_hi = -10.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double px = p0x + sx[k] * hx, py = p0y + sy[k] * hy;
+    double nrm2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      D[k][j] = m[j] + px * e1[j] + py * e2[j];
+      nrm2 += D[k][j] * D[k][j];
+    }
+    const double nrm = sqrt(nrm2);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) D[k][j] /= nrm;
+    bx.sin_lo = fmin(bx.sin_lo, -D[k][1]);
+    bx.sin_hi = fmax(bx.sin_hi, -D[k][1]);
+    double dp = atan2(D[k][0], D[k][2]) - phic;
+    if (dp > kPi) dp -= 2.0 * kPi;
+    if (dp < -kPi) dp += 2.0 * kPi;
+    bx.dphi_lo = fmin(bx.dphi_lo, dp);
+    bx.dphi_hi = fmax(bx.dphi_hi, dp);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double* A = D[k];
+    const double* Bv = D[(k + 1) & 3];
+    const double n[3] = {A[1] * Bv[2] - A[2] * Bv[1], A[2] * Bv[0] - A[0] * Bv[2], A[0] * Bv[1] - A[1] * Bv[0]};
+    const double nn = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+    if (!(nn > 0.0)) continue;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const double sg = h == 0 ? -1.0 : 1.0;  // towards the north pole, then the south pole
+      // the pole direction projected onto the edge's great-circle plane
+      double v[3] = {-(sg * n[1]) * n[0] / nn, sg - (sg * n[1]) * n[1] / nn, -(sg * n[1]) * n[2] / nn};
+      const double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      if (!(vn > 0.0)) continue;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) v[j] /= vn;
+      const double t1 = (A[1] * v[2] - A[2] * v[1]) * n[0] + (A[2] * v[0] - A[0] * v[2]) * n[1] +
+                        (A[0] * v[1] - A[1] * v[0]) * n[2];
+      const double t2 = (v[1] * Bv[2] - v[2] * Bv[1]) * n[0] + (v[2] * Bv[0] - v[0] * Bv[2]) * n[1] +
+                        (v[0] * Bv[1] - v[1] * Bv[0]) * n[2];
+      if (t1 >= 0.0 && t2 >= 0.0) {
+        bx.sin_lo = fmin(bx.sin_lo, -v[1]);
+        bx.sin_hi = fmax(bx.sin_hi, -v[1]);
+      }
+    }
+  }
+  if (bx.north) bx.sin_hi = 1.0;
+  if (bx.south) bx.sin_lo = -1.0;
+}
+
 // Spherical footprint of one kept ERP item: the float record (tangent frame e1 east, e2 = mu^ x e1;
 // P, c, s33 the tangent, tangent-radial and radial blocks of Sigma~; (l0, l1; 0, l2) the factor
 // of P^-1 / 2; u1 = l0 e1 + l1 e2, u2 = l2 e2, w = mu^ - (P^-1 c)_1 e1 - (P^-1 c)_2 e2,
@@ -296,6 +374,8 @@ __device__ inline bool sph_item(const Geo& g, const Cam& cam, const Cov3& cv, co
   out.s1 = make_float4((float)u2[1], (float)u2[2], (float)w[0], (float)w[1]);
   out.s2 = make_float4((float)w[2], (float)k2, o, (float)p_min);
   out.s3 = make_float4(rgb[0], rgb[1], rgb[2], 0.0f);
+  bool ell = false;
+  double ep0x = 0.0, ep0y = 0.0, ehx = 0.0, ehy = 0.0;  // the ellipse's centre and bounding-box half widths
   // Gnomonic ellipse of the rays that can reach alpha >= 1/255: with g = (d . e1, d . e2),
   // s = d . mu^, p = g / s, m <= k^2 reads (1 - k^2 kappa) p^T P^-1 p <= k^2 (1 + a . p)^2
   // (a = -P^-1 c, kappa = s33 - c^T P^-1 c), an ellipse when k^2 s33 < 1 (the ellipsoid stays in
@@ -309,11 +389,17 @@ __device__ inline bool sph_item(const Geo& g, const Cam& cam, const Cov3& cv, co
     const double M22 = f * (P11 / det) - kk * a2 * a2;
     const double detM = M11 * M22 - M12 * M12;
     float p0x = 0.0f, p0y = 0.0f, rho = -1.0f, sl = 0.0f;
-    if (kk * s33 < 0.999 && detM > 0.0 && M11 > 0.0) {
+    ell = kk * s33 < 0.999 && detM > 0.0 && M11 > 0.0;
+    if (ell) {
       const double q0 = (M22 * a1 - M12 * a2) / detM, q1 = (M11 * a2 - M12 * a1) / detM;  // M^-1 a
-      p0x = (float)(kk * q0);
-      p0y = (float)(kk * q1);
-      rho = round_up_f32(sqrt(kk + kk * kk * (a1 * q0 + a2 * q1)) * (1.0 + 1e-3));
+      const double rho2 = kk + kk * kk * (a1 * q0 + a2 * q1);
+      ep0x = kk * q0;
+      ep0y = kk * q1;
+      ehx = sqrt(rho2 * M22 / detM) * (1.0 + 1e-3);
+      ehy = sqrt(rho2 * M11 / detM) * (1.0 + 1e-3);
+      p0x = (float)ep0x;
+      p0y = (float)ep0y;
+      rho = round_up_f32(sqrt(rho2) * (1.0 + 1e-3));
       sl = round_up_f32(sqrt(0.5 * (M11 + M22 + sqrt((M11 - M22) * (M11 - M22) + 4.0 * M12 * M12))));
     }
     cn.c1 = make_float4((float)e1[0], (float)e1[2], (float)e2[0], (float)e2[1]);
@@ -335,6 +421,28 @@ __device__ inline bool sph_item(const Geo& g, const Cam& cam, const Cov3& cv, co
   cn.c0 = make_float4((float)m[0], (float)m[1], (float)m[2], round_up_f32(beta));
   const double thc = atan2(-g.mu[1], g.rho);
   const double Hd = (double)H, Wd = (double)W;
+  if (ell) {
+    // tile rectangle from the ellipse's bounding box (tighter than the cone for anisotropic
+    // footprints)
+    LatLonBox bx;
+    gnomonic_box(m, e1, e2, ep0x, ep0y, ehx, ehy, atan2(g.mu[0], g.mu[2]), bx);
+    const double vlo = Hd / 2.0 - (Hd / kPi) * asin(fmin(1.0, bx.sin_hi)) - 1e-2;
+    const double vhi = Hd / 2.0 - (Hd / kPi) * asin(fmax(-1.0, bx.sin_lo)) + 1e-2;
+    const double rlo = fmax(0.0, floor(vlo / B)), rhi = fmin((double)(nty - 1), floor(vhi / B));
+    const int nrows = (int)(rhi - rlo + 1.0);
+    if (nrows <= 0) return false;
+    int col0 = 0, ncols = ntx;
+    const double clo = floor((g.u + (Wd / (2.0 * kPi)) * bx.dphi_lo - 1e-2) / B);
+    const double chi = floor((g.u + (Wd / (2.0 * kPi)) * bx.dphi_hi + 1e-2) / B);
+    if (!bx.north && !bx.south && chi - clo + 1.0 < (double)ntx) {
+      long long c0 = (long long)clo % ntx;
+      if (c0 < 0) c0 += ntx;
+      col0 = (int)c0;
+      ncols = (int)(chi - clo + 1.0);
+    }
+    rr = Rect{(uint16_t)col0, (uint16_t)ncols, (uint16_t)rlo, (uint16_t)nrows};
+    return true;
+  }
   const double vlo = Hd / 2.0 - (Hd / kPi) * (thc + beta) - 1e-2, vhi = Hd / 2.0 - (Hd / kPi) * (thc - beta) + 1e-2;
   const double rlo = fmax(0.0, floor(vlo / B)), rhi = fmin((double)(nty - 1), floor(vhi / B));
   const int nrows = (int)(rhi - rlo + 1.0);

@@ -11,14 +11,14 @@ from tests._util import settings
 pytestmark = pytest.mark.gpu
 
 
-def _setup():
+def _setup(**kw):
     import torch
     from paper_2410_20686_amd.rasterizer import Rasterizer, TrainStep
     sc = scenes.roaming_scene(6007, 3, seed=51)
     cams = scenes.uneven_cameras(3, seed=51, sizes=((128, 64), (256, 128), (512, 256)))
     t = G.to_gpu(sc, cams)
     wh = [tuple(int(x) for x in r) for r in cams.wh]
-    rast = Rasterizer(sc.n, 3, wh, settings(), pair_capacity=4 * sc.n * len(wh))
+    rast = Rasterizer(sc.n, 3, wh, settings(**kw), pair_capacity=8 * sc.n * len(wh))
     dL = torch.from_numpy(scenes.upstream_gradient(cams, 1051)).cuda()
     return sc, cams, t, rast, TrainStep(rast, t[:5], t[5], dL)
 
@@ -39,9 +39,10 @@ def _compare(a, b):
                          {k: g.cpu().numpy() for k, g in zip(names, b[1])}, rtol=1e-4, floor=1e-5)
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("footprint", ["affine", "spherical"])
+def test_graph_replays_match_eager(footprint):
     import torch
-    sc, cams, t, rast, step = _setup()
+    sc, cams, t, rast, step = _setup(footprint=footprint)
     step.run()
     ref = _snapshot(step)
     step.capture()
