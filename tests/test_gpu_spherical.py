@@ -98,3 +98,11 @@ def test_backward_matches_oracle(case):
     else:
         rep = G.assert_grads_close(res["grads"], ref)
     print(name, rep)
+
+
+@pytest.mark.parametrize("tile", [8, 32])
+def test_backward_other_tiles(tile):
+    """Tile 8: one wavefront per tile; tile 32: sixteen wavefronts sharing one set of LDS
+    accumulators (atomics) instead of a slot set per wavefront."""
+    name, sc, cams, st = CASES[0]
+    test_backward_matches_oracle((name, sc, cams, dict(st, tile=tile)))
