@@ -15,6 +15,7 @@
 // wavefronts with LDS float atomics, and reach global memory with one float atomic per
 // (Gaussian, tile, quantity).
 // One launch covers all views of a step: the grid spans the global tile ids of every view.
+#include <type_traits>
 #include <utility>
 
 #include "common.h"
@@ -206,8 +207,9 @@ __device__ inline uint32_t group_mask(uint32_t m) {
   }
 }
 
+// Returns whether the seam wrap is the identity for every staged entry (uniform).
 template <int TILE, int BATCH, int PX = 1>
-__device__ inline void stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __restrict__ pair_items,
+__device__ inline bool stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __restrict__ pair_items,
                                    const Rec* __restrict__ rec, uint32_t first, int dir, int cnt, int tx0, int ty0,
                                    float Wf, float half, int (&nq)[Stage<TILE, BATCH, PX>::NQ],
                                    const float* __restrict__ depth = nullptr) {
@@ -216,6 +218,7 @@ __device__ inline void stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __
   const uint64_t below = ln == 0 ? 0ull : (~0ull >> (kWave - ln));
 #pragma unroll
   for (int q = 0; q < St::NQ; ++q) nq[q] = 0;
+  bool nowrap = true, all_nowrap = true;
   for (int r0 = 0; r0 < cnt; r0 += St::N) {
     const int e = r0 + t;
     uint32_t m = 0;
@@ -224,9 +227,9 @@ __device__ inline void stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __
       const Rec r = rec[item];
       S.s0[e] = r.r0;
       // the fourth word (the half extent, needed only for the mask below) carries whether every
-      // pixel centre of the tile lies within W/2 - 1 of u: the seam wrap is then the identity,
-      // which the reverse compositor skips with a uniform branch
+      // pixel centre of the tile lies within W/2 - 1 of u: the seam wrap is then the identity
       const float reach = fabsf((float)tx0 + 0.5f * (float)TILE - r.r0.x) + 0.5f * (float)TILE + 1.0f;
+      nowrap = nowrap && reach < half;
       S.s1[e] = make_float4(r.r1.x, r.r1.y, r.r1.z, reach < half ? 1.0f : 0.0f);
       S.s2[e] = r.r2;
       S.sid[e] = item;
@@ -262,8 +265,9 @@ __device__ inline void stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __
       if ((m >> q) & 1u) S.list[q][nq[q] + pre + (int)within[q]] = (uint8_t)e;
       nq[q] += tot;
     }
-    __syncthreads();
+    all_nowrap = __syncthreads_and(nowrap) != 0;
   }
+  return all_nowrap;
 }
 
 // COUNT: also record the per-pixel work counters read by odgs_debug_pixel_counts (a separate
@@ -298,14 +302,17 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
     if (__syncthreads_count(done) == N) break;
     const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
     int nq[St::NQ];
-    stage_batch<TILE, BATCH>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq, DEPTH ? depth : nullptr);
+    const bool nowrap =
+        stage_batch<TILE, BATCH>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq, DEPTH ? depth : nullptr);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
+    // one list walk, instantiated without the seam wrap for batches where it is the identity
+    auto walk = [&](auto wrapc) {
     for (int i = 0; i < n; ++i) {
       if (__builtin_amdgcn_ballot_w64(!done) == 0ull) break;  // uniform: every pixel has finished
       const int k = S.list[wq][i];
       const float4 a = S.s0[k];
       const float4 b = S.s1[k];
-      const float du = wrap_du(px - a.x, Wf, half);
+      const float du = decltype(wrapc)::value ? wrap_du(px - a.x, Wf, half) : px - a.x;
       const float dv = py - a.y;
       const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
       const float power = -fmaf(t1, t1, t2 * t2);
@@ -331,6 +338,11 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
         ncontrib += acc ? 1 : 0;
       }
     }
+    };
+    if (nowrap)
+      walk(std::false_type{});
+    else
+      walk(std::true_type{});
   }
   const int64_t plane = (int64_t)W * H;
   const int64_t pix = (int64_t)y * W + x;
