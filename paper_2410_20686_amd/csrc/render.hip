@@ -297,7 +297,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
   const uint2 rg = ranges[g];
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f;
   int last = 0, ncontrib = 0, nev = 0, lastev = 0;
-  bool done = false;
+  int done = 0;  // an int rather than a bool: the ballots below then compile to one compare
   for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
     if (__syncthreads_count(done) == N) break;
     const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
     // one list walk, instantiated without the seam wrap for batches where it is the identity
     auto walk = [&](auto wrapc) {
     for (int i = 0; i < n; ++i) {
-      if (__builtin_amdgcn_ballot_w64(!done) == 0ull) break;  // uniform: every pixel has finished
+      if (__builtin_amdgcn_ballot_w64(done == 0) == 0ull) break;  // uniform: every pixel has finished
       const int k = S.list[wq][i];
       const float4 a = S.s0[k];
       const float4 b = S.s1[k];
@@ -317,14 +317,14 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
       const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
       const float power = -fmaf(t1, t1, t2 * t2);
       if (COUNT) nev += done ? 0 : 1;
-      const bool ok = !done && !(power > 0.0f || power < b.z);
+      const bool ok = done == 0 && !(power > 0.0f || power < b.z);
       if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
       float alpha = b.y * __expf(power);
       alpha = alpha > kAlphaMax ? kAlphaMax : alpha;
       const float Tn = T * (1.0f - alpha);
       const bool stop = ok && Tn < kTStop;
       const bool acc = ok && !(Tn < kTStop);
-      done = done || stop;
+      done = stop ? 1 : done;
       const float4 c = S.s2[k];
       const float w = acc ? alpha * T : 0.0f;
       C0 = fmaf(w, c.x, C0);
