@@ -193,7 +193,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
   const uint2 rg = ranges[g];
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, Dsum = 0.0f;
   int last = 0;
-  bool done = false;
+  int done = 0;  // an int rather than a bool: the ballots below then compile to one compare
   for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
     if (__syncthreads_count(done) == N) break;
     const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
@@ -201,19 +201,19 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
     sph_stage_batch<TILE, BATCH>(S, pair_items, rec, cull, base, 1, cnt, qrad, nq, DEPTH ? depth : nullptr);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
-      if (__builtin_amdgcn_ballot_w64(!done) == 0ull) break;  // uniform: every pixel has finished
+      if (__builtin_amdgcn_ballot_w64(done == 0) == 0ull) break;  // uniform: every pixel has finished
       const int k = S.list[wq][i];
       const float4 c = S.s2[k];
       float power, t1, t2, h, D, qh;
       const bool hit = sph_eval(S.s0[k], S.s1[k], c, d, power, t1, t2, h, D, qh);
-      const bool ok = !done && hit;
+      const bool ok = done == 0 && hit;
       if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
       float alpha = c.z * __expf(power);
       alpha = alpha > kAlphaMax ? kAlphaMax : alpha;
       const float Tn = T * (1.0f - alpha);
       const bool stop = ok && Tn < kTStop;
       const bool acc = ok && !(Tn < kTStop);
-      done = done || stop;
+      done = stop ? 1 : done;
       const float4 col = S.s3[k];
       const float w = acc ? alpha * T : 0.0f;
       C0 = fmaf(w, col.x, C0);
