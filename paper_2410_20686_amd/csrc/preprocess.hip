@@ -76,30 +76,30 @@ __device__ inline void sh_basis(double x, double y, double z, double* Y) {
   }
 }
 
-// Gradient of each basis polynomial w.r.t. (x, y, z) (before projection onto the sphere).
+// sum_k w_k grad Y_k at (x, y, z): the gradient of each basis polynomial (before projection onto
+// the sphere) weighted and summed on the fly, without materialising the K x 3 table.
 template <int K>
-__device__ inline void sh_basis_grad(double x, double y, double z, double (*dY)[3]) {
-  dY[0][0] = dY[0][1] = dY[0][2] = 0.0;
+__device__ inline void sh_grad_dot(double x, double y, double z, const double* w, double g[3]) {
+  g[0] = g[1] = g[2] = 0.0;
   if constexpr (K > 1) {
-    dY[1][0] = 0.0; dY[1][1] = kY1; dY[1][2] = 0.0;
-    dY[2][0] = 0.0; dY[2][1] = 0.0; dY[2][2] = kY1;
-    dY[3][0] = kY1; dY[3][1] = 0.0; dY[3][2] = 0.0;
+    g[0] += kY1 * w[3];
+    g[1] += kY1 * w[1];
+    g[2] += kY1 * w[2];
   }
   if constexpr (K > 4) {
-    dY[4][0] = kY2a * y; dY[4][1] = kY2a * x; dY[4][2] = 0.0;
-    dY[5][0] = 0.0; dY[5][1] = kY2a * z; dY[5][2] = kY2a * y;
-    dY[6][0] = -2.0 * kY2b * x; dY[6][1] = -2.0 * kY2b * y; dY[6][2] = 4.0 * kY2b * z;
-    dY[7][0] = kY2a * z; dY[7][1] = 0.0; dY[7][2] = kY2a * x;
-    dY[8][0] = 2.0 * kY2c * x; dY[8][1] = -2.0 * kY2c * y; dY[8][2] = 0.0;
+    g[0] += kY2a * (y * w[4] + z * w[7]) + x * (2.0 * kY2c * w[8] - 2.0 * kY2b * w[6]);
+    g[1] += kY2a * (x * w[4] + z * w[5]) - y * (2.0 * kY2b * w[6] + 2.0 * kY2c * w[8]);
+    g[2] += kY2a * (y * w[5] + x * w[7]) + 4.0 * kY2b * z * w[6];
     if constexpr (K > 9) {
       const double xx = x * x, yy = y * y, zz = z * z;
-      dY[9][0] = 6.0 * kY3a * x * y; dY[9][1] = 3.0 * kY3a * (xx - yy); dY[9][2] = 0.0;
-      dY[10][0] = kY3b * y * z; dY[10][1] = kY3b * x * z; dY[10][2] = kY3b * x * y;
-      dY[11][0] = -2.0 * kY3c * x * y; dY[11][1] = kY3c * (4.0 * zz - xx - 3.0 * yy); dY[11][2] = 8.0 * kY3c * y * z;
-      dY[12][0] = -6.0 * kY3d * x * z; dY[12][1] = -6.0 * kY3d * y * z; dY[12][2] = kY3d * (6.0 * zz - 3.0 * xx - 3.0 * yy);
-      dY[13][0] = kY3c * (4.0 * zz - 3.0 * xx - yy); dY[13][1] = -2.0 * kY3c * x * y; dY[13][2] = 8.0 * kY3c * x * z;
-      dY[14][0] = 2.0 * kY3e * x * z; dY[14][1] = -2.0 * kY3e * y * z; dY[14][2] = kY3e * (xx - yy);
-      dY[15][0] = 3.0 * kY3a * (xx - yy); dY[15][1] = -6.0 * kY3a * x * y; dY[15][2] = 0.0;
+      g[0] += 6.0 * kY3a * x * y * w[9] + kY3b * y * z * w[10] - 2.0 * kY3c * x * y * w[11] -
+              6.0 * kY3d * x * z * w[12] + kY3c * (4.0 * zz - 3.0 * xx - yy) * w[13] + 2.0 * kY3e * x * z * w[14] +
+              3.0 * kY3a * (xx - yy) * w[15];
+      g[1] += 3.0 * kY3a * (xx - yy) * w[9] + kY3b * x * z * w[10] + kY3c * (4.0 * zz - xx - 3.0 * yy) * w[11] -
+              6.0 * kY3d * y * z * w[12] - 2.0 * kY3c * x * y * w[13] - 2.0 * kY3e * y * z * w[14] -
+              6.0 * kY3a * x * y * w[15];
+      g[2] += kY3b * x * y * w[10] + 8.0 * kY3c * y * z * w[11] + kY3d * (6.0 * zz - 3.0 * xx - 3.0 * yy) * w[12] +
+              8.0 * kY3c * x * z * w[13] + kY3e * (xx - yy) * w[14];
     }
   }
 }
@@ -630,12 +630,82 @@ struct DensAcc {
   double tau_min, tau_max;
 };
 
-// Last step of both adjoints: dL/dSigma -> scales and (normalised) quaternion, then the writes.
+// Adjoint of one view's colour = max(0, sum_k sh_k Y_k(dir) + 0.5), dir = (m - c) / |m - c|:
+// adds dL/dsh to gsh (float accumulators) and the direction path to gm.
 template <int K>
+__device__ inline void colour_adjoint(const double m[3], const Cam& cam, const float* coef, const double gcol[3],
+                                      float* gsh, double gm[3]) {
+  double d[3], dist;
+  view_dir(m, cam, d, dist);
+  double Y[K];
+  sh_basis<K>(d[0], d[1], d[2], Y);
+  double w[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) w[k] = 0.0;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc = acc + (double)coef[k * 3 + ch] * Y[k];
+    acc = acc + 0.5;
+    if (!(acc > 0.0)) continue;
+    const double gc = gcol[ch];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      gsh[k * 3 + ch] += (float)(gc * Y[k]);
+      w[k] += gc * (double)coef[k * 3 + ch];
+    }
+  }
+  double gdir[3];
+  sh_grad_dot<K>(d[0], d[1], d[2], w, gdir);
+  const double dd = gdir[0] * d[0] + gdir[1] * d[1] + gdir[2] * d[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gm[k] += (gdir[k] - d[k] * dd) / dist;
+}
+
+// Colour part of the adjoint, one thread per Gaussian, run before the geometry part: dL/dsh
+// (written) and the direction path of dL/dmean (written; the geometry part adds to it).  The
+// per-item colour gradients sit at offset `off` of records of `stride` values.
+template <int K>
+__global__ __launch_bounds__(256) void colour_bwd_kernel(int64_t n, const float* __restrict__ means,
+                                                         const float* __restrict__ sh, const float* __restrict__ cams,
+                                                         ViewTable vt, const uint32_t* __restrict__ count,
+                                                         const float* __restrict__ g2d, int stride, int off,
+                                                         float* __restrict__ d_means, float* __restrict__ d_sh) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double m[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) m[k] = (double)means[k * n + i];
+  float coef[K * 3];
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) coef[k] = sh[(int64_t)k * n + i];
+  float gsh[K * 3];
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) gsh[k] = 0.0f;
+  double gm[3] = {0.0, 0.0, 0.0};
+  for (int v = 0; v < vt.n_views; ++v) {
+    const int64_t item = (int64_t)v * n + i;
+    if (count[item] == 0) continue;
+    const double gcol[3] = {(double)g2d[item * stride + off], (double)g2d[item * stride + off + 1],
+                            (double)g2d[item * stride + off + 2]};
+    if (gcol[0] == 0.0 && gcol[1] == 0.0 && gcol[2] == 0.0) continue;
+    Cam cam;
+    load_cam(cams, v, cam);
+    colour_adjoint<K>(m, cam, coef, gcol, gsh, gm);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) d_means[k * n + i] = (float)gm[k];
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = gsh[k];
+}
+
+// Last step of both geometry adjoints: dL/dSigma -> scales and (normalised) quaternion, then the
+// writes; the mean gradient is added to the colour part already in d_means.
 __device__ inline void write_param_grads(int64_t n, int64_t i, const double s[3], const Cov3& cv, const double gm[3],
-                                         const double gS[9], double go, const double* gsh, float* __restrict__ d_means,
+                                         const double gS[9], double go, float* __restrict__ d_means,
                                          float* __restrict__ d_scales, float* __restrict__ d_quats,
-                                         float* __restrict__ d_opac, float* __restrict__ d_sh) {
+                                         float* __restrict__ d_opac) {
   // Sigma = M M^T, M = Rq diag(s): dM = 2 dSigma M (dSigma symmetric).
   double dM[9];
 #pragma unroll
@@ -668,12 +738,10 @@ __device__ inline void write_param_grads(int64_t n, int64_t i, const double s[3]
   d_quats[3 * n + i] = (float)((gz - z * dot) * iq);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    d_means[k * n + i] = (float)gm[k];
+    d_means[k * n + i] = (float)((double)d_means[k * n + i] + gm[k]);
     d_scales[k * n + i] = (float)gs[k];
   }
   d_opac[i] = (float)go;
-#pragma unroll
-  for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = (float)gsh[k];
 }
 
 template <int K, bool STATS>
@@ -692,18 +760,12 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
   for (int k = 0; k < 3; ++k) s[k] = (double)scales[k * n + i];
 #pragma unroll
   for (int k = 0; k < 4; ++k) q[k] = (double)quats[k * n + i];
-  float coef[K * 3];
-#pragma unroll
-  for (int k = 0; k < K * 3; ++k) coef[k] = sh[(int64_t)k * n + i];
   Cov3 cv;
   cov3(s, q, cv);
 
   double gm[3] = {0.0, 0.0, 0.0};
   double gS[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // dL/dSigma (symmetric)
   double go = 0.0;
-  double gsh[K * 3];
-#pragma unroll
-  for (int k = 0; k < K * 3; ++k) gsh[k] = 0.0;
   double st_grad = 0.0, st_tau = 0.0;
   int st_count = 0;
 
@@ -805,38 +867,10 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     // mu = R m + t  =>  dm = R^T dmu
 #pragma unroll
     for (int k = 0; k < 3; ++k) gm[k] += cam.R[k] * dmu[0] + cam.R[3 + k] * dmu[1] + cam.R[6 + k] * dmu[2];
-    go += g[5];
-    // colour = max(0, sum_k sh_k Y_k(dir) + 0.5), dir = (m - c) / |m - c|
-    double d[3], dist;
-    view_dir(m, cam, d, dist);
-    double Y[K];
-    sh_basis<K>(d[0], d[1], d[2], Y);
-    double dY[K][3];
-    sh_basis_grad<K>(d[0], d[1], d[2], dY);
-    double gdir[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      double acc = 0.0;
-#pragma unroll
-      for (int k = 0; k < K; ++k) acc = acc + (double)coef[k * 3 + ch] * Y[k];
-      acc = acc + 0.5;
-      if (!(acc > 0.0)) continue;
-      const double gc = g[6 + ch];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        gsh[k * 3 + ch] += gc * Y[k];
-        const double w = gc * (double)coef[k * 3 + ch];
-        gdir[0] += w * dY[k][0];
-        gdir[1] += w * dY[k][1];
-        gdir[2] += w * dY[k][2];
-      }
-    }
-    const double dd = gdir[0] * d[0] + gdir[1] * d[1] + gdir[2] * d[2];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) gm[k] += (gdir[k] - d[k] * dd) / dist;
+    go += g[5];  // the colour entries g[6..8] went to colour_bwd_kernel
   }
 
-  write_param_grads<K>(n, i, s, cv, gm, gS, go, gsh, d_means, d_scales, d_quats, d_opac, d_sh);
+  write_param_grads(n, i, s, cv, gm, gS, go, d_means, d_scales, d_quats, d_opac);
   if (STATS && st_count > 0) {
     dacc.grad_sum[i] = (float)((double)dacc.grad_sum[i] + st_grad);
     dacc.tau_sum[i] = (float)((double)dacc.tau_sum[i] + st_tau);
@@ -867,17 +901,11 @@ __global__ __launch_bounds__(256) void preprocess_sph_bwd_kernel(
   for (int k = 0; k < 3; ++k) s[k] = (double)scales[k * n + i];
 #pragma unroll
   for (int k = 0; k < 4; ++k) q[k] = (double)quats[k * n + i];
-  float coef[K * 3];
-#pragma unroll
-  for (int k = 0; k < K * 3; ++k) coef[k] = sh[(int64_t)k * n + i];
   Cov3 cv;
   cov3(s, q, cv);
   double gm[3] = {0.0, 0.0, 0.0};
   double gS[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // dL/dSigma (symmetric)
   double go = 0.0;
-  double gsh[K * 3];
-#pragma unroll
-  for (int k = 0; k < K * 3; ++k) gsh[k] = 0.0;
   for (int v = 0; v < vt.n_views; ++v) {
     const int64_t item = (int64_t)v * n + i;
     if (count[item] == 0) continue;
@@ -926,37 +954,9 @@ __global__ __launch_bounds__(256) void preprocess_sph_bwd_kernel(
     for (int a = 0; a < 3; ++a) dmu[a] = (g[a] - mh[a] * dot) / r + mh[a] * gr;
 #pragma unroll
     for (int k = 0; k < 3; ++k) gm[k] += cam.R[k] * dmu[0] + cam.R[3 + k] * dmu[1] + cam.R[6 + k] * dmu[2];
-    go += g[9];
-    // colour = max(0, sum_k sh_k Y_k(dir) + 0.5), dir = (m - c) / |m - c|
-    double d[3], dist;
-    view_dir(m, cam, d, dist);
-    double Y[K];
-    sh_basis<K>(d[0], d[1], d[2], Y);
-    double dY[K][3];
-    sh_basis_grad<K>(d[0], d[1], d[2], dY);
-    double gdir[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      double acc = 0.0;
-#pragma unroll
-      for (int k = 0; k < K; ++k) acc = acc + (double)coef[k * 3 + ch] * Y[k];
-      acc = acc + 0.5;
-      if (!(acc > 0.0)) continue;
-      const double gcol = g[10 + ch];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        gsh[k * 3 + ch] += gcol * Y[k];
-        const double wk = gcol * (double)coef[k * 3 + ch];
-        gdir[0] += wk * dY[k][0];
-        gdir[1] += wk * dY[k][1];
-        gdir[2] += wk * dY[k][2];
-      }
-    }
-    const double dd = gdir[0] * d[0] + gdir[1] * d[1] + gdir[2] * d[2];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) gm[k] += (gdir[k] - d[k] * dd) / dist;
+    go += g[9];  // the colour entries g[10..12] went to colour_bwd_kernel
   }
-  write_param_grads<K>(n, i, s, cv, gm, gS, go, gsh, d_means, d_scales, d_quats, d_opac, d_sh);
+  write_param_grads(n, i, s, cv, gm, gS, go, d_means, d_scales, d_quats, d_opac);
 }
 
 Params make_params(const odgs_plan* p) {
@@ -1021,6 +1021,19 @@ hipError_t launch_preprocess_bwd(const odgs_plan* p, const float* means, const f
   const unsigned grid = (unsigned)((p->n + 255) / 256);
   const uint32_t* count = ws_ptr<uint32_t>(ws, p->off_count);
   float* g2d = ws_ptr<float>(ws, p->off_g2d);
+  // colour part first (writes d_sh and the colour path of d_means), then the geometry part,
+  // which adds to d_means and clears the consumed records
+  const int stride = p->g2d_stride, off = p->g2d_stride - 3;
+#define ODGS_COLB(KK)                                                                                              \
+  hipLaunchKernelGGL(colour_bwd_kernel<KK>, dim3(grid), dim3(256), 0, st, p->n, means, sh, cams, vt, count, g2d,   \
+                     stride, off, d_means, d_sh)
+  switch (p->sh_degree) {
+    case 0: ODGS_COLB(1); break;
+    case 1: ODGS_COLB(4); break;
+    case 2: ODGS_COLB(9); break;
+    default: ODGS_COLB(16); break;
+  }
+#undef ODGS_COLB
 #define ODGS_PREB(KK)                                                                                        \
   if (plan_spherical(p))                                                                                     \
     hipLaunchKernelGGL((preprocess_sph_bwd_kernel<KK>), dim3(grid), dim3(256), 0, st, p->n, means, scales,     \
