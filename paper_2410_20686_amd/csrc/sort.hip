@@ -294,11 +294,12 @@ __global__ __launch_bounds__(256) void item_offsets_kernel(const Rect* __restric
   }
 }
 
-// Pair-parallel emission: block b writes pairs [b * kEmitPairs, (b + 1) * kEmitPairs), one thread
-// per pair, so stores are coalesced whatever the items' sizes.  The block locates its items with
-// one binary search over the item offsets, stages them in LDS, and each thread finds its item by
-// a binary search in LDS.
-constexpr int kEmitPairs = 1024;
+// Pair-parallel emission: block b writes pairs [b * kEmitPairs, (b + 1) * kEmitPairs), four
+// consecutive pairs per thread, so stores are coalesced whatever the items' sizes.  The block
+// locates its items with one binary search over the item offsets, stages them in LDS, and each
+// thread finds the item of its first pair by a binary search in LDS.
+constexpr int kEmitRun = 4;  // consecutive pairs per thread
+constexpr int kEmitPairs = 256 * kEmitRun;
 
 __device__ inline int64_t upper_bound_u32(const uint32_t* a, int64_t n, uint32_t x) {
   int64_t lo = 0, hi = n;
@@ -343,21 +344,50 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restr
     s_ntx[t] = (uint16_t)(vt.W[v] / tile);
   }
   __syncthreads();
-  for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256) {
-    int lo = 0, hi = m;  // largest idx with s_off[idx] <= p
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_off[mid] <= p) lo = mid;
-      else hi = mid;
+  // each thread emits kEmitRun consecutive pairs: one search, then the rectangle is walked by
+  // increments (row-major, columns wrapping at the seam), and one 16-byte store per array
+  static_assert(kEmitPairs == 256 * kEmitRun && kEmitRun == 4, "four consecutive pairs per thread");
+  const uint32_t q = p0 + (uint32_t)(kEmitRun * threadIdx.x);
+  if (q >= p1) return;
+  int lo = 0, hi = m;  // largest idx with s_off[idx] <= q
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (s_off[mid] <= q) lo = mid;
+    else hi = mid;
+  }
+  Rect rr = s_rect[lo];
+  uint32_t ntx = s_ntx[lo];
+  uint32_t local = q - s_off[lo];
+  uint32_t r = local / rr.ncols, c = local - r * rr.ncols;
+  uint32_t key[kEmitRun], val[kEmitRun];
+#pragma unroll
+  for (int j = 0; j < kEmitRun; ++j) {
+    const uint32_t pj = q + (uint32_t)j;
+    // next item once this one's pairs are used up (items without pairs here are skipped)
+    while (lo + 1 < m && s_off[lo + 1] <= pj) {
+      ++lo;
+      rr = s_rect[lo];
+      ntx = s_ntx[lo];
+      r = 0;
+      c = 0;
     }
-    const Rect rr = s_rect[lo];
-    const uint32_t local = p - s_off[lo];
-    const uint32_t r = local / rr.ncols;
-    uint32_t col = rr.col0 + (local - r * rr.ncols);
-    const uint32_t ntx = s_ntx[lo];
+    uint32_t col = rr.col0 + c;
     if (col >= ntx) col -= ntx;
-    pkey[p] = s_tb[lo] + (uint32_t)(rr.row0 + r) * ntx + col;
-    pval[p] = s_item[lo];
+    key[j] = s_tb[lo] + (uint32_t)(rr.row0 + r) * ntx + col;
+    val[j] = s_item[lo];
+    if (++c == rr.ncols) {
+      c = 0;
+      ++r;
+    }
+  }
+  if (q + kEmitRun <= p1) {
+    *reinterpret_cast<uint4*>(pkey + q) = make_uint4(key[0], key[1], key[2], key[3]);
+    *reinterpret_cast<uint4*>(pval + q) = make_uint4(val[0], val[1], val[2], val[3]);
+  } else {
+    for (int j = 0; j < kEmitRun && q + (uint32_t)j < p1; ++j) {
+      pkey[q + j] = key[j];
+      pval[q + j] = val[j];
+    }
   }
 }
 
