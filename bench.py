@@ -76,7 +76,9 @@ def parse():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=0, help="forward LDS batch (0: library default)")
     ap.add_argument("--batch-bwd", type=int, default=0, help="reverse LDS batch (0: library default)")
-    ap.add_argument("--n", type=int, default=500_000)
+    ap.add_argument("--n", type=int, default=0, help="Gaussian count (0: the workload's own)")
+    ap.add_argument("--workload", default="M", choices=("M", "cfg0", "cfg1", "cfg2", "cfg3", "cfg4"),
+                    help="M is the metric's workload; the others are context runs (same JSON fields)")
     ap.add_argument("--autotune", action="store_true", help="pick the tile and batch sizes with the autotuner first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a known-size reference "
@@ -149,7 +151,7 @@ def main():
     from paper_2410_20686_amd.rasterizer import Rasterizer, TrainStep
 
     t0 = time.time()
-    sc, cams, st = scenes.config("M", n=args.n)
+    sc, cams, st = scenes.config(args.workload, n=args.n or None)
     st = dict(st, tile=args.tile, batch=args.batch, batch_bwd=args.batch_bwd)
     wh = [tuple(int(x) for x in r) for r in cams.wh]
     V = len(wh)
@@ -297,9 +299,9 @@ def main():
         O.backward(sc, cams, st, gpix, mode=32, pix=pix)
         dt = time.time() - tc
         cpu = dict(value=round(len(pix) / 1e6 / dt, 6), unit="MP/s", cores=O.num_threads(), kind="oracle",
-                   sample="%d random pixels (%d per view) of workload M, brute-force forward + backward in FP32 "
+                   sample="%d random pixels (%d per view) of workload %s, brute-force forward + backward in FP32 "
                           "decision mode, each call including its own per-Gaussian projection of all views; %.1f s"
-                          % (len(pix), args.cpu_pixels_per_view, dt))
+                          % (len(pix), args.cpu_pixels_per_view, args.workload, dt))
         log("cpu baseline", cpu)
 
     value = mp_per_step / (ms_batched / 1e3)
@@ -307,9 +309,11 @@ def main():
         "metric": METRIC, "value": round(value, 2), "unit": "MP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_batched, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "M: 500k Gaussians (roaming: 70%% in 50 blobs, 30%% shell r 2-20, SH degree 3), "
-                               "%d views 2048x1024, fwd+bwd, all views batched in one HIP graph per step" % V,
-                   "gaussians": sc.n, "views": V, "width": wh[0][0], "height": wh[0][1], "sh_degree": 3,
+        "config": {"workload": ("M: 500k Gaussians (roaming: 70%% in 50 blobs, 30%% shell r 2-20, SH degree 3), "
+                                "%d views 2048x1024, fwd+bwd, all views batched in one HIP graph per step" % V)
+                   if args.workload == "M" else "%s (context run, not the metric's workload): %d Gaussians, "
+                   "views %s" % (args.workload, sc.n, sorted(set(wh))),
+                   "gaussians": sc.n, "views": V, "width": wh[0][0], "height": wh[0][1], "sh_degree": sc.sh_degree,
                    "tile": st["tile"], "batch": rast.plan.s.batch, "batch_bwd": rast.plan.s.batch_bwd,
                    "pairs": status["n_pairs"],
                    "autotuned": tuned is not None},
