@@ -501,7 +501,9 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   const float dl0 = dimg[pix], dl1 = dimg[plane + pix], dl2 = dimg[2 * plane + pix];
   float T = ws_T[gp];
   const int last = ws_last[gp];
-  float S0 = T * bg0, S1 = T * bg1, S2 = T * bg2;  // colour of everything behind, incl. background
+  // dL/dC . (colour of everything behind, incl. background): the only way the colour behind a
+  // Gaussian enters its alpha gradient, so one scalar replaces the three channels
+  float DS = T * fmaf(dl0, bg0, fmaf(dl1, bg1, dl2 * bg2));
   // largest `last` of the wavefront (uniform) and of the workgroup
   int wmax = last;
 #pragma unroll
@@ -554,12 +556,10 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       T = ok ? T * inv_om : T;  // transmittance in front of this Gaussian
       const float w = alpha * T;
       const float4 c = S.s2[k];
-      const float dL_da =
-          dl0 * fmaf(c.x, T, -S0 * inv_om) + dl1 * fmaf(c.y, T, -S1 * inv_om) + dl2 * fmaf(c.z, T, -S2 * inv_om);
+      const float dc = fmaf(dl0, c.x, fmaf(dl1, c.y, dl2 * c.z));  // dL/dC . colour
+      const float dL_da = fmaf(dc, T, -DS * inv_om);
       const float wk = ok ? w : 0.0f;
-      S0 = fmaf(c.x, wk, S0);
-      S1 = fmaf(c.y, wk, S1);
-      S2 = fmaf(c.z, wk, S2);
+      DS = fmaf(dc, wk, DS);
       const float dpow = (ok && !clamped) ? dL_da * alpha : 0.0f;
       float gq[9];
       // with w = Sigma^-1 d = 2 L^T (t1, t2): d power / d(u, v) = w, d power / d Sigma_2D = w w^T / 2
@@ -610,7 +610,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
 
 // Reverse compositing state of one pixel (back to front from its last contributor).
 struct BwdPixel {
-  float T, S0, S1, S2, dl0, dl1, dl2;
+  float T, DS, dl0, dl1, dl2;  // DS = dL/dC . (colour of everything behind, incl. background)
   int last;
 };
 
@@ -626,12 +626,10 @@ __device__ inline void bwd_pixel_step(BwdPixel& P, bool ok, float power, float t
   const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
   P.T = ok ? P.T * inv_om : P.T;  // transmittance in front of this Gaussian
   const float w = alpha * P.T;
-  const float dL_da = P.dl0 * fmaf(c.x, P.T, -P.S0 * inv_om) + P.dl1 * fmaf(c.y, P.T, -P.S1 * inv_om) +
-                      P.dl2 * fmaf(c.z, P.T, -P.S2 * inv_om);
+  const float dc = fmaf(P.dl0, c.x, fmaf(P.dl1, c.y, P.dl2 * c.z));  // dL/dC . colour
+  const float dL_da = fmaf(dc, P.T, -P.DS * inv_om);
   const float wk = ok ? w : 0.0f;
-  P.S0 = fmaf(c.x, wk, P.S0);
-  P.S1 = fmaf(c.y, wk, P.S1);
-  P.S2 = fmaf(c.z, wk, P.S2);
+  P.DS = fmaf(dc, wk, P.DS);
   const bool live = ok && !clamped;
   const float dpow = live ? dL_da * alpha : 0.0f;
   // with w = Sigma^-1 d = 2 L^T (t1, t2): d power / d(u, v) = w, d power / d Sigma_2D = w w^T / 2
@@ -685,8 +683,8 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
   B.T = ws_T[gp + 8];
   A.last = ws_last[gp];
   B.last = ws_last[gp + 8];
-  A.S0 = A.T * bg0, A.S1 = A.T * bg1, A.S2 = A.T * bg2;  // colour behind, incl. background
-  B.S0 = B.T * bg0, B.S1 = B.T * bg1, B.S2 = B.T * bg2;
+  A.DS = A.T * fmaf(A.dl0, bg0, fmaf(A.dl1, bg1, A.dl2 * bg2));  // the background behind everything
+  B.DS = B.T * fmaf(B.dl0, bg0, fmaf(B.dl1, bg1, B.dl2 * bg2));
   // largest `last` of the wavefront (uniform) and of the workgroup
   int wmax = max(A.last, B.last);
 #pragma unroll

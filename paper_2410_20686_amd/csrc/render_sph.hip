@@ -293,7 +293,8 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
   const float dl0 = dimg[pix], dl1 = dimg[plane + pix], dl2 = dimg[2 * plane + pix];
   float T = ws_T[gp];
   const int last = ws_last[gp];
-  float S0 = T * bg0, S1 = T * bg1, S2 = T * bg2;
+  // dL/dC . (colour of everything behind, incl. background), one scalar for the three channels
+  float DS = T * fmaf(dl0, bg0, fmaf(dl1, bg1, dl2 * bg2));
   int wmax = last;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
@@ -334,12 +335,10 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
       T = ok ? T * inv_om : T;  // transmittance in front of this Gaussian
       const float w = alpha * T;
       const float4 col = S.s3[k];
-      const float dL_da = dl0 * fmaf(col.x, T, -S0 * inv_om) + dl1 * fmaf(col.y, T, -S1 * inv_om) +
-                          dl2 * fmaf(col.z, T, -S2 * inv_om);
+      const float dc = fmaf(dl0, col.x, fmaf(dl1, col.y, dl2 * col.z));  // dL/dC . colour
+      const float dL_da = fmaf(dc, T, -DS * inv_om);
       const float wk = ok ? w : 0.0f;
-      S0 = fmaf(col.x, wk, S0);
-      S1 = fmaf(col.y, wk, S1);
-      S2 = fmaf(col.z, wk, S2);
+      DS = fmaf(dc, wk, DS);
       const bool live = ok && !clamped;
       const float dpow = live ? dL_da * alpha : 0.0f;
       // z = (2 / D) (h (t1 u1 + t2 u2) - qh w), zero on lanes that do not contribute
