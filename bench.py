@@ -34,7 +34,7 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 #   a test = one (pixel, list entry) evaluation of the Gaussian's exponent and footprint test;
 #   an accept = one (pixel, Gaussian) contribution.
 OPS_FWD_TEST, OPS_FWD_ACCEPT = 14, 14
-OPS_BWD_TEST, OPS_BWD_ACCEPT = 15, 50
+OPS_BWD_TEST, OPS_BWD_ACCEPT = 15, 42
 
 
 PROFILE = os.path.join(ROOT, "profiles", "render_kernels_M_500k_8x2048x1024.txt")
