@@ -48,9 +48,12 @@ __device__ inline float lane63(float v) { return __int_as_float(__builtin_amdgcn
 
 
 // Sums nine per-lane values over each 16-lane row in four DPP exchange steps (pairs (i, 15-i),
-// (i, 7-i), (i, 3-i), (i, i^1) inside the row; each step halves the slots a lane holds).  Lane i
-// ends with the row sum of value kRowSlot[i % 16] (none where the table says 15).
-constexpr uint64_t kRowSlot = 0xFFF8F765FF43F210ull;  // nibble i = value index held by row lane i
+// (i, 7-i), (i, 3-i), (i, i^1) inside the row).  Values 0..7 are transposed (each step halves the
+// slots a lane holds: value index = lane bits 3,2,1 read as 4*b3 + 2*b2 + b1 on even lanes); value
+// 8 is summed in place through the first three steps and takes the odd lanes in the last one.
+// Lane i ends with the row sum of value kRowSlot[i % 16] (none where the table says 15; value 8,
+// held by all eight odd lanes, is assigned to lane 1 only).
+constexpr uint64_t kRowSlot = 0xF7F6F5F4F3F2F180ull;  // nibble i = value index held by row lane i
 
 
 // Sum of a value over the eight lanes of an aligned 8-lane group (every lane gets the sum).
@@ -95,15 +98,17 @@ __device__ inline float red_finish(const float4& r0, const float4& r1) {
 }
 
 __device__ inline float row_reduce9(const float (&g)[9], bool b3, bool b2, bool b1, bool b0) {
-  float a[5];
+  float a[4];
 #pragma unroll
-  for (int j = 0; j < 5; ++j) a[j] = bfly<0x140>(g[j], j < 4 ? g[5 + j] : 0.0f, b3);  // row_mirror
-  float c[3];
+  for (int j = 0; j < 4; ++j) a[j] = bfly<0x140>(g[j], g[4 + j], b3);  // row_mirror
+  float s8 = g[8] + dpp_read<0x140>(g[8]);
+  float c[2];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) c[j] = bfly<0x141>(a[j], j < 2 ? a[3 + j] : 0.0f, b2);  // row_half_mirror
-  const float d0 = bfly<0x1B>(c[0], c[2], b1);                                         // quad_perm [3,2,1,0]
-  const float d1 = bfly<0x1B>(c[1], 0.0f, b1);
-  return bfly<0xB1>(d0, d1, b0);                                                        // quad_perm [1,0,3,2]
+  for (int j = 0; j < 2; ++j) c[j] = bfly<0x141>(a[j], a[2 + j], b2);  // row_half_mirror
+  s8 += dpp_read<0x141>(s8);
+  const float d = bfly<0x1B>(c[0], c[1], b1);                             // quad_perm [3,2,1,0]
+  s8 += dpp_read<0x1B>(s8);
+  return bfly<0xB1>(d, s8, b0);                                           // quad_perm [1,0,3,2]
 }
 
 
@@ -458,6 +463,44 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_fwd2_kernel(
   }
 }
 
+// Reverse compositing state of one pixel (back to front from its last contributor).
+struct BwdPixel {
+  float T, DS, dl0, dl1, dl2;  // DS = dL/dC . (colour of everything behind, incl. background)
+  int last;
+};
+
+// The shape values are accumulated per pixel without their constant factors, which are powers of
+// two (with h = Sigma^-1 d / 2 = L^T (t1, t2): d power / d(u, v) = 2 h, d power / d Sigma_2D = 2 h h^T,
+// whose off-diagonal slot takes both symmetric entries, 4 h_u h_v); multiplying the per-tile sums by
+// them once at the flush gives exactly the same floats.
+__device__ inline float g2d_flush_scale(int q) { return q == 3 ? 4.0f : (q < 5 ? 2.0f : 1.0f); }
+
+// One pixel's contribution of a Gaussian to the nine 2D gradients (added to gq when ADD, else
+// written, both before g2d_flush_scale), and the pixel's recursion step.  `ok`: the Gaussian
+// contributed to this pixel; t1 = l0 du + l1 dv, bxt2 = l2^2 dv.
+template <bool ADD>
+__device__ inline void bwd_pixel_step(BwdPixel& P, bool ok, float power, float t1, float bxt2, const float4& a,
+                                      const float4& b, const float4& c, float (&gq)[9]) {
+  const float G = __expf(power);
+  const float araw = b.y * G;
+  const bool live = ok && !(araw > kAlphaMax);  // contributes and unclamped: alpha depends on the inputs
+  // alpha = 0 where the Gaussian does not contribute, so its weight below is 0 without a select
+  const float alpha = ok ? fminf(araw, kAlphaMax) : 0.0f;
+  const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
+  P.T = ok ? P.T * inv_om : P.T;  // transmittance in front of this Gaussian
+  const float wk = alpha * P.T;
+  const float dc = fmaf(P.dl0, c.x, fmaf(P.dl1, c.y, P.dl2 * c.z));  // dL/dC . colour
+  const float dL_da = fmaf(dc, P.T, -P.DS * inv_om);
+  P.DS = fmaf(dc, wk, P.DS);
+  const float dla = live ? dL_da : 0.0f;
+  const float dpow = dla * alpha;
+  const float hx = a.z * t1, hy = fmaf(a.w, t1, bxt2);
+  const float g0 = dpow * hx, g1 = dpow * hy;
+  const float h[9] = {g0, g1, g0 * hx, g0 * hy, g1 * hy, dla * G, wk * P.dl0, wk * P.dl1, wk * P.dl2};
+#pragma unroll
+  for (int q = 0; q < 9; ++q) gq[q] = ADD ? gq[q] + h[q] : h[q];
+}
+
 // g2d layout: [items][9] = d/du, d/dv, d/dS_uu, d/dS_uv, d/dS_vv, d/dopacity, d/dr, d/dg,
 // d/db(colour), where Sigma_2D = [[S_uu, S_uv], [S_uv, S_vv]] (S_uv the shared off-diagonal).
 // Accumulating w.r.t. Sigma_2D rather than its inverse keeps the sums well scaled for very
@@ -498,14 +541,15 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   const int64_t pix = (int64_t)y * W + x;
   const int64_t gp = vt.pix_base[v] + pix;
   const float* dimg = dL_drgb + 3 * vt.pix_base[v];
-  const float dl0 = dimg[pix], dl1 = dimg[plane + pix], dl2 = dimg[2 * plane + pix];
-  float T = ws_T[gp];
-  const int last = ws_last[gp];
+  BwdPixel P;
+  P.dl0 = dimg[pix], P.dl1 = dimg[plane + pix], P.dl2 = dimg[2 * plane + pix];
+  P.T = ws_T[gp];
+  P.last = ws_last[gp];
   // dL/dC . (colour of everything behind, incl. background): the only way the colour behind a
   // Gaussian enters its alpha gradient, so one scalar replaces the three channels
-  float DS = T * fmaf(dl0, bg0, fmaf(dl1, bg1, dl2 * bg2));
+  P.DS = P.T * fmaf(P.dl0, bg0, fmaf(P.dl1, bg1, P.dl2 * bg2));
   // largest `last` of the wavefront (uniform) and of the workgroup
-  int wmax = last;
+  int wmax = P.last;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
   wmax = __builtin_amdgcn_readfirstlane(wmax);
@@ -544,35 +588,13 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       const float dv = py - a.y;
       const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
       const float power = -fmaf(t1, t1, t2 * t2);
-      const bool ok = jrel < last && !(power > 0.0f || power < b.z);
+      const bool ok = jrel < P.last && !(power > 0.0f || power < b.z);
       if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
       float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
       if (kSlots && pend) red_read(red[wq], lane, r0, r1);  // previous accepted entry's values
-      const float G = __expf(power);
-      float alpha = b.y * G;
-      const bool clamped = alpha > kAlphaMax;
-      alpha = clamped ? kAlphaMax : alpha;
-      const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
-      T = ok ? T * inv_om : T;  // transmittance in front of this Gaussian
-      const float w = alpha * T;
       const float4 c = S.s2[k];
-      const float dc = fmaf(dl0, c.x, fmaf(dl1, c.y, dl2 * c.z));  // dL/dC . colour
-      const float dL_da = fmaf(dc, T, -DS * inv_om);
-      const float wk = ok ? w : 0.0f;
-      DS = fmaf(dc, wk, DS);
-      const float dpow = (ok && !clamped) ? dL_da * alpha : 0.0f;
       float gq[9];
-      // with w = Sigma^-1 d = 2 L^T (t1, t2): d power / d(u, v) = w, d power / d Sigma_2D = w w^T / 2
-      const float wx = 2.0f * a.z * t1, wy = 2.0f * fmaf(a.w, t1, b.x * t2);
-      gq[0] = dpow * wx;
-      gq[1] = dpow * wy;
-      gq[2] = 0.5f * gq[0] * wx;
-      gq[3] = gq[0] * wy;
-      gq[4] = 0.5f * gq[1] * wy;
-      gq[5] = (ok && !clamped) ? dL_da * G : 0.0f;
-      gq[6] = wk * dl0;
-      gq[7] = wk * dl1;
-      gq[8] = wk * dl2;
+      bwd_pixel_step<false>(P, ok, power, t1, b.x * t2, a, b, c, gq);
       if constexpr (kSlots) {
         if (pend) {
           const float sj = red_finish(r0, r1);
@@ -602,43 +624,10 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       float s = acc[0][q][t];
 #pragma unroll
       for (int w = 1; w < NS; ++w) s += acc[w][q][t];
-      if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s);
+      if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s * g2d_flush_scale(q));
     }
     __syncthreads();
   }
-}
-
-// Reverse compositing state of one pixel (back to front from its last contributor).
-struct BwdPixel {
-  float T, DS, dl0, dl1, dl2;  // DS = dL/dC . (colour of everything behind, incl. background)
-  int last;
-};
-
-// One pixel's contribution of a Gaussian to the nine 2D gradients (added to gq when ADD, else
-// written), and the pixel's recursion step.  `ok`: the Gaussian contributed to this pixel.
-template <bool ADD>
-__device__ inline void bwd_pixel_step(BwdPixel& P, bool ok, float power, float t1, float t2, const float4& a,
-                                      const float4& b, const float4& c, float (&gq)[9]) {
-  const float G = __expf(power);
-  float alpha = b.y * G;
-  const bool clamped = alpha > kAlphaMax;
-  alpha = clamped ? kAlphaMax : alpha;
-  const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
-  P.T = ok ? P.T * inv_om : P.T;  // transmittance in front of this Gaussian
-  const float w = alpha * P.T;
-  const float dc = fmaf(P.dl0, c.x, fmaf(P.dl1, c.y, P.dl2 * c.z));  // dL/dC . colour
-  const float dL_da = fmaf(dc, P.T, -P.DS * inv_om);
-  const float wk = ok ? w : 0.0f;
-  P.DS = fmaf(dc, wk, P.DS);
-  const bool live = ok && !clamped;
-  const float dpow = live ? dL_da * alpha : 0.0f;
-  // with w = Sigma^-1 d = 2 L^T (t1, t2): d power / d(u, v) = w, d power / d Sigma_2D = w w^T / 2
-  const float wx = 2.0f * a.z * t1, wy = 2.0f * fmaf(a.w, t1, b.x * t2);
-  const float g0 = dpow * wx, g1 = dpow * wy;
-  const float h[9] = {g0, g1, 0.5f * g0 * wx, g0 * wy, 0.5f * g1 * wy, live ? dL_da * G : 0.0f,
-                      wk * P.dl0, wk * P.dl1, wk * P.dl2};
-#pragma unroll
-  for (int q = 0; q < 9; ++q) gq[q] = ADD ? gq[q] + h[q] : h[q];
 }
 
 // Reverse compositing with two pixels per lane (16x16 and 32x32 tiles): wavefront w owns quadrants
@@ -722,18 +711,20 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
       }
       const float t1a = fmaf(a.z, dua, l1dv), t1b = fmaf(a.z, dub, l1dv);
       const float pa = -fmaf(t1a, t1a, t22), pb = -fmaf(t1b, t1b, t22);
-      const bool oka = jrel < A.last && !(pa > 0.0f || pa < b.z);
-      const bool okb = jrel < B.last && !(pb > 0.0f || pb < b.z);
-      if (__builtin_amdgcn_ballot_w64(oka || okb) == 0ull) continue;  // uniform
+      const bool ina = !(pa > 0.0f || pa < b.z), inb = !(pb > 0.0f || pb < b.z);
+      const bool oka = jrel < A.last && ina, okb = jrel < B.last && inb;
+      // ballots of the single compares (each is its own lane mask) rather than of their conjunction
+      const uint64_t bala = __builtin_amdgcn_ballot_w64(jrel < A.last) & __builtin_amdgcn_ballot_w64(ina);
+      const uint64_t balb = __builtin_amdgcn_ballot_w64(jrel < B.last) & __builtin_amdgcn_ballot_w64(inb);
+      if ((bala | balb) == 0ull) continue;  // uniform
       const float4 c = S.s2[k];
+      const float bxt2 = b.x * t2;
       float gq[9];
-      const bool anya = __builtin_amdgcn_ballot_w64(oka) != 0ull;  // uniform
-      const bool anyb = __builtin_amdgcn_ballot_w64(okb) != 0ull;
-      if (anya) {
-        bwd_pixel_step<false>(A, oka, pa, t1a, t2, a, b, c, gq);
-        if (anyb) bwd_pixel_step<true>(B, okb, pb, t1b, t2, a, b, c, gq);
+      if (bala != 0ull) {
+        bwd_pixel_step<false>(A, oka, pa, t1a, bxt2, a, b, c, gq);
+        if (balb != 0ull) bwd_pixel_step<true>(B, okb, pb, t1b, bxt2, a, b, c, gq);
       } else {
-        bwd_pixel_step<false>(B, okb, pb, t1b, t2, a, b, c, gq);
+        bwd_pixel_step<false>(B, okb, pb, t1b, bxt2, a, b, c, gq);
       }
       const float rs = row_reduce9(gq, lane & 8, lane & 4, lane & 2, lane & 1);
       if constexpr (kSlots) {
@@ -751,7 +742,7 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
       float s = acc[0][q][t];
 #pragma unroll
       for (int w = 1; w < NS; ++w) s += acc[w][q][t];
-      if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s);
+      if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s * g2d_flush_scale(q));
     }
     __syncthreads();
   }
