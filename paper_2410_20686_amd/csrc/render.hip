@@ -302,9 +302,12 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
   const uint2 rg = ranges[g];
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f;
   int last = 0, ncontrib = 0, nev = 0, lastev = 0;
-  int done = 0;  // an int rather than a bool: the ballots below then compile to one compare
+  // 0 while the pixel composites, NaN once it has stopped: added to the exponent's sum of squares
+  // it makes the accept compare itself false for every later Gaussian (with 0 the sum is the same
+  // float), so the wavefront's ballots are of single compares
+  float qstop = 0.0f;
   for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
-    if (__syncthreads_count(done) == N) break;
+    if (__syncthreads_count(!(qstop == 0.0f)) == N) break;
     const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
     int nq[St::NQ];
     const bool nowrap =
@@ -313,25 +316,25 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
     // one list walk, instantiated without the seam wrap for batches where it is the identity
     auto walk = [&](auto wrapc) {
     for (int i = 0; i < n; ++i) {
-      if (__builtin_amdgcn_ballot_w64(done == 0) == 0ull) break;  // uniform: every pixel has finished
+      if (__builtin_amdgcn_ballot_w64(qstop == 0.0f) == 0ull) break;  // uniform: every pixel has finished
       const int k = S.list[wq][i];
       const float4 a = S.s0[k];
       const float4 b = S.s1[k];
       const float du = decltype(wrapc)::value ? wrap_du(px - a.x, Wf, half) : px - a.x;
       const float dv = py - a.y;
       const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
-      const float power = -fmaf(t1, t1, t2 * t2);
-      if (COUNT) nev += done ? 0 : 1;
-      const bool ok = done == 0 && !(power > 0.0f || power < b.z);
+      const float power = -fmaf(t1, t1, fmaf(t2, t2, qstop));
+      if (COUNT) nev += qstop == 0.0f ? 1 : 0;
+      // alpha >= 1/255 (power <= 0 always: a sum of squares; NaN once stopped)
+      const bool ok = power >= b.z;
       if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
-      float alpha = b.y * __expf(power);
-      alpha = alpha > kAlphaMax ? kAlphaMax : alpha;
+      const float alpha = fminf(b.y * __expf(power), kAlphaMax);
       const float Tn = T * (1.0f - alpha);
       const bool stop = ok && Tn < kTStop;
       const bool acc = ok && !(Tn < kTStop);
-      done = stop ? 1 : done;
+      qstop = stop ? __builtin_nanf("") : qstop;
       const float4 c = S.s2[k];
-      const float w = acc ? alpha * T : 0.0f;
+      const float w = (acc ? alpha : 0.0f) * T;  // (a select of the product compiles to a branch here)
       C0 = fmaf(w, c.x, C0);
       C1 = fmaf(w, c.y, C1);
       C2 = fmaf(w, c.z, C2);
@@ -376,8 +379,7 @@ struct FwdPixel {
 
 // One Gaussian's front-to-back step for one pixel (Eq. alphablending with the 3DGS constants).
 __device__ inline void fwd_pixel_step(FwdPixel& P, bool ok, float power, const float4& b, const float4& c, int pos) {
-  float alpha = b.y * __expf(power);
-  alpha = alpha > kAlphaMax ? kAlphaMax : alpha;
+  const float alpha = fminf(b.y * __expf(power), kAlphaMax);
   const float Tn = P.T * (1.0f - alpha);
   const bool stop = ok && Tn < kTStop;
   const bool acc = ok && !(Tn < kTStop);
@@ -496,9 +498,12 @@ __device__ inline void bwd_pixel_step(BwdPixel& P, bool ok, float power, float t
   const float dpow = dla * alpha;
   const float hx = a.z * t1, hy = fmaf(a.w, t1, bxt2);
   const float g0 = dpow * hx, g1 = dpow * hy;
-  const float h[9] = {g0, g1, g0 * hx, g0 * hy, g1 * hy, dla * G, wk * P.dl0, wk * P.dl1, wk * P.dl2};
+  // values 2..8 are products x_q y_q (fused into the running sums when adding)
+  const float x[7] = {g0, g0, g1, dla, wk, wk, wk}, y[7] = {hx, hy, hy, G, P.dl0, P.dl1, P.dl2};
+  gq[0] = ADD ? gq[0] + g0 : g0;
+  gq[1] = ADD ? gq[1] + g1 : g1;
 #pragma unroll
-  for (int q = 0; q < 9; ++q) gq[q] = ADD ? gq[q] + h[q] : h[q];
+  for (int q = 0; q < 7; ++q) gq[2 + q] = ADD ? fmaf(x[q], y[q], gq[2 + q]) : x[q] * y[q];
 }
 
 // g2d layout: [items][9] = d/du, d/dv, d/dS_uu, d/dS_uv, d/dS_vv, d/dopacity, d/dr, d/dg,

@@ -208,8 +208,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
       const bool hit = sph_eval(S.s0[k], S.s1[k], c, d, power, t1, t2, h, D, qh);
       const bool ok = done == 0 && hit;
       if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
-      float alpha = c.z * __expf(power);
-      alpha = alpha > kAlphaMax ? kAlphaMax : alpha;
+      const float alpha = fminf(c.z * __expf(power), kAlphaMax);
       const float Tn = T * (1.0f - alpha);
       const bool stop = ok && Tn < kTStop;
       const bool acc = ok && !(Tn < kTStop);
@@ -237,20 +236,34 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
   if (out_T) out_T[gp] = T;
 }
 
-// Sums sixteen per-lane values over each 16-lane row in four DPP exchange steps (partners
-// 15 - i, 7 - i, 3 - i, i ^ 1 inside the row); lane i ends with the row sum of value i % 16.
-__device__ inline float row_reduce16(const float (&g)[16], int lane) {
+// Sums thirteen per-lane values over each 16-lane row in four DPP exchange steps (partners
+// 15 - i, 7 - i, 3 - i, i ^ 1 inside the row).  Each step pairs the registers a lane holds, the lane
+// keeping one slot of each pair by a bit of its index, except that values 5, 6 and 7 (which have
+// no partner slot) are summed in place in the first step.  Lane i ends with the row sum of value
+// kSphRowSlot[i % 16] (none where the table says 15: the second copies of values 5, 6, 7).
+constexpr uint64_t kSphRowSlot = 0xFBF9FAC873516240ull;  // nibble i = value index held by row lane i
+
+__device__ inline float row_reduce13(const float (&g)[kNV], int lane) {
+#pragma clang fp contract(off)  // keeps the in-place sums single DPP adds (not an FMA with the product)
   const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
   float a[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) a[j] = bfly<0x140>(g[j], g[8 + j], b3);  // row_mirror
+  for (int j = 0; j < 5; ++j) a[j] = bfly<0x140>(g[j], g[8 + j], b3);  // row_mirror
+#pragma unroll
+  for (int j = 5; j < 8; ++j) a[j] = g[j] + dpp_read<0x140>(g[j]);
   float c[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) c[j] = bfly<0x141>(a[j], a[4 + j], b2);  // row_half_mirror
-  const float e0 = bfly<0x1B>(c[0], c[2], b1);                         // quad_perm [3,2,1,0]
-  const float e1 = bfly<0x1B>(c[1], c[3], b1);
-  return bfly<0xB1>(e0, e1, b0);                                       // quad_perm [1,0,3,2]
+  for (int j = 0; j < 4; ++j) c[j] = bfly<0x141>(a[2 * j], a[2 * j + 1], b2);  // row_half_mirror
+  const float e0 = bfly<0x1B>(c[0], c[1], b1);                                 // quad_perm [3,2,1,0]
+  const float e1 = bfly<0x1B>(c[2], c[3], b1);
+  return bfly<0xB1>(e0, e1, b0);                                               // quad_perm [1,0,3,2]
 }
+
+// The per-pixel values are accumulated without their constant factors (z / 2 in place of z, no
+// 1/2 on the diagonal): value q is multiplied by 2^e_q, e_q = bits 2q..2q+1 of kSphFlushExp, once
+// per (Gaussian, tile) at the flush, which gives exactly the same floats.
+constexpr uint32_t kSphFlushExp = 0x19A55u;  // e = 1,1,1, 1,2,2,1,2,1, 0,0,0,0
+__device__ inline float sph_flush_scale(int q) { return (float)(1u << ((kSphFlushExp >> (2 * q)) & 3u)); }
 
 // g2d layout [items][13]: d/dmu^ (3), d/dSigma~ (xx, xy, xz, yy, yz, zz; off-diagonals as one
 // shared variable), d/dopacity, d/d(r, g, b).  With A = Sigma~^-1 and the ray's closest approach
@@ -328,48 +341,35 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
       const bool ok = jrel < last && hit;
       if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
       const float G = __expf(power);
-      float alpha = c.z * G;
-      const bool clamped = alpha > kAlphaMax;
-      alpha = clamped ? kAlphaMax : alpha;
+      const float araw = c.z * G;
+      const bool live = ok && !(araw > kAlphaMax);  // contributes and unclamped
+      // alpha = 0 where the Gaussian does not contribute, so its weight below is 0 without a select
+      const float alpha = ok ? fminf(araw, kAlphaMax) : 0.0f;
       const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
       T = ok ? T * inv_om : T;  // transmittance in front of this Gaussian
-      const float w = alpha * T;
+      const float wk = alpha * T;
       const float4 col = S.s3[k];
       const float dc = fmaf(dl0, col.x, fmaf(dl1, col.y, dl2 * col.z));  // dL/dC . colour
       const float dL_da = fmaf(dc, T, -DS * inv_om);
-      const float wk = ok ? w : 0.0f;
       DS = fmaf(dc, wk, DS);
-      const bool live = ok && !clamped;
-      const float dpow = live ? dL_da * alpha : 0.0f;
-      // z = (2 / D) (h (t1 u1 + t2 u2) - qh w), zero on lanes that do not contribute
-      const float s2 = live ? 2.0f * __builtin_amdgcn_rcpf(D) : 0.0f;
+      const float dla = live ? dL_da : 0.0f;
+      const float dpow = dla * alpha;
+      // z / 2 = (1 / D) (h (t1 u1 + t2 u2) - qh w), zero on lanes that do not contribute (D may
+      // be 0 there)
+      const float s1 = live ? __builtin_amdgcn_rcpf(D) : 0.0f;
       const float ht1 = h * t1, ht2 = h * t2;
-      const float zx = s2 * fmaf(ht1, a.x, fmaf(ht2, a.w, -qh * b.z));
-      const float zy = s2 * fmaf(ht1, a.y, fmaf(ht2, b.x, -qh * b.w));
-      const float zz = s2 * fmaf(ht1, a.z, fmaf(ht2, b.y, -qh * c.x));
+      const float zx = s1 * fmaf(ht1, a.x, fmaf(ht2, a.w, -qh * b.z));
+      const float zy = s1 * fmaf(ht1, a.y, fmaf(ht2, b.x, -qh * b.w));
+      const float zz = s1 * fmaf(ht1, a.z, fmaf(ht2, b.y, -qh * c.x));
       const float gx = dpow * zx, gy = dpow * zy, gz = dpow * zz;
-      float gv[16];
-      gv[0] = gx;
-      gv[1] = gy;
-      gv[2] = gz;
-      gv[3] = 0.5f * gx * zx;  // dpow z z^T / 2, the shared off-diagonals counted twice
-      gv[4] = gx * zy;
-      gv[5] = gx * zz;
-      gv[6] = 0.5f * gy * zy;
-      gv[7] = gy * zz;
-      gv[8] = 0.5f * gz * zz;
-      gv[9] = live ? dL_da * G : 0.0f;
-      gv[10] = wk * dl0;
-      gv[11] = wk * dl1;
-      gv[12] = wk * dl2;
-      gv[13] = 0.0f;
-      gv[14] = 0.0f;
-      gv[15] = 0.0f;
-      const float rs = row_reduce16(gv, lane);
-      const int slot = lane & 15;
+      // before sph_flush_scale: dpow z, then dpow z z^T / 2 with the shared off-diagonals twice
+      const float gv[kNV] = {gx,      gy,      gz,       gx * zx,  gx * zy,  gx * zz, gy * zy,
+                             gy * zz, gz * zz, dla * G, wk * dl0, wk * dl1, wk * dl2};
+      const float rs = row_reduce13(gv, lane);
+      const int slot = (int)((kSphRowSlot >> (4 * (lane & 15))) & 0xF);
       if constexpr (kSlots) {
         const float ws = sum_rows(rs);
-        if (lane < kNV) acc[wq][lane][k] = ws;
+        if (lane < 16 && slot < kNV) acc[wq][slot][k] = ws;
       } else {
         if (slot < kNV) atomicAdd(&acc[0][slot][k], rs);
       }
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
       float s = acc[0][q][t];
 #pragma unroll
       for (int w = 1; w < NS; ++w) s += acc[w][q][t];
-      if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * kNV + q], s);
+      if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * kNV + q], s * sph_flush_scale(q));
     }
     __syncthreads();
   }
