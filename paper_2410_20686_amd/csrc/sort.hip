@@ -301,12 +301,20 @@ __global__ __launch_bounds__(256) void item_offsets_kernel(const Rect* __restric
 constexpr int kEmitRun = 4;  // consecutive pairs per thread
 constexpr int kEmitPairs = 256 * kEmitRun;
 
-__device__ inline int64_t upper_bound_u32(const uint32_t* a, int64_t n, uint32_t x) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (a[mid] <= x) lo = mid + 1;
-    else hi = mid;
+// Last index in [0, n) with a[idx] <= x, for nondecreasing a with a[0] <= x, searched by one
+// whole wavefront: each round probes 64 evenly spaced entries of the interval at once and keeps
+// the stretch between the last probe <= x and the next one, so about four rounds of dependent
+// loads cover millions of entries (a binary search takes twenty-odd).  Uniform result.
+__device__ inline int64_t wave_last_le(const uint32_t* __restrict__ a, int64_t n, uint32_t x) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int64_t lo = 0, hi = n;  // a[lo] <= x; hi == n or a[hi] > x
+  while (hi - lo > 1) {
+    const int64_t step = (hi - lo + kWave - 1) / kWave;
+    const int64_t idx = lo + (int64_t)lane * step;
+    const bool le = idx < hi && a[idx] <= x;  // true on a prefix of the lanes, lane 0 included
+    const int k = __popcll(__builtin_amdgcn_ballot_w64(le)) - 1;
+    lo += (int64_t)k * step;
+    hi = min(hi, lo + step);
   }
   return lo;
 }
@@ -327,9 +335,11 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restr
   const uint32_t p0 = blockIdx.x * (uint32_t)kEmitPairs;
   if (p0 >= np) return;  // uniform
   const uint32_t p1 = min(p0 + (uint32_t)kEmitPairs, np);
-  if (threadIdx.x == 0) {
-    s_range[0] = upper_bound_u32(ioff, items, p0) - 1;      // item holding pair p0
-    s_range[1] = upper_bound_u32(ioff, items, p1 - 1) - 1;  // item holding pair p1 - 1
+  // the first wavefront finds the item holding pair p0, the second the one holding pair p1 - 1
+  const int wv = threadIdx.x >> 6;
+  if (wv < 2) {
+    const int64_t it = wave_last_le(ioff, items, wv == 0 ? p0 : p1 - 1);
+    if ((threadIdx.x & (kWave - 1)) == 0) s_range[wv] = it;
   }
   __syncthreads();
   const int64_t i0 = s_range[0];
