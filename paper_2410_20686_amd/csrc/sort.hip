@@ -84,18 +84,31 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t
   hist[t * nblocks + blockIdx.x] = c;
 }
 
-// Block d: exclusive scan of hist[d][0..nblocks) in place; digit total to digit_tot[d].
+// Block d: exclusive scan of hist[d][0..nblocks) in place; digit total to digit_tot[d].  Each
+// thread takes kDigitIpt consecutive entries per round, so a row of thousands of sort blocks
+// needs a few block-wide scans rather than one per 256 entries.
+constexpr int kDigitIpt = 8;
+
 __global__ __launch_bounds__(256) void radix_digit_scan_kernel(uint32_t* __restrict__ hist, int nblocks,
                                                                uint32_t* __restrict__ digit_tot) {
   __shared__ uint32_t lds[4];
   uint32_t* row = hist + (size_t)blockIdx.x * nblocks;
   uint32_t carry = 0;
-  for (int base = 0; base < nblocks; base += 256) {
-    const int k = base + threadIdx.x;
-    const uint32_t x = k < nblocks ? row[k] : 0u;
+  for (int base = 0; base < nblocks; base += 256 * kDigitIpt) {
+    const int k0 = base + (int)threadIdx.x * kDigitIpt;
+    uint32_t x[kDigitIpt], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kDigitIpt; ++j) {
+      x[j] = k0 + j < nblocks ? row[k0 + j] : 0u;
+      sum += x[j];
+    }
     uint32_t total;
-    const uint32_t incl = block_incl_scan256(x, lds, total);
-    if (k < nblocks) row[k] = carry + incl - x;
+    uint32_t run = carry + block_incl_scan256(sum, lds, total) - sum;
+#pragma unroll
+    for (int j = 0; j < kDigitIpt; ++j) {
+      if (k0 + j < nblocks) row[k0 + j] = run;
+      run += x[j];
+    }
     carry += total;
   }
   if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
