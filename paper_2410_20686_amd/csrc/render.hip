@@ -235,7 +235,9 @@ __device__ inline bool stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __
       // pixel centre of the tile lies within W/2 - 1 of u: the seam wrap is then the identity
       const float reach = fabsf((float)tx0 + 0.5f * (float)TILE - r.r0.x) + 0.5f * (float)TILE + 1.0f;
       nowrap = nowrap && reach < half;
-      S.s1[e] = make_float4(r.r1.x, r.r1.y, r.r1.z, reach < half ? 1.0f : 0.0f);
+      // staged as (l2, p_min, opacity, no-wrap flag): the accept test reads its two words with one
+      // 8-byte LDS load at an immediate offset
+      S.s1[e] = make_float4(r.r1.x, r.r1.z, r.r1.y, reach < half ? 1.0f : 0.0f);
       S.s2[e] = r.r2;
       S.sid[e] = item;
       if (depth) S.dep[e] = depth[item];
@@ -326,13 +328,12 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
       const float power = -fmaf(t1, t1, fmaf(t2, t2, qstop));
       if (COUNT) nev += qstop == 0.0f ? 1 : 0;
       // alpha >= 1/255 (power <= 0 always: a sum of squares; NaN once stopped)
-      const bool ok = power >= b.z;
+      const bool ok = power >= b.y;
       if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
-      const float alpha = fminf(b.y * __expf(power), kAlphaMax);
+      const float alpha = fminf(b.z * __expf(power), kAlphaMax);
       const float Tn = T * (1.0f - alpha);
-      const bool stop = ok && Tn < kTStop;
       const bool acc = ok && !(Tn < kTStop);
-      qstop = stop ? __builtin_nanf("") : qstop;
+      qstop = ok != acc ? __builtin_nanf("") : qstop;  // stop: reached, but T would drop below 1e-4
       const float4 c = S.s2[k];
       const float w = (acc ? alpha : 0.0f) * T;  // (a select of the product compiles to a branch here)
       C0 = fmaf(w, c.x, C0);
@@ -379,11 +380,10 @@ struct FwdPixel {
 
 // One Gaussian's front-to-back step for one pixel (Eq. alphablending with the 3DGS constants).
 __device__ inline void fwd_pixel_step(FwdPixel& P, bool ok, float power, const float4& b, const float4& c, int pos) {
-  const float alpha = fminf(b.y * __expf(power), kAlphaMax);
+  const float alpha = fminf(b.z * __expf(power), kAlphaMax);
   const float Tn = P.T * (1.0f - alpha);
-  const bool stop = ok && Tn < kTStop;
   const bool acc = ok && !(Tn < kTStop);
-  P.done = P.done || stop;
+  P.done = P.done || ok != acc;  // stop: reached, but T would drop below 1e-4
   const float w = acc ? alpha * P.T : 0.0f;
   P.C0 = fmaf(w, c.x, P.C0);
   P.C1 = fmaf(w, c.y, P.C1);
@@ -434,8 +434,8 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_fwd2_kernel(
       const float dua = wrap_du(pxa - a.x, Wf, half), dub = wrap_du(pxb - a.x, Wf, half);
       const float t1a = fmaf(a.z, dua, l1dv), t1b = fmaf(a.z, dub, l1dv);
       const float pa = -fmaf(t1a, t1a, t22), pb = -fmaf(t1b, t1b, t22);
-      const bool oka = !A.done && !(pa > 0.0f || pa < b.z);
-      const bool okb = !B.done && !(pb > 0.0f || pb < b.z);
+      const bool oka = !A.done && !(pa > 0.0f || pa < b.y);
+      const bool okb = !B.done && !(pb > 0.0f || pb < b.y);
       const bool anya = __builtin_amdgcn_ballot_w64(oka) != 0ull;  // uniform
       const bool anyb = __builtin_amdgcn_ballot_w64(okb) != 0ull;
       if (!anya && !anyb) continue;
@@ -484,7 +484,7 @@ template <bool ADD>
 __device__ inline void bwd_pixel_step(BwdPixel& P, bool ok, float power, float t1, float bxt2, const float4& a,
                                       const float4& b, const float4& c, float (&gq)[9]) {
   const float G = __expf(power);
-  const float araw = b.y * G;
+  const float araw = b.z * G;
   const bool live = ok && !(araw > kAlphaMax);  // contributes and unclamped: alpha depends on the inputs
   // alpha = 0 where the Gaussian does not contribute, so its weight below is 0 without a select
   const float alpha = ok ? fminf(araw, kAlphaMax) : 0.0f;
@@ -593,7 +593,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       const float dv = py - a.y;
       const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
       const float power = -fmaf(t1, t1, t2 * t2);
-      const bool ok = jrel < P.last && !(power > 0.0f || power < b.z);
+      const bool ok = jrel < P.last && !(power > 0.0f || power < b.y);
       if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
       float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
       if (kSlots && pend) red_read(red[wq], lane, r0, r1);  // previous accepted entry's values
@@ -716,7 +716,7 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
       }
       const float t1a = fmaf(a.z, dua, l1dv), t1b = fmaf(a.z, dub, l1dv);
       const float pa = -fmaf(t1a, t1a, t22), pb = -fmaf(t1b, t1b, t22);
-      const bool ina = !(pa > 0.0f || pa < b.z), inb = !(pb > 0.0f || pb < b.z);
+      const bool ina = !(pa > 0.0f || pa < b.y), inb = !(pb > 0.0f || pb < b.y);
       const bool oka = jrel < A.last && ina, okb = jrel < B.last && inb;
       // ballots of the single compares (each is its own lane mask) rather than of their conjunction
       const uint64_t bala = __builtin_amdgcn_ballot_w64(jrel < A.last) & __builtin_amdgcn_ballot_w64(ina);

@@ -210,9 +210,8 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
       if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
       const float alpha = fminf(c.z * __expf(power), kAlphaMax);
       const float Tn = T * (1.0f - alpha);
-      const bool stop = ok && Tn < kTStop;
       const bool acc = ok && !(Tn < kTStop);
-      done = stop ? 1 : done;
+      done = ok != acc ? 1 : done;  // stop: reached, but T would drop below 1e-4
       const float4 col = S.s3[k];
       const float w = acc ? alpha * T : 0.0f;
       C0 = fmaf(w, col.x, C0);
