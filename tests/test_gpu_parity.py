@@ -207,6 +207,34 @@ def test_empty_and_fully_culled_scenes():
         np.testing.assert_array_equal(g, 0.0)
 
 
+@pytest.mark.parametrize("big", [False, True], ids=["one_tile", "many_tiles"])
+def test_single_visible_gaussian(big):
+    """One item with pairs among culled ones (zero counts, sorted last): the pair emission's
+    search for each block's items meets runs of equal offsets; key list bit-exact, image and
+    gradients against the oracle."""
+    from tests._util import make_scene
+    cams = scenes.identity_cameras(1024, 512)
+    st = settings(bg=(0.1, 0.2, 0.3), tile=8)
+    scale = 1.5 if big else 0.01  # at 3 units: ~4k tiles (several emission blocks), or a few
+    sc = make_scene([[0, -3.0, 0], [0, 0, 3.0], [0, 0, 0.1], [2.0, 0, 0]], [[scale] * 3, [scale] * 3, [0.1] * 3, [0.1] * 3],
+                    opac=[0.002, 0.6, 0.5, 0.001], dtype=np.float32)
+    fwd = O.render(sc, cams, st, mode=32)
+    dL = _masked_upstream(cams, fwd["margin"], seed=1100)
+    res = G.run_gpu(sc, cams, st, dL=dL, return_rast=True)
+    keys, gauss = res["rast"].keys()
+    okeys, ovals = O.keys(sc, cams, st)
+    assert res["status"]["n_visible"] == 1 and res["status"]["n_pairs"] == len(okeys) > 0
+    assert (len(okeys) > 1000) == big
+    np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint64), okeys)
+    np.testing.assert_array_equal(gauss.cpu().numpy().astype(np.uint32), ovals)
+    ok = G.strict_pixels(fwd["margin"])
+    okc = np.concatenate([np.tile(ok[o:o + w * h], 3) for o, w, h in _views(cams)])
+    assert np.abs(res["rgb"] - fwd["rgb"])[okc].max() <= G.RGB_ATOL
+    np.testing.assert_array_equal(res["T"][~ok] >= 0, True)
+    ref = O.backward(sc, cams, st, dL, mode=32)
+    G.assert_grads_close(res["grads"], ref)
+
+
 @pytest.mark.parametrize("case", CASES[:3], ids=[c[0] for c in CASES[:3]])
 def test_work_counters(case):
     """The counting forward variant gives the same image, the oracle's contributor counts, and
