@@ -186,8 +186,9 @@ int odgs_bin_sort(const odgs_plan* plan, void* ws, size_t ws_bytes, void* stream
  * transmittance (accumulated alpha = 1 - T); out_depth [V][H][W] (may be NULL) the
  * alpha-weighted depth sum_j alpha_j T_j d_j with d_j the sort depth (radial distance in ERP
  * views, camera z in pinhole views; divide by 1 - T for the expected depth of the covered part).
- * Keeps per-pixel T, the list position after the last contributor (both read by the backward)
- * and the work counters of odgs_debug_pixel_counts in the workspace. */
+ * Keeps per-pixel T, the list position after the last contributor, each staged list entry's
+ * culling mask (all three read by the backward) and the work counters of
+ * odgs_debug_pixel_counts in the workspace. */
 int odgs_render_fwd(const odgs_plan* plan, void* ws, size_t ws_bytes, float* out_rgb, float* out_T, float* out_depth,
                     void* stream);
 
@@ -204,7 +205,9 @@ int odgs_render_bwd(const odgs_plan* plan, const float* means, const float* scal
 /* First backward stage: reverse compositing of every pixel of every view (Eq. alphablending
  * differentiated), accumulating per-(Gaussian, view) gradients of the ERP position, the 2D
  * covariance Sigma_2D (dilation included), the opacity and the colour into the workspace (which
- * odgs_bin_sort and odgs_project_bwd leave cleared).  dL_drgb has the layout of out_rgb. */
+ * odgs_bin_sort and odgs_project_bwd leave cleared).  dL_drgb has the layout of out_rgb.
+ * Requires odgs_render_fwd on this workspace after its last odgs_bin_sort (the compositing state
+ * it reads is the forward's). */
 int odgs_composite_bwd(const odgs_plan* plan, void* ws, size_t ws_bytes, const float* dL_drgb, void* stream);
 
 /* Second backward stage: adjoint of the per-(Gaussian, view) projection (Eq. omni_Jacobian and

@@ -212,12 +212,19 @@ __device__ inline uint32_t group_mask(uint32_t m) {
   }
 }
 
+// The culling masks travel from the forward to the backward: the forward stores, per list position,
+// the mask in the reverse compositor's granularity (the wavefronts' two-quadrant groups for tiles of
+// 16 and 32, the one quadrant of an 8x8 tile) into the pair buffer the sort leaves unused, and the
+// backward loads it instead of evaluating the footprint again.  The backward reads only list
+// positions before its tile's last contributor, all of which the forward staged.
+enum QuadMaskMode { kMaskEval = 0, kMaskStore = 1, kMaskLoad = 2 };
+
 // Returns whether the seam wrap is the identity for every staged entry (uniform).
-template <int TILE, int BATCH, int PX = 1>
+template <int TILE, int BATCH, int PX = 1, int QM = kMaskEval>
 __device__ inline bool stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __restrict__ pair_items,
                                    const Rec* __restrict__ rec, uint32_t first, int dir, int cnt, int tx0, int ty0,
                                    float Wf, float half, int (&nq)[Stage<TILE, BATCH, PX>::NQ],
-                                   const float* __restrict__ depth = nullptr) {
+                                   const float* __restrict__ depth = nullptr, uint8_t* __restrict__ qmask = nullptr) {
   using St = Stage<TILE, BATCH, PX>;
   const int t = threadIdx.x, ln = t & (kWave - 1), wv = t >> 6;
   const uint64_t below = ln == 0 ? 0ull : (~0ull >> (kWave - ln));
@@ -228,7 +235,8 @@ __device__ inline bool stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __
     const int e = r0 + t;
     uint32_t m = 0;
     if (e < cnt) {
-      const uint32_t item = pair_items[first + dir * e];
+      const uint32_t pos = first + dir * e;
+      const uint32_t item = pair_items[pos];
       const Rec r = rec[item];
       S.s0[e] = r.r0;
       // the fourth word (the half extent, needed only for the mask below) carries whether every
@@ -241,7 +249,13 @@ __device__ inline bool stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __
       S.s2[e] = r.r2;
       S.sid[e] = item;
       if (depth) S.dep[e] = depth[item];
-      m = group_mask<PX>(quadrant_mask<TILE>(r, tx0, ty0, Wf, half));
+      if constexpr (QM == kMaskLoad) {
+        m = qmask[pos];  // stored in this granularity (two-pixel groups at 16 and 32, one quadrant at 8)
+      } else {
+        const uint32_t mq = quadrant_mask<TILE>(r, tx0, ty0, Wf, half);
+        m = group_mask<PX>(mq);
+        if constexpr (QM == kMaskStore) qmask[pos] = (uint8_t)(TILE >= 16 ? group_mask<2>(mq) : mq);
+      }
     }
     uint32_t within[St::NQ];
 #pragma unroll
@@ -285,7 +299,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
     float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
     int32_t* __restrict__ ws_ncontrib, int32_t* __restrict__ ws_neval, int32_t* __restrict__ ws_lasteval, float bg0,
-    float bg1, float bg2, const float* __restrict__ depth, float* __restrict__ out_depth) {
+    float bg1, float bg2, const float* __restrict__ depth, float* __restrict__ out_depth, uint8_t* __restrict__ qmask) {
   using St = Stage<TILE, BATCH>;
   constexpr int N = St::N;
   __shared__ St S;
@@ -313,7 +327,8 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
     const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
     int nq[St::NQ];
     const bool nowrap =
-        stage_batch<TILE, BATCH>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq, DEPTH ? depth : nullptr);
+        stage_batch<TILE, BATCH, 1, kMaskStore>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq,
+                                                DEPTH ? depth : nullptr, qmask);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     // one list walk, instantiated without the seam wrap for batches where it is the identity
     auto walk = [&](auto wrapc) {
@@ -399,7 +414,7 @@ template <int TILE, int BATCH>
 __global__ __launch_bounds__(TILE* TILE / 2) void render_fwd2_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
     float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
-    float bg0, float bg1, float bg2) {
+    float bg0, float bg1, float bg2, uint8_t* __restrict__ qmask) {
   using St = Stage<TILE, BATCH, 2>;
   constexpr int N = St::N;
   constexpr int QPR = TILE / 8;
@@ -422,7 +437,7 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_fwd2_kernel(
     if (__syncthreads_count(A.done && B.done) == N) break;
     const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
     int nq[St::NQ];
-    stage_batch<TILE, BATCH, 2>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq);
+    stage_batch<TILE, BATCH, 2, kMaskStore>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq, nullptr, qmask);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
       if (__builtin_amdgcn_ballot_w64(!(A.done && B.done)) == 0ull) break;  // uniform
@@ -516,7 +531,9 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
                                                                 const Rec* __restrict__ rec, const float* __restrict__ ws_T,
                                                                 const int32_t* __restrict__ ws_last,
                                                                 const float* __restrict__ dL_drgb, float* __restrict__ g2d,
-                                                                int64_t items, float bg0, float bg1, float bg2) {
+                                                                int64_t items, float bg0, float bg1, float bg2,
+                                                                const uint8_t* __restrict__ qmask) {
+  static_assert(TILE == 8, "tiles of 16 and 32 take the two-pixel kernel (the stored masks are per two quadrants)");
   using St = Stage<TILE, BATCH>;
   constexpr int N = St::N;
   // Up to four wavefronts per tile: each wavefront owns a slot per (value, entry) and the slots
@@ -573,7 +590,8 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
     }
     int nq[St::NQ];
     // entry e is list position end - 1 - e (back to front)
-    stage_batch<TILE, BATCH>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq);
+    stage_batch<TILE, BATCH, 1, kMaskLoad>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq, nullptr,
+                                           const_cast<uint8_t*>(qmask));
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     bool pend = false;  // an accepted entry whose values 0..7 still wait in red (uniform)
     int pk = 0;
@@ -643,7 +661,7 @@ template <int TILE, int BATCH>
 __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
     const float* __restrict__ ws_T, const int32_t* __restrict__ ws_last, const float* __restrict__ dL_drgb,
-    float* __restrict__ g2d, int64_t items, float bg0, float bg1, float bg2) {
+    float* __restrict__ g2d, int64_t items, float bg0, float bg1, float bg2, const uint8_t* __restrict__ qmask) {
   using St = Stage<TILE, BATCH, 2>;
   constexpr int N = St::N;
   constexpr int QPR = TILE / 8;
@@ -699,7 +717,8 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
     }
     int nq[St::NQ];
     // entry e is list position end - 1 - e (back to front)
-    stage_batch<TILE, BATCH, 2>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq);
+    stage_batch<TILE, BATCH, 2, kMaskLoad>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq, nullptr,
+                                           const_cast<uint8_t*>(qmask));
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
       const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);  // uniform entry index
@@ -791,12 +810,12 @@ template <int TILE, int BATCH>
 struct FwdRun {
   static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
                   const Rec* rec, float* out_rgb, float* out_T, float* wT, int32_t* wl, int32_t* wn, int32_t* we,
-                  int32_t* wle, const float* depth, float* out_depth, hipStream_t st) {
+                  int32_t* wle, const float* depth, float* out_depth, uint8_t* qmask, hipStream_t st) {
     const bool count = (p->s.flags & ODGS_FLAG_COUNT_WORK) != 0;
 #define ODGS_FWD1(C, D)                                                                                        \
   hipLaunchKernelGGL((render_fwd_kernel<TILE, BATCH, C, D>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, \
                      items, rec, out_rgb, out_T, wT, wl, wn, we, wle, p->s.bg[0], p->s.bg[1], p->s.bg[2], depth,  \
-                     out_depth)
+                     out_depth, qmask)
     // the counting and depth variants keep one pixel per lane (counters per 8x8 quadrant)
     if (count && out_depth)
       ODGS_FWD1(true, true);
@@ -806,7 +825,7 @@ struct FwdRun {
       ODGS_FWD1(false, true);
     else if constexpr (TILE >= 32)  // at 16x16 the union of two quadrants' lists costs more than it saves
       hipLaunchKernelGGL((render_fwd2_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE / 2), 0, st, vt, ranges,
-                         items, rec, out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+                         items, rec, out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
     else
       ODGS_FWD1(false, false);
 #undef ODGS_FWD1
@@ -816,15 +835,16 @@ struct FwdRun {
 template <int TILE, int BATCH>
 struct BwdRun {
   static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
-                  const Rec* rec, const float* wT, const int32_t* wl, const float* dL, float* g2d, hipStream_t st) {
+                  const Rec* rec, const float* wT, const int32_t* wl, const float* dL, float* g2d, const uint8_t* qmask,
+                  hipStream_t st) {
     // two pixels per lane (tiles of 16 and 32): one cross-lane reduction per 128 pixels; an 8x8
     // tile has a single quadrant and keeps one pixel per lane
     if constexpr (TILE >= 16)
       hipLaunchKernelGGL((render_bwd2_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE / 2), 0, st, vt, ranges,
-                         items, rec, wT, wl, dL, g2d, p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+                         items, rec, wT, wl, dL, g2d, p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
     else
       hipLaunchKernelGGL((render_bwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items,
-                         rec, wT, wl, dL, g2d, p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+                         rec, wT, wl, dL, g2d, p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
   }
 };
 
@@ -859,8 +879,9 @@ hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float
   int32_t* we = ws_ptr<int32_t>(ws, p->off_neval);
   int32_t* wle = ws_ptr<int32_t>(ws, p->off_lasteval);
   const float* depth = ws_ptr<float>(ws, p->off_depth);
+  uint8_t* qmask = ws_ptr<uint8_t>(ws, p->off_pval[p->pair_final ^ 1]);  // unused by the sort's result
   if (!dispatch<FwdRun>(p->s.tile, p->s.batch, p, tiles, vt, ranges, items, rec, out_rgb, out_T, wT, wl, wn, we, wle,
-                        depth, out_depth, st))
+                        depth, out_depth, qmask, st))
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -875,7 +896,8 @@ hipError_t launch_render_bwd(const odgs_plan* p, void* ws, const float* dL_drgb,
   const Rec* rec = ws_ptr<Rec>(ws, p->off_rec);
   const float* wT = ws_ptr<float>(ws, p->off_T);
   const int32_t* wl = ws_ptr<int32_t>(ws, p->off_last);
-  if (!dispatch<BwdRun>(p->s.tile, p->s.batch_bwd, p, tiles, vt, ranges, items, rec, wT, wl, dL_drgb, g2d, st))
+  const uint8_t* qmask = ws_ptr<uint8_t>(ws, p->off_pval[p->pair_final ^ 1]);  // written by the forward
+  if (!dispatch<BwdRun>(p->s.tile, p->s.batch_bwd, p, tiles, vt, ranges, items, rec, wT, wl, dL_drgb, g2d, qmask, st))
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
