@@ -71,13 +71,20 @@ __device__ inline void sph_stage_init(SphStage<TILE, BATCH>& S, const double2* _
   __syncthreads();
 }
 
+// How the quadrant masks are obtained: evaluated; evaluated and stored per list position (the
+// forward, into the pair buffer the sort leaves unused); or loaded from there (the backward, which
+// visits only list positions before its tile's last contributor, all staged by the forward).
+enum SphMaskMode { kSphMaskEval = 0, kSphMaskStore = 1, kSphMaskLoad = 2 };
+
 // Stage `cnt` records (entry e <- list position first + dir * e) and build every wavefront's
 // order-preserving list of the entries whose cone reaches its quadrant.
-template <int TILE, int BATCH>
+template <int TILE, int BATCH, int QM = kSphMaskEval>
 __device__ inline void sph_stage_batch(SphStage<TILE, BATCH>& S, const uint32_t* __restrict__ pair_items,
                                        const SphRec* __restrict__ rec, const SphCull* __restrict__ cull,
                                        uint32_t first, int dir, int cnt, float qrad,
-                                       int (&nq)[SphStage<TILE, BATCH>::NQ], const float* __restrict__ depth) {
+                                       int (&nq)[SphStage<TILE, BATCH>::NQ], const float* __restrict__ depth,
+                                       uint16_t* __restrict__ qmask = nullptr) {
+  static_assert(SphStage<TILE, BATCH>::NQ <= 16, "a quadrant mask fits 16 bits");
   using St = SphStage<TILE, BATCH>;
   const int t = threadIdx.x, ln = t & (kWave - 1), wv = t >> 6;
   const uint64_t below = ln == 0 ? 0ull : (~0ull >> (kWave - ln));
@@ -87,7 +94,8 @@ __device__ inline void sph_stage_batch(SphStage<TILE, BATCH>& S, const uint32_t*
     const int e = r0 + t;
     uint32_t m = 0;
     if (e < cnt) {
-      const uint32_t item = pair_items[first + dir * e];
+      const uint32_t pos = first + dir * e;
+      const uint32_t item = pair_items[pos];
       const SphRec r = rec[item];
       S.s0[e] = r.s0;
       S.s1[e] = r.s1;
@@ -95,32 +103,37 @@ __device__ inline void sph_stage_batch(SphStage<TILE, BATCH>& S, const uint32_t*
       S.s3[e] = r.s3;
       S.sid[e] = item;
       if (depth) S.dep[e] = depth[item];
-      const SphCull cu = cull[item];
-      const float4 c = cu.c0;
-      // cone: hit iff angle(quadrant centre, mu^) <= beta + qrad; the 1e-5 slack covers the float
-      // rounding of the dot product and of the cosine
-      const float lim = c.w + qrad >= 3.14159f ? -2.0f : cosf(c.w + qrad) - 1e-5f;
-      const float cq = cosf(qrad), sq = sinf(qrad);
+      if constexpr (QM == kSphMaskLoad) {
+        m = qmask[pos];
+      } else {
+        const SphCull cu = cull[item];
+        const float4 c = cu.c0;
+        // cone: hit iff angle(quadrant centre, mu^) <= beta + qrad; the 1e-5 slack covers the float
+        // rounding of the dot product and of the cosine
+        const float lim = c.w + qrad >= 3.14159f ? -2.0f : cosf(c.w + qrad) - 1e-5f;
+        const float cq = cosf(qrad), sq = sinf(qrad);
 #pragma unroll
-      for (int q = 0; q < St::NQ; ++q) {
-        const float3 d = S.qdir[q];
-        const float sd = fmaf(d.z, c.z, fmaf(d.y, c.y, d.x * c.x));  // cos of the centre's angle to mu^
-        bool hit = sd >= lim;
-        // ellipse: every ray of the quadrant is within qrad of the centre ray, hence at most
-        // gamma_max = gamma_c + qrad from mu^, and the gnomonic map stretches distances by at most
-        // sec^2(gamma_max) there: the images lie within r_q = qrad sec^2(gamma_max) of the
-        // centre's image p_c.  The quadrant is kept iff that disk can meet the ellipse:
-        // (p_c - p0)^T M (p_c - p0) <= (rho + sqrt(lambda_max) r_q)^2 (1e-3 relative slack).
-        const float cmax = fmaf(sd, cq, -sqrtf(fmaxf(0.0f, fmaf(-sd, sd, 1.0f))) * sq);  // cos(gamma_max)
-        if (hit && cu.c3.z > 0.0f && cmax > 0.05f) {
-          const float inv = 1.0f / sd;
-          const float px = fmaf(d.z, cu.c1.y, d.x * cu.c1.x) * inv - cu.c2.y;
-          const float py = fmaf(d.z, cu.c2.x, fmaf(d.y, cu.c1.w, d.x * cu.c1.z)) * inv - cu.c2.z;
-          const float qv = fmaf(cu.c2.w * px, px, py * fmaf(2.0f * cu.c3.x, px, cu.c3.y * py));
-          const float rr = fmaf(cu.c3.w, qrad / (cmax * cmax), cu.c3.z);
-          hit = qv <= rr * rr * 1.001f + 1e-6f;
+        for (int q = 0; q < St::NQ; ++q) {
+          const float3 d = S.qdir[q];
+          const float sd = fmaf(d.z, c.z, fmaf(d.y, c.y, d.x * c.x));  // cos of the centre's angle to mu^
+          bool hit = sd >= lim;
+          // ellipse: every ray of the quadrant is within qrad of the centre ray, hence at most
+          // gamma_max = gamma_c + qrad from mu^, and the gnomonic map stretches distances by at most
+          // sec^2(gamma_max) there: the images lie within r_q = qrad sec^2(gamma_max) of the
+          // centre's image p_c.  The quadrant is kept iff that disk can meet the ellipse:
+          // (p_c - p0)^T M (p_c - p0) <= (rho + sqrt(lambda_max) r_q)^2 (1e-3 relative slack).
+          const float cmax = fmaf(sd, cq, -sqrtf(fmaxf(0.0f, fmaf(-sd, sd, 1.0f))) * sq);  // cos(gamma_max)
+          if (hit && cu.c3.z > 0.0f && cmax > 0.05f) {
+            const float inv = 1.0f / sd;
+            const float px = fmaf(d.z, cu.c1.y, d.x * cu.c1.x) * inv - cu.c2.y;
+            const float py = fmaf(d.z, cu.c2.x, fmaf(d.y, cu.c1.w, d.x * cu.c1.z)) * inv - cu.c2.z;
+            const float qv = fmaf(cu.c2.w * px, px, py * fmaf(2.0f * cu.c3.x, px, cu.c3.y * py));
+            const float rr = fmaf(cu.c3.w, qrad / (cmax * cmax), cu.c3.z);
+            hit = qv <= rr * rr * 1.001f + 1e-6f;
+          }
+          m |= hit ? (1u << q) : 0u;
         }
-        m |= hit ? (1u << q) : 0u;
+        if constexpr (QM == kSphMaskStore) qmask[pos] = (uint16_t)m;
       }
     }
     uint32_t within[St::NQ];
@@ -173,7 +186,8 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items,
     const SphRec* __restrict__ rec, const SphCull* __restrict__ cull, const double2* __restrict__ dirs,
     float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
-    float bg0, float bg1, float bg2, const float* __restrict__ depth, float* __restrict__ out_depth) {
+    float bg0, float bg1, float bg2, const float* __restrict__ depth, float* __restrict__ out_depth,
+    uint16_t* __restrict__ qmask) {
   using St = SphStage<TILE, BATCH>;
   constexpr int N = St::N;
   __shared__ St S;
@@ -198,7 +212,8 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
     if (__syncthreads_count(done) == N) break;
     const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
     int nq[St::NQ];
-    sph_stage_batch<TILE, BATCH>(S, pair_items, rec, cull, base, 1, cnt, qrad, nq, DEPTH ? depth : nullptr);
+    sph_stage_batch<TILE, BATCH, kSphMaskStore>(S, pair_items, rec, cull, base, 1, cnt, qrad, nq,
+                                                DEPTH ? depth : nullptr, qmask);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
       if (__builtin_amdgcn_ballot_w64(done == 0) == 0ull) break;  // uniform: every pixel has finished
@@ -275,7 +290,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items,
     const SphRec* __restrict__ rec, const SphCull* __restrict__ cull, const double2* __restrict__ dirs,
     const float* __restrict__ ws_T, const int32_t* __restrict__ ws_last, const float* __restrict__ dL_drgb,
-    float* __restrict__ g2d, float bg0, float bg1, float bg2) {
+    float* __restrict__ g2d, float bg0, float bg1, float bg2, const uint16_t* __restrict__ qmask) {
   using St = SphStage<TILE, BATCH>;
   constexpr int N = St::N;
   constexpr bool kSlots = St::NW <= 4;  // a slot set per wavefront, else one shared set (LDS atomics)
@@ -326,7 +341,8 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
     }
     int nq[St::NQ];
     // entry e is list position end - 1 - e (back to front)
-    sph_stage_batch<TILE, BATCH>(S, pair_items, rec, cull, rg.x + end - 1, -1, cnt, qrad, nq, nullptr);
+    sph_stage_batch<TILE, BATCH, kSphMaskLoad>(S, pair_items, rec, cull, rg.x + end - 1, -1, cnt, qrad, nq, nullptr,
+                                               const_cast<uint16_t*>(qmask));
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
       const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);
@@ -390,15 +406,15 @@ template <int TILE, int BATCH>
 struct SphFwdRun {
   static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
                   const SphRec* rec, const SphCull* cone, const double2* dirs, float* out_rgb, float* out_T, float* wT,
-                  int32_t* wl, const float* depth, float* out_depth, hipStream_t st) {
+                  int32_t* wl, const float* depth, float* out_depth, uint16_t* qmask, hipStream_t st) {
     if (out_depth)
       hipLaunchKernelGGL((render_sph_fwd_kernel<TILE, BATCH, true>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges,
                          items, rec, cone, dirs, out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], depth,
-                         out_depth);
+                         out_depth, qmask);
     else
       hipLaunchKernelGGL((render_sph_fwd_kernel<TILE, BATCH, false>), dim3(tiles), dim3(TILE * TILE), 0, st, vt,
                          ranges, items, rec, cone, dirs, out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2],
-                         depth, out_depth);
+                         depth, out_depth, qmask);
   }
 };
 
@@ -406,9 +422,9 @@ template <int TILE, int BATCH>
 struct SphBwdRun {
   static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
                   const SphRec* rec, const SphCull* cone, const double2* dirs, const float* wT, const int32_t* wl,
-                  const float* dL, float* g2d, hipStream_t st) {
+                  const float* dL, float* g2d, const uint16_t* qmask, hipStream_t st) {
     hipLaunchKernelGGL((render_sph_bwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items,
-                       rec, cone, dirs, wT, wl, dL, g2d, p->s.bg[0], p->s.bg[1], p->s.bg[2]);
+                       rec, cone, dirs, wT, wl, dL, g2d, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
   }
 };
 
@@ -437,7 +453,8 @@ hipError_t launch_render_sph_fwd(const odgs_plan* p, void* ws, float* out_rgb, f
                                ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]), ws_ptr<SphRec>(ws, p->off_srec),
                                ws_ptr<SphCull>(ws, p->off_cone), ws_ptr<double2>(ws, p->off_dirs), out_rgb, out_T,
                                ws_ptr<float>(ws, p->off_T), ws_ptr<int32_t>(ws, p->off_last),
-                               ws_ptr<float>(ws, p->off_depth), out_depth, st))
+                               ws_ptr<float>(ws, p->off_depth), out_depth,
+                               ws_ptr<uint16_t>(ws, p->off_pval[p->pair_final ^ 1]), st))  // masks: unused pair buffer
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -450,7 +467,8 @@ hipError_t launch_render_sph_bwd(const odgs_plan* p, void* ws, const float* dL_d
                                ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]), ws_ptr<SphRec>(ws, p->off_srec),
                                ws_ptr<SphCull>(ws, p->off_cone), ws_ptr<double2>(ws, p->off_dirs),
                                ws_ptr<float>(ws, p->off_T), ws_ptr<int32_t>(ws, p->off_last), dL_drgb,
-                               ws_ptr<float>(ws, p->off_g2d), st))
+                               ws_ptr<float>(ws, p->off_g2d),
+                               ws_ptr<uint16_t>(ws, p->off_pval[p->pair_final ^ 1]), st))  // the forward's masks
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
