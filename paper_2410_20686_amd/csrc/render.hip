@@ -1,19 +1,21 @@
 // Compositing kernels of the omnidirectional rasterizer, gfx950.
 //
-// One workgroup per (view, tile); one thread per pixel; every 64-wide wavefront owns an 8x8
-// pixel quadrant of the tile.  The tile's depth-ordered list is staged through LDS in batches;
-// while staging, each record gets a bit mask of the quadrants its padded footprint rectangle
-// overlaps, so a wavefront skips, with a uniform branch, every Gaussian that cannot reach any of
-// its 64 pixels.  (The mask is conservative: a skipped Gaussian has alpha < 1/255 at every pixel
-// of the quadrant, so results are identical to testing every pixel.)
+// One workgroup per (view, tile).  Pixels are grouped in 8x8 quadrants: a 64-wide wavefront owns
+// one quadrant with one pixel per lane (forward at tiles 8 and 16, backward at 8) or two side by
+// side with two pixels per lane (forward at 32, backward at 16 and 32).  The tile's depth-ordered
+// list is staged through LDS in batches; while the forward stages, each record gets a bit mask of
+// the quadrants its footprint can reach, so a wavefront skips, with a uniform branch, every
+// Gaussian that cannot reach any of its pixels.  (The mask is conservative: a skipped Gaussian has
+// alpha < 1/255 at every pixel of the quadrant, so results are identical to testing every pixel.)
+// The forward stores the masks per list position and the backward loads them.
 //
 // Forward: front-to-back compositing (Eq. gaussian2d, Eq. alphablending) until a pixel's
 // transmittance would drop below 1e-4; the workgroup stops loading batches once every pixel is
 // done.  Backward: back to front from the last contributor, transmittance recovered by
 // multiplying with 1/(1 - alpha); the nine per-pixel gradients of the 2D quantities are summed
-// over each 16-lane row by a DPP butterfly that leaves one value per lane, over rows and
-// wavefronts with LDS float atomics, and reach global memory with one float atomic per
-// (Gaussian, tile, quantity).
+// over each 16-lane row by a DPP butterfly that leaves one value per lane, over the four rows by
+// the row-swap permutes, kept per wavefront in LDS, and reach global memory with one float atomic
+// per (Gaussian, tile, quantity).
 // One launch covers all views of a step: the grid spans the global tile ids of every view.
 #include <type_traits>
 #include <utility>

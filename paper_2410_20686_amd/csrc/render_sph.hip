@@ -6,13 +6,14 @@
 // d of its ray (from the per-view ray table, rounded once to float), and a Gaussian's exponent is
 // -qh / D with t1 = u1 . d, t2 = u2 . d, h = w . d, qh = t1^2 + t2^2, D = h^2 + k2 qh (the maximum
 // of the 3D Gaussian along the ray, see SphRec); it reaches the pixel iff h > 0 and
-// p_min D + qh <= 0.  While staging, a record's quadrant mask comes from its culling data
-// (SphCull): a quadrant is skipped when the angle between its centre ray and mu^ exceeds the cone
-// half-angle beta plus the quadrant's angular radius, or when the disk that holds the gnomonic
-// images of the quadrant's rays misses the item's gnomonic ellipse.
+// p_min D + qh <= 0.  While the forward stages, a record's quadrant mask comes from its culling
+// data (SphCull): a quadrant is skipped when the angle between its centre ray and mu^ exceeds the
+// cone half-angle beta plus the quadrant's angular radius, or when the disk that holds the
+// gnomonic images of the quadrant's rays misses the item's gnomonic ellipse.  The forward stores
+// the masks per list position; the backward loads them.
 //
 // Backward: per accepted (Gaussian, wavefront) the 13 gradient values (mu^ (3), Sigma~ (6),
-// opacity, rgb) are summed over each 16-lane row by a 16-slot DPP butterfly and over rows by the
+// opacity, rgb) are summed over each 16-lane row by a DPP butterfly and over rows by the
 // row-swap permutes, kept per wavefront in LDS, and flushed with one float atomic per (Gaussian,
 // tile, value) to contiguous 52-byte records.
 #include "common.h"
