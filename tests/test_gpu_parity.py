@@ -273,6 +273,34 @@ def test_other_tiles_forward_and_backward(tile, batch):
     G.assert_grads_close(res["grads"], ref)
 
 
+def backward_after_forward_variant(sc, cams, st, variant, seed):
+    """Backward after the counting or the depth forward (not the plain one): those variants also
+    hand the culling masks to the backward.  Returns (GPU gradients, oracle gradients)."""
+    import torch
+    from paper_2410_20686_amd.rasterizer import Rasterizer
+    st = dict(st, count_work=variant == "count")
+    fwd = O.render(sc, cams, st, mode=32)
+    dL = _masked_upstream(cams, fwd["margin"], seed=seed)
+    rast = Rasterizer(sc.n, sc.sh_degree, [tuple(int(x) for x in r) for r in cams.wh], st)
+    t = G.to_gpu(sc, cams)
+    rast.bin_checked(*t)
+    depth = torch.empty(rast.pixels, dtype=torch.float32, device="cuda") if variant == "depth" else None
+    rast.render_fwd(out_depth=depth)
+    rast.composite_bwd(torch.from_numpy(np.ascontiguousarray(dL, dtype=np.float32)).cuda())
+    g = tuple(torch.empty_like(x) for x in t[:5])
+    rast.project_bwd(*t, g)
+    torch.cuda.synchronize()
+    got = dict(zip(("means", "scales", "quats", "opacities", "sh"), (x.cpu().numpy() for x in g)))
+    return got, O.backward(sc, cams, st, dL, mode=32)
+
+
+@pytest.mark.parametrize("tile,variant", [(8, "depth"), (16, "count"), (32, "count"), (32, "depth")])
+def test_backward_after_counting_or_depth_forward(tile, variant):
+    name, sc, cams, st = CASES[1]
+    got, ref = backward_after_forward_variant(sc, cams, dict(st, tile=tile), variant, seed=1009)
+    G.assert_grads_close(got, ref)
+
+
 @pytest.mark.parametrize("tile", [8, 16, 32])
 def test_alpha_weighted_depth_output(tile):
     """The forward's depth output against the oracle's sum_j alpha_j T_j d_j (ERP and pinhole

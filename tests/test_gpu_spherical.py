@@ -100,6 +100,14 @@ def test_backward_matches_oracle(case):
     print(name, rep)
 
 
+@pytest.mark.parametrize("tile", [16, 32])
+def test_backward_after_depth_forward(tile):
+    """The depth forward variant also hands its quadrant masks to the backward."""
+    name, sc, cams, st = CASES[0]
+    got, ref = P.backward_after_forward_variant(sc, cams, dict(st, tile=tile), "depth", seed=1051)
+    G.assert_grads_close(got, ref)
+
+
 @pytest.mark.parametrize("tile", [8, 32])
 def test_backward_other_tiles(tile):
     """Tile 8: one wavefront per tile; tile 32: sixteen wavefronts sharing one set of LDS
