@@ -226,7 +226,8 @@ template <int TILE, int BATCH, int PX = 1, int QM = kMaskEval>
 __device__ inline bool stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __restrict__ pair_items,
                                    const Rec* __restrict__ rec, uint32_t first, int dir, int cnt, int tx0, int ty0,
                                    float Wf, float half, int (&nq)[Stage<TILE, BATCH, PX>::NQ],
-                                   const float* __restrict__ depth = nullptr, uint8_t* __restrict__ qmask = nullptr) {
+                                   const float* __restrict__ depth = nullptr, uint8_t* __restrict__ qmask_out = nullptr,
+                                   const uint8_t* __restrict__ qmask_in = nullptr) {
   using St = Stage<TILE, BATCH, PX>;
   const int t = threadIdx.x, ln = t & (kWave - 1), wv = t >> 6;
   const uint64_t below = ln == 0 ? 0ull : (~0ull >> (kWave - ln));
@@ -252,11 +253,11 @@ __device__ inline bool stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __
       S.sid[e] = item;
       if (depth) S.dep[e] = depth[item];
       if constexpr (QM == kMaskLoad) {
-        m = qmask[pos];  // stored in this granularity (two-pixel groups at 16 and 32, one quadrant at 8)
+        m = qmask_in[pos];  // stored in this granularity (two-pixel groups at 16 and 32, one quadrant at 8)
       } else {
         const uint32_t mq = quadrant_mask<TILE>(r, tx0, ty0, Wf, half);
         m = group_mask<PX>(mq);
-        if constexpr (QM == kMaskStore) qmask[pos] = (uint8_t)(TILE >= 16 ? group_mask<2>(mq) : mq);
+        if constexpr (QM == kMaskStore) qmask_out[pos] = (uint8_t)(TILE >= 16 ? group_mask<2>(mq) : mq);
       }
     }
     uint32_t within[St::NQ];
@@ -593,7 +594,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
     int nq[St::NQ];
     // entry e is list position end - 1 - e (back to front)
     stage_batch<TILE, BATCH, 1, kMaskLoad>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq, nullptr,
-                                           const_cast<uint8_t*>(qmask));
+                                           nullptr, qmask);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     bool pend = false;  // an accepted entry whose values 0..7 still wait in red (uniform)
     int pk = 0;
@@ -720,7 +721,7 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
     int nq[St::NQ];
     // entry e is list position end - 1 - e (back to front)
     stage_batch<TILE, BATCH, 2, kMaskLoad>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq, nullptr,
-                                           const_cast<uint8_t*>(qmask));
+                                           nullptr, qmask);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
       const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);  // uniform entry index

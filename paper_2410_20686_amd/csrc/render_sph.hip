@@ -84,7 +84,8 @@ __device__ inline void sph_stage_batch(SphStage<TILE, BATCH>& S, const uint32_t*
                                        const SphRec* __restrict__ rec, const SphCull* __restrict__ cull,
                                        uint32_t first, int dir, int cnt, float qrad,
                                        int (&nq)[SphStage<TILE, BATCH>::NQ], const float* __restrict__ depth,
-                                       uint16_t* __restrict__ qmask = nullptr) {
+                                       uint16_t* __restrict__ qmask_out = nullptr,
+                                       const uint16_t* __restrict__ qmask_in = nullptr) {
   static_assert(SphStage<TILE, BATCH>::NQ <= 16, "a quadrant mask fits 16 bits");
   using St = SphStage<TILE, BATCH>;
   const int t = threadIdx.x, ln = t & (kWave - 1), wv = t >> 6;
@@ -105,7 +106,7 @@ __device__ inline void sph_stage_batch(SphStage<TILE, BATCH>& S, const uint32_t*
       S.sid[e] = item;
       if (depth) S.dep[e] = depth[item];
       if constexpr (QM == kSphMaskLoad) {
-        m = qmask[pos];
+        m = qmask_in[pos];
       } else {
         const SphCull cu = cull[item];
         const float4 c = cu.c0;
@@ -134,7 +135,7 @@ __device__ inline void sph_stage_batch(SphStage<TILE, BATCH>& S, const uint32_t*
           }
           m |= hit ? (1u << q) : 0u;
         }
-        if constexpr (QM == kSphMaskStore) qmask[pos] = (uint16_t)m;
+        if constexpr (QM == kSphMaskStore) qmask_out[pos] = (uint16_t)m;
       }
     }
     uint32_t within[St::NQ];
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
     int nq[St::NQ];
     // entry e is list position end - 1 - e (back to front)
     sph_stage_batch<TILE, BATCH, kSphMaskLoad>(S, pair_items, rec, cull, rg.x + end - 1, -1, cnt, qrad, nq, nullptr,
-                                               const_cast<uint16_t*>(qmask));
+                                               nullptr, qmask);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
       const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);
