@@ -1,7 +1,7 @@
 """Helpers for the GPU parity tests: run the HIP path through the C ABI on numpy inputs."""
 import numpy as np
 
-# Tolerances (spec: colours 1e-4 absolute per pixel, gradients 1e-3 relative per element).
+# Tolerances: colours 1e-4 absolute per pixel, gradients 1e-3 relative per element.
 RGB_ATOL = 1e-4
 GRAD_RTOL = 1e-3
 GRAD_FLOOR = 1e-3 * 1e-3   # absolute floor, times the largest |gradient| of the tensor
