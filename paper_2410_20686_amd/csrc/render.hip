@@ -306,6 +306,12 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
   using St = Stage<TILE, BATCH>;
   constexpr int N = St::N;
   __shared__ St S;
+  // s_used[q][e]: some still-compositing pixel of quadrant q reaches entry e of the batch being
+  // walked.  For list positions before a pixel's last contributor, that test here and the
+  // backward's are the same float decision, so these quadrants include every one whose pixels the
+  // backward must visit the entry for (and little else); that mask, in the backward's
+  // granularity, is what the backward loads.
+  __shared__ uint8_t s_used[St::NQ][BATCH];
   const int g = blockIdx.x;
   const int v = view_of_tile(vt, g);
   const int W = vt.W[v], H = vt.H[v];
@@ -325,13 +331,30 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
   // it makes the accept compare itself false for every later Gaussian (with 0 the sum is the same
   // float), so the wavefront's ballots are of single compares
   float qstop = 0.0f;
+  // writes the masks of the batch walked last (after a barrier) and clears s_used for the next
+  auto flush_used = [&](uint32_t first, int n_walked) {
+    for (int e = threadIdx.x; e < BATCH; e += N) {
+      if (e < n_walked) {
+        uint32_t mq = 0;
+#pragma unroll
+        for (int q = 0; q < St::NQ; ++q) mq |= s_used[q][e] ? (1u << q) : 0u;
+        qmask[first + e] = (uint8_t)(TILE >= 16 ? group_mask<2>(mq) : mq);
+      }
+#pragma unroll
+      for (int q = 0; q < St::NQ; ++q) s_used[q][e] = 0;
+    }
+  };
+  uint32_t walked_base = 0;
+  int walked_cnt = 0;
   for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
-    if (__syncthreads_count(!(qstop == 0.0f)) == N) break;
+    const bool all_done = __syncthreads_count(!(qstop == 0.0f)) == N;
+    flush_used(walked_base, walked_cnt);
+    walked_cnt = 0;
+    if (all_done) break;
     const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
     int nq[St::NQ];
     const bool nowrap =
-        stage_batch<TILE, BATCH, 1, kMaskStore>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq,
-                                                DEPTH ? depth : nullptr, qmask);
+        stage_batch<TILE, BATCH>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq, DEPTH ? depth : nullptr);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     // one list walk, instantiated without the seam wrap for batches where it is the identity
     auto walk = [&](auto wrapc) {
@@ -348,6 +371,9 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
       // alpha >= 1/255 (power <= 0 always: a sum of squares; NaN once stopped)
       const bool ok = power >= b.y;
       if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
+      // some pixel of this quadrant reaches the entry (it is accepted there unless that pixel
+      // stops at it, in which case the backward does not need it for that pixel: a superset)
+      s_used[wq][k] = 1;
       const float alpha = fminf(b.z * __expf(power), kAlphaMax);
       const float Tn = T * (1.0f - alpha);
       const bool acc = ok && !(Tn < kTStop);
@@ -364,13 +390,18 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
         lastev = acc ? nev : lastev;
         ncontrib += acc ? 1 : 0;
       }
+
     }
     };
     if (nowrap)
       walk(std::false_type{});
     else
       walk(std::true_type{});
+    walked_base = base;
+    walked_cnt = cnt;
   }
+  __syncthreads();
+  flush_used(walked_base, walked_cnt);
   const int64_t plane = (int64_t)W * H;
   const int64_t pix = (int64_t)y * W + x;
   float* img = out_rgb + 3 * vt.pix_base[v];
