@@ -215,10 +215,13 @@ __device__ inline uint32_t group_mask(uint32_t m) {
 }
 
 // The culling masks travel from the forward to the backward: the forward stores, per list position,
-// the mask in the reverse compositor's granularity (the wavefronts' two-quadrant groups for tiles of
+// a mask in the reverse compositor's granularity (the wavefronts' two-quadrant groups for tiles of
 // 16 and 32, the one quadrant of an 8x8 tile) into the pair buffer the sort leaves unused, and the
-// backward loads it instead of evaluating the footprint again.  The backward reads only list
-// positions before its tile's last contributor, all of which the forward staged.
+// backward loads it instead of evaluating the footprint again.  The two-pixel forward (tile 32)
+// stores the footprint masks while staging; the one-pixel forward stores, after walking each batch,
+// the quadrants in which some of its pixels reached the entry (a narrower mask, see s_used).  The
+// backward reads only list positions before its tile's last contributor, all of which the forward
+// staged.
 enum QuadMaskMode { kMaskEval = 0, kMaskStore = 1, kMaskLoad = 2 };
 
 // Returns whether the seam wrap is the identity for every staged entry (uniform).
