@@ -72,10 +72,11 @@ __device__ inline void sph_stage_init(SphStage<TILE, BATCH>& S, const double2* _
   __syncthreads();
 }
 
-// How the quadrant masks are obtained: evaluated; evaluated and stored per list position (the
-// forward, into the pair buffer the sort leaves unused); or loaded from there (the backward, which
-// visits only list positions before its tile's last contributor, all staged by the forward).
-enum SphMaskMode { kSphMaskEval = 0, kSphMaskStore = 1, kSphMaskLoad = 2 };
+// How the quadrant masks are obtained: evaluated (the forward, which after walking each batch
+// stores per list position the quadrants its pixels reached, into the pair buffer the sort leaves
+// unused), or loaded from there (the backward, which visits only list positions before its tile's
+// last contributor, all staged by the forward).
+enum SphMaskMode { kSphMaskEval = 0, kSphMaskLoad = 2 };
 
 // Stage `cnt` records (entry e <- list position first + dir * e) and build every wavefront's
 // order-preserving list of the entries whose cone reaches its quadrant.
@@ -84,7 +85,6 @@ __device__ inline void sph_stage_batch(SphStage<TILE, BATCH>& S, const uint32_t*
                                        const SphRec* __restrict__ rec, const SphCull* __restrict__ cull,
                                        uint32_t first, int dir, int cnt, float qrad,
                                        int (&nq)[SphStage<TILE, BATCH>::NQ], const float* __restrict__ depth,
-                                       uint16_t* __restrict__ qmask_out = nullptr,
                                        const uint16_t* __restrict__ qmask_in = nullptr) {
   static_assert(SphStage<TILE, BATCH>::NQ <= 16, "a quadrant mask fits 16 bits");
   using St = SphStage<TILE, BATCH>;
@@ -135,7 +135,6 @@ __device__ inline void sph_stage_batch(SphStage<TILE, BATCH>& S, const uint32_t*
           }
           m |= hit ? (1u << q) : 0u;
         }
-        if constexpr (QM == kSphMaskStore) qmask_out[pos] = (uint16_t)m;
       }
     }
     uint32_t within[St::NQ];
@@ -193,6 +192,10 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
   using St = SphStage<TILE, BATCH>;
   constexpr int N = St::N;
   __shared__ St S;
+  // s_used[q][e]: some still-compositing pixel of quadrant q reaches entry e of the batch being
+  // walked (before a pixel's last contributor this test and the backward's are the same float
+  // decision); after the batch these quadrants are the mask handed to the backward
+  __shared__ uint8_t s_used[St::NQ][BATCH];
   const int g = blockIdx.x;
   const int v = view_of_tile(vt, g);
   const int W = vt.W[v], H = vt.H[v];
@@ -210,12 +213,29 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, Dsum = 0.0f;
   int last = 0;
   int done = 0;  // an int rather than a bool: the ballots below then compile to one compare
+  // writes the masks of the batch walked last (after a barrier) and clears s_used for the next
+  auto flush_used = [&](uint32_t first, int n_walked) {
+    for (int e = threadIdx.x; e < BATCH; e += N) {
+      if (e < n_walked) {
+        uint32_t mq = 0;
+#pragma unroll
+        for (int q = 0; q < St::NQ; ++q) mq |= s_used[q][e] ? (1u << q) : 0u;
+        qmask[first + e] = (uint16_t)mq;
+      }
+#pragma unroll
+      for (int q = 0; q < St::NQ; ++q) s_used[q][e] = 0;
+    }
+  };
+  uint32_t walked_base = 0;
+  int walked_cnt = 0;
   for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
-    if (__syncthreads_count(done) == N) break;
+    const bool all_done = __syncthreads_count(done) == N;
+    flush_used(walked_base, walked_cnt);
+    walked_cnt = 0;
+    if (all_done) break;
     const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
     int nq[St::NQ];
-    sph_stage_batch<TILE, BATCH, kSphMaskStore>(S, pair_items, rec, cull, base, 1, cnt, qrad, nq,
-                                                DEPTH ? depth : nullptr, qmask);
+    sph_stage_batch<TILE, BATCH>(S, pair_items, rec, cull, base, 1, cnt, qrad, nq, DEPTH ? depth : nullptr);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
       if (__builtin_amdgcn_ballot_w64(done == 0) == 0ull) break;  // uniform: every pixel has finished
@@ -225,6 +245,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
       const bool hit = sph_eval(S.s0[k], S.s1[k], c, d, power, t1, t2, h, D, qh);
       const bool ok = done == 0 && hit;
       if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
+      s_used[wq][k] = 1;  // reached here (accepted unless that pixel stops at it: a superset)
       const float alpha = fminf(c.z * __expf(power), kAlphaMax);
       const float Tn = T * (1.0f - alpha);
       const bool acc = ok && !(Tn < kTStop);
@@ -238,7 +259,11 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
       T = acc ? Tn : T;
       last = acc ? (int)(base - rg.x) + k + 1 : last;
     }
+    walked_base = base;
+    walked_cnt = cnt;
   }
+  __syncthreads();
+  flush_used(walked_base, walked_cnt);
   const int64_t plane = (int64_t)W * H;
   const int64_t pix = (int64_t)y * W + x;
   float* img = out_rgb + 3 * vt.pix_base[v];
@@ -344,7 +369,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
     int nq[St::NQ];
     // entry e is list position end - 1 - e (back to front)
     sph_stage_batch<TILE, BATCH, kSphMaskLoad>(S, pair_items, rec, cull, rg.x + end - 1, -1, cnt, qrad, nq, nullptr,
-                                               nullptr, qmask);
+                                               qmask);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
       const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);
