@@ -123,11 +123,11 @@ __device__ inline float rect_min_quadratic(float a, float b, float c, float nba,
   float m = 3.0e38f;
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
-    const float x = e ? x1 : x0;  // vertical edge: best y = -b x / c, clamped
-    const float y = fminf(fmaxf(nbc * x, y0), y1);
+    const float x = e ? x1 : x0;  // vertical edge: best y = -b x / c, clamped (median of three)
+    const float y = __builtin_amdgcn_fmed3f(nbc * x, y0, y1);
     m = fminf(m, fmaf(a * x, x, y * fmaf(2.0f * b, x, c * y)));
     const float yy = e ? y1 : y0;  // horizontal edge
-    const float xx = fminf(fmaxf(nba * yy, x0), x1);
+    const float xx = __builtin_amdgcn_fmed3f(nba * yy, x0, x1);
     m = fminf(m, fmaf(a * xx, xx, yy * fmaf(2.0f * b, xx, c * yy)));
   }
   return m;
