@@ -217,19 +217,18 @@ __device__ inline uint32_t group_mask(uint32_t m) {
 // The culling masks travel from the forward to the backward: the forward stores, per list position,
 // a mask in the reverse compositor's granularity (the wavefronts' two-quadrant groups for tiles of
 // 16 and 32, the one quadrant of an 8x8 tile) into the pair buffer the sort leaves unused, and the
-// backward loads it instead of evaluating the footprint again.  The two-pixel forward (tile 32)
-// stores the footprint masks while staging; the one-pixel forward stores, after walking each batch,
-// the quadrants in which some of its pixels reached the entry (a narrower mask, see s_used).  The
-// backward reads only list positions before its tile's last contributor, all of which the forward
-// staged.
-enum QuadMaskMode { kMaskEval = 0, kMaskStore = 1, kMaskLoad = 2 };
+// backward loads it instead of evaluating the footprint again.  The mask is written after the
+// forward walks each batch: the quadrants (or groups) in which some of its pixels reached the entry
+// (see s_used), narrower than the footprint's.  The backward reads only list positions before its
+// tile's last contributor, all of which the forward staged.
+enum QuadMaskMode { kMaskEval = 0, kMaskLoad = 2 };
 
 // Returns whether the seam wrap is the identity for every staged entry (uniform).
 template <int TILE, int BATCH, int PX = 1, int QM = kMaskEval>
 __device__ inline bool stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __restrict__ pair_items,
                                    const Rec* __restrict__ rec, uint32_t first, int dir, int cnt, int tx0, int ty0,
                                    float Wf, float half, int (&nq)[Stage<TILE, BATCH, PX>::NQ],
-                                   const float* __restrict__ depth = nullptr, uint8_t* __restrict__ qmask_out = nullptr,
+                                   const float* __restrict__ depth = nullptr,
                                    const uint8_t* __restrict__ qmask_in = nullptr) {
   using St = Stage<TILE, BATCH, PX>;
   const int t = threadIdx.x, ln = t & (kWave - 1), wv = t >> 6;
@@ -258,9 +257,7 @@ __device__ inline bool stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __
       if constexpr (QM == kMaskLoad) {
         m = qmask_in[pos];  // stored in this granularity (two-pixel groups at 16 and 32, one quadrant at 8)
       } else {
-        const uint32_t mq = quadrant_mask<TILE>(r, tx0, ty0, Wf, half);
-        m = group_mask<PX>(mq);
-        if constexpr (QM == kMaskStore) qmask_out[pos] = (uint8_t)(TILE >= 16 ? group_mask<2>(mq) : mq);
+        m = group_mask<PX>(quadrant_mask<TILE>(r, tx0, ty0, Wf, half));
       }
     }
     uint32_t within[St::NQ];
@@ -456,6 +453,7 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_fwd2_kernel(
   constexpr int N = St::N;
   constexpr int QPR = TILE / 8;
   __shared__ St S;
+  __shared__ uint8_t s_used[St::NQ][BATCH];  // as in the one-pixel forward, per wavefront group
   const int g = blockIdx.x;
   const int v = view_of_tile(vt, g);
   const int W = vt.W[v], H = vt.H[v];
@@ -470,11 +468,29 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_fwd2_kernel(
   const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
   const uint2 rg = ranges[g];
   FwdPixel A{1.0f, 0.0f, 0.0f, 0.0f, 0, false}, B{1.0f, 0.0f, 0.0f, 0.0f, 0, false};
+  // writes the masks of the batch walked last (after a barrier) and clears s_used for the next
+  auto flush_used = [&](uint32_t first, int n_walked) {
+    for (int e = threadIdx.x; e < BATCH; e += N) {
+      if (e < n_walked) {
+        uint32_t mg = 0;
+#pragma unroll
+        for (int q = 0; q < St::NQ; ++q) mg |= s_used[q][e] ? (1u << q) : 0u;
+        qmask[first + e] = (uint8_t)mg;
+      }
+#pragma unroll
+      for (int q = 0; q < St::NQ; ++q) s_used[q][e] = 0;
+    }
+  };
+  uint32_t walked_base = 0;
+  int walked_cnt = 0;
   for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
-    if (__syncthreads_count(A.done && B.done) == N) break;
+    const bool all_done = __syncthreads_count(A.done && B.done) == N;
+    flush_used(walked_base, walked_cnt);
+    walked_cnt = 0;
+    if (all_done) break;
     const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
     int nq[St::NQ];
-    stage_batch<TILE, BATCH, 2, kMaskStore>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq, nullptr, qmask);
+    stage_batch<TILE, BATCH, 2>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
       if (__builtin_amdgcn_ballot_w64(!(A.done && B.done)) == 0ull) break;  // uniform
@@ -491,12 +507,17 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_fwd2_kernel(
       const bool anya = __builtin_amdgcn_ballot_w64(oka) != 0ull;  // uniform
       const bool anyb = __builtin_amdgcn_ballot_w64(okb) != 0ull;
       if (!anya && !anyb) continue;
+      s_used[wq][k] = 1;  // reached by some pixel of the group (see the one-pixel forward)
       const float4 c = S.s2[k];
       const int pos = (int)(base - rg.x) + k + 1;
       if (anya) fwd_pixel_step(A, oka, pa, b, c, pos);
       if (anyb) fwd_pixel_step(B, okb, pb, b, c, pos);
     }
+    walked_base = base;
+    walked_cnt = cnt;
   }
+  __syncthreads();
+  flush_used(walked_base, walked_cnt);
   const int64_t plane = (int64_t)W * H;
   const int64_t pix = (int64_t)y * W + x;
   float* img = out_rgb + 3 * vt.pix_base[v];
@@ -628,7 +649,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
     int nq[St::NQ];
     // entry e is list position end - 1 - e (back to front)
     stage_batch<TILE, BATCH, 1, kMaskLoad>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq, nullptr,
-                                           nullptr, qmask);
+                                           qmask);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     bool pend = false;  // an accepted entry whose values 0..7 still wait in red (uniform)
     int pk = 0;
@@ -755,7 +776,7 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
     int nq[St::NQ];
     // entry e is list position end - 1 - e (back to front)
     stage_batch<TILE, BATCH, 2, kMaskLoad>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq, nullptr,
-                                           nullptr, qmask);
+                                           qmask);
     const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
     for (int i = 0; i < n; ++i) {
       const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);  // uniform entry index
