@@ -30,38 +30,34 @@ HBM_PEAK_GBS = 8000.0
 # FP32 vector issue rate without packed instructions: 256 CUs x 64 lanes x 2.4 GHz (lane-ops/s)
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
-# Algorithmic FP32 lane-operations per unit of compositing work (itemised in the design doc):
-#   a test = one (pixel, list entry) evaluation of the Gaussian's exponent and footprint test;
-#   an accept = one (pixel, Gaussian) contribution.
-OPS_FWD_TEST, OPS_FWD_ACCEPT = 14, 14
-OPS_BWD_TEST, OPS_BWD_ACCEPT = 15, 42
+# Algorithmic FP32 lane-operations per (pixel, list entry) evaluation of the compositors: about 9
+# when the entry is rejected (offset, exponent, footprint test) and about 23 (forward) or 50
+# (reverse) when it is accepted, exp included (the per-unit figures of the measurement plan).
+OPS_REJECT = 9
+OPS_FWD_ACCEPT, OPS_BWD_ACCEPT = 23, 50
+
+# Algorithmic HBM bytes of one fwd+bwd step (SH degree 3): per Gaussian, the parameters read
+# (236 B) in the forward, read again and their gradients written (236 + 236 B) in the backward,
+# once per step for all views; per (Gaussian, view) item a 48 B record and 16 B of scan state in
+# the forward and 40 B of 2D gradients in the backward; per Gaussian-tile pair 12 B emitted, >= 24 B
+# sorted and a 44 B record gathered by each compositor; per pixel 20 B written by the forward
+# (RGB, T, last index) and 20 B read by the backward (dL/dRGB, T, last index).
+def step_bytes(n, views, pairs, pixels):
+    return 3 * 236 * n + (48 + 16 + 40) * n * views + (12 + 24 + 44 + 44) * pairs + 40 * pixels
 
 
 PROFILE = os.path.join(ROOT, "profiles", "render_kernels_M_500k_8x2048x1024.txt")
 
 
-def kernel_source_hash() -> str:
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("paper_2410_20686_amd/csrc/render.hip", "paper_2410_20686_amd/csrc/common.h",
-              "paper_2410_20686_amd/csrc/wave.h"):
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of the reverse compositor from the committed rocprofv3 counter summary
-    (calibrated FETCH_SIZE + WRITE_SIZE), or None when the summary is missing, covers another
-    kernel instance, or was taken from different kernel source."""
-    try:
-        with open(PROFILE) as f:
-            kv = dict(line.split(": ", 1) for line in f.read().splitlines() if ": " in line and not line.startswith("#"))
-    except OSError:
+def profiled(kernel: str):
+    """The committed rocprofv3 summary's figures for one kernel (average duration, calibrated HBM
+    bytes per launch, ...), or None when the summary is missing, lacks the kernel, or was taken
+    from other compositor sources."""
+    from paper_2410_20686_amd import profiling
+    rows, src = profiling.read_summary(PROFILE)
+    if not rows or src != profiling.source_hash(ROOT):
         return None
-    if kv.get("kernel", "").strip() != kernel or kv.get("source_sha256_16", "").strip() != kernel_source_hash():
-        return None
-    return int(float(kv["traffic_bytes_per_launch"]))
+    return rows.get(kernel)
 
 
 def log(*a):
@@ -79,6 +75,9 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="Gaussian count (0: the workload's own)")
     ap.add_argument("--workload", default="M", choices=("M", "cfg0", "cfg1", "cfg2", "cfg3", "cfg4"),
                     help="M is the metric's workload; the others are context runs (same JSON fields)")
+    ap.add_argument("--schedule", default="persistent", choices=("persistent", "grid", "tile_id"),
+                    help="compositor tile scheduling: persistent longest-first queue (default), one workgroup "
+                         "per tile in queue order, or one workgroup per tile in tile id order")
     ap.add_argument("--autotune", action="store_true", help="pick the tile and batch sizes with the autotuner first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a known-size reference "
@@ -152,7 +151,7 @@ def main():
 
     t0 = time.time()
     sc, cams, st = scenes.config(args.workload, n=args.n or None)
-    st = dict(st, tile=args.tile, batch=args.batch, batch_bwd=args.batch_bwd)
+    st = dict(st, tile=args.tile, batch=args.batch, batch_bwd=args.batch_bwd, schedule=args.schedule)
     wh = [tuple(int(x) for x in r) for r in cams.wh]
     V = len(wh)
     mp_per_step = sum(w * h for w, h in wh) / 1e6
@@ -273,8 +272,8 @@ def main():
     # roofline of the dominant kernel (reverse compositing: one kernel per odgs_composite_bwd call)
     dom = max(stages, key=stages.get)
     alg_ops = {
-        "fwd": OPS_FWD_TEST * evals_fwd + OPS_FWD_ACCEPT * contrib_total,
-        "composite_bwd": OPS_BWD_TEST * evals_bwd + OPS_BWD_ACCEPT * contrib_total,
+        "fwd": OPS_REJECT * (evals_fwd - contrib_total) + OPS_FWD_ACCEPT * contrib_total,
+        "composite_bwd": OPS_REJECT * (evals_bwd - contrib_total) + OPS_BWD_ACCEPT * contrib_total,
     }
     roof = None
     if dom in alg_ops:
@@ -283,11 +282,24 @@ def main():
             kname = "odgs::render_bwd%s_kernel<%d, %d>" % ("2" if st["tile"] >= 16 else "", st["tile"],
                                                           rast.plan.s.batch_bwd)
         else:
-            kname = "odgs::render_fwd_kernel<%d, %d, false>" % (st["tile"], rast.plan.s.batch)
+            kname = "odgs::render_fwd%s_kernel<%d, %d%s>" % ("2" if st["tile"] >= 32 else "", st["tile"],
+                                                            rast.plan.s.batch, "" if st["tile"] >= 32 else
+                                                            ", false, false")
+        prof = profiled(kname)
         roof = dict(bound="alu", kernel=dom, achieved=round(achieved, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Top/s",
-                    frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=measured_traffic(kname),
+                    frac=round(achieved / ALU_PEAK_TOPS, 4),
+                    traffic=int(prof["traffic_bytes"]) if prof else None,
+                    ops_per_launch=alg_ops[dom], duration_us=round(stages[dom] * 1e3, 1),
+                    duration_us_profile=prof["avg_us"] if prof else None,
+                    hbm_frac_profile=prof["hbm_frac"] if prof else None,
+                    lds_frac_profile=prof["lds_frac"] if prof else None,
+                    valu_issue_profile=prof["valu_issue"] if prof else None,
                     work=dict(tests=evals_bwd if dom == "composite_bwd" else evals_fwd, accepts=contrib_total,
                               wave_iters=wave_iters[1] if dom == "composite_bwd" else wave_iters[0]))
+    # the whole step against the HBM roofline, with the algorithmic bytes of one step
+    sb = step_bytes(sc.n, V, int(status["n_pairs"]), sum(w * h for w, h in wh))
+    hbm_step = dict(bytes=sb, GBs=round(sb / (ms_batched / 1e3) / 1e9, 1),
+                    frac=round(sb / (ms_batched / 1e3) / (HBM_PEAK_GBS * 1e9), 4))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -315,13 +327,14 @@ def main():
                    "views %s" % (args.workload, sc.n, sorted(set(wh))),
                    "gaussians": sc.n, "views": V, "width": wh[0][0], "height": wh[0][1], "sh_degree": sc.sh_degree,
                    "tile": st["tile"], "batch": rast.plan.s.batch, "batch_bwd": rast.plan.s.batch_bwd,
-                   "pairs": status["n_pairs"],
+                   "pairs": status["n_pairs"], "schedule": args.schedule,
                    "autotuned": tuned is not None},
         "per_view": per_view,
         "train_iteration": train,
         "spherical_footprint": sph,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roof,
+        "hbm_step": hbm_step,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

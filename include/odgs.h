@@ -48,11 +48,21 @@ enum {
 
 #define ODGS_MAX_VIEWS 64
 #define ODGS_STATUS_OVERFLOW 1 /* more Gaussian-tile pairs than plan->pair_capacity */
+#define ODGS_STATUS_STALE_FORWARD 2 /* odgs_composite_bwd found no odgs_render_fwd of the current pair
+                                       list (none since the last odgs_bin_sort): it accumulated
+                                       nothing, so the 2D gradients stay zero */
 #define ODGS_FLAG_COUNT_WORK 1 /* settings flag: odgs_render_fwd also records the per-pixel work
                                   counters of odgs_debug_pixel_counts (slower; for measurement) */
 #define ODGS_FLAG_SPHERICAL 2  /* settings flag: spherical footprint instead of the local affine
                                   approximation, see below (not with pinhole views, not with
                                   ODGS_FLAG_COUNT_WORK, no densification statistics) */
+/* Scheduling of the two compositing launches, which cover the tiles of every view.  odgs_bin_sort
+ * ends by queueing all (view, tile) pairs by descending list length (its compositing cost).
+ * Default: persistent launches, as many workgroups as fit on the device, each claiming the next
+ * queue entry when it finishes a tile, so the longest tiles of all views start first and the
+ * short ones fill the tail.  The two flags below select the alternatives (measurement): */
+#define ODGS_FLAG_SCHED_GRID 4    /* one workgroup per tile, taking the queue in order */
+#define ODGS_FLAG_SCHED_TILE_ID 8 /* one workgroup per tile in global tile id order (no queue) */
 
 /* Spherical footprint (ODGS_FLAG_SPHERICAL).  The paper names its local affine approximation
  * of the projected Gaussian as its limitation (Sec. 5).  With this flag every pixel ray t d
@@ -83,13 +93,23 @@ typedef struct odgs_settings {
   int32_t flags;    /* ODGS_FLAG_* bits, 0 for none */
 } odgs_settings;
 
-/* Device status record at byte offset plan->off_status of the workspace. */
+/* Device status record at byte offset plan->off_status of the workspace.  odgs_preprocess resets
+ * every field except bin_gen. */
 typedef struct odgs_status {
   int32_t flags;      /* ODGS_STATUS_* bits */
   int32_t n_pairs_stored; /* min(n_pairs, pair_capacity): pairs actually sorted and rendered */
   int64_t n_pairs;    /* Gaussian-tile pairs P of the last odgs_preprocess */
   int64_t n_visible;  /* (Gaussian, view) items that survived culling */
-  int64_t reserved2;
+  uint32_t bin_gen;   /* incremented by every odgs_bin_sort (wraps) */
+  uint32_t fwd_gen;   /* bin_gen of the pair list the last odgs_render_fwd composited; set to
+                         ~bin_gen by odgs_preprocess and odgs_bin_sort.  The reverse compositor
+                         reads the forward's per-entry culling masks and per-pixel state, so it
+                         runs only when fwd_gen == bin_gen (else ODGS_STATUS_STALE_FORWARD) */
+  int64_t n_culled;   /* (Gaussian, view) items culled: outside the shell, at a pole, degenerate
+                         2D covariance, opacity below 1/255, no tile reached, or non-finite */
+  int64_t n_nonfinite; /* Gaussians with a NaN or infinite parameter (mean, scale, quaternion,
+                          opacity or SH coefficient) or a zero quaternion; all their items are
+                          culled */
 } odgs_status;
 
 /* Plain-data description of one workload and of its workspace layout.  Filled by
@@ -114,7 +134,7 @@ typedef struct odgs_plan {
   size_t off_status, off_rec, off_rect, off_count, off_depth, off_dkey[2], off_did[2], off_srect, off_blocksum, off_pkey[2],
       off_pval[2],
       off_hist, off_digit, off_ranges, off_T, off_last, off_ncontrib, off_neval,
-      off_lasteval, off_g2d, off_srec, off_cone, off_dirs;
+      off_lasteval, off_g2d, off_srec, off_cone, off_dirs, off_queue;
   int32_t depth_final;     /* which of the two depth-sort buffers holds the sorted result */
   int32_t pair_final;      /* which of the two pair buffers holds the sorted result */
   size_t ws_bytes;
@@ -308,11 +328,13 @@ int odgs_debug_records(const odgs_plan* plan, const void* ws, float* out, void* 
 int odgs_debug_pixel_counts(const odgs_plan* plan, const void* ws, int32_t* out, void* stream);
 
 /* Per-item 2D gradients accumulated by odgs_composite_bwd and not yet consumed by
- * odgs_project_bwd, float [items][9]: d/du, d/dv, d/dSigma_uu, d/dSigma_uv (the off-diagonal as
+ * odgs_project_bwd, double [items][9]: d/du, d/dv, d/dSigma_uu, d/dSigma_uv (the off-diagonal as
  * one shared variable), d/dSigma_vv (Sigma_2D with dilation), d/dopacity, d/dr, d/dg, d/db.
- * Spherical footprint: float [items][13]: d/dmu^ (3), d/dSigma~ (xx, xy, xz, yy, yz, zz; the
- * off-diagonals as one shared variable), d/dopacity, d/dr, d/dg, d/db. */
-int odgs_debug_g2d(const odgs_plan* plan, const void* ws, float* out, void* stream);
+ * Spherical footprint: double [items][13]: d/dmu^ (3), d/dSigma~ (xx, xy, xz, yy, yz, zz; the
+ * off-diagonals as one shared variable), d/dopacity, d/dr, d/dg, d/db.  Each tile's float sum
+ * over its pixels is added in double, so the cross-tile total does not depend on the order in
+ * which tiles finish (to double rounding, far below float resolution). */
+int odgs_debug_g2d(const odgs_plan* plan, const void* ws, double* out, void* stream);
 
 /* The sorted pair list as 64-bit keys (global tile << 32 | depth bits) and Gaussian indices,
  * first min(P, cap) entries (P from the status record, read by the caller). */

@@ -15,8 +15,12 @@ LIB_PATH = os.path.join(_HERE, "libodgs.so")
 MAX_VIEWS = 64
 OK, EINVAL, ENOSPACE, EHIP = 0, -1, -2, -3
 STATUS_OVERFLOW = 1
+STATUS_STALE_FORWARD = 2
 FLAG_COUNT_WORK = 1
 FLAG_SPHERICAL = 2
+FLAG_SCHED_GRID = 4
+FLAG_SCHED_TILE_ID = 8
+SCHEDULES = {"persistent": 0, "grid": FLAG_SCHED_GRID, "tile_id": FLAG_SCHED_TILE_ID}
 
 EXPORTS = ("odgs_plan_init", "odgs_plan_set_pinhole", "odgs_workspace_bytes", "odgs_preprocess", "odgs_bin_sort", "odgs_render_fwd",
            "odgs_render_bwd", "odgs_composite_bwd", "odgs_project_bwd", "odgs_status_offset", "odgs_strerror",
@@ -52,13 +56,14 @@ class DensifyParams(ctypes.Structure):
 
 class Status(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_int32), ("n_pairs_stored", ctypes.c_int32), ("n_pairs", ctypes.c_int64),
-                ("n_visible", ctypes.c_int64), ("reserved2", ctypes.c_int64)]
+                ("n_visible", ctypes.c_int64), ("bin_gen", ctypes.c_uint32), ("fwd_gen", ctypes.c_uint32),
+                ("n_culled", ctypes.c_int64), ("n_nonfinite", ctypes.c_int64)]
 
 
 _OFFSETS = ["off_status", "off_rec", "off_rect", "off_count", "off_depth", "off_dkey0", "off_dkey1", "off_did0", "off_did1", "off_srect",
             "off_blocksum", "off_pkey0", "off_pkey1", "off_pval0", "off_pval1", "off_hist", "off_digit",
             "off_ranges", "off_T", "off_last", "off_ncontrib", "off_neval", "off_lasteval", "off_g2d", "off_srec",
-            "off_cone", "off_dirs"]
+            "off_cone", "off_dirs", "off_queue"]
 
 
 class Plan(ctypes.Structure):
@@ -145,17 +150,22 @@ def _check(rc: int, what: str):
 
 
 def make_settings(tile=16, batch=0, batch_bwd=0, near=0.2, far=1e4, dilation=0.3, pole_eps=1e-4,
-                  bg=(0.0, 0.0, 0.0), count_work=False, footprint="affine") -> Settings:
+                  bg=(0.0, 0.0, 0.0), count_work=False, footprint="affine", schedule="persistent") -> Settings:
     """footprint: "affine" (the paper's local affine approximation) or "spherical"
-    (ODGS_FLAG_SPHERICAL: the exact per-ray maximum of each 3D Gaussian)."""
+    (ODGS_FLAG_SPHERICAL: the exact per-ray maximum of each 3D Gaussian).  schedule: the
+    compositors' tile scheduling, "persistent" (longest-first queue), "grid" (one workgroup per
+    tile in queue order) or "tile_id" (one workgroup per tile in tile id order)."""
     if footprint not in ("affine", "spherical"):
         raise ValueError("footprint must be 'affine' or 'spherical'")
+    if schedule not in SCHEDULES:
+        raise ValueError("schedule must be one of %s" % sorted(SCHEDULES))
     s = Settings()
     s.tile, s.batch, s.batch_bwd = int(tile), int(batch), int(batch_bwd)
     s.near_r, s.far_r, s.dilation, s.pole_eps = float(near), float(far), float(dilation), float(pole_eps)
     for k in range(3):
         s.bg[k] = float(bg[k])
-    s.flags = (FLAG_COUNT_WORK if count_work else 0) | (FLAG_SPHERICAL if footprint == "spherical" else 0)
+    s.flags = ((FLAG_COUNT_WORK if count_work else 0) | (FLAG_SPHERICAL if footprint == "spherical" else 0)
+               | SCHEDULES[schedule])
     return s
 
 

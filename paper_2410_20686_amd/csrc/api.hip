@@ -68,7 +68,9 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   if (st.batch == 0) st.batch = st.tile == 8 ? 64 : 256;
   if (st.batch_bwd == 0) st.batch_bwd = st.tile == 8 ? 32 : (st.tile == 16 ? 64 : 256);
   if (!batch_ok(st.tile, st.batch) || !batch_ok(st.tile, st.batch_bwd)) return ODGS_EINVAL;
-  if (st.flags & ~(ODGS_FLAG_COUNT_WORK | ODGS_FLAG_SPHERICAL)) return ODGS_EINVAL;
+  if (st.flags & ~(ODGS_FLAG_COUNT_WORK | ODGS_FLAG_SPHERICAL | ODGS_FLAG_SCHED_GRID | ODGS_FLAG_SCHED_TILE_ID))
+    return ODGS_EINVAL;
+  if ((st.flags & ODGS_FLAG_SCHED_GRID) && (st.flags & ODGS_FLAG_SCHED_TILE_ID)) return ODGS_EINVAL;
   if ((st.flags & ODGS_FLAG_COUNT_WORK) && (st.flags & ODGS_FLAG_SPHERICAL)) return ODGS_EINVAL;
   if (!(st.near_r >= 0.0f) || !(st.far_r > st.near_r) || !(st.dilation >= 0.0f) || !(st.pole_eps >= 0.0f))
     return ODGS_EINVAL;
@@ -137,7 +139,8 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   plan->off_lasteval = take((size_t)pixels * 4);
   const bool sph = (st.flags & ODGS_FLAG_SPHERICAL) != 0;
   plan->g2d_stride = sph ? 13 : 9;
-  plan->off_g2d = take((size_t)plan->g2d_stride * I * 4);
+  plan->off_g2d = take((size_t)plan->g2d_stride * I * 8);  // double
+  plan->off_queue = take(64 + (size_t)tiles * 4);  // counters (forward, reverse), then the tile queue
   int64_t dirs = 0;
   for (int v = 0; v < n_views; ++v) dirs += plan->width[v] + plan->height[v];
   plan->off_srec = take(sph ? (size_t)I * sizeof(SphRec) : 0);
@@ -306,7 +309,7 @@ int odgs_debug_records(const odgs_plan* plan, const void* ws, float* out, void* 
   return hip_status(launch_debug_records(plan, ws, out, static_cast<hipStream_t>(stream)));
 }
 
-int odgs_debug_g2d(const odgs_plan* plan, const void* ws, float* out, void* stream) {
+int odgs_debug_g2d(const odgs_plan* plan, const void* ws, double* out, void* stream) {
   if (!plan || !ws || (plan->items > 0 && !out)) return ODGS_EINVAL;
   return hip_status(launch_debug_g2d(plan, ws, out, static_cast<hipStream_t>(stream)));
 }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "../../include/odgs.h"
 
 namespace odgs {
@@ -69,6 +71,51 @@ __device__ inline int view_of_tile(const ViewTable& vt, int32_t g) {
 
 __device__ inline int view_of_item(int64_t item, int64_t n) { return (int)(item / n); }
 
+// Tile scheduling of the compositors (one launch covers the tiles of every view).  Binning ends
+// by building a work queue of all global tile ids, longest list first.  Persistent launches (as
+// many workgroups as fit on the device at once) claim queue entries one at a time with an atomic
+// counter, the last workgroup to find the queue empty clearing the counters for the next launch;
+// otherwise one workgroup per tile takes queue entry blockIdx.x (order == nullptr: tile id
+// blockIdx.x, no queue).
+struct TileSched {
+  const uint32_t* order;  // tile ids by descending list length, or nullptr
+  uint32_t* ctr;          // persistent: {next queue entry, finished workgroups}; nullptr: one tile each
+  odgs_status* status;
+  int32_t tiles;
+};
+
+// Next tile of this workgroup (uniform), or -1 when it is done.  `round` starts at 0; `slot` is
+// a workgroup-shared word.  Contains barriers in persistent mode.
+__device__ inline int claim_tile(const TileSched& s, uint32_t& round, uint32_t* slot) {
+  if (!s.ctr) {
+    if (round++) return -1;
+    return s.order ? (int)s.order[blockIdx.x] : (int)blockIdx.x;
+  }
+  __syncthreads();  // every thread has read the previous claim
+  if (threadIdx.x == 0) {
+    const uint32_t e = atomicAdd(&s.ctr[0], 1u);
+    // queue drained: every workgroup passes here once, so the last one resets the counters
+    if (e >= (uint32_t)s.tiles && atomicAdd(&s.ctr[1], 1u) == gridDim.x - 1) {
+      atomicExch(&s.ctr[0], 0u);
+      atomicExch(&s.ctr[1], 0u);
+    }
+    *slot = e;
+  }
+  __syncthreads();
+  const uint32_t e = *slot;
+  return e < (uint32_t)s.tiles ? (int)s.order[e] : -1;
+}
+
+// The forward marks the pair list it composited; the reverse compositor runs only on that list.
+__device__ inline void mark_forward(const TileSched& s) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) s.status->fwd_gen = s.status->bin_gen;
+}
+__device__ inline bool forward_is_stale(const TileSched& s) {
+  const bool stale = s.status->fwd_gen != s.status->bin_gen;
+  if (stale && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&s.status->flags, ODGS_STATUS_STALE_FORWARD);
+  return stale;
+}
+
 inline ViewTable make_view_table(const odgs_plan* p) {
   ViewTable vt{};
   vt.n_views = p->n_views;
@@ -123,9 +170,27 @@ hipError_t launch_adam_step(int64_t n, int32_t sh_degree, const odgs_param_ptrs&
                             const float* lr, int32_t* step, const odgs_adam_hyper& hp, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* ptr, uint32_t value, int64_t n, hipStream_t st);
 hipError_t launch_status_reset(const odgs_plan* p, void* ws, hipStream_t st);
+// Scheduling of a compositor launch: the queue, and for persistent launches the counter pair
+// (which = 0 forward, 1 reverse) and the grid that fits `per_cu` workgroups on every CU.
+TileSched make_sched(const odgs_plan* p, void* ws, int which);
+int sched_grid(const TileSched& s, int per_cu);
+
+// Launch of a compositor kernel whose last parameter is its TileSched: a persistent launch sizes
+// its grid from the kernel's occupancy (workgroups resident per CU); otherwise one workgroup per
+// tile.
+template <typename... KArgs, typename... Args>
+inline void launch_sched(void (*kernel)(KArgs...), const TileSched& s, int threads, hipStream_t st, Args&&... args) {
+  int grid = s.tiles;
+  if (s.ctr) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess) per_cu = 1;
+    grid = sched_grid(s, per_cu);
+  }
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), 0, st, std::forward<Args>(args)..., s);
+}
 hipError_t launch_debug_records(const odgs_plan* p, const void* ws, float* out, hipStream_t st);
 hipError_t launch_debug_pixel_counts(const odgs_plan* p, const void* ws, int32_t* out, hipStream_t st);
-hipError_t launch_debug_g2d(const odgs_plan* p, const void* ws, float* out, hipStream_t st);
+hipError_t launch_debug_g2d(const odgs_plan* p, const void* ws, double* out, hipStream_t st);
 hipError_t launch_debug_keys(const odgs_plan* p, const void* ws, int64_t cap, uint64_t* keys, uint32_t* gauss,
                              hipStream_t st);
 

@@ -504,10 +504,18 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
   float coef[K * 3];
 #pragma unroll
   for (int k = 0; k < K * 3; ++k) coef[k] = sh[(int64_t)k * n + ii];
+  // a NaN or infinite parameter, or a zero quaternion: every item of the Gaussian is culled
+  bool fin = isfinite(o) && (q[0] != 0.0 || q[1] != 0.0 || q[2] != 0.0 || q[3] != 0.0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) fin = fin && isfinite(m[k]) && isfinite(s[k]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) fin = fin && isfinite(q[k]);
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) fin = fin && isfinite(coef[k]);
   Cov3 cv;
   cov3(s, q, cv);
   const double p_min = -log(255.0 * (double)o);
-  unsigned long long visible = 0;
+  unsigned long long visible = 0, culled = 0;
 
   for (int v = 0; v < vt.n_views; ++v) {
     Cam cam;
@@ -515,7 +523,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
     const int W = vt.W[v], H = vt.H[v];
     Geo g;
     const Pin pin{(double)vt.pin[v][0], (double)vt.pin[v][1], (double)vt.pin[v][2], (double)vt.pin[v][3]};
-    bool kept = live && geometry(m, cam, cv, W, H, P, pin, g);
+    bool kept = live && fin && geometry(m, cam, cv, W, H, P, pin, g);
     float depth = (float)g.depth;
     Rec out;
     Rect rr{0, 0, 0, 0};
@@ -609,12 +617,21 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
       dkey[item] = kept ? __float_as_uint(depth) : 0xffffffffu;
     }
     visible += kept ? 1 : 0;
+    culled += (live && !kept) ? 1 : 0;
   }
-  // one atomic per wave for the visible-item counter
-  unsigned long long tot = visible;
+  // one atomic per wave for each counter
+  unsigned long long tot = visible, tcul = culled, tnf = (live && !fin) ? 1 : 0;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-  if ((threadIdx.x & (kWave - 1)) == 0 && tot) atomicAdd((unsigned long long*)&status->n_visible, tot);
+  for (int off = 32; off > 0; off >>= 1) {
+    tot += __shfl_xor(tot, off);
+    tcul += __shfl_xor(tcul, off);
+    tnf += __shfl_xor(tnf, off);
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (tot) atomicAdd((unsigned long long*)&status->n_visible, tot);
+    if (tcul) atomicAdd((unsigned long long*)&status->n_culled, tcul);
+    if (tnf) atomicAdd((unsigned long long*)&status->n_nonfinite, tnf);
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -670,7 +687,7 @@ template <int K>
 __global__ __launch_bounds__(256) void colour_bwd_kernel(int64_t n, const float* __restrict__ means,
                                                          const float* __restrict__ sh, const float* __restrict__ cams,
                                                          ViewTable vt, const uint32_t* __restrict__ count,
-                                                         const float* __restrict__ g2d, int stride, int off,
+                                                         const double* __restrict__ g2d, int stride, int off,
                                                          float* __restrict__ d_means, float* __restrict__ d_sh) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -687,8 +704,7 @@ __global__ __launch_bounds__(256) void colour_bwd_kernel(int64_t n, const float*
   for (int v = 0; v < vt.n_views; ++v) {
     const int64_t item = (int64_t)v * n + i;
     if (count[item] == 0) continue;
-    const double gcol[3] = {(double)g2d[item * stride + off], (double)g2d[item * stride + off + 1],
-                            (double)g2d[item * stride + off + 2]};
+    const double gcol[3] = {g2d[item * stride + off], g2d[item * stride + off + 1], g2d[item * stride + off + 2]};
     if (gcol[0] == 0.0 && gcol[1] == 0.0 && gcol[2] == 0.0) continue;
     Cam cam;
     load_cam(cams, v, cam);
@@ -748,7 +764,7 @@ template <int K, bool STATS>
 __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     int64_t n, const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
     const float* __restrict__ opac, const float* __restrict__ sh, const float* __restrict__ cams, ViewTable vt, Params P,
-    const uint32_t* __restrict__ count, float* __restrict__ g2d, int64_t items, float* __restrict__ d_means,
+    const uint32_t* __restrict__ count, double* __restrict__ g2d, int64_t items, float* __restrict__ d_means,
     float* __restrict__ d_scales, float* __restrict__ d_quats, float* __restrict__ d_opac, float* __restrict__ d_sh,
     DensAcc dacc) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -776,7 +792,7 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     bool any = false;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      g[k] = (double)g2d[item * 9 + k];
+      g[k] = g2d[item * 9 + k];
       any = any || g[k] != 0.0;
     }
     if (STATS) {
@@ -797,7 +813,7 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     if (!any) continue;
     // consumed: leave the accumulators cleared for the next reverse compositing pass
 #pragma unroll
-    for (int k = 0; k < 9; ++k) g2d[item * 9 + k] = 0.0f;
+    for (int k = 0; k < 9; ++k) g2d[item * 9 + k] = 0.0;
     Cam cam;
     load_cam(cams, v, cam);
     Geo G;
@@ -889,7 +905,7 @@ template <int K>
 __global__ __launch_bounds__(256) void preprocess_sph_bwd_kernel(
     int64_t n, const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
     const float* __restrict__ opac, const float* __restrict__ sh, const float* __restrict__ cams, ViewTable vt, Params P,
-    const uint32_t* __restrict__ count, float* __restrict__ g2d, float* __restrict__ d_means,
+    const uint32_t* __restrict__ count, double* __restrict__ g2d, float* __restrict__ d_means,
     float* __restrict__ d_scales, float* __restrict__ d_quats, float* __restrict__ d_opac, float* __restrict__ d_sh) {
   constexpr int NV = 13;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -913,12 +929,12 @@ __global__ __launch_bounds__(256) void preprocess_sph_bwd_kernel(
     bool any = false;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      g[k] = (double)g2d[item * NV + k];
+      g[k] = g2d[item * NV + k];
       any = any || g[k] != 0.0;
     }
     if (!any) continue;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) g2d[item * NV + k] = 0.0f;
+    for (int k = 0; k < NV; ++k) g2d[item * NV + k] = 0.0;
     Cam cam;
     load_cam(cams, v, cam);
     Geo G;
@@ -1020,7 +1036,7 @@ hipError_t launch_preprocess_bwd(const odgs_plan* p, const float* means, const f
   const Params P = make_params(p);
   const unsigned grid = (unsigned)((p->n + 255) / 256);
   const uint32_t* count = ws_ptr<uint32_t>(ws, p->off_count);
-  float* g2d = ws_ptr<float>(ws, p->off_g2d);
+  double* g2d = ws_ptr<double>(ws, p->off_g2d);
   // colour part first (writes d_sh and the colour path of d_means), then the geometry part,
   // which adds to d_means and clears the consumed records
   const int stride = p->g2d_stride, off = p->g2d_stride - 3;

@@ -302,7 +302,8 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
     float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
     int32_t* __restrict__ ws_ncontrib, int32_t* __restrict__ ws_neval, int32_t* __restrict__ ws_lasteval, float bg0,
-    float bg1, float bg2, const float* __restrict__ depth, float* __restrict__ out_depth, uint8_t* __restrict__ qmask) {
+    float bg1, float bg2, const float* __restrict__ depth, float* __restrict__ out_depth, uint8_t* __restrict__ qmask,
+    TileSched sc) {
   using St = Stage<TILE, BATCH>;
   constexpr int N = St::N;
   __shared__ St S;
@@ -312,112 +313,116 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
   // backward must visit the entry for (and little else); that mask, in the backward's
   // granularity, is what the backward loads.
   __shared__ uint8_t s_used[St::NQ][BATCH];
-  const int g = blockIdx.x;
-  const int v = view_of_tile(vt, g);
-  const int W = vt.W[v], H = vt.H[v];
-  const int ntx = W / TILE;
-  const int lt = g - vt.tile_base[v];
-  const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
-  int lx, ly;
-  local_pixel<TILE>(threadIdx.x, lx, ly);
-  const int x = tx0 + lx, y = ty0 + ly;
-  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // this wavefront's quadrant (uniform)
-  const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-  const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
-  const uint2 rg = ranges[g];
-  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f;
-  int last = 0, ncontrib = 0, nev = 0, lastev = 0;
-  // 0 while the pixel composites, NaN once it has stopped: added to the exponent's sum of squares
-  // it makes the accept compare itself false for every later Gaussian (with 0 the sum is the same
-  // float), so the wavefront's ballots are of single compares
-  float qstop = 0.0f;
-  // writes the masks of the batch walked last (after a barrier) and clears s_used for the next
-  auto flush_used = [&](uint32_t first, int n_walked) {
-    for (int e = threadIdx.x; e < BATCH; e += N) {
-      if (e < n_walked) {
-        uint32_t mq = 0;
+  mark_forward(sc);
+  __shared__ uint32_t s_claim;
+  uint32_t round = 0;
+  for (int g; (g = claim_tile(sc, round, &s_claim)) >= 0;) {
+    const int v = view_of_tile(vt, g);
+    const int W = vt.W[v], H = vt.H[v];
+    const int ntx = W / TILE;
+    const int lt = g - vt.tile_base[v];
+    const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+    int lx, ly;
+    local_pixel<TILE>(threadIdx.x, lx, ly);
+    const int x = tx0 + lx, y = ty0 + ly;
+    const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // this wavefront's quadrant (uniform)
+    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
+    const uint2 rg = ranges[g];
+    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f;
+    int last = 0, ncontrib = 0, nev = 0, lastev = 0;
+    // 0 while the pixel composites, NaN once it has stopped: added to the exponent's sum of squares
+    // it makes the accept compare itself false for every later Gaussian (with 0 the sum is the same
+    // float), so the wavefront's ballots are of single compares
+    float qstop = 0.0f;
+    // writes the masks of the batch walked last (after a barrier) and clears s_used for the next
+    auto flush_used = [&](uint32_t first, int n_walked) {
+      for (int e = threadIdx.x; e < BATCH; e += N) {
+        if (e < n_walked) {
+          uint32_t mq = 0;
 #pragma unroll
-        for (int q = 0; q < St::NQ; ++q) mq |= s_used[q][e] ? (1u << q) : 0u;
-        qmask[first + e] = (uint8_t)(TILE >= 16 ? group_mask<2>(mq) : mq);
-      }
+          for (int q = 0; q < St::NQ; ++q) mq |= s_used[q][e] ? (1u << q) : 0u;
+          qmask[first + e] = (uint8_t)(TILE >= 16 ? group_mask<2>(mq) : mq);
+        }
 #pragma unroll
-      for (int q = 0; q < St::NQ; ++q) s_used[q][e] = 0;
-    }
-  };
-  uint32_t walked_base = 0;
-  int walked_cnt = 0;
-  for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
-    const bool all_done = __syncthreads_count(!(qstop == 0.0f)) == N;
-    flush_used(walked_base, walked_cnt);
-    walked_cnt = 0;
-    if (all_done) break;
-    const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
-    int nq[St::NQ];
-    const bool nowrap =
-        stage_batch<TILE, BATCH>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq, DEPTH ? depth : nullptr);
-    const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
-    // one list walk, instantiated without the seam wrap for batches where it is the identity
-    auto walk = [&](auto wrapc) {
-    for (int i = 0; i < n; ++i) {
-      if (__builtin_amdgcn_ballot_w64(qstop == 0.0f) == 0ull) break;  // uniform: every pixel has finished
-      const int k = S.list[wq][i];
-      const float4 a = S.s0[k];
-      const float4 b = S.s1[k];
-      const float du = decltype(wrapc)::value ? wrap_du(px - a.x, Wf, half) : px - a.x;
-      const float dv = py - a.y;
-      const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
-      const float power = -fmaf(t1, t1, fmaf(t2, t2, qstop));
-      if (COUNT) nev += qstop == 0.0f ? 1 : 0;
-      // alpha >= 1/255 (power <= 0 always: a sum of squares; NaN once stopped)
-      const bool ok = power >= b.y;
-      if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
-      // some pixel of this quadrant reaches the entry (it is accepted there unless that pixel
-      // stops at it, in which case the backward does not need it for that pixel: a superset)
-      s_used[wq][k] = 1;
-      const float alpha = fminf(b.z * __expf(power), kAlphaMax);
-      const float Tn = T * (1.0f - alpha);
-      const bool acc = ok && !(Tn < kTStop);
-      qstop = ok != acc ? __builtin_nanf("") : qstop;  // stop: reached, but T would drop below 1e-4
-      const float4 c = S.s2[k];
-      const float w = (acc ? alpha : 0.0f) * T;  // (a select of the product compiles to a branch here)
-      C0 = fmaf(w, c.x, C0);
-      C1 = fmaf(w, c.y, C1);
-      C2 = fmaf(w, c.z, C2);
-      if (DEPTH) D = D + w * S.dep[k];
-      T = acc ? Tn : T;
-      last = acc ? (int)(base - rg.x) + k + 1 : last;
-      if (COUNT) {
-        lastev = acc ? nev : lastev;
-        ncontrib += acc ? 1 : 0;
+        for (int q = 0; q < St::NQ; ++q) s_used[q][e] = 0;
       }
-
-    }
     };
-    if (nowrap)
-      walk(std::false_type{});
-    else
-      walk(std::true_type{});
-    walked_base = base;
-    walked_cnt = cnt;
+    uint32_t walked_base = 0;
+    int walked_cnt = 0;
+    for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
+      const bool all_done = __syncthreads_count(!(qstop == 0.0f)) == N;
+      flush_used(walked_base, walked_cnt);
+      walked_cnt = 0;
+      if (all_done) break;
+      const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
+      int nq[St::NQ];
+      const bool nowrap =
+          stage_batch<TILE, BATCH>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq, DEPTH ? depth : nullptr);
+      const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
+      // one list walk, instantiated without the seam wrap for batches where it is the identity
+      auto walk = [&](auto wrapc) {
+      for (int i = 0; i < n; ++i) {
+        if (__builtin_amdgcn_ballot_w64(qstop == 0.0f) == 0ull) break;  // uniform: every pixel has finished
+        const int k = S.list[wq][i];
+        const float4 a = S.s0[k];
+        const float4 b = S.s1[k];
+        const float du = decltype(wrapc)::value ? wrap_du(px - a.x, Wf, half) : px - a.x;
+        const float dv = py - a.y;
+        const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
+        const float power = -fmaf(t1, t1, fmaf(t2, t2, qstop));
+        if (COUNT) nev += qstop == 0.0f ? 1 : 0;
+        // alpha >= 1/255 (power <= 0 always: a sum of squares; NaN once stopped)
+        const bool ok = power >= b.y;
+        if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
+        // some pixel of this quadrant reaches the entry (it is accepted there unless that pixel
+        // stops at it, in which case the backward does not need it for that pixel: a superset)
+        s_used[wq][k] = 1;
+        const float alpha = fminf(b.z * __expf(power), kAlphaMax);
+        const float Tn = T * (1.0f - alpha);
+        const bool acc = ok && !(Tn < kTStop);
+        qstop = ok != acc ? __builtin_nanf("") : qstop;  // stop: reached, but T would drop below 1e-4
+        const float4 c = S.s2[k];
+        const float w = (acc ? alpha : 0.0f) * T;  // (a select of the product compiles to a branch here)
+        C0 = fmaf(w, c.x, C0);
+        C1 = fmaf(w, c.y, C1);
+        C2 = fmaf(w, c.z, C2);
+        if (DEPTH) D = D + w * S.dep[k];
+        T = acc ? Tn : T;
+        last = acc ? (int)(base - rg.x) + k + 1 : last;
+        if (COUNT) {
+          lastev = acc ? nev : lastev;
+          ncontrib += acc ? 1 : 0;
+        }
+
+      }
+      };
+      if (nowrap)
+        walk(std::false_type{});
+      else
+        walk(std::true_type{});
+      walked_base = base;
+      walked_cnt = cnt;
+    }
+    __syncthreads();
+    flush_used(walked_base, walked_cnt);
+    const int64_t plane = (int64_t)W * H;
+    const int64_t pix = (int64_t)y * W + x;
+    float* img = out_rgb + 3 * vt.pix_base[v];
+    img[pix] = fmaf(T, bg0, C0);
+    img[plane + pix] = fmaf(T, bg1, C1);
+    img[2 * plane + pix] = fmaf(T, bg2, C2);
+    const int64_t gp = vt.pix_base[v] + pix;
+    ws_T[gp] = T;
+    ws_last[gp] = last;
+    if (COUNT) {
+      ws_ncontrib[gp] = ncontrib;
+      ws_neval[gp] = nev;
+      ws_lasteval[gp] = lastev;
+    }
+    if (DEPTH) out_depth[gp] = D;
+    if (out_T) out_T[gp] = T;
   }
-  __syncthreads();
-  flush_used(walked_base, walked_cnt);
-  const int64_t plane = (int64_t)W * H;
-  const int64_t pix = (int64_t)y * W + x;
-  float* img = out_rgb + 3 * vt.pix_base[v];
-  img[pix] = fmaf(T, bg0, C0);
-  img[plane + pix] = fmaf(T, bg1, C1);
-  img[2 * plane + pix] = fmaf(T, bg2, C2);
-  const int64_t gp = vt.pix_base[v] + pix;
-  ws_T[gp] = T;
-  ws_last[gp] = last;
-  if (COUNT) {
-    ws_ncontrib[gp] = ncontrib;
-    ws_neval[gp] = nev;
-    ws_lasteval[gp] = lastev;
-  }
-  if (DEPTH) out_depth[gp] = D;
-  if (out_T) out_T[gp] = T;
 }
 
 // Forward compositing state of one pixel.
@@ -448,93 +453,97 @@ template <int TILE, int BATCH>
 __global__ __launch_bounds__(TILE* TILE / 2) void render_fwd2_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
     float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
-    float bg0, float bg1, float bg2, uint8_t* __restrict__ qmask) {
+    float bg0, float bg1, float bg2, uint8_t* __restrict__ qmask, TileSched sc) {
   using St = Stage<TILE, BATCH, 2>;
   constexpr int N = St::N;
   constexpr int QPR = TILE / 8;
   __shared__ St S;
   __shared__ uint8_t s_used[St::NQ][BATCH];  // as in the one-pixel forward, per wavefront group
-  const int g = blockIdx.x;
-  const int v = view_of_tile(vt, g);
-  const int W = vt.W[v], H = vt.H[v];
-  const int ntx = W / TILE;
-  const int lt = g - vt.tile_base[v];
-  const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int qa = 2 * wq;
-  const int x = tx0 + (qa % QPR) * 8 + (lane & 7), y = ty0 + (qa / QPR) * 8 + (lane >> 3);
-  const float pxa = (float)x + 0.5f, pxb = (float)(x + 8) + 0.5f, py = (float)y + 0.5f;
-  const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
-  const uint2 rg = ranges[g];
-  FwdPixel A{1.0f, 0.0f, 0.0f, 0.0f, 0, false}, B{1.0f, 0.0f, 0.0f, 0.0f, 0, false};
-  // writes the masks of the batch walked last (after a barrier) and clears s_used for the next
-  auto flush_used = [&](uint32_t first, int n_walked) {
-    for (int e = threadIdx.x; e < BATCH; e += N) {
-      if (e < n_walked) {
-        uint32_t mg = 0;
+  mark_forward(sc);
+  __shared__ uint32_t s_claim;
+  uint32_t round = 0;
+  for (int g; (g = claim_tile(sc, round, &s_claim)) >= 0;) {
+    const int v = view_of_tile(vt, g);
+    const int W = vt.W[v], H = vt.H[v];
+    const int ntx = W / TILE;
+    const int lt = g - vt.tile_base[v];
+    const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int qa = 2 * wq;
+    const int x = tx0 + (qa % QPR) * 8 + (lane & 7), y = ty0 + (qa / QPR) * 8 + (lane >> 3);
+    const float pxa = (float)x + 0.5f, pxb = (float)(x + 8) + 0.5f, py = (float)y + 0.5f;
+    const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
+    const uint2 rg = ranges[g];
+    FwdPixel A{1.0f, 0.0f, 0.0f, 0.0f, 0, false}, B{1.0f, 0.0f, 0.0f, 0.0f, 0, false};
+    // writes the masks of the batch walked last (after a barrier) and clears s_used for the next
+    auto flush_used = [&](uint32_t first, int n_walked) {
+      for (int e = threadIdx.x; e < BATCH; e += N) {
+        if (e < n_walked) {
+          uint32_t mg = 0;
 #pragma unroll
-        for (int q = 0; q < St::NQ; ++q) mg |= s_used[q][e] ? (1u << q) : 0u;
-        qmask[first + e] = (uint8_t)mg;
+          for (int q = 0; q < St::NQ; ++q) mg |= s_used[q][e] ? (1u << q) : 0u;
+          qmask[first + e] = (uint8_t)mg;
+        }
+#pragma unroll
+        for (int q = 0; q < St::NQ; ++q) s_used[q][e] = 0;
       }
-#pragma unroll
-      for (int q = 0; q < St::NQ; ++q) s_used[q][e] = 0;
+    };
+    uint32_t walked_base = 0;
+    int walked_cnt = 0;
+    for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
+      const bool all_done = __syncthreads_count(A.done && B.done) == N;
+      flush_used(walked_base, walked_cnt);
+      walked_cnt = 0;
+      if (all_done) break;
+      const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
+      int nq[St::NQ];
+      stage_batch<TILE, BATCH, 2>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq);
+      const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
+      for (int i = 0; i < n; ++i) {
+        if (__builtin_amdgcn_ballot_w64(!(A.done && B.done)) == 0ull) break;  // uniform
+        const int k = S.list[wq][i];
+        const float4 a = S.s0[k];
+        const float4 b = S.s1[k];
+        const float dv = py - a.y;
+        const float l1dv = a.w * dv, t2 = b.x * dv, t22 = t2 * t2;
+        const float dua = wrap_du(pxa - a.x, Wf, half), dub = wrap_du(pxb - a.x, Wf, half);
+        const float t1a = fmaf(a.z, dua, l1dv), t1b = fmaf(a.z, dub, l1dv);
+        const float pa = -fmaf(t1a, t1a, t22), pb = -fmaf(t1b, t1b, t22);
+        const bool oka = !A.done && !(pa > 0.0f || pa < b.y);
+        const bool okb = !B.done && !(pb > 0.0f || pb < b.y);
+        const bool anya = __builtin_amdgcn_ballot_w64(oka) != 0ull;  // uniform
+        const bool anyb = __builtin_amdgcn_ballot_w64(okb) != 0ull;
+        if (!anya && !anyb) continue;
+        s_used[wq][k] = 1;  // reached by some pixel of the group (see the one-pixel forward)
+        const float4 c = S.s2[k];
+        const int pos = (int)(base - rg.x) + k + 1;
+        if (anya) fwd_pixel_step(A, oka, pa, b, c, pos);
+        if (anyb) fwd_pixel_step(B, okb, pb, b, c, pos);
+      }
+      walked_base = base;
+      walked_cnt = cnt;
     }
-  };
-  uint32_t walked_base = 0;
-  int walked_cnt = 0;
-  for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
-    const bool all_done = __syncthreads_count(A.done && B.done) == N;
+    __syncthreads();
     flush_used(walked_base, walked_cnt);
-    walked_cnt = 0;
-    if (all_done) break;
-    const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
-    int nq[St::NQ];
-    stage_batch<TILE, BATCH, 2>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq);
-    const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
-    for (int i = 0; i < n; ++i) {
-      if (__builtin_amdgcn_ballot_w64(!(A.done && B.done)) == 0ull) break;  // uniform
-      const int k = S.list[wq][i];
-      const float4 a = S.s0[k];
-      const float4 b = S.s1[k];
-      const float dv = py - a.y;
-      const float l1dv = a.w * dv, t2 = b.x * dv, t22 = t2 * t2;
-      const float dua = wrap_du(pxa - a.x, Wf, half), dub = wrap_du(pxb - a.x, Wf, half);
-      const float t1a = fmaf(a.z, dua, l1dv), t1b = fmaf(a.z, dub, l1dv);
-      const float pa = -fmaf(t1a, t1a, t22), pb = -fmaf(t1b, t1b, t22);
-      const bool oka = !A.done && !(pa > 0.0f || pa < b.y);
-      const bool okb = !B.done && !(pb > 0.0f || pb < b.y);
-      const bool anya = __builtin_amdgcn_ballot_w64(oka) != 0ull;  // uniform
-      const bool anyb = __builtin_amdgcn_ballot_w64(okb) != 0ull;
-      if (!anya && !anyb) continue;
-      s_used[wq][k] = 1;  // reached by some pixel of the group (see the one-pixel forward)
-      const float4 c = S.s2[k];
-      const int pos = (int)(base - rg.x) + k + 1;
-      if (anya) fwd_pixel_step(A, oka, pa, b, c, pos);
-      if (anyb) fwd_pixel_step(B, okb, pb, b, c, pos);
+    const int64_t plane = (int64_t)W * H;
+    const int64_t pix = (int64_t)y * W + x;
+    float* img = out_rgb + 3 * vt.pix_base[v];
+    img[pix] = fmaf(A.T, bg0, A.C0);
+    img[plane + pix] = fmaf(A.T, bg1, A.C1);
+    img[2 * plane + pix] = fmaf(A.T, bg2, A.C2);
+    img[pix + 8] = fmaf(B.T, bg0, B.C0);
+    img[plane + pix + 8] = fmaf(B.T, bg1, B.C1);
+    img[2 * plane + pix + 8] = fmaf(B.T, bg2, B.C2);
+    const int64_t gp = vt.pix_base[v] + pix;
+    ws_T[gp] = A.T;
+    ws_T[gp + 8] = B.T;
+    ws_last[gp] = A.last;
+    ws_last[gp + 8] = B.last;
+    if (out_T) {
+      out_T[gp] = A.T;
+      out_T[gp + 8] = B.T;
     }
-    walked_base = base;
-    walked_cnt = cnt;
-  }
-  __syncthreads();
-  flush_used(walked_base, walked_cnt);
-  const int64_t plane = (int64_t)W * H;
-  const int64_t pix = (int64_t)y * W + x;
-  float* img = out_rgb + 3 * vt.pix_base[v];
-  img[pix] = fmaf(A.T, bg0, A.C0);
-  img[plane + pix] = fmaf(A.T, bg1, A.C1);
-  img[2 * plane + pix] = fmaf(A.T, bg2, A.C2);
-  img[pix + 8] = fmaf(B.T, bg0, B.C0);
-  img[plane + pix + 8] = fmaf(B.T, bg1, B.C1);
-  img[2 * plane + pix + 8] = fmaf(B.T, bg2, B.C2);
-  const int64_t gp = vt.pix_base[v] + pix;
-  ws_T[gp] = A.T;
-  ws_T[gp + 8] = B.T;
-  ws_last[gp] = A.last;
-  ws_last[gp + 8] = B.last;
-  if (out_T) {
-    out_T[gp] = A.T;
-    out_T[gp + 8] = B.T;
   }
 }
 
@@ -588,9 +597,9 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
                                                                 const uint32_t* __restrict__ pair_items,
                                                                 const Rec* __restrict__ rec, const float* __restrict__ ws_T,
                                                                 const int32_t* __restrict__ ws_last,
-                                                                const float* __restrict__ dL_drgb, float* __restrict__ g2d,
+                                                                const float* __restrict__ dL_drgb, double* __restrict__ g2d,
                                                                 int64_t items, float bg0, float bg1, float bg2,
-                                                                const uint8_t* __restrict__ qmask) {
+                                                                const uint8_t* __restrict__ qmask, TileSched sc) {
   static_assert(TILE == 8, "tiles of 16 and 32 take the two-pixel kernel (the stored masks are per two quadrants)");
   using St = Stage<TILE, BATCH>;
   constexpr int N = St::N;
@@ -602,112 +611,116 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   __shared__ float acc[NS][9][BATCH + 1];  // padded rows: the nine slot writes hit nine banks
   __shared__ float red[kSlots ? St::NW : 1][8][kRedStride];  // per-wavefront reduction scratch
   __shared__ int smax;
-  const int g = blockIdx.x;
-  const int v = view_of_tile(vt, g);
-  const int W = vt.W[v], H = vt.H[v];
-  const int ntx = W / TILE;
-  const int lt = g - vt.tile_base[v];
-  const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
-  int lx, ly;
-  local_pixel<TILE>(threadIdx.x, lx, ly);
-  const int x = tx0 + lx, y = ty0 + ly;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int slot = (int)((kRowSlot >> (4 * (lane & 15))) & 0xF);
-  const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-  const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
-  const uint2 rg = ranges[g];
-  const int64_t plane = (int64_t)W * H;
-  const int64_t pix = (int64_t)y * W + x;
-  const int64_t gp = vt.pix_base[v] + pix;
-  const float* dimg = dL_drgb + 3 * vt.pix_base[v];
-  BwdPixel P;
-  P.dl0 = dimg[pix], P.dl1 = dimg[plane + pix], P.dl2 = dimg[2 * plane + pix];
-  P.T = ws_T[gp];
-  P.last = ws_last[gp];
-  // dL/dC . (colour of everything behind, incl. background): the only way the colour behind a
-  // Gaussian enters its alpha gradient, so one scalar replaces the three channels
-  P.DS = P.T * fmaf(P.dl0, bg0, fmaf(P.dl1, bg1, P.dl2 * bg2));
-  // largest `last` of the wavefront (uniform) and of the workgroup
-  int wmax = P.last;
+  if (forward_is_stale(sc)) return;  // uniform
+  __shared__ uint32_t s_claim;
+  uint32_t round = 0;
+  for (int g; (g = claim_tile(sc, round, &s_claim)) >= 0;) {
+    const int v = view_of_tile(vt, g);
+    const int W = vt.W[v], H = vt.H[v];
+    const int ntx = W / TILE;
+    const int lt = g - vt.tile_base[v];
+    const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+    int lx, ly;
+    local_pixel<TILE>(threadIdx.x, lx, ly);
+    const int x = tx0 + lx, y = ty0 + ly;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int slot = (int)((kRowSlot >> (4 * (lane & 15))) & 0xF);
+    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
+    const uint2 rg = ranges[g];
+    const int64_t plane = (int64_t)W * H;
+    const int64_t pix = (int64_t)y * W + x;
+    const int64_t gp = vt.pix_base[v] + pix;
+    const float* dimg = dL_drgb + 3 * vt.pix_base[v];
+    BwdPixel P;
+    P.dl0 = dimg[pix], P.dl1 = dimg[plane + pix], P.dl2 = dimg[2 * plane + pix];
+    P.T = ws_T[gp];
+    P.last = ws_last[gp];
+    // dL/dC . (colour of everything behind, incl. background): the only way the colour behind a
+    // Gaussian enters its alpha gradient, so one scalar replaces the three channels
+    P.DS = P.T * fmaf(P.dl0, bg0, fmaf(P.dl1, bg1, P.dl2 * bg2));
+    // largest `last` of the wavefront (uniform) and of the workgroup
+    int wmax = P.last;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
-  wmax = __builtin_amdgcn_readfirstlane(wmax);
-  if (threadIdx.x == 0) smax = 0;
-  __syncthreads();
-  if (lane == 0) atomicMax(&smax, wmax);
-  __syncthreads();
-  const int end_all = smax;
-  for (int end = end_all; end > 0; end -= BATCH) {
-    const int cnt = min(BATCH, end);
-    for (int t = threadIdx.x; t < cnt; t += N) {
+    for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
+    wmax = __builtin_amdgcn_readfirstlane(wmax);
+    if (threadIdx.x == 0) smax = 0;
+    __syncthreads();
+    if (lane == 0) atomicMax(&smax, wmax);
+    __syncthreads();
+    const int end_all = smax;
+    for (int end = end_all; end > 0; end -= BATCH) {
+      const int cnt = min(BATCH, end);
+      for (int t = threadIdx.x; t < cnt; t += N) {
 #pragma unroll
-      for (int w = 0; w < NS; ++w)
+        for (int w = 0; w < NS; ++w)
 #pragma unroll
-        for (int q = 0; q < 9; ++q) acc[w][q][t] = 0.0f;
-    }
-    int nq[St::NQ];
-    // entry e is list position end - 1 - e (back to front)
-    stage_batch<TILE, BATCH, 1, kMaskLoad>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq, nullptr,
-                                           qmask);
-    const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
-    bool pend = false;  // an accepted entry whose values 0..7 still wait in red (uniform)
-    int pk = 0;
-    // software pipeline: the next entry's list index and records are read while this one is
-    // processed, taking two LDS round trips off each iteration's dependency chain
-    int kn = n > 0 ? S.list[wq][0] : 0;  // entries 0..n-1 of the list are valid
-    float4 an = S.s0[kn], bn = S.s1[kn];
-    for (int i = 0; i < n; ++i) {
-      const int k = __builtin_amdgcn_readfirstlane(kn);  // uniform entry index
-      const float4 a = an, b = bn;
-      kn = S.list[wq][min(i + 1, n - 1)];
-      an = S.s0[kn];
-      bn = S.s1[kn];
-      const int jrel = end - 1 - k;
-      if (jrel >= wmax) continue;  // uniform: behind every contributor of this wavefront
-      const float du = wrap_du(px - a.x, Wf, half);
-      const float dv = py - a.y;
-      const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
-      const float power = -fmaf(t1, t1, t2 * t2);
-      const bool ok = jrel < P.last && !(power > 0.0f || power < b.y);
-      if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
-      float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
-      if (kSlots && pend) red_read(red[wq], lane, r0, r1);  // previous accepted entry's values
-      const float4 c = S.s2[k];
-      float gq[9];
-      bwd_pixel_step<false>(P, ok, power, t1, b.x * t2, a, b, c, gq);
-      if constexpr (kSlots) {
-        if (pend) {
-          const float sj = red_finish(r0, r1);
-          if ((lane & 7) == 0) acc[wq][lane >> 3][pk] = sj;
-        }
-        red_write(red[wq], gq, lane);
-        const float s8 = wave_sum(gq[8]);
-        if (lane == 1) acc[wq][8][k] = s8;
-        pend = true;
-        pk = k;
-      } else {
-        const float rs = row_reduce9(gq, lane & 8, lane & 4, lane & 2, lane & 1);
-        if (slot < 9) atomicAdd(&acc[0][slot][k], rs);  // 9 lanes per row, 4 rows: one LDS atomic
+          for (int q = 0; q < 9; ++q) acc[w][q][t] = 0.0f;
       }
-    }
-    if (kSlots && pend) {
-      float4 r0, r1;
-      red_read(red[wq], lane, r0, r1);
-      const float sj = red_finish(r0, r1);
-      if ((lane & 7) == 0) acc[wq][lane >> 3][pk] = sj;
-    }
-    __syncthreads();
-    // nine consecutive lanes carry one entry's nine values, so one atomic instruction covers
-    // about seven items' contiguous 36-byte gradient records instead of 64 scattered lines
-    for (int x = threadIdx.x; x < 9 * cnt; x += N) {
-      const int t = x / 9, q = x - 9 * t;
-      float s = acc[0][q][t];
+      int nq[St::NQ];
+      // entry e is list position end - 1 - e (back to front)
+      stage_batch<TILE, BATCH, 1, kMaskLoad>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq, nullptr,
+                                             qmask);
+      const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
+      bool pend = false;  // an accepted entry whose values 0..7 still wait in red (uniform)
+      int pk = 0;
+      // software pipeline: the next entry's list index and records are read while this one is
+      // processed, taking two LDS round trips off each iteration's dependency chain
+      int kn = n > 0 ? S.list[wq][0] : 0;  // entries 0..n-1 of the list are valid
+      float4 an = S.s0[kn], bn = S.s1[kn];
+      for (int i = 0; i < n; ++i) {
+        const int k = __builtin_amdgcn_readfirstlane(kn);  // uniform entry index
+        const float4 a = an, b = bn;
+        kn = S.list[wq][min(i + 1, n - 1)];
+        an = S.s0[kn];
+        bn = S.s1[kn];
+        const int jrel = end - 1 - k;
+        if (jrel >= wmax) continue;  // uniform: behind every contributor of this wavefront
+        const float du = wrap_du(px - a.x, Wf, half);
+        const float dv = py - a.y;
+        const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
+        const float power = -fmaf(t1, t1, t2 * t2);
+        const bool ok = jrel < P.last && !(power > 0.0f || power < b.y);
+        if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
+        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+        if (kSlots && pend) red_read(red[wq], lane, r0, r1);  // previous accepted entry's values
+        const float4 c = S.s2[k];
+        float gq[9];
+        bwd_pixel_step<false>(P, ok, power, t1, b.x * t2, a, b, c, gq);
+        if constexpr (kSlots) {
+          if (pend) {
+            const float sj = red_finish(r0, r1);
+            if ((lane & 7) == 0) acc[wq][lane >> 3][pk] = sj;
+          }
+          red_write(red[wq], gq, lane);
+          const float s8 = wave_sum(gq[8]);
+          if (lane == 1) acc[wq][8][k] = s8;
+          pend = true;
+          pk = k;
+        } else {
+          const float rs = row_reduce9(gq, lane & 8, lane & 4, lane & 2, lane & 1);
+          if (slot < 9) atomicAdd(&acc[0][slot][k], rs);  // 9 lanes per row, 4 rows: one LDS atomic
+        }
+      }
+      if (kSlots && pend) {
+        float4 r0, r1;
+        red_read(red[wq], lane, r0, r1);
+        const float sj = red_finish(r0, r1);
+        if ((lane & 7) == 0) acc[wq][lane >> 3][pk] = sj;
+      }
+      __syncthreads();
+      // nine consecutive lanes carry one entry's nine values, so one atomic instruction covers
+      // about seven items' contiguous 36-byte gradient records instead of 64 scattered lines
+      for (int x = threadIdx.x; x < 9 * cnt; x += N) {
+        const int t = x / 9, q = x - 9 * t;
+        double s = (double)acc[0][q][t];
 #pragma unroll
-      for (int w = 1; w < NS; ++w) s += acc[w][q][t];
-      if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s * g2d_flush_scale(q));
+        for (int w = 1; w < NS; ++w) s += (double)acc[w][q][t];
+        if (s != 0.0) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s * (double)g2d_flush_scale(q));
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -719,7 +732,8 @@ template <int TILE, int BATCH>
 __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
     const float* __restrict__ ws_T, const int32_t* __restrict__ ws_last, const float* __restrict__ dL_drgb,
-    float* __restrict__ g2d, int64_t items, float bg0, float bg1, float bg2, const uint8_t* __restrict__ qmask) {
+    double* __restrict__ g2d, int64_t items, float bg0, float bg1, float bg2, const uint8_t* __restrict__ qmask,
+    TileSched sc) {
   using St = Stage<TILE, BATCH, 2>;
   constexpr int N = St::N;
   constexpr int QPR = TILE / 8;
@@ -728,105 +742,109 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
   __shared__ St S;
   __shared__ float acc[NS][9][BATCH + 1];  // padded rows: the nine slot writes hit nine banks
   __shared__ int smax;
-  const int g = blockIdx.x;
-  const int v = view_of_tile(vt, g);
-  const int W = vt.W[v], H = vt.H[v];
-  const int ntx = W / TILE;
-  const int lt = g - vt.tile_base[v];
-  const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int qa = 2 * wq;  // quadrant of pixel A; pixel B is 8 pixels to the right
-  const int x = tx0 + (qa % QPR) * 8 + (lane & 7), y = ty0 + (qa / QPR) * 8 + (lane >> 3);
-  const int slot = (int)((kRowSlot >> (4 * (lane & 15))) & 0xF);
-  const float pxa = (float)x + 0.5f, pxb = (float)(x + 8) + 0.5f, py = (float)y + 0.5f;
-  const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
-  const uint2 rg = ranges[g];
-  const int64_t plane = (int64_t)W * H;
-  const int64_t pix = (int64_t)y * W + x;
-  const int64_t gp = vt.pix_base[v] + pix;
-  const float* dimg = dL_drgb + 3 * vt.pix_base[v];
-  BwdPixel A, B;
-  A.dl0 = dimg[pix], A.dl1 = dimg[plane + pix], A.dl2 = dimg[2 * plane + pix];
-  B.dl0 = dimg[pix + 8], B.dl1 = dimg[plane + pix + 8], B.dl2 = dimg[2 * plane + pix + 8];
-  A.T = ws_T[gp];
-  B.T = ws_T[gp + 8];
-  A.last = ws_last[gp];
-  B.last = ws_last[gp + 8];
-  A.DS = A.T * fmaf(A.dl0, bg0, fmaf(A.dl1, bg1, A.dl2 * bg2));  // the background behind everything
-  B.DS = B.T * fmaf(B.dl0, bg0, fmaf(B.dl1, bg1, B.dl2 * bg2));
-  // largest `last` of the wavefront (uniform) and of the workgroup
-  int wmax = max(A.last, B.last);
+  if (forward_is_stale(sc)) return;  // uniform
+  __shared__ uint32_t s_claim;
+  uint32_t round = 0;
+  for (int g; (g = claim_tile(sc, round, &s_claim)) >= 0;) {
+    const int v = view_of_tile(vt, g);
+    const int W = vt.W[v], H = vt.H[v];
+    const int ntx = W / TILE;
+    const int lt = g - vt.tile_base[v];
+    const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int qa = 2 * wq;  // quadrant of pixel A; pixel B is 8 pixels to the right
+    const int x = tx0 + (qa % QPR) * 8 + (lane & 7), y = ty0 + (qa / QPR) * 8 + (lane >> 3);
+    const int slot = (int)((kRowSlot >> (4 * (lane & 15))) & 0xF);
+    const float pxa = (float)x + 0.5f, pxb = (float)(x + 8) + 0.5f, py = (float)y + 0.5f;
+    const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
+    const uint2 rg = ranges[g];
+    const int64_t plane = (int64_t)W * H;
+    const int64_t pix = (int64_t)y * W + x;
+    const int64_t gp = vt.pix_base[v] + pix;
+    const float* dimg = dL_drgb + 3 * vt.pix_base[v];
+    BwdPixel A, B;
+    A.dl0 = dimg[pix], A.dl1 = dimg[plane + pix], A.dl2 = dimg[2 * plane + pix];
+    B.dl0 = dimg[pix + 8], B.dl1 = dimg[plane + pix + 8], B.dl2 = dimg[2 * plane + pix + 8];
+    A.T = ws_T[gp];
+    B.T = ws_T[gp + 8];
+    A.last = ws_last[gp];
+    B.last = ws_last[gp + 8];
+    A.DS = A.T * fmaf(A.dl0, bg0, fmaf(A.dl1, bg1, A.dl2 * bg2));  // the background behind everything
+    B.DS = B.T * fmaf(B.dl0, bg0, fmaf(B.dl1, bg1, B.dl2 * bg2));
+    // largest `last` of the wavefront (uniform) and of the workgroup
+    int wmax = max(A.last, B.last);
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
-  wmax = __builtin_amdgcn_readfirstlane(wmax);
-  if (threadIdx.x == 0) smax = 0;
-  __syncthreads();
-  if (lane == 0) atomicMax(&smax, wmax);
-  __syncthreads();
-  const int end_all = smax;
-  for (int end = end_all; end > 0; end -= BATCH) {
-    const int cnt = min(BATCH, end);
-    for (int t = threadIdx.x; t < cnt; t += N) {
-#pragma unroll
-      for (int w = 0; w < NS; ++w)
-#pragma unroll
-        for (int q = 0; q < 9; ++q) acc[w][q][t] = 0.0f;
-    }
-    int nq[St::NQ];
-    // entry e is list position end - 1 - e (back to front)
-    stage_batch<TILE, BATCH, 2, kMaskLoad>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq, nullptr,
-                                           qmask);
-    const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
-    for (int i = 0; i < n; ++i) {
-      const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);  // uniform entry index
-      const int jrel = end - 1 - k;
-      if (jrel >= wmax) continue;  // uniform: behind every contributor of this wavefront
-      const float4 a = S.s0[k];
-      const float4 b = S.s1[k];
-      const float dv = py - a.y;
-      const float l1dv = a.w * dv, t2 = b.x * dv, t22 = t2 * t2;
-      float dua = pxa - a.x, dub = pxb - a.x;
-      if (__builtin_amdgcn_readfirstlane(__float_as_int(b.w)) == 0) {  // uniform: the seam is within reach
-        dua = wrap_du(dua, Wf, half);
-        dub = wrap_du(dub, Wf, half);
-      }
-      const float t1a = fmaf(a.z, dua, l1dv), t1b = fmaf(a.z, dub, l1dv);
-      const float pa = -fmaf(t1a, t1a, t22), pb = -fmaf(t1b, t1b, t22);
-      const bool ina = !(pa > 0.0f || pa < b.y), inb = !(pb > 0.0f || pb < b.y);
-      const bool oka = jrel < A.last && ina, okb = jrel < B.last && inb;
-      // ballots of the single compares (each is its own lane mask) rather than of their conjunction
-      const uint64_t bala = __builtin_amdgcn_ballot_w64(jrel < A.last) & __builtin_amdgcn_ballot_w64(ina);
-      const uint64_t balb = __builtin_amdgcn_ballot_w64(jrel < B.last) & __builtin_amdgcn_ballot_w64(inb);
-      if ((bala | balb) == 0ull) continue;  // uniform
-      const float4 c = S.s2[k];
-      const float bxt2 = b.x * t2;
-      float gq[9];
-      if (bala != 0ull) {
-        bwd_pixel_step<false>(A, oka, pa, t1a, bxt2, a, b, c, gq);
-        if (balb != 0ull) bwd_pixel_step<true>(B, okb, pb, t1b, bxt2, a, b, c, gq);
-      } else {
-        bwd_pixel_step<false>(B, okb, pb, t1b, bxt2, a, b, c, gq);
-      }
-      const float rs = row_reduce9(gq, lane & 8, lane & 4, lane & 2, lane & 1);
-      if constexpr (kSlots) {
-        const float ws = sum_rows(rs);
-        if (lane < 16 && slot < 9) acc[wq][slot][k] = ws;
-      } else {
-        if (slot < 9) atomicAdd(&acc[0][slot][k], rs);
-      }
-    }
+    for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
+    wmax = __builtin_amdgcn_readfirstlane(wmax);
+    if (threadIdx.x == 0) smax = 0;
     __syncthreads();
-    // nine consecutive lanes carry one entry's nine values, so one atomic instruction covers
-    // about seven items' contiguous 36-byte gradient records instead of 64 scattered lines
-    for (int x = threadIdx.x; x < 9 * cnt; x += N) {
-      const int t = x / 9, q = x - 9 * t;
-      float s = acc[0][q][t];
-#pragma unroll
-      for (int w = 1; w < NS; ++w) s += acc[w][q][t];
-      if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s * g2d_flush_scale(q));
-    }
+    if (lane == 0) atomicMax(&smax, wmax);
     __syncthreads();
+    const int end_all = smax;
+    for (int end = end_all; end > 0; end -= BATCH) {
+      const int cnt = min(BATCH, end);
+      for (int t = threadIdx.x; t < cnt; t += N) {
+#pragma unroll
+        for (int w = 0; w < NS; ++w)
+#pragma unroll
+          for (int q = 0; q < 9; ++q) acc[w][q][t] = 0.0f;
+      }
+      int nq[St::NQ];
+      // entry e is list position end - 1 - e (back to front)
+      stage_batch<TILE, BATCH, 2, kMaskLoad>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq, nullptr,
+                                             qmask);
+      const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
+      for (int i = 0; i < n; ++i) {
+        const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);  // uniform entry index
+        const int jrel = end - 1 - k;
+        if (jrel >= wmax) continue;  // uniform: behind every contributor of this wavefront
+        const float4 a = S.s0[k];
+        const float4 b = S.s1[k];
+        const float dv = py - a.y;
+        const float l1dv = a.w * dv, t2 = b.x * dv, t22 = t2 * t2;
+        float dua = pxa - a.x, dub = pxb - a.x;
+        if (__builtin_amdgcn_readfirstlane(__float_as_int(b.w)) == 0) {  // uniform: the seam is within reach
+          dua = wrap_du(dua, Wf, half);
+          dub = wrap_du(dub, Wf, half);
+        }
+        const float t1a = fmaf(a.z, dua, l1dv), t1b = fmaf(a.z, dub, l1dv);
+        const float pa = -fmaf(t1a, t1a, t22), pb = -fmaf(t1b, t1b, t22);
+        const bool ina = !(pa > 0.0f || pa < b.y), inb = !(pb > 0.0f || pb < b.y);
+        const bool oka = jrel < A.last && ina, okb = jrel < B.last && inb;
+        // ballots of the single compares (each is its own lane mask) rather than of their conjunction
+        const uint64_t bala = __builtin_amdgcn_ballot_w64(jrel < A.last) & __builtin_amdgcn_ballot_w64(ina);
+        const uint64_t balb = __builtin_amdgcn_ballot_w64(jrel < B.last) & __builtin_amdgcn_ballot_w64(inb);
+        if ((bala | balb) == 0ull) continue;  // uniform
+        const float4 c = S.s2[k];
+        const float bxt2 = b.x * t2;
+        float gq[9];
+        if (bala != 0ull) {
+          bwd_pixel_step<false>(A, oka, pa, t1a, bxt2, a, b, c, gq);
+          if (balb != 0ull) bwd_pixel_step<true>(B, okb, pb, t1b, bxt2, a, b, c, gq);
+        } else {
+          bwd_pixel_step<false>(B, okb, pb, t1b, bxt2, a, b, c, gq);
+        }
+        const float rs = row_reduce9(gq, lane & 8, lane & 4, lane & 2, lane & 1);
+        if constexpr (kSlots) {
+          const float ws = sum_rows(rs);
+          if (lane < 16 && slot < 9) acc[wq][slot][k] = ws;
+        } else {
+          if (slot < 9) atomicAdd(&acc[0][slot][k], rs);
+        }
+      }
+      __syncthreads();
+      // nine consecutive lanes carry one entry's nine values, so one atomic instruction covers
+      // about seven items' contiguous 36-byte gradient records instead of 64 scattered lines
+      for (int x = threadIdx.x; x < 9 * cnt; x += N) {
+        const int t = x / 9, q = x - 9 * t;
+        double s = (double)acc[0][q][t];
+#pragma unroll
+        for (int w = 1; w < NS; ++w) s += (double)acc[w][q][t];
+        if (s != 0.0) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s * (double)g2d_flush_scale(q));
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -866,14 +884,14 @@ __global__ void debug_pixel_counts_kernel(const int32_t* __restrict__ last, cons
 
 template <int TILE, int BATCH>
 struct FwdRun {
-  static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
-                  const Rec* rec, float* out_rgb, float* out_T, float* wT, int32_t* wl, int32_t* wn, int32_t* we,
-                  int32_t* wle, const float* depth, float* out_depth, uint8_t* qmask, hipStream_t st) {
+  static void run(const odgs_plan* p, const TileSched& sc, const ViewTable& vt, const uint2* ranges,
+                  const uint32_t* items, const Rec* rec, float* out_rgb, float* out_T, float* wT, int32_t* wl,
+                  int32_t* wn, int32_t* we, int32_t* wle, const float* depth, float* out_depth, uint8_t* qmask,
+                  hipStream_t st) {
     const bool count = (p->s.flags & ODGS_FLAG_COUNT_WORK) != 0;
-#define ODGS_FWD1(C, D)                                                                                        \
-  hipLaunchKernelGGL((render_fwd_kernel<TILE, BATCH, C, D>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, \
-                     items, rec, out_rgb, out_T, wT, wl, wn, we, wle, p->s.bg[0], p->s.bg[1], p->s.bg[2], depth,  \
-                     out_depth, qmask)
+#define ODGS_FWD1(C, D)                                                                                             \
+  launch_sched(render_fwd_kernel<TILE, BATCH, C, D>, sc, TILE * TILE, st, vt, ranges, items, rec, out_rgb, out_T, wT, \
+               wl, wn, we, wle, p->s.bg[0], p->s.bg[1], p->s.bg[2], depth, out_depth, qmask)
     // the counting and depth variants keep one pixel per lane (counters per 8x8 quadrant)
     if (count && out_depth)
       ODGS_FWD1(true, true);
@@ -882,8 +900,8 @@ struct FwdRun {
     else if (out_depth)
       ODGS_FWD1(false, true);
     else if constexpr (TILE >= 32)  // at 16x16 the union of two quadrants' lists costs more than it saves
-      hipLaunchKernelGGL((render_fwd2_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE / 2), 0, st, vt, ranges,
-                         items, rec, out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
+      launch_sched(render_fwd2_kernel<TILE, BATCH>, sc, TILE * TILE / 2, st, vt, ranges, items, rec, out_rgb, out_T,
+                   wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
     else
       ODGS_FWD1(false, false);
 #undef ODGS_FWD1
@@ -892,17 +910,17 @@ struct FwdRun {
 
 template <int TILE, int BATCH>
 struct BwdRun {
-  static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
-                  const Rec* rec, const float* wT, const int32_t* wl, const float* dL, float* g2d, const uint8_t* qmask,
-                  hipStream_t st) {
+  static void run(const odgs_plan* p, const TileSched& sc, const ViewTable& vt, const uint2* ranges,
+                  const uint32_t* items, const Rec* rec, const float* wT, const int32_t* wl, const float* dL, double* g2d,
+                  const uint8_t* qmask, hipStream_t st) {
     // two pixels per lane (tiles of 16 and 32): one cross-lane reduction per 128 pixels; an 8x8
     // tile has a single quadrant and keeps one pixel per lane
     if constexpr (TILE >= 16)
-      hipLaunchKernelGGL((render_bwd2_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE / 2), 0, st, vt, ranges,
-                         items, rec, wT, wl, dL, g2d, p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
+      launch_sched(render_bwd2_kernel<TILE, BATCH>, sc, TILE * TILE / 2, st, vt, ranges, items, rec, wT, wl, dL, g2d,
+                   p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
     else
-      hipLaunchKernelGGL((render_bwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items,
-                         rec, wT, wl, dL, g2d, p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
+      launch_sched(render_bwd_kernel<TILE, BATCH>, sc, TILE * TILE, st, vt, ranges, items, rec, wT, wl, dL, g2d,
+                   p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
   }
 };
 
@@ -938,7 +956,8 @@ hipError_t launch_render_fwd(const odgs_plan* p, void* ws, float* out_rgb, float
   int32_t* wle = ws_ptr<int32_t>(ws, p->off_lasteval);
   const float* depth = ws_ptr<float>(ws, p->off_depth);
   uint8_t* qmask = ws_ptr<uint8_t>(ws, p->off_pval[p->pair_final ^ 1]);  // unused by the sort's result
-  if (!dispatch<FwdRun>(p->s.tile, p->s.batch, p, tiles, vt, ranges, items, rec, out_rgb, out_T, wT, wl, wn, we, wle,
+  const TileSched sc = make_sched(p, ws, 0);
+  if (!dispatch<FwdRun>(p->s.tile, p->s.batch, p, sc, vt, ranges, items, rec, out_rgb, out_T, wT, wl, wn, we, wle,
                         depth, out_depth, qmask, st))
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -948,14 +967,15 @@ hipError_t launch_render_bwd(const odgs_plan* p, void* ws, const float* dL_drgb,
   const ViewTable vt = make_view_table(p);
   const int tiles = p->tile_base[p->n_views];
   if (tiles == 0) return hipSuccess;
-  float* g2d = ws_ptr<float>(ws, p->off_g2d);
+  double* g2d = ws_ptr<double>(ws, p->off_g2d);
   const uint2* ranges = ws_ptr<uint2>(ws, p->off_ranges);
   const uint32_t* items = ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]);
   const Rec* rec = ws_ptr<Rec>(ws, p->off_rec);
   const float* wT = ws_ptr<float>(ws, p->off_T);
   const int32_t* wl = ws_ptr<int32_t>(ws, p->off_last);
   const uint8_t* qmask = ws_ptr<uint8_t>(ws, p->off_pval[p->pair_final ^ 1]);  // written by the forward
-  if (!dispatch<BwdRun>(p->s.tile, p->s.batch_bwd, p, tiles, vt, ranges, items, rec, wT, wl, dL_drgb, g2d, qmask, st))
+  const TileSched sc = make_sched(p, ws, 1);
+  if (!dispatch<BwdRun>(p->s.tile, p->s.batch_bwd, p, sc, vt, ranges, items, rec, wT, wl, dL_drgb, g2d, qmask, st))
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -968,16 +988,16 @@ hipError_t launch_debug_records(const odgs_plan* p, const void* ws, float* out, 
   return hipGetLastError();
 }
 
-__global__ void debug_copy_kernel(const float* __restrict__ src, int64_t n, float* __restrict__ dst) {
+__global__ void debug_copy_kernel(const double* __restrict__ src, int64_t n, double* __restrict__ dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
 }
 
-hipError_t launch_debug_g2d(const odgs_plan* p, const void* ws, float* out, hipStream_t st) {
+hipError_t launch_debug_g2d(const odgs_plan* p, const void* ws, double* out, hipStream_t st) {
   const int64_t n = (int64_t)p->g2d_stride * p->items;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(debug_copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                     ws_ptr<float>(ws, p->off_g2d), n, out);
+                     ws_ptr<double>(ws, p->off_g2d), n, out);
   return hipGetLastError();
 }
 

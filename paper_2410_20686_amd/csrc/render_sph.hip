@@ -188,7 +188,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
     const SphRec* __restrict__ rec, const SphCull* __restrict__ cull, const double2* __restrict__ dirs,
     float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
     float bg0, float bg1, float bg2, const float* __restrict__ depth, float* __restrict__ out_depth,
-    uint16_t* __restrict__ qmask) {
+    uint16_t* __restrict__ qmask, TileSched sc) {
   using St = SphStage<TILE, BATCH>;
   constexpr int N = St::N;
   __shared__ St S;
@@ -196,85 +196,89 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_fwd_kernel(
   // walked (before a pixel's last contributor this test and the backward's are the same float
   // decision); after the batch these quadrants are the mask handed to the backward
   __shared__ uint8_t s_used[St::NQ][BATCH];
-  const int g = blockIdx.x;
-  const int v = view_of_tile(vt, g);
-  const int W = vt.W[v], H = vt.H[v];
-  const int ntx = W / TILE;
-  const int lt = g - vt.tile_base[v];
-  const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
-  int lx, ly;
-  local_pixel<TILE>(threadIdx.x, lx, ly);
-  const int x = tx0 + lx, y = ty0 + ly;
-  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const float3 d = pixel_ray(dirs, vt, v, x, y);
-  const float qrad = quadrant_radius(W, H);
-  sph_stage_init<TILE, BATCH>(S, dirs, vt, v, tx0, ty0);
-  const uint2 rg = ranges[g];
-  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, Dsum = 0.0f;
-  int last = 0;
-  int done = 0;  // an int rather than a bool: the ballots below then compile to one compare
-  // writes the masks of the batch walked last (after a barrier) and clears s_used for the next
-  auto flush_used = [&](uint32_t first, int n_walked) {
-    for (int e = threadIdx.x; e < BATCH; e += N) {
-      if (e < n_walked) {
-        uint32_t mq = 0;
+  mark_forward(sc);
+  __shared__ uint32_t s_claim;
+  uint32_t round = 0;
+  for (int g; (g = claim_tile(sc, round, &s_claim)) >= 0;) {
+    const int v = view_of_tile(vt, g);
+    const int W = vt.W[v], H = vt.H[v];
+    const int ntx = W / TILE;
+    const int lt = g - vt.tile_base[v];
+    const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+    int lx, ly;
+    local_pixel<TILE>(threadIdx.x, lx, ly);
+    const int x = tx0 + lx, y = ty0 + ly;
+    const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const float3 d = pixel_ray(dirs, vt, v, x, y);
+    const float qrad = quadrant_radius(W, H);
+    sph_stage_init<TILE, BATCH>(S, dirs, vt, v, tx0, ty0);
+    const uint2 rg = ranges[g];
+    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, Dsum = 0.0f;
+    int last = 0;
+    int done = 0;  // an int rather than a bool: the ballots below then compile to one compare
+    // writes the masks of the batch walked last (after a barrier) and clears s_used for the next
+    auto flush_used = [&](uint32_t first, int n_walked) {
+      for (int e = threadIdx.x; e < BATCH; e += N) {
+        if (e < n_walked) {
+          uint32_t mq = 0;
 #pragma unroll
-        for (int q = 0; q < St::NQ; ++q) mq |= s_used[q][e] ? (1u << q) : 0u;
-        qmask[first + e] = (uint16_t)mq;
+          for (int q = 0; q < St::NQ; ++q) mq |= s_used[q][e] ? (1u << q) : 0u;
+          qmask[first + e] = (uint16_t)mq;
+        }
+#pragma unroll
+        for (int q = 0; q < St::NQ; ++q) s_used[q][e] = 0;
       }
-#pragma unroll
-      for (int q = 0; q < St::NQ; ++q) s_used[q][e] = 0;
+    };
+    uint32_t walked_base = 0;
+    int walked_cnt = 0;
+    for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
+      const bool all_done = __syncthreads_count(done) == N;
+      flush_used(walked_base, walked_cnt);
+      walked_cnt = 0;
+      if (all_done) break;
+      const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
+      int nq[St::NQ];
+      sph_stage_batch<TILE, BATCH>(S, pair_items, rec, cull, base, 1, cnt, qrad, nq, DEPTH ? depth : nullptr);
+      const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
+      for (int i = 0; i < n; ++i) {
+        if (__builtin_amdgcn_ballot_w64(done == 0) == 0ull) break;  // uniform: every pixel has finished
+        const int k = S.list[wq][i];
+        const float4 c = S.s2[k];
+        float power, t1, t2, h, D, qh;
+        const bool hit = sph_eval(S.s0[k], S.s1[k], c, d, power, t1, t2, h, D, qh);
+        const bool ok = done == 0 && hit;
+        if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
+        s_used[wq][k] = 1;  // reached here (accepted unless that pixel stops at it: a superset)
+        const float alpha = fminf(c.z * __expf(power), kAlphaMax);
+        const float Tn = T * (1.0f - alpha);
+        const bool acc = ok && !(Tn < kTStop);
+        done = ok != acc ? 1 : done;  // stop: reached, but T would drop below 1e-4
+        const float4 col = S.s3[k];
+        const float w = acc ? alpha * T : 0.0f;
+        C0 = fmaf(w, col.x, C0);
+        C1 = fmaf(w, col.y, C1);
+        C2 = fmaf(w, col.z, C2);
+        if (DEPTH) Dsum = Dsum + w * S.dep[k];
+        T = acc ? Tn : T;
+        last = acc ? (int)(base - rg.x) + k + 1 : last;
+      }
+      walked_base = base;
+      walked_cnt = cnt;
     }
-  };
-  uint32_t walked_base = 0;
-  int walked_cnt = 0;
-  for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
-    const bool all_done = __syncthreads_count(done) == N;
+    __syncthreads();
     flush_used(walked_base, walked_cnt);
-    walked_cnt = 0;
-    if (all_done) break;
-    const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
-    int nq[St::NQ];
-    sph_stage_batch<TILE, BATCH>(S, pair_items, rec, cull, base, 1, cnt, qrad, nq, DEPTH ? depth : nullptr);
-    const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
-    for (int i = 0; i < n; ++i) {
-      if (__builtin_amdgcn_ballot_w64(done == 0) == 0ull) break;  // uniform: every pixel has finished
-      const int k = S.list[wq][i];
-      const float4 c = S.s2[k];
-      float power, t1, t2, h, D, qh;
-      const bool hit = sph_eval(S.s0[k], S.s1[k], c, d, power, t1, t2, h, D, qh);
-      const bool ok = done == 0 && hit;
-      if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
-      s_used[wq][k] = 1;  // reached here (accepted unless that pixel stops at it: a superset)
-      const float alpha = fminf(c.z * __expf(power), kAlphaMax);
-      const float Tn = T * (1.0f - alpha);
-      const bool acc = ok && !(Tn < kTStop);
-      done = ok != acc ? 1 : done;  // stop: reached, but T would drop below 1e-4
-      const float4 col = S.s3[k];
-      const float w = acc ? alpha * T : 0.0f;
-      C0 = fmaf(w, col.x, C0);
-      C1 = fmaf(w, col.y, C1);
-      C2 = fmaf(w, col.z, C2);
-      if (DEPTH) Dsum = Dsum + w * S.dep[k];
-      T = acc ? Tn : T;
-      last = acc ? (int)(base - rg.x) + k + 1 : last;
-    }
-    walked_base = base;
-    walked_cnt = cnt;
+    const int64_t plane = (int64_t)W * H;
+    const int64_t pix = (int64_t)y * W + x;
+    float* img = out_rgb + 3 * vt.pix_base[v];
+    img[pix] = fmaf(T, bg0, C0);
+    img[plane + pix] = fmaf(T, bg1, C1);
+    img[2 * plane + pix] = fmaf(T, bg2, C2);
+    const int64_t gp = vt.pix_base[v] + pix;
+    ws_T[gp] = T;
+    ws_last[gp] = last;
+    if (DEPTH) out_depth[gp] = Dsum;
+    if (out_T) out_T[gp] = T;
   }
-  __syncthreads();
-  flush_used(walked_base, walked_cnt);
-  const int64_t plane = (int64_t)W * H;
-  const int64_t pix = (int64_t)y * W + x;
-  float* img = out_rgb + 3 * vt.pix_base[v];
-  img[pix] = fmaf(T, bg0, C0);
-  img[plane + pix] = fmaf(T, bg1, C1);
-  img[2 * plane + pix] = fmaf(T, bg2, C2);
-  const int64_t gp = vt.pix_base[v] + pix;
-  ws_T[gp] = T;
-  ws_last[gp] = last;
-  if (DEPTH) out_depth[gp] = Dsum;
-  if (out_T) out_T[gp] = T;
 }
 
 // Sums thirteen per-lane values over each 16-lane row in four DPP exchange steps (partners
@@ -317,7 +321,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items,
     const SphRec* __restrict__ rec, const SphCull* __restrict__ cull, const double2* __restrict__ dirs,
     const float* __restrict__ ws_T, const int32_t* __restrict__ ws_last, const float* __restrict__ dL_drgb,
-    float* __restrict__ g2d, float bg0, float bg1, float bg2, const uint16_t* __restrict__ qmask) {
+    double* __restrict__ g2d, float bg0, float bg1, float bg2, const uint16_t* __restrict__ qmask, TileSched sc) {
   using St = SphStage<TILE, BATCH>;
   constexpr int N = St::N;
   constexpr bool kSlots = St::NW <= 4;  // a slot set per wavefront, else one shared set (LDS atomics)
@@ -325,133 +329,136 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
   __shared__ St S;
   __shared__ float acc[NS][kNV][BATCH + 1];
   __shared__ int smax;
-  const int g = blockIdx.x;
-  const int v = view_of_tile(vt, g);
-  const int W = vt.W[v], H = vt.H[v];
-  const int ntx = W / TILE;
-  const int lt = g - vt.tile_base[v];
-  const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
-  int lx, ly;
-  local_pixel<TILE>(threadIdx.x, lx, ly);
-  const int x = tx0 + lx, y = ty0 + ly;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const float3 d = pixel_ray(dirs, vt, v, x, y);
-  const float qrad = quadrant_radius(W, H);
-  sph_stage_init<TILE, BATCH>(S, dirs, vt, v, tx0, ty0);
-  const uint2 rg = ranges[g];
-  const int64_t plane = (int64_t)W * H;
-  const int64_t pix = (int64_t)y * W + x;
-  const int64_t gp = vt.pix_base[v] + pix;
-  const float* dimg = dL_drgb + 3 * vt.pix_base[v];
-  const float dl0 = dimg[pix], dl1 = dimg[plane + pix], dl2 = dimg[2 * plane + pix];
-  float T = ws_T[gp];
-  const int last = ws_last[gp];
-  // dL/dC . (colour of everything behind, incl. background), one scalar for the three channels
-  float DS = T * fmaf(dl0, bg0, fmaf(dl1, bg1, dl2 * bg2));
-  int wmax = last;
+  if (forward_is_stale(sc)) return;  // uniform
+  __shared__ uint32_t s_claim;
+  uint32_t round = 0;
+  for (int g; (g = claim_tile(sc, round, &s_claim)) >= 0;) {
+    const int v = view_of_tile(vt, g);
+    const int W = vt.W[v], H = vt.H[v];
+    const int ntx = W / TILE;
+    const int lt = g - vt.tile_base[v];
+    const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+    int lx, ly;
+    local_pixel<TILE>(threadIdx.x, lx, ly);
+    const int x = tx0 + lx, y = ty0 + ly;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const float3 d = pixel_ray(dirs, vt, v, x, y);
+    const float qrad = quadrant_radius(W, H);
+    sph_stage_init<TILE, BATCH>(S, dirs, vt, v, tx0, ty0);
+    const uint2 rg = ranges[g];
+    const int64_t plane = (int64_t)W * H;
+    const int64_t pix = (int64_t)y * W + x;
+    const int64_t gp = vt.pix_base[v] + pix;
+    const float* dimg = dL_drgb + 3 * vt.pix_base[v];
+    const float dl0 = dimg[pix], dl1 = dimg[plane + pix], dl2 = dimg[2 * plane + pix];
+    float T = ws_T[gp];
+    const int last = ws_last[gp];
+    // dL/dC . (colour of everything behind, incl. background), one scalar for the three channels
+    float DS = T * fmaf(dl0, bg0, fmaf(dl1, bg1, dl2 * bg2));
+    int wmax = last;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
-  wmax = __builtin_amdgcn_readfirstlane(wmax);
-  if (threadIdx.x == 0) smax = 0;
-  __syncthreads();
-  if (lane == 0) atomicMax(&smax, wmax);
-  __syncthreads();
-  const int end_all = smax;
-  for (int end = end_all; end > 0; end -= BATCH) {
-    const int cnt = min(BATCH, end);
-    for (int t = threadIdx.x; t < cnt; t += N) {
+    for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
+    wmax = __builtin_amdgcn_readfirstlane(wmax);
+    if (threadIdx.x == 0) smax = 0;
+    __syncthreads();
+    if (lane == 0) atomicMax(&smax, wmax);
+    __syncthreads();
+    const int end_all = smax;
+    for (int end = end_all; end > 0; end -= BATCH) {
+      const int cnt = min(BATCH, end);
+      for (int t = threadIdx.x; t < cnt; t += N) {
 #pragma unroll
-      for (int w = 0; w < NS; ++w)
+        for (int w = 0; w < NS; ++w)
 #pragma unroll
-        for (int q = 0; q < kNV; ++q) acc[w][q][t] = 0.0f;
-    }
-    int nq[St::NQ];
-    // entry e is list position end - 1 - e (back to front)
-    sph_stage_batch<TILE, BATCH, kSphMaskLoad>(S, pair_items, rec, cull, rg.x + end - 1, -1, cnt, qrad, nq, nullptr,
-                                               qmask);
-    const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
-    for (int i = 0; i < n; ++i) {
-      const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);
-      const int jrel = end - 1 - k;
-      if (jrel >= wmax) continue;  // uniform: behind every contributor of this wavefront
-      const float4 a = S.s0[k], b = S.s1[k], c = S.s2[k];
-      float power, t1, t2, h, D, qh;
-      // evaluated on every lane (no short circuit): the gradient terms below are formed on all
-      // lanes and zeroed by selects, which needs finite operands
-      const bool hit = sph_eval(a, b, c, d, power, t1, t2, h, D, qh);
-      const bool ok = jrel < last && hit;
-      if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
-      const float G = __expf(power);
-      const float araw = c.z * G;
-      const bool live = ok && !(araw > kAlphaMax);  // contributes and unclamped
-      // alpha = 0 where the Gaussian does not contribute, so its weight below is 0 without a select
-      const float alpha = ok ? fminf(araw, kAlphaMax) : 0.0f;
-      const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
-      T = ok ? T * inv_om : T;  // transmittance in front of this Gaussian
-      const float wk = alpha * T;
-      const float4 col = S.s3[k];
-      const float dc = fmaf(dl0, col.x, fmaf(dl1, col.y, dl2 * col.z));  // dL/dC . colour
-      const float dL_da = fmaf(dc, T, -DS * inv_om);
-      DS = fmaf(dc, wk, DS);
-      const float dla = live ? dL_da : 0.0f;
-      const float dpow = dla * alpha;
-      // z / 2 = (1 / D) (h (t1 u1 + t2 u2) - qh w), zero on lanes that do not contribute (D may
-      // be 0 there)
-      const float s1 = live ? __builtin_amdgcn_rcpf(D) : 0.0f;
-      const float ht1 = h * t1, ht2 = h * t2;
-      const float zx = s1 * fmaf(ht1, a.x, fmaf(ht2, a.w, -qh * b.z));
-      const float zy = s1 * fmaf(ht1, a.y, fmaf(ht2, b.x, -qh * b.w));
-      const float zz = s1 * fmaf(ht1, a.z, fmaf(ht2, b.y, -qh * c.x));
-      const float gx = dpow * zx, gy = dpow * zy, gz = dpow * zz;
-      // before sph_flush_scale: dpow z, then dpow z z^T / 2 with the shared off-diagonals twice
-      const float gv[kNV] = {gx,      gy,      gz,       gx * zx,  gx * zy,  gx * zz, gy * zy,
-                             gy * zz, gz * zz, dla * G, wk * dl0, wk * dl1, wk * dl2};
-      const float rs = row_reduce13(gv, lane);
-      const int slot = (int)((kSphRowSlot >> (4 * (lane & 15))) & 0xF);
-      if constexpr (kSlots) {
-        const float ws = sum_rows(rs);
-        if (lane < 16 && slot < kNV) acc[wq][slot][k] = ws;
-      } else {
-        if (slot < kNV) atomicAdd(&acc[0][slot][k], rs);
+          for (int q = 0; q < kNV; ++q) acc[w][q][t] = 0.0f;
       }
-    }
-    __syncthreads();
-    // thirteen consecutive lanes carry one entry's values: contiguous 52-byte records
-    for (int xx = threadIdx.x; xx < kNV * cnt; xx += N) {
-      const int t = xx / kNV, q = xx - kNV * t;
-      float s = acc[0][q][t];
+      int nq[St::NQ];
+      // entry e is list position end - 1 - e (back to front)
+      sph_stage_batch<TILE, BATCH, kSphMaskLoad>(S, pair_items, rec, cull, rg.x + end - 1, -1, cnt, qrad, nq, nullptr,
+                                                 qmask);
+      const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
+      for (int i = 0; i < n; ++i) {
+        const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);
+        const int jrel = end - 1 - k;
+        if (jrel >= wmax) continue;  // uniform: behind every contributor of this wavefront
+        const float4 a = S.s0[k], b = S.s1[k], c = S.s2[k];
+        float power, t1, t2, h, D, qh;
+        // evaluated on every lane (no short circuit): the gradient terms below are formed on all
+        // lanes and zeroed by selects, which needs finite operands
+        const bool hit = sph_eval(a, b, c, d, power, t1, t2, h, D, qh);
+        const bool ok = jrel < last && hit;
+        if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
+        const float G = __expf(power);
+        const float araw = c.z * G;
+        const bool live = ok && !(araw > kAlphaMax);  // contributes and unclamped
+        // alpha = 0 where the Gaussian does not contribute, so its weight below is 0 without a select
+        const float alpha = ok ? fminf(araw, kAlphaMax) : 0.0f;
+        const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
+        T = ok ? T * inv_om : T;  // transmittance in front of this Gaussian
+        const float wk = alpha * T;
+        const float4 col = S.s3[k];
+        const float dc = fmaf(dl0, col.x, fmaf(dl1, col.y, dl2 * col.z));  // dL/dC . colour
+        const float dL_da = fmaf(dc, T, -DS * inv_om);
+        DS = fmaf(dc, wk, DS);
+        const float dla = live ? dL_da : 0.0f;
+        const float dpow = dla * alpha;
+        // z / 2 = (1 / D) (h (t1 u1 + t2 u2) - qh w), zero on lanes that do not contribute (D may
+        // be 0 there)
+        const float s1 = live ? __builtin_amdgcn_rcpf(D) : 0.0f;
+        const float ht1 = h * t1, ht2 = h * t2;
+        const float zx = s1 * fmaf(ht1, a.x, fmaf(ht2, a.w, -qh * b.z));
+        const float zy = s1 * fmaf(ht1, a.y, fmaf(ht2, b.x, -qh * b.w));
+        const float zz = s1 * fmaf(ht1, a.z, fmaf(ht2, b.y, -qh * c.x));
+        const float gx = dpow * zx, gy = dpow * zy, gz = dpow * zz;
+        // before sph_flush_scale: dpow z, then dpow z z^T / 2 with the shared off-diagonals twice
+        const float gv[kNV] = {gx,      gy,      gz,       gx * zx,  gx * zy,  gx * zz, gy * zy,
+                               gy * zz, gz * zz, dla * G, wk * dl0, wk * dl1, wk * dl2};
+        const float rs = row_reduce13(gv, lane);
+        const int slot = (int)((kSphRowSlot >> (4 * (lane & 15))) & 0xF);
+        if constexpr (kSlots) {
+          const float ws = sum_rows(rs);
+          if (lane < 16 && slot < kNV) acc[wq][slot][k] = ws;
+        } else {
+          if (slot < kNV) atomicAdd(&acc[0][slot][k], rs);
+        }
+      }
+      __syncthreads();
+      // thirteen consecutive lanes carry one entry's values: contiguous 52-byte records
+      for (int xx = threadIdx.x; xx < kNV * cnt; xx += N) {
+        const int t = xx / kNV, q = xx - kNV * t;
+        double s = (double)acc[0][q][t];
 #pragma unroll
-      for (int w = 1; w < NS; ++w) s += acc[w][q][t];
-      if (s != 0.0f) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * kNV + q], s * sph_flush_scale(q));
+        for (int w = 1; w < NS; ++w) s += (double)acc[w][q][t];
+        if (s != 0.0) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * kNV + q], s * (double)sph_flush_scale(q));
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
 template <int TILE, int BATCH>
 struct SphFwdRun {
-  static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
-                  const SphRec* rec, const SphCull* cone, const double2* dirs, float* out_rgb, float* out_T, float* wT,
-                  int32_t* wl, const float* depth, float* out_depth, uint16_t* qmask, hipStream_t st) {
+  static void run(const odgs_plan* p, const TileSched& sc, const ViewTable& vt, const uint2* ranges,
+                  const uint32_t* items, const SphRec* rec, const SphCull* cone, const double2* dirs, float* out_rgb,
+                  float* out_T, float* wT, int32_t* wl, const float* depth, float* out_depth, uint16_t* qmask,
+                  hipStream_t st) {
     if (out_depth)
-      hipLaunchKernelGGL((render_sph_fwd_kernel<TILE, BATCH, true>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges,
-                         items, rec, cone, dirs, out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], depth,
-                         out_depth, qmask);
+      launch_sched(render_sph_fwd_kernel<TILE, BATCH, true>, sc, TILE * TILE, st, vt, ranges, items, rec, cone, dirs,
+                   out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], depth, out_depth, qmask);
     else
-      hipLaunchKernelGGL((render_sph_fwd_kernel<TILE, BATCH, false>), dim3(tiles), dim3(TILE * TILE), 0, st, vt,
-                         ranges, items, rec, cone, dirs, out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2],
-                         depth, out_depth, qmask);
+      launch_sched(render_sph_fwd_kernel<TILE, BATCH, false>, sc, TILE * TILE, st, vt, ranges, items, rec, cone, dirs,
+                   out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], depth, out_depth, qmask);
   }
 };
 
 template <int TILE, int BATCH>
 struct SphBwdRun {
-  static void run(const odgs_plan* p, int tiles, const ViewTable& vt, const uint2* ranges, const uint32_t* items,
-                  const SphRec* rec, const SphCull* cone, const double2* dirs, const float* wT, const int32_t* wl,
-                  const float* dL, float* g2d, const uint16_t* qmask, hipStream_t st) {
-    hipLaunchKernelGGL((render_sph_bwd_kernel<TILE, BATCH>), dim3(tiles), dim3(TILE * TILE), 0, st, vt, ranges, items,
-                       rec, cone, dirs, wT, wl, dL, g2d, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
+  static void run(const odgs_plan* p, const TileSched& sc, const ViewTable& vt, const uint2* ranges,
+                  const uint32_t* items, const SphRec* rec, const SphCull* cone, const double2* dirs, const float* wT,
+                  const int32_t* wl, const float* dL, double* g2d, const uint16_t* qmask, hipStream_t st) {
+    launch_sched(render_sph_bwd_kernel<TILE, BATCH>, sc, TILE * TILE, st, vt, ranges, items, rec, cone, dirs, wT, wl, dL,
+                 g2d, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
   }
 };
 
@@ -476,7 +483,7 @@ hipError_t launch_render_sph_fwd(const odgs_plan* p, void* ws, float* out_rgb, f
   const ViewTable vt = make_view_table(p);
   const int tiles = p->tile_base[p->n_views];
   if (tiles == 0) return hipSuccess;
-  if (!sph_dispatch<SphFwdRun>(p->s.tile, p->s.batch, p, tiles, vt, ws_ptr<uint2>(ws, p->off_ranges),
+  if (!sph_dispatch<SphFwdRun>(p->s.tile, p->s.batch, p, make_sched(p, ws, 0), vt, ws_ptr<uint2>(ws, p->off_ranges),
                                ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]), ws_ptr<SphRec>(ws, p->off_srec),
                                ws_ptr<SphCull>(ws, p->off_cone), ws_ptr<double2>(ws, p->off_dirs), out_rgb, out_T,
                                ws_ptr<float>(ws, p->off_T), ws_ptr<int32_t>(ws, p->off_last),
@@ -490,11 +497,11 @@ hipError_t launch_render_sph_bwd(const odgs_plan* p, void* ws, const float* dL_d
   const ViewTable vt = make_view_table(p);
   const int tiles = p->tile_base[p->n_views];
   if (tiles == 0) return hipSuccess;
-  if (!sph_dispatch<SphBwdRun>(p->s.tile, p->s.batch_bwd, p, tiles, vt, ws_ptr<uint2>(ws, p->off_ranges),
+  if (!sph_dispatch<SphBwdRun>(p->s.tile, p->s.batch_bwd, p, make_sched(p, ws, 1), vt, ws_ptr<uint2>(ws, p->off_ranges),
                                ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]), ws_ptr<SphRec>(ws, p->off_srec),
                                ws_ptr<SphCull>(ws, p->off_cone), ws_ptr<double2>(ws, p->off_dirs),
                                ws_ptr<float>(ws, p->off_T), ws_ptr<int32_t>(ws, p->off_last), dL_drgb,
-                               ws_ptr<float>(ws, p->off_g2d),
+                               ws_ptr<double>(ws, p->off_g2d),
                                ws_ptr<uint16_t>(ws, p->off_pval[p->pair_final ^ 1]), st))  // the forward's masks
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -268,6 +268,10 @@ __global__ __launch_bounds__(256) void count_top_kernel(const uint32_t* __restri
     carry += total;
   }
   if (threadIdx.x == 0) {
+    // a new pair list: no forward has composited it yet
+    const uint32_t gen = status->bin_gen + 1u;
+    status->bin_gen = gen;
+    status->fwd_gen = ~gen;
     status->n_pairs = (int64_t)carry;
     const int64_t stored = (int64_t)carry < capacity ? (int64_t)carry : capacity;
     status->n_pairs_stored = (int32_t)stored;
@@ -448,13 +452,55 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* __restrict_
   }
 }
 
+// Work queue of the compositors: every global tile id, in descending order of its list length
+// (the tile's compositing cost), bucketed on a logarithmic scale with 32 buckets per octave (the
+// order inside a bucket is arbitrary); one workgroup.  Also clears the persistent launches'
+// counters.
+constexpr int kQueueThreads = 1024;
+
+__device__ inline uint32_t cost_bucket(uint32_t len) {
+  // 0 for an empty list, else 1 + 32 log2(len) (exponent and top five mantissa bits; <= 993)
+  return len == 0 ? 0u : 1u + ((__float_as_uint((float)len) - 0x3f800000u) >> 18);
+}
+
+__global__ __launch_bounds__(kQueueThreads) void tile_queue_kernel(const uint2* __restrict__ ranges, int tiles,
+                                                                  uint32_t* __restrict__ ctr,
+                                                                  uint32_t* __restrict__ order) {
+  __shared__ uint32_t start[kQueueThreads];  // one bucket per thread
+  __shared__ uint32_t wsum[kQueueThreads / kWave];
+  const int t = threadIdx.x, lane = t & (kWave - 1), w = t >> 6;
+  start[t] = 0;
+  if (t < 4) ctr[t] = 0u;
+  __syncthreads();
+  for (int i = t; i < tiles; i += kQueueThreads) {
+    const uint2 r = ranges[i];
+    atomicAdd(&start[cost_bucket(r.y - r.x)], 1u);
+  }
+  __syncthreads();
+  // descending: thread t takes bucket kQueueThreads - 1 - t; exclusive scan over t
+  const uint32_t c = start[kQueueThreads - 1 - t];
+  const uint32_t incl = wave_incl_scan(c);
+  if (lane == kWave - 1) wsum[w] = incl;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int k = 0; k < w; ++k) pre += wsum[k];
+  start[kQueueThreads - 1 - t] = pre + incl - c;
+  __syncthreads();
+  for (int i = t; i < tiles; i += kQueueThreads) {
+    const uint2 r = ranges[i];
+    order[atomicAdd(&start[cost_bucket(r.y - r.x)], 1u)] = (uint32_t)i;
+  }
+}
+
 __global__ void status_reset_kernel(odgs_status* st) {
   if (threadIdx.x == 0) {
     st->flags = 0;
     st->n_pairs_stored = 0;
     st->n_pairs = 0;
     st->n_visible = 0;
-    st->reserved2 = 0;
+    st->n_culled = 0;
+    st->n_nonfinite = 0;
+    st->fwd_gen = ~st->bin_gen;  // bin_gen survives resets
   }
 }
 
@@ -485,6 +531,25 @@ hipError_t launch_status_reset(const odgs_plan* p, void* ws, hipStream_t st) {
   return hipGetLastError();
 }
 
+TileSched make_sched(const odgs_plan* p, void* ws, int which) {
+  uint32_t* q = ws_ptr<uint32_t>(ws, p->off_queue);
+  TileSched s{};
+  s.status = ws_ptr<odgs_status>(ws, p->off_status);
+  s.tiles = p->tile_base[p->n_views];
+  s.order = (p->s.flags & ODGS_FLAG_SCHED_TILE_ID) ? nullptr : q + 16;  // after 64 bytes of counters
+  s.ctr = (p->s.flags & (ODGS_FLAG_SCHED_GRID | ODGS_FLAG_SCHED_TILE_ID)) ? nullptr : q + 2 * which;
+  return s;
+}
+
+int sched_grid(const TileSched& s, int per_cu) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 1;
+  const int64_t g = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
+  return (int)(g < s.tiles ? g : s.tiles);
+}
+
 hipError_t launch_fill_u32(uint32_t* ptr, uint32_t value, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ptr, value, n);
@@ -500,9 +565,14 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * (int64_t)p->tile_base[p->n_views], st);
   if (e != hipSuccess) return e;
   // the backward's 2D gradient accumulators start cleared
-  e = launch_fill_u32(ws_ptr<uint32_t>(ws, p->off_g2d), 0u, (int64_t)p->g2d_stride * p->items, st);
+  e = launch_fill_u32(ws_ptr<uint32_t>(ws, p->off_g2d), 0u, 2 * (int64_t)p->g2d_stride * p->items, st);  // doubles
   if (e != hipSuccess) return e;
-  if (items == 0) return hipSuccess;
+  const int tiles = p->tile_base[p->n_views];
+  uint32_t* queue = ws_ptr<uint32_t>(ws, p->off_queue);
+  if (items == 0) {
+    hipLaunchKernelGGL(tile_queue_kernel, dim3(1), dim3(kQueueThreads), 0, st, ranges, tiles, queue, queue + 16);
+    return hipGetLastError();
+  }
   // 1. items by radial depth (culled items carry the largest key)
   uint32_t* dk[2] = {ws_ptr<uint32_t>(ws, p->off_dkey[0]), ws_ptr<uint32_t>(ws, p->off_dkey[1])};
   uint32_t* di[2] = {ws_ptr<uint32_t>(ws, p->off_did[0]), ws_ptr<uint32_t>(ws, p->off_did[1])};
@@ -535,6 +605,8 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
   // 5. tile ranges
   hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((p->pair_capacity + 256 * kRangeKeys - 1) / (256 * kRangeKeys))),
                      dim3(256), 0, st, pk[p->pair_final], status, ranges);
+  // 6. the compositors' work queue, longest list first
+  hipLaunchKernelGGL(tile_queue_kernel, dim3(1), dim3(kQueueThreads), 0, st, ranges, tiles, queue, queue + 16);
   return hipGetLastError();
 }
 

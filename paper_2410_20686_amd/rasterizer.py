@@ -16,8 +16,8 @@ import torch
 
 from . import _odgs as B
 
-DEFAULT_SETTINGS = dict(tile=16, batch=0, batch_bwd=0, count_work=False, pinhole=None, footprint="affine", near=0.2,
-                        far=1.0e4, dilation=0.3, pole_eps=1.0e-4, bg=(0.0, 0.0, 0.0))
+DEFAULT_SETTINGS = dict(tile=16, batch=0, batch_bwd=0, count_work=False, pinhole=None, footprint="affine",
+                        schedule="persistent", near=0.2, far=1.0e4, dilation=0.3, pole_eps=1.0e-4, bg=(0.0, 0.0, 0.0))
 
 
 def _ptr(t: torch.Tensor | None):
@@ -82,7 +82,8 @@ class Rasterizer:
         """Read the device status record (synchronises with the current stream)."""
         raw = self.ws[self.status_offset:self.status_offset + ctypes.sizeof(B.Status)].cpu().numpy().tobytes()
         st = B.Status.from_buffer_copy(raw)
-        return dict(flags=st.flags, n_pairs=st.n_pairs, n_pairs_stored=st.n_pairs_stored, n_visible=st.n_visible)
+        return dict(flags=st.flags, n_pairs=st.n_pairs, n_pairs_stored=st.n_pairs_stored, n_visible=st.n_visible,
+                    n_culled=st.n_culled, n_nonfinite=st.n_nonfinite, bin_gen=st.bin_gen, fwd_gen=st.fwd_gen)
 
     def _check_inputs(self, means, scales, quats, opac, sh, cams):
         K = (self.sh_degree + 1) ** 2
@@ -100,6 +101,7 @@ class Rasterizer:
         B.odgs_preprocess(self.plan, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opac), _ptr(sh), _ptr(cams),
                           _ptr(self.ws), self.ws_bytes, s)
         B.odgs_bin_sort(self.plan, _ptr(self.ws), self.ws_bytes, s)
+        self.generation += 1  # new pair lists: no backward may use an earlier forward's state
 
     def bin_checked(self, means, scales, quats, opac, sh, cams) -> dict:
         """Bin, then read the status; on pair-list overflow grow the capacity and bin again."""
@@ -167,7 +169,7 @@ class Rasterizer:
         footprint, G = 9: d/du, d/dv, d/dSigma_uu, d/dSigma_uv (shared), d/dSigma_vv, d/dopacity,
         d/dr, d/dg, d/db.  Spherical footprint, G = 13: d/dmu^ (3), d/dSigma~ (xx, xy, xz, yy, yz,
         zz; shared off-diagonals), d/dopacity, d/d(r, g, b)."""
-        out = torch.empty((self.n * len(self.wh), int(self.plan.g2d_stride)), dtype=torch.float32, device=self.device)
+        out = torch.empty((self.n * len(self.wh), int(self.plan.g2d_stride)), dtype=torch.float64, device=self.device)
         B.odgs_debug_g2d(self.plan, _ptr(self.ws), _ptr(out), _stream())
         return out
 
@@ -246,8 +248,8 @@ class _RenderFn(torch.autograd.Function):
     def backward(ctx, g_rgb, g_T):
         rast = ctx.rast
         if rast.generation != ctx.generation:
-            raise RuntimeError("the rasterizer ran another forward before this backward; its workspace no "
-                               "longer holds this forward's lists")
+            raise RuntimeError("the rasterizer ran another forward (or binning) before this backward; its "
+                               "workspace no longer holds this forward's lists")
         means, scales, quats, opac, sh, cams = ctx.saved_tensors
         grads = rast.render_bwd(means, scales, quats, opac, sh, cams, g_rgb.contiguous())
         return (*grads, None, None)

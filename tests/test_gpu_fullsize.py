@@ -76,12 +76,12 @@ def test_cfg2_roaming_500k_4096x2048():
 
 def test_M_500k_8x2048x1024_batched():
     sc, cams, st = scenes.config("M")
-    _check(sc, cams, st, n_pix=96, seed=1005, key_views=2)
+    _check(sc, cams, st, n_pix=96, seed=1005, key_views=cams.n_views)
 
 
 def test_cfg3_1M_8x2048x1024_batched():
     sc, cams, st = scenes.config("cfg3")
-    _check(sc, cams, st, n_pix=64, seed=1003)
+    _check(sc, cams, st, n_pix=64, seed=1003, key_views=cams.n_views)
 
 
 def test_cfg1_100k_2048x1024():
@@ -105,4 +105,4 @@ def test_cfg4_16_uneven_views_autotuned():
     del t, dL
     torch.cuda.empty_cache()
     _check(sc, cams, dict(st, tile=best["tile"], batch=best["batch"], batch_bwd=best["batch_bwd"]), n_pix=48,
-           seed=1004, key_views=1)
+           seed=1004, key_views=cams.n_views)

@@ -1,0 +1,123 @@
+"""Compositor scheduling and the device status record, through the C ABI.
+
+* The three tile schedules (persistent longest-first queue, one workgroup per tile in queue order,
+  one workgroup per tile in tile id order) composite the same tiles, so images are bit-identical
+  and gradients agree to the order in which per-tile partial sums reach the FP64 accumulators.
+* The work queue is a permutation of the global tile ids in non-increasing list length.
+* The reverse compositor refuses a pair list the forward has not composited (a bin_sort between
+  them), reporting it in the status record instead of reading stale culling masks.
+* Culled and non-finite items are counted.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2410_20686_amd import scenes
+from tests import _gpu as G
+from tests._util import settings
+from tests.test_gpu_parity import CASES, _masked_upstream
+
+pytestmark = pytest.mark.gpu
+
+
+def _uneven_case():
+    sc = scenes.roaming_scene(6007, 3, seed=81)
+    cams = scenes.uneven_cameras(4, seed=81, sizes=((128, 64), (256, 128), (512, 256)))
+    return sc, cams
+
+
+@pytest.mark.parametrize("footprint", ["affine", "spherical"])
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_schedules_agree(tile, footprint):
+    sc, cams = _uneven_case()
+    st = settings(tile=tile, footprint=footprint)
+    fwd = O.render(sc, cams, st, mode=32)
+    dL = _masked_upstream(cams, fwd["margin"], seed=1081)
+    runs = {s: G.run_gpu(sc, cams, dict(st, schedule=s), dL=dL) for s in ("persistent", "grid", "tile_id")}
+    base = runs["tile_id"]
+    for s in ("persistent", "grid"):
+        np.testing.assert_array_equal(runs[s]["rgb"], base["rgb"])
+        np.testing.assert_array_equal(runs[s]["T"], base["T"])
+        G.assert_grads_close(runs[s]["grads"], base["grads"], rtol=1e-6, floor=1e-9)
+    # and the default schedule against the oracle
+    ok = G.strict_pixels(fwd["margin"])
+    assert np.abs(runs["persistent"]["T"] - fwd["T"])[ok].max() <= G.RGB_ATOL
+    ref = O.backward(sc, cams, st, dL, mode=32)
+    G.assert_grads_close(runs["persistent"]["grads"], ref)
+
+
+def test_queue_is_longest_first_permutation():
+    import torch
+    sc, cams = _uneven_case()
+    res = G.run_gpu(sc, cams, settings(), return_rast=True)
+    rast = res["rast"]
+    p = rast.plan
+    tiles = int(p.tile_base[cams.n_views])
+    q = rast.ws[p.off_queue + 64:p.off_queue + 64 + 4 * tiles].view(torch.int32).cpu().numpy()
+    r = rast.ws[p.off_ranges:p.off_ranges + 8 * tiles].view(torch.int32).cpu().numpy().reshape(tiles, 2)
+    np.testing.assert_array_equal(np.sort(q), np.arange(tiles))
+    length = (r[:, 1] - r[:, 0])[q].astype(np.float64)
+    # longest first, up to cost buckets 1/32 of an octave wide: no later entry is longer than
+    # 33/32 of an earlier one (empty tiles last)
+    later_max = np.maximum.accumulate(length[::-1])[::-1]
+    assert (later_max[1:] <= length[:-1] * (33.0 / 32.0)).all()
+    ctr = rast.ws[p.off_queue:p.off_queue + 16].view(torch.int32).cpu().numpy()
+    np.testing.assert_array_equal(ctr, 0)  # left cleared by the persistent forward
+
+
+def test_backward_refuses_a_stale_pair_list():
+    """bin_sort between forward and backward: the reverse compositor accumulates nothing and sets
+    the stale-forward flag; a forward on the new list clears the condition."""
+    import torch
+    from paper_2410_20686_amd import _odgs as B
+    from paper_2410_20686_amd.rasterizer import Rasterizer
+    name, sc, cams, st = CASES[1]
+    wh = [tuple(int(x) for x in r) for r in cams.wh]
+    rast = Rasterizer(sc.n, sc.sh_degree, wh, st)
+    t = G.to_gpu(sc, cams)
+    rast.bin_checked(*t)
+    rast.render_fwd()
+    dL = torch.from_numpy(scenes.upstream_gradient(cams, 1090).astype(np.float32)).cuda()
+    rast.bin(*t)  # new pair list, no forward
+    rast.composite_bwd(dL)
+    s = rast.status()
+    assert s["flags"] & B.STATUS_STALE_FORWARD and s["fwd_gen"] != s["bin_gen"]
+    assert not rast.g2d().abs().max().item()
+    # preprocess resets the flags; the forward marks the list, and the backward runs
+    rast.bin(*t)
+    rast.render_fwd()
+    rast.composite_bwd(dL)
+    s = rast.status()
+    assert not s["flags"] & B.STATUS_STALE_FORWARD and s["fwd_gen"] == s["bin_gen"]
+    assert rast.g2d().abs().max().item() > 0
+
+
+def test_culled_and_nonfinite_counters():
+    """Gaussians with a NaN / infinite parameter or a zero quaternion are culled in every view
+    and counted; the others render as the oracle renders the scene without them."""
+    sc0 = scenes.sphere_scene(2003, 3, seed=91)
+    cams = scenes.yaw_cameras(2, 256, 128, seed=91)
+    st = settings()
+    bad = np.array([5, 77, 400, 1001, 1500, 2002])
+    sc = sc0.copy()
+    sc.means[1, bad[0]] = np.nan
+    sc.scales[2, bad[1]] = np.inf
+    sc.quats[:, bad[2]] = 0.0
+    sc.opacities[bad[3]] = np.nan
+    sc.sh[17, bad[4]] = -np.inf
+    sc.quats[3, bad[5]] = np.nan
+    keep = np.setdiff1d(np.arange(sc.n), bad)
+    good = sc0.subset(keep)
+    res = G.run_gpu(sc, cams, st, return_rast=True)
+    s = res["status"]
+    rows = O.project(good, cams, st)
+    kept = int((rows[..., O.F_KEPT] > 0).sum())
+    assert s["n_nonfinite"] == len(bad)
+    assert s["n_visible"] == kept and s["n_culled"] == cams.n_views * sc.n - kept
+    okeys, ovals = O.keys(good, cams, st)
+    keys, gauss = res["rast"].keys()
+    np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint64), okeys)
+    np.testing.assert_array_equal(gauss.cpu().numpy(), keep[ovals])
+    ref = O.render(good, cams, st, mode=32)
+    ok = G.strict_pixels(ref["margin"])
+    assert np.abs(res["T"] - ref["T"])[ok].max() <= G.RGB_ATOL
