@@ -707,6 +707,7 @@ struct Contrib {
   int32_t idx;
   int clamped;
   double du, dv;
+  double power;  // the exponent as the compositing pass evaluated it (its own precision)
 };
 
 struct PixResult {
@@ -766,7 +767,7 @@ PixResult composite(const int32_t* order, int64_t count, const Rec<R>* recs, int
     T = Tn;
     res.n_contrib++;
     res.sig = mix(res.sig, ((uint64_t)(uint32_t)idx << 1) | (uint64_t)clamped);
-    if (contrib) contrib->push_back(Contrib{idx, clamped, (double)du, (double)dv});
+    if (contrib) contrib->push_back(Contrib{idx, clamped, (double)du, (double)dv, (double)power});
   }
   for (int c = 0; c < 3; ++c) res.rgb[c] = (double)C[c] + (double)T * bg[c];
   res.T = (double)T;
@@ -923,7 +924,7 @@ PixResult composite_sph(const int32_t* order, int64_t count, const SR* recs, con
     T = Tn;
     res.n_contrib++;
     res.sig = mix(res.sig, ((uint64_t)(uint32_t)idx << 1) | (uint64_t)clamped);
-    if (contrib) contrib->push_back(Contrib{idx, clamped, 0.0, 0.0});
+    if (contrib) contrib->push_back(Contrib{idx, clamped, 0.0, 0.0, (double)power});
   }
   for (int c = 0; c < 3; ++c) res.rgb[c] = (double)C[c] + (double)T * bg[c];
   res.T = (double)T;
@@ -1111,7 +1112,7 @@ PixResult render_pixel_sph(const Prepared& P, const std::vector<SR>& recs, const
 // with d power / d(a, b, c) = -(du^2/2, du dv, dv^2/2) and d power / d(u, v) = Sigma^-1 d.
 // g2d layout per item: [u, v, conic a, conic b, conic c, opacity, r, g, b].
 void pixel_backward(const std::vector<Contrib>& cl, const std::vector<Rec<double>>& rec64, const double* gpix,
-                    const double* bg, double* g2d_view, int stride) {
+                    const double* bg, double* g2d_view, int stride, bool decided_power) {
   const size_t n = cl.size();
   std::vector<double> alpha(n), T(n + 1), G(n);
   T[0] = 1.0;
@@ -1119,7 +1120,7 @@ void pixel_backward(const std::vector<Contrib>& cl, const std::vector<Rec<double
     const Rec<double>& g = rec64[cl[j].idx];
     const double du = cl[j].du, dv = cl[j].dv;
     const double t1 = g.l0 * du + g.l1 * dv, t2 = g.l2 * dv;
-    const double power = -(t1 * t1 + t2 * t2);
+    const double power = decided_power ? cl[j].power : -(t1 * t1 + t2 * t2);
     G[j] = std::exp(power);
     alpha[j] = cl[j].clamped ? 0.99 : g.o * G[j];
     T[j + 1] = T[j] * (1.0 - alpha[j]);
@@ -1170,7 +1171,7 @@ void pixel_backward(const std::vector<Contrib>& cl, const std::vector<Rec<double
 //   g_def [stride]: mu^ (3), A (6, off-diagonals as one shared variable), opacity, r, g, b.
 //   g_ker [13] (optional): the kernel's layout, mu^ (3), Sigma~ (6, shared), opacity, rgb, from
 //     dm/dSigma~ = -A (dm/dA) A = -z z^T with z = A v.
-void pixel_backward_sph(const std::vector<Contrib>& cl, const std::vector<SphRec64>& rec, const double d[3],
+void pixel_backward_sph(const std::vector<Contrib>& cl, const std::vector<SphRec64>& rec, const double d[3], bool decided_power,
                         const double* gpix, const double* bg, double* g_def, int stride, double* g_ker) {
   const size_t n = cl.size();
   std::vector<double> alpha(n), T(n + 1), G(n), pw(n);
@@ -1179,6 +1180,7 @@ void pixel_backward_sph(const std::vector<Contrib>& cl, const std::vector<SphRec
     const SphRec64& g = rec[cl[j].idx];
     double p = 0.0;
     sph_power(g, d, p);
+    if (decided_power) p = cl[j].power;
     pw[j] = p;
     G[j] = std::exp(p);
     alpha[j] = cl[j].clamped ? 0.99 : g.o * G[j];
@@ -1507,11 +1509,17 @@ int oracle_render(const double* means, const double* scales, const double* quats
 // inputs, G = 9 (affine) or 13 (spherical footprint: mu^, A, opacity, rgb); g2d_kernel
 // (optional, spherical footprint only) [V][N][13] the same in the kernel's variables (mu^,
 // Sigma~, opacity, rgb).
+// mode 33: the mode-32 contributor lists, and each contributor's alpha from the exponent exactly as
+// that float pass evaluated it (everything else double): the same derivative taken at the float
+// exponents, whose distance from mode 32's gradient measures how far float evaluation of the
+// exponent alone moves each gradient element.
 int oracle_backward(const double* means, const double* scales, const double* quats, const double* opac,
                     const double* sh, int64_t n, int deg, const double* cams, const int32_t* wh, int V,
                     const double* settings, int mode, const int32_t* pix, int64_t npix, const double* dL,
                     double* d_means, double* d_scales, double* d_quats, double* d_opac, double* d_sh, double* g2d,
                     double* g2d_kernel) {
+  const bool decided = mode == 33;
+  if (decided) mode = 32;
   Scene sc = make_scene(means, scales, quats, opac, sh, n, deg);
   Prepared P;
   prepare(sc, cams, wh, V, settings, P);
@@ -1533,7 +1541,7 @@ int oracle_backward(const double* means, const double* scales, const double* qua
         else render_pixel_sph<double, SphRec64>(P, s64, nullptr, v, x, y, &cl);
         double d[3];
         pixel_dir(x, y, W, H, d);
-        pixel_backward_sph(cl, s64, d, gpix, P.st.bg, gv, stride, gk);
+        pixel_backward_sph(cl, s64, d, decided, gpix, P.st.bg, gv, stride, gk);
       };
       if (pix == nullptr) {
         const int64_t off = pix_offset(P, v);
@@ -1572,7 +1580,7 @@ int oracle_backward(const double* means, const double* scales, const double* qua
       std::vector<Contrib> cl;
       if (mode == 32) render_pixel<float>(P, r32, nullptr, v, x, y, &cl);
       else render_pixel<double>(P, r64, nullptr, v, x, y, &cl);
-      pixel_backward(cl, rvals, gpix, P.st.bg, gv, stride);
+      pixel_backward(cl, rvals, gpix, P.st.bg, gv, stride, decided);
     };
     if (pix == nullptr) {
       const int64_t off = pix_offset(P, v);

@@ -14,8 +14,8 @@
 // done.  Backward: back to front from the last contributor, transmittance recovered by
 // multiplying with 1/(1 - alpha); the nine per-pixel gradients of the 2D quantities are summed
 // over each 16-lane row by a DPP butterfly that leaves one value per lane, over the four rows by
-// the row-swap permutes, kept per wavefront in LDS, and reach global memory with one float atomic
-// per (Gaussian, tile, quantity).
+// the row-swap permutes, kept per wavefront in LDS, and reach global memory with one double atomic
+// per (Gaussian, tile, quantity), so the totals do not depend on the order in which tiles finish.
 // One launch covers all views of a step: the grid spans the global tile ids of every view.
 #include <type_traits>
 #include <utility>
@@ -553,17 +553,46 @@ struct BwdPixel {
   int last;
 };
 
-// The shape values are accumulated per pixel without their constant factors, which are powers of
-// two (with h = Sigma^-1 d / 2 = L^T (t1, t2): d power / d(u, v) = 2 h, d power / d Sigma_2D = 2 h h^T,
-// whose off-diagonal slot takes both symmetric entries, 4 h_u h_v); multiplying the per-tile sums by
-// them once at the flush gives exactly the same floats.
-__device__ inline float g2d_flush_scale(int q) { return q == 3 ? 4.0f : (q < 5 ? 2.0f : 1.0f); }
+// The position and shape sums are taken in the footprint's whitened coordinates t = L d
+// (t1 = l0 du + l1 dv, t2 = l2 dv, L = [[l0, l1], [0, l2]] the record's factor of Sigma^-1 / 2, so
+// power = -|t|^2): per pixel dpow * t and dpow * t t^T, whose entries are all of the same order for
+// any footprint shape.  With h = L^T t = Sigma^-1 d / 2, d power / d(u, v) = 2 h and
+// d power / d Sigma_2D = 2 h h^T, so the per-tile sums S_t = sum dpow t and Z = sum dpow t t^T map
+// exactly to g_(u,v) = 2 L^T S_t and g_Sigma = 2 L^T Z L.  That map is applied once per (Gaussian,
+// tile) in double at the flush.  (Summing dpow h h^T directly in float loses the long axis of a
+// needle-like footprint: there h lies almost along the short axis and the long-axis component of
+// h h^T sits ~1e5 below the rounding of the short one.)
+template <int NS, int B>
+__device__ inline double acc_total(const float (&acc)[NS][9][B], int q, int t) {
+  double s = (double)acc[0][q][t];
+#pragma unroll
+  for (int w = 1; w < NS; ++w) s += (double)acc[w][q][t];
+  return s;
+}
 
-// One pixel's contribution of a Gaussian to the nine 2D gradients (added to gq when ADD, else
-// written, both before g2d_flush_scale), and the pixel's recursion step.  `ok`: the Gaussian
-// contributed to this pixel; t1 = l0 du + l1 dv, bxt2 = l2^2 dv.
+// Value q of an entry's 2D-gradient record (layout of g2d) from its per-wavefront sums; a, b: the
+// entry's staged record words (l0 = a.z, l1 = a.w, l2 = b.x).
+template <int NS, int B>
+__device__ inline double g2d_flush_value(const float (&acc)[NS][9][B], int q, int t, const float4& a, const float4& b) {
+  const double l0 = a.z, l1 = a.w, l2 = b.x;
+  switch (q) {
+    case 0: return 2.0 * l0 * acc_total(acc, 0, t);
+    case 1: return 2.0 * (l1 * acc_total(acc, 0, t) + l2 * acc_total(acc, 1, t));
+    case 2: return 2.0 * (l0 * l0) * acc_total(acc, 2, t);
+    case 3: return 4.0 * l0 * (l1 * acc_total(acc, 2, t) + l2 * acc_total(acc, 3, t));
+    case 4: {
+      const double z11 = acc_total(acc, 2, t), z12 = acc_total(acc, 3, t), z22 = acc_total(acc, 4, t);
+      return 2.0 * ((l1 * l1) * z11 + 2.0 * (l1 * l2) * z12 + (l2 * l2) * z22);
+    }
+    default: return acc_total(acc, q, t);
+  }
+}
+
+// One pixel's contribution of a Gaussian to the nine per-tile sums (added to gq when ADD, else
+// written; slots 0..4 in whitened coordinates as above), and the pixel's recursion step.  `ok`:
+// the Gaussian contributed to this pixel; t1 = l0 du + l1 dv, t2 = l2 dv.
 template <bool ADD>
-__device__ inline void bwd_pixel_step(BwdPixel& P, bool ok, float power, float t1, float bxt2, const float4& a,
+__device__ inline void bwd_pixel_step(BwdPixel& P, bool ok, float power, float t1, float t2, const float4& a,
                                       const float4& b, const float4& c, float (&gq)[9]) {
   const float G = __expf(power);
   const float araw = b.z * G;
@@ -578,10 +607,9 @@ __device__ inline void bwd_pixel_step(BwdPixel& P, bool ok, float power, float t
   P.DS = fmaf(dc, wk, P.DS);
   const float dla = live ? dL_da : 0.0f;
   const float dpow = dla * alpha;
-  const float hx = a.z * t1, hy = fmaf(a.w, t1, bxt2);
-  const float g0 = dpow * hx, g1 = dpow * hy;
+  const float g0 = dpow * t1, g1 = dpow * t2;
   // values 2..8 are products x_q y_q (fused into the running sums when adding)
-  const float x[7] = {g0, g0, g1, dla, wk, wk, wk}, y[7] = {hx, hy, hy, G, P.dl0, P.dl1, P.dl2};
+  const float x[7] = {g0, g0, g1, dla, wk, wk, wk}, y[7] = {t1, t2, t2, G, P.dl0, P.dl1, P.dl2};
   gq[0] = ADD ? gq[0] + g0 : g0;
   gq[1] = ADD ? gq[1] + g1 : g1;
 #pragma unroll
@@ -589,9 +617,8 @@ __device__ inline void bwd_pixel_step(BwdPixel& P, bool ok, float power, float t
 }
 
 // g2d layout: [items][9] = d/du, d/dv, d/dS_uu, d/dS_uv, d/dS_vv, d/dopacity, d/dr, d/dg,
-// d/db(colour), where Sigma_2D = [[S_uu, S_uv], [S_uv, S_vv]] (S_uv the shared off-diagonal).
-// Accumulating w.r.t. Sigma_2D rather than its inverse keeps the sums well scaled for very
-// anisotropic footprints (no later multiplication by the inverse covariance twice).
+// d/db(colour), where Sigma_2D = [[S_uu, S_uv], [S_uv, S_vv]] (S_uv the shared off-diagonal),
+// formed per (Gaussian, tile) from the whitened-coordinate sums (g2d_flush_value).
 template <int TILE, int BATCH>
 __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, const uint2* __restrict__ ranges,
                                                                 const uint32_t* __restrict__ pair_items,
@@ -687,7 +714,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
         if (kSlots && pend) red_read(red[wq], lane, r0, r1);  // previous accepted entry's values
         const float4 c = S.s2[k];
         float gq[9];
-        bwd_pixel_step<false>(P, ok, power, t1, b.x * t2, a, b, c, gq);
+        bwd_pixel_step<false>(P, ok, power, t1, t2, a, b, c, gq);
         if constexpr (kSlots) {
           if (pend) {
             const float sj = red_finish(r0, r1);
@@ -711,13 +738,11 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       }
       __syncthreads();
       // nine consecutive lanes carry one entry's nine values, so one atomic instruction covers
-      // about seven items' contiguous 36-byte gradient records instead of 64 scattered lines
+      // about seven items' contiguous 72-byte gradient records instead of 64 scattered lines
       for (int x = threadIdx.x; x < 9 * cnt; x += N) {
         const int t = x / 9, q = x - 9 * t;
-        double s = (double)acc[0][q][t];
-#pragma unroll
-        for (int w = 1; w < NS; ++w) s += (double)acc[w][q][t];
-        if (s != 0.0) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s * (double)g2d_flush_scale(q));
+        const double s = g2d_flush_value(acc, q, t, S.s0[t], S.s1[t]);
+        if (s != 0.0) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s);
       }
       __syncthreads();
     }
@@ -737,8 +762,11 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
   using St = Stage<TILE, BATCH, 2>;
   constexpr int N = St::N;
   constexpr int QPR = TILE / 8;
-  constexpr bool kSlots = St::NW <= 4;
-  constexpr int NS = kSlots ? St::NW : 1;
+  // A slot set per wavefront up to four wavefronts; beyond (tile 32: eight) wavefronts w and w + 4
+  // share set w % 4 and add into it.  Two additions onto a cleared slot give the same float in
+  // either order (addition is commutative), so the per-tile sums do not depend on wavefront timing.
+  constexpr int NS = St::NW <= 4 ? St::NW : 4;
+  static_assert(St::NW <= 2 * NS, "at most two wavefronts per slot set");
   __shared__ St S;
   __shared__ float acc[NS][9][BATCH + 1];  // padded rows: the nine slot writes hit nine banks
   __shared__ int smax;
@@ -817,31 +845,29 @@ __global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
         const uint64_t balb = __builtin_amdgcn_ballot_w64(jrel < B.last) & __builtin_amdgcn_ballot_w64(inb);
         if ((bala | balb) == 0ull) continue;  // uniform
         const float4 c = S.s2[k];
-        const float bxt2 = b.x * t2;
         float gq[9];
         if (bala != 0ull) {
-          bwd_pixel_step<false>(A, oka, pa, t1a, bxt2, a, b, c, gq);
-          if (balb != 0ull) bwd_pixel_step<true>(B, okb, pb, t1b, bxt2, a, b, c, gq);
+          bwd_pixel_step<false>(A, oka, pa, t1a, t2, a, b, c, gq);
+          if (balb != 0ull) bwd_pixel_step<true>(B, okb, pb, t1b, t2, a, b, c, gq);
         } else {
-          bwd_pixel_step<false>(B, okb, pb, t1b, bxt2, a, b, c, gq);
+          bwd_pixel_step<false>(B, okb, pb, t1b, t2, a, b, c, gq);
         }
         const float rs = row_reduce9(gq, lane & 8, lane & 4, lane & 2, lane & 1);
-        if constexpr (kSlots) {
-          const float ws = sum_rows(rs);
-          if (lane < 16 && slot < 9) acc[wq][slot][k] = ws;
-        } else {
-          if (slot < 9) atomicAdd(&acc[0][slot][k], rs);
+        const float ws = sum_rows(rs);
+        if (lane < 16 && slot < 9) {
+          if constexpr (St::NW > NS)
+            atomicAdd(&acc[wq % NS][slot][k], ws);
+          else
+            acc[wq][slot][k] = ws;
         }
       }
       __syncthreads();
       // nine consecutive lanes carry one entry's nine values, so one atomic instruction covers
-      // about seven items' contiguous 36-byte gradient records instead of 64 scattered lines
+      // about seven items' contiguous 72-byte gradient records instead of 64 scattered lines
       for (int x = threadIdx.x; x < 9 * cnt; x += N) {
         const int t = x / 9, q = x - 9 * t;
-        double s = (double)acc[0][q][t];
-#pragma unroll
-        for (int w = 1; w < NS; ++w) s += (double)acc[w][q][t];
-        if (s != 0.0) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s * (double)g2d_flush_scale(q));
+        const double s = g2d_flush_value(acc, q, t, S.s0[t], S.s1[t]);
+        if (s != 0.0) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s);
       }
       __syncthreads();
     }

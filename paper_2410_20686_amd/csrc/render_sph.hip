@@ -14,8 +14,8 @@
 //
 // Backward: per accepted (Gaussian, wavefront) the 13 gradient values (mu^ (3), Sigma~ (6),
 // opacity, rgb) are summed over each 16-lane row by a DPP butterfly and over rows by the
-// row-swap permutes, kept per wavefront in LDS, and flushed with one float atomic per (Gaussian,
-// tile, value) to contiguous 52-byte records.
+// row-swap permutes, kept per wavefront in LDS, and flushed with one double atomic per (Gaussian,
+// tile, value) to contiguous 104-byte records.
 #include "common.h"
 #include "wave.h"
 
@@ -304,18 +304,59 @@ __device__ inline float row_reduce13(const float (&g)[kNV], int lane) {
   return bfly<0xB1>(e0, e1, b0);                                               // quad_perm [1,0,3,2]
 }
 
-// The per-pixel values are accumulated without their constant factors (z / 2 in place of z, no
-// 1/2 on the diagonal): value q is multiplied by 2^e_q, e_q = bits 2q..2q+1 of kSphFlushExp, once
-// per (Gaussian, tile) at the flush, which gives exactly the same floats.
-constexpr uint32_t kSphFlushExp = 0x19A55u;  // e = 1,1,1, 1,2,2,1,2,1, 0,0,0,0
-__device__ inline float sph_flush_scale(int q) { return (float)(1u << ((kSphFlushExp >> (2 * q)) & 3u)); }
-
 // g2d layout [items][13]: d/dmu^ (3), d/dSigma~ (xx, xy, xz, yy, yz, zz; off-diagonals as one
 // shared variable), d/dopacity, d/d(r, g, b).  With A = Sigma~^-1 and the ray's closest approach
 // t* d (t* = h / D) the exponent p = -m / 2 has dp/dmu^ = z and dp/dSigma~ = z z^T / 2, where
-// z = A (t* d - mu^) = (2 / D) (h (t1 u1 + t2 u2) - qh w) (A = 2 (u1 u1^T + u2 u2^T) + (2 / k2) w w^T,
-// u1, u2 tangent, w . mu^ = 1): no inverse and no cancellation at the footprint's scale.  Like
-// the affine path this accumulates w.r.t. the covariance, which keeps the sums well scaled.
+// z = A (t* d - mu^) = 2 N^T y, y = (h t1, h t2, qh) / D, N = [u1; u2; -w] (rows; A = 2 (u1 u1^T +
+// u2 u2^T) + (2 / k2) w w^T, u1, u2 tangent, w . mu^ = 1).  y is the offset in the Gaussian's
+// whitened coordinates (up to constant factors per component), all three of the same order, so the
+// per-tile sums S_y = sum dpow y and Y = sum dpow y y^T stay well scaled for any shape; they map
+// exactly to g_mu^ = 2 N^T S_y and g_Sigma~ = 2 N^T Y N, applied once per (Gaussian, tile) in
+// double at the flush.
+template <int NS, int B>
+__device__ inline double sph_acc_total(const float (&acc)[NS][kNV][B], int q, int t) {
+  double s = (double)acc[0][q][t];
+#pragma unroll
+  for (int w = 1; w < NS; ++w) s += (double)acc[w][q][t];
+  return s;
+}
+
+// Component i of the columns of N = [u1; u2; -w] (rows), i.e. (u1_i, u2_i, -w_i), from the staged
+// record words (u1 = a.xyz, u2 = (a.w, b.x, b.y), w = (b.z, b.w, c.x)); selects, no indexed array.
+__device__ inline void sph_ncol(int i, const float4& a, const float4& b, const float4& c, float& n0, float& n1,
+                                float& n2) {
+  n0 = i == 0 ? a.x : (i == 1 ? a.y : a.z);
+  n1 = i == 0 ? a.w : (i == 1 ? b.x : b.y);
+  n2 = -(i == 0 ? b.z : (i == 1 ? b.w : c.x));
+}
+
+// Value q of an entry's gradient record (layout of g2d) from its per-wavefront sums (slots: S_y (3),
+// Y (y1y1, y1y2, y1y3, y2y2, y2y3, y3y3), opacity, rgb); a, b, c: the entry's staged record words.
+template <int NS, int B>
+__device__ inline double sph_flush_value(const float (&acc)[NS][kNV][B], int q, int t, const float4& a, const float4& b,
+                                         const float4& c) {
+  if (q >= 9) return sph_acc_total(acc, q, t);
+  if (q < 3) {
+    float n0, n1, n2;
+    sph_ncol(q, a, b, c, n0, n1, n2);
+    return 2.0 * ((double)n0 * sph_acc_total(acc, 0, t) + (double)n1 * sph_acc_total(acc, 1, t) +
+                  (double)n2 * sph_acc_total(acc, 2, t));
+  }
+  // Sigma~ entry (i, j), q - 3 = 0..5 -> (0,0) (0,1) (0,2) (1,1) (1,2) (2,2)
+  const int i = (q >= 6) + (q >= 8), j = q == 3 ? 0 : ((q == 4 || q == 6) ? 1 : 2);
+  float a0, a1, a2, b0, b1, b2;
+  sph_ncol(i, a, b, c, a0, a1, a2);
+  sph_ncol(j, a, b, c, b0, b1, b2);
+  const double y00 = sph_acc_total(acc, 3, t), y01 = sph_acc_total(acc, 4, t), y02 = sph_acc_total(acc, 5, t);
+  const double y11 = sph_acc_total(acc, 6, t), y12 = sph_acc_total(acc, 7, t), y22 = sph_acc_total(acc, 8, t);
+  // n_i^T Y n_j
+  const double m0 = y00 * b0 + y01 * b1 + y02 * b2;
+  const double m1 = y01 * b0 + y11 * b1 + y12 * b2;
+  const double m2 = y02 * b0 + y12 * b1 + y22 * b2;
+  const double nyn = a0 * m0 + a1 * m1 + a2 * m2;
+  return (i == j ? 2.0 : 4.0) * nyn;  // the shared off-diagonal takes both symmetric entries
+}
+
 template <int TILE, int BATCH>
 __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items,
@@ -324,8 +365,10 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
     double* __restrict__ g2d, float bg0, float bg1, float bg2, const uint16_t* __restrict__ qmask, TileSched sc) {
   using St = SphStage<TILE, BATCH>;
   constexpr int N = St::N;
-  constexpr bool kSlots = St::NW <= 4;  // a slot set per wavefront, else one shared set (LDS atomics)
-  constexpr int NS = kSlots ? St::NW : 1;
+  // A slot set per wavefront up to four wavefronts; beyond (tile 32: sixteen) wavefronts w and
+  // w + NW / 2 share set w % (NW / 2) and add into it: two additions onto a cleared slot give the
+  // same float in either order, so the per-tile sums do not depend on wavefront timing.
+  constexpr int NS = St::NW <= 4 ? St::NW : St::NW / 2;
   __shared__ St S;
   __shared__ float acc[NS][kNV][BATCH + 1];
   __shared__ int smax;
@@ -403,34 +446,30 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
         DS = fmaf(dc, wk, DS);
         const float dla = live ? dL_da : 0.0f;
         const float dpow = dla * alpha;
-        // z / 2 = (1 / D) (h (t1 u1 + t2 u2) - qh w), zero on lanes that do not contribute (D may
-        // be 0 there)
+        // whitened offset y = (h t1, h t2, qh) / D, zero on lanes that do not contribute (D may be
+        // 0 there)
         const float s1 = live ? __builtin_amdgcn_rcpf(D) : 0.0f;
-        const float ht1 = h * t1, ht2 = h * t2;
-        const float zx = s1 * fmaf(ht1, a.x, fmaf(ht2, a.w, -qh * b.z));
-        const float zy = s1 * fmaf(ht1, a.y, fmaf(ht2, b.x, -qh * b.w));
-        const float zz = s1 * fmaf(ht1, a.z, fmaf(ht2, b.y, -qh * c.x));
-        const float gx = dpow * zx, gy = dpow * zy, gz = dpow * zz;
-        // before sph_flush_scale: dpow z, then dpow z z^T / 2 with the shared off-diagonals twice
-        const float gv[kNV] = {gx,      gy,      gz,       gx * zx,  gx * zy,  gx * zz, gy * zy,
-                               gy * zz, gz * zz, dla * G, wk * dl0, wk * dl1, wk * dl2};
+        const float y1 = s1 * (h * t1), y2 = s1 * (h * t2), y3 = s1 * qh;
+        const float gx = dpow * y1, gy = dpow * y2, gz = dpow * y3;
+        const float gv[kNV] = {gx,      gy,      gz,       gx * y1,  gx * y2,  gx * y3, gy * y2,
+                               gy * y3, gz * y3, dla * G, wk * dl0, wk * dl1, wk * dl2};
         const float rs = row_reduce13(gv, lane);
         const int slot = (int)((kSphRowSlot >> (4 * (lane & 15))) & 0xF);
-        if constexpr (kSlots) {
-          const float ws = sum_rows(rs);
-          if (lane < 16 && slot < kNV) acc[wq][slot][k] = ws;
-        } else {
-          if (slot < kNV) atomicAdd(&acc[0][slot][k], rs);
+        const float ws = sum_rows(rs);
+        if (lane < 16 && slot < kNV) {
+          if constexpr (St::NW > NS)
+            atomicAdd(&acc[wq % NS][slot][k], ws);
+          else
+            acc[wq][slot][k] = ws;
         }
       }
       __syncthreads();
-      // thirteen consecutive lanes carry one entry's values: contiguous 52-byte records
+      // thirteen consecutive lanes carry one entry's values: contiguous 104-byte records
+#pragma unroll 1
       for (int xx = threadIdx.x; xx < kNV * cnt; xx += N) {
         const int t = xx / kNV, q = xx - kNV * t;
-        double s = (double)acc[0][q][t];
-#pragma unroll
-        for (int w = 1; w < NS; ++w) s += (double)acc[w][q][t];
-        if (s != 0.0) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * kNV + q], s * (double)sph_flush_scale(q));
+        const double s = sph_flush_value(acc, q, t, S.s0[t], S.s1[t], S.s2[t]);
+        if (s != 0.0) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * kNV + q], s);
       }
       __syncthreads();
     }

@@ -45,23 +45,38 @@ def run_gpu(scene, cams, settings, dL=None, pair_capacity=None, return_rast=Fals
 
 
 def assert_grads_close(gpu, ref, names=("means", "scales", "quats", "opacities", "sh"), rtol=GRAD_RTOL,
-                       floor=GRAD_FLOOR, per_gaussian_floor=None):
-    """|gpu - ref| <= rtol |ref| + floor * max|ref| (over the tensor), plus optionally, for the
-    tensors named in per_gaussian_floor, that fraction of the largest |ref| component of the same
-    Gaussian (for quantities whose small components are cancellations of the large ones)."""
+                       floor=GRAD_FLOOR, slack=None):
+    """|gpu - ref| <= rtol |ref| + floor * max|ref| (over the tensor), plus, per element, the
+    tensors' entries in `slack` when given (float_exponent_slack)."""
     report = {}
     for k in names:
         a, b = np.asarray(gpu[k], dtype=np.float64), np.asarray(ref[k], dtype=np.float64)
         gmax = np.abs(b).max() if b.size else 0.0
         err = np.abs(a - b)
         lim = rtol * np.abs(b) + floor * gmax
-        if per_gaussian_floor and k in per_gaussian_floor and b.ndim == 2 and b.size:
-            lim = lim + per_gaussian_floor[k] * np.abs(b).max(axis=0, keepdims=True)
+        if slack is not None:
+            lim = lim + np.asarray(slack[k], dtype=np.float64)
         bad = ~(err <= lim)  # NaN counts as out of tolerance
         report[k] = (int(bad.sum()), float((err / np.maximum(lim, 1e-300)).max()) if b.size else 0.0)
         assert not bad.any(), "%s: %d elements out of tolerance, worst ratio %.3g, example gpu=%r ref=%r" % (
             k, bad.sum(), report[k][1], a[bad][:3], b[bad][:3])
     return report
+
+
+def float_exponent_slack(scene, cams, settings, dL, ref):
+    """Per-element distance between the oracle's gradient (mode 32: float contributor decisions,
+    double arithmetic) and the same derivative taken at the exponents as the float pass evaluated
+    them (mode 33).  A float32 renderer composites with float exponents, so its gradient can sit
+    this far from the double-exponent reference before any error of its own; the spherical
+    footprint's exponent of a needle-like Gaussian (axis ratios ~800:1) is where this reaches the
+    1e-3 scale.  Keys: the five parameter tensors, plus "g2d" (kernel layout) for the spherical
+    footprint."""
+    from oracle import oracle as O
+    alt = O.backward(scene, cams, settings, dL, mode=33, want_g2d="g2d_kernel" in ref)
+    out = {k: np.abs(ref[k] - alt[k]) for k in ("means", "scales", "quats", "opacities", "sh")}
+    if "g2d_kernel" in ref:
+        out["g2d"] = np.abs(ref["g2d_kernel"] - alt["g2d_kernel"])
+    return out
 
 
 def strict_pixels(margin, threshold=TERM_MARGIN):

@@ -72,31 +72,15 @@ def test_backward_matches_oracle(case):
     labels = ("mx", "my", "mz", "Sxx", "Sxy", "Sxz", "Syy", "Syz", "Szz", "opacity", "r", "g", "b")
     g, r = res["g2d"], ref["g2d_kernel"]
     assert g.shape[-1] == 13
-    if name == "sph_needles":
-        # Axis ratios up to 800:1: an item's mu^ and Sigma~ gradients are sums over its pixels of
-        # terms that cancel to a small remainder along the long axis, so the float sums' rounding
-        # (relative to the terms, not the remainder) is judged against 1e-4 of the item's vector
-        # (mu^) or matrix (Sigma~) gradient besides the element's own 1e-3.
-        for sl in (slice(0, 3), slice(3, 9)):
-            scale = np.abs(r[..., sl]).max(axis=-1, keepdims=True)
-            err = np.abs(g[..., sl] - r[..., sl])
-            lim = G.GRAD_RTOL * np.abs(r[..., sl]) + 1e-4 * scale + G.GRAD_FLOOR * np.abs(r[..., sl]).max()
-            assert (err <= lim).all(), (sl, np.count_nonzero(~(err <= lim)))
-        rest = labels[9:]
-        G.assert_grads_close({k: g[..., 9 + j] for j, k in enumerate(rest)},
-                             {k: r[..., 9 + j] for j, k in enumerate(rest)}, names=rest)
-    else:
-        G.assert_grads_close({k: g[..., j] for j, k in enumerate(labels)},
-                             {k: r[..., j] for j, k in enumerate(labels)}, names=labels)
+    # every tensor, needles included, at the gradient tolerance plus the per-element distance the
+    # float evaluation of the exponent alone puts between a float renderer and the reference
+    sl = G.float_exponent_slack(sc, cams, st, dL, ref)
+    G.assert_grads_close({k: g[..., j] for j, k in enumerate(labels)},
+                         {k: r[..., j] for j, k in enumerate(labels)}, names=labels,
+                         slack={k: sl["g2d"][..., j] for j, k in enumerate(labels)})
     adj = O.project_adjoint(sc, cams, st, res["g2d"].astype(np.float64))
     G.assert_grads_close(res["grads"], adj, rtol=1e-5, floor=1e-7)
-    # needles: see the affine parity test (scale / rotation gradients cancel along the long axis);
-    # their mean gradients carry the cancellation noted above, judged per Gaussian like there
-    if name == "sph_needles":
-        rep = G.assert_grads_close(res["grads"], ref, names=("means", "opacities", "sh"),
-                                   per_gaussian_floor={"means": 1e-4})
-    else:
-        rep = G.assert_grads_close(res["grads"], ref)
+    rep = G.assert_grads_close(res["grads"], ref, slack=sl)
     print(name, rep)
 
 

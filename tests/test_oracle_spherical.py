@@ -288,3 +288,23 @@ def test_kernel_layout_adjoint_reproduces_the_backward():
     for k in ("means", "scales", "quats", "opacities", "sh"):
         np.testing.assert_allclose(h[k], g[k], rtol=1e-7, atol=1e-10 * np.abs(g[k]).max())
     assert np.abs(g["means"]).max() > 0
+
+
+@pytest.mark.parametrize("footprint", ["affine", "spherical"])
+def test_float_exponent_mode_moves_gradients_only_slightly(footprint):
+    """Mode 33 (the derivative taken at the float pass's own exponents) differs from the reference
+    (mode 32) only through the exponents' float rounding: on ordinary Gaussians by less than 5e-5
+    (affine) or 5e-4 (spherical: three-term dot products of the ray with whitening vectors of
+    length ~1/angular size) relative per element, plus a 1e-7 floor of the tensor's scale."""
+    sc = scenes.roaming_scene(700, 3, seed=44, r_range=(1.5, 6.0))
+    cams = scenes.uneven_cameras(2, seed=44, sizes=((128, 64), (256, 128)))
+    st = settings(footprint=footprint)
+    dL = scenes.upstream_gradient(cams, 1044).astype(np.float64)
+    a = O.backward(sc, cams, st, dL, mode=32)
+    b = O.backward(sc, cams, st, dL, mode=33)
+    moved = 0.0
+    for k in ("means", "scales", "quats", "opacities", "sh"):
+        lim = (5e-5 if footprint == "affine" else 5e-4) * np.abs(a[k]) + 1e-7 * np.abs(a[k]).max()
+        assert (np.abs(a[k] - b[k]) <= lim).all(), k
+        moved = max(moved, np.abs(a[k] - b[k]).max())
+    assert moved > 0.0  # the float exponents do differ from the double ones somewhere
