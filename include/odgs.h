@@ -43,7 +43,8 @@ enum {
   ODGS_OK = 0,
   ODGS_EINVAL = -1,    /* invalid argument (null or misaligned pointer, size out of range) */
   ODGS_ENOSPACE = -2,  /* workspace smaller than odgs_workspace_bytes(plan) */
-  ODGS_EHIP = -3       /* a kernel launch failed */
+  ODGS_EHIP = -3,      /* a kernel launch failed */
+  ODGS_ETOOBIG = -4    /* input beyond the fixed scratch of a no-allocation entry point */
 };
 
 #define ODGS_MAX_VIEWS 64
@@ -284,6 +285,17 @@ size_t odgs_l1_loss_workspace_bytes(int64_t count);
  * odgs_render_bwd) and L into loss[0] (device float), summed in double in a fixed order. */
 int odgs_l1_loss(const float* rgb, const float* target, int64_t count, float* dL, float* loss, void* ws,
                  size_t ws_bytes, void* stream);
+
+/* odgs_l1_loss without a workspace, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * results (bit-identical), with the per-block partial sums in a fixed 512 KiB device array of the
+ * library (one per GPU, held until the process ends; its address is looked up on the first call
+ * on each device).  Calls nothing that allocates.  count <= ODGS_L1_NOALLOC_MAX_COUNT, else
+ * ODGS_ETOOBIG before anything is enqueued.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (different streams, or host threads) race and must be serialised by the
+ * caller.  `stream` must belong to the current device. */
+#define ODGS_L1_NOALLOC_MAX_COUNT (65536LL * 4096LL)
+int odgs_l1_loss_noalloc(const float* rgb, const float* target, int64_t count, float* dL, float* loss, void* stream);
 
 /* One Adam step (Kingma & Ba; PyTorch's placement of eps) over parameters kept before their
  * activations: raw scales are log-scales (scale = exp(raw)), raw opacities logits (opacity =

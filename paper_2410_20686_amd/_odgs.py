@@ -13,7 +13,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libodgs.so")
 
 MAX_VIEWS = 64
-OK, EINVAL, ENOSPACE, EHIP = 0, -1, -2, -3
+OK, EINVAL, ENOSPACE, EHIP, ETOOBIG = 0, -1, -2, -3, -4
+L1_NOALLOC_MAX_COUNT = 65536 * 4096
 STATUS_OVERFLOW = 1
 STATUS_STALE_FORWARD = 2
 FLAG_COUNT_WORK = 1
@@ -25,6 +26,7 @@ SCHEDULES = {"persistent": 0, "grid": FLAG_SCHED_GRID, "tile_id": FLAG_SCHED_TIL
 EXPORTS = ("odgs_plan_init", "odgs_plan_set_pinhole", "odgs_workspace_bytes", "odgs_preprocess", "odgs_bin_sort", "odgs_render_fwd",
            "odgs_render_bwd", "odgs_composite_bwd", "odgs_project_bwd", "odgs_status_offset", "odgs_strerror",
            "odgs_densify", "odgs_densify_workspace_bytes", "odgs_l1_loss", "odgs_l1_loss_workspace_bytes",
+           "odgs_l1_loss_noalloc",
            "odgs_adam_step",
            "odgs_plan_size", "odgs_debug_records", "odgs_debug_keys", "odgs_debug_pixel_counts", "odgs_debug_g2d")
 
@@ -120,6 +122,8 @@ def lib():
         L.odgs_l1_loss_workspace_bytes.restype = c_sz
         L.odgs_l1_loss.argtypes = [P, P, c_i64, P, P, P, c_sz, P]
         L.odgs_l1_loss.restype = c_i32
+        L.odgs_l1_loss_noalloc.argtypes = [P, P, c_i64, P, P, P]
+        L.odgs_l1_loss_noalloc.restype = c_i32
         pptr = ctypes.POINTER(ParamPtrs)
         L.odgs_adam_step.argtypes = [c_i64, c_i32, pptr, pptr, pptr, pptr, pptr, P, P, ctypes.POINTER(AdamHyper), P]
         L.odgs_adam_step.restype = c_i32
@@ -232,6 +236,10 @@ def odgs_l1_loss_workspace_bytes(count: int) -> int:
 
 def odgs_l1_loss(rgb, target, count, dL, loss, ws, ws_bytes, stream):
     _check(lib().odgs_l1_loss(rgb, target, int(count), dL, loss, ws, ws_bytes, stream), "odgs_l1_loss")
+
+
+def odgs_l1_loss_noalloc(rgb, target, count, dL, loss, stream):
+    _check(lib().odgs_l1_loss_noalloc(rgb, target, int(count), dL, loss, stream), "odgs_l1_loss_noalloc")
 
 
 def odgs_adam_step(n, sh_degree, raw: ParamPtrs, act: ParamPtrs, grad: ParamPtrs, m: ParamPtrs, v: ParamPtrs, lr, step,

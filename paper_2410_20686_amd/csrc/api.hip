@@ -227,6 +227,14 @@ int odgs_l1_loss(const float* rgb, const float* target, int64_t count, float* dL
   return hip_status(launch_l1(rgb, target, count, dL, loss, ws, static_cast<hipStream_t>(stream)));
 }
 
+int odgs_l1_loss_noalloc(const float* rgb, const float* target, int64_t count, float* dL, float* loss, void* stream) {
+  if (count < 0 || !loss || !aligned(loss, 4)) return ODGS_EINVAL;
+  if (count > 0 && (!rgb || !target || !dL || !aligned(rgb, 4) || !aligned(target, 4) || !aligned(dL, 4)))
+    return ODGS_EINVAL;
+  if (count > l1_noalloc_max_count()) return ODGS_ETOOBIG;
+  return hip_status(launch_l1_noalloc(rgb, target, count, dL, loss, static_cast<hipStream_t>(stream)));
+}
+
 namespace {
 bool params_ok(const odgs_param_ptrs* p) {
   if (!p) return false;
@@ -300,6 +308,7 @@ const char* odgs_strerror(int code) {
     case ODGS_EINVAL: return "invalid argument";
     case ODGS_ENOSPACE: return "workspace too small";
     case ODGS_EHIP: return "HIP kernel launch failed";
+    case ODGS_ETOOBIG: return "input larger than the static scratch of a no-allocation entry point";
     default: return "unknown error";
   }
 }

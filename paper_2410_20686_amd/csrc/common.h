@@ -165,6 +165,9 @@ size_t densify_workspace_bytes(int64_t n);
 size_t l1_workspace_bytes(int64_t count);
 hipError_t launch_l1(const float* rgb, const float* tgt, int64_t count, float* dL, float* loss, void* ws,
                      hipStream_t st);
+int64_t l1_noalloc_max_count();
+hipError_t launch_l1_noalloc(const float* rgb, const float* tgt, int64_t count, float* dL, float* loss,
+                             hipStream_t st);
 hipError_t launch_adam_step(int64_t n, int32_t sh_degree, const odgs_param_ptrs& raw, const odgs_param_ptrs& act,
                             const odgs_param_ptrs& grad, const odgs_param_ptrs& m, const odgs_param_ptrs& v,
                             const float* lr, int32_t* step, const odgs_adam_hyper& hp, hipStream_t st);

@@ -2,9 +2,20 @@
 // of the Gaussian parameters kept before their activations (the 3DGS recipe the paper trains
 // with, per its implementation details: scale = exp(raw), opacity = sigmoid(raw), quaternions
 // normalised inside the rasterizer).  Both are streaming passes bound by HBM bandwidth.
+#include <mutex>
+
 #include "common.h"
 
 namespace odgs {
+
+// Scratch of odgs_l1_loss_noalloc: the per-block partial sums of l1_kernel, kept in a file-scope
+// device array so that entry point allocates nothing.  Every GPU the library runs on holds its own
+// copy at its own address until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: kernels get the address hipGetSymbolAddress returns for the current
+// device (l1_scratch_ptr), never the array's name.
+constexpr int kL1ScratchBlocks = 65536;  // 512 KiB of doubles
+static __device__ __align__(256) double scratch[kL1ScratchBlocks];
+
 namespace {
 
 constexpr int kL1Threads = 256;
@@ -100,7 +111,31 @@ void launch_adam(float* raw, float* act, const float* grad, float* m, float* v, 
                      v, count, split, lr, g0, g1, step, a);
 }
 
+// Device address of `scratch` on the current device, looked up once per device (with that device
+// current) on its first use and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t l1_scratch_ptr(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
+
+int64_t l1_noalloc_max_count() { return (int64_t)kL1ScratchBlocks * kL1Block; }
 
 size_t l1_workspace_bytes(int64_t count) {
   return (((size_t)l1_blocks(count) * sizeof(double) + 255) / 256) * 256 + 256;
@@ -116,6 +151,17 @@ hipError_t launch_l1(const float* rgb, const float* tgt, int64_t count, float* d
   hipLaunchKernelGGL(l1_final_kernel, dim3(1), dim3(256), 0, st, partial, nb,
                      count > 0 ? 1.0 / (double)count : 0.0, loss);
   return hipGetLastError();
+}
+
+hipError_t launch_l1_noalloc(const float* rgb, const float* tgt, int64_t count, float* dL, float* loss,
+                             hipStream_t st) {
+  if (count > l1_noalloc_max_count()) return hipErrorInvalidValue;
+  double* partial = nullptr;
+  const hipError_t e = l1_scratch_ptr(&partial);
+  if (e != hipSuccess) return e;
+  // every block of l1_kernel writes its partial and l1_final_kernel reads exactly those, so the
+  // array needs no clearing between calls
+  return launch_l1(rgb, tgt, count, dL, loss, partial, st);
 }
 
 hipError_t launch_adam_step(int64_t n, int32_t sh_degree, const odgs_param_ptrs& raw, const odgs_param_ptrs& act,

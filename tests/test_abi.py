@@ -131,3 +131,13 @@ def test_densify_validates_on_host(lib):
     assert call(outs=[fake] * 6 + [ctypes.c_void_p(256 * 1024 + 4), fake]) == B.EINVAL  # misaligned counts
     assert call(dp=B.DensifyParams(float("nan"), 1e-3, 0.005, 0.0)) == B.EINVAL
     assert call(dp=B.DensifyParams(10.0, 1e-3, 0.005, -1.0)) == B.EINVAL
+
+
+def test_noalloc_l1_rejects_sizes_beyond_its_scratch(lib):
+    """Checked on the host before anything is enqueued (no device memory is touched)."""
+    fake = 1 << 20  # 256-aligned stand-ins: never dereferenced on these paths
+    rc = lib.odgs_l1_loss_noalloc(fake, fake, B.L1_NOALLOC_MAX_COUNT + 1, fake, fake, None)
+    assert rc == B.ETOOBIG
+    assert b"scratch" in lib.odgs_strerror(rc)
+    assert lib.odgs_l1_loss_noalloc(fake, fake, -1, fake, fake, None) == B.EINVAL
+    assert lib.odgs_l1_loss_noalloc(fake, fake, 10, fake, None, None) == B.EINVAL
