@@ -75,9 +75,10 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="Gaussian count (0: the workload's own)")
     ap.add_argument("--workload", default="M", choices=("M", "cfg0", "cfg1", "cfg2", "cfg3", "cfg4"),
                     help="M is the metric's workload; the others are context runs (same JSON fields)")
-    ap.add_argument("--schedule", default="persistent", choices=("persistent", "grid", "tile_id"),
-                    help="compositor tile scheduling: persistent longest-first queue (default), one workgroup "
-                         "per tile in queue order, or one workgroup per tile in tile id order")
+    ap.add_argument("--schedule", default="queue", choices=("queue", "persistent", "tile_id"),
+                    help="compositor tile scheduling: one workgroup per tile, longest list first (default), "
+                         "persistent workgroups claiming tiles from that queue, or one workgroup per tile in "
+                         "tile id order")
     ap.add_argument("--autotune", action="store_true", help="pick the tile and batch sizes with the autotuner first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a known-size reference "

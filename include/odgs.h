@@ -59,11 +59,12 @@ enum {
                                   ODGS_FLAG_COUNT_WORK, no densification statistics) */
 /* Scheduling of the two compositing launches, which cover the tiles of every view.  odgs_bin_sort
  * ends by queueing all (view, tile) pairs by descending list length (its compositing cost).
- * Default: persistent launches, as many workgroups as fit on the device, each claiming the next
- * queue entry when it finishes a tile, so the longest tiles of all views start first and the
- * short ones fill the tail.  The two flags below select the alternatives (measurement): */
-#define ODGS_FLAG_SCHED_GRID 4    /* one workgroup per tile, taking the queue in order */
-#define ODGS_FLAG_SCHED_TILE_ID 8 /* one workgroup per tile in global tile id order (no queue) */
+ * Default: one workgroup per tile, workgroup b taking queue entry b, so the longest tiles of all
+ * views are dispatched first and the short ones fill the tail (the hardware dispatcher starts
+ * workgroups in id order as slots free up).  The two flags below select the alternatives: */
+#define ODGS_FLAG_SCHED_PERSISTENT 4 /* persistent launches: as many workgroups as fit on the device,
+                                        each claiming the next queue entry when it finishes a tile */
+#define ODGS_FLAG_SCHED_TILE_ID 8    /* one workgroup per tile in global tile id order (no queue) */
 
 /* Spherical footprint (ODGS_FLAG_SPHERICAL).  The paper names its local affine approximation
  * of the projected Gaussian as its limitation (Sec. 5).  With this flag every pixel ray t d
@@ -189,7 +190,7 @@ size_t odgs_workspace_bytes(const odgs_plan* plan /*[host]*/);
  * 3D covariance R S S^T R^T (Sec. 3.1), tangent-plane Jacobian J_omni (Eq. omni_Jacobian),
  * 2D covariance J_omni W Sigma W^T J_omni^T plus dilation, its inverse, SH colour, radial
  * depth, and the footprint's tile rectangle.  Binning decisions are taken in FP64.
- * Resets the status record. */
+ * Resets the status record and clears the per-item 2D-gradient accumulators of odgs_composite_bwd. */
 int odgs_preprocess(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
                     const float* opacities, const float* sh, const float* cams, void* ws, size_t ws_bytes,
                     void* stream);
@@ -226,14 +227,15 @@ int odgs_render_bwd(const odgs_plan* plan, const float* means, const float* scal
 /* First backward stage: reverse compositing of every pixel of every view (Eq. alphablending
  * differentiated), accumulating per-(Gaussian, view) gradients of the ERP position, the 2D
  * covariance Sigma_2D (dilation included), the opacity and the colour into the workspace (which
- * odgs_bin_sort and odgs_project_bwd leave cleared).  dL_drgb has the layout of out_rgb.
+ * odgs_preprocess leaves cleared).  dL_drgb has the layout of out_rgb.
  * Requires odgs_render_fwd on this workspace after its last odgs_bin_sort (the compositing state
  * it reads is the forward's). */
 int odgs_composite_bwd(const odgs_plan* plan, void* ws, size_t ws_bytes, const float* dL_drgb, void* stream);
 
 /* Second backward stage: adjoint of the per-(Gaussian, view) projection (Eq. omni_Jacobian and
  * its derivative, Sigma = R S S^T R^T with the quaternion normalisation, SH colour), summed over
- * views into the five gradient arrays (OVERWRITTEN); clears the workspace's 2D gradients.
+ * views into the five gradient arrays (OVERWRITTEN); the workspace's 2D gradients stay as they
+ * are (odgs_debug_g2d can read them) until the next odgs_preprocess clears them.
  * acc [host] (may be NULL): densification statistics to accumulate, see odgs_densify_acc. */
 int odgs_project_bwd(const odgs_plan* plan, const float* means, const float* scales, const float* quats,
                      const float* opacities, const float* sh, const float* cams, void* ws, size_t ws_bytes,

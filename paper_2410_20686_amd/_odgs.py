@@ -19,9 +19,9 @@ STATUS_OVERFLOW = 1
 STATUS_STALE_FORWARD = 2
 FLAG_COUNT_WORK = 1
 FLAG_SPHERICAL = 2
-FLAG_SCHED_GRID = 4
+FLAG_SCHED_PERSISTENT = 4
 FLAG_SCHED_TILE_ID = 8
-SCHEDULES = {"persistent": 0, "grid": FLAG_SCHED_GRID, "tile_id": FLAG_SCHED_TILE_ID}
+SCHEDULES = {"queue": 0, "persistent": FLAG_SCHED_PERSISTENT, "tile_id": FLAG_SCHED_TILE_ID}
 
 EXPORTS = ("odgs_plan_init", "odgs_plan_set_pinhole", "odgs_workspace_bytes", "odgs_preprocess", "odgs_bin_sort", "odgs_render_fwd",
            "odgs_render_bwd", "odgs_composite_bwd", "odgs_project_bwd", "odgs_status_offset", "odgs_strerror",
@@ -154,11 +154,12 @@ def _check(rc: int, what: str):
 
 
 def make_settings(tile=16, batch=0, batch_bwd=0, near=0.2, far=1e4, dilation=0.3, pole_eps=1e-4,
-                  bg=(0.0, 0.0, 0.0), count_work=False, footprint="affine", schedule="persistent") -> Settings:
+                  bg=(0.0, 0.0, 0.0), count_work=False, footprint="affine", schedule="queue") -> Settings:
     """footprint: "affine" (the paper's local affine approximation) or "spherical"
     (ODGS_FLAG_SPHERICAL: the exact per-ray maximum of each 3D Gaussian).  schedule: the
-    compositors' tile scheduling, "persistent" (longest-first queue), "grid" (one workgroup per
-    tile in queue order) or "tile_id" (one workgroup per tile in tile id order)."""
+    compositors' tile scheduling, "queue" (one workgroup per tile, longest list first),
+    "persistent" (device-filling workgroups claiming tiles from that queue) or "tile_id" (one
+    workgroup per tile in tile id order)."""
     if footprint not in ("affine", "spherical"):
         raise ValueError("footprint must be 'affine' or 'spherical'")
     if schedule not in SCHEDULES:

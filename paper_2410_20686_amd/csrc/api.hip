@@ -68,9 +68,9 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   if (st.batch == 0) st.batch = st.tile == 8 ? 64 : 256;
   if (st.batch_bwd == 0) st.batch_bwd = st.tile == 8 ? 32 : (st.tile == 16 ? 64 : 256);
   if (!batch_ok(st.tile, st.batch) || !batch_ok(st.tile, st.batch_bwd)) return ODGS_EINVAL;
-  if (st.flags & ~(ODGS_FLAG_COUNT_WORK | ODGS_FLAG_SPHERICAL | ODGS_FLAG_SCHED_GRID | ODGS_FLAG_SCHED_TILE_ID))
+  if (st.flags & ~(ODGS_FLAG_COUNT_WORK | ODGS_FLAG_SPHERICAL | ODGS_FLAG_SCHED_PERSISTENT | ODGS_FLAG_SCHED_TILE_ID))
     return ODGS_EINVAL;
-  if ((st.flags & ODGS_FLAG_SCHED_GRID) && (st.flags & ODGS_FLAG_SCHED_TILE_ID)) return ODGS_EINVAL;
+  if ((st.flags & ODGS_FLAG_SCHED_PERSISTENT) && (st.flags & ODGS_FLAG_SCHED_TILE_ID)) return ODGS_EINVAL;
   if ((st.flags & ODGS_FLAG_COUNT_WORK) && (st.flags & ODGS_FLAG_SPHERICAL)) return ODGS_EINVAL;
   if (!(st.near_r >= 0.0f) || !(st.far_r > st.near_r) || !(st.dilation >= 0.0f) || !(st.pole_eps >= 0.0f))
     return ODGS_EINVAL;
@@ -129,7 +129,9 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   plan->off_pval[0] = take((size_t)pair_capacity * 4);
   plan->off_pval[1] = take((size_t)pair_capacity * 4);
   const int64_t hb = plan->item_blocks > plan->pair_blocks ? plan->item_blocks : plan->pair_blocks;
-  plan->off_hist = take((size_t)256 * hb * 4);
+  // radix histograms; after the pair sort also the tile queue's per-(block, bucket) counts
+  const int64_t qwords = (tiles + 4095) / 4096 * 1024;
+  plan->off_hist = take((size_t)(256 * hb > qwords ? 256 * hb : qwords) * 4);
   plan->off_digit = take(256 * 4);
   plan->off_ranges = take((size_t)tiles * 8);
   plan->off_T = take((size_t)pixels * 4);

@@ -489,7 +489,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
                                                          Rec* __restrict__ rec, Rect* __restrict__ rect,
                                                          uint32_t* __restrict__ count, uint32_t* __restrict__ dkey,
                                                          float* __restrict__ depth_out, odgs_status* __restrict__ status,
-                                                         SphRec* __restrict__ srec, SphCull* __restrict__ cone) {
+                                                         SphRec* __restrict__ srec, SphCull* __restrict__ cone,
+                                                         double* __restrict__ g2d, int g2d_stride) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < n;
   const int64_t ii = live ? i : 0;
@@ -618,6 +619,17 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
     }
     visible += kept ? 1 : 0;
     culled += (live && !kept) ? 1 : 0;
+  }
+  // The reverse compositor adds into the per-item 2D-gradient records: clear this block's records
+  // of every view here (contiguous per view, coalesced), where the HBM traffic overlaps the FP64
+  // arithmetic above instead of taking a pass of its own.
+  {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t words = (n - i0 < (int64_t)blockDim.x ? n - i0 : (int64_t)blockDim.x) * g2d_stride;
+    for (int v = 0; v < vt.n_views; ++v) {
+      double* base = g2d + ((int64_t)v * n + i0) * g2d_stride;
+      for (int64_t w = threadIdx.x; w < words; w += blockDim.x) base[w] = 0.0;
+    }
   }
   // one atomic per wave for each counter
   unsigned long long tot = visible, tcul = culled, tnf = (live && !fin) ? 1 : 0;
@@ -811,9 +823,6 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
       ++st_count;
     }
     if (!any) continue;
-    // consumed: leave the accumulators cleared for the next reverse compositing pass
-#pragma unroll
-    for (int k = 0; k < 9; ++k) g2d[item * 9 + k] = 0.0;
     Cam cam;
     load_cam(cams, v, cam);
     Geo G;
@@ -899,8 +908,7 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
 // off-diagonals as one shared variable), opacity, r, g, b.  With Sigma~ = W Sigma W^T / r^2 +
 // delta I, mu^ = mu / r and r = |mu|:  dL/d(W Sigma W^T) = dL/dSigma~ / r^2,
 // dL/dr = -2 <dL/dSigma~, W Sigma W^T> / r^3,  dL/dmu = (I - mu^ mu^^T) dL/dmu^ / r + mu^ dL/dr;
-// colour as in the affine adjoint.  Sums over views, overwrites the parameter gradients, clears
-// the consumed g2d entries.
+// colour as in the affine adjoint.  Sums over views, overwrites the parameter gradients.
 template <int K>
 __global__ __launch_bounds__(256) void preprocess_sph_bwd_kernel(
     int64_t n, const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
@@ -933,8 +941,6 @@ __global__ __launch_bounds__(256) void preprocess_sph_bwd_kernel(
       any = any || g[k] != 0.0;
     }
     if (!any) continue;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) g2d[item * NV + k] = 0.0;
     Cam cam;
     load_cam(cams, v, cam);
     Geo G;
@@ -999,6 +1005,7 @@ hipError_t launch_preprocess(const odgs_plan* p, const float* means, const float
   uint32_t* dkey = ws_ptr<uint32_t>(ws, p->off_dkey[0]);
   float* depth = ws_ptr<float>(ws, p->off_depth);
   odgs_status* status = ws_ptr<odgs_status>(ws, p->off_status);
+  double* g2d = ws_ptr<double>(ws, p->off_g2d);
   SphRec* srec = nullptr;
   SphCull* cone = nullptr;
   if (plan_spherical(p)) {
@@ -1011,10 +1018,10 @@ hipError_t launch_preprocess(const odgs_plan* p, const float* means, const float
 #define ODGS_PRE(KK)                                                                                              \
   if (srec)                                                                                                       \
     hipLaunchKernelGGL((preprocess_kernel<KK, true>), dim3(grid), dim3(256), 0, st, p->n, means, scales, quats,     \
-                       opac, sh, cams, vt, P, rec, rect, count, dkey, depth, status, srec, cone);                 \
+                       opac, sh, cams, vt, P, rec, rect, count, dkey, depth, status, srec, cone, g2d, p->g2d_stride);  \
   else                                                                                                            \
     hipLaunchKernelGGL((preprocess_kernel<KK, false>), dim3(grid), dim3(256), 0, st, p->n, means, scales, quats,    \
-                       opac, sh, cams, vt, P, rec, rect, count, dkey, depth, status, srec, cone)
+                       opac, sh, cams, vt, P, rec, rect, count, dkey, depth, status, srec, cone, g2d, p->g2d_stride)
   switch (p->sh_degree) {
     case 0: ODGS_PRE(1); break;
     case 1: ODGS_PRE(4); break;
@@ -1038,7 +1045,7 @@ hipError_t launch_preprocess_bwd(const odgs_plan* p, const float* means, const f
   const uint32_t* count = ws_ptr<uint32_t>(ws, p->off_count);
   double* g2d = ws_ptr<double>(ws, p->off_g2d);
   // colour part first (writes d_sh and the colour path of d_means), then the geometry part,
-  // which adds to d_means and clears the consumed records
+  // which adds to d_means
   const int stride = p->g2d_stride, off = p->g2d_stride - 3;
 #define ODGS_COLB(KK)                                                                                              \
   hipLaunchKernelGGL(colour_bwd_kernel<KK>, dim3(grid), dim3(256), 0, st, p->n, means, sh, cams, vt, count, g2d,   \

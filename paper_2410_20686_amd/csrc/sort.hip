@@ -454,42 +454,77 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* __restrict_
 
 // Work queue of the compositors: every global tile id, in descending order of its list length
 // (the tile's compositing cost), bucketed on a logarithmic scale with 32 buckets per octave (the
-// order inside a bucket is arbitrary); one workgroup.  Also clears the persistent launches'
-// counters.
-constexpr int kQueueThreads = 1024;
+// order inside a bucket is arbitrary).  Three small launches: per-block bucket counts, one scan
+// that turns them into per-(block, bucket) starts, and the scatter.
+constexpr int kQueueBuckets = 1024;
+constexpr int kQueueTiles = 4096;  // tiles per block of the count and scatter kernels (16 per thread)
 
 __device__ inline uint32_t cost_bucket(uint32_t len) {
   // 0 for an empty list, else 1 + 32 log2(len) (exponent and top five mantissa bits; <= 993)
   return len == 0 ? 0u : 1u + ((__float_as_uint((float)len) - 0x3f800000u) >> 18);
 }
 
-__global__ __launch_bounds__(kQueueThreads) void tile_queue_kernel(const uint2* __restrict__ ranges, int tiles,
-                                                                  uint32_t* __restrict__ ctr,
-                                                                  uint32_t* __restrict__ order) {
-  __shared__ uint32_t start[kQueueThreads];  // one bucket per thread
-  __shared__ uint32_t wsum[kQueueThreads / kWave];
-  const int t = threadIdx.x, lane = t & (kWave - 1), w = t >> 6;
-  start[t] = 0;
-  if (t < 4) ctr[t] = 0u;
+// bstart[block][bucket] = number of the block's tiles in the bucket (every entry written).
+__global__ __launch_bounds__(256) void queue_count_kernel(const uint2* __restrict__ ranges, int tiles,
+                                                          uint32_t* __restrict__ bstart) {
+  __shared__ uint32_t h[kQueueBuckets];
+  for (int b = threadIdx.x; b < kQueueBuckets; b += 256) h[b] = 0;
   __syncthreads();
-  for (int i = t; i < tiles; i += kQueueThreads) {
-    const uint2 r = ranges[i];
-    atomicAdd(&start[cost_bucket(r.y - r.x)], 1u);
+  for (int k = 0; k < kQueueTiles / 256; ++k) {
+    const int i = blockIdx.x * kQueueTiles + k * 256 + threadIdx.x;
+    if (i < tiles) {
+      const uint2 r = ranges[i];
+      atomicAdd(&h[cost_bucket(r.y - r.x)], 1u);
+    }
   }
   __syncthreads();
-  // descending: thread t takes bucket kQueueThreads - 1 - t; exclusive scan over t
-  const uint32_t c = start[kQueueThreads - 1 - t];
+  for (int b = threadIdx.x; b < kQueueBuckets; b += 256) bstart[(size_t)blockIdx.x * kQueueBuckets + b] = h[b];
+}
+
+// Buckets in descending order, blocks in order: the counts become each (block, bucket)'s first
+// queue position.  One workgroup; also clears the persistent launches' counters.
+__global__ __launch_bounds__(kQueueBuckets) void queue_scan_kernel(uint32_t* __restrict__ bstart, int nblocks,
+                                                                   uint32_t* __restrict__ ctr) {
+  __shared__ uint32_t wsum[kQueueBuckets / kWave];
+  const int t = threadIdx.x, lane = t & (kWave - 1), w = t >> 6;
+  const int bucket = kQueueBuckets - 1 - t;
+  if (t < 4) ctr[t] = 0u;
+  uint32_t c = 0;
+  for (int b = 0; b < nblocks; ++b) c += bstart[(size_t)b * kQueueBuckets + bucket];
   const uint32_t incl = wave_incl_scan(c);
   if (lane == kWave - 1) wsum[w] = incl;
   __syncthreads();
-  uint32_t pre = 0;
-  for (int k = 0; k < w; ++k) pre += wsum[k];
-  start[kQueueThreads - 1 - t] = pre + incl - c;
-  __syncthreads();
-  for (int i = t; i < tiles; i += kQueueThreads) {
-    const uint2 r = ranges[i];
-    order[atomicAdd(&start[cost_bucket(r.y - r.x)], 1u)] = (uint32_t)i;
+  uint32_t run = incl - c;
+  for (int k = 0; k < w; ++k) run += wsum[k];
+  for (int b = 0; b < nblocks; ++b) {
+    uint32_t* e = bstart + (size_t)b * kQueueBuckets + bucket;
+    const uint32_t x = *e;
+    *e = run;
+    run += x;
   }
+}
+
+__global__ __launch_bounds__(256) void queue_scatter_kernel(const uint2* __restrict__ ranges, int tiles,
+                                                            const uint32_t* __restrict__ bstart,
+                                                            uint32_t* __restrict__ order) {
+  __shared__ uint32_t cur[kQueueBuckets];
+  for (int b = threadIdx.x; b < kQueueBuckets; b += 256) cur[b] = bstart[(size_t)blockIdx.x * kQueueBuckets + b];
+  __syncthreads();
+  for (int k = 0; k < kQueueTiles / 256; ++k) {
+    const int i = blockIdx.x * kQueueTiles + k * 256 + threadIdx.x;
+    if (i < tiles) {
+      const uint2 r = ranges[i];
+      order[atomicAdd(&cur[cost_bucket(r.y - r.x)], 1u)] = (uint32_t)i;
+    }
+  }
+}
+
+hipError_t launch_tile_queue(const uint2* ranges, int tiles, uint32_t* bstart, uint32_t* queue, hipStream_t st) {
+  const int nb = (tiles + kQueueTiles - 1) / kQueueTiles;
+  if (nb > 0) hipLaunchKernelGGL(queue_count_kernel, dim3(nb), dim3(256), 0, st, ranges, tiles, bstart);
+  hipLaunchKernelGGL(queue_scan_kernel, dim3(1), dim3(kQueueBuckets), 0, st, bstart, nb, queue);
+  if (nb > 0) hipLaunchKernelGGL(queue_scatter_kernel, dim3(nb), dim3(256), 0, st, ranges, tiles, bstart, queue + 16);
+  return hipGetLastError();
 }
 
 __global__ void status_reset_kernel(odgs_status* st) {
@@ -537,7 +572,7 @@ TileSched make_sched(const odgs_plan* p, void* ws, int which) {
   s.status = ws_ptr<odgs_status>(ws, p->off_status);
   s.tiles = p->tile_base[p->n_views];
   s.order = (p->s.flags & ODGS_FLAG_SCHED_TILE_ID) ? nullptr : q + 16;  // after 64 bytes of counters
-  s.ctr = (p->s.flags & (ODGS_FLAG_SCHED_GRID | ODGS_FLAG_SCHED_TILE_ID)) ? nullptr : q + 2 * which;
+  s.ctr = (p->s.flags & ODGS_FLAG_SCHED_PERSISTENT) ? q + 2 * which : nullptr;
   return s;
 }
 
@@ -564,15 +599,9 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
   uint2* ranges = ws_ptr<uint2>(ws, p->off_ranges);
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * (int64_t)p->tile_base[p->n_views], st);
   if (e != hipSuccess) return e;
-  // the backward's 2D gradient accumulators start cleared
-  e = launch_fill_u32(ws_ptr<uint32_t>(ws, p->off_g2d), 0u, 2 * (int64_t)p->g2d_stride * p->items, st);  // doubles
-  if (e != hipSuccess) return e;
   const int tiles = p->tile_base[p->n_views];
   uint32_t* queue = ws_ptr<uint32_t>(ws, p->off_queue);
-  if (items == 0) {
-    hipLaunchKernelGGL(tile_queue_kernel, dim3(1), dim3(kQueueThreads), 0, st, ranges, tiles, queue, queue + 16);
-    return hipGetLastError();
-  }
+  if (items == 0) return launch_tile_queue(ranges, tiles, hist, queue, st);
   // 1. items by radial depth (culled items carry the largest key)
   uint32_t* dk[2] = {ws_ptr<uint32_t>(ws, p->off_dkey[0]), ws_ptr<uint32_t>(ws, p->off_dkey[1])};
   uint32_t* di[2] = {ws_ptr<uint32_t>(ws, p->off_did[0]), ws_ptr<uint32_t>(ws, p->off_did[1])};
@@ -605,9 +634,8 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
   // 5. tile ranges
   hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((p->pair_capacity + 256 * kRangeKeys - 1) / (256 * kRangeKeys))),
                      dim3(256), 0, st, pk[p->pair_final], status, ranges);
-  // 6. the compositors' work queue, longest list first
-  hipLaunchKernelGGL(tile_queue_kernel, dim3(1), dim3(kQueueThreads), 0, st, ranges, tiles, queue, queue + 16);
-  return hipGetLastError();
+  // 6. the compositors' work queue, longest list first (its scratch: the free radix histograms)
+  return launch_tile_queue(ranges, tiles, hist, queue, st);
 }
 
 }  // namespace odgs

@@ -1,7 +1,7 @@
 """Compositor scheduling and the device status record, through the C ABI.
 
-* The three tile schedules (persistent longest-first queue, one workgroup per tile in queue order,
-  one workgroup per tile in tile id order) composite the same tiles, so images are bit-identical
+* The three tile schedules (one workgroup per tile in longest-first queue order, persistent
+  workgroups claiming tiles from that queue, one workgroup per tile in tile id order) composite the same tiles, so images are bit-identical
   and gradients agree to the order in which per-tile partial sums reach the FP64 accumulators.
 * The work queue is a permutation of the global tile ids in non-increasing list length.
 * The reverse compositor refuses a pair list the forward has not composited (a bin_sort between
@@ -33,23 +33,23 @@ def test_schedules_agree(tile, footprint):
     st = settings(tile=tile, footprint=footprint)
     fwd = O.render(sc, cams, st, mode=32)
     dL = _masked_upstream(cams, fwd["margin"], seed=1081)
-    runs = {s: G.run_gpu(sc, cams, dict(st, schedule=s), dL=dL) for s in ("persistent", "grid", "tile_id")}
+    runs = {s: G.run_gpu(sc, cams, dict(st, schedule=s), dL=dL) for s in ("queue", "persistent", "tile_id")}
     base = runs["tile_id"]
-    for s in ("persistent", "grid"):
+    for s in ("queue", "persistent"):
         np.testing.assert_array_equal(runs[s]["rgb"], base["rgb"])
         np.testing.assert_array_equal(runs[s]["T"], base["T"])
         G.assert_grads_close(runs[s]["grads"], base["grads"], rtol=1e-6, floor=1e-9)
     # and the default schedule against the oracle
     ok = G.strict_pixels(fwd["margin"])
-    assert np.abs(runs["persistent"]["T"] - fwd["T"])[ok].max() <= G.RGB_ATOL
+    assert np.abs(runs["queue"]["T"] - fwd["T"])[ok].max() <= G.RGB_ATOL
     ref = O.backward(sc, cams, st, dL, mode=32)
-    G.assert_grads_close(runs["persistent"]["grads"], ref)
+    G.assert_grads_close(runs["queue"]["grads"], ref)
 
 
 def test_queue_is_longest_first_permutation():
     import torch
     sc, cams = _uneven_case()
-    res = G.run_gpu(sc, cams, settings(), return_rast=True)
+    res = G.run_gpu(sc, cams, settings(schedule="persistent"), return_rast=True)
     rast = res["rast"]
     p = rast.plan
     tiles = int(p.tile_base[cams.n_views])
