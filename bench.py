@@ -287,13 +287,19 @@ def main():
                                                             rast.plan.s.batch, "" if st["tile"] >= 32 else
                                                             ", false, false")
         prof = profiled(kname)
+        # the same algorithmic work over the committed profile's average duration of this kernel
+        ach_prof = alg_ops[dom] / (prof["avg_us"] * 1e-6) / 1e12 if prof else None
         roof = dict(bound="alu", kernel=dom, achieved=round(achieved, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Top/s",
                     frac=round(achieved / ALU_PEAK_TOPS, 4),
                     traffic=int(prof["traffic_bytes"]) if prof else None,
                     ops_per_launch=alg_ops[dom], duration_us=round(stages[dom] * 1e3, 1),
                     duration_us_profile=prof["avg_us"] if prof else None,
+                    achieved_profile=round(ach_prof, 3) if prof else None,
+                    frac_profile=round(ach_prof / ALU_PEAK_TOPS, 4) if prof else None,
                     hbm_frac_profile=prof["hbm_frac"] if prof else None,
-                    lds_frac_profile=prof["lds_frac"] if prof else None,
+                    lds_busy_profile=prof.get("lds_busy") if prof else None,
+                    lds_bw_frac_profile=prof.get("lds_bw_frac") if prof else None,
+                    lane_util_profile=prof.get("lanes") if prof else None,
                     valu_issue_profile=prof["valu_issue"] if prof else None,
                     work=dict(tests=evals_bwd if dom == "composite_bwd" else evals_fwd, accepts=contrib_total,
                               wave_iters=wave_iters[1] if dom == "composite_bwd" else wave_iters[0]))

@@ -130,9 +130,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
   constexpr int ROUNDS = PER_WAVE / kWave;
   __shared__ uint32_t s_key[kSortBlockItems];
   __shared__ uint32_t s_val[kSortBlockItems];
-  __shared__ uint32_t wh[NW][256];    // per-wavefront running digit counts, then their prefixes
-  __shared__ uint32_t lstart[256];    // local (block) start of each digit
-  __shared__ uint32_t gstart[256];    // global start of each digit for this block
+  __shared__ uint32_t wh[NW][256];    // per-wavefront running digit counts, then local placement starts
+  __shared__ uint32_t gshift[256];    // global start minus local start of each digit for this block
   __shared__ uint32_t lds[4];
   const int t = threadIdx.x, lane = t & (kWave - 1), wave = t >> 6;
   const uint32_t n = active_count(n_dev, n_host);
@@ -142,7 +141,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
   uint32_t total;
   const uint32_t dt = digit_tot[t];
   const uint32_t incl = block_incl_scan256(dt, lds, total);
-  gstart[t] = incl - dt + hist[t * nblocks + blockIdx.x];
+  const uint32_t gstart = incl - dt + hist[t * nblocks + blockIdx.x];  // global start of digit t
 #pragma unroll
   for (int w = 0; w < NW; ++w) wh[w][t] = 0;
   __syncthreads();
@@ -177,17 +176,25 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // per digit: exclusive prefix over the wavefronts, block totals, local digit starts
+  // per digit: block-local start (exclusive prefix over digits of the block totals) plus the
+  // wavefront's exclusive prefix, folded into one placement start per (wavefront, digit); and
+  // the digit's global-minus-local shift for the write-out (one LDS read per key in each phase)
   {
     uint32_t run = 0;
+    uint32_t c[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-      const uint32_t c = wh[w][t];
-      wh[w][t] = run;
-      run += c;
+      c[w] = wh[w][t];
+      run += c[w];
     }
     const uint32_t ci = block_incl_scan256(run, lds, total);
-    lstart[t] = ci - run;
+    uint32_t start = ci - run;  // local start of digit t
+    gshift[t] = gstart - start;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      wh[w][t] = start;
+      start += c[w];
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -195,7 +202,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t li = (uint32_t)(wave * PER_WAVE + r * kWave + lane);
     if (li < nb) {
       const uint32_t d = (key[r] >> shift) & 255u;
-      const uint32_t p = lstart[d] + wh[wave][d] + rank[r];
+      const uint32_t p = wh[wave][d] + rank[r];
       s_key[p] = key[r];
       s_val[p] = val[r];
     }
@@ -207,7 +214,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     if (i < nb) {
       const uint32_t k = s_key[i];
       const uint32_t d = (k >> shift) & 255u;
-      const uint32_t pos = gstart[d] + (i - lstart[d]);
+      const uint32_t pos = gshift[d] + i;  // unsigned wrap-around: global start + (i - local start)
       if (pos < n) {  // always true for a consistent histogram; keeps a corrupted one in bounds
         kout[pos] = k;
         vout[pos] = s_val[i];

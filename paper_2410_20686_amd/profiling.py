@@ -67,10 +67,14 @@ def counters(pmc_dir: str):
 
 
 def short(name: str) -> str:
+    """Kernel name without return type, anonymous namespace and argument list."""
+    name = name.replace("(anonymous namespace)::", "").strip()
+    if name.startswith("void "):
+        name = name[5:]
     return name.split("(")[0].strip()
 
 
-def summarize(trace_dir, pmc_dirs, calib_mib, out_path, cmd_trace, cmd_pmc, root, key_kernel):
+def summarize(trace_dir, pmc_dirs, calib_mib, out_path, cmd_trace, cmd_pmc, root, key_kernel, cmd_summary=""):
     stats = kernel_stats(trace_dir)
     pmc = defaultdict(dict)
     for d in pmc_dirs:
@@ -94,6 +98,10 @@ def summarize(trace_dir, pmc_dirs, calib_mib, out_path, cmd_trace, cmd_pmc, root
         thr_valu = mean(c.get("SQ_THREAD_CYCLES_VALU", []))
         lds_active = mean(c.get("SQ_LDS_IDX_ACTIVE", []))
         lds_conf = mean(c.get("SQ_LDS_BANK_CONFLICT", []))
+        # bytes moved by LDS instructions (64-byte units, active lanes only)
+        lds_units = sum(mean(c.get(k, [])) if c.get(k) else 0.0 for k in
+                        ("SQ_INSTS_LDS_LOAD_BANDWIDTH", "SQ_INSTS_LDS_STORE_BANDWIDTH", "SQ_INSTS_LDS_ATOMIC_BANDWIDTH"))
+        has_ldsbw = any(c.get(k) for k in ("SQ_INSTS_LDS_LOAD_BANDWIDTH", "SQ_INSTS_LDS_STORE_BANDWIDTH"))
         rows.append(dict(
             kernel=short(name), calls=calls, avg_us=avg_ns / 1e3, total_ms=calls * avg_ns / 1e6,
             traffic_gb=traffic / 1e9, hbm_gbs=traffic / dur / 1e9 if dur > 0 else float("nan"),
@@ -103,7 +111,8 @@ def summarize(trace_dir, pmc_dirs, calib_mib, out_path, cmd_trace, cmd_pmc, root
             valu_issue_frac=valu * 4 / (CUS * SIMDS_PER_CU * CLOCK) / dur if dur > 0 else float("nan"),
             lane_util=thr_valu / (act_valu * 64) if act_valu and act_valu == act_valu else float("nan"),
             lds_frac=lds_active / (CUS * CLOCK * dur) if dur > 0 else float("nan"),
-            lds_gbs=(lds_active - lds_conf) * LDS_BYTES_PER_CLK_CU / dur / 1e9 if dur > 0 else float("nan"),
+            lds_gbs=lds_units * 64 / dur / 1e9 if (dur > 0 and has_ldsbw) else float("nan"),
+            lds_bw_frac=lds_units * 64 / dur / LDS_PEAK if (dur > 0 and has_ldsbw) else float("nan"),
             lds_conflict=lds_conf / lds_active if lds_active else float("nan"),
             full=name))
     total_ms = sum(r["total_ms"] for r in rows)
@@ -113,6 +122,8 @@ def summarize(trace_dir, pmc_dirs, calib_mib, out_path, cmd_trace, cmd_pmc, root
     lines.append("# kernel trace:  " + cmd_trace)
     for c in cmd_pmc:
         lines.append("# counters:      " + c)
+    if cmd_summary:
+        lines.append("# summary:       " + cmd_summary)
     lines.append("#")
     lines.append("# peaks (MI355X): HBM 8 TB/s; VALU issue 1,024 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction;")
     lines.append("#   LDS %d B per clock per CU (32 banks x 4 B) x 256 CUs x 2.4 GHz = %.1f TB/s" %
@@ -120,24 +131,25 @@ def summarize(trace_dir, pmc_dirs, calib_mib, out_path, cmd_trace, cmd_pmc, root
     lines.append("# hbm_frac = calibrated (FETCH_SIZE + WRITE_SIZE) bytes / avg duration / 8 TB/s")
     lines.append("# valu_issue = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz) / avg duration")
     lines.append("# lane_util = SQ_THREAD_CYCLES_VALU / (64 x SQ_ACTIVE_INST_VALU): active lanes per VALU instruction")
-    lines.append("# lds_frac = SQ_LDS_IDX_ACTIVE / (256 CUs x 2.4 GHz x avg duration); lds_GB/s = (SQ_LDS_IDX_ACTIVE -")
-    lines.append("#   SQ_LDS_BANK_CONFLICT) x 128 B / avg duration; lds_conf = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE")
+    lines.append("# lds_busy = SQ_LDS_IDX_ACTIVE / (256 CUs x 2.4 GHz x avg duration): fraction of cycles the LDS is busy")
+    lines.append("# LDS_GB/s = 64 B x (SQ_INSTS_LDS_LOAD_BANDWIDTH + _STORE_ + _ATOMIC_BANDWIDTH) / avg duration: bytes the")
+    lines.append("#   LDS instructions moved (active lanes); lds_bw = that / LDS peak; ldscf = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE")
     lines.append("")
     lines.append("## HBM traffic calibration: one %d MiB device-to-device copy (%s)" % (calib_mib, COPY_KERNEL))
     lines.append("factor_fetch %.4f  factor_write %.4f  (bytes = counter KiB * 1024 * factor)" % (f_fetch, f_write))
     lines.append("")
     lines.append("## per kernel (averages per dispatch)")
-    hdr = ("%-44s %5s %9s %7s %8s %8s %6s %10s %6s %6s %6s %8s %6s" %
-           ("kernel", "calls", "avg_us", "pct", "traffic", "HBM_GB/s", "hbm", "VALU_inst", "valu", "lanes", "lds",
-            "LDS_GB/s", "ldscf"))
+    hdr = ("%-44s %5s %9s %7s %8s %8s %6s %10s %6s %6s %8s %8s %6s %6s" %
+           ("kernel", "calls", "avg_us", "pct", "traffic", "HBM_GB/s", "hbm", "VALU_inst", "valu", "lanes", "lds_busy",
+            "LDS_GB/s", "lds_bw", "ldscf"))
     lines.append(hdr)
     fmt = lambda x, f: ("%" + f) % x if x == x else "-"
     for r in rows:
-        lines.append("%-44s %5d %9.1f %6.1f%% %8s %8s %6s %10s %6s %6s %6s %8s %6s" % (
+        lines.append("%-44s %5d %9.1f %6.1f%% %8s %8s %6s %10s %6s %6s %8s %8s %6s %6s" % (
             r["kernel"][:44], r["calls"], r["avg_us"], 100 * r["total_ms"] / total_ms, fmt(r["traffic_gb"], ".4f"),
             fmt(r["hbm_gbs"], ".0f"), fmt(r["hbm_frac"], ".3f"), fmt(r["valu_insts"], ".3e"),
             fmt(r["valu_issue_frac"], ".3f"), fmt(r["lane_util"], ".3f"), fmt(r["lds_frac"], ".3f"),
-            fmt(r["lds_gbs"], ".0f"), fmt(r["lds_conflict"], ".3f")))
+            fmt(r["lds_gbs"], ".0f"), fmt(r["lds_bw_frac"], ".3f"), fmt(r["lds_conflict"], ".3f")))
     key = next((r for r in rows if r["kernel"] == key_kernel), None)
     lines.append("")
     lines.append("## machine-readable (read by bench.py)")
@@ -145,8 +157,9 @@ def summarize(trace_dir, pmc_dirs, calib_mib, out_path, cmd_trace, cmd_pmc, root
     for r in rows:
         if r["traffic_gb"] == r["traffic_gb"]:
             lines.append("kernel: %s | avg_us %.3f | traffic_bytes %.0f | hbm_frac %.4f | valu_issue %.4f | lanes %.4f"
-                         " | lds_frac %.4f" % (r["kernel"], r["avg_us"], r["traffic_gb"] * 1e9, r["hbm_frac"],
-                                               r["valu_issue_frac"], r["lane_util"], r["lds_frac"]))
+                         " | lds_busy %.4f | lds_gbs %.1f | lds_bw_frac %.4f" % (
+                             r["kernel"], r["avg_us"], r["traffic_gb"] * 1e9, r["hbm_frac"], r["valu_issue_frac"],
+                             r["lane_util"], r["lds_frac"], r["lds_gbs"], r["lds_bw_frac"]))
     if key is None:
         lines.append("# note: key kernel %s not found" % key_kernel)
     with open(out_path, "w") as f:
@@ -185,9 +198,10 @@ def main():
     ap.add_argument("--cmd-trace", default="")
     ap.add_argument("--cmd-pmc", action="append", default=[])
     ap.add_argument("--key-kernel", default="")
+    ap.add_argument("--cmd-summary", default="")
     a = ap.parse_args()
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    summarize(a.trace, a.pmc, a.calib_mib, a.out, a.cmd_trace, a.cmd_pmc, root, a.key_kernel)
+    summarize(a.trace, a.pmc, a.calib_mib, a.out, a.cmd_trace, a.cmd_pmc, root, a.key_kernel, a.cmd_summary)
 
 
 if __name__ == "__main__":
