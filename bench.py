@@ -88,7 +88,7 @@ def parse():
     ap.add_argument("--no-spherical", action="store_true",
                     help="skip timing the same step with the spherical (exact per-ray) footprint")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels-per-view", type=int, default=768)
+    ap.add_argument("--cpu-pixels-per-view", type=int, default=4096)
     return ap.parse_args()
 
 
@@ -314,13 +314,13 @@ def main():
         _, pix = scenes.sparse_upstream_gradient(cams, 2005, args.cpu_pixels_per_view)
         gpix = np.random.default_rng(3005).standard_normal((len(pix), 3))
         tc = time.time()
-        O.render(sc, cams, st, mode=32, pix=pix)
-        O.backward(sc, cams, st, gpix, mode=32, pix=pix)
+        O.render(sc, cams, st, mode=32, pix=pix, band=True)
+        O.backward(sc, cams, st, gpix, mode=32, pix=pix, band=True)
         dt = time.time() - tc
         cpu = dict(value=round(len(pix) / 1e6 / dt, 6), unit="MP/s", cores=O.num_threads(), kind="oracle",
-                   sample="%d random pixels (%d per view) of workload %s, brute-force forward + backward in FP32 "
-                          "decision mode, each call including its own per-Gaussian projection of all views; %.1f s"
-                          % (len(pix), args.cpu_pixels_per_view, args.workload, dt))
+                   sample="%d random pixels (%d per view) of workload %s, band-mode (tile-list candidates) forward "
+                          "+ backward in FP32 decision mode, each call including its own projection of all items and "
+                          "tile-list construction; %.1f s" % (len(pix), args.cpu_pixels_per_view, args.workload, dt))
         log("cpu baseline", cpu)
 
     value = mp_per_step / (ms_batched / 1e3)

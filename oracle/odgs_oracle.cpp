@@ -1517,12 +1517,17 @@ int oracle_backward(const double* means, const double* scales, const double* qua
                     const double* sh, int64_t n, int deg, const double* cams, const int32_t* wh, int V,
                     const double* settings, int mode, const int32_t* pix, int64_t npix, const double* dL,
                     double* d_means, double* d_scales, double* d_quats, double* d_opac, double* d_sh, double* g2d,
-                    double* g2d_kernel) {
+                    double* g2d_kernel, int band) {
   const bool decided = mode == 33;
   if (decided) mode = 32;
   Scene sc = make_scene(means, scales, quats, opac, sh, n, deg);
   Prepared P;
   prepare(sc, cams, wh, V, settings, P);
+  // band = 1: each pixel's candidates are its tile's key list instead of every kept Gaussian
+  // (identical contributor lists by construction, far less work)
+  Candidates cand;
+  if (band) build_band(P, cand);
+  const Candidates* cp = band ? &cand : nullptr;
   const int stride = P.st.spherical ? 13 : 9;
   std::vector<double> acc((size_t)V * n * stride, 0.0);
   std::vector<double> acck(P.st.spherical && g2d_kernel ? (size_t)V * n * 13 : 0, 0.0);
@@ -1537,8 +1542,8 @@ int oracle_backward(const double* means, const double* scales, const double* qua
       auto run = [&](int x, int y, const double* gpix) {
         if (gpix[0] == 0.0 && gpix[1] == 0.0 && gpix[2] == 0.0) return;
         std::vector<Contrib> cl;
-        if (mode == 32) render_pixel_sph<float, SphRec32>(P, s32, nullptr, v, x, y, &cl);
-        else render_pixel_sph<double, SphRec64>(P, s64, nullptr, v, x, y, &cl);
+        if (mode == 32) render_pixel_sph<float, SphRec32>(P, s32, cp, v, x, y, &cl);
+        else render_pixel_sph<double, SphRec64>(P, s64, cp, v, x, y, &cl);
         double d[3];
         pixel_dir(x, y, W, H, d);
         pixel_backward_sph(cl, s64, d, decided, gpix, P.st.bg, gv, stride, gk);
@@ -1578,8 +1583,8 @@ int oracle_backward(const double* means, const double* scales, const double* qua
     auto run = [&](int x, int y, const double* gpix) {
       if (gpix[0] == 0.0 && gpix[1] == 0.0 && gpix[2] == 0.0) return;
       std::vector<Contrib> cl;
-      if (mode == 32) render_pixel<float>(P, r32, nullptr, v, x, y, &cl);
-      else render_pixel<double>(P, r64, nullptr, v, x, y, &cl);
+      if (mode == 32) render_pixel<float>(P, r32, cp, v, x, y, &cl);
+      else render_pixel<double>(P, r64, cp, v, x, y, &cl);
       pixel_backward(cl, rvals, gpix, P.st.bg, gv, stride, decided);
     };
     if (pix == nullptr) {

@@ -58,7 +58,7 @@ def lib():
         L.oracle_keys.restype = i64
         L.oracle_render.argtypes = scene_args + [i32, i32, P, i64, P, P, P, P, P, P]
         L.oracle_render.restype = i32
-        L.oracle_backward.argtypes = scene_args + [i32, P, i64, P, P, P, P, P, P, P, P]
+        L.oracle_backward.argtypes = scene_args + [i32, P, i64, P, P, P, P, P, P, P, P, i32]
         L.oracle_backward.restype = i32
         L.oracle_project_adjoint.argtypes = scene_args + [P, P, P, P, P, P]
         L.oracle_project_adjoint.restype = i32
@@ -168,11 +168,14 @@ def spherical(settings) -> bool:
 
 
 def backward(scene, cams, settings, dL: np.ndarray, mode: int = 32, pix: np.ndarray | None = None,
-             want_g2d: bool = False):
+             want_g2d: bool = False, band: bool = False):
     """Gradient of sum(dL * rgb) w.r.t. every parameter (float64), and optionally the per-item
     gradients of the compositor's inputs: affine footprint g2d [V][N][9] (u, v, conic a, b, c,
     opacity, r, g, b); spherical footprint g2d [V][N][13] (mu^, A, opacity, rgb) and g2d_kernel
-    [V][N][13] (mu^, Sigma~, opacity, rgb; the reverse compositor's layout)."""
+    [V][N][13] (mu^, Sigma~, opacity, rgb; the reverse compositor's layout).  mode 32 or 64 as
+    in render; mode 33: mode 32's contributors with each alpha taken at the float pass's own
+    exponent.  band: candidates from the tile lists instead of every kept Gaussian (the same
+    contributor lists, much faster)."""
     a = _Args(scene, cams, settings)
     n, K = a.n, (a.deg + 1) ** 2
     gm, gs, gq = np.zeros((3, n)), np.zeros((3, n)), np.zeros((4, n))
@@ -183,7 +186,7 @@ def backward(scene, cams, settings, dL: np.ndarray, mode: int = 32, pix: np.ndar
     d = np.ascontiguousarray(dL, dtype=np.float64)
     pp = None if pix is None else np.ascontiguousarray(pix, dtype=np.int32)
     lib().oracle_backward(*a.tuple(), mode, _p(pp), 0 if pp is None else pp.shape[0], _p(d),
-                          _p(gm), _p(gs), _p(gq), _p(go), _p(gsh), _p(g2d), _p(g2dk))
+                          _p(gm), _p(gs), _p(gq), _p(go), _p(gsh), _p(g2d), _p(g2dk), int(band))
     out = dict(means=gm, scales=gs, quats=gq, opacities=go, sh=gsh)
     if want_g2d:
         out["g2d"] = g2d
