@@ -600,7 +600,9 @@ __device__ inline void bwd_pixel_step(BwdPixel& P, bool ok, float power, float t
   // alpha = 0 where the Gaussian does not contribute, so its weight below is 0 without a select
   const float alpha = ok ? fminf(araw, kAlphaMax) : 0.0f;
   const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
-  P.T = ok ? P.T * inv_om : P.T;  // transmittance in front of this Gaussian
+  // transmittance in front of this Gaussian; where it does not contribute alpha = 0 and the
+  // reciprocal of 1 is exactly 1 (powers of two are exact), so T is unchanged without a select
+  P.T = P.T * inv_om;
   const float wk = alpha * P.T;
   const float dc = fmaf(P.dl0, c.x, fmaf(P.dl1, c.y, P.dl2 * c.z));  // dL/dC . colour
   const float dL_da = fmaf(dc, P.T, -P.DS * inv_om);

@@ -438,7 +438,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
         // alpha = 0 where the Gaussian does not contribute, so its weight below is 0 without a select
         const float alpha = ok ? fminf(araw, kAlphaMax) : 0.0f;
         const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
-        T = ok ? T * inv_om : T;  // transmittance in front of this Gaussian
+        T = T * inv_om;  // transmittance in front of this Gaussian (alpha = 0: times exactly 1)
         const float wk = alpha * T;
         const float4 col = S.s3[k];
         const float dc = fmaf(dl0, col.x, fmaf(dl1, col.y, dl2 * col.z));  // dL/dC . colour
