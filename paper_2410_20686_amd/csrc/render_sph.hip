@@ -357,8 +357,11 @@ __device__ inline double sph_flush_value(const float (&acc)[NS][kNV][B], int q, 
   return (i == j ? 2.0 : 4.0) * nyn;  // the shared off-diagonal takes both symmetric entries
 }
 
+// At tile 16 the flush's double arithmetic would otherwise set the register budget (91 VGPRs, five
+// wavefronts per SIMD); asking for six keeps the loop's allocation (72, no spills).
 template <int TILE, int BATCH>
-__global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
+__global__ __launch_bounds__(TILE* TILE) __attribute__((amdgpu_waves_per_eu(TILE == 16 && BATCH <= 64 ? 6 : 1)))
+void render_sph_bwd_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items,
     const SphRec* __restrict__ rec, const SphCull* __restrict__ cull, const double2* __restrict__ dirs,
     const float* __restrict__ ws_T, const int32_t* __restrict__ ws_last, const float* __restrict__ dL_drgb,
