@@ -63,7 +63,7 @@ def assert_grads_close(gpu, ref, names=("means", "scales", "quats", "opacities",
     return report
 
 
-def float_exponent_slack(scene, cams, settings, dL, ref):
+def float_exponent_slack(scene, cams, settings, dL, ref, pix=None):
     """Per-element distance between the oracle's gradient (mode 32: float contributor decisions,
     double arithmetic) and the same derivative taken at the exponents as the float pass evaluated
     them (mode 33).  A float32 renderer composites with float exponents, so its gradient can sit
@@ -72,7 +72,7 @@ def float_exponent_slack(scene, cams, settings, dL, ref):
     1e-3 scale.  Keys: the five parameter tensors, plus "g2d" (kernel layout) for the spherical
     footprint."""
     from oracle import oracle as O
-    alt = O.backward(scene, cams, settings, dL, mode=33, want_g2d="g2d_kernel" in ref)
+    alt = O.backward(scene, cams, settings, dL, mode=33, pix=pix, want_g2d="g2d_kernel" in ref)
     out = {k: np.abs(ref[k] - alt[k]) for k in ("means", "scales", "quats", "opacities", "sh")}
     if "g2d_kernel" in ref:
         out["g2d"] = np.abs(ref["g2d_kernel"] - alt["g2d_kernel"])
