@@ -279,9 +279,12 @@ def main():
     roof = None
     if dom in alg_ops:
         achieved = alg_ops[dom] / (stages[dom] / 1e3) / 1e12
-        if dom == "composite_bwd":  # two pixels per lane from 16x16 tiles up
-            kname = "odgs::render_bwd%s_kernel<%d, %d>" % ("2" if st["tile"] >= 16 else "", st["tile"],
-                                                          rast.plan.s.batch_bwd)
+        if dom == "composite_bwd":  # one wavefront per 16x16 tile (four pixels per lane), else two or one
+            if st["tile"] == 16:
+                kname = "odgs::render_bwd4_kernel<%d>" % rast.plan.s.batch_bwd
+            else:
+                kname = "odgs::render_bwd%s_kernel<%d, %d>" % ("2" if st["tile"] >= 32 else "", st["tile"],
+                                                              rast.plan.s.batch_bwd)
         else:
             kname = "odgs::render_fwd%s_kernel<%d, %d%s>" % ("2" if st["tile"] >= 32 else "", st["tile"],
                                                             rast.plan.s.batch, "" if st["tile"] >= 32 else

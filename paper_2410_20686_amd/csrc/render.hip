@@ -342,7 +342,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
           uint32_t mq = 0;
 #pragma unroll
           for (int q = 0; q < St::NQ; ++q) mq |= s_used[q][e] ? (1u << q) : 0u;
-          qmask[first + e] = (uint8_t)(TILE >= 16 ? group_mask<2>(mq) : mq);
+          qmask[first + e] = (uint8_t)(TILE >= 32 ? group_mask<2>(mq) : mq);
         }
 #pragma unroll
         for (int q = 0; q < St::NQ; ++q) s_used[q][e] = 0;
@@ -751,6 +751,135 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   }
 }
 
+// Reverse compositing of a 16x16 tile by one wavefront, four pixels per lane (lane l holds pixel
+// (l % 8, l / 8) of each quadrant): the four quadrants' contributions to an entry are added in
+// registers and reduced across lanes once, and a quadrant the forward's pixels did not reach
+// (its bit in the staged mask) costs nothing for that entry.
+template <int BATCH>
+struct Stage4 {
+  float4 s0[BATCH];
+  float4 s1[BATCH];
+  float4 s2[BATCH];
+  uint32_t sid[BATCH];
+  uint8_t list[BATCH];
+  uint8_t msk[BATCH];
+};
+
+template <int BATCH>
+__global__ __launch_bounds__(kWave) void render_bwd4_kernel(
+    ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
+    const float* __restrict__ ws_T, const int32_t* __restrict__ ws_last, const float* __restrict__ dL_drgb,
+    double* __restrict__ g2d, int64_t items, float bg0, float bg1, float bg2, const uint8_t* __restrict__ qmask,
+    TileSched sc) {
+  constexpr int TILE = 16;
+  __shared__ Stage4<BATCH> S;
+  __shared__ float acc[1][9][BATCH + 1];
+  if (forward_is_stale(sc)) return;  // uniform
+  __shared__ uint32_t s_claim;
+  uint32_t round = 0;
+  const int lane = threadIdx.x;
+  const int slot = (int)((kRowSlot >> (4 * (lane & 15))) & 0xF);
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+  for (int g; (g = claim_tile(sc, round, &s_claim)) >= 0;) {
+    const int v = view_of_tile(vt, g);
+    const int W = vt.W[v], H = vt.H[v];
+    const int ntx = W / TILE;
+    const int lt = g - vt.tile_base[v];
+    const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+    const int x = tx0 + (lane & 7), y = ty0 + (lane >> 3);
+    const float px0 = (float)x + 0.5f, px1 = (float)(x + 8) + 0.5f;
+    const float py0 = (float)y + 0.5f, py1 = (float)(y + 8) + 0.5f;
+    const float Wf = (float)W, half = wrap_half(vt, v);
+    const uint2 rg = ranges[g];
+    const int64_t plane = (int64_t)W * H;
+    const float* dimg = dL_drgb + 3 * vt.pix_base[v];
+    BwdPixel P[4];  // quadrant q = 2 * qy + qx
+    int wmax = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t pix = (int64_t)(y + 8 * (q >> 1)) * W + x + 8 * (q & 1);
+      const int64_t gp = vt.pix_base[v] + pix;
+      P[q].dl0 = dimg[pix], P[q].dl1 = dimg[plane + pix], P[q].dl2 = dimg[2 * plane + pix];
+      P[q].T = ws_T[gp];
+      P[q].last = ws_last[gp];
+      P[q].DS = P[q].T * fmaf(P[q].dl0, bg0, fmaf(P[q].dl1, bg1, P[q].dl2 * bg2));
+      wmax = max(wmax, P[q].last);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
+    wmax = __builtin_amdgcn_readfirstlane(wmax);
+    for (int end = wmax; end > 0; end -= BATCH) {
+      const int cnt = min(BATCH, end);
+      // stage entries end - 1 - e (back to front) with their quadrant masks; list those reaching
+      // any quadrant, in order
+      int n = 0;
+      for (int r0 = 0; r0 < cnt; r0 += kWave) {
+        const int e = r0 + lane;
+        uint32_t m = 0;
+        if (e < cnt) {
+          const uint32_t pos = rg.x + end - 1 - e;
+          const uint32_t item = pair_items[pos];
+          const Rec r = rec[item];
+          S.s0[e] = r.r0;
+          const float reach = fabsf((float)tx0 + 0.5f * (float)TILE - r.r0.x) + 0.5f * (float)TILE + 1.0f;
+          S.s1[e] = make_float4(r.r1.x, r.r1.z, r.r1.y, reach < half ? 1.0f : 0.0f);
+          S.s2[e] = r.r2;
+          S.sid[e] = item;
+          m = qmask[pos];
+          S.msk[e] = (uint8_t)m;
+#pragma unroll
+          for (int q = 0; q < 9; ++q) acc[0][q][e] = 0.0f;
+        }
+        const uint64_t bl = __builtin_amdgcn_ballot_w64(m != 0u);
+        if (m != 0u) S.list[n + __popcll(bl & below)] = (uint8_t)e;
+        n += __popcll(bl);
+      }
+      __syncthreads();
+      for (int i = 0; i < n; ++i) {
+        const int k = __builtin_amdgcn_readfirstlane(S.list[i]);
+        const int jrel = end - 1 - k;
+        const float4 a = S.s0[k];
+        const float4 b = S.s1[k];
+        const uint32_t mq = __builtin_amdgcn_readfirstlane(S.msk[k]);
+        const bool wrap = __builtin_amdgcn_readfirstlane(__float_as_int(b.w)) == 0;  // uniform
+        float du0 = px0 - a.x, du1 = px1 - a.x;
+        if (wrap) {
+          du0 = wrap_du(du0, Wf, half);
+          du1 = wrap_du(du1, Wf, half);
+        }
+        const float4 c = S.s2[k];
+        float gq[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) gq[q] = 0.0f;
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (!((mq >> q) & 1u)) continue;  // uniform: no pixel of this quadrant reached the entry
+          const float dv = (q >> 1 ? py1 : py0) - a.y;
+          const float du = q & 1 ? du1 : du0;
+          const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
+          const float p = -fmaf(t1, t1, t2 * t2);
+          const bool ok = jrel < P[q].last && !(p < b.y);
+          if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
+          bwd_pixel_step<true>(P[q], ok, p, t1, t2, a, b, c, gq);
+          any = true;
+        }
+        if (!any) continue;  // uniform
+        const float rs = row_reduce9(gq, lane & 8, lane & 4, lane & 2, lane & 1);
+        const float ws = sum_rows(rs);
+        if (lane < 16 && slot < 9) acc[0][slot][k] = ws;
+      }
+      __syncthreads();
+      for (int xq = lane; xq < 9 * cnt; xq += kWave) {
+        const int t = xq / 9, q = xq - 9 * t;
+        const double s = g2d_flush_value(acc, q, t, S.s0[t], S.s1[t]);
+        if (s != 0.0) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s);
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Reverse compositing with two pixels per lane (16x16 and 32x32 tiles): wavefront w owns quadrants
 // 2w and 2w + 1 (side by side), lane l the pixel (l % 8, l / 8) of each.  Both pixels' gradient
 // contributions are added in registers, so each (entry, wavefront) needs one cross-lane
@@ -943,7 +1072,10 @@ struct BwdRun {
                   const uint8_t* qmask, hipStream_t st) {
     // two pixels per lane (tiles of 16 and 32): one cross-lane reduction per 128 pixels; an 8x8
     // tile has a single quadrant and keeps one pixel per lane
-    if constexpr (TILE >= 16)
+    if constexpr (TILE == 16)
+      launch_sched(render_bwd4_kernel<BATCH>, sc, kWave, st, vt, ranges, items, rec, wT, wl, dL, g2d, p->items,
+                   p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
+    else if constexpr (TILE >= 32)
       launch_sched(render_bwd2_kernel<TILE, BATCH>, sc, TILE * TILE / 2, st, vt, ranges, items, rec, wT, wl, dL, g2d,
                    p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
     else
