@@ -75,40 +75,87 @@ __device__ inline int view_of_item(int64_t item, int64_t n) { return (int)(item 
 // by building a work queue of all global tile ids, longest list first.  Persistent launches (as
 // many workgroups as fit on the device at once) claim queue entries one at a time with an atomic
 // counter, the last workgroup to find the queue empty clearing the counters for the next launch;
-// otherwise one workgroup per tile takes queue entry blockIdx.x (order == nullptr: tile id
-// blockIdx.x, no queue).
+// otherwise one workgroup per task takes task blockIdx.x (order == nullptr: tile id blockIdx.x, no
+// queue).
+//
+// A task is a whole tile or, for compositors that take them (split_cap > 0), one 8x8 quadrant of
+// one of the longest tiles: binning counts the tiles whose lists reach the split length (at most
+// split_cap of them, all at the front of the queue), and each of those becomes four tasks, so that
+// a single long list is composited by four wavefronts at once instead of setting the launch's
+// length by itself.  Tasks 0 .. 4 nsplit - 1 are those quadrants (task e: quadrant e % 4 of queue
+// entry e / 4), then come the remaining queue entries as whole tiles.
 struct TileSched {
   const uint32_t* order;  // tile ids by descending list length, or nullptr
-  uint32_t* ctr;          // persistent: {next queue entry, finished workgroups}; nullptr: one tile each
+  uint32_t* ctr;          // persistent: {next task, finished workgroups}; nullptr: one task each
   odgs_status* status;
+  uint32_t* split;        // {tiles split by binning, tiles split by the last forward}
   int32_t tiles;
+  int32_t split_cap;      // 0: whole tiles only
 };
 
-// Next tile of this workgroup (uniform), or -1 when it is done.  `round` starts at 0; `slot` is
-// a workgroup-shared word.  Contains barriers in persistent mode.
-__device__ inline int claim_tile(const TileSched& s, uint32_t& round, uint32_t* slot) {
+// Upper bound of the task count of a launch (its grid without a persistent launch).
+inline int sched_tasks(const TileSched& s) { return s.tiles + 3 * s.split_cap; }
+
+// Next task of this workgroup (uniform): returns its tile and sets `sel` to the quadrants it
+// covers (0xF: the whole tile), or returns -1 when the workgroup is done.  `nsplit` (uniform, at
+// most split_cap) is the number of split tiles; `round` starts at 0; `slot` is a workgroup-shared
+// word.  Contains barriers in persistent mode.
+__device__ inline int claim_task(const TileSched& s, int nsplit, uint32_t& round, uint32_t* slot, uint32_t& sel) {
+  const uint32_t total = (uint32_t)(s.tiles + 3 * nsplit);
+  uint32_t e;
   if (!s.ctr) {
     if (round++) return -1;
-    return s.order ? (int)s.order[blockIdx.x] : (int)blockIdx.x;
-  }
-  __syncthreads();  // every thread has read the previous claim
-  if (threadIdx.x == 0) {
-    const uint32_t e = atomicAdd(&s.ctr[0], 1u);
-    // queue drained: every workgroup passes here once, so the last one resets the counters
-    if (e >= (uint32_t)s.tiles && atomicAdd(&s.ctr[1], 1u) == gridDim.x - 1) {
-      atomicExch(&s.ctr[0], 0u);
-      atomicExch(&s.ctr[1], 0u);
+    e = blockIdx.x;
+  } else {
+    __syncthreads();  // every thread has read the previous claim
+    if (threadIdx.x == 0) {
+      const uint32_t c = atomicAdd(&s.ctr[0], 1u);
+      // queue drained: every workgroup passes here once, so the last one resets the counters
+      if (c >= total && atomicAdd(&s.ctr[1], 1u) == gridDim.x - 1) {
+        atomicExch(&s.ctr[0], 0u);
+        atomicExch(&s.ctr[1], 0u);
+      }
+      *slot = c;
     }
-    *slot = e;
+    __syncthreads();
+    e = *slot;
   }
-  __syncthreads();
-  const uint32_t e = *slot;
-  return e < (uint32_t)s.tiles ? (int)s.order[e] : -1;
+  if (e >= total) return -1;
+  if (!s.order) {
+    sel = 0xFu;
+    return (int)e;
+  }
+  if (e < 4u * (uint32_t)nsplit) {
+    sel = 1u << (e & 3u);
+    return (int)s.order[e >> 2];
+  }
+  sel = 0xFu;
+  return (int)s.order[e - 3u * (uint32_t)nsplit];
 }
 
-// The forward marks the pair list it composited; the reverse compositor runs only on that list.
-__device__ inline void mark_forward(const TileSched& s) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) s.status->fwd_gen = s.status->bin_gen;
+// Next whole tile of this workgroup (compositors that take no quadrant tasks).
+__device__ inline int claim_tile(const TileSched& s, uint32_t& round, uint32_t* slot) {
+  uint32_t sel;
+  return claim_task(s, 0, round, slot, sel);
+}
+
+// Split tiles of a forward launch (uniform): what binning chose, within this launch's cap.
+__device__ inline int forward_split(const TileSched& s) {
+  return s.split_cap > 0 && s.order ? (int)min(s.split[0], (uint32_t)s.split_cap) : 0;
+}
+// Split tiles of a reverse launch: those of the forward it follows (which wrote the culling masks
+// of the split tiles' quadrants separately), within this launch's cap.
+__device__ inline int reverse_split(const TileSched& s) {
+  return s.split_cap > 0 && s.order ? (int)min(s.split[1], (uint32_t)s.split_cap) : 0;
+}
+
+// The forward marks the pair list it composited, and how many tiles it split; the reverse
+// compositor runs only on that list.
+__device__ inline void mark_forward(const TileSched& s, int nsplit = 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s.status->fwd_gen = s.status->bin_gen;
+    s.split[1] = (uint32_t)nsplit;
+  }
 }
 __device__ inline bool forward_is_stale(const TileSched& s) {
   const bool stale = s.status->fwd_gen != s.status->bin_gen;
@@ -174,8 +221,16 @@ hipError_t launch_adam_step(int64_t n, int32_t sh_degree, const odgs_param_ptrs&
 hipError_t launch_fill_u32(uint32_t* ptr, uint32_t value, int64_t n, hipStream_t st);
 hipError_t launch_status_reset(const odgs_plan* p, void* ws, hipStream_t st);
 // Scheduling of a compositor launch: the queue, and for persistent launches the counter pair
-// (which = 0 forward, 1 reverse) and the grid that fits `per_cu` workgroups on every CU.
+// (which = 0 forward, 1 reverse) and the grid that fits `per_cu` workgroups on every CU.  Whole
+// tiles only (split_cap 0); split_tile_cap gives the cap of compositors that take quadrant tasks.
 TileSched make_sched(const odgs_plan* p, void* ws, int which);
+int split_tile_cap(int tiles);
+// The schedule of a compositor that takes quadrant tasks (only with the queue, which names the
+// longest tiles).
+inline TileSched with_split(TileSched s) {
+  if (s.order) s.split_cap = split_tile_cap(s.tiles);
+  return s;
+}
 int sched_grid(const TileSched& s, int per_cu);
 
 // Launch of a compositor kernel whose last parameter is its TileSched: a persistent launch sizes
@@ -183,7 +238,7 @@ int sched_grid(const TileSched& s, int per_cu);
 // tile.
 template <typename... KArgs, typename... Args>
 inline void launch_sched(void (*kernel)(KArgs...), const TileSched& s, int threads, hipStream_t st, Args&&... args) {
-  int grid = s.tiles;
+  int grid = sched_tasks(s);
   if (s.ctr) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess) per_cu = 1;

@@ -140,8 +140,9 @@ __device__ inline float rect_min_quadratic(float a, float b, float c, float nba,
 // (rounding of products and of du, dv) and the rounding of this test, so no contributing pixel
 // is ever skipped.  Quadrants whose horizontal span reaches the +-W/2 wrap point keep the
 // rectangle test only.
+// Only the quadrants in `sel` (uniform) are tested; the others read as not reached.
 template <int TILE>
-__device__ inline uint32_t quadrant_mask(const Rec& r, int tx0, int ty0, float Wf, float half) {
+__device__ inline uint32_t quadrant_mask(const Rec& r, int tx0, int ty0, float Wf, float half, uint32_t sel = ~0u) {
   constexpr int QPR = TILE / 8;
   const float u = r.r0.x, v = r.r0.y, eu = r.r1.w, ev = r.r2.w;
   // inverse covariance [[a, b], [b, c]] = 2 L^T L of the stored factor
@@ -154,6 +155,7 @@ __device__ inline uint32_t quadrant_mask(const Rec& r, int tx0, int ty0, float W
   uint32_t mask = 0;
 #pragma unroll
   for (int q = 0; q < QPR * QPR; ++q) {
+    if (!((sel >> q) & 1u)) continue;
     const float qcx = (float)(tx0 + (q % QPR) * 8 + 4);
     const float qcy = (float)(ty0 + (q / QPR) * 8 + 4);
     float du = qcx - u;
@@ -422,6 +424,145 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
     }
     if (DEPTH) out_depth[gp] = D;
     if (out_T) out_T[gp] = T;
+  }
+}
+
+// Forward compositing of a 16x16 tile by one wavefront, four pixels per lane (lane l holds pixel
+// (l % 8, l / 8) of each quadrant): the tile's list is staged once with each entry's quadrant mask
+// (the footprint test of the one-pixel forward), and an entry is evaluated only for the quadrants
+// it can reach and whose pixels still composite.  The quadrants in which some pixel reached an
+// entry are handed to the backward as in the one-pixel forward.  A quadrant task of a split tile
+// (see TileSched) runs the same code with its one quadrant selected, and hands its masks over in
+// the byte plane of its quadrant (plane q at byte offset q * qplane; whole tiles use plane 0).
+template <int BATCH>
+struct FwdStage4 {
+  float4 s0[BATCH];
+  float4 s1[BATCH];
+  float4 s2[BATCH];
+  uint8_t list[BATCH];
+  uint8_t msk[BATCH];
+  uint8_t used[BATCH];
+};
+
+template <int BATCH>
+__global__ __launch_bounds__(kWave) void render_fwd4_kernel(
+    ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
+    float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
+    float bg0, float bg1, float bg2, uint8_t* __restrict__ qmask, int64_t qplane, TileSched sc) {
+  constexpr int TILE = 16;
+  __shared__ FwdStage4<BATCH> S;
+  const int nsplit = forward_split(sc);
+  mark_forward(sc, nsplit);
+  __shared__ uint32_t s_claim;
+  uint32_t round = 0, sel = 0;
+  const int lane = threadIdx.x;
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+  for (int g; (g = claim_task(sc, nsplit, round, &s_claim, sel)) >= 0;) {
+    const int v = view_of_tile(vt, g);
+    const int W = vt.W[v], H = vt.H[v];
+    const int ntx = W / TILE;
+    const int lt = g - vt.tile_base[v];
+    const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+    const int x = tx0 + (lane & 7), y = ty0 + (lane >> 3);
+    const float px0 = (float)x + 0.5f, px1 = (float)(x + 8) + 0.5f;
+    const float py0 = (float)y + 0.5f, py1 = (float)(y + 8) + 0.5f;
+    const float Wf = (float)W, half = wrap_half(vt, v);
+    const uint2 rg = ranges[g];
+    float T[4], C0[4], C1[4], C2[4], qstop[4];  // qstop: 0 while compositing, NaN once stopped
+    int last[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T[q] = 1.0f;
+      C0[q] = C1[q] = C2[q] = 0.0f;
+      qstop[q] = 0.0f;
+      last[q] = 0;
+    }
+    uint32_t alive = sel;  // selected quadrants with a pixel still compositing (uniform)
+    uint8_t* qm = qmask + (sel == 0xFu ? 0 : (int64_t)__builtin_ctz(sel) * qplane);
+    for (uint32_t base = rg.x; base < rg.y && alive != 0u; base += BATCH) {
+      const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
+      int n = 0;
+      for (int r0 = 0; r0 < cnt; r0 += kWave) {
+        const int e = r0 + lane;
+        uint32_t m = 0;
+        if (e < cnt) {
+          const Rec r = rec[pair_items[base + e]];
+          S.s0[e] = r.r0;
+          const float reach = fabsf((float)tx0 + 0.5f * (float)TILE - r.r0.x) + 0.5f * (float)TILE + 1.0f;
+          S.s1[e] = make_float4(r.r1.x, r.r1.z, r.r1.y, reach < half ? 1.0f : 0.0f);
+          S.s2[e] = r.r2;
+          S.used[e] = 0;
+          m = quadrant_mask<TILE>(r, tx0, ty0, Wf, half, sel);
+          S.msk[e] = (uint8_t)m;
+        }
+        const uint64_t bl = __builtin_amdgcn_ballot_w64(m != 0u);
+        if (m != 0u) S.list[n + __popcll(bl & below)] = (uint8_t)e;
+        n += __popcll(bl);
+      }
+      __syncthreads();
+      for (int i = 0; i < n && alive != 0u; ++i) {
+        const int k = __builtin_amdgcn_readfirstlane(S.list[i]);
+        const uint32_t mq = __builtin_amdgcn_readfirstlane(S.msk[k]) & alive;
+        if (mq == 0u) continue;  // uniform
+        const float4 a = S.s0[k];
+        const float4 b = S.s1[k];
+        const bool wrap = __builtin_amdgcn_readfirstlane(__float_as_int(b.w)) == 0;  // uniform
+        float du0 = px0 - a.x, du1 = px1 - a.x;
+        if (wrap) {
+          du0 = wrap_du(du0, Wf, half);
+          du1 = wrap_du(du1, Wf, half);
+        }
+        uint32_t used = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (!((mq >> q) & 1u)) continue;  // uniform
+          const float dv = (q >> 1 ? py1 : py0) - a.y;
+          const float du = q & 1 ? du1 : du0;
+          const float t1 = fmaf(a.z, du, a.w * dv), t2 = b.x * dv;
+          const float power = -fmaf(t1, t1, fmaf(t2, t2, qstop[q]));
+          const bool ok = power >= b.y;  // alpha >= 1/255 (NaN once the pixel has stopped)
+          const uint64_t bok = __builtin_amdgcn_ballot_w64(ok);
+          if (bok == 0ull) continue;  // uniform
+          used |= 1u << q;
+          const float4 c = S.s2[k];
+          const float alpha = fminf(b.z * __expf(power), kAlphaMax);
+          const float Tn = T[q] * (1.0f - alpha);
+          const bool acc = ok && !(Tn < kTStop);
+          qstop[q] = ok != acc ? __builtin_nanf("") : qstop[q];  // stop: reached, but T would drop below 1e-4
+          const float w = (acc ? alpha : 0.0f) * T[q];
+          C0[q] = fmaf(w, c.x, C0[q]);
+          C1[q] = fmaf(w, c.y, C1[q]);
+          C2[q] = fmaf(w, c.z, C2[q]);
+          T[q] = acc ? Tn : T[q];
+          last[q] = acc ? (int)(base - rg.x) + k + 1 : last[q];
+          if (__builtin_amdgcn_ballot_w64(ok != acc) != 0ull &&
+              __builtin_amdgcn_ballot_w64(qstop[q] == 0.0f) == 0ull)
+            alive &= ~(1u << q);  // uniform: every pixel of this quadrant has stopped
+        }
+        if (lane == 0 && used) S.used[k] = (uint8_t)used;
+      }
+      __syncthreads();
+      // the backward's masks for this batch: the quadrants in which some pixel reached each entry
+      for (int e = lane; e < cnt; e += kWave) qm[base + e] = S.used[e];
+      __syncthreads();
+    }
+    // entries past the point where every pixel stopped were never reached: their masks stay as
+    // the binning left them, and the backward (which stops at each tile's last contributor) never
+    // reads them
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!((sel >> q) & 1u)) continue;
+      const int64_t pix = (int64_t)(y + 8 * (q >> 1)) * W + x + 8 * (q & 1);
+      float* img = out_rgb + 3 * vt.pix_base[v];
+      const int64_t plane = (int64_t)W * H;
+      img[pix] = fmaf(T[q], bg0, C0[q]);
+      img[plane + pix] = fmaf(T[q], bg1, C1[q]);
+      img[2 * plane + pix] = fmaf(T[q], bg2, C2[q]);
+      const int64_t gp = vt.pix_base[v] + pix;
+      ws_T[gp] = T[q];
+      ws_last[gp] = last[q];
+      if (out_T) out_T[gp] = T[q];
+    }
   }
 }
 
@@ -770,17 +911,18 @@ __global__ __launch_bounds__(kWave) void render_bwd4_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
     const float* __restrict__ ws_T, const int32_t* __restrict__ ws_last, const float* __restrict__ dL_drgb,
     double* __restrict__ g2d, int64_t items, float bg0, float bg1, float bg2, const uint8_t* __restrict__ qmask,
-    TileSched sc) {
+    int64_t qplane, TileSched sc) {
   constexpr int TILE = 16;
   __shared__ Stage4<BATCH> S;
   __shared__ float acc[1][9][BATCH + 1];
   if (forward_is_stale(sc)) return;  // uniform
+  const int nsplit = reverse_split(sc);
   __shared__ uint32_t s_claim;
-  uint32_t round = 0;
+  uint32_t round = 0, sel = 0;
   const int lane = threadIdx.x;
   const int slot = (int)((kRowSlot >> (4 * (lane & 15))) & 0xF);
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
-  for (int g; (g = claim_tile(sc, round, &s_claim)) >= 0;) {
+  for (int g; (g = claim_task(sc, nsplit, round, &s_claim, sel)) >= 0;) {
     const int v = view_of_tile(vt, g);
     const int W = vt.W[v], H = vt.H[v];
     const int ntx = W / TILE;
@@ -797,6 +939,10 @@ __global__ __launch_bounds__(kWave) void render_bwd4_kernel(
     int wmax = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+      if (!((sel >> q) & 1u)) {
+        P[q].last = 0;  // not this task's: never reached, its other members never read
+        continue;
+      }
       const int64_t pix = (int64_t)(y + 8 * (q >> 1)) * W + x + 8 * (q & 1);
       const int64_t gp = vt.pix_base[v] + pix;
       P[q].dl0 = dimg[pix], P[q].dl1 = dimg[plane + pix], P[q].dl2 = dimg[2 * plane + pix];
@@ -805,6 +951,7 @@ __global__ __launch_bounds__(kWave) void render_bwd4_kernel(
       P[q].DS = P[q].T * fmaf(P[q].dl0, bg0, fmaf(P[q].dl1, bg1, P[q].dl2 * bg2));
       wmax = max(wmax, P[q].last);
     }
+    const uint8_t* qm = qmask + (sel == 0xFu ? 0 : (int64_t)__builtin_ctz(sel) * qplane);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
     wmax = __builtin_amdgcn_readfirstlane(wmax);
@@ -825,7 +972,7 @@ __global__ __launch_bounds__(kWave) void render_bwd4_kernel(
           S.s1[e] = make_float4(r.r1.x, r.r1.z, r.r1.y, reach < half ? 1.0f : 0.0f);
           S.s2[e] = r.r2;
           S.sid[e] = item;
-          m = qmask[pos];
+          m = qm[pos] & sel;
           S.msk[e] = (uint8_t)m;
 #pragma unroll
           for (int q = 0; q < 9; ++q) acc[0][q][e] = 0.0f;
@@ -1056,7 +1203,10 @@ struct FwdRun {
       ODGS_FWD1(true, false);
     else if (out_depth)
       ODGS_FWD1(false, true);
-    else if constexpr (TILE >= 32)  // at 16x16 the union of two quadrants' lists costs more than it saves
+    else if constexpr (TILE == 16)
+      launch_sched(render_fwd4_kernel<BATCH>, with_split(sc), kWave, st, vt, ranges, items, rec, out_rgb, out_T, wT,
+                   wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask, (int64_t)p->pair_capacity);
+    else if constexpr (TILE >= 32)
       launch_sched(render_fwd2_kernel<TILE, BATCH>, sc, TILE * TILE / 2, st, vt, ranges, items, rec, out_rgb, out_T,
                    wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
     else
@@ -1070,11 +1220,12 @@ struct BwdRun {
   static void run(const odgs_plan* p, const TileSched& sc, const ViewTable& vt, const uint2* ranges,
                   const uint32_t* items, const Rec* rec, const float* wT, const int32_t* wl, const float* dL, double* g2d,
                   const uint8_t* qmask, hipStream_t st) {
-    // two pixels per lane (tiles of 16 and 32): one cross-lane reduction per 128 pixels; an 8x8
-    // tile has a single quadrant and keeps one pixel per lane
+    // four pixels per lane in one wavefront at 16x16 (split tiles as the forward split them), two
+    // pixels per lane at 32x32 (one cross-lane reduction per 128 pixels); an 8x8 tile has a single
+    // quadrant and keeps one pixel per lane
     if constexpr (TILE == 16)
-      launch_sched(render_bwd4_kernel<BATCH>, sc, kWave, st, vt, ranges, items, rec, wT, wl, dL, g2d, p->items,
-                   p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
+      launch_sched(render_bwd4_kernel<BATCH>, with_split(sc), kWave, st, vt, ranges, items, rec, wT, wl, dL, g2d,
+                   p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask, (int64_t)p->pair_capacity);
     else if constexpr (TILE >= 32)
       launch_sched(render_bwd2_kernel<TILE, BATCH>, sc, TILE * TILE / 2, st, vt, ranges, items, rec, wT, wl, dL, g2d,
                    p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);

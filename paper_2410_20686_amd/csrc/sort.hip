@@ -465,6 +465,13 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* __restrict_
 // that turns them into per-(block, bucket) starts, and the scatter.
 constexpr int kQueueBuckets = 1024;
 constexpr int kQueueTiles = 4096;  // tiles per block of the count and scatter kernels (16 per thread)
+// A list is split into quadrant tasks (for compositors that take them) when one wavefront alone
+// would take long against the whole launch: when it holds at least kSplitLen pairs and at least
+// 1 / kSplitShare of all pairs.  At most split_tile_cap(tiles) lists are split: an eighth of the
+// tiles, or kSplitCapMin.
+constexpr uint32_t kSplitLen = 1024;
+constexpr uint32_t kSplitShare = 4096;
+constexpr int kSplitCapMin = 1024;
 
 __device__ inline uint32_t cost_bucket(uint32_t len) {
   // 0 for an empty list, else 1 + 32 log2(len) (exponent and top five mantissa bits; <= 993)
@@ -489,9 +496,11 @@ __global__ __launch_bounds__(256) void queue_count_kernel(const uint2* __restric
 }
 
 // Buckets in descending order, blocks in order: the counts become each (block, bucket)'s first
-// queue position.  One workgroup; also clears the persistent launches' counters.
+// queue position.  One workgroup; also clears the persistent launches' counters and records the
+// number of tiles to split (those with lists of kSplitLen or more, at most split_cap).
 __global__ __launch_bounds__(kQueueBuckets) void queue_scan_kernel(uint32_t* __restrict__ bstart, int nblocks,
-                                                                   uint32_t* __restrict__ ctr) {
+                                                                   uint32_t* __restrict__ ctr, uint32_t split_cap,
+                                                                   const uint32_t* __restrict__ n_pairs) {
   __shared__ uint32_t wsum[kQueueBuckets / kWave];
   const int t = threadIdx.x, lane = t & (kWave - 1), w = t >> 6;
   const int bucket = kQueueBuckets - 1 - t;
@@ -503,6 +512,8 @@ __global__ __launch_bounds__(kQueueBuckets) void queue_scan_kernel(uint32_t* __r
   __syncthreads();
   uint32_t run = incl - c;
   for (int k = 0; k < w; ++k) run += wsum[k];
+  // tiles in this bucket or above: the first run + c queue entries
+  if (bucket == (int)cost_bucket(max(kSplitLen, *n_pairs / kSplitShare))) ctr[4] = min(run + c, split_cap);
   for (int b = 0; b < nblocks; ++b) {
     uint32_t* e = bstart + (size_t)b * kQueueBuckets + bucket;
     const uint32_t x = *e;
@@ -526,10 +537,12 @@ __global__ __launch_bounds__(256) void queue_scatter_kernel(const uint2* __restr
   }
 }
 
-hipError_t launch_tile_queue(const uint2* ranges, int tiles, uint32_t* bstart, uint32_t* queue, hipStream_t st) {
+hipError_t launch_tile_queue(const uint2* ranges, int tiles, const uint32_t* n_pairs, uint32_t* bstart,
+                             uint32_t* queue, hipStream_t st) {
   const int nb = (tiles + kQueueTiles - 1) / kQueueTiles;
   if (nb > 0) hipLaunchKernelGGL(queue_count_kernel, dim3(nb), dim3(256), 0, st, ranges, tiles, bstart);
-  hipLaunchKernelGGL(queue_scan_kernel, dim3(1), dim3(kQueueBuckets), 0, st, bstart, nb, queue);
+  hipLaunchKernelGGL(queue_scan_kernel, dim3(1), dim3(kQueueBuckets), 0, st, bstart, nb, queue,
+                     (uint32_t)split_tile_cap(tiles), n_pairs);
   if (nb > 0) hipLaunchKernelGGL(queue_scatter_kernel, dim3(nb), dim3(256), 0, st, ranges, tiles, bstart, queue + 16);
   return hipGetLastError();
 }
@@ -580,8 +593,12 @@ TileSched make_sched(const odgs_plan* p, void* ws, int which) {
   s.tiles = p->tile_base[p->n_views];
   s.order = (p->s.flags & ODGS_FLAG_SCHED_TILE_ID) ? nullptr : q + 16;  // after 64 bytes of counters
   s.ctr = (p->s.flags & ODGS_FLAG_SCHED_PERSISTENT) ? q + 2 * which : nullptr;
+  s.split = q + 4;
+  s.split_cap = 0;
   return s;
 }
+
+int split_tile_cap(int tiles) { return tiles < kSplitCapMin ? tiles : std::max(kSplitCapMin, tiles / 8); }
 
 int sched_grid(const TileSched& s, int per_cu) {
   int dev = 0, cus = 0;
@@ -589,7 +606,7 @@ int sched_grid(const TileSched& s, int per_cu) {
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
     cus = 1;
   const int64_t g = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
-  return (int)(g < s.tiles ? g : s.tiles);
+  return (int)(g < sched_tasks(s) ? g : sched_tasks(s));
 }
 
 hipError_t launch_fill_u32(uint32_t* ptr, uint32_t value, int64_t n, hipStream_t st) {
@@ -608,7 +625,8 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
   if (e != hipSuccess) return e;
   const int tiles = p->tile_base[p->n_views];
   uint32_t* queue = ws_ptr<uint32_t>(ws, p->off_queue);
-  if (items == 0) return launch_tile_queue(ranges, tiles, hist, queue, st);
+  const uint32_t* n_dev = reinterpret_cast<const uint32_t*>(&status->n_pairs_stored);
+  if (items == 0) return launch_tile_queue(ranges, tiles, n_dev, hist, queue, st);
   // 1. items by radial depth (culled items carry the largest key)
   uint32_t* dk[2] = {ws_ptr<uint32_t>(ws, p->off_dkey[0]), ws_ptr<uint32_t>(ws, p->off_dkey[1])};
   uint32_t* di[2] = {ws_ptr<uint32_t>(ws, p->off_did[0]), ws_ptr<uint32_t>(ws, p->off_did[1])};
@@ -634,7 +652,6 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
                      0, st, sorted_ids, ioff, srect, status, items, p->n, vt, p->s.tile, pk[0],
                      pv[0]);
   // 4. stable sort of the pairs by global tile
-  const uint32_t* n_dev = reinterpret_cast<const uint32_t*>(&status->n_pairs_stored);
   e = radix_sort(pk[0], pv[0], pk[1], pv[1], false, n_dev, (uint32_t)p->pair_capacity, p->tile_bits, p->pair_blocks,
                  hist, digit, st);
   if (e != hipSuccess) return e;
@@ -642,7 +659,7 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
   hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((p->pair_capacity + 256 * kRangeKeys - 1) / (256 * kRangeKeys))),
                      dim3(256), 0, st, pk[p->pair_final], status, ranges);
   // 6. the compositors' work queue, longest list first (its scratch: the free radix histograms)
-  return launch_tile_queue(ranges, tiles, hist, queue, st);
+  return launch_tile_queue(ranges, tiles, n_dev, hist, queue, st);
 }
 
 }  // namespace odgs

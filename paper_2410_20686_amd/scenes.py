@@ -250,7 +250,7 @@ def sparse_upstream_gradient(cams: Cameras, seed: int, n_pixels: int):
     return grad, np.ascontiguousarray(np.concatenate(pix, axis=0), dtype=np.int32)
 
 
-DEFAULT_SETTINGS = dict(tile=16, batch=256, batch_bwd=64, near=0.2, far=1.0e4, dilation=0.3, pole_eps=1.0e-4,
+DEFAULT_SETTINGS = dict(tile=16, batch=0, batch_bwd=0, near=0.2, far=1.0e4, dilation=0.3, pole_eps=1.0e-4,
                         bg=(0.0, 0.0, 0.0))
 
 

@@ -34,7 +34,7 @@ def test_plan_layout(lib):
     assert p.n_views == 3 and p.items == 3 * 12345
     assert list(p.tile_base[:4]) == [0, 2048, 2048 + 8192, 2048 + 8192 + 8]
     assert p.pix_base[3] == 1024 * 512 + 2048 * 1024 + 64 * 32
-    assert p.tile_bits == 14 and p.s.batch == 256 and p.s.batch_bwd == 64
+    assert p.tile_bits == 14 and p.s.batch == 64 and p.s.batch_bwd == 64
     sph_only = ("off_srec", "off_cone", "off_dirs")  # empty regions (at the end) without the spherical flag
     offs = sorted(getattr(p, n) for n in B._OFFSETS if n not in sph_only)
     assert all(o % 256 == 0 for o in offs)

@@ -247,10 +247,11 @@ def test_work_counters(case):
     np.testing.assert_array_equal(plain["rast"].pixel_counts().cpu().numpy()[:, 0], cnt[:, 0])
 
 
-@pytest.mark.parametrize("tile,batch", [(8, 32), (8, 256), (32, 64), (32, 256)])
+@pytest.mark.parametrize("tile,batch", [(8, 32), (8, 256), (16, 32), (16, 256), (32, 64), (32, 256)])
 def test_other_tiles_forward_and_backward(tile, batch):
-    """The other compositor instances: one pixel per lane at 8x8 tiles, two pixels per lane with
-    shared LDS slots at 32x32 tiles, at the smallest and largest LDS batches."""
+    """The compositor instances at the smallest and largest LDS batches: one pixel per lane at 8x8
+    tiles, four pixels per lane in one wavefront at 16x16 tiles, two pixels per lane with shared
+    LDS slots at 32x32 tiles."""
     name, sc, cams, st = CASES[1]
     st = dict(st, tile=tile, batch=batch, batch_bwd=batch)
     fwd = O.render(sc, cams, st, mode=32)

@@ -4,6 +4,8 @@
   workgroups claiming tiles from that queue, one workgroup per tile in tile id order) composite the same tiles, so images are bit-identical
   and gradients agree to the order in which per-tile partial sums reach the FP64 accumulators.
 * The work queue is a permutation of the global tile ids in non-increasing list length.
+* Tiles with long lists are split into quadrant tasks by the queue schedules, with the same images
+  and (up to summation order) gradients.
 * The reverse compositor refuses a pair list the forward has not composited (a bin_sort between
   them), reporting it in the status record instead of reading stale culling masks.
 * Culled and non-finite items are counted.
@@ -15,7 +17,7 @@ from oracle import oracle as O
 from paper_2410_20686_amd import scenes
 from tests import _gpu as G
 from tests._util import settings
-from tests.test_gpu_parity import CASES, _masked_upstream
+from tests.test_gpu_parity import CASES, _masked_upstream, _views
 
 pytestmark = pytest.mark.gpu
 
@@ -63,6 +65,59 @@ def test_queue_is_longest_first_permutation():
     assert (later_max[1:] <= length[:-1] * (33.0 / 32.0)).all()
     ctr = rast.ws[p.off_queue:p.off_queue + 16].view(torch.int32).cpu().numpy()
     np.testing.assert_array_equal(ctr, 0)  # left cleared by the persistent forward
+
+
+def _long_list_case(opacity_scale):
+    """Two 128x64 views inside a shell of 16k Gaussians.  With the opacities scaled down (and so
+    the footprints) about half the 16x16 tiles have lists of 1024 pairs or more and most pixels
+    composite to the end of their lists; at full opacity every tile's list is that long and pixels
+    stop early."""
+    sc = scenes.sphere_scene(16000, 3, seed=87, r_range=(0.5, 1.5))
+    sc.opacities[:] = sc.opacities * opacity_scale
+    return sc, scenes.identity_cameras(128, 64, 2)
+
+
+@pytest.mark.parametrize("opacity_scale", [0.03, 1.0])
+def test_split_tiles(opacity_scale):
+    """Tiles whose lists reach 1024 pairs are composited as four single-quadrant tasks (forward and
+    reverse) under the queue schedules: images bit-identical to whole-tile compositing in tile id
+    order, 2D gradients and parameter gradients against the oracle."""
+    import torch
+    sc, cams = _long_list_case(opacity_scale)
+    st = settings(tile=16)
+    fwd = O.render(sc, cams, st, mode=32)
+    dL = _masked_upstream(cams, fwd["margin"], seed=1083)
+    runs = {s: G.run_gpu(sc, cams, dict(st, schedule=s), dL=dL, return_rast=True, split_bwd=True)
+            for s in ("queue", "persistent", "tile_id")}
+    for s, res in runs.items():
+        rast = res["rast"]
+        p = rast.plan
+        tiles = int(p.tile_base[cams.n_views])
+        r = rast.ws[p.off_ranges:p.off_ranges + 8 * tiles].view(torch.int32).cpu().numpy().reshape(tiles, 2)
+        hdr = rast.ws[p.off_queue:p.off_queue + 64].view(torch.int32).cpu().numpy()
+        long_lists = int(((r[:, 1] - r[:, 0]) >= 1024).sum())
+        assert 0 < long_lists <= tiles and (opacity_scale == 1.0 or long_lists < tiles)
+        assert hdr[4] == long_lists  # counted by binning (fewer than 1024 tiles: no cap)
+        assert hdr[5] == (0 if s == "tile_id" else long_lists)  # split by the forward
+    base = runs["tile_id"]
+    for s in ("queue", "persistent"):
+        np.testing.assert_array_equal(runs[s]["rgb"], base["rgb"])
+        np.testing.assert_array_equal(runs[s]["T"], base["T"])
+        # a quadrant task sums its entries' float contributions over 64 pixels, a whole tile over
+        # 256: the per-(entry, tile) partial sums round differently, so only the parity tolerance
+        # holds between the two
+        G.assert_grads_close(runs[s]["grads"], base["grads"])
+    res = runs["queue"]
+    ok = G.strict_pixels(fwd["margin"])
+    assert np.abs(res["T"] - fwd["T"])[ok].max() <= G.RGB_ATOL
+    okc = np.concatenate([np.tile(ok[o:o + w * h], 3) for o, w, h in _views(cams)])
+    assert np.abs(res["rgb"] - fwd["rgb"])[okc].max() <= G.RGB_ATOL
+    ref = O.backward(sc, cams, st, dL, mode=32, want_g2d=True)
+    ref2d = O.g2d_to_sigma(O.project(sc, cams, st), ref["g2d"])
+    labels = ("u", "v", "S_uu", "S_uv", "S_vv", "opacity", "r", "g", "b")
+    G.assert_grads_close({k: res["g2d"][..., j] for j, k in enumerate(labels)},
+                         {k: ref2d[..., j] for j, k in enumerate(labels)}, names=labels)
+    G.assert_grads_close(res["grads"], ref)
 
 
 def test_backward_refuses_a_stale_pair_list():
