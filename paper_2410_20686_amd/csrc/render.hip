@@ -439,8 +439,7 @@ struct FwdStage4 {
   float4 s0[BATCH];
   float4 s1[BATCH];
   float4 s2[BATCH];
-  uint8_t list[BATCH];
-  uint8_t msk[BATCH];
+  uint16_t list[BATCH];  // entry index | quadrant mask << 8
   uint8_t used[BATCH];
 };
 
@@ -493,16 +492,16 @@ __global__ __launch_bounds__(kWave) void render_fwd4_kernel(
           S.s2[e] = r.r2;
           S.used[e] = 0;
           m = quadrant_mask<TILE>(r, tx0, ty0, Wf, half, sel);
-          S.msk[e] = (uint8_t)m;
         }
         const uint64_t bl = __builtin_amdgcn_ballot_w64(m != 0u);
-        if (m != 0u) S.list[n + __popcll(bl & below)] = (uint8_t)e;
+        if (m != 0u) S.list[n + __popcll(bl & below)] = (uint16_t)(e | (m << 8));
         n += __popcll(bl);
       }
       __syncthreads();
-      for (int i = 0; i < n && alive != 0u; ++i) {
-        const int k = __builtin_amdgcn_readfirstlane(S.list[i]);
-        const uint32_t mq = __builtin_amdgcn_readfirstlane(S.msk[k]) & alive;
+      for (int i = 0; i < n; ++i) {
+        const uint32_t km = __builtin_amdgcn_readfirstlane(S.list[i]);
+        const int k = (int)(km & 0xFFu);
+        const uint32_t mq = (km >> 8) & alive;
         if (mq == 0u) continue;  // uniform
         const float4 a = S.s0[k];
         const float4 b = S.s1[k];
@@ -535,12 +534,14 @@ __global__ __launch_bounds__(kWave) void render_fwd4_kernel(
           C2[q] = fmaf(w, c.z, C2[q]);
           T[q] = acc ? Tn : T[q];
           last[q] = acc ? (int)(base - rg.x) + k + 1 : last[q];
-          if (__builtin_amdgcn_ballot_w64(ok != acc) != 0ull &&
-              __builtin_amdgcn_ballot_w64(qstop[q] == 0.0f) == 0ull)
-            alive &= ~(1u << q);  // uniform: every pixel of this quadrant has stopped
         }
         if (lane == 0 && used) S.used[k] = (uint8_t)used;
       }
+      // quadrants whose pixels have all stopped (taken once per batch: within a batch a stopped
+      // quadrant costs its test per entry, which no longer reaches any pixel)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (((alive >> q) & 1u) && __builtin_amdgcn_ballot_w64(qstop[q] == 0.0f) == 0ull) alive &= ~(1u << q);
       __syncthreads();
       // the backward's masks for this batch: the quadrants in which some pixel reached each entry
       for (int e = lane; e < cnt; e += kWave) qm[base + e] = S.used[e];
@@ -770,7 +771,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
                                                                 const float* __restrict__ dL_drgb, double* __restrict__ g2d,
                                                                 int64_t items, float bg0, float bg1, float bg2,
                                                                 const uint8_t* __restrict__ qmask, TileSched sc) {
-  static_assert(TILE == 8, "tiles of 16 and 32 take the two-pixel kernel (the stored masks are per two quadrants)");
+  static_assert(TILE == 8, "tiles of 16 and 32 take the four- and two-pixel kernels");
   using St = Stage<TILE, BATCH>;
   constexpr int N = St::N;
   // Up to four wavefronts per tile: each wavefront owns a slot per (value, entry) and the slots
@@ -902,8 +903,7 @@ struct Stage4 {
   float4 s1[BATCH];
   float4 s2[BATCH];
   uint32_t sid[BATCH];
-  uint8_t list[BATCH];
-  uint8_t msk[BATCH];
+  uint16_t list[BATCH];  // entry index | quadrant mask << 8
 };
 
 template <int BATCH>
@@ -973,21 +973,21 @@ __global__ __launch_bounds__(kWave) void render_bwd4_kernel(
           S.s2[e] = r.r2;
           S.sid[e] = item;
           m = qm[pos] & sel;
-          S.msk[e] = (uint8_t)m;
 #pragma unroll
           for (int q = 0; q < 9; ++q) acc[0][q][e] = 0.0f;
         }
         const uint64_t bl = __builtin_amdgcn_ballot_w64(m != 0u);
-        if (m != 0u) S.list[n + __popcll(bl & below)] = (uint8_t)e;
+        if (m != 0u) S.list[n + __popcll(bl & below)] = (uint16_t)(e | (m << 8));
         n += __popcll(bl);
       }
       __syncthreads();
       for (int i = 0; i < n; ++i) {
-        const int k = __builtin_amdgcn_readfirstlane(S.list[i]);
+        const uint32_t km = __builtin_amdgcn_readfirstlane(S.list[i]);
+        const int k = (int)(km & 0xFFu);
         const int jrel = end - 1 - k;
         const float4 a = S.s0[k];
         const float4 b = S.s1[k];
-        const uint32_t mq = __builtin_amdgcn_readfirstlane(S.msk[k]);
+        const uint32_t mq = km >> 8;
         const bool wrap = __builtin_amdgcn_readfirstlane(__float_as_int(b.w)) == 0;  // uniform
         float du0 = px0 - a.x, du1 = px1 - a.x;
         if (wrap) {
