@@ -318,12 +318,17 @@ __global__ __launch_bounds__(256) void item_offsets_kernel(const Rect* __restric
   }
 }
 
-// Pair-parallel emission: block b writes pairs [b * kEmitPairs, (b + 1) * kEmitPairs), four
-// consecutive pairs per thread, so stores are coalesced whatever the items' sizes.  The block
-// locates its items with one binary search over the item offsets, stages them in LDS, and each
-// thread finds the item of its first pair by a binary search in LDS.
+// Pair-parallel emission: block b writes the pairs of sort block b, [b * kSortBlockItems,
+// (b + 1) * kSortBlockItems), in rounds of kEmitPairs, four consecutive pairs per thread, so
+// stores are coalesced whatever the items' sizes.  Per round the block locates its items with one
+// search over the item offsets, stages them in LDS, and each thread finds the item of its first
+// pair by a binary search in LDS.  The block also counts the low tile digit of its pairs: the
+// histogram the tile sort's first pass needs (hist[digit * nblocks + b]), so that pass does not
+// read the keys once more to count them.
 constexpr int kEmitRun = 4;  // consecutive pairs per thread
 constexpr int kEmitPairs = 256 * kEmitRun;
+constexpr int kEmitRounds = kSortBlockItems / kEmitPairs;
+static_assert(kEmitRounds * kEmitPairs == kSortBlockItems, "whole rounds per sort block");
 
 // Last index in [0, n) with a[idx] <= x, for nondecreasing a with a[0] <= x, searched by one
 // whole wavefront: each round probes 64 evenly spaced entries of the interval at once and keeps
@@ -343,22 +348,12 @@ __device__ inline int64_t wave_last_le(const uint32_t* __restrict__ a, int64_t n
   return lo;
 }
 
-__global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restrict__ sorted_ids,
-                                                         const uint32_t* __restrict__ ioff,
-                                                         const Rect* __restrict__ srect,
-                                                         const odgs_status* __restrict__ status, int64_t items,
-                                                         int64_t n, ViewTable vt, int tile, uint32_t* __restrict__ pkey,
-                                                         uint32_t* __restrict__ pval) {
-  __shared__ uint32_t s_off[kEmitPairs + 1];
-  __shared__ uint32_t s_item[kEmitPairs + 1];
-  __shared__ Rect s_rect[kEmitPairs + 1];
-  __shared__ uint32_t s_tb[kEmitPairs + 1];
-  __shared__ uint16_t s_ntx[kEmitPairs + 1];
-  __shared__ int64_t s_range[2];
-  const uint32_t np = (uint32_t)status->n_pairs_stored;
-  const uint32_t p0 = blockIdx.x * (uint32_t)kEmitPairs;
-  if (p0 >= np) return;  // uniform
-  const uint32_t p1 = min(p0 + (uint32_t)kEmitPairs, np);
+// One round of emit_pairs_kernel: pairs [p0, p1), also counted into the wavefront's histogram.
+__device__ inline void emit_round(const uint32_t* __restrict__ sorted_ids, const uint32_t* __restrict__ ioff,
+                                  const Rect* __restrict__ srect, int64_t items, int64_t n, const ViewTable& vt,
+                                  int tile, uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, uint32_t p0,
+                                  uint32_t p1, uint32_t* s_off, uint32_t* s_item, Rect* s_rect, uint32_t* s_tb,
+                                  uint16_t* s_ntx, int64_t* s_range, uint32_t* hw) {
   // the first wavefront finds the item holding pair p0, the second the one holding pair p1 - 1
   const int wv = threadIdx.x >> 6;
   if (wv < 2) {
@@ -414,6 +409,9 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restr
       ++r;
     }
   }
+#pragma unroll
+  for (int j = 0; j < kEmitRun; ++j)
+    if (q + (uint32_t)j < p1) atomicAdd(&hw[key[j] & 255u], 1u);
   if (q + kEmitRun <= p1) {
     *reinterpret_cast<uint4*>(pkey + q) = make_uint4(key[0], key[1], key[2], key[3]);
     *reinterpret_cast<uint4*>(pval + q) = make_uint4(val[0], val[1], val[2], val[3]);
@@ -423,6 +421,39 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restr
       pval[q + j] = val[j];
     }
   }
+}
+
+__global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restrict__ sorted_ids,
+                                                         const uint32_t* __restrict__ ioff,
+                                                         const Rect* __restrict__ srect,
+                                                         const odgs_status* __restrict__ status, int64_t items,
+                                                         int64_t n, ViewTable vt, int tile, uint32_t* __restrict__ pkey,
+                                                         uint32_t* __restrict__ pval, uint32_t* __restrict__ hist,
+                                                         int nblocks) {
+  __shared__ uint32_t s_off[kEmitPairs + 1];
+  __shared__ uint32_t s_item[kEmitPairs + 1];
+  __shared__ Rect s_rect[kEmitPairs + 1];
+  __shared__ uint32_t s_tb[kEmitPairs + 1];
+  __shared__ uint16_t s_ntx[kEmitPairs + 1];
+  __shared__ int64_t s_range[2];
+  __shared__ uint32_t h[kSortThreads / kWave][256];  // per-wavefront digit counts
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int w = 0; w < kSortThreads / kWave; ++w) h[w][t] = 0;
+  const uint32_t np = (uint32_t)status->n_pairs_stored;
+  const uint32_t b0 = blockIdx.x * (uint32_t)kSortBlockItems;
+  for (int round = 0; round < kEmitRounds; ++round) {
+    const uint32_t p0 = b0 + (uint32_t)(round * kEmitPairs);
+    if (p0 >= np) break;  // uniform
+    __syncthreads();  // the previous round's staging has been read
+    emit_round(sorted_ids, ioff, srect, items, n, vt, tile, pkey, pval, p0, min(p0 + (uint32_t)kEmitPairs, np),
+               s_off, s_item, s_rect, s_tb, s_ntx, s_range, h[t >> 6]);
+  }
+  __syncthreads();
+  uint32_t c = 0;
+#pragma unroll
+  for (int w = 0; w < kSortThreads / kWave; ++w) c += h[w][t];
+  hist[t * nblocks + blockIdx.x] = c;  // every (digit, block) entry, zero past the pairs
 }
 
 // Tile ranges from the sorted keys: each thread scans eight consecutive keys (two 16-byte loads
@@ -559,16 +590,18 @@ __global__ void status_reset_kernel(odgs_status* st) {
   }
 }
 
+// first_hist: the first pass's histogram is already in `hist` (written by the producer of the keys).
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, bool identity_vals,
                       const uint32_t* n_dev, uint32_t n_host, int bits, int nblocks, uint32_t* hist,
-                      uint32_t* digit_tot, hipStream_t st) {
+                      uint32_t* digit_tot, hipStream_t st, bool first_hist = false) {
   uint32_t* kb[2] = {k0, k1};
   uint32_t* vb[2] = {v0, v1};
   int cur = 0;
   for (int shift = 0; shift < bits; shift += 8) {
     const uint32_t* vin = (shift == 0 && identity_vals) ? nullptr : vb[cur];
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(nblocks), dim3(kSortThreads), 0, st, kb[cur], n_dev, n_host, shift,
-                       hist, nblocks);
+    if (shift > 0 || !first_hist)
+      hipLaunchKernelGGL(radix_hist_kernel, dim3(nblocks), dim3(kSortThreads), 0, st, kb[cur], n_dev, n_host, shift,
+                         hist, nblocks);
     hipLaunchKernelGGL(radix_digit_scan_kernel, dim3(256), dim3(256), 0, st, hist, nblocks, digit_tot);
     hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblocks), dim3(kSortThreads), 0, st, kb[cur], vin, kb[cur ^ 1],
                        vb[cur ^ 1], n_dev, n_host, shift, hist, digit_tot, nblocks);
@@ -648,12 +681,12 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
   uint32_t* ioff = dk[p->depth_final ^ 1];
   hipLaunchKernelGGL(item_offsets_kernel, dim3(sblocks), dim3(256), 0, st, srect, boff, items, p->pair_capacity,
                      ioff);
-  hipLaunchKernelGGL(emit_pairs_kernel, dim3((unsigned)((p->pair_capacity + kEmitPairs - 1) / kEmitPairs)), dim3(256),
-                     0, st, sorted_ids, ioff, srect, status, items, p->n, vt, p->s.tile, pk[0],
-                     pv[0]);
-  // 4. stable sort of the pairs by global tile
+  if (p->pair_blocks > 0)
+    hipLaunchKernelGGL(emit_pairs_kernel, dim3((unsigned)p->pair_blocks), dim3(kSortThreads), 0, st, sorted_ids, ioff,
+                       srect, status, items, p->n, vt, p->s.tile, pk[0], pv[0], hist, p->pair_blocks);
+  // 4. stable sort of the pairs by global tile (the first pass's histogram counted by the emission)
   e = radix_sort(pk[0], pv[0], pk[1], pv[1], false, n_dev, (uint32_t)p->pair_capacity, p->tile_bits, p->pair_blocks,
-                 hist, digit, st);
+                 hist, digit, st, true);
   if (e != hipSuccess) return e;
   // 5. tile ranges
   hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((p->pair_capacity + 256 * kRangeKeys - 1) / (256 * kRangeKeys))),
