@@ -353,14 +353,8 @@ __device__ inline void emit_round(const uint32_t* __restrict__ sorted_ids, const
                                   const Rect* __restrict__ srect, int64_t items, int64_t n, const ViewTable& vt,
                                   int tile, uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, uint32_t p0,
                                   uint32_t p1, uint32_t* s_off, uint32_t* s_item, Rect* s_rect, uint32_t* s_tb,
-                                  uint16_t* s_ntx, int64_t* s_range, uint32_t* hw) {
-  // the first wavefront finds the item holding pair p0, the second the one holding pair p1 - 1
-  const int wv = threadIdx.x >> 6;
-  if (wv < 2) {
-    const int64_t it = wave_last_le(ioff, items, wv == 0 ? p0 : p1 - 1);
-    if ((threadIdx.x & (kWave - 1)) == 0) s_range[wv] = it;
-  }
-  __syncthreads();
+                                  uint16_t* s_ntx, const int64_t* s_range, uint32_t* hw) {
+  // s_range: the items holding pairs p0 and p1 - 1
   const int64_t i0 = s_range[0];
   const int m = (int)(s_range[1] - i0 + 1);  // <= kEmitPairs: every listed item owns >= 1 pair here
   for (int t = threadIdx.x; t < m; t += 256) {
@@ -435,19 +429,35 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restr
   __shared__ Rect s_rect[kEmitPairs + 1];
   __shared__ uint32_t s_tb[kEmitPairs + 1];
   __shared__ uint16_t s_ntx[kEmitPairs + 1];
-  __shared__ int64_t s_range[2];
+  __shared__ int64_t s_range[kEmitRounds][2];
   __shared__ uint32_t h[kSortThreads / kWave][256];  // per-wavefront digit counts
   const int t = threadIdx.x;
 #pragma unroll
   for (int w = 0; w < kSortThreads / kWave; ++w) h[w][t] = 0;
   const uint32_t np = (uint32_t)status->n_pairs_stored;
   const uint32_t b0 = blockIdx.x * (uint32_t)kSortBlockItems;
+  {
+    // wavefront w finds the items holding the first and last pair of round w (all rounds' searches
+    // at once: their dependent loads overlap)
+    static_assert(kEmitRounds == kSortThreads / kWave, "one wavefront per round");
+    const int w = t >> 6;
+    const uint32_t p0 = b0 + (uint32_t)(w * kEmitPairs);
+    if (p0 < np) {
+      const uint32_t p1 = min(p0 + (uint32_t)kEmitPairs, np);
+      const int64_t first = wave_last_le(ioff, items, p0);
+      const int64_t last = wave_last_le(ioff, items, p1 - 1);
+      if ((t & (kWave - 1)) == 0) {
+        s_range[w][0] = first;
+        s_range[w][1] = last;
+      }
+    }
+  }
   for (int round = 0; round < kEmitRounds; ++round) {
     const uint32_t p0 = b0 + (uint32_t)(round * kEmitPairs);
     if (p0 >= np) break;  // uniform
-    __syncthreads();  // the previous round's staging has been read
+    __syncthreads();  // the searches are done, the previous round's staging has been read
     emit_round(sorted_ids, ioff, srect, items, n, vt, tile, pkey, pval, p0, min(p0 + (uint32_t)kEmitPairs, np),
-               s_off, s_item, s_rect, s_tb, s_ntx, s_range, h[t >> 6]);
+               s_off, s_item, s_rect, s_tb, s_ntx, s_range[round], h[t >> 6]);
   }
   __syncthreads();
   uint32_t c = 0;
