@@ -1,8 +1,9 @@
 // Compositing kernels of the spherical footprint (ODGS_FLAG_SPHERICAL), gfx950.
 //
-// Same structure as the affine compositors: one workgroup per (view, tile), one thread per
-// pixel, every 64-wide wavefront owns an 8x8 quadrant, the tile's depth-ordered list is staged
-// through LDS in batches.  What changes is the evaluation: each pixel carries the unit direction
+// Same structure as the affine compositors: at 16x16 tiles one wavefront per tile (or per
+// quadrant of a split tile) with four pixels per lane; at 8x8 and 32x32 one workgroup per (view,
+// tile), one thread per pixel, every 64-wide wavefront owning an 8x8 quadrant; the tile's
+// depth-ordered list is staged through LDS in batches.  What changes is the evaluation: each pixel carries the unit direction
 // d of its ray (from the per-view ray table, rounded once to float), and a Gaussian's exponent is
 // -qh / D with t1 = u1 . d, t2 = u2 . d, h = w . d, qh = t1^2 + t2^2, D = h^2 + k2 qh (the maximum
 // of the 3D Gaussian along the ray, see SphRec); it reaches the pixel iff h > 0 and
@@ -13,9 +14,9 @@
 // the masks per list position; the backward loads them.
 //
 // Backward: per accepted (Gaussian, wavefront) the 13 gradient values (mu^ (3), Sigma~ (6),
-// opacity, rgb) are summed over each 16-lane row by a DPP butterfly and over rows by the
-// row-swap permutes, kept per wavefront in LDS, and flushed with one double atomic per (Gaussian,
-// tile, value) to contiguous 104-byte records.
+// opacity, rgb), summed first over a lane's pixels, are summed over each 16-lane row by a DPP
+// butterfly and over rows by the row-swap permutes, kept per wavefront in LDS, and flushed with one
+// double atomic per (Gaussian, tile or task, value) to contiguous 104-byte records.
 #include "common.h"
 #include "wave.h"
 
@@ -72,6 +73,43 @@ __device__ inline void sph_stage_init(SphStage<TILE, BATCH>& S, const double2* _
   __syncthreads();
 }
 
+// Quadrants of a tile (centre rays qdir[NQ]) that the item's culling data admits, among those in
+// `sel` (uniform).  A quadrant is kept unless the angle between its centre ray and mu^ exceeds
+// the cone half-angle beta plus the quadrant's angular radius qrad, or the disk that holds the
+// gnomonic images of the quadrant's rays misses the item's gnomonic ellipse.
+template <int NQ>
+__device__ inline uint32_t sph_quadrant_mask(const SphCull& cu, const float3* qdir, float qrad, uint32_t sel = ~0u) {
+  const float4 c = cu.c0;
+  // cone: hit iff angle(quadrant centre, mu^) <= beta + qrad; the 1e-5 slack covers the float
+  // rounding of the dot product and of the cosine
+  const float lim = c.w + qrad >= 3.14159f ? -2.0f : cosf(c.w + qrad) - 1e-5f;
+  const float cq = cosf(qrad), sq = sinf(qrad);
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (!((sel >> q) & 1u)) continue;
+    const float3 d = qdir[q];
+    const float sd = fmaf(d.z, c.z, fmaf(d.y, c.y, d.x * c.x));  // cos of the centre's angle to mu^
+    bool hit = sd >= lim;
+    // ellipse: every ray of the quadrant is within qrad of the centre ray, hence at most
+    // gamma_max = gamma_c + qrad from mu^, and the gnomonic map stretches distances by at most
+    // sec^2(gamma_max) there: the images lie within r_q = qrad sec^2(gamma_max) of the
+    // centre's image p_c.  The quadrant is kept iff that disk can meet the ellipse:
+    // (p_c - p0)^T M (p_c - p0) <= (rho + sqrt(lambda_max) r_q)^2 (1e-3 relative slack).
+    const float cmax = fmaf(sd, cq, -sqrtf(fmaxf(0.0f, fmaf(-sd, sd, 1.0f))) * sq);  // cos(gamma_max)
+    if (hit && cu.c3.z > 0.0f && cmax > 0.05f) {
+      const float inv = 1.0f / sd;
+      const float px = fmaf(d.z, cu.c1.y, d.x * cu.c1.x) * inv - cu.c2.y;
+      const float py = fmaf(d.z, cu.c2.x, fmaf(d.y, cu.c1.w, d.x * cu.c1.z)) * inv - cu.c2.z;
+      const float qv = fmaf(cu.c2.w * px, px, py * fmaf(2.0f * cu.c3.x, px, cu.c3.y * py));
+      const float rr = fmaf(cu.c3.w, qrad / (cmax * cmax), cu.c3.z);
+      hit = qv <= rr * rr * 1.001f + 1e-6f;
+    }
+    m |= hit ? (1u << q) : 0u;
+  }
+  return m;
+}
+
 // How the quadrant masks are obtained: evaluated (the forward, which after walking each batch
 // stores per list position the quadrants its pixels reached, into the pair buffer the sort leaves
 // unused), or loaded from there (the backward, which visits only list positions before its tile's
@@ -108,33 +146,7 @@ __device__ inline void sph_stage_batch(SphStage<TILE, BATCH>& S, const uint32_t*
       if constexpr (QM == kSphMaskLoad) {
         m = qmask_in[pos];
       } else {
-        const SphCull cu = cull[item];
-        const float4 c = cu.c0;
-        // cone: hit iff angle(quadrant centre, mu^) <= beta + qrad; the 1e-5 slack covers the float
-        // rounding of the dot product and of the cosine
-        const float lim = c.w + qrad >= 3.14159f ? -2.0f : cosf(c.w + qrad) - 1e-5f;
-        const float cq = cosf(qrad), sq = sinf(qrad);
-#pragma unroll
-        for (int q = 0; q < St::NQ; ++q) {
-          const float3 d = S.qdir[q];
-          const float sd = fmaf(d.z, c.z, fmaf(d.y, c.y, d.x * c.x));  // cos of the centre's angle to mu^
-          bool hit = sd >= lim;
-          // ellipse: every ray of the quadrant is within qrad of the centre ray, hence at most
-          // gamma_max = gamma_c + qrad from mu^, and the gnomonic map stretches distances by at most
-          // sec^2(gamma_max) there: the images lie within r_q = qrad sec^2(gamma_max) of the
-          // centre's image p_c.  The quadrant is kept iff that disk can meet the ellipse:
-          // (p_c - p0)^T M (p_c - p0) <= (rho + sqrt(lambda_max) r_q)^2 (1e-3 relative slack).
-          const float cmax = fmaf(sd, cq, -sqrtf(fmaxf(0.0f, fmaf(-sd, sd, 1.0f))) * sq);  // cos(gamma_max)
-          if (hit && cu.c3.z > 0.0f && cmax > 0.05f) {
-            const float inv = 1.0f / sd;
-            const float px = fmaf(d.z, cu.c1.y, d.x * cu.c1.x) * inv - cu.c2.y;
-            const float py = fmaf(d.z, cu.c2.x, fmaf(d.y, cu.c1.w, d.x * cu.c1.z)) * inv - cu.c2.z;
-            const float qv = fmaf(cu.c2.w * px, px, py * fmaf(2.0f * cu.c3.x, px, cu.c3.y * py));
-            const float rr = fmaf(cu.c3.w, qrad / (cmax * cmax), cu.c3.z);
-            hit = qv <= rr * rr * 1.001f + 1e-6f;
-          }
-          m |= hit ? (1u << q) : 0u;
-        }
+        m = sph_quadrant_mask<St::NQ>(cull[item], S.qdir, qrad);
       }
     }
     uint32_t within[St::NQ];
@@ -357,11 +369,9 @@ __device__ inline double sph_flush_value(const float (&acc)[NS][kNV][B], int q, 
   return (i == j ? 2.0 : 4.0) * nyn;  // the shared off-diagonal takes both symmetric entries
 }
 
-// At tile 16 the flush's double arithmetic would otherwise set the register budget (91 VGPRs, five
-// wavefronts per SIMD); asking for six keeps the loop's allocation (72, no spills).
+// One pixel per lane (tiles of 8 and 32).
 template <int TILE, int BATCH>
-__global__ __launch_bounds__(TILE* TILE) __attribute__((amdgpu_waves_per_eu(TILE == 16 && BATCH <= 64 ? 6 : 1)))
-void render_sph_bwd_kernel(
+__global__ __launch_bounds__(TILE* TILE) void render_sph_bwd_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items,
     const SphRec* __restrict__ rec, const SphCull* __restrict__ cull, const double2* __restrict__ dirs,
     const float* __restrict__ ws_T, const int32_t* __restrict__ ws_last, const float* __restrict__ dL_drgb,
@@ -479,13 +489,325 @@ void render_sph_bwd_kernel(
   }
 }
 
+// One-wavefront compositing of a 16x16 tile, four pixels per lane (lane l holds pixel (l % 8, l / 8)
+// of each 8x8 quadrant q = 2 qy + qx), as in the affine compositors: the list is staged once per
+// batch with each entry's quadrant mask (one 16-bit LDS word, entry | mask << 8), an entry is
+// evaluated only for the quadrants in its mask, and the reverse compositor reduces the four
+// pixels' 13 gradient values across lanes once per entry.  A task is a whole tile or one quadrant
+// of a split tile (TileSched); the culling masks handed from the forward to the backward are one
+// byte per list position, in the byte plane of the task's quadrant (plane q at byte offset
+// q * qplane; whole tiles use plane 0).
+template <int BATCH, bool DEPTH>
+struct SphFwdStage4 {
+  float4 s0[BATCH];
+  float4 s1[BATCH];
+  float4 s2[BATCH];
+  float4 s3[BATCH];
+  float dep[DEPTH ? BATCH : 1];
+  uint16_t list[BATCH];
+  uint8_t used[BATCH];
+  float3 qdir[4];
+};
+
+template <int BATCH, bool DEPTH>
+__global__ __launch_bounds__(kWave) void render_sph_fwd4_kernel(
+    ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items,
+    const SphRec* __restrict__ rec, const SphCull* __restrict__ cull, const double2* __restrict__ dirs,
+    float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
+    float bg0, float bg1, float bg2, const float* __restrict__ depth, float* __restrict__ out_depth,
+    uint8_t* __restrict__ qmask, int64_t qplane, TileSched sc) {
+  constexpr int TILE = 16;
+  __shared__ SphFwdStage4<BATCH, DEPTH> S;
+  const int nsplit = forward_split(sc);
+  mark_forward(sc, nsplit);
+  __shared__ uint32_t s_claim;
+  uint32_t round = 0, sel = 0;
+  const int lane = threadIdx.x;
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+  for (int g; (g = claim_task(sc, nsplit, round, &s_claim, sel)) >= 0;) {
+    const int v = view_of_tile(vt, g);
+    const int W = vt.W[v], H = vt.H[v];
+    const int ntx = W / TILE;
+    const int lt = g - vt.tile_base[v];
+    const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+    const int x = tx0 + (lane & 7), y = ty0 + (lane >> 3);
+    float3 d[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d[q] = pixel_ray(dirs, vt, v, x + 8 * (q & 1), y + 8 * (q >> 1));
+    const float qrad = quadrant_radius(W, H);
+    if (lane < 4) S.qdir[lane] = pixel_ray(dirs, vt, v, tx0 + (lane & 1) * 8 + 4, ty0 + (lane >> 1) * 8 + 4);
+    __syncthreads();
+    const uint2 rg = ranges[g];
+    float T[4], C0[4], C1[4], C2[4], Ds[4];
+    int last[4], done[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T[q] = 1.0f;
+      C0[q] = C1[q] = C2[q] = Ds[q] = 0.0f;
+      last[q] = 0;
+      done[q] = 0;
+    }
+    uint32_t alive = sel;  // selected quadrants with a pixel still compositing (uniform)
+    uint8_t* qm = qmask + (sel == 0xFu ? 0 : (int64_t)__builtin_ctz(sel) * qplane);
+    for (uint32_t base = rg.x; base < rg.y && alive != 0u; base += BATCH) {
+      const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
+      int n = 0;
+      for (int r0 = 0; r0 < cnt; r0 += kWave) {
+        const int e = r0 + lane;
+        uint32_t m = 0;
+        if (e < cnt) {
+          const uint32_t item = pair_items[base + e];
+          const SphRec r = rec[item];
+          S.s0[e] = r.s0;
+          S.s1[e] = r.s1;
+          S.s2[e] = r.s2;
+          S.s3[e] = r.s3;
+          if constexpr (DEPTH) S.dep[e] = depth[item];
+          S.used[e] = 0;
+          m = sph_quadrant_mask<4>(cull[item], S.qdir, qrad, sel);
+        }
+        const uint64_t bl = __builtin_amdgcn_ballot_w64(m != 0u);
+        if (m != 0u) S.list[n + __popcll(bl & below)] = (uint16_t)(e | (m << 8));
+        n += __popcll(bl);
+      }
+      __syncthreads();
+      for (int i = 0; i < n; ++i) {
+        const uint32_t km = __builtin_amdgcn_readfirstlane(S.list[i]);
+        const int k = (int)(km & 0xFFu);
+        const uint32_t mq = (km >> 8) & alive;
+        if (mq == 0u) continue;  // uniform
+        const float4 a = S.s0[k], b = S.s1[k], c = S.s2[k];
+        uint32_t used = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (!((mq >> q) & 1u)) continue;  // uniform
+          float power, t1, t2, h, D, qh;
+          const bool hit = sph_eval(a, b, c, d[q], power, t1, t2, h, D, qh);
+          const bool ok = done[q] == 0 && hit;
+          if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
+          used |= 1u << q;  // reached here (accepted unless that pixel stops at it: a superset)
+          const float alpha = fminf(c.z * __expf(power), kAlphaMax);
+          const float Tn = T[q] * (1.0f - alpha);
+          const bool acc = ok && !(Tn < kTStop);
+          done[q] = ok != acc ? 1 : done[q];  // stop: reached, but T would drop below 1e-4
+          const float4 col = S.s3[k];
+          const float w = acc ? alpha * T[q] : 0.0f;
+          C0[q] = fmaf(w, col.x, C0[q]);
+          C1[q] = fmaf(w, col.y, C1[q]);
+          C2[q] = fmaf(w, col.z, C2[q]);
+          if constexpr (DEPTH) Ds[q] = Ds[q] + w * S.dep[k];
+          T[q] = acc ? Tn : T[q];
+          last[q] = acc ? (int)(base - rg.x) + k + 1 : last[q];
+        }
+        if (lane == 0 && used) S.used[k] = (uint8_t)used;
+      }
+      // quadrants whose pixels have all stopped, taken once per batch
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (((alive >> q) & 1u) && __builtin_amdgcn_ballot_w64(done[q] == 0) == 0ull) alive &= ~(1u << q);
+      __syncthreads();
+      for (int e = lane; e < cnt; e += kWave) qm[base + e] = S.used[e];
+      __syncthreads();
+    }
+    // list positions past the point where every pixel stopped keep no mask: the backward, which
+    // stops at each quadrant's last contributor, never reads them
+    const int64_t plane = (int64_t)W * H;
+    float* img = out_rgb + 3 * vt.pix_base[v];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!((sel >> q) & 1u)) continue;
+      const int64_t pix = (int64_t)(y + 8 * (q >> 1)) * W + x + 8 * (q & 1);
+      img[pix] = fmaf(T[q], bg0, C0[q]);
+      img[plane + pix] = fmaf(T[q], bg1, C1[q]);
+      img[2 * plane + pix] = fmaf(T[q], bg2, C2[q]);
+      const int64_t gp = vt.pix_base[v] + pix;
+      ws_T[gp] = T[q];
+      ws_last[gp] = last[q];
+      if constexpr (DEPTH) out_depth[gp] = Ds[q];
+      if (out_T) out_T[gp] = T[q];
+    }
+  }
+}
+
+template <int BATCH>
+struct SphBwdStage4 {
+  float4 s0[BATCH];
+  float4 s1[BATCH];
+  float4 s2[BATCH];
+  float4 s3[BATCH];
+  uint32_t sid[BATCH];
+  uint16_t list[BATCH];
+};
+
+template <int BATCH>
+__global__ __launch_bounds__(kWave) void render_sph_bwd4_kernel(
+    ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items,
+    const SphRec* __restrict__ rec, const double2* __restrict__ dirs, const float* __restrict__ ws_T,
+    const int32_t* __restrict__ ws_last, const float* __restrict__ dL_drgb, double* __restrict__ g2d, float bg0,
+    float bg1, float bg2, const uint8_t* __restrict__ qmask, int64_t qplane, TileSched sc) {
+  constexpr int TILE = 16;
+  __shared__ SphBwdStage4<BATCH> S;
+  __shared__ float acc[1][kNV][BATCH + 1];
+  if (forward_is_stale(sc)) return;  // uniform
+  const int nsplit = reverse_split(sc);
+  __shared__ uint32_t s_claim;
+  uint32_t round = 0, sel = 0;
+  const int lane = threadIdx.x;
+  const int slot = (int)((kSphRowSlot >> (4 * (lane & 15))) & 0xF);
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+  for (int g; (g = claim_task(sc, nsplit, round, &s_claim, sel)) >= 0;) {
+    const int v = view_of_tile(vt, g);
+    const int W = vt.W[v], H = vt.H[v];
+    const int ntx = W / TILE;
+    const int lt = g - vt.tile_base[v];
+    const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+    const int x = tx0 + (lane & 7), y = ty0 + (lane >> 3);
+    const uint2 rg = ranges[g];
+    const int64_t plane = (int64_t)W * H;
+    const float* dimg = dL_drgb + 3 * vt.pix_base[v];
+    float3 d[4];
+    float dl0[4], dl1[4], dl2[4], T[4], DS[4];
+    int last[4], qmax[4];  // qmax: the quadrant's last contributor over its pixels (uniform)
+    int wmax = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!((sel >> q) & 1u)) {
+        last[q] = 0;  // not this task's: never reached, its other members never read
+        qmax[q] = 0;
+        continue;
+      }
+      const int px = x + 8 * (q & 1), py = y + 8 * (q >> 1);
+      const int64_t pix = (int64_t)py * W + px;
+      const int64_t gp = vt.pix_base[v] + pix;
+      d[q] = pixel_ray(dirs, vt, v, px, py);
+      dl0[q] = dimg[pix], dl1[q] = dimg[plane + pix], dl2[q] = dimg[2 * plane + pix];
+      T[q] = ws_T[gp];
+      last[q] = ws_last[gp];
+      // dL/dC . (colour of everything behind, incl. background), one scalar for the three channels
+      DS[q] = T[q] * fmaf(dl0[q], bg0, fmaf(dl1[q], bg1, dl2[q] * bg2));
+      int m = last[q];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+      qmax[q] = __builtin_amdgcn_readfirstlane(m);
+      wmax = max(wmax, qmax[q]);
+    }
+    const uint8_t* qm = qmask + (sel == 0xFu ? 0 : (int64_t)__builtin_ctz(sel) * qplane);
+    for (int end = wmax; end > 0; end -= BATCH) {
+      const int cnt = min(BATCH, end);
+      // stage entries end - 1 - e (back to front) with the forward's masks; list those reaching
+      // any selected quadrant, in order
+      int n = 0;
+      for (int r0 = 0; r0 < cnt; r0 += kWave) {
+        const int e = r0 + lane;
+        uint32_t m = 0;
+        if (e < cnt) {
+          const uint32_t pos = rg.x + end - 1 - e;
+          const uint32_t item = pair_items[pos];
+          const SphRec r = rec[item];
+          S.s0[e] = r.s0;
+          S.s1[e] = r.s1;
+          S.s2[e] = r.s2;
+          S.s3[e] = r.s3;
+          S.sid[e] = item;
+          m = qm[pos] & sel;
+#pragma unroll
+          for (int j = 0; j < kNV; ++j) acc[0][j][e] = 0.0f;
+        }
+        const uint64_t bl = __builtin_amdgcn_ballot_w64(m != 0u);
+        if (m != 0u) S.list[n + __popcll(bl & below)] = (uint16_t)(e | (m << 8));
+        n += __popcll(bl);
+      }
+      __syncthreads();
+      for (int i = 0; i < n; ++i) {
+        const uint32_t km = __builtin_amdgcn_readfirstlane(S.list[i]);
+        const int k = (int)(km & 0xFFu);
+        const int jrel = end - 1 - k;
+        const uint32_t mq = km >> 8;
+        const float4 a = S.s0[k], b = S.s1[k], c = S.s2[k];
+        const float4 col = S.s3[k];
+        float gv[kNV];
+#pragma unroll
+        for (int j = 0; j < kNV; ++j) gv[j] = 0.0f;
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (!((mq >> q) & 1u) || jrel >= qmax[q]) continue;  // uniform
+          float power, t1, t2, h, D, qh;
+          // evaluated on every lane (no short circuit): the gradient terms below are formed on
+          // all lanes and zeroed by selects, which needs finite operands
+          const bool hit = sph_eval(a, b, c, d[q], power, t1, t2, h, D, qh);
+          const bool ok = jrel < last[q] && hit;
+          if (__builtin_amdgcn_ballot_w64(ok) == 0ull) continue;  // uniform
+          any = true;
+          const float G = __expf(power);
+          const float araw = c.z * G;
+          const bool live = ok && !(araw > kAlphaMax);  // contributes and unclamped
+          // alpha = 0 where the Gaussian does not contribute, so its weight below is 0 without a select
+          const float alpha = ok ? fminf(araw, kAlphaMax) : 0.0f;
+          const float inv_om = __builtin_amdgcn_rcpf(1.0f - alpha);
+          T[q] = T[q] * inv_om;  // transmittance in front of this Gaussian (alpha = 0: times exactly 1)
+          const float wk = alpha * T[q];
+          const float dc = fmaf(dl0[q], col.x, fmaf(dl1[q], col.y, dl2[q] * col.z));  // dL/dC . colour
+          const float dL_da = fmaf(dc, T[q], -DS[q] * inv_om);
+          DS[q] = fmaf(dc, wk, DS[q]);
+          const float dla = live ? dL_da : 0.0f;
+          const float dpow = dla * alpha;
+          // whitened offset y = (h t1, h t2, qh) / D, zero on lanes that do not contribute
+          const float s1 = live ? __builtin_amdgcn_rcpf(D) : 0.0f;
+          const float y1 = s1 * (h * t1), y2 = s1 * (h * t2), y3 = s1 * qh;
+          const float gx = dpow * y1, gy = dpow * y2, gz = dpow * y3;
+          gv[0] += gx;
+          gv[1] += gy;
+          gv[2] += gz;
+          gv[3] = fmaf(gx, y1, gv[3]);
+          gv[4] = fmaf(gx, y2, gv[4]);
+          gv[5] = fmaf(gx, y3, gv[5]);
+          gv[6] = fmaf(gy, y2, gv[6]);
+          gv[7] = fmaf(gy, y3, gv[7]);
+          gv[8] = fmaf(gz, y3, gv[8]);
+          gv[9] = fmaf(dla, G, gv[9]);
+          gv[10] = fmaf(wk, dl0[q], gv[10]);
+          gv[11] = fmaf(wk, dl1[q], gv[11]);
+          gv[12] = fmaf(wk, dl2[q], gv[12]);
+        }
+        if (!any) continue;  // uniform
+        const float rs = row_reduce13(gv, lane);
+        const float ws = sum_rows(rs);
+        if (lane < 16 && slot < kNV) acc[0][slot][k] = ws;
+      }
+      __syncthreads();
+      // thirteen consecutive lanes carry one entry's values: contiguous 104-byte records
+#pragma unroll 1
+      for (int xx = lane; xx < kNV * cnt; xx += kWave) {
+        const int t = xx / kNV, q = xx - kNV * t;
+        const double s = sph_flush_value(acc, q, t, S.s0[t], S.s1[t], S.s2[t]);
+        if (s != 0.0) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * kNV + q], s);
+      }
+      __syncthreads();
+    }
+  }
+}
+
 template <int TILE, int BATCH>
 struct SphFwdRun {
   static void run(const odgs_plan* p, const TileSched& sc, const ViewTable& vt, const uint2* ranges,
                   const uint32_t* items, const SphRec* rec, const SphCull* cone, const double2* dirs, float* out_rgb,
-                  float* out_T, float* wT, int32_t* wl, const float* depth, float* out_depth, uint16_t* qmask,
+                  float* out_T, float* wT, int32_t* wl, const float* depth, float* out_depth, void* qmask_buf,
                   hipStream_t st) {
-    if (out_depth)
+    // masks: bytes in per-quadrant planes at 16x16 (four pixels per lane), 16 bits per position
+    // otherwise
+    uint16_t* qmask = static_cast<uint16_t*>(qmask_buf);
+    uint8_t* qmask8 = static_cast<uint8_t*>(qmask_buf);
+    const int64_t qplane = p->pair_capacity;
+    if constexpr (TILE == 16) {
+      if (out_depth)
+        launch_sched(render_sph_fwd4_kernel<BATCH, true>, with_split(sc), kWave, st, vt, ranges, items, rec, cone, dirs,
+                     out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], depth, out_depth, qmask8, qplane);
+      else
+        launch_sched(render_sph_fwd4_kernel<BATCH, false>, with_split(sc), kWave, st, vt, ranges, items, rec, cone,
+                     dirs, out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], depth, out_depth, qmask8,
+                     qplane);
+    } else if (out_depth)
       launch_sched(render_sph_fwd_kernel<TILE, BATCH, true>, sc, TILE * TILE, st, vt, ranges, items, rec, cone, dirs,
                    out_rgb, out_T, wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], depth, out_depth, qmask);
     else
@@ -498,9 +820,14 @@ template <int TILE, int BATCH>
 struct SphBwdRun {
   static void run(const odgs_plan* p, const TileSched& sc, const ViewTable& vt, const uint2* ranges,
                   const uint32_t* items, const SphRec* rec, const SphCull* cone, const double2* dirs, const float* wT,
-                  const int32_t* wl, const float* dL, double* g2d, const uint16_t* qmask, hipStream_t st) {
-    launch_sched(render_sph_bwd_kernel<TILE, BATCH>, sc, TILE * TILE, st, vt, ranges, items, rec, cone, dirs, wT, wl, dL,
-                 g2d, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
+                  const int32_t* wl, const float* dL, double* g2d, const void* qmask_buf, hipStream_t st) {
+    if constexpr (TILE == 16)
+      launch_sched(render_sph_bwd4_kernel<BATCH>, with_split(sc), kWave, st, vt, ranges, items, rec, dirs, wT, wl, dL,
+                   g2d, p->s.bg[0], p->s.bg[1], p->s.bg[2], static_cast<const uint8_t*>(qmask_buf),
+                   (int64_t)p->pair_capacity);
+    else
+      launch_sched(render_sph_bwd_kernel<TILE, BATCH>, sc, TILE * TILE, st, vt, ranges, items, rec, cone, dirs, wT, wl,
+                   dL, g2d, p->s.bg[0], p->s.bg[1], p->s.bg[2], static_cast<const uint16_t*>(qmask_buf));
   }
 };
 
@@ -530,7 +857,7 @@ hipError_t launch_render_sph_fwd(const odgs_plan* p, void* ws, float* out_rgb, f
                                ws_ptr<SphCull>(ws, p->off_cone), ws_ptr<double2>(ws, p->off_dirs), out_rgb, out_T,
                                ws_ptr<float>(ws, p->off_T), ws_ptr<int32_t>(ws, p->off_last),
                                ws_ptr<float>(ws, p->off_depth), out_depth,
-                               ws_ptr<uint16_t>(ws, p->off_pval[p->pair_final ^ 1]), st))  // masks: unused pair buffer
+                               ws_ptr<void>(ws, p->off_pval[p->pair_final ^ 1]), st))  // masks: unused pair buffer
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -544,7 +871,7 @@ hipError_t launch_render_sph_bwd(const odgs_plan* p, void* ws, const float* dL_d
                                ws_ptr<SphCull>(ws, p->off_cone), ws_ptr<double2>(ws, p->off_dirs),
                                ws_ptr<float>(ws, p->off_T), ws_ptr<int32_t>(ws, p->off_last), dL_drgb,
                                ws_ptr<double>(ws, p->off_g2d),
-                               ws_ptr<uint16_t>(ws, p->off_pval[p->pair_final ^ 1]), st))  // the forward's masks
+                               ws_ptr<const void>(ws, p->off_pval[p->pair_final ^ 1]), st))  // the forward's masks
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
