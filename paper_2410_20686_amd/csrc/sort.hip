@@ -507,11 +507,13 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* __restrict_
 constexpr int kQueueBuckets = 1024;
 constexpr int kQueueTiles = 4096;  // tiles per block of the count and scatter kernels (16 per thread)
 // A list is split into quadrant tasks (for compositors that take them) when one wavefront alone
-// would take long against the whole launch: when it holds at least kSplitLen pairs and at least
-// 1 / kSplitShare of all pairs.  At most split_tile_cap(tiles) lists are split: an eighth of the
-// tiles, or kSplitCapMin.
+// would take long against the whole launch: when it holds at least 1 / kSplitShare of all pairs
+// and, with kSplitAllTiles tiles or more, at least kSplitLen pairs (with fewer tiles than that the
+// device has wavefront slots to spare, and every list is split).  At most split_tile_cap(tiles)
+// lists are split: an eighth of the tiles, or kSplitCapMin.
 constexpr uint32_t kSplitLen = 1024;
 constexpr uint32_t kSplitShare = 4096;
+constexpr int kSplitAllTiles = 4096;
 constexpr int kSplitCapMin = 1024;
 
 __device__ inline uint32_t cost_bucket(uint32_t len) {
@@ -541,6 +543,7 @@ __global__ __launch_bounds__(256) void queue_count_kernel(const uint2* __restric
 // number of tiles to split (those with lists of kSplitLen or more, at most split_cap).
 __global__ __launch_bounds__(kQueueBuckets) void queue_scan_kernel(uint32_t* __restrict__ bstart, int nblocks,
                                                                    uint32_t* __restrict__ ctr, uint32_t split_cap,
+                                                                   uint32_t split_floor,
                                                                    const uint32_t* __restrict__ n_pairs) {
   __shared__ uint32_t wsum[kQueueBuckets / kWave];
   const int t = threadIdx.x, lane = t & (kWave - 1), w = t >> 6;
@@ -554,7 +557,7 @@ __global__ __launch_bounds__(kQueueBuckets) void queue_scan_kernel(uint32_t* __r
   uint32_t run = incl - c;
   for (int k = 0; k < w; ++k) run += wsum[k];
   // tiles in this bucket or above: the first run + c queue entries
-  if (bucket == (int)cost_bucket(max(kSplitLen, *n_pairs / kSplitShare))) ctr[4] = min(run + c, split_cap);
+  if (bucket == (int)cost_bucket(max(split_floor, *n_pairs / kSplitShare))) ctr[4] = min(run + c, split_cap);
   for (int b = 0; b < nblocks; ++b) {
     uint32_t* e = bstart + (size_t)b * kQueueBuckets + bucket;
     const uint32_t x = *e;
@@ -583,7 +586,7 @@ hipError_t launch_tile_queue(const uint2* ranges, int tiles, const uint32_t* n_p
   const int nb = (tiles + kQueueTiles - 1) / kQueueTiles;
   if (nb > 0) hipLaunchKernelGGL(queue_count_kernel, dim3(nb), dim3(256), 0, st, ranges, tiles, bstart);
   hipLaunchKernelGGL(queue_scan_kernel, dim3(1), dim3(kQueueBuckets), 0, st, bstart, nb, queue,
-                     (uint32_t)split_tile_cap(tiles), n_pairs);
+                     (uint32_t)split_tile_cap(tiles), tiles >= kSplitAllTiles ? kSplitLen : 1u, n_pairs);
   if (nb > 0) hipLaunchKernelGGL(queue_scatter_kernel, dim3(nb), dim3(256), 0, st, ranges, tiles, bstart, queue + 16);
   return hipGetLastError();
 }

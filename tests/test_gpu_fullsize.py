@@ -1,5 +1,5 @@
 """Parity at the workloads' full sizes, in the launch configuration the benchmark times (all
-views batched, tile 16, batch 256): bit-exact key lists, colours at sampled pixels against the
+views batched, tile 16, default LDS batches): bit-exact key lists, colours at sampled pixels against the
 brute-force oracle, and every parameter gradient under an upstream gradient that is non-zero
 only on the sampled pixels (so the oracle evaluates those pixels only, while the GPU runs the
 whole image)."""
@@ -70,6 +70,7 @@ def _check(sc, cams, st, n_pix, seed, key_views=None):
         np.testing.assert_array_equal(gauss[sel], ovals)
         if key_views == cams.n_views:
             assert res["status"]["n_pairs"] == len(okeys)
+    return res
 
 
 def test_cfg2_roaming_500k_4096x2048():
@@ -80,6 +81,23 @@ def test_cfg2_roaming_500k_4096x2048():
 def test_M_500k_8x2048x1024_batched():
     sc, cams, st = scenes.config("M")
     _check(sc, cams, st, n_pix=96, seed=1005, key_views=cams.n_views)
+
+
+def test_M_single_view_split_tiles():
+    """One view of M alone (the per-view launch): its longest lists are split into quadrant tasks
+    while the rest stay whole tiles, in one forward and one reverse launch."""
+    import torch
+    from tests.test_gpu_sched_status import expected_split_tiles
+    sc, cams, st = scenes.config("M")
+    cams = cams.view(0)
+    res = _check(sc, cams, st, n_pix=256, seed=1025, key_views=1)
+    rast = res["rast"]
+    p = rast.plan
+    tiles = int(p.tile_base[1])
+    r = rast.ws[p.off_ranges:p.off_ranges + 8 * tiles].view(torch.int32).cpu().numpy().reshape(tiles, 2)
+    hdr = rast.ws[p.off_queue:p.off_queue + 64].view(torch.int32).cpu().numpy()
+    split = expected_split_tiles(r[:, 1] - r[:, 0])
+    assert 0 < split < tiles and hdr[4] == split and hdr[5] == split
 
 
 def test_M_spherical_footprint_batched():

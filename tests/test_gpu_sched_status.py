@@ -1,11 +1,13 @@
 """Compositor scheduling and the device status record, through the C ABI.
 
-* The three tile schedules (one workgroup per tile in longest-first queue order, persistent
-  workgroups claiming tiles from that queue, one workgroup per tile in tile id order) composite the same tiles, so images are bit-identical
-  and gradients agree to the order in which per-tile partial sums reach the FP64 accumulators.
+* The three tile schedules (one workgroup per task in longest-first queue order, persistent
+  workgroups claiming tasks from that queue, one workgroup per tile in tile id order) composite the
+  same pixels in the same order, so images are bit-identical; gradients agree to the order in which
+  per-tile partial sums reach the FP64 accumulators, and where the queue splits tiles into quadrant
+  tasks, to the parity tolerance.
 * The work queue is a permutation of the global tile ids in non-increasing list length.
-* Tiles with long lists are split into quadrant tasks by the queue schedules, with the same images
-  and (up to summation order) gradients.
+* The longest lists (every list, in a launch of few tiles) are split into quadrant tasks by the
+  queue schedules, with the same images and (up to summation order) gradients.
 * The reverse compositor refuses a pair list the forward has not composited (a bin_sort between
   them), reporting it in the status record instead of reading stale culling masks.
 * Culled and non-finite items are counted.
@@ -36,11 +38,17 @@ def test_schedules_agree(tile, footprint):
     fwd = O.render(sc, cams, st, mode=32)
     dL = _masked_upstream(cams, fwd["margin"], seed=1081)
     runs = {s: G.run_gpu(sc, cams, dict(st, schedule=s), dL=dL) for s in ("queue", "persistent", "tile_id")}
-    base = runs["tile_id"]
-    for s in ("queue", "persistent"):
-        np.testing.assert_array_equal(runs[s]["rgb"], base["rgb"])
-        np.testing.assert_array_equal(runs[s]["T"], base["T"])
-        G.assert_grads_close(runs[s]["grads"], base["grads"], rtol=1e-6, floor=1e-9)
+    for s in ("persistent", "tile_id"):
+        np.testing.assert_array_equal(runs[s]["rgb"], runs["queue"]["rgb"])
+        np.testing.assert_array_equal(runs[s]["T"], runs["queue"]["T"])
+    # the two queue schedules take the same tasks: only the order of the FP64 totals differs
+    G.assert_grads_close(runs["persistent"]["grads"], runs["queue"]["grads"], rtol=1e-6, floor=1e-9)
+    if tile == 16:
+        # at 16x16 the queue splits this small launch's lists into quadrant tasks, whose float
+        # partial sums per entry round differently from whole tiles': the parity tolerance
+        G.assert_grads_close(runs["tile_id"]["grads"], runs["queue"]["grads"])
+    else:
+        G.assert_grads_close(runs["tile_id"]["grads"], runs["queue"]["grads"], rtol=1e-6, floor=1e-9)
     # and the default schedule against the oracle
     ok = G.strict_pixels(fwd["margin"])
     assert np.abs(runs["queue"]["T"] - fwd["T"])[ok].max() <= G.RGB_ATOL
@@ -68,20 +76,37 @@ def test_queue_is_longest_first_permutation():
 
 
 def _long_list_case(opacity_scale):
-    """Two 128x64 views inside a shell of 16k Gaussians.  With the opacities scaled down (and so
-    the footprints) about half the 16x16 tiles have lists of 1024 pairs or more and most pixels
-    composite to the end of their lists; at full opacity every tile's list is that long and pixels
-    stop early."""
+    """Two 128x64 views inside a shell of 16k Gaussians: lists of about a thousand pairs per 16x16
+    tile.  Scaling the opacities down (and so the footprints) keeps most pixels compositing to the
+    end of their lists; at full opacity they stop early."""
     sc = scenes.sphere_scene(16000, 3, seed=87, r_range=(0.5, 1.5))
     sc.opacities[:] = sc.opacities * opacity_scale
     return sc, scenes.identity_cameras(128, 64, 2)
 
 
+def expected_split_tiles(lengths):
+    """Tiles the queue splits into quadrant tasks: lists in the cost bucket of the split length or
+    above (buckets of 1/32 octave: exponent and top five mantissa bits of the float length), the
+    split length being 1/4096 of all pairs, and at least 1024 pairs once there are 4096 tiles or
+    more; at most max(1024, tiles / 8) tiles (all of them below 1024)."""
+    lengths = np.asarray(lengths, dtype=np.int64)
+    tiles = len(lengths)
+
+    def bucket(x):
+        x = np.asarray(x, dtype=np.int64)
+        b = 1 + ((x.astype(np.float32).view(np.uint32).astype(np.int64) - 0x3F800000) >> 18)
+        return np.where(x == 0, 0, b)
+
+    thr = max(1024 if tiles >= 4096 else 1, int(lengths.sum()) // 4096)
+    cap = tiles if tiles < 1024 else max(1024, tiles // 8)
+    return min(int((bucket(lengths) >= bucket(thr)).sum()), cap)
+
+
 @pytest.mark.parametrize("footprint,opacity_scale", [("affine", 0.03), ("affine", 1.0), ("spherical", 0.03)])
 def test_split_tiles(footprint, opacity_scale):
-    """Tiles whose lists reach 1024 pairs are composited as four single-quadrant tasks (forward and
-    reverse) under the queue schedules: images bit-identical to whole-tile compositing in tile id
-    order, 2D gradients and parameter gradients against the oracle."""
+    """Under the queue schedules a launch of few tiles composites every non-empty 16x16 list as four
+    single-quadrant tasks (forward and reverse): images bit-identical to whole-tile compositing in
+    tile id order, 2D gradients and parameter gradients against the oracle."""
     import torch
     sc, cams = _long_list_case(opacity_scale)
     st = settings(tile=16, footprint=footprint)
@@ -95,12 +120,10 @@ def test_split_tiles(footprint, opacity_scale):
         tiles = int(p.tile_base[cams.n_views])
         r = rast.ws[p.off_ranges:p.off_ranges + 8 * tiles].view(torch.int32).cpu().numpy().reshape(tiles, 2)
         hdr = rast.ws[p.off_queue:p.off_queue + 64].view(torch.int32).cpu().numpy()
-        long_lists = int(((r[:, 1] - r[:, 0]) >= 1024).sum())
-        assert 0 < long_lists <= tiles
-        if footprint == "affine" and opacity_scale < 1.0:
-            assert long_lists < tiles  # split and whole tiles in one launch
-        assert hdr[4] == long_lists  # counted by binning (fewer than 1024 tiles: no cap)
-        assert hdr[5] == (0 if s == "tile_id" else long_lists)  # split by the forward
+        split = expected_split_tiles(r[:, 1] - r[:, 0])
+        assert split > 0
+        assert hdr[4] == split  # counted by binning
+        assert hdr[5] == (0 if s == "tile_id" else split)  # split by the forward
     base = runs["tile_id"]
     for s in ("queue", "persistent"):
         np.testing.assert_array_equal(runs[s]["rgb"], base["rgb"])
