@@ -79,7 +79,7 @@ def tune(params, cams: torch.Tensor, dL: torch.Tensor, sh_degree: int, wh, setti
             row["fwd"][b] = _time(step.fwd, reps)
         for b in batches[tile]:
             rast.set_batches(rast.plan.s.batch, b)
-            # the reverse projection clears the accumulators the reverse compositor adds to
+            # (the accumulators keep adding up across repetitions without a preprocess: timing only)
             row["bwd"][b] = _time(lambda: (step.composite_bwd(), step.project_bwd()), reps)
         row["batch"] = min(row["fwd"], key=row["fwd"].get)
         row["batch_bwd"] = min(row["bwd"], key=row["bwd"].get)
