@@ -67,8 +67,8 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=0, help="forward LDS batch (0: library default)")
     ap.add_argument("--batch-bwd", type=int, default=0, help="reverse LDS batch (0: library default)")
