@@ -59,12 +59,17 @@ enum {
                                   ODGS_FLAG_COUNT_WORK, no densification statistics) */
 /* Scheduling of the two compositing launches, which cover the tiles of every view.  odgs_bin_sort
  * ends by queueing all (view, tile) pairs by descending list length (its compositing cost).
- * Default: one workgroup per tile, workgroup b taking queue entry b, so the longest tiles of all
- * views are dispatched first and the short ones fill the tail (the hardware dispatcher starts
- * workgroups in id order as slots free up).  The two flags below select the alternatives: */
+ * Default: one workgroup per task, workgroup b taking task b, so the longest tiles of all views
+ * are dispatched first and the short ones fill the tail (the hardware dispatcher starts
+ * workgroups in id order as slots free up).  A task is a tile, or at 16x16 tiles one 8x8 quadrant
+ * of a tile whose list is long against the launch (at least 1/4096 of all pairs and, with 4096
+ * tiles or more, at least 1024 pairs; at most an eighth of the tiles): those are split into four
+ * tasks at the front of the queue, so that one list does not set the launch's length.  The two
+ * flags below select the alternatives: */
 #define ODGS_FLAG_SCHED_PERSISTENT 4 /* persistent launches: as many workgroups as fit on the device,
-                                        each claiming the next queue entry when it finishes a tile */
-#define ODGS_FLAG_SCHED_TILE_ID 8    /* one workgroup per tile in global tile id order (no queue) */
+                                        each claiming the next task when it finishes one */
+#define ODGS_FLAG_SCHED_TILE_ID 8    /* one workgroup per tile in global tile id order (no queue, no
+                                        split tiles) */
 
 /* Spherical footprint (ODGS_FLAG_SPHERICAL).  The paper names its local affine approximation
  * of the projected Gaussian as its limitation (Sec. 5).  With this flag every pixel ray t d
