@@ -63,7 +63,7 @@ enum {
  * are dispatched first and the short ones fill the tail (the hardware dispatcher starts
  * workgroups in id order as slots free up).  A task is a tile, or at 16x16 tiles one 8x8 quadrant
  * of a tile whose list is long against the launch (at least 1/4096 of all pairs and, with 4096
- * tiles or more, at least 1024 pairs; at most an eighth of the tiles): those are split into four
+ * tiles or more, at least 1024 pairs; at most max(1024, tiles / 8) tiles): those are split into four
  * tasks at the front of the queue, so that one list does not set the launch's length.  The two
  * flags below select the alternatives: */
 #define ODGS_FLAG_SCHED_PERSISTENT 4 /* persistent launches: as many workgroups as fit on the device,
