@@ -89,9 +89,10 @@ enum {
 typedef struct odgs_settings {
   int32_t tile;     /* tile edge in pixels: 8, 16 or 32; every W and H must be a multiple */
   int32_t batch;    /* Gaussians the forward compositor stages in LDS per round: 32, 64, 128 or 256
-                       (64..256 at tile 32); 0 = default (256 at tile 32, else 64) */
-  int32_t batch_bwd; /* the same for the reverse compositor; 0 = default (32 at tile 8, 64 at tile 16,
-                        256 at tile 32) */
+                       (64..256 at tile 32); 0 = default (256 for the spherical footprint at
+                       tile 32, else 64) */
+  int32_t batch_bwd; /* the same for the reverse compositor; 0 = default (32 at tile 8, 256 for the
+                        spherical footprint at tile 32, else 64) */
   float near_r;     /* spherical-shell culling radii (Sec. 3.2): keep near_r < |mu| < far_r */
   float far_r;
   float dilation;   /* added to the 2D covariance's diagonal (3DGS low-pass), e.g. 0.3 */

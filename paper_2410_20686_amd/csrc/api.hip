@@ -65,8 +65,11 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   if (n * (int64_t)n_views >= (int64_t(1) << 31)) return ODGS_EINVAL;
   odgs_settings st = *s;
   if (st.tile != 8 && st.tile != 16 && st.tile != 32) return ODGS_EINVAL;
-  if (st.batch == 0) st.batch = st.tile == 32 ? 256 : 64;
-  if (st.batch_bwd == 0) st.batch_bwd = st.tile == 8 ? 32 : (st.tile == 16 ? 64 : 256);
+  // one-wavefront compositors (16x16 blocks) stage 64 entries at a time; the spherical footprint's
+  // 32x32 compositors have a workgroup of 1024 threads to fill
+  const bool sph32 = st.tile == 32 && (st.flags & ODGS_FLAG_SPHERICAL);
+  if (st.batch == 0) st.batch = sph32 ? 256 : 64;
+  if (st.batch_bwd == 0) st.batch_bwd = st.tile == 8 ? 32 : (sph32 ? 256 : 64);
   if (!batch_ok(st.tile, st.batch) || !batch_ok(st.tile, st.batch_bwd)) return ODGS_EINVAL;
   if (st.flags & ~(ODGS_FLAG_COUNT_WORK | ODGS_FLAG_SPHERICAL | ODGS_FLAG_SCHED_PERSISTENT | ODGS_FLAG_SCHED_TILE_ID))
     return ODGS_EINVAL;

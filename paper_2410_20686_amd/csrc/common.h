@@ -78,12 +78,13 @@ __device__ inline int view_of_item(int64_t item, int64_t n) { return (int)(item 
 // otherwise one workgroup per task takes task blockIdx.x (order == nullptr: tile id blockIdx.x, no
 // queue).
 //
-// A task is a whole tile or, for compositors that take them (split_cap > 0), one 8x8 quadrant of
-// one of the longest tiles: binning counts the tiles whose lists reach the split length (at most
-// split_cap of them, all at the front of the queue), and each of those becomes four tasks, so that
-// a single long list is composited by four wavefronts at once instead of setting the launch's
-// length by itself.  Tasks 0 .. 4 nsplit - 1 are those quadrants (task e: quadrant e % 4 of queue
-// entry e / 4), then come the remaining queue entries as whole tiles.
+// A task is a whole tile or, for compositors that take them (split_cap > 0), one of four parts of
+// a tile: binning counts the tiles whose lists reach the split length (at most split_cap of them,
+// all at the front of the queue), and each of those becomes four tasks, so that a single long list
+// is composited by four wavefronts at once instead of setting the launch's length by itself.
+// Tasks 0 .. 4 nsplit - 1 are those parts (task e: part e % 4 of queue entry e / 4; of tile
+// e / 4 without a queue), then come the remaining queue entries as whole tiles.  With split_all
+// every tile is split (32x32 tiles composited as four 16x16 parts).
 struct TileSched {
   const uint32_t* order;  // tile ids by descending list length, or nullptr
   uint32_t* ctr;          // persistent: {next task, finished workgroups}; nullptr: one task each
@@ -91,21 +92,30 @@ struct TileSched {
   uint32_t* split;        // {tiles split by binning, tiles split by the last forward}
   int32_t tiles;
   int32_t split_cap;      // 0: whole tiles only
+  int32_t split_all;      // every tile in four parts (split_cap == tiles)
 };
 
 // Upper bound of the task count of a launch (its grid without a persistent launch).
 inline int sched_tasks(const TileSched& s) { return s.tiles + 3 * s.split_cap; }
 
-// Next task of this workgroup (uniform): returns its tile and sets `sel` to the quadrants it
-// covers (0xF: the whole tile), or returns -1 when the workgroup is done.  `nsplit` (uniform, at
-// most split_cap) is the number of split tiles; `round` starts at 0; `slot` is a workgroup-shared
-// word.  Contains barriers in persistent mode.
+// Next task of this workgroup (uniform): returns its tile and sets `sel` to the part it covers
+// (1 << part; 0xF: the whole tile), or returns -1 when the workgroup is done.  `nsplit` (uniform,
+// at most split_cap) is the number of split tiles; `round` starts at 0; `slot` is a
+// workgroup-shared word.  Contains barriers in persistent mode.
 __device__ inline int claim_task(const TileSched& s, int nsplit, uint32_t& round, uint32_t* slot, uint32_t& sel) {
   const uint32_t total = (uint32_t)(s.tiles + 3 * nsplit);
   uint32_t e;
   if (!s.ctr) {
     if (round++) return -1;
     e = blockIdx.x;
+    // The dispatcher hands workgroups to the 8 XCDs in turn, each with its own L2: the four parts
+    // of a split tile (which stage the same list) go to four consecutive workgroups of one XCD
+    // (groups of eight tiles, in queue order; the tail of an incomplete group stays in order).
+    constexpr uint32_t kXcds = 8;
+    if (e < (uint32_t)(nsplit / kXcds) * 4u * kXcds) {
+      const uint32_t k = e / kXcds;
+      e = 4u * ((k / 4u) * kXcds + e % kXcds) + k % 4u;
+    }
   } else {
     __syncthreads();  // every thread has read the previous claim
     if (threadIdx.x == 0) {
@@ -121,16 +131,15 @@ __device__ inline int claim_task(const TileSched& s, int nsplit, uint32_t& round
     e = *slot;
   }
   if (e >= total) return -1;
-  if (!s.order) {
-    sel = 0xFu;
-    return (int)e;
-  }
+  uint32_t idx;
   if (e < 4u * (uint32_t)nsplit) {
     sel = 1u << (e & 3u);
-    return (int)s.order[e >> 2];
+    idx = e >> 2;
+  } else {
+    sel = 0xFu;
+    idx = e - 3u * (uint32_t)nsplit;
   }
-  sel = 0xFu;
-  return (int)s.order[e - 3u * (uint32_t)nsplit];
+  return s.order ? (int)s.order[idx] : (int)idx;
 }
 
 // Next whole tile of this workgroup (compositors that take no quadrant tasks).
@@ -139,13 +148,16 @@ __device__ inline int claim_tile(const TileSched& s, uint32_t& round, uint32_t* 
   return claim_task(s, 0, round, slot, sel);
 }
 
-// Split tiles of a forward launch (uniform): what binning chose, within this launch's cap.
+// Split tiles of a forward launch (uniform): every tile with split_all, else what binning chose
+// (within this launch's cap; none without the queue, which names the longest tiles).
 __device__ inline int forward_split(const TileSched& s) {
+  if (s.split_all) return s.tiles;
   return s.split_cap > 0 && s.order ? (int)min(s.split[0], (uint32_t)s.split_cap) : 0;
 }
-// Split tiles of a reverse launch: those of the forward it follows (which wrote the culling masks
-// of the split tiles' quadrants separately), within this launch's cap.
+// Split tiles of a reverse launch: every tile with split_all, else those of the forward it follows
+// (which wrote the culling masks of the split tiles' parts separately), within this launch's cap.
 __device__ inline int reverse_split(const TileSched& s) {
+  if (s.split_all) return s.tiles;
   return s.split_cap > 0 && s.order ? (int)min(s.split[1], (uint32_t)s.split_cap) : 0;
 }
 
@@ -229,6 +241,12 @@ int split_tile_cap(int tiles);
 // longest tiles).
 inline TileSched with_split(TileSched s) {
   if (s.order) s.split_cap = split_tile_cap(s.tiles);
+  return s;
+}
+// The schedule of a compositor that takes every tile in four parts.
+inline TileSched with_parts(TileSched s) {
+  s.split_cap = s.tiles;
+  s.split_all = 1;
   return s;
 }
 int sched_grid(const TileSched& s, int per_cu);

@@ -1,13 +1,16 @@
 // Compositing kernels of the omnidirectional rasterizer, gfx950.
 //
-// One workgroup per (view, tile).  Pixels are grouped in 8x8 quadrants: a 64-wide wavefront owns
-// one quadrant with one pixel per lane (forward at tiles 8 and 16, backward at 8) or two side by
-// side with two pixels per lane (forward at 32, backward at 16 and 32).  The tile's depth-ordered
-// list is staged through LDS in batches; while the forward stages, each record gets a bit mask of
-// the quadrants its footprint can reach, so a wavefront skips, with a uniform branch, every
-// Gaussian that cannot reach any of its pixels.  (The mask is conservative: a skipped Gaussian has
-// alpha < 1/255 at every pixel of the quadrant, so results are identical to testing every pixel.)
-// The forward stores the masks per list position and the backward loads them.
+// Pixels are grouped in 8x8 quadrants.  At tiles of 16 and 32 one 64-wide wavefront composites a
+// 16x16 block, four pixels per lane (lane l holds pixel (l % 8, l / 8) of each quadrant): a whole
+// 16x16 tile, one quadrant of a split tile, or one of the four blocks of a 32x32 tile (the tasks
+// of TileSched).  At tiles of 8, and in the counting and depth variants of the forward, one
+// workgroup per (view, tile) with one pixel per lane, each wavefront owning one quadrant.  The
+// tile's depth-ordered list is staged through LDS in batches; while the forward stages, each
+// record gets a bit mask of the quadrants its footprint can reach, so a quadrant skips, with a
+// uniform branch, every Gaussian that cannot reach any of its pixels.  (The mask is conservative: a
+// skipped Gaussian has alpha < 1/255 at every pixel of the quadrant, so results are identical to
+// testing every pixel.)  The forward stores the masks per list position and the backward loads
+// them.
 //
 // Forward: front-to-back compositing (Eq. gaussian2d, Eq. alphablending) until a pixel's
 // transmittance would drop below 1e-4; the workgroup stops loading batches once every pixel is
@@ -182,14 +185,13 @@ __device__ inline float wrap_du(float du, float Wf, float half) {
 }
 
 // Stage `cnt` records of a tile list into LDS (entry e <- list position first + dir * e) and
-// build, for every wavefront, the order-preserving list of entries whose footprint reaches its
-// pixels.  With PX pixels per lane a wavefront owns PX horizontally adjacent quadrants (8x8
-// pixel blocks), so there are NQ / PX lists.  Counts per list are returned in nq[] (identical
-// in every thread).
-template <int TILE, int BATCH, int PX = 1>
+// build, for every wavefront (one per 8x8 quadrant, one pixel per lane), the order-preserving
+// list of entries whose footprint reaches its pixels.  Counts per list are returned in nq[]
+// (identical in every thread).
+template <int TILE, int BATCH>
 struct Stage {
-  static constexpr int N = TILE * TILE / PX;  // threads
-  static constexpr int NQ = (TILE / 8) * (TILE / 8) / PX;  // lists = wavefronts
+  static constexpr int N = TILE * TILE;  // threads
+  static constexpr int NQ = (TILE / 8) * (TILE / 8);  // lists = wavefronts
   static constexpr int NW = N / kWave;
   static_assert(NQ == NW, "one list per wavefront");
   float4 s0[BATCH];
@@ -202,37 +204,23 @@ struct Stage {
   uint32_t tot[NQ];
 };
 
-// Quadrant mask -> mask of the wavefronts' quadrant groups (PX adjacent quadrants each).
-template <int PX>
-__device__ inline uint32_t group_mask(uint32_t m) {
-  if constexpr (PX == 1) {
-    return m;
-  } else {
-    static_assert(PX == 2, "one or two pixels per lane");
-    uint32_t g = 0;
-#pragma unroll
-    for (int r = 0; r < 8; ++r) g |= ((m >> (2 * r)) & 3u) ? (1u << r) : 0u;
-    return g;
-  }
-}
-
 // The culling masks travel from the forward to the backward: the forward stores, per list position,
-// a mask in the reverse compositor's granularity (the wavefronts' two-quadrant groups for tiles of
-// 16 and 32, the one quadrant of an 8x8 tile) into the pair buffer the sort leaves unused, and the
-// backward loads it instead of evaluating the footprint again.  The mask is written after the
-// forward walks each batch: the quadrants (or groups) in which some of its pixels reached the entry
-// (see s_used), narrower than the footprint's.  The backward reads only list positions before its
-// tile's last contributor, all of which the forward staged.
+// the quadrants of the reverse compositor's task in which some of its pixels reached the entry (see
+// s_used; narrower than the footprint's) into the pair buffer the sort leaves unused, and the
+// backward loads them instead of evaluating the footprint again: one byte per position, in byte
+// planes at 16x16 blocks (the task's plane, see task_block).  The mask is written after the forward
+// walks each batch.  The backward reads only list positions before its tile's last contributor,
+// all of which the forward staged.
 enum QuadMaskMode { kMaskEval = 0, kMaskLoad = 2 };
 
 // Returns whether the seam wrap is the identity for every staged entry (uniform).
-template <int TILE, int BATCH, int PX = 1, int QM = kMaskEval>
-__device__ inline bool stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __restrict__ pair_items,
+template <int TILE, int BATCH, int QM = kMaskEval>
+__device__ inline bool stage_batch(Stage<TILE, BATCH>& S, const uint32_t* __restrict__ pair_items,
                                    const Rec* __restrict__ rec, uint32_t first, int dir, int cnt, int tx0, int ty0,
-                                   float Wf, float half, int (&nq)[Stage<TILE, BATCH, PX>::NQ],
+                                   float Wf, float half, int (&nq)[Stage<TILE, BATCH>::NQ],
                                    const float* __restrict__ depth = nullptr,
                                    const uint8_t* __restrict__ qmask_in = nullptr) {
-  using St = Stage<TILE, BATCH, PX>;
+  using St = Stage<TILE, BATCH>;
   const int t = threadIdx.x, ln = t & (kWave - 1), wv = t >> 6;
   const uint64_t below = ln == 0 ? 0ull : (~0ull >> (kWave - ln));
 #pragma unroll
@@ -257,9 +245,9 @@ __device__ inline bool stage_batch(Stage<TILE, BATCH, PX>& S, const uint32_t* __
       S.sid[e] = item;
       if (depth) S.dep[e] = depth[item];
       if constexpr (QM == kMaskLoad) {
-        m = qmask_in[pos];  // stored in this granularity (two-pixel groups at 16 and 32, one quadrant at 8)
+        m = qmask_in[pos];
       } else {
-        m = group_mask<PX>(quadrant_mask<TILE>(r, tx0, ty0, Wf, half));
+        m = quadrant_mask<TILE>(r, tx0, ty0, Wf, half);
       }
     }
     uint32_t within[St::NQ];
@@ -305,7 +293,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
     float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
     int32_t* __restrict__ ws_ncontrib, int32_t* __restrict__ ws_neval, int32_t* __restrict__ ws_lasteval, float bg0,
     float bg1, float bg2, const float* __restrict__ depth, float* __restrict__ out_depth, uint8_t* __restrict__ qmask,
-    TileSched sc) {
+    int64_t qplane, TileSched sc) {
   using St = Stage<TILE, BATCH>;
   constexpr int N = St::N;
   __shared__ St S;
@@ -344,7 +332,18 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
           uint32_t mq = 0;
 #pragma unroll
           for (int q = 0; q < St::NQ; ++q) mq |= s_used[q][e] ? (1u << q) : 0u;
-          qmask[first + e] = (uint8_t)(TILE >= 32 ? group_mask<2>(mq) : mq);
+          if constexpr (TILE >= 32) {
+            // the reverse compositor takes each 16x16 block b = 2 by + bx of a 32x32 tile as a
+            // task: its four quadrants' bits go to byte plane b
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              const int q0 = 8 * (b >> 1) + 2 * (b & 1);  // quadrant (2 bx, 2 by) of the 4x4 grid
+              qmask[(int64_t)b * qplane + first + e] =
+                  (uint8_t)(((mq >> q0) & 3u) | (((mq >> (q0 + 4)) & 3u) << 2));
+            }
+          } else {
+            qmask[first + e] = (uint8_t)mq;
+          }
         }
 #pragma unroll
         for (int q = 0; q < St::NQ; ++q) s_used[q][e] = 0;
@@ -434,6 +433,26 @@ __global__ __launch_bounds__(TILE* TILE) void render_fwd_kernel(
 // entry are handed to the backward as in the one-pixel forward.  A quadrant task of a split tile
 // (see TileSched) runs the same code with its one quadrant selected, and hands its masks over in
 // the byte plane of its quadrant (plane q at byte offset q * qplane; whole tiles use plane 0).
+// The 16x16 pixel block a task composites: its origin (bx0, by0), its quadrants (`sel`, updated)
+// and the byte plane of its culling masks.  BIN = 16: the tile, or one quadrant of a split tile
+// (plane q); BIN = 32: part p of the tile, the 16x16 block p = 2 by + bx with all four quadrants
+// (plane p).
+template <int BIN>
+__device__ inline void task_block(const ViewTable& vt, int v, int g, uint32_t& sel, int& bx0, int& by0, int& plane) {
+  const int ntx = vt.W[v] / BIN;
+  const int lt = g - vt.tile_base[v];
+  bx0 = (lt % ntx) * BIN;
+  by0 = (lt / ntx) * BIN;
+  plane = sel == 0xFu ? 0 : __builtin_ctz(sel);
+  if constexpr (BIN == 32) {
+    bx0 += 16 * (plane & 1);
+    by0 += 16 * (plane >> 1);
+    sel = 0xFu;
+  } else {
+    static_assert(BIN == 16, "blocks of 16x16 pixels in tiles of 16 or 32");
+  }
+}
+
 template <int BATCH>
 struct FwdStage4 {
   float4 s0[BATCH];
@@ -443,7 +462,7 @@ struct FwdStage4 {
   uint8_t used[BATCH];
 };
 
-template <int BATCH>
+template <int BIN, int BATCH>
 __global__ __launch_bounds__(kWave) void render_fwd4_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
     float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
@@ -459,9 +478,8 @@ __global__ __launch_bounds__(kWave) void render_fwd4_kernel(
   for (int g; (g = claim_task(sc, nsplit, round, &s_claim, sel)) >= 0;) {
     const int v = view_of_tile(vt, g);
     const int W = vt.W[v], H = vt.H[v];
-    const int ntx = W / TILE;
-    const int lt = g - vt.tile_base[v];
-    const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+    int tx0, ty0, pl;
+    task_block<BIN>(vt, v, g, sel, tx0, ty0, pl);
     const int x = tx0 + (lane & 7), y = ty0 + (lane >> 3);
     const float px0 = (float)x + 0.5f, px1 = (float)(x + 8) + 0.5f;
     const float py0 = (float)y + 0.5f, py1 = (float)(y + 8) + 0.5f;
@@ -477,7 +495,7 @@ __global__ __launch_bounds__(kWave) void render_fwd4_kernel(
       last[q] = 0;
     }
     uint32_t alive = sel;  // selected quadrants with a pixel still compositing (uniform)
-    uint8_t* qm = qmask + (sel == 0xFu ? 0 : (int64_t)__builtin_ctz(sel) * qplane);
+    uint8_t* qm = qmask + (int64_t)pl * qplane;
     for (uint32_t base = rg.x; base < rg.y && alive != 0u; base += BATCH) {
       const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
       int n = 0;
@@ -567,128 +585,6 @@ __global__ __launch_bounds__(kWave) void render_fwd4_kernel(
   }
 }
 
-// Forward compositing state of one pixel.
-struct FwdPixel {
-  float T, C0, C1, C2;
-  int last;
-  bool done;
-};
-
-// One Gaussian's front-to-back step for one pixel (Eq. alphablending with the 3DGS constants).
-__device__ inline void fwd_pixel_step(FwdPixel& P, bool ok, float power, const float4& b, const float4& c, int pos) {
-  const float alpha = fminf(b.z * __expf(power), kAlphaMax);
-  const float Tn = P.T * (1.0f - alpha);
-  const bool acc = ok && !(Tn < kTStop);
-  P.done = P.done || ok != acc;  // stop: reached, but T would drop below 1e-4
-  const float w = acc ? alpha * P.T : 0.0f;
-  P.C0 = fmaf(w, c.x, P.C0);
-  P.C1 = fmaf(w, c.y, P.C1);
-  P.C2 = fmaf(w, c.z, P.C2);
-  P.T = acc ? Tn : P.T;
-  P.last = acc ? pos : P.last;
-}
-
-// Forward compositing with two pixels per lane (32x32 tiles), the layout of the two-pixel
-// reverse compositor: wavefront w owns quadrants 2w and 2w + 1, lane l pixel (l % 8, l / 8) of
-// each.  Two independent pixel chains per lane share each entry's list index and record reads.
-template <int TILE, int BATCH>
-__global__ __launch_bounds__(TILE* TILE / 2) void render_fwd2_kernel(
-    ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
-    float* __restrict__ out_rgb, float* __restrict__ out_T, float* __restrict__ ws_T, int32_t* __restrict__ ws_last,
-    float bg0, float bg1, float bg2, uint8_t* __restrict__ qmask, TileSched sc) {
-  using St = Stage<TILE, BATCH, 2>;
-  constexpr int N = St::N;
-  constexpr int QPR = TILE / 8;
-  __shared__ St S;
-  __shared__ uint8_t s_used[St::NQ][BATCH];  // as in the one-pixel forward, per wavefront group
-  mark_forward(sc);
-  __shared__ uint32_t s_claim;
-  uint32_t round = 0;
-  for (int g; (g = claim_tile(sc, round, &s_claim)) >= 0;) {
-    const int v = view_of_tile(vt, g);
-    const int W = vt.W[v], H = vt.H[v];
-    const int ntx = W / TILE;
-    const int lt = g - vt.tile_base[v];
-    const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int qa = 2 * wq;
-    const int x = tx0 + (qa % QPR) * 8 + (lane & 7), y = ty0 + (qa / QPR) * 8 + (lane >> 3);
-    const float pxa = (float)x + 0.5f, pxb = (float)(x + 8) + 0.5f, py = (float)y + 0.5f;
-    const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
-    const uint2 rg = ranges[g];
-    FwdPixel A{1.0f, 0.0f, 0.0f, 0.0f, 0, false}, B{1.0f, 0.0f, 0.0f, 0.0f, 0, false};
-    // writes the masks of the batch walked last (after a barrier) and clears s_used for the next
-    auto flush_used = [&](uint32_t first, int n_walked) {
-      for (int e = threadIdx.x; e < BATCH; e += N) {
-        if (e < n_walked) {
-          uint32_t mg = 0;
-#pragma unroll
-          for (int q = 0; q < St::NQ; ++q) mg |= s_used[q][e] ? (1u << q) : 0u;
-          qmask[first + e] = (uint8_t)mg;
-        }
-#pragma unroll
-        for (int q = 0; q < St::NQ; ++q) s_used[q][e] = 0;
-      }
-    };
-    uint32_t walked_base = 0;
-    int walked_cnt = 0;
-    for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
-      const bool all_done = __syncthreads_count(A.done && B.done) == N;
-      flush_used(walked_base, walked_cnt);
-      walked_cnt = 0;
-      if (all_done) break;
-      const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
-      int nq[St::NQ];
-      stage_batch<TILE, BATCH, 2>(S, pair_items, rec, base, 1, cnt, tx0, ty0, Wf, half, nq);
-      const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
-      for (int i = 0; i < n; ++i) {
-        if (__builtin_amdgcn_ballot_w64(!(A.done && B.done)) == 0ull) break;  // uniform
-        const int k = S.list[wq][i];
-        const float4 a = S.s0[k];
-        const float4 b = S.s1[k];
-        const float dv = py - a.y;
-        const float l1dv = a.w * dv, t2 = b.x * dv, t22 = t2 * t2;
-        const float dua = wrap_du(pxa - a.x, Wf, half), dub = wrap_du(pxb - a.x, Wf, half);
-        const float t1a = fmaf(a.z, dua, l1dv), t1b = fmaf(a.z, dub, l1dv);
-        const float pa = -fmaf(t1a, t1a, t22), pb = -fmaf(t1b, t1b, t22);
-        const bool oka = !A.done && !(pa > 0.0f || pa < b.y);
-        const bool okb = !B.done && !(pb > 0.0f || pb < b.y);
-        const bool anya = __builtin_amdgcn_ballot_w64(oka) != 0ull;  // uniform
-        const bool anyb = __builtin_amdgcn_ballot_w64(okb) != 0ull;
-        if (!anya && !anyb) continue;
-        s_used[wq][k] = 1;  // reached by some pixel of the group (see the one-pixel forward)
-        const float4 c = S.s2[k];
-        const int pos = (int)(base - rg.x) + k + 1;
-        if (anya) fwd_pixel_step(A, oka, pa, b, c, pos);
-        if (anyb) fwd_pixel_step(B, okb, pb, b, c, pos);
-      }
-      walked_base = base;
-      walked_cnt = cnt;
-    }
-    __syncthreads();
-    flush_used(walked_base, walked_cnt);
-    const int64_t plane = (int64_t)W * H;
-    const int64_t pix = (int64_t)y * W + x;
-    float* img = out_rgb + 3 * vt.pix_base[v];
-    img[pix] = fmaf(A.T, bg0, A.C0);
-    img[plane + pix] = fmaf(A.T, bg1, A.C1);
-    img[2 * plane + pix] = fmaf(A.T, bg2, A.C2);
-    img[pix + 8] = fmaf(B.T, bg0, B.C0);
-    img[plane + pix + 8] = fmaf(B.T, bg1, B.C1);
-    img[2 * plane + pix + 8] = fmaf(B.T, bg2, B.C2);
-    const int64_t gp = vt.pix_base[v] + pix;
-    ws_T[gp] = A.T;
-    ws_T[gp + 8] = B.T;
-    ws_last[gp] = A.last;
-    ws_last[gp + 8] = B.last;
-    if (out_T) {
-      out_T[gp] = A.T;
-      out_T[gp + 8] = B.T;
-    }
-  }
-}
-
 // Reverse compositing state of one pixel (back to front from its last contributor).
 struct BwdPixel {
   float T, DS, dl0, dl1, dl2;  // DS = dL/dC . (colour of everything behind, incl. background)
@@ -771,7 +667,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
                                                                 const float* __restrict__ dL_drgb, double* __restrict__ g2d,
                                                                 int64_t items, float bg0, float bg1, float bg2,
                                                                 const uint8_t* __restrict__ qmask, TileSched sc) {
-  static_assert(TILE == 8, "tiles of 16 and 32 take the four- and two-pixel kernels");
+  static_assert(TILE == 8, "tiles of 16 and 32 take the four-pixel kernel");
   using St = Stage<TILE, BATCH>;
   constexpr int N = St::N;
   // Up to four wavefronts per tile: each wavefront owns a slot per (value, entry) and the slots
@@ -831,7 +727,7 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
       }
       int nq[St::NQ];
       // entry e is list position end - 1 - e (back to front)
-      stage_batch<TILE, BATCH, 1, kMaskLoad>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq, nullptr,
+      stage_batch<TILE, BATCH, kMaskLoad>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq, nullptr,
                                              qmask);
       const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
       bool pend = false;  // an accepted entry whose values 0..7 still wait in red (uniform)
@@ -906,7 +802,7 @@ struct Stage4 {
   uint16_t list[BATCH];  // entry index | quadrant mask << 8
 };
 
-template <int BATCH>
+template <int BIN, int BATCH>
 __global__ __launch_bounds__(kWave) void render_bwd4_kernel(
     ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
     const float* __restrict__ ws_T, const int32_t* __restrict__ ws_last, const float* __restrict__ dL_drgb,
@@ -925,9 +821,8 @@ __global__ __launch_bounds__(kWave) void render_bwd4_kernel(
   for (int g; (g = claim_task(sc, nsplit, round, &s_claim, sel)) >= 0;) {
     const int v = view_of_tile(vt, g);
     const int W = vt.W[v], H = vt.H[v];
-    const int ntx = W / TILE;
-    const int lt = g - vt.tile_base[v];
-    const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
+    int tx0, ty0, pl;
+    task_block<BIN>(vt, v, g, sel, tx0, ty0, pl);
     const int x = tx0 + (lane & 7), y = ty0 + (lane >> 3);
     const float px0 = (float)x + 0.5f, px1 = (float)(x + 8) + 0.5f;
     const float py0 = (float)y + 0.5f, py1 = (float)(y + 8) + 0.5f;
@@ -951,7 +846,7 @@ __global__ __launch_bounds__(kWave) void render_bwd4_kernel(
       P[q].DS = P[q].T * fmaf(P[q].dl0, bg0, fmaf(P[q].dl1, bg1, P[q].dl2 * bg2));
       wmax = max(wmax, P[q].last);
     }
-    const uint8_t* qm = qmask + (sel == 0xFu ? 0 : (int64_t)__builtin_ctz(sel) * qplane);
+    const uint8_t* qm = qmask + (int64_t)pl * qplane;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
     wmax = __builtin_amdgcn_readfirstlane(wmax);
@@ -965,16 +860,18 @@ __global__ __launch_bounds__(kWave) void render_bwd4_kernel(
         uint32_t m = 0;
         if (e < cnt) {
           const uint32_t pos = rg.x + end - 1 - e;
-          const uint32_t item = pair_items[pos];
-          const Rec r = rec[item];
-          S.s0[e] = r.r0;
-          const float reach = fabsf((float)tx0 + 0.5f * (float)TILE - r.r0.x) + 0.5f * (float)TILE + 1.0f;
-          S.s1[e] = make_float4(r.r1.x, r.r1.z, r.r1.y, reach < half ? 1.0f : 0.0f);
-          S.s2[e] = r.r2;
-          S.sid[e] = item;
           m = qm[pos] & sel;
+          if (m != 0u) {  // records only of the entries the forward's pixels reached
+            const uint32_t item = pair_items[pos];
+            const Rec r = rec[item];
+            S.s0[e] = r.r0;
+            const float reach = fabsf((float)tx0 + 0.5f * (float)TILE - r.r0.x) + 0.5f * (float)TILE + 1.0f;
+            S.s1[e] = make_float4(r.r1.x, r.r1.z, r.r1.y, reach < half ? 1.0f : 0.0f);
+            S.s2[e] = r.r2;
+            S.sid[e] = item;
 #pragma unroll
-          for (int q = 0; q < 9; ++q) acc[0][q][e] = 0.0f;
+            for (int q = 0; q < 9; ++q) acc[0][q][e] = 0.0f;
+          }
         }
         const uint64_t bl = __builtin_amdgcn_ballot_w64(m != 0u);
         if (m != 0u) S.list[n + __popcll(bl & below)] = (uint16_t)(e | (m << 8));
@@ -1017,133 +914,10 @@ __global__ __launch_bounds__(kWave) void render_bwd4_kernel(
         if (lane < 16 && slot < 9) acc[0][slot][k] = ws;
       }
       __syncthreads();
-      for (int xq = lane; xq < 9 * cnt; xq += kWave) {
-        const int t = xq / 9, q = xq - 9 * t;
-        const double s = g2d_flush_value(acc, q, t, S.s0[t], S.s1[t]);
-        if (s != 0.0) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s);
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// Reverse compositing with two pixels per lane (16x16 and 32x32 tiles): wavefront w owns quadrants
-// 2w and 2w + 1 (side by side), lane l the pixel (l % 8, l / 8) of each.  Both pixels' gradient
-// contributions are added in registers, so each (entry, wavefront) needs one cross-lane
-// reduction for 128 pixels, and the per-entry LDS reads and loop control are shared.
-template <int TILE, int BATCH>
-__global__ __launch_bounds__(TILE* TILE / 2) void render_bwd2_kernel(
-    ViewTable vt, const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_items, const Rec* __restrict__ rec,
-    const float* __restrict__ ws_T, const int32_t* __restrict__ ws_last, const float* __restrict__ dL_drgb,
-    double* __restrict__ g2d, int64_t items, float bg0, float bg1, float bg2, const uint8_t* __restrict__ qmask,
-    TileSched sc) {
-  using St = Stage<TILE, BATCH, 2>;
-  constexpr int N = St::N;
-  constexpr int QPR = TILE / 8;
-  // A slot set per wavefront up to four wavefronts; beyond (tile 32: eight) wavefronts w and w + 4
-  // share set w % 4 and add into it.  Two additions onto a cleared slot give the same float in
-  // either order (addition is commutative), so the per-tile sums do not depend on wavefront timing.
-  constexpr int NS = St::NW <= 4 ? St::NW : 4;
-  static_assert(St::NW <= 2 * NS, "at most two wavefronts per slot set");
-  __shared__ St S;
-  __shared__ float acc[NS][9][BATCH + 1];  // padded rows: the nine slot writes hit nine banks
-  __shared__ int smax;
-  if (forward_is_stale(sc)) return;  // uniform
-  __shared__ uint32_t s_claim;
-  uint32_t round = 0;
-  for (int g; (g = claim_tile(sc, round, &s_claim)) >= 0;) {
-    const int v = view_of_tile(vt, g);
-    const int W = vt.W[v], H = vt.H[v];
-    const int ntx = W / TILE;
-    const int lt = g - vt.tile_base[v];
-    const int tx0 = (lt % ntx) * TILE, ty0 = (lt / ntx) * TILE;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int qa = 2 * wq;  // quadrant of pixel A; pixel B is 8 pixels to the right
-    const int x = tx0 + (qa % QPR) * 8 + (lane & 7), y = ty0 + (qa / QPR) * 8 + (lane >> 3);
-    const int slot = (int)((kRowSlot >> (4 * (lane & 15))) & 0xF);
-    const float pxa = (float)x + 0.5f, pxb = (float)(x + 8) + 0.5f, py = (float)y + 0.5f;
-    const float Wf = (float)W, half = wrap_half(vt, v);  // no seam in pinhole views
-    const uint2 rg = ranges[g];
-    const int64_t plane = (int64_t)W * H;
-    const int64_t pix = (int64_t)y * W + x;
-    const int64_t gp = vt.pix_base[v] + pix;
-    const float* dimg = dL_drgb + 3 * vt.pix_base[v];
-    BwdPixel A, B;
-    A.dl0 = dimg[pix], A.dl1 = dimg[plane + pix], A.dl2 = dimg[2 * plane + pix];
-    B.dl0 = dimg[pix + 8], B.dl1 = dimg[plane + pix + 8], B.dl2 = dimg[2 * plane + pix + 8];
-    A.T = ws_T[gp];
-    B.T = ws_T[gp + 8];
-    A.last = ws_last[gp];
-    B.last = ws_last[gp + 8];
-    A.DS = A.T * fmaf(A.dl0, bg0, fmaf(A.dl1, bg1, A.dl2 * bg2));  // the background behind everything
-    B.DS = B.T * fmaf(B.dl0, bg0, fmaf(B.dl1, bg1, B.dl2 * bg2));
-    // largest `last` of the wavefront (uniform) and of the workgroup
-    int wmax = max(A.last, B.last);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
-    wmax = __builtin_amdgcn_readfirstlane(wmax);
-    if (threadIdx.x == 0) smax = 0;
-    __syncthreads();
-    if (lane == 0) atomicMax(&smax, wmax);
-    __syncthreads();
-    const int end_all = smax;
-    for (int end = end_all; end > 0; end -= BATCH) {
-      const int cnt = min(BATCH, end);
-      for (int t = threadIdx.x; t < cnt; t += N) {
-#pragma unroll
-        for (int w = 0; w < NS; ++w)
-#pragma unroll
-          for (int q = 0; q < 9; ++q) acc[w][q][t] = 0.0f;
-      }
-      int nq[St::NQ];
-      // entry e is list position end - 1 - e (back to front)
-      stage_batch<TILE, BATCH, 2, kMaskLoad>(S, pair_items, rec, rg.x + end - 1, -1, cnt, tx0, ty0, Wf, half, nq, nullptr,
-                                             qmask);
-      const int n = __builtin_amdgcn_readfirstlane(nq[wq]);
-      for (int i = 0; i < n; ++i) {
-        const int k = __builtin_amdgcn_readfirstlane(S.list[wq][i]);  // uniform entry index
-        const int jrel = end - 1 - k;
-        if (jrel >= wmax) continue;  // uniform: behind every contributor of this wavefront
-        const float4 a = S.s0[k];
-        const float4 b = S.s1[k];
-        const float dv = py - a.y;
-        const float l1dv = a.w * dv, t2 = b.x * dv, t22 = t2 * t2;
-        float dua = pxa - a.x, dub = pxb - a.x;
-        if (__builtin_amdgcn_readfirstlane(__float_as_int(b.w)) == 0) {  // uniform: the seam is within reach
-          dua = wrap_du(dua, Wf, half);
-          dub = wrap_du(dub, Wf, half);
-        }
-        const float t1a = fmaf(a.z, dua, l1dv), t1b = fmaf(a.z, dub, l1dv);
-        const float pa = -fmaf(t1a, t1a, t22), pb = -fmaf(t1b, t1b, t22);
-        const bool ina = !(pa > 0.0f || pa < b.y), inb = !(pb > 0.0f || pb < b.y);
-        const bool oka = jrel < A.last && ina, okb = jrel < B.last && inb;
-        // ballots of the single compares (each is its own lane mask) rather than of their conjunction
-        const uint64_t bala = __builtin_amdgcn_ballot_w64(jrel < A.last) & __builtin_amdgcn_ballot_w64(ina);
-        const uint64_t balb = __builtin_amdgcn_ballot_w64(jrel < B.last) & __builtin_amdgcn_ballot_w64(inb);
-        if ((bala | balb) == 0ull) continue;  // uniform
-        const float4 c = S.s2[k];
-        float gq[9];
-        if (bala != 0ull) {
-          bwd_pixel_step<false>(A, oka, pa, t1a, t2, a, b, c, gq);
-          if (balb != 0ull) bwd_pixel_step<true>(B, okb, pb, t1b, t2, a, b, c, gq);
-        } else {
-          bwd_pixel_step<false>(B, okb, pb, t1b, t2, a, b, c, gq);
-        }
-        const float rs = row_reduce9(gq, lane & 8, lane & 4, lane & 2, lane & 1);
-        const float ws = sum_rows(rs);
-        if (lane < 16 && slot < 9) {
-          if constexpr (St::NW > NS)
-            atomicAdd(&acc[wq % NS][slot][k], ws);
-          else
-            acc[wq][slot][k] = ws;
-        }
-      }
-      __syncthreads();
-      // nine consecutive lanes carry one entry's nine values, so one atomic instruction covers
-      // about seven items' contiguous 72-byte gradient records instead of 64 scattered lines
-      for (int x = threadIdx.x; x < 9 * cnt; x += N) {
-        const int t = x / 9, q = x - 9 * t;
+      // the listed entries only (the others reached no pixel of this task)
+      for (int xq = lane; xq < 9 * n; xq += kWave) {
+        const int i = xq / 9, q = xq - 9 * i;
+        const int t = S.list[i] & 0xFF;
         const double s = g2d_flush_value(acc, q, t, S.s0[t], S.s1[t]);
         if (s != 0.0) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * 9 + q], s);
       }
@@ -1195,7 +969,8 @@ struct FwdRun {
     const bool count = (p->s.flags & ODGS_FLAG_COUNT_WORK) != 0;
 #define ODGS_FWD1(C, D)                                                                                             \
   launch_sched(render_fwd_kernel<TILE, BATCH, C, D>, sc, TILE * TILE, st, vt, ranges, items, rec, out_rgb, out_T, wT, \
-               wl, wn, we, wle, p->s.bg[0], p->s.bg[1], p->s.bg[2], depth, out_depth, qmask)
+               wl, wn, we, wle, p->s.bg[0], p->s.bg[1], p->s.bg[2], depth, out_depth, qmask,                         \
+               (int64_t)p->pair_capacity)
     // the counting and depth variants keep one pixel per lane (counters per 8x8 quadrant)
     if (count && out_depth)
       ODGS_FWD1(true, true);
@@ -1204,11 +979,11 @@ struct FwdRun {
     else if (out_depth)
       ODGS_FWD1(false, true);
     else if constexpr (TILE == 16)
-      launch_sched(render_fwd4_kernel<BATCH>, with_split(sc), kWave, st, vt, ranges, items, rec, out_rgb, out_T, wT,
-                   wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask, (int64_t)p->pair_capacity);
-    else if constexpr (TILE >= 32)
-      launch_sched(render_fwd2_kernel<TILE, BATCH>, sc, TILE * TILE / 2, st, vt, ranges, items, rec, out_rgb, out_T,
-                   wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
+      launch_sched(render_fwd4_kernel<16, BATCH>, with_split(sc), kWave, st, vt, ranges, items, rec, out_rgb, out_T,
+                   wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask, (int64_t)p->pair_capacity);
+    else if constexpr (TILE == 32)
+      launch_sched(render_fwd4_kernel<32, BATCH>, with_parts(sc), kWave, st, vt, ranges, items, rec, out_rgb, out_T,
+                   wT, wl, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask, (int64_t)p->pair_capacity);
     else
       ODGS_FWD1(false, false);
 #undef ODGS_FWD1
@@ -1220,15 +995,15 @@ struct BwdRun {
   static void run(const odgs_plan* p, const TileSched& sc, const ViewTable& vt, const uint2* ranges,
                   const uint32_t* items, const Rec* rec, const float* wT, const int32_t* wl, const float* dL, double* g2d,
                   const uint8_t* qmask, hipStream_t st) {
-    // four pixels per lane in one wavefront at 16x16 (split tiles as the forward split them), two
-    // pixels per lane at 32x32 (one cross-lane reduction per 128 pixels); an 8x8 tile has a single
-    // quadrant and keeps one pixel per lane
+    // four pixels per lane in one wavefront per 16x16 block (split tiles as the forward split
+    // them; 32x32 tiles as four blocks); an 8x8 tile has a single quadrant and keeps one pixel per
+    // lane
     if constexpr (TILE == 16)
-      launch_sched(render_bwd4_kernel<BATCH>, with_split(sc), kWave, st, vt, ranges, items, rec, wT, wl, dL, g2d,
+      launch_sched(render_bwd4_kernel<16, BATCH>, with_split(sc), kWave, st, vt, ranges, items, rec, wT, wl, dL, g2d,
                    p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask, (int64_t)p->pair_capacity);
-    else if constexpr (TILE >= 32)
-      launch_sched(render_bwd2_kernel<TILE, BATCH>, sc, TILE * TILE / 2, st, vt, ranges, items, rec, wT, wl, dL, g2d,
-                   p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);
+    else if constexpr (TILE == 32)
+      launch_sched(render_bwd4_kernel<32, BATCH>, with_parts(sc), kWave, st, vt, ranges, items, rec, wT, wl, dL, g2d,
+                   p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask, (int64_t)p->pair_capacity);
     else
       launch_sched(render_bwd_kernel<TILE, BATCH>, sc, TILE * TILE, st, vt, ranges, items, rec, wT, wl, dL, g2d,
                    p->items, p->s.bg[0], p->s.bg[1], p->s.bg[2], qmask);

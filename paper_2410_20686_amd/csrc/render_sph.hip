@@ -702,16 +702,18 @@ __global__ __launch_bounds__(kWave) void render_sph_bwd4_kernel(
         uint32_t m = 0;
         if (e < cnt) {
           const uint32_t pos = rg.x + end - 1 - e;
-          const uint32_t item = pair_items[pos];
-          const SphRec r = rec[item];
-          S.s0[e] = r.s0;
-          S.s1[e] = r.s1;
-          S.s2[e] = r.s2;
-          S.s3[e] = r.s3;
-          S.sid[e] = item;
           m = qm[pos] & sel;
+          if (m != 0u) {  // records only of the entries the forward's pixels reached
+            const uint32_t item = pair_items[pos];
+            const SphRec r = rec[item];
+            S.s0[e] = r.s0;
+            S.s1[e] = r.s1;
+            S.s2[e] = r.s2;
+            S.s3[e] = r.s3;
+            S.sid[e] = item;
 #pragma unroll
-          for (int j = 0; j < kNV; ++j) acc[0][j][e] = 0.0f;
+            for (int j = 0; j < kNV; ++j) acc[0][j][e] = 0.0f;
+          }
         }
         const uint64_t bl = __builtin_amdgcn_ballot_w64(m != 0u);
         if (m != 0u) S.list[n + __popcll(bl & below)] = (uint16_t)(e | (m << 8));
@@ -776,10 +778,11 @@ __global__ __launch_bounds__(kWave) void render_sph_bwd4_kernel(
         if (lane < 16 && slot < kNV) acc[0][slot][k] = ws;
       }
       __syncthreads();
-      // thirteen consecutive lanes carry one entry's values: contiguous 104-byte records
+      // thirteen consecutive lanes carry one listed entry's values: contiguous 104-byte records
 #pragma unroll 1
-      for (int xx = lane; xx < kNV * cnt; xx += kWave) {
-        const int t = xx / kNV, q = xx - kNV * t;
+      for (int xx = lane; xx < kNV * n; xx += kWave) {
+        const int i = xx / kNV, q = xx - kNV * i;
+        const int t = S.list[i] & 0xFF;
         const double s = sph_flush_value(acc, q, t, S.s0[t], S.s1[t], S.s2[t]);
         if (s != 0.0) unsafeAtomicAdd(&g2d[(int64_t)S.sid[t] * kNV + q], s);
       }

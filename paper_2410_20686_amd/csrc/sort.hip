@@ -641,6 +641,7 @@ TileSched make_sched(const odgs_plan* p, void* ws, int which) {
   s.ctr = (p->s.flags & ODGS_FLAG_SCHED_PERSISTENT) ? q + 2 * which : nullptr;
   s.split = q + 4;
   s.split_cap = 0;
+  s.split_all = 0;
   return s;
 }
 
