@@ -279,16 +279,14 @@ def main():
     roof = None
     if dom in alg_ops:
         achieved = alg_ops[dom] / (stages[dom] / 1e3) / 1e12
-        if dom == "composite_bwd":  # one wavefront per 16x16 tile (four pixels per lane), else two or one
-            if st["tile"] == 16:
-                kname = "odgs::render_bwd4_kernel<%d>" % rast.plan.s.batch_bwd
-            else:
-                kname = "odgs::render_bwd%s_kernel<%d, %d>" % ("2" if st["tile"] >= 32 else "", st["tile"],
-                                                              rast.plan.s.batch_bwd)
+        # one wavefront per 16x16 block at tiles of 16 and 32, one workgroup per tile at 8
+        if dom == "composite_bwd":
+            kname = ("odgs::render_bwd4_kernel<%d, %d>" if st["tile"] >= 16 else "odgs::render_bwd_kernel<%d, %d>") % (
+                st["tile"], rast.plan.s.batch_bwd)
+        elif st["tile"] >= 16:
+            kname = "odgs::render_fwd4_kernel<%d, %d>" % (st["tile"], rast.plan.s.batch)
         else:
-            kname = "odgs::render_fwd%s_kernel<%d, %d%s>" % ("2" if st["tile"] >= 32 else "", st["tile"],
-                                                            rast.plan.s.batch, "" if st["tile"] >= 32 else
-                                                            ", false, false")
+            kname = "odgs::render_fwd_kernel<%d, %d, false, false>" % (st["tile"], rast.plan.s.batch)
         prof = profiled(kname)
         # the same algorithmic work over the committed profile's average duration of this kernel
         ach_prof = alg_ops[dom] / (prof["avg_us"] * 1e-6) / 1e12 if prof else None
