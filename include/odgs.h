@@ -150,7 +150,7 @@ typedef struct odgs_plan {
 
 /* Fill `plan` for n Gaussians of SH degree sh_degree seen by n_views views of sizes
  * wh [host] = {W0, H0, W1, H1, ...}, with room for pair_capacity Gaussian-tile pairs
- * (pair_capacity < 2^31).  Pure host computation. */
+ * (pair_capacity < 2^31; fewer than 2^29 tiles over all views).  Pure host computation. */
 int odgs_plan_init(odgs_plan* plan /*[host]*/, int64_t n, int32_t sh_degree, int32_t n_views, const int32_t* wh /*[host]*/,
                    const odgs_settings* s /*[host]*/, int64_t pair_capacity);
 

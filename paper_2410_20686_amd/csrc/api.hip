@@ -93,7 +93,8 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
     plan->pix_base[v] = pixels;
     tiles += (int64_t)(W / st.tile) * (H / st.tile);
     pixels += (int64_t)W * H;
-    if (tiles >= (int64_t(1) << 31) || pixels >= (int64_t(1) << 40)) return ODGS_EINVAL;
+    // up to four compositing tasks per tile must fit a launch grid
+    if (tiles >= (int64_t(1) << 29) || pixels >= (int64_t(1) << 40)) return ODGS_EINVAL;
   }
   plan->tile_base[n_views] = (int32_t)tiles;
   plan->pix_base[n_views] = pixels;
