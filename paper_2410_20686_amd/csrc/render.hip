@@ -670,8 +670,8 @@ __global__ __launch_bounds__(TILE* TILE) void render_bwd_kernel(ViewTable vt, co
   static_assert(TILE == 8, "tiles of 16 and 32 take the four-pixel kernel");
   using St = Stage<TILE, BATCH>;
   constexpr int N = St::N;
-  // Up to four wavefronts per tile: each wavefront owns a slot per (value, entry) and the slots
-  // are summed at the flush, so no LDS atomics; more wavefronts share one slot set atomically.
+  // One wavefront per 8x8 tile, owning a slot per (value, entry) (the slot-set logic is written
+  // for up to four wavefronts, whose sets are summed at the flush, so no LDS atomics).
   constexpr bool kSlots = St::NW <= 4;
   constexpr int NS = kSlots ? St::NW : 1;
   __shared__ St S;
