@@ -77,6 +77,7 @@ def test_spherical_plan_layout(lib):
     (dict(tile=32, batch=32), [(64, 32)]),
     (dict(tile=16, batch=100), [(64, 32)]),
     (dict(tile=16), [(64, 32)] * 65),
+    (dict(tile=8), [(32768, 16384)] * 64),  # 2^29 tiles: four compositing tasks per tile overflow a grid
     (dict(tile=16, far=0.1), [(64, 32)]),
 ])
 def test_plan_rejects_bad_settings(lib, kw, wh):
