@@ -106,7 +106,9 @@ typedef struct odgs_settings {
 typedef struct odgs_status {
   int32_t flags;      /* ODGS_STATUS_* bits */
   int32_t n_pairs_stored; /* min(n_pairs, pair_capacity): pairs actually sorted and rendered */
-  int64_t n_pairs;    /* Gaussian-tile pairs P of the last odgs_preprocess */
+  int64_t n_pairs;    /* Gaussian-tile pairs P of the last odgs_preprocess (with coarse binning, when
+                         the 32x32 tiles' pairs already overflow: four times their number, an upper
+                         bound of P to grow the capacity to) */
   int64_t n_visible;  /* (Gaussian, view) items that survived culling */
   uint32_t bin_gen;   /* incremented by every odgs_bin_sort (wraps) */
   uint32_t fwd_gen;   /* bin_gen of the pair list the last odgs_render_fwd composited; set to
@@ -144,7 +146,12 @@ typedef struct odgs_plan {
       off_hist, off_digit, off_ranges, off_T, off_last, off_ncontrib, off_neval,
       off_lasteval, off_g2d, off_srec, off_cone, off_dirs, off_queue;
   int32_t depth_final;     /* which of the two depth-sort buffers holds the sorted result */
-  int32_t pair_final;      /* which of the two pair buffers holds the sorted result */
+  int32_t pair_final;      /* which of the two pair buffers holds the sorted result (coarse binning:
+                              the item buffer of that pair holds the refined lists) */
+  int32_t coarse;          /* 1: pairs are binned and sorted by 32x32 tiles, then refined into the 16x16
+                              tiles' lists (tile 16 with every W and H a multiple of 32) */
+  int32_t coarse_bits;     /* significant bits of a global 32x32 tile id (coarse binning) */
+  int32_t tile_base32[ODGS_MAX_VIEWS + 1];  /* first global 32x32 tile id of each view (coarse) */
   size_t ws_bytes;
 } odgs_plan;
 

@@ -76,7 +76,9 @@ class Plan(ctypes.Structure):
                  ("items", ctypes.c_int64), ("pair_capacity", ctypes.c_int64), ("tile_bits", ctypes.c_int32),
                  ("item_blocks", ctypes.c_int32), ("pair_blocks", ctypes.c_int32), ("g2d_stride", ctypes.c_int32)]
                 + [(name, ctypes.c_size_t) for name in _OFFSETS]
-                + [("depth_final", ctypes.c_int32), ("pair_final", ctypes.c_int32), ("ws_bytes", ctypes.c_size_t)])
+                + [("depth_final", ctypes.c_int32), ("pair_final", ctypes.c_int32), ("coarse", ctypes.c_int32),
+                   ("coarse_bits", ctypes.c_int32), ("tile_base32", ctypes.c_int32 * (MAX_VIEWS + 1)),
+                   ("ws_bytes", ctypes.c_size_t)])
 
 
 _lib = None

@@ -109,6 +109,22 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   if (plan->pair_blocks < 1) plan->pair_blocks = 1;
   plan->depth_final = (4 % 2);                  // 4 passes of 8 bits over 32-bit depths
   plan->pair_final = ((bits + 7) / 8) % 2;      // passes over the tile bits
+  // Coarse binning at 16x16 tiles: pairs by 32x32 tile (about half as many), sorted, then split
+  // into the four 16x16 tiles' lists, which land in the other pair buffer.
+  int64_t tiles32 = 0;
+  bool coarse = st.tile == 16;
+  for (int v = 0; v < n_views; ++v) coarse = coarse && wh[2 * v] % 32 == 0 && wh[2 * v + 1] % 32 == 0;
+  for (int v = 0; v < n_views; ++v) {
+    plan->tile_base32[v] = (int32_t)tiles32;
+    if (coarse) tiles32 += (int64_t)(wh[2 * v] / 32) * (wh[2 * v + 1] / 32);
+  }
+  plan->tile_base32[n_views] = (int32_t)tiles32;
+  int cbits = 1;
+  while ((int64_t(1) << cbits) < tiles32) ++cbits;
+  if (cbits > 24) coarse = false;  // the sort passes must leave the mask bits (28..31) of the keys alone
+  plan->coarse = coarse ? 1 : 0;
+  plan->coarse_bits = coarse ? cbits : 0;
+  if (coarse) plan->pair_final = (((cbits + 7) / 8) % 2) ^ 1;
   const int64_t I = plan->items;
   const int64_t sblocks = (I + 1023) / 1024 + 1;
   size_t off = 0;
@@ -133,7 +149,8 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   plan->off_pval[0] = take((size_t)pair_capacity * 4);
   plan->off_pval[1] = take((size_t)pair_capacity * 4);
   const int64_t hb = plan->item_blocks > plan->pair_blocks ? plan->item_blocks : plan->pair_blocks;
-  // radix histograms; after the pair sort also the tile queue's per-(block, bucket) counts
+  // radix histograms; after the pair sort the coarse refinement's per-chunk counts (16 bytes per
+  // sort block), then the tile queue's per-(block, bucket) counts
   const int64_t qwords = (tiles + 4095) / 4096 * 1024;
   plan->off_hist = take((size_t)(256 * hb > qwords ? 256 * hb : qwords) * 4);
   plan->off_digit = take(256 * 4);

@@ -23,6 +23,7 @@ struct ViewTable {
   int64_t pix_base[ODGS_MAX_VIEWS + 1];
   float pin[ODGS_MAX_VIEWS][4];  // fx, fy, cx, cy of pinhole views; fx == 0: equirectangular
   int32_t dir_base[ODGS_MAX_VIEWS + 1];  // first entry of each view's ray table (W columns, then H rows)
+  int32_t tile_base32[ODGS_MAX_VIEWS + 1];  // first global 32x32 tile id of each view (coarse binning)
 };
 
 // Half width at which horizontal offsets wrap round the +-pi seam: W/2 for ERP views, none
@@ -189,6 +190,7 @@ inline ViewTable make_view_table(const odgs_plan* p) {
   }
   vt.dir_base[0] = 0;
   for (int v = 0; v < p->n_views; ++v) vt.dir_base[v + 1] = vt.dir_base[v] + p->width[v] + p->height[v];
+  for (int v = 0; v <= p->n_views; ++v) vt.tile_base32[v] = p->tile_base32[v];
   return vt;
 }
 

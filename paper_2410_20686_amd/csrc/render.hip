@@ -949,6 +949,55 @@ __global__ void debug_keys_kernel(const uint32_t* __restrict__ pkey, const uint3
   gauss[j] = (uint32_t)(item % n);
 }
 
+// Coarse binning: the 16x16 tiles' lists sit in the item buffer in four regions (by quadrant of the
+// 32x32 tile); written out in global 16x16 tile order (one workgroup: a scan of the list lengths per
+// 1024 tiles, then each wavefront copies whole lists).
+__global__ __launch_bounds__(1024) void debug_keys_coarse_kernel(const uint2* __restrict__ ranges, int tiles,
+                                                                 const uint32_t* __restrict__ items,
+                                                                 const float* __restrict__ depth, int64_t cap,
+                                                                 int64_t n, uint64_t* __restrict__ keys,
+                                                                 uint32_t* __restrict__ gauss) {
+  __shared__ uint32_t wsum[1024 / kWave];
+  __shared__ uint32_t s_off[1024];
+  __shared__ uint2 s_rg[1024];
+  const int t = threadIdx.x, lane = t & (kWave - 1), w = t >> 6;
+  int64_t carry = 0;
+  for (int base = 0; base < tiles; base += 1024) {
+    const uint2 rg = base + t < tiles ? ranges[base + t] : make_uint2(0u, 0u);
+    const uint32_t len = rg.y - rg.x;
+    uint32_t incl = len;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t y = __shfl_up(incl, off);
+      if (lane >= off) incl += y;
+    }
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    uint32_t pre = 0, total = 0;
+    for (int q = 0; q < 1024 / kWave; ++q) {
+      pre += q < w ? wsum[q] : 0u;
+      total += wsum[q];
+    }
+    s_off[t] = pre + incl - len;
+    s_rg[t] = rg;
+    __syncthreads();
+    for (int k = w; k < 1024 && base + k < tiles; k += 1024 / kWave) {
+      const uint2 r = s_rg[k];
+      const int64_t o = carry + s_off[k];
+      for (uint32_t j = lane; j < r.y - r.x; j += kWave) {
+        const int64_t pos = o + j;
+        if (pos < cap) {
+          const uint32_t item = items[r.x + j];
+          keys[pos] = ((uint64_t)(base + k) << 32) | (uint64_t)__float_as_uint(depth[item]);
+          gauss[pos] = (uint32_t)(item % n);
+        }
+      }
+    }
+    carry += total;
+    __syncthreads();
+  }
+}
+
 __global__ void debug_pixel_counts_kernel(const int32_t* __restrict__ last, const int32_t* __restrict__ nc,
                                           const int32_t* __restrict__ ne, const int32_t* __restrict__ le,
                                           int64_t pixels, int32_t* __restrict__ out) {
@@ -1099,6 +1148,12 @@ hipError_t launch_debug_pixel_counts(const odgs_plan* p, const void* ws, int32_t
 hipError_t launch_debug_keys(const odgs_plan* p, const void* ws, int64_t cap, uint64_t* keys, uint32_t* gauss,
                              hipStream_t st) {
   if (cap <= 0) return hipSuccess;
+  if (p->coarse) {
+    hipLaunchKernelGGL(debug_keys_coarse_kernel, dim3(1), dim3(1024), 0, st, ws_ptr<uint2>(ws, p->off_ranges),
+                       p->tile_base[p->n_views], ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]),
+                       ws_ptr<float>(ws, p->off_depth), cap, p->n, keys, gauss);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(debug_keys_kernel, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st,
                      ws_ptr<uint32_t>(ws, p->off_pkey[p->pair_final]), ws_ptr<uint32_t>(ws, p->off_pval[p->pair_final]),
                      ws_ptr<float>(ws, p->off_depth), ws_ptr<odgs_status>(ws, p->off_status), cap, p->n, keys, gauss);

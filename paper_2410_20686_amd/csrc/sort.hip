@@ -227,11 +227,53 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 constexpr int kScanIpt = 4;
 constexpr int kScanBlockItems = 256 * kScanIpt;
 
+// Coarse binning (16x16 tiles, every W and H a multiple of 32): an item's pairs are the 32x32
+// tiles its 16x16-tile rectangle r touches, columns c0 .. c0 + nc - 1 (an unwrapped range, taken
+// modulo W / 32 like r's own columns) and rows r0 .. r0 + nr - 1, each pair carrying the mask of
+// the four 16x16 tiles b = 2 by + bx of its 32x32 tile that r covers.
+struct CoarseRect {
+  int c0, nc, r0, nr;
+};
+
+__device__ inline CoarseRect coarse_rect(const Rect& r, int ntx16) {
+  CoarseRect c{0, 0, 0, 0};
+  if (r.ncols == 0 || r.nrows == 0) return c;
+  if (r.ncols >= ntx16) {  // every column (col0 = 0)
+    c.nc = ntx16 >> 1;
+  } else {
+    c.c0 = r.col0 >> 1;
+    c.nc = ((r.col0 + r.ncols - 1) >> 1) - c.c0 + 1;
+  }
+  c.r0 = r.row0 >> 1;
+  c.nr = ((r.row0 + r.nrows - 1) >> 1) - c.r0 + 1;
+  return c;
+}
+
+// Mask of the 16x16 tiles of 32x32 tile (column cu, unwrapped; row ru) that r covers.
+__device__ inline uint32_t coarse_mask(const Rect& r, int ntx16, int cu, int ru) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int x = 2 * cu + (b & 1), y = 2 * ru + (b >> 1);
+    const bool col = r.ncols >= ntx16 || (x >= r.col0 && x < r.col0 + r.ncols);
+    const bool row = y >= r.row0 && y < r.row0 + r.nrows;
+    m |= (col && row) ? (1u << b) : 0u;
+  }
+  return m;
+}
+
+// Key bits above the coarse tile id: the 16x16-tile mask (coarse tile ids stay below 2^27).
+constexpr int kMaskShift = 28;
+constexpr uint32_t kTileIdMask = (1u << kMaskShift) - 1u;
+
 // Gathers the items' tile rectangles into depth order (the one random access of binning; the
-// offset and emission passes then read them sequentially) and reduces the tile counts per block.
+// offset and emission passes then read them sequentially), writes each item's pair count in depth
+// order (scnt; 32x32 tiles with coarse binning) and reduces the counts per block.
 __global__ __launch_bounds__(256) void count_reduce_kernel(const uint32_t* __restrict__ sorted_ids,
-                                                           const Rect* __restrict__ rect, int64_t items,
-                                                           Rect* __restrict__ srect, uint32_t* __restrict__ block_sum) {
+                                                           const Rect* __restrict__ rect, int64_t items, int64_t n,
+                                                           ViewTable vt, int coarse, Rect* __restrict__ srect,
+                                                           uint32_t* __restrict__ scnt,
+                                                           uint32_t* __restrict__ block_sum) {
   __shared__ uint32_t lds[4];
   const int64_t start = (int64_t)blockIdx.x * kScanBlockItems;
   uint32_t s = 0;
@@ -239,9 +281,16 @@ __global__ __launch_bounds__(256) void count_reduce_kernel(const uint32_t* __res
   for (int k = 0; k < kScanIpt; ++k) {
     const int64_t j = start + k * 256 + threadIdx.x;  // coalesced
     if (j < items) {
-      const Rect r = rect[sorted_ids[j]];
+      const uint32_t item = sorted_ids[j];
+      const Rect r = rect[item];
       srect[j] = r;
-      s += (uint32_t)r.ncols * (uint32_t)r.nrows;
+      uint32_t c = (uint32_t)r.ncols * (uint32_t)r.nrows;
+      if (coarse) {
+        const CoarseRect cr = coarse_rect(r, vt.W[view_of_item(item, n)] / 16);
+        c = (uint32_t)(cr.nc * cr.nr);
+      }
+      scnt[j] = c;
+      s += c;
     }
   }
   uint32_t total;
@@ -289,7 +338,7 @@ __global__ __launch_bounds__(256) void count_top_kernel(const uint32_t* __restri
 // First pair position of every depth-sorted item (clamped to the capacity: items starting past
 // it emit nothing).  Pairs of one item are contiguous and items follow depth order, so a later
 // stable sort by tile keeps (depth, index) order inside every tile.
-__global__ __launch_bounds__(256) void item_offsets_kernel(const Rect* __restrict__ srect,
+__global__ __launch_bounds__(256) void item_offsets_kernel(const uint32_t* __restrict__ scnt,
                                                            const uint64_t* __restrict__ block_off, int64_t items,
                                                            int64_t capacity, uint32_t* __restrict__ ioff) {
   __shared__ uint32_t lds[4];
@@ -299,12 +348,7 @@ __global__ __launch_bounds__(256) void item_offsets_kernel(const Rect* __restric
 #pragma unroll
   for (int k = 0; k < kScanIpt; ++k) {
     const int64_t j = start + threadIdx.x * kScanIpt + k;
-    if (j < items) {
-      const Rect r = srect[j];
-      cnt[k] = (uint32_t)r.ncols * (uint32_t)r.nrows;
-    } else {
-      cnt[k] = 0u;
-    }
+    cnt[k] = j < items ? scnt[j] : 0u;
     s += cnt[k];
   }
   uint32_t total;
@@ -349,6 +393,7 @@ __device__ inline int64_t wave_last_le(const uint32_t* __restrict__ a, int64_t n
 }
 
 // One round of emit_pairs_kernel: pairs [p0, p1), also counted into the wavefront's histogram.
+template <bool COARSE>
 __device__ inline void emit_round(const uint32_t* __restrict__ sorted_ids, const uint32_t* __restrict__ ioff,
                                   const Rect* __restrict__ srect, int64_t items, int64_t n, const ViewTable& vt,
                                   int tile, uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, uint32_t p0,
@@ -363,8 +408,8 @@ __device__ inline void emit_round(const uint32_t* __restrict__ sorted_ids, const
     s_off[t] = ioff[i0 + t];
     s_item[t] = item;
     s_rect[t] = srect[i0 + t];
-    s_tb[t] = (uint32_t)vt.tile_base[v];
-    s_ntx[t] = (uint16_t)(vt.W[v] / tile);
+    s_tb[t] = (uint32_t)(COARSE ? vt.tile_base32[v] : vt.tile_base[v]);
+    s_ntx[t] = (uint16_t)(vt.W[v] / tile);  // 16x16 tiles per row with coarse binning
   }
   __syncthreads();
   // each thread emits kEmitRun consecutive pairs: one search, then the rectangle is walked by
@@ -380,8 +425,11 @@ __device__ inline void emit_round(const uint32_t* __restrict__ sorted_ids, const
   }
   Rect rr = s_rect[lo];
   uint32_t ntx = s_ntx[lo];
+  // the rectangle walked: the item's 16x16 tiles, or the 32x32 tiles they fall in
+  CoarseRect cr{(int)rr.col0, (int)rr.ncols, (int)rr.row0, (int)rr.nrows};
+  if constexpr (COARSE) cr = coarse_rect(rr, (int)ntx);
   uint32_t local = q - s_off[lo];
-  uint32_t r = local / rr.ncols, c = local - r * rr.ncols;
+  uint32_t r = local / (uint32_t)cr.nc, c = local - r * (uint32_t)cr.nc;
   uint32_t key[kEmitRun], val[kEmitRun];
 #pragma unroll
   for (int j = 0; j < kEmitRun; ++j) {
@@ -391,14 +439,23 @@ __device__ inline void emit_round(const uint32_t* __restrict__ sorted_ids, const
       ++lo;
       rr = s_rect[lo];
       ntx = s_ntx[lo];
+      cr = CoarseRect{(int)rr.col0, (int)rr.ncols, (int)rr.row0, (int)rr.nrows};
+      if constexpr (COARSE) cr = coarse_rect(rr, (int)ntx);
       r = 0;
       c = 0;
     }
-    uint32_t col = rr.col0 + c;
-    if (col >= ntx) col -= ntx;
-    key[j] = s_tb[lo] + (uint32_t)(rr.row0 + r) * ntx + col;
+    const uint32_t cu = (uint32_t)cr.c0 + c;  // unwrapped column
+    if constexpr (COARSE) {
+      const uint32_t ntx32 = ntx >> 1;
+      const uint32_t col = cu >= ntx32 ? cu - ntx32 : cu;
+      key[j] = (s_tb[lo] + (uint32_t)(cr.r0 + (int)r) * ntx32 + col) |
+               (coarse_mask(rr, (int)ntx, (int)cu, cr.r0 + (int)r) << kMaskShift);
+    } else {
+      const uint32_t col = cu >= ntx ? cu - ntx : cu;
+      key[j] = s_tb[lo] + (uint32_t)(cr.r0 + (int)r) * ntx + col;
+    }
     val[j] = s_item[lo];
-    if (++c == rr.ncols) {
+    if (++c == (uint32_t)cr.nc) {
       c = 0;
       ++r;
     }
@@ -417,6 +474,7 @@ __device__ inline void emit_round(const uint32_t* __restrict__ sorted_ids, const
   }
 }
 
+template <bool COARSE>
 __global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restrict__ sorted_ids,
                                                          const uint32_t* __restrict__ ioff,
                                                          const Rect* __restrict__ srect,
@@ -456,8 +514,9 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restr
     const uint32_t p0 = b0 + (uint32_t)(round * kEmitPairs);
     if (p0 >= np) break;  // uniform
     __syncthreads();  // the searches are done, the previous round's staging has been read
-    emit_round(sorted_ids, ioff, srect, items, n, vt, tile, pkey, pval, p0, min(p0 + (uint32_t)kEmitPairs, np),
-               s_off, s_item, s_rect, s_tb, s_ntx, s_range[round], h[t >> 6]);
+    emit_round<COARSE>(sorted_ids, ioff, srect, items, n, vt, tile, pkey, pval, p0,
+                       min(p0 + (uint32_t)kEmitPairs, np), s_off, s_item, s_rect, s_tb, s_ntx, s_range[round],
+                       h[t >> 6]);
   }
   __syncthreads();
   uint32_t c = 0;
@@ -497,6 +556,186 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* __restrict_
       if (last || next != k[i]) ranges[k[i]].y = j + 1;
     }
     prev = k[i];
+  }
+}
+
+// Refinement of the coarse lists (coarse binning): the sorted 32x32-tile list is split into the
+// lists of the 16x16 tiles by the masks its keys carry.  The refined list has four regions, one per
+// quadrant b of a 32x32 tile (b = 2*row + column): region b holds, in list order, every pair whose
+// mask has bit b, so each 16x16 tile's list is one contiguous run in (depth, index) order.  A pair's
+// position is the region's base plus the number of earlier pairs with bit b: four bit counts
+// scanned over the whole list, chunk by chunk (the sort's blocks), with no per-tile work.  A chunk
+// is four wavefronts of kRefineIters rounds of 64 consecutive pairs.
+constexpr int kRefineWavePairs = kSortBlockItems / (kSortThreads / kWave);
+constexpr int kRefineIters = kRefineWavePairs / kWave;
+
+__device__ inline void coarse_tile_of(const ViewTable& vt, int T, int& v, int& cx, int& cy) {
+  v = 0;
+  while (T >= vt.tile_base32[v + 1]) ++v;
+  const int ntx32 = vt.W[v] / 32, lt = T - vt.tile_base32[v];
+  cx = lt % ntx32;
+  cy = lt / ntx32;
+}
+
+// Per-chunk counts of the four mask bits.
+__global__ __launch_bounds__(kSortThreads) void refine_count_kernel(const uint32_t* __restrict__ keys,
+                                                                    const odgs_status* __restrict__ status,
+                                                                    uint4* __restrict__ cnt) {
+  __shared__ uint32_t wc[kSortThreads / kWave][4];
+  const uint32_t n = (uint32_t)status->n_pairs_stored;
+  const uint32_t base = blockIdx.x * (uint32_t)kSortBlockItems;
+  if (base >= n) return;  // uniform per block
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+  const uint32_t wbase = base + (uint32_t)(w * kRefineWavePairs) + (uint32_t)lane;
+  uint32_t c[4] = {0u, 0u, 0u, 0u};
+#pragma unroll 4
+  for (int i = 0; i < kRefineIters; ++i) {
+    const uint32_t j = wbase + (uint32_t)(i * kWave);
+    const uint32_t m = j < n ? keys[j] >> kMaskShift : 0u;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) c[b] += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64((m >> b) & 1u));
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) wc[w][b] = c[b];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kSortThreads / kWave; ++q) s += wc[q][threadIdx.x];
+    reinterpret_cast<uint32_t*>(cnt + blockIdx.x)[threadIdx.x] = s;
+  }
+}
+
+// Exclusive scan of the chunk counts in place (one workgroup), the region bases and the coarse pair
+// count into `meta` (words 0..3 and 4), and the refined pair total into the status record (the
+// pair count and stored count of the 16x16 lists; overflow past the capacity as for the lists
+// themselves).  When the coarse list itself overflowed, the refined count is of a truncated list:
+// the pair count reported is then four times the coarse one, an upper bound of the true count (a
+// coarse pair holds at most four 16x16 pairs).
+__global__ __launch_bounds__(1024) void refine_scan_kernel(uint4* __restrict__ cnt, uint32_t* __restrict__ meta,
+                                                           int64_t capacity, odgs_status* __restrict__ status) {
+  __shared__ uint32_t wsum[1024 / kWave][4];
+  const int t = threadIdx.x, lane = t & (kWave - 1), w = t >> 6;
+  const uint32_t n = (uint32_t)status->n_pairs_stored;
+  const int chunks = (int)((n + (uint32_t)kSortBlockItems - 1) / (uint32_t)kSortBlockItems);
+  uint32_t carry[4] = {0u, 0u, 0u, 0u};  // each bit count is at most n < 2^31
+  for (int base = 0; base < chunks; base += 1024) {
+    const int k = base + t;
+    const uint4 x4 = k < chunks ? cnt[k] : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t x[4] = {x4.x, x4.y, x4.z, x4.w};
+    uint32_t incl[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      incl[b] = wave_incl_scan(x[b]);
+      if (lane == kWave - 1) wsum[w][b] = incl[b];
+    }
+    __syncthreads();
+    uint32_t ex[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      uint32_t pre = 0, total = 0;
+      for (int q = 0; q < 1024 / kWave; ++q) {
+        pre += q < w ? wsum[q][b] : 0u;
+        total += wsum[q][b];
+      }
+      ex[b] = carry[b] + pre + incl[b] - x[b];
+      carry[b] += total;
+    }
+    __syncthreads();
+    if (k < chunks) cnt[k] = make_uint4(ex[0], ex[1], ex[2], ex[3]);
+  }
+  __syncthreads();  // every thread has read the stored count
+  if (t == 0) {
+    int64_t r = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      meta[b] = (uint32_t)(r < capacity ? r : capacity);
+      r += carry[b];
+    }
+    meta[4] = n;
+    const bool truncated = (status->flags & ODGS_STATUS_OVERFLOW) != 0;
+    status->n_pairs = truncated ? 4 * status->n_pairs : r;
+    status->n_pairs_stored = (int32_t)(r < capacity ? r : capacity);
+    if (r > capacity) status->flags |= ODGS_STATUS_OVERFLOW;
+  }
+}
+
+// The writes: each wavefront recounts its pairs' bits before each round of 64 (ballots), so the
+// pairs of one region that a round holds land in consecutive positions.  The pair that starts a
+// 32x32 tile's run sets the starts of its four 16x16 tiles' ranges, the one that ends it the ends.
+__global__ __launch_bounds__(kSortThreads) void refine_write_kernel(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, const uint4* __restrict__ pre,
+    const uint32_t* __restrict__ meta, ViewTable vt, uint32_t capacity, uint32_t* __restrict__ out,
+    uint2* __restrict__ ranges16) {
+  __shared__ uint32_t wc[kSortThreads / kWave][4];
+  const uint32_t n = meta[4];
+  const uint32_t base = blockIdx.x * (uint32_t)kSortBlockItems;
+  if (base >= n) return;  // uniform per block
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+  const uint32_t wbase = base + (uint32_t)(w * kRefineWavePairs);
+  uint32_t key[kRefineIters], val[kRefineIters];
+  uint32_t c[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int i = 0; i < kRefineIters; ++i) {
+    const uint32_t j = wbase + (uint32_t)(i * kWave + lane);
+    key[i] = j < n ? keys[j] : 0u;  // no mask bits past the list
+    val[i] = j < n ? vals[j] : 0u;
+    const uint32_t m = key[i] >> kMaskShift;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) c[b] += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64((m >> b) & 1u));
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) wc[w][b] = c[b];
+  }
+  __syncthreads();
+  const uint4 p4 = pre[blockIdx.x];
+  uint32_t run[4] = {meta[0] + p4.x, meta[1] + p4.y, meta[2] + p4.z, meta[3] + p4.w};
+  for (int q = 0; q < w; ++q) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) run[b] += wc[q][b];
+  }
+  // tile of the pair before this lane's first one
+  uint32_t last = wbase > 0 && wbase - 1 < n ? keys[wbase - 1] & kTileIdMask : 0xFFFFFFFFu;
+#pragma unroll
+  for (int i = 0; i < kRefineIters; ++i) {
+    const uint32_t j = wbase + (uint32_t)(i * kWave + lane);
+    const bool live = j < n;
+    const uint32_t m = key[i] >> kMaskShift, t = key[i] & kTileIdMask;
+    const uint32_t up = __shfl_up(t, 1);
+    const uint32_t prev = lane == 0 ? last : up;
+    // tile of the pair after this one (lane 63: the next round's first pair); none past the list
+    const uint32_t down = __shfl_down(t, 1);
+    const uint32_t first = i + 1 < kRefineIters ? __shfl(key[i + 1], 0) & kTileIdMask : 0u;
+    uint32_t next = down;
+    if (lane == kWave - 1)
+      next = i + 1 < kRefineIters ? first : (j + 1 < n ? keys[j + 1] & kTileIdMask : 0xFFFFFFFFu);
+    if (j + 1 >= n) next = 0xFFFFFFFFu;
+    last = __shfl(t, kWave - 1);
+    uint32_t g[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const uint32_t bit = (m >> b) & 1u;
+      const uint64_t bb = __builtin_amdgcn_ballot_w64(bit);
+      g[b] = run[b] + (uint32_t)__popcll(bb & below);
+      if (bit && g[b] < capacity) out[g[b]] = val[i];
+      run[b] += (uint32_t)__popcll(bb);
+    }
+    const bool head = live && prev != t, tail = live && next != t;
+    if (head || tail) {
+      int v, cx, cy;
+      coarse_tile_of(vt, (int)t, v, cx, cy);
+      const int ntx16 = vt.W[v] / 16;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int tile16 = vt.tile_base[v] + (2 * cy + (b >> 1)) * ntx16 + 2 * cx + (b & 1);
+        if (head) ranges16[tile16].x = min(g[b], capacity);
+        if (tail) ranges16[tile16].y = min(g[b] + ((m >> b) & 1u), capacity);
+      }
+    }
   }
 }
 
@@ -685,26 +924,49 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
   uint32_t* bsum = ws_ptr<uint32_t>(ws, p->off_blocksum);
   uint64_t* boff = reinterpret_cast<uint64_t*>(bsum + align_up((size_t)sblocks, 64));
   Rect* srect = ws_ptr<Rect>(ws, p->off_srect);
+  const ViewTable vt = make_view_table(p);
+  const bool coarse = p->coarse != 0;
+  uint32_t* scnt = di[p->depth_final ^ 1];  // per-item pair counts in depth order (free id buffer)
   hipLaunchKernelGGL(count_reduce_kernel, dim3(sblocks), dim3(256), 0, st, sorted_ids, ws_ptr<Rect>(ws, p->off_rect),
-                     items, srect, bsum);
+                     items, p->n, vt, coarse ? 1 : 0, srect, scnt, bsum);
   hipLaunchKernelGGL(count_top_kernel, dim3(1), dim3(256), 0, st, bsum, boff, sblocks, p->pair_capacity, status);
   // 3. emit pairs: per-item offsets (into the free ping-pong buffer), then pair-parallel writes
   uint32_t* pk[2] = {ws_ptr<uint32_t>(ws, p->off_pkey[0]), ws_ptr<uint32_t>(ws, p->off_pkey[1])};
   uint32_t* pv[2] = {ws_ptr<uint32_t>(ws, p->off_pval[0]), ws_ptr<uint32_t>(ws, p->off_pval[1])};
-  const ViewTable vt = make_view_table(p);
   uint32_t* ioff = dk[p->depth_final ^ 1];
-  hipLaunchKernelGGL(item_offsets_kernel, dim3(sblocks), dim3(256), 0, st, srect, boff, items, p->pair_capacity,
+  hipLaunchKernelGGL(item_offsets_kernel, dim3(sblocks), dim3(256), 0, st, scnt, boff, items, p->pair_capacity,
                      ioff);
-  if (p->pair_blocks > 0)
-    hipLaunchKernelGGL(emit_pairs_kernel, dim3((unsigned)p->pair_blocks), dim3(kSortThreads), 0, st, sorted_ids, ioff,
-                       srect, status, items, p->n, vt, p->s.tile, pk[0], pv[0], hist, p->pair_blocks);
+  if (p->pair_blocks > 0) {
+    if (coarse)
+      hipLaunchKernelGGL(emit_pairs_kernel<true>, dim3((unsigned)p->pair_blocks), dim3(kSortThreads), 0, st,
+                         sorted_ids, ioff, srect, status, items, p->n, vt, p->s.tile, pk[0], pv[0], hist,
+                         p->pair_blocks);
+    else
+      hipLaunchKernelGGL(emit_pairs_kernel<false>, dim3((unsigned)p->pair_blocks), dim3(kSortThreads), 0, st,
+                         sorted_ids, ioff, srect, status, items, p->n, vt, p->s.tile, pk[0], pv[0], hist,
+                         p->pair_blocks);
+  }
   // 4. stable sort of the pairs by global tile (the first pass's histogram counted by the emission)
-  e = radix_sort(pk[0], pv[0], pk[1], pv[1], false, n_dev, (uint32_t)p->pair_capacity, p->tile_bits, p->pair_blocks,
-                 hist, digit, st, true);
+  const int bits = coarse ? p->coarse_bits : p->tile_bits;
+  e = radix_sort(pk[0], pv[0], pk[1], pv[1], false, n_dev, (uint32_t)p->pair_capacity, bits, p->pair_blocks, hist,
+                 digit, st, true);
   if (e != hipSuccess) return e;
-  // 5. tile ranges
-  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((p->pair_capacity + 256 * kRangeKeys - 1) / (256 * kRangeKeys))),
-                     dim3(256), 0, st, pk[p->pair_final], status, ranges);
+  const int sorted = sort_passes(bits) % 2;  // the buffer pair holding the sorted list
+  if (!coarse) {
+    // 5. tile ranges
+    hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((p->pair_capacity + 256 * kRangeKeys - 1) / (256 * kRangeKeys))),
+                       dim3(256), 0, st, pk[sorted], status, ranges);
+  } else {
+    // 5. the 32x32 tiles' list split into the 16x16 tiles' lists and ranges, in the other pair
+    //    buffer (scratch: the free radix histograms)
+    uint4* cnt = reinterpret_cast<uint4*>(hist);  // per chunk (sort block)
+    uint32_t* meta = hist + align_up((size_t)p->pair_blocks * 4, 64);
+    const unsigned cgrid = (unsigned)p->pair_blocks;
+    hipLaunchKernelGGL(refine_count_kernel, dim3(cgrid), dim3(kSortThreads), 0, st, pk[sorted], status, cnt);
+    hipLaunchKernelGGL(refine_scan_kernel, dim3(1), dim3(1024), 0, st, cnt, meta, p->pair_capacity, status);
+    hipLaunchKernelGGL(refine_write_kernel, dim3(cgrid), dim3(kSortThreads), 0, st, pk[sorted], pv[sorted], cnt, meta,
+                       vt, (uint32_t)p->pair_capacity, pv[sorted ^ 1], ranges);
+  }
   // 6. the compositors' work queue, longest list first (its scratch: the free radix histograms)
   return launch_tile_queue(ranges, tiles, n_dev, hist, queue, st);
 }
