@@ -52,30 +52,57 @@ __device__ inline uint32_t active_count(const uint32_t* n_dev, uint32_t n_host) 
 
 // Per-block histogram of the 8-bit digit at `shift`: hist[digit * nblocks + block].  Each
 // wavefront counts into its own LDS histogram (a quarter of the same-address atomics), reading
-// four consecutive keys per 16-byte load.
+// four consecutive keys per 16-byte load.  AGG (for a pass over a key's top digit, which takes few
+// distinct values): the lanes of a round holding the same digit are found by ballots over its
+// bits and only the lowest of them adds their number, instead of one contended atomic per key.
+template <bool AGG>
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
                                                                  const uint32_t* __restrict__ n_dev, uint32_t n_host,
-                                                                 int shift, uint32_t* __restrict__ hist, int nblocks) {
+                                                                 int shift, int dbits, uint32_t* __restrict__ hist,
+                                                                 int nblocks) {
   constexpr int NW = kSortThreads / kWave;
   __shared__ uint32_t h[NW][256];
   const int t = threadIdx.x, wave = t >> 6;
+  const uint32_t n = active_count(n_dev, n_host);
+  const uint32_t start = blockIdx.x * (uint32_t)kSortBlockItems;
+  if (start >= n) return;  // uniform: blocks past the keys are neither scanned nor scattered
 #pragma unroll
   for (int w = 0; w < NW; ++w) h[w][t] = 0;
   __syncthreads();
-  const uint32_t n = active_count(n_dev, n_host);
-  const uint32_t start = blockIdx.x * (uint32_t)kSortBlockItems;
+  if constexpr (AGG) {
+    const int lane = t & (kWave - 1);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    uint32_t k[kSortIpt];
 #pragma unroll
-  for (int r = 0; r < kSortIpt / 4; ++r) {
-    const uint32_t idx = start + 4u * (uint32_t)(r * kSortThreads + t);
-    if (idx + 4 <= n) {
-      const uint4 k4 = *reinterpret_cast<const uint4*>(keys + idx);
-      atomicAdd(&h[wave][(k4.x >> shift) & 255u], 1u);
-      atomicAdd(&h[wave][(k4.y >> shift) & 255u], 1u);
-      atomicAdd(&h[wave][(k4.z >> shift) & 255u], 1u);
-      atomicAdd(&h[wave][(k4.w >> shift) & 255u], 1u);
-    } else {
-      for (uint32_t i = idx; i < n && i < idx + 4; ++i) atomicAdd(&h[wave][(keys[i] >> shift) & 255u], 1u);
+    for (int r = 0; r < kSortIpt; ++r)  // unconditional loads stay in flight together
+      k[r] = keys[min(start + (uint32_t)(r * kSortThreads + t), n - 1)];
+#pragma unroll
+    for (int r = 0; r < kSortIpt; ++r) {
+      const uint32_t idx = start + (uint32_t)(r * kSortThreads + t);
+      const bool valid = idx < n;
+      const uint32_t d = (k[r] >> shift) & 255u;
+      uint64_t peers = __builtin_amdgcn_ballot_w64(valid);
+      for (int b = 0; b < dbits; ++b) {  // the digit's bits above dbits are zero in every key
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __builtin_amdgcn_ballot_w64(bit);
+        peers &= bit ? bb : ~bb;
+      }
+      if (valid && (peers & below) == 0ull) atomicAdd(&h[wave][d], (uint32_t)__popcll(peers));
     }
+  } else if (start + (uint32_t)kSortBlockItems <= n) {  // a whole block: 16-byte loads, all in flight
+    uint4 k4[kSortIpt / 4];
+#pragma unroll
+    for (int r = 0; r < kSortIpt / 4; ++r)
+      k4[r] = *reinterpret_cast<const uint4*>(keys + start + 4u * (uint32_t)(r * kSortThreads + t));
+#pragma unroll
+    for (int r = 0; r < kSortIpt / 4; ++r) {
+      atomicAdd(&h[wave][(k4[r].x >> shift) & 255u], 1u);
+      atomicAdd(&h[wave][(k4[r].y >> shift) & 255u], 1u);
+      atomicAdd(&h[wave][(k4[r].z >> shift) & 255u], 1u);
+      atomicAdd(&h[wave][(k4[r].w >> shift) & 255u], 1u);
+    }
+  } else {
+    for (uint32_t i = start + (uint32_t)t; i < n; i += kSortThreads) atomicAdd(&h[wave][(keys[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
   uint32_t c = 0;
@@ -84,29 +111,32 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t
   hist[t * nblocks + blockIdx.x] = c;
 }
 
-// Block d: exclusive scan of hist[d][0..nblocks) in place; digit total to digit_tot[d].  Each
-// thread takes kDigitIpt consecutive entries per round, so a row of thousands of sort blocks
-// needs a few block-wide scans rather than one per 256 entries.
+// Block d: exclusive scan of hist[d][0..live) in place, over the blocks that hold keys; digit
+// total to digit_tot[d].  Each thread takes kDigitIpt consecutive entries per round, so a row of
+// thousands of sort blocks needs a few block-wide scans rather than one per 256 entries.
 constexpr int kDigitIpt = 8;
 
 __global__ __launch_bounds__(256) void radix_digit_scan_kernel(uint32_t* __restrict__ hist, int nblocks,
+                                                               const uint32_t* __restrict__ n_dev, uint32_t n_host,
                                                                uint32_t* __restrict__ digit_tot) {
   __shared__ uint32_t lds[4];
   uint32_t* row = hist + (size_t)blockIdx.x * nblocks;
+  const uint32_t n = active_count(n_dev, n_host);
+  const int live = min(nblocks, (int)((n + (uint32_t)kSortBlockItems - 1) / (uint32_t)kSortBlockItems));
   uint32_t carry = 0;
-  for (int base = 0; base < nblocks; base += 256 * kDigitIpt) {
+  for (int base = 0; base < live; base += 256 * kDigitIpt) {
     const int k0 = base + (int)threadIdx.x * kDigitIpt;
     uint32_t x[kDigitIpt], sum = 0;
 #pragma unroll
     for (int j = 0; j < kDigitIpt; ++j) {
-      x[j] = k0 + j < nblocks ? row[k0 + j] : 0u;
+      x[j] = k0 + j < live ? row[k0 + j] : 0u;
       sum += x[j];
     }
     uint32_t total;
     uint32_t run = carry + block_incl_scan256(sum, lds, total) - sum;
 #pragma unroll
     for (int j = 0; j < kDigitIpt; ++j) {
-      if (k0 + j < nblocks) row[k0 + j] = run;
+      if (k0 + j < live) row[k0 + j] = run;
       run += x[j];
     }
     carry += total;
@@ -123,7 +153,7 @@ __global__ __launch_bounds__(256) void radix_digit_scan_kernel(uint32_t* __restr
 // consecutive addresses of each digit's output run.
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift, int dbits,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot, int nblocks) {
   constexpr int NW = kSortThreads / kWave;
   constexpr int PER_WAVE = kSortBlockItems / NW;
@@ -162,6 +192,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     uint64_t peers = __builtin_amdgcn_ballot_w64(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
+      if (b >= dbits) break;  // uniform: the digit's higher bits are zero in every key
       const bool bit = (d >> b) & 1u;
       const uint64_t bb = __builtin_amdgcn_ballot_w64(bit);
       peers &= bit ? bb : ~bb;
@@ -275,18 +306,29 @@ __global__ __launch_bounds__(256) void count_reduce_kernel(const uint32_t* __res
                                                            uint32_t* __restrict__ scnt,
                                                            uint32_t* __restrict__ block_sum) {
   __shared__ uint32_t lds[4];
+  __shared__ int s_w16[ODGS_MAX_VIEWS];  // 16x16 tiles per row of each view (coarse binning)
+  if (threadIdx.x < vt.n_views) s_w16[threadIdx.x] = vt.W[threadIdx.x] / 16;
+  __syncthreads();
   const int64_t start = (int64_t)blockIdx.x * kScanBlockItems;
-  uint32_t s = 0;
+  // all loads first (indices clamped into the list), so the four gathers are in flight together
+  uint32_t id[kScanIpt];
+  Rect r[kScanIpt];
 #pragma unroll
   for (int k = 0; k < kScanIpt; ++k) {
     const int64_t j = start + k * 256 + threadIdx.x;  // coalesced
+    id[k] = sorted_ids[j < items ? j : items - 1];
+  }
+#pragma unroll
+  for (int k = 0; k < kScanIpt; ++k) r[k] = rect[id[k]];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanIpt; ++k) {
+    const int64_t j = start + k * 256 + threadIdx.x;
     if (j < items) {
-      const uint32_t item = sorted_ids[j];
-      const Rect r = rect[item];
-      srect[j] = r;
-      uint32_t c = (uint32_t)r.ncols * (uint32_t)r.nrows;
+      srect[j] = r[k];
+      uint32_t c = (uint32_t)r[k].ncols * (uint32_t)r[k].nrows;
       if (coarse) {
-        const CoarseRect cr = coarse_rect(r, vt.W[view_of_item(item, n)] / 16);
+        const CoarseRect cr = coarse_rect(r[k], s_w16[id[k] / (uint32_t)n]);  // item ids are below 2^32
         c = (uint32_t)(cr.nc * cr.nr);
       }
       scnt[j] = c;
@@ -302,13 +344,20 @@ __global__ __launch_bounds__(256) void count_reduce_kernel(const uint32_t* __res
 __global__ __launch_bounds__(256) void count_top_kernel(const uint32_t* __restrict__ block_sum,
                                                         uint64_t* __restrict__ block_off, int nblocks,
                                                         int64_t capacity, odgs_status* __restrict__ status) {
+  constexpr int IPT = 16;  // consecutive block sums per thread and round
   __shared__ uint64_t wtot[4];
   uint64_t carry = 0;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
-  for (int base = 0; base < nblocks; base += 256) {
-    const int k = base + threadIdx.x;
-    const uint64_t x = k < nblocks ? (uint64_t)block_sum[k] : 0ull;
-    uint64_t incl = x;
+  for (int base = 0; base < nblocks; base += 256 * IPT) {
+    const int k0 = base + (int)threadIdx.x * IPT;
+    uint32_t x[IPT];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      x[j] = k0 + j < nblocks ? block_sum[k0 + j] : 0u;
+      sum += x[j];
+    }
+    uint64_t incl = sum;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
       const uint64_t y = __shfl_up(incl, off);
@@ -320,7 +369,12 @@ __global__ __launch_bounds__(256) void count_top_kernel(const uint32_t* __restri
     for (int q = 0; q < w; ++q) pre += wtot[q];
     const uint64_t total = wtot[0] + wtot[1] + wtot[2] + wtot[3];
     __syncthreads();
-    if (k < nblocks) block_off[k] = carry + pre + incl - x;
+    uint64_t run = carry + pre + incl - sum;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      if (k0 + j < nblocks) block_off[k0 + j] = run;
+      run += x[j];
+    }
     carry += total;
   }
   if (threadIdx.x == 0) {
@@ -588,10 +642,11 @@ __global__ __launch_bounds__(kSortThreads) void refine_count_kernel(const uint32
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
   const uint32_t wbase = base + (uint32_t)(w * kRefineWavePairs) + (uint32_t)lane;
   uint32_t c[4] = {0u, 0u, 0u, 0u};
-#pragma unroll 4
+#pragma unroll
   for (int i = 0; i < kRefineIters; ++i) {
     const uint32_t j = wbase + (uint32_t)(i * kWave);
-    const uint32_t m = j < n ? keys[j] >> kMaskShift : 0u;
+    const uint32_t kj = keys[min(j, n - 1)];  // unconditional loads stay in flight together
+    const uint32_t m = j < n ? kj >> kMaskShift : 0u;
 #pragma unroll
     for (int b = 0; b < 4; ++b) c[b] += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64((m >> b) & 1u));
   }
@@ -620,15 +675,24 @@ __global__ __launch_bounds__(1024) void refine_scan_kernel(uint4* __restrict__ c
   const int t = threadIdx.x, lane = t & (kWave - 1), w = t >> 6;
   const uint32_t n = (uint32_t)status->n_pairs_stored;
   const int chunks = (int)((n + (uint32_t)kSortBlockItems - 1) / (uint32_t)kSortBlockItems);
+  constexpr int IPT = 4;                 // consecutive chunks per thread and round
   uint32_t carry[4] = {0u, 0u, 0u, 0u};  // each bit count is at most n < 2^31
-  for (int base = 0; base < chunks; base += 1024) {
-    const int k = base + t;
-    const uint4 x4 = k < chunks ? cnt[k] : make_uint4(0u, 0u, 0u, 0u);
-    const uint32_t x[4] = {x4.x, x4.y, x4.z, x4.w};
+  for (int base = 0; base < chunks; base += 1024 * IPT) {
+    const int k0 = base + t * IPT;
+    uint4 x[IPT];
+    uint32_t s[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      x[j] = k0 + j < chunks ? cnt[k0 + j] : make_uint4(0u, 0u, 0u, 0u);
+      s[0] += x[j].x;
+      s[1] += x[j].y;
+      s[2] += x[j].z;
+      s[3] += x[j].w;
+    }
     uint32_t incl[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      incl[b] = wave_incl_scan(x[b]);
+      incl[b] = wave_incl_scan(s[b]);
       if (lane == kWave - 1) wsum[w][b] = incl[b];
     }
     __syncthreads();
@@ -640,11 +704,18 @@ __global__ __launch_bounds__(1024) void refine_scan_kernel(uint4* __restrict__ c
         pre += q < w ? wsum[q][b] : 0u;
         total += wsum[q][b];
       }
-      ex[b] = carry[b] + pre + incl[b] - x[b];
+      ex[b] = carry[b] + pre + incl[b] - s[b];
       carry[b] += total;
     }
     __syncthreads();
-    if (k < chunks) cnt[k] = make_uint4(ex[0], ex[1], ex[2], ex[3]);
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      if (k0 + j < chunks) cnt[k0 + j] = make_uint4(ex[0], ex[1], ex[2], ex[3]);
+      ex[0] += x[j].x;
+      ex[1] += x[j].y;
+      ex[2] += x[j].z;
+      ex[3] += x[j].w;
+    }
   }
   __syncthreads();  // every thread has read the stored count
   if (t == 0) {
@@ -681,8 +752,10 @@ __global__ __launch_bounds__(kSortThreads) void refine_write_kernel(
 #pragma unroll
   for (int i = 0; i < kRefineIters; ++i) {
     const uint32_t j = wbase + (uint32_t)(i * kWave + lane);
-    key[i] = j < n ? keys[j] : 0u;  // no mask bits past the list
-    val[i] = j < n ? vals[j] : 0u;
+    const uint32_t jc = min(j, n - 1);  // unconditional loads stay in flight together
+    key[i] = keys[jc];
+    val[i] = vals[jc];
+    if (j >= n) key[i] = 0u;  // no mask bits past the list
     const uint32_t m = key[i] >> kMaskShift;
 #pragma unroll
     for (int b = 0; b < 4; ++b) c[b] += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64((m >> b) & 1u));
@@ -851,12 +924,18 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, bo
   int cur = 0;
   for (int shift = 0; shift < bits; shift += 8) {
     const uint32_t* vin = (shift == 0 && identity_vals) ? nullptr : vb[cur];
-    if (shift > 0 || !first_hist)
-      hipLaunchKernelGGL(radix_hist_kernel, dim3(nblocks), dim3(kSortThreads), 0, st, kb[cur], n_dev, n_host, shift,
-                         hist, nblocks);
-    hipLaunchKernelGGL(radix_digit_scan_kernel, dim3(256), dim3(256), 0, st, hist, nblocks, digit_tot);
+    if (shift > 0 || !first_hist) {
+      if (shift + 8 >= bits)  // the top digit: few distinct values
+        hipLaunchKernelGGL(radix_hist_kernel<true>, dim3(nblocks), dim3(kSortThreads), 0, st, kb[cur], n_dev, n_host,
+                           shift, bits - shift, hist, nblocks);
+      else
+        hipLaunchKernelGGL(radix_hist_kernel<false>, dim3(nblocks), dim3(kSortThreads), 0, st, kb[cur], n_dev, n_host,
+                           shift, 8, hist, nblocks);
+    }
+    hipLaunchKernelGGL(radix_digit_scan_kernel, dim3(256), dim3(256), 0, st, hist, nblocks, n_dev, n_host, digit_tot);
     hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblocks), dim3(kSortThreads), 0, st, kb[cur], vin, kb[cur ^ 1],
-                       vb[cur ^ 1], n_dev, n_host, shift, hist, digit_tot, nblocks);
+                       vb[cur ^ 1], n_dev, n_host, shift, bits - shift < 8 ? bits - shift : 8, hist, digit_tot,
+                       nblocks);
     cur ^= 1;
   }
   return hipGetLastError();
