@@ -149,10 +149,13 @@ int odgs_plan_init(odgs_plan* plan, int64_t n, int32_t sh_degree, int32_t n_view
   plan->off_pval[0] = take((size_t)pair_capacity * 4);
   plan->off_pval[1] = take((size_t)pair_capacity * 4);
   const int64_t hb = plan->item_blocks > plan->pair_blocks ? plan->item_blocks : plan->pair_blocks;
-  // radix histograms; after the pair sort the coarse refinement's per-chunk counts (16 bytes per
-  // sort block), then the tile queue's per-(block, bucket) counts
+  // radix histograms; before binning the preprocess workgroups' item counts, after the pair sort
+  // the coarse refinement's per-chunk counts (16 bytes per sort block), then the tile queue's
+  // per-(block, bucket) counts
   const int64_t qwords = (tiles + 4095) / 4096 * 1024;
-  plan->off_hist = take((size_t)(256 * hb > qwords ? 256 * hb : qwords) * 4);
+  int64_t hwords = 256 * hb > qwords ? 256 * hb : qwords;
+  if (hwords < preprocess_blocks(n, n_views)) hwords = preprocess_blocks(n, n_views);
+  plan->off_hist = take((size_t)hwords * 4);
   plan->off_digit = take(256 * 4);
   plan->off_ranges = take((size_t)tiles * 8);
   plan->off_T = take((size_t)pixels * 4);

@@ -272,6 +272,11 @@ hipError_t launch_debug_g2d(const odgs_plan* p, const void* ws, double* out, hip
 hipError_t launch_debug_keys(const odgs_plan* p, const void* ws, int64_t cap, uint64_t* keys, uint32_t* gauss,
                              hipStream_t st);
 
+// Preprocess workgroups: one per (256-Gaussian chunk, group of views), the chunks padded to a
+// multiple of 8 (the XCDs), each leaving one word of item counts in the radix histograms' region
+// (at most n_views groups).
+inline int64_t preprocess_blocks(int64_t n, int32_t groups) { return (n + 8 * 256 - 1) / (8 * 256) * 8 * groups; }
+
 // Sort sizes: 256 threads x kSortIpt keys per block.
 constexpr int kSortThreads = 256;
 constexpr int kSortIpt = 16;
