@@ -527,7 +527,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
   cov3(s, q, cv);
   const double p_min = -log(255.0 * (double)o);
   unsigned long long visible = 0, culled = 0;
-  for (int v = v0; v < v1; ++v) {
+  // (one view per thread in the spherical instantiation: a loop of one trip that the compiler sees)
+  for (int v = v0; v < (SPH ? min(v1, v0 + 1) : v1); ++v) {
     Cam cam;
     load_cam(cams, v, cam);
     const int W = vt.W[v], H = vt.H[v];

@@ -50,7 +50,7 @@ __device__ inline uint32_t active_count(const uint32_t* n_dev, uint32_t n_host) 
   return n_dev ? min(*n_dev, n_host) : n_host;
 }
 
-// Per-block histogram of the 8-bit digit at `shift`: hist[digit * nblocks + block].  Each
+// Per-block histogram of the digit of `dbits` (<= 8) bits at `shift`: hist[digit * nblocks + block].  Each
 // wavefront counts into its own LDS histogram (a quarter of the same-address atomics), reading
 // four consecutive keys per 16-byte load.  AGG (for a pass over a key's top digit, which takes few
 // distinct values): the lanes of a round holding the same digit are found by ballots over its
@@ -60,6 +60,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t
                                                                  const uint32_t* __restrict__ n_dev, uint32_t n_host,
                                                                  int shift, int dbits, uint32_t* __restrict__ hist,
                                                                  int nblocks) {
+  const uint32_t dmask = (1u << dbits) - 1u;
   constexpr int NW = kSortThreads / kWave;
   __shared__ uint32_t h[NW][256];
   const int t = threadIdx.x, wave = t >> 6;
@@ -80,9 +81,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t
     for (int r = 0; r < kSortIpt; ++r) {
       const uint32_t idx = start + (uint32_t)(r * kSortThreads + t);
       const bool valid = idx < n;
-      const uint32_t d = (k[r] >> shift) & 255u;
+      const uint32_t d = (k[r] >> shift) & dmask;
       uint64_t peers = __builtin_amdgcn_ballot_w64(valid);
-      for (int b = 0; b < dbits; ++b) {  // the digit's bits above dbits are zero in every key
+      for (int b = 0; b < dbits; ++b) {
         const bool bit = (d >> b) & 1u;
         const uint64_t bb = __builtin_amdgcn_ballot_w64(bit);
         peers &= bit ? bb : ~bb;
@@ -96,13 +97,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t
       k4[r] = *reinterpret_cast<const uint4*>(keys + start + 4u * (uint32_t)(r * kSortThreads + t));
 #pragma unroll
     for (int r = 0; r < kSortIpt / 4; ++r) {
-      atomicAdd(&h[wave][(k4[r].x >> shift) & 255u], 1u);
-      atomicAdd(&h[wave][(k4[r].y >> shift) & 255u], 1u);
-      atomicAdd(&h[wave][(k4[r].z >> shift) & 255u], 1u);
-      atomicAdd(&h[wave][(k4[r].w >> shift) & 255u], 1u);
+      atomicAdd(&h[wave][(k4[r].x >> shift) & dmask], 1u);
+      atomicAdd(&h[wave][(k4[r].y >> shift) & dmask], 1u);
+      atomicAdd(&h[wave][(k4[r].z >> shift) & dmask], 1u);
+      atomicAdd(&h[wave][(k4[r].w >> shift) & dmask], 1u);
     }
   } else {
-    for (uint32_t i = start + (uint32_t)t; i < n; i += kSortThreads) atomicAdd(&h[wave][(keys[i] >> shift) & 255u], 1u);
+    for (uint32_t i = start + (uint32_t)t; i < n; i += kSortThreads) atomicAdd(&h[wave][(keys[i] >> shift) & dmask], 1u);
   }
   __syncthreads();
   uint32_t c = 0;
@@ -144,9 +145,10 @@ __global__ __launch_bounds__(256) void radix_digit_scan_kernel(uint32_t* __restr
   if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
-// Stable scatter of one digit pass.  vin == nullptr means the values are the input positions.
+// Stable scatter of one digit pass (a digit of `dbits` <= 8 bits at `shift`).  vin == nullptr
+// means the values are the input positions.
 // Phase 1: each wavefront ranks its own contiguous quarter of the block's keys (rounds of 64 in
-// input order; per round a multi-split by 8 ballots gives the rank among same-digit peers, added
+// input order; per round a multi-split by dbits ballots gives the rank among same-digit peers, added
 // to the wavefront's running per-digit count in LDS) with no block barriers; one exclusive prefix
 // over the wavefronts per digit then makes the ranks block-wide and stable.  Phase 2 places the
 // keys digit-sorted in LDS; phase 3 writes them out in that order, so consecutive threads store
@@ -155,6 +157,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift, int dbits,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot, int nblocks) {
+  const uint32_t dmask = (1u << dbits) - 1u;
   constexpr int NW = kSortThreads / kWave;
   constexpr int PER_WAVE = kSortBlockItems / NW;
   constexpr int ROUNDS = PER_WAVE / kWave;
@@ -188,11 +191,11 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
   for (int r = 0; r < ROUNDS; ++r) {
     const uint32_t li = (uint32_t)(wave * PER_WAVE + r * kWave + lane);
     const bool valid = li < nb;
-    const uint32_t d = (key[r] >> shift) & 255u;
+    const uint32_t d = (key[r] >> shift) & dmask;
     uint64_t peers = __builtin_amdgcn_ballot_w64(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      if (b >= dbits) break;  // uniform: the digit's higher bits are zero in every key
+      if (b >= dbits) break;  // uniform
       const bool bit = (d >> b) & 1u;
       const uint64_t bb = __builtin_amdgcn_ballot_w64(bit);
       peers &= bit ? bb : ~bb;
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
   for (int r = 0; r < ROUNDS; ++r) {
     const uint32_t li = (uint32_t)(wave * PER_WAVE + r * kWave + lane);
     if (li < nb) {
-      const uint32_t d = (key[r] >> shift) & 255u;
+      const uint32_t d = (key[r] >> shift) & dmask;
       const uint32_t p = wh[wave][d] + rank[r];
       s_key[p] = key[r];
       s_val[p] = val[r];
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t i = r * kSortThreads + t;
     if (i < nb) {
       const uint32_t k = s_key[i];
-      const uint32_t d = (k >> shift) & 255u;
+      const uint32_t d = (k >> shift) & dmask;
       const uint32_t pos = gshift[d] + i;  // unsigned wrap-around: global start + (i - local start)
       if (pos < n) {  // always true for a consistent histogram; keeps a corrupted one in bounds
         kout[pos] = k;
@@ -452,7 +455,7 @@ __device__ inline void emit_round(const uint32_t* __restrict__ sorted_ids, const
                                   const Rect* __restrict__ srect, int64_t items, int64_t n, const ViewTable& vt,
                                   int tile, uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, uint32_t p0,
                                   uint32_t p1, uint32_t* s_off, uint32_t* s_item, Rect* s_rect, uint32_t* s_tb,
-                                  uint16_t* s_ntx, const int64_t* s_range, uint32_t* hw) {
+                                  uint16_t* s_ntx, const int64_t* s_range, uint32_t* hw, uint32_t dmask) {
   // s_range: the items holding pairs p0 and p1 - 1
   const int64_t i0 = s_range[0];
   const int m = (int)(s_range[1] - i0 + 1);  // <= kEmitPairs: every listed item owns >= 1 pair here
@@ -516,7 +519,7 @@ __device__ inline void emit_round(const uint32_t* __restrict__ sorted_ids, const
   }
 #pragma unroll
   for (int j = 0; j < kEmitRun; ++j)
-    if (q + (uint32_t)j < p1) atomicAdd(&hw[key[j] & 255u], 1u);
+    if (q + (uint32_t)j < p1) atomicAdd(&hw[key[j] & dmask], 1u);
   if (q + kEmitRun <= p1) {
     *reinterpret_cast<uint4*>(pkey + q) = make_uint4(key[0], key[1], key[2], key[3]);
     *reinterpret_cast<uint4*>(pval + q) = make_uint4(val[0], val[1], val[2], val[3]);
@@ -535,7 +538,7 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restr
                                                          const odgs_status* __restrict__ status, int64_t items,
                                                          int64_t n, ViewTable vt, int tile, uint32_t* __restrict__ pkey,
                                                          uint32_t* __restrict__ pval, uint32_t* __restrict__ hist,
-                                                         int nblocks) {
+                                                         int nblocks, uint32_t dmask) {
   __shared__ uint32_t s_off[kEmitPairs + 1];
   __shared__ uint32_t s_item[kEmitPairs + 1];
   __shared__ Rect s_rect[kEmitPairs + 1];
@@ -570,7 +573,7 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restr
     __syncthreads();  // the searches are done, the previous round's staging has been read
     emit_round<COARSE>(sorted_ids, ioff, srect, items, n, vt, tile, pkey, pval, p0,
                        min(p0 + (uint32_t)kEmitPairs, np), s_off, s_item, s_rect, s_tb, s_ntx, s_range[round],
-                       h[t >> 6]);
+                       h[t >> 6], dmask);
   }
   __syncthreads();
   uint32_t c = 0;
@@ -915,6 +918,14 @@ __global__ void status_reset_kernel(odgs_status* st) {
   }
 }
 
+// Digit width of each pass over `bits` key bits: as many passes as 8-bit digits would take, the
+// bits spread evenly over them (14 bits: two 7-bit passes, whose scatters write runs twice as long
+// as an 8-bit digit's).
+int sort_digit_bits(int bits) {
+  const int passes = (bits + 7) / 8;
+  return (bits + passes - 1) / passes;
+}
+
 // first_hist: the first pass's histogram is already in `hist` (written by the producer of the keys).
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, bool identity_vals,
                       const uint32_t* n_dev, uint32_t n_host, int bits, int nblocks, uint32_t* hist,
@@ -922,20 +933,21 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, bo
   uint32_t* kb[2] = {k0, k1};
   uint32_t* vb[2] = {v0, v1};
   int cur = 0;
-  for (int shift = 0; shift < bits; shift += 8) {
+  const int dw = sort_digit_bits(bits);
+  for (int shift = 0; shift < bits; shift += dw) {
     const uint32_t* vin = (shift == 0 && identity_vals) ? nullptr : vb[cur];
+    const int dbits = bits - shift < dw ? bits - shift : dw;
     if (shift > 0 || !first_hist) {
-      if (shift + 8 >= bits)  // the top digit: few distinct values
+      if (shift + dw >= bits)  // the top digit: few distinct values
         hipLaunchKernelGGL(radix_hist_kernel<true>, dim3(nblocks), dim3(kSortThreads), 0, st, kb[cur], n_dev, n_host,
-                           shift, bits - shift, hist, nblocks);
+                           shift, dbits, hist, nblocks);
       else
         hipLaunchKernelGGL(radix_hist_kernel<false>, dim3(nblocks), dim3(kSortThreads), 0, st, kb[cur], n_dev, n_host,
-                           shift, 8, hist, nblocks);
+                           shift, dbits, hist, nblocks);
     }
     hipLaunchKernelGGL(radix_digit_scan_kernel, dim3(256), dim3(256), 0, st, hist, nblocks, n_dev, n_host, digit_tot);
     hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblocks), dim3(kSortThreads), 0, st, kb[cur], vin, kb[cur ^ 1],
-                       vb[cur ^ 1], n_dev, n_host, shift, bits - shift < 8 ? bits - shift : 8, hist, digit_tot,
-                       nblocks);
+                       vb[cur ^ 1], n_dev, n_host, shift, dbits, hist, digit_tot, nblocks);
     cur ^= 1;
   }
   return hipGetLastError();
@@ -1015,18 +1027,19 @@ hipError_t launch_bin_sort(const odgs_plan* p, void* ws, hipStream_t st) {
   uint32_t* ioff = dk[p->depth_final ^ 1];
   hipLaunchKernelGGL(item_offsets_kernel, dim3(sblocks), dim3(256), 0, st, scnt, boff, items, p->pair_capacity,
                      ioff);
+  const int bits = coarse ? p->coarse_bits : p->tile_bits;
+  const uint32_t dmask0 = (1u << sort_digit_bits(bits)) - 1u;  // the first tile pass's digit
   if (p->pair_blocks > 0) {
     if (coarse)
       hipLaunchKernelGGL(emit_pairs_kernel<true>, dim3((unsigned)p->pair_blocks), dim3(kSortThreads), 0, st,
                          sorted_ids, ioff, srect, status, items, p->n, vt, p->s.tile, pk[0], pv[0], hist,
-                         p->pair_blocks);
+                         p->pair_blocks, dmask0);
     else
       hipLaunchKernelGGL(emit_pairs_kernel<false>, dim3((unsigned)p->pair_blocks), dim3(kSortThreads), 0, st,
                          sorted_ids, ioff, srect, status, items, p->n, vt, p->s.tile, pk[0], pv[0], hist,
-                         p->pair_blocks);
+                         p->pair_blocks, dmask0);
   }
   // 4. stable sort of the pairs by global tile (the first pass's histogram counted by the emission)
-  const int bits = coarse ? p->coarse_bits : p->tile_bits;
   e = radix_sort(pk[0], pv[0], pk[1], pv[1], false, n_dev, (uint32_t)p->pair_capacity, bits, p->pair_blocks, hist,
                  digit, st, true);
   if (e != hipSuccess) return e;
