@@ -71,6 +71,15 @@ enum {
 #define ODGS_FLAG_SCHED_TILE_ID 8    /* one workgroup per tile in global tile id order (no queue, no
                                         split tiles) */
 
+/* Binning at 16x16 tiles when every view's width and height is a multiple of 32.  By default a
+ * plan of 16384 tiles or more bins coarsely: its pairs are sorted by 32x32 tile, each carrying the
+ * mask of the four 16x16 tiles its rectangle covers, and the sorted list is then split into the
+ * 16x16 tiles' lists (about half as many keys to sort; the lists are the same either way).  Smaller
+ * plans sort by 16x16 tile directly (fewer launches).  The flags select one of the two regardless
+ * of size (coarse binning still needs tile 16 and the multiples of 32; setting both is an error): */
+#define ODGS_FLAG_BIN_COARSE 16
+#define ODGS_FLAG_BIN_DIRECT 32
+
 /* Spherical footprint (ODGS_FLAG_SPHERICAL).  The paper names its local affine approximation
  * of the projected Gaussian as its limitation (Sec. 5).  With this flag every pixel ray t d
  * (t > 0, d the unit direction through the pixel centre, Eq. equirec_proj inverted) receives the

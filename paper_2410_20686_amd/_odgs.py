@@ -22,6 +22,9 @@ FLAG_SPHERICAL = 2
 FLAG_SCHED_PERSISTENT = 4
 FLAG_SCHED_TILE_ID = 8
 SCHEDULES = {"queue": 0, "persistent": FLAG_SCHED_PERSISTENT, "tile_id": FLAG_SCHED_TILE_ID}
+FLAG_BIN_COARSE = 16
+FLAG_BIN_DIRECT = 32
+BINNINGS = {"auto": 0, "coarse": FLAG_BIN_COARSE, "direct": FLAG_BIN_DIRECT}
 
 EXPORTS = ("odgs_plan_init", "odgs_plan_set_pinhole", "odgs_workspace_bytes", "odgs_preprocess", "odgs_bin_sort", "odgs_render_fwd",
            "odgs_render_bwd", "odgs_composite_bwd", "odgs_project_bwd", "odgs_status_offset", "odgs_strerror",
@@ -156,23 +159,27 @@ def _check(rc: int, what: str):
 
 
 def make_settings(tile=16, batch=0, batch_bwd=0, near=0.2, far=1e4, dilation=0.3, pole_eps=1e-4,
-                  bg=(0.0, 0.0, 0.0), count_work=False, footprint="affine", schedule="queue") -> Settings:
+                  bg=(0.0, 0.0, 0.0), count_work=False, footprint="affine", schedule="queue",
+                  binning="auto") -> Settings:
     """footprint: "affine" (the paper's local affine approximation) or "spherical"
     (ODGS_FLAG_SPHERICAL: the exact per-ray maximum of each 3D Gaussian).  schedule: the
     compositors' tile scheduling, "queue" (one workgroup per tile, longest list first),
     "persistent" (device-filling workgroups claiming tiles from that queue) or "tile_id" (one
-    workgroup per tile in tile id order)."""
+    workgroup per tile in tile id order).  binning (16x16 tiles): "auto" (by 32x32 tile, then
+    split into the 16x16 lists, from 16384 tiles on; else directly), "coarse" or "direct"."""
     if footprint not in ("affine", "spherical"):
         raise ValueError("footprint must be 'affine' or 'spherical'")
     if schedule not in SCHEDULES:
         raise ValueError("schedule must be one of %s" % sorted(SCHEDULES))
+    if binning not in BINNINGS:
+        raise ValueError("binning must be one of %s" % sorted(BINNINGS))
     s = Settings()
     s.tile, s.batch, s.batch_bwd = int(tile), int(batch), int(batch_bwd)
     s.near_r, s.far_r, s.dilation, s.pole_eps = float(near), float(far), float(dilation), float(pole_eps)
     for k in range(3):
         s.bg[k] = float(bg[k])
     s.flags = ((FLAG_COUNT_WORK if count_work else 0) | (FLAG_SPHERICAL if footprint == "spherical" else 0)
-               | SCHEDULES[schedule])
+               | SCHEDULES[schedule] | BINNINGS[binning])
     return s
 
 

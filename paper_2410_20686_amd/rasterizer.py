@@ -17,7 +17,8 @@ import torch
 from . import _odgs as B
 
 DEFAULT_SETTINGS = dict(tile=16, batch=0, batch_bwd=0, count_work=False, pinhole=None, footprint="affine",
-                        schedule="queue", near=0.2, far=1.0e4, dilation=0.3, pole_eps=1.0e-4, bg=(0.0, 0.0, 0.0))
+                        schedule="queue", binning="auto", near=0.2, far=1.0e4, dilation=0.3, pole_eps=1.0e-4,
+                        bg=(0.0, 0.0, 0.0))
 
 
 def _ptr(t: torch.Tensor | None):

@@ -45,6 +45,30 @@ def test_plan_layout(lib):
     assert p.g2d_stride == 9
 
 
+def test_binning_choice(lib):
+    """Coarse binning (32x32-tile sort, then the 16x16 lists) by default from 16384 tiles on, only
+    at tile 16 with every side a multiple of 32; the flags force either path."""
+    big = [(2048, 1024)] * 2  # 16,384 tiles of 16x16
+    small = [(256, 128), (512, 256)]
+    plan = lambda wh, **kw: B.odgs_plan_init(1000, 0, wh, B.make_settings(**kw), 100_000)
+    p = plan(big)
+    assert p.coarse == 1 and p.coarse_bits == 12 and list(p.tile_base32[:3]) == [0, 2048, 4096]
+    assert p.pair_final == (((p.coarse_bits + 7) // 8) % 2) ^ 1  # sort passes, then refined into the other buffer
+    assert plan(big[:1] + [(1024, 512)]).coarse == 0  # 10,240 tiles
+    assert plan(big, binning="direct").coarse == 0
+    assert plan(big, tile=8).coarse == 0 and plan(big, tile=32).coarse == 0
+    assert plan(small).coarse == 0
+    q = plan(small, binning="coarse")
+    assert q.coarse == 1 and list(q.tile_base32[:3]) == [0, 32, 160]
+    assert plan([(256, 128), (80, 48)], binning="coarse").coarse == 0  # 80 and 48: not multiples of 32
+    st = B.make_settings()
+    st.flags = B.FLAG_BIN_COARSE | B.FLAG_BIN_DIRECT
+    with pytest.raises(B.OdgsError):
+        B.odgs_plan_init(1000, 0, small, st, 100_000)
+    with pytest.raises(ValueError):
+        B.make_settings(binning="fine")
+
+
 def test_spherical_plan_layout(lib):
     wh = [(1024, 512), (64, 32)]
     p = B.odgs_plan_init(12345, 3, wh, B.make_settings(tile=16, footprint="spherical"), 1_000_003)

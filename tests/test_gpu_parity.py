@@ -84,12 +84,16 @@ def test_records_match_oracle(case):
         assert np.mean(ulp == 0) > 0.999, (name, col, np.mean(ulp == 0))
 
 
-@pytest.mark.parametrize("tile", [8, 16, 32])
+@pytest.mark.parametrize("tile,binning", [(8, "auto"), (16, "direct"), (16, "coarse"), (32, "auto")])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_key_list_bit_exact(case, tile):
+def test_key_list_bit_exact(case, tile, binning):
+    """Key lists (tile, depth) and Gaussian ids equal the oracle's, at 16x16 tiles both by the
+    direct sort and by coarse binning (32x32 tiles split into their 16x16 lists)."""
     name, sc, cams, st = case
-    st = dict(st, tile=tile)
+    st = dict(st, tile=tile, binning=binning)
     res = G.run_gpu(sc, cams, st, return_rast=True)
+    if tile == 16:
+        assert res["rast"].plan.coarse == (1 if binning == "coarse" else 0)
     keys, gauss = res["rast"].keys()
     okeys, ovals = O.keys(sc, cams, st)
     assert res["status"]["n_pairs"] == len(okeys)
@@ -174,10 +178,15 @@ def test_batched_equals_per_view():
     G.assert_grads_close(res["grads"], grads, rtol=1e-4, floor=1e-6)
 
 
-def test_overflow_is_reported_and_recovered():
+@pytest.mark.parametrize("binning", ["direct", "coarse"])
+def test_overflow_is_reported_and_recovered(binning):
+    """A pair list past the capacity sets the overflow bit; the rasterizer grows the buffers to the
+    reported count (with coarse binning an upper bound when the 32x32 pairs already overflow) and
+    bins again."""
     sc, cams, st = scenes.config("cfg0")
+    st = dict(st, binning=binning)
     res = G.run_gpu(sc, cams, st, pair_capacity=1000, return_rast=True)
-    assert res["rast"].capacity > 1000
+    assert res["rast"].capacity > 1000 and res["rast"].plan.coarse == (binning == "coarse")
     okeys, _ = O.keys(sc, cams, st)
     assert res["status"]["n_pairs"] == len(okeys)
     ref = O.render(sc, cams, st, mode=32)
