@@ -35,10 +35,10 @@ def test_pinhole_records(case):
     P.test_records_match_oracle(case)
 
 
-@pytest.mark.parametrize("tile", [8, 16, 32])
+@pytest.mark.parametrize("tile,binning", [(8, "auto"), (16, "direct"), (16, "coarse"), (32, "auto")])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_pinhole_key_list_bit_exact(case, tile):
-    P.test_key_list_bit_exact(case, tile)
+def test_pinhole_key_list_bit_exact(case, tile, binning):
+    P.check_key_list(case, tile, binning)
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
