@@ -577,6 +577,7 @@ __global__ __launch_bounds__(kWave) void render_sph_fwd4_kernel(
         const uint32_t mq = (km >> 8) & alive;
         if (mq == 0u) continue;  // uniform
         const float4 a = S.s0[k], b = S.s1[k], c = S.s2[k];
+        const float4 col = S.s3[k];  // once per entry, not per accepting quadrant
         uint32_t used = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -590,7 +591,6 @@ __global__ __launch_bounds__(kWave) void render_sph_fwd4_kernel(
           const float Tn = T[q] * (1.0f - alpha);
           const bool acc = ok && !(Tn < kTStop);
           done[q] = ok != acc ? 1 : done[q];  // stop: reached, but T would drop below 1e-4
-          const float4 col = S.s3[k];
           const float w = acc ? alpha * T[q] : 0.0f;
           C0[q] = fmaf(w, col.x, C0[q]);
           C1[q] = fmaf(w, col.y, C1[q]);
