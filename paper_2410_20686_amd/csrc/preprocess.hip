@@ -641,8 +641,9 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
     }
   }
   // the workgroup's kept and culled items into part[workgroup] (summed by count_fold_kernel: one
-  // atomic per wavefront on a single status word would serialise thousands of them); non-finite
-  // Gaussians, counted in the group of their first view, by one atomic per wavefront that has any
+  // atomic per wavefront on a single status word would serialise thousands of them), or, in a
+  // launch of few workgroups (part null), by one atomic per workgroup; non-finite Gaussians,
+  // counted in the group of their first view, by one atomic per wavefront that has any
   __shared__ uint32_t wsum[256 / kWave];
   uint32_t tw = (uint32_t)visible | ((uint32_t)culled << 16);
   unsigned long long tnf = (live && !fin && v0 == 0) ? 1 : 0;
@@ -656,7 +657,15 @@ __global__ __launch_bounds__(256) void preprocess_kernel(int64_t n, const float*
     if (tnf) atomicAdd((unsigned long long*)&status->n_nonfinite, tnf);
   }
   __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  if (threadIdx.x == 0) {
+    const uint32_t s = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (part) {
+      part[blockIdx.x] = s;
+    } else {
+      if (s & 0xFFFFu) atomicAdd((unsigned long long*)&status->n_visible, (unsigned long long)(s & 0xFFFFu));
+      if (s >> 16) atomicAdd((unsigned long long*)&status->n_culled, (unsigned long long)(s >> 16));
+    }
+  }
 }
 
 // Sum of the preprocess workgroups' (kept | culled << 16) counts into the status record.
@@ -1037,6 +1046,8 @@ Params make_params(const odgs_plan* p) {
 
 }  // namespace
 
+constexpr unsigned kFoldMinBlocks = 512;
+
 hipError_t launch_preprocess(const odgs_plan* p, const float* means, const float* scales, const float* quats,
                              const float* opac, const float* sh, const float* cams, void* ws, hipStream_t st) {
   if (p->n == 0) return hipSuccess;
@@ -1050,7 +1061,8 @@ hipError_t launch_preprocess(const odgs_plan* p, const float* means, const float
   // (two or four groups: 3.31 and 3.37 ms per step, against 3.30 ms).
   const int vgroups = plan_spherical(p) ? p->n_views : 1;
   const unsigned grid = (unsigned)preprocess_blocks(p->n, vgroups);
-  uint32_t* part = ws_ptr<uint32_t>(ws, p->off_hist);
+  // (up to kFoldMinBlocks workgroups add their counts with one atomic each, without the fold launch)
+  uint32_t* part = grid > kFoldMinBlocks ? ws_ptr<uint32_t>(ws, p->off_hist) : nullptr;
   Rec* rec = ws_ptr<Rec>(ws, p->off_rec);
   Rect* rect = ws_ptr<Rect>(ws, p->off_rect);
   uint32_t* count = ws_ptr<uint32_t>(ws, p->off_count);
@@ -1083,7 +1095,7 @@ hipError_t launch_preprocess(const odgs_plan* p, const float* means, const float
     default: ODGS_PRE(16); break;
   }
 #undef ODGS_PRE
-  hipLaunchKernelGGL(count_fold_kernel, dim3(1), dim3(1024), 0, st, part, (int)grid, status);
+  if (part) hipLaunchKernelGGL(count_fold_kernel, dim3(1), dim3(1024), 0, st, part, (int)grid, status);
   return hipGetLastError();
 }
 
