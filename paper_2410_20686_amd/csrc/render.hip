@@ -516,8 +516,10 @@ __global__ __launch_bounds__(kWave) void render_fwd4_kernel(
         n += __popcll(bl);
       }
       __syncthreads();
+      uint32_t kmn = S.list[0];  // the next entry's list word, read one entry ahead
       for (int i = 0; i < n; ++i) {
-        const uint32_t km = __builtin_amdgcn_readfirstlane(S.list[i]);
+        const uint32_t km = __builtin_amdgcn_readfirstlane(kmn);
+        kmn = S.list[min(i + 1, n - 1)];
         const int k = (int)(km & 0xFFu);
         const uint32_t mq = (km >> 8) & alive;
         if (mq == 0u) continue;  // uniform
@@ -878,8 +880,10 @@ __global__ __launch_bounds__(kWave) void render_bwd4_kernel(
         n += __popcll(bl);
       }
       __syncthreads();
+      uint32_t kmn = S.list[0];  // the next entry's list word, read one entry ahead
       for (int i = 0; i < n; ++i) {
-        const uint32_t km = __builtin_amdgcn_readfirstlane(S.list[i]);
+        const uint32_t km = __builtin_amdgcn_readfirstlane(kmn);
+        kmn = S.list[min(i + 1, n - 1)];
         const int k = (int)(km & 0xFFu);
         const int jrel = end - 1 - k;
         const float4 a = S.s0[k];
