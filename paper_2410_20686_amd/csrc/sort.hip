@@ -455,18 +455,33 @@ __device__ inline void emit_round(const uint32_t* __restrict__ sorted_ids, const
                                   const Rect* __restrict__ srect, int64_t items, int64_t n, const ViewTable& vt,
                                   int tile, uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, uint32_t p0,
                                   uint32_t p1, uint32_t* s_off, uint32_t* s_item, Rect* s_rect, uint32_t* s_tb,
-                                  uint16_t* s_ntx, const int64_t* s_range, uint32_t* hw, uint32_t dmask) {
+                                  uint16_t* s_ntx, const int64_t* s_range, uint32_t* hw, uint32_t dmask,
+                                  const uint32_t* s_vtb, const uint16_t* s_vntx) {
   // s_range: the items holding pairs p0 and p1 - 1
   const int64_t i0 = s_range[0];
   const int m = (int)(s_range[1] - i0 + 1);  // <= kEmitPairs: every listed item owns >= 1 pair here
-  for (int t = threadIdx.x; t < m; t += 256) {
-    const uint32_t item = sorted_ids[i0 + t];
-    const int v = view_of_item(item, n);
-    s_off[t] = ioff[i0 + t];
-    s_item[t] = item;
-    s_rect[t] = srect[i0 + t];
-    s_tb[t] = (uint32_t)(COARSE ? vt.tile_base32[v] : vt.tile_base[v]);
-    s_ntx[t] = (uint16_t)(vt.W[v] / tile);  // 16x16 tiles per row with coarse binning
+  // staged with every load in flight first (indices clamped into the round's items)
+  constexpr int R = kEmitPairs / 256;
+  uint32_t item[R], off[R];
+  Rect rc[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int64_t j = i0 + min(k * 256 + (int)threadIdx.x, m - 1);
+    item[k] = sorted_ids[j];
+    off[k] = ioff[j];
+    rc[k] = srect[j];
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int t = k * 256 + (int)threadIdx.x;
+    if (t < m) {
+      const uint32_t v = item[k] / (uint32_t)n;  // item ids are below 2^32
+      s_off[t] = off[k];
+      s_item[t] = item[k];
+      s_rect[t] = rc[k];
+      s_tb[t] = s_vtb[v];
+      s_ntx[t] = s_vntx[v];
+    }
   }
   __syncthreads();
   // each thread emits kEmitRun consecutive pairs: one search, then the rectangle is walked by
@@ -546,9 +561,15 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restr
   __shared__ uint16_t s_ntx[kEmitPairs + 1];
   __shared__ int64_t s_range[kEmitRounds][2];
   __shared__ uint32_t h[kSortThreads / kWave][256];  // per-wavefront digit counts
+  __shared__ uint32_t s_vtb[ODGS_MAX_VIEWS];  // per view: first global tile id (32x32 with coarse binning)
+  __shared__ uint16_t s_vntx[ODGS_MAX_VIEWS];  // per view: tiles per row (16x16 with coarse binning)
   const int t = threadIdx.x;
 #pragma unroll
   for (int w = 0; w < kSortThreads / kWave; ++w) h[w][t] = 0;
+  if (t < vt.n_views) {
+    s_vtb[t] = (uint32_t)(COARSE ? vt.tile_base32[t] : vt.tile_base[t]);
+    s_vntx[t] = (uint16_t)(vt.W[t] / tile);
+  }
   const uint32_t np = (uint32_t)status->n_pairs_stored;
   const uint32_t b0 = blockIdx.x * (uint32_t)kSortBlockItems;
   {
@@ -573,7 +594,7 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const uint32_t* __restr
     __syncthreads();  // the searches are done, the previous round's staging has been read
     emit_round<COARSE>(sorted_ids, ioff, srect, items, n, vt, tile, pkey, pval, p0,
                        min(p0 + (uint32_t)kEmitPairs, np), s_off, s_item, s_rect, s_tb, s_ntx, s_range[round],
-                       h[t >> 6], dmask);
+                       h[t >> 6], dmask, s_vtb, s_vntx);
   }
   __syncthreads();
   uint32_t c = 0;
