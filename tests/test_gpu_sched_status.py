@@ -182,6 +182,23 @@ def test_backward_refuses_a_stale_pair_list():
     assert rast.g2d().abs().max().item() > 0
 
 
+def test_status_counters_many_workgroups():
+    """Past 512 preprocess workgroups the kept and culled counts are summed per workgroup and
+    folded by a separate kernel (below, one atomic per workgroup): the totals are the oracle's."""
+    sc = scenes.sphere_scene(140_001, 0, seed=93)  # 69 chunks of 2048 -> 552 workgroups
+    cams = scenes.yaw_cameras(1, 256, 128, seed=93)
+    st = settings()
+    bad = np.array([3, 70_000, 140_000])
+    sc.means[0, bad] = np.nan
+    res = G.run_gpu(sc, cams, st)
+    s = res["status"]
+    rows = O.project(sc.subset(np.setdiff1d(np.arange(sc.n), bad)), cams, st)
+    kept = int((rows[..., O.F_KEPT] > 0).sum())
+    assert s["n_nonfinite"] == len(bad)
+    assert s["n_visible"] == kept and s["n_culled"] == sc.n - kept
+    assert s["n_pairs"] > 0
+
+
 def test_culled_and_nonfinite_counters():
     """Gaussians with a NaN / infinite parameter or a zero quaternion are culled in every view
     and counted; the others render as the oracle renders the scene without them."""
